@@ -1,0 +1,197 @@
+/*
+ * gr.h - C ABI of the MI355X (gfx950) constraint/gauge solver for the
+ * constrained-ADM N-body method of Barrera-Hinojosa & Li 2019 ("GRAMSES I").
+ *
+ * Every time step the method solves, on a periodic box in conformal flatness,
+ * ten elliptic equations (paper sec. 2.4 solution scheme, code-unit forms of
+ * sec. 4.1.1, multigrid forms of sec. 4.3):
+ *   V_i  : Lap V_i = 3 Om a (s_i - <s_i>)                 (momentum constraint)
+ *   U    : Lap U   = -1/4 d_j V^j
+ *   Psi  : regularised Hamiltonian constraint, chi = 1 - Psi/(2 a^2 c^2),
+ *          psi = a^(1/2) chi                               (sec. 4.3.2.1)
+ *   xi   : regularised CMC lapse equation, xi = Phi chi, alpha = 1 + Phi/(a^2c^2)
+ *                                                          (sec. 4.3.2.2)
+ *   B^i  : Lap B^i = 2 d_j[alpha chi^-6 A^ij]              (shift, MD gauge)
+ *   b    : Lap b   = -1/4 d_j B^j,  beta^i = B^i + d^i b
+ * with A_ij = d_iV_j + d_jV_i - 1/2 delta_ij d_kV^k + 2 d_i d_j U, all on a
+ * cell-centred uniform grid with the 7-point Laplacian and 3-point central
+ * differences of sec. 4.3.1, by FAS multigrid V-cycles smoothed by red-black
+ * Gauss-Seidel with one pointwise Newton step per visit.
+ *
+ * Conventions
+ *   - Every function returns an int status: GR_OK (0) or a negative code;
+ *     gr_last_error() gives a thread-local message.  No C++ exception crosses
+ *     the ABI.
+ *   - Device memory belongs to the caller.  gr_workspace_bytes() says how much
+ *     one grid needs; the caller allocates it (e.g. a torch uint8 tensor) and
+ *     hands it over with gr_bind().  After gr_bind() the library never
+ *     allocates device memory.  The workspace must outlive the grid handle.
+ *   - Arrays are float64 (or float32 where a dtype argument says so),
+ *     C order [z][y][x] with x fastest, n^3 elements, device pointers.
+ *   - All work is enqueued on the stream given to gr_bind() (a hipStream_t;
+ *     NULL = the null stream).  Calls are stream-ordered; only
+ *     gr_solve_constraints() and gr_solve_equation() synchronise the stream,
+ *     once per V-cycle, to read the 16-byte residual norm that decides
+ *     stopping, and before returning.
+ *   - Handles are not thread-safe: one thread at a time per grid.
+ */
+#ifndef GR_H
+#define GR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define GR_OK 0
+#define GR_EINVAL (-1)    /* bad argument: null pointer, size, field id, dtype   */
+#define GR_EDEVICE (-2)   /* a HIP call failed                                   */
+#define GR_ENOTCONV (-3)  /* max_cycles reached before rtol (report is filled)   */
+#define GR_ENAN (-4)      /* NaN/Inf in a residual norm (report is filled)       */
+#define GR_ESTATE (-6)    /* grid not bound to a workspace                       */
+
+/* ---- equation kinds (low-level gr_solve_equation) ---- */
+#define GR_KIND_POISSON 0     /* Lap phi = f                                     */
+#define GR_KIND_HAMILTONIAN 1 /* chi Lap Psi + A(chi^6-1) - AA chi^-6/4 + <F>chi = f */
+#define GR_KIND_CMC 2         /* Lap xi - m2 xi = f - <f> - <m2 xi>              */
+
+/* ---- field ids ---- */
+enum {
+    /* the ten solved potentials, in solve order groups */
+    GR_VX = 0, GR_VY = 1, GR_VZ = 2, GR_U = 3, GR_PSI = 4, GR_XI = 5,
+    GR_BX = 6, GR_BY = 7, GR_BZ = 8, GR_BB = 9,
+    /* matter sources (conformal, code units; sec. 3 and 4.1.2) */
+    GR_S0 = 10, GR_SX = 11, GR_SY = 12, GR_SZ = 13, GR_SM = 14,
+    /* geometric source A_ij A^ij, valid after a solve that built it */
+    GR_AA = 15,
+    /* derived, get only: Phi = xi/chi, alpha = 1 + Phi/(a^2c^2),
+       psi = a^(1/2) chi, beta^i = B^i + d_i b */
+    GR_PHI = 16, GR_ALPHA = 17, GR_CONF = 18, GR_BETAX = 19, GR_BETAY = 20, GR_BETAZ = 21,
+    /* low-level slots read by gr_solve_equation / gr_debug_*: fine source f
+       and operator coefficient (AA for the Hamiltonian, m2 for CMC) */
+    GR_RHS = 22, GR_COEF = 23,
+    GR_NUM_FIELD_IDS = 24
+};
+
+#define GR_F64 0
+#define GR_F32 1
+
+#define GR_FP64 0   /* plain FP64 multigrid                                   */
+#define GR_MIXED 1  /* FP32 inner V-cycles, FP64 residual/update (iterative refinement) */
+
+#define GR_GUESS_ZERO 0     /* start every solved field from 0                 */
+#define GR_GUESS_CURRENT 1  /* start from the values held (previous step / set_field) */
+
+#define GR_ALL_FIELDS 0x3FFu
+
+typedef struct gr_grid_s *gr_grid;
+
+/* Code-unit parameters (sec. 4.1.1): fiducial scale factor a, Omega_m and the
+ * speed of light c~ = c/(L H0). */
+typedef struct {
+    double a;
+    double omega_m;
+    double c_tilde;
+} gr_params;
+
+/* Periodic cube of n^3 cells of spacing h (h = 1/n for the unit box).
+ * n must be even and >= 2; the multigrid hierarchy halves n while n/2 is
+ * even (so 2^k grids go down to 2^3, 48 and 96 down to 6^3). */
+typedef struct {
+    int n;
+    double h;
+} gr_grid_desc;
+
+/* Solve options.  Defaults (what a zeroed struct means is NOT the default;
+ * use gr_default_opts): nu1 = nu2 = 2, max_cycles = 100, rtol = 1e-10,
+ * precision = GR_FP64, guess = GR_GUESS_ZERO, field_mask = GR_ALL_FIELDS.
+ * Stopping: at the start of each cycle, rms(eps)/rms(f) <= rtol with eps the
+ * fine residual L(phi) - f of the (regularised) equation (a zero source uses
+ * rms(eps) <= rtol).  rtol <= 0 runs exactly max_cycles cycles and
+ * returns GR_OK. */
+typedef struct {
+    int nu1, nu2, max_cycles;
+    double rtol;
+    int precision;
+    int guess;
+    unsigned field_mask;
+} gr_solve_opts;
+
+typedef struct {
+    int status;
+    int cycles[10];     /* V-cycles (mixed: refinement steps) per field        */
+    double rel_res[10]; /* final rms(eps)/rms(f) per field                     */
+    double seconds;     /* host wall time of the call                          */
+    int fallback;       /* mixed precision: fields that fell back to FP64      */
+} gr_solve_report;
+
+/* Fill *o with the defaults above. */
+int gr_default_opts(gr_solve_opts *o);
+
+/* Create a grid handle (host memory only).  Errors: GR_EINVAL for a null
+ * pointer, odd or < 2 n, n > 1024, h <= 0, or non-positive a / c~. */
+int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out);
+
+/* Bytes of device workspace the grid needs (all levels, all fields). */
+int gr_workspace_bytes(gr_grid g, size_t *bytes);
+
+/* Bind caller-owned device memory (>= gr_workspace_bytes, 256-byte aligned)
+ * and a hipStream_t (may be NULL).  Zero-fills every field and source.
+ * Re-binding replaces both. */
+int gr_bind(gr_grid g, void *d_workspace, size_t bytes, void *hip_stream);
+
+/* CIC deposit of the conformal matter sources (sec. 4.1.2) from np particles:
+ * d_pos[np][3] positions in [0,1) (x,y,z), d_u[np][3] lower-index momenta u_i,
+ * equal masses `mass` (code units).  Cell-centred cloud-in-cell weights with
+ * periodic wrap; the Lorentz factor W^2 = c^2 + a^-2 chi^-4 u_i u_i uses the
+ * Psi currently held (the previous step's Psi^n, sec. 4.5), CIC-interpolated
+ * to the particle.  Overwrites s0, s_i and the stress trace s_m
+ * (s_m = gamma^ij s_ij += w m a^-2 chi^-4 u_i u_i/(W c h^3)).  Positions
+ * outside [0,1) are wrapped. */
+int gr_deposit_sources(gr_grid g, const double *d_pos, const double *d_u, double mass,
+                       int64_t n_particles);
+
+/* Copy n^3 values of dtype GR_F64/GR_F32 from d_src into a field slot
+ * (solved fields as guesses, sources, GR_RHS, GR_COEF).  Derived ids are
+ * rejected with GR_EINVAL. */
+int gr_set_field(gr_grid g, int field, const void *d_src, int dtype);
+
+/* Copy (or, for derived ids, compute) a field into d_dst (n^3 of dtype). */
+int gr_get_field(gr_grid g, int field, void *d_dst, int dtype);
+
+/* Solve the ten equations in the order V_i -> U -> (A_ij, AA) -> Psi -> xi ->
+ * B^i -> b from the sources held (sec. 2.4 steps 1-4; sec. 4.3 forms).
+ * Fields outside opts->field_mask are not solved; their held values feed
+ * later equations.  host_report may be NULL.  Returns the first non-OK
+ * status among the fields (all fields are still attempted). */
+int gr_solve_constraints(gr_grid g, const gr_solve_opts *opts, gr_solve_report *host_report);
+
+/* Low level: solve one equation of `kind` for field slot `field` (0..9) with
+ * source GR_RHS and coefficient GR_COEF as set by gr_set_field.  Fills
+ * cycles[0] / rel_res[0] of the report. */
+int gr_solve_equation(gr_grid g, int kind, int field, const gr_solve_opts *opts,
+                      gr_solve_report *host_report);
+
+/* Low level, for step-by-step comparisons: `nsweeps` red-black Newton sweeps
+ * of the finest level (even colour first) on field slot `field` with source
+ * GR_RHS, coefficient GR_COEF and frozen scalars Fbar (Hamiltonian
+ * regulariser <F>) and fshift (subtracted from the source). */
+int gr_debug_sweep(gr_grid g, int kind, int field, double Fbar, double fshift, int nsweeps);
+
+/* Low level: fine residual L(phi) - (f - fshift) of field slot `field` into
+ * d_out (n^3 float64). */
+int gr_debug_residual(gr_grid g, int kind, int field, double Fbar, double fshift, double *d_out);
+
+/* Destroy a handle (the workspace stays the caller's). NULL is accepted. */
+int gr_destroy_grid(gr_grid g);
+
+/* Thread-local message of the last failing call on this thread. */
+const char *gr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GR_H */

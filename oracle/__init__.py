@@ -69,6 +69,8 @@ def lib():
                                        C.c_int, C.c_int, C.POINTER(C.c_int), C.c_double,
                                        C.POINTER(C.c_int), P, P]
         _lib.orc_derived.argtypes = [C.c_int, C.POINTER(_Params), P, P, P, P, P, P, P, P, P, P]
+        _lib.orc_cycle_residual.argtypes = [C.c_int, C.c_double, C.POINTER(_Params), C.c_int, P, P, P]
+        _lib.orc_cycle_residual.restype = C.c_double
     return _lib
 
 
@@ -203,6 +205,16 @@ def solve_all(s0, sx, sy, sz, sm, guesses=None, prm=None, nu1=2, nu2=2, max_cycl
                              _p(_f64(sm)), ptrs, nu1, nu2, mc.ctypes.data_as(C.POINTER(C.c_int)), rtol,
                              cycles, rel, _p(AA))
     return dict(zip(FIELDS, fields)), st, list(cycles), list(rel), AA
+
+
+def cycle_residual(kind, phi, f, coef=None, prm=None, h=None):
+    """rms(eps)/rms(f) of a pinned iterate with the frozen means evaluated from it."""
+    prm = prm or params()
+    phi = _f64(phi)
+    coef = _f64(coef) if coef is not None else np.zeros_like(phi)
+    n = phi.shape[0]
+    return lib().orc_cycle_residual(n, h if h is not None else 1.0 / n, C.byref(prm), kind, _p(phi),
+                                    _p(_f64(f)), _p(coef))
 
 
 def derived(psi, xi, Bx, By, Bz, b, prm=None):

@@ -43,7 +43,7 @@
  *   R6 stop when rms(eps)/rms(f) <= rtol, evaluated at the start of a cycle;
  *      rtol <= 0 means "run exactly max_cycles cycles".
  *   R7 s_m is the stress trace gamma^ij s_ij with the particle's own
- *      chi (CIC-interpolated Psi), i.e. m (W^2 - c^2)/(W c) per particle.
+ *      chi (CIC-interpolated Psi): m a^-2 chi^-4 u.u/(W c) per particle.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -427,7 +427,8 @@ void orc_prolong_add(int m, const double *e, double *fine) { prolong_add(e, m, f
 /* Cloud-in-cell deposit (sec. 4.1.2), cell-centred weights with periodic wrap.
  * Per particle: chi_p = 1 - kappa * (CIC-interpolated Psi^n),
  * W^2 = c^2 + a^-2 chi_p^-4 sum_l u_l^2   (Lorentz factor, sec. 4.4),
- * s0 += w m W/(c h^3), s_l += w m u_l/(c h^3), s_m += w m (W^2-c^2)/(W c h^3).
+ * s0 += w m W/(c h^3), s_l += w m u_l/(c h^3) and the stress trace
+ * s_m = gamma^ij s_ij += w m a^-2 chi^-4 u.u/(W c h^3)  (s_ij ~ u_i u_j/(W c)).
  * pos, u: [np][3]; psi may be NULL (Psi^n = 0). Outputs are overwritten. */
 void orc_cic_deposit(int n, const orc_params *prm, long np, const double *pos, const double *u,
                      double mass, const double *psi, double *s0, double *sx, double *sy, double *sz,
@@ -462,12 +463,13 @@ void orc_cic_deposit(int n, const orc_params *prm, long np, const double *pos, c
         double chi = 1.0 - kap * psi_p;
         double chi2 = chi * chi;
         double u2 = u[3 * q] * u[3 * q] + u[3 * q + 1] * u[3 * q + 1] + u[3 * q + 2] * u[3 * q + 2];
-        double W = sqrt(c * c + u2 / (a * a * chi2 * chi2));
+        double g_uu = u2 / (a * a * chi2 * chi2); /* gamma^ij u_i u_j */
+        double W = sqrt(c * c + g_uu);
         double q0 = mass * W / (c * vol);
         double qx = mass * u[3 * q] / (c * vol);
         double qy = mass * u[3 * q + 1] / (c * vol);
         double qz = mass * u[3 * q + 2] / (c * vol);
-        double qm = mass * (W * W - c * c) / (W * c * vol);
+        double qm = mass * g_uu / (W * c * vol); /* gamma^ij s_ij, s_ij ~ u_i u_j/(W c) */
         for (int cc = 0; cc < 8; ++cc) {
             int ox = cc & 1, oy = (cc >> 1) & 1, oz = cc >> 2;
             double w = (ox ? t[0] : 1.0 - t[0]) * (oy ? t[1] : 1.0 - t[1]) * (oz ? t[2] : 1.0 - t[2]);
@@ -647,4 +649,32 @@ void orc_derived(int n, const orc_params *prm, const double *psi, const double *
                 betay[p] = By[p] + dcen(b, n, h, 1, i, j, k);
                 betaz[p] = Bz[p] + dcen(b, n, h, 2, i, j, k);
             }
+}
+
+/* The stopping quantity of a given (pinned) iterate, as evaluated at the
+ * start of a cycle: frozen means from phi, then rms(eps)/rms(f - fshift).
+ * Used to check full-size results where a complete oracle solve is too slow. */
+double orc_cycle_residual(int n, double h, const orc_params *prm, int kind, const double *phi,
+                          const double *f, const double *coef)
+{
+    long N = (long)n * n * n;
+    op_t op = {kind, 1.0 / (2.0 * prm->a * prm->a * prm->c_tilde * prm->c_tilde),
+               1.5 * prm->a * prm->omega_m, 0.0, 0.0};
+    if (kind == ORC_HAMILTONIAN) {
+        double s = 0.0;
+        for (long p = 0; p < N; ++p) s += ham_F(op.kappa, op.A, phi[p], f[p], coef[p]);
+        op.Fbar = s / (double)N;
+    } else if (kind == ORC_CMC) {
+        double s = 0.0;
+        for (long p = 0; p < N; ++p) s += coef[p] * phi[p];
+        op.fshift = mean_of(f, N) + s / (double)N;
+    }
+    double *r = malloc(N * sizeof(double));
+    double *fe = malloc(N * sizeof(double));
+    residual(&op, phi, f, coef, n, h, r);
+    for (long p = 0; p < N; ++p) fe[p] = f[p] - op.fshift;
+    double rn = rms_of(r, N), fn = rms_of(fe, N);
+    free(r);
+    free(fe);
+    return rn / (fn > 0.0 ? fn : 1.0);
 }

@@ -1,0 +1,98 @@
+// Internal declarations shared by the HIP translation units of libgrmg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "gr.h"
+
+namespace grmg {
+
+constexpr int kMaxLevels = 12;
+constexpr int kCoarseSweeps = 32;   // red-black sweeps at the coarsest level
+constexpr int kReduceBlocks = 1024; // partial sums per reduction (fixed => deterministic)
+constexpr int kReduceThreads = 256;
+
+// Device scalar slots (doubles) in the workspace.
+enum Slot {
+    S_ZERO = 0,      // always 0: frozen scalars of coarse levels
+    S_MEAN = 1,      // mean for pinning / correction projection
+    S_FBAR = 2,      // Hamiltonian regulariser <F> (finest level)
+    S_FSHIFT = 3,    // CMC finest-level source shift <f> + <m2 xi>
+    S_FMEAN = 4,     // CMC <f> (once per solve)
+    S_RN = 5,        // sum eps^2   (pair with S_FN)
+    S_FN = 6,        // sum (f - fshift)^2
+    S_SCRATCH = 8,   // 8 general slots
+    S_NUM = 32
+};
+
+// Operator constants of one equation.
+struct OpConst {
+    double kappa; // 1/(2 a^2 c^2)
+    double A;     // 3/2 a Om
+};
+
+struct Level {
+    int n;
+    double h;
+    long N;
+    double *phi;  // level iterate (level 0: the field itself, set per solve)
+    double *phi0; // restricted iterate R phi (FAS), or saved copy at the coarsest
+    double *f;    // level source (level 0: fine source GR_RHS)
+    double *coef; // operator coefficient (level 0: GR_COEF)
+    double *tmp;  // scratch of the level size
+};
+
+
+// ---- stencil.hip launchers ----
+void launch_rb_sweep(int kind, hipStream_t s, double *phi, const double *f, const double *coef, int n,
+                     double h, OpConst oc, const double *fbar, const double *fshift);
+void launch_residual_restrict(int kind, hipStream_t s, const double *phi, const double *f,
+                              const double *coef, int n, double h, OpConst oc, const double *fbar,
+                              const double *fshift, double *phi_c, double *phi0_c, double *rr_c);
+void launch_coarse_rhs(int kind, hipStream_t s, const double *phi_c, const double *coef_c,
+                       const double *rr_c, int m, double H, OpConst oc, double *f_c);
+void launch_prolong_correct(hipStream_t s, double *phi_f, int n, const double *phi_c, const double *phi0_c);
+void launch_restrict(hipStream_t s, const double *fine, int n, double *coarse);
+void launch_residual(int kind, hipStream_t s, const double *phi, const double *f, const double *coef, int n,
+                     double h, OpConst oc, const double *fbar, const double *fshift, double *r);
+
+// reductions: partial sums (kReduceBlocks x ncomp) then a fixed-order finalise
+// out[slot + c] = add[c] + scale * sum_c   (add may be null)
+void launch_sum(hipStream_t s, const double *x, const double *y, long N, double *partials);
+void launch_sum_ham_F(hipStream_t s, const double *psi, const double *f, const double *coef, long N,
+                      OpConst oc, double *partials);
+void launch_sum_prod(hipStream_t s, const double *x, const double *y, long N, double *partials);
+void launch_res_norms(int kind, hipStream_t s, const double *phi, const double *f, const double *coef,
+                      int n, double h, OpConst oc, const double *fbar, const double *fshift,
+                      double *partials);
+void launch_finalize(hipStream_t s, const double *partials, int ncomp, double scale, const double *add,
+                     double *out);
+
+void launch_fill(hipStream_t s, double *x, long N, double v);
+void launch_copy(hipStream_t s, double *dst, const double *src, long N);
+void launch_sub_scalar(hipStream_t s, double *x, long N, const double *scal);
+void launch_convert_f32_to_f64(hipStream_t s, double *dst, const float *src, long N);
+void launch_convert_f64_to_f32(hipStream_t s, float *dst, const double *src, long N);
+void launch_set_scalar(hipStream_t s, double *slot, double v);
+
+// ---- sources.hip launchers ----
+void launch_cic_deposit(hipStream_t s, int n, double a, double c_tilde, const double *pos, const double *u,
+                        double mass, long np, const double *psi, double *s0, double *sx, double *sy,
+                        double *sz, double *sm);
+void launch_shift_scale(hipStream_t s, double *out, const double *in, long N, double scale,
+                        const double *mean);
+void launch_div_quarter(hipStream_t s, double *out, const double *gx, const double *gy, const double *gz,
+                        int n, double h);
+void launch_build_Aij(hipStream_t s, double *const A6[6], double *AA, const double *Vx, const double *Vy,
+                      const double *Vz, const double *U, int n, double h);
+void launch_ham_rhs(hipStream_t s, double *f, const double *s0, long N, double A);
+void launch_build_cmc(hipStream_t s, double *m2, double *f, const double *psi, const double *s0,
+                      const double *sm, const double *AA, long N, double a, double om, double c_tilde);
+void launch_shift_source(hipStream_t s, double *fB[3], const double *psi, const double *xi,
+                         double *const A6[6], int n, double h, double a, double c_tilde);
+void launch_derived(hipStream_t s, int which, double *out, const double *psi, const double *xi,
+                    const double *Bcomp, const double *b, int n, double h, double a, double c_tilde);
+
+} // namespace grmg

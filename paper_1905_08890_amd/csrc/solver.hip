@@ -1,0 +1,529 @@
+// C ABI (include/gr.h) and host orchestration of the multigrid solve:
+// workspace layout, the FAS V-cycle schedule, cycle control with the
+// stopping test, and the ten-field dependency order of the paper's
+// solution scheme (sec. 2.4; equations of sec. 4.3).
+#include <cstdarg>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "gr_internal.h"
+
+using namespace grmg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(GR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+#define LAUNCHCHK()                                                                               \
+    do {                                                                                          \
+        hipError_t e_ = hipGetLastError();                                                        \
+        if (e_ != hipSuccess) return fail(GR_EDEVICE, "kernel launch: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+#define CHK(expr)                                                                                 \
+    do {                                                                                          \
+        int st_ = (expr);                                                                         \
+        if (st_ != GR_OK) return st_;                                                             \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+} // namespace
+
+struct gr_grid_s {
+    int n = 0;
+    double h = 0.0;
+    gr_params prm{};
+    int nlev = 0;
+    Level lev[kMaxLevels]{};
+    // fine-level arrays
+    double *field[10]{};
+    double *src[5]{}; // s0, sx, sy, sz, sm
+    double *A6[6]{};
+    double *AA = nullptr;
+    double *fB[3]{}; // sources of B^i (kept for the three solves)
+    double *partials = nullptr;
+    double *scal = nullptr;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    size_t ws_bytes = 0;
+
+    long N() const { return (long)n * n * n; }
+    OpConst oc() const
+    {
+        OpConst o;
+        o.kappa = 1.0 / (2.0 * prm.a * prm.a * prm.c_tilde * prm.c_tilde);
+        o.A = 1.5 * prm.a * prm.omega_m;
+        return o;
+    }
+};
+
+namespace {
+
+int num_levels(int n)
+{
+    int L = 1;
+    while (n % 4 == 0) {
+        n /= 2;
+        ++L;
+    }
+    return L;
+}
+
+// Carve the workspace; with base == nullptr only count bytes.
+size_t layout(gr_grid g, char *base)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> double * {
+        double *p = base ? reinterpret_cast<double *>(base + off) : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    const size_t fb = sizeof(double) * (size_t)g->N();
+    for (int f = 0; f < 10; ++f) g->field[f] = take(fb);
+    for (int s = 0; s < 5; ++s) g->src[s] = take(fb);
+    for (int c = 0; c < 6; ++c) g->A6[c] = take(fb);
+    g->AA = take(fb);
+    for (int c = 0; c < 3; ++c) g->fB[c] = take(fb);
+    for (int l = 0; l < g->nlev; ++l) {
+        Level &L = g->lev[l];
+        const size_t lb = sizeof(double) * (size_t)L.N;
+        L.phi = (l == 0) ? nullptr : take(lb);
+        L.phi0 = take(lb);
+        L.f = take(lb);
+        L.coef = take(lb);
+        L.tmp = take(lb);
+    }
+    g->partials = take(sizeof(double) * kReduceBlocks * 4);
+    g->scal = take(sizeof(double) * S_NUM);
+    return off;
+}
+
+// ------------------------------------------------------------ reductions
+
+int reduce_mean(gr_grid g, const double *x, const double *y, long N, double *out)
+{
+    launch_sum(g->stream, x, y, N, g->partials);
+    launch_finalize(g->stream, g->partials, 1, 1.0 / (double)N, nullptr, out);
+    LAUNCHCHK();
+    return GR_OK;
+}
+
+// pin: phi -= mean(phi)
+int pin_mean(gr_grid g, double *phi, long N)
+{
+    CHK(reduce_mean(g, phi, nullptr, N, g->scal + S_MEAN));
+    launch_sub_scalar(g->stream, phi, N, g->scal + S_MEAN);
+    LAUNCHCHK();
+    return GR_OK;
+}
+
+// ------------------------------------------------------------ V-cycle
+
+struct EqCtx {
+    int kind;
+    OpConst oc;
+    int nu1, nu2;
+};
+
+const double *fbar_ptr(gr_grid g, int l) { return g->scal + (l == 0 ? S_FBAR : S_ZERO); }
+const double *fshift_ptr(gr_grid g, int l) { return g->scal + (l == 0 ? S_FSHIFT : S_ZERO); }
+
+int vcycle(gr_grid g, const EqCtx &E, int l)
+{
+    Level &L = g->lev[l];
+    hipStream_t s = g->stream;
+    if (l == g->nlev - 1) {
+        // coarsest: 32 sweeps, then remove the mean of the correction
+        launch_copy(s, L.tmp, L.phi, L.N);
+        for (int it = 0; it < kCoarseSweeps; ++it)
+            launch_rb_sweep(E.kind, s, L.phi, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l));
+        CHK(reduce_mean(g, L.phi, L.tmp, L.N, g->scal + S_MEAN));
+        launch_sub_scalar(s, L.phi, L.N, g->scal + S_MEAN);
+        LAUNCHCHK();
+        return GR_OK;
+    }
+    for (int it = 0; it < E.nu1; ++it)
+        launch_rb_sweep(E.kind, s, L.phi, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l));
+    Level &C = g->lev[l + 1];
+    // R phi -> C.phi and C.phi0; R eps -> C.tmp; then f^H = L^H(R phi) - R eps
+    launch_residual_restrict(E.kind, s, L.phi, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l),
+                             C.phi, C.phi0, C.tmp);
+    launch_coarse_rhs(E.kind, s, C.phi, C.coef, C.tmp, C.n, C.h, E.oc, C.f);
+    LAUNCHCHK();
+    CHK(vcycle(g, E, l + 1));
+    launch_prolong_correct(s, L.phi, L.n, C.phi, C.phi0);
+    for (int it = 0; it < E.nu2; ++it)
+        launch_rb_sweep(E.kind, s, L.phi, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l));
+    LAUNCHCHK();
+    return GR_OK;
+}
+
+// Solve one equation for `phi` (fine), with fine source lev[0].f and fine
+// coefficient lev[0].coef already in place.  Follows the cycle definition:
+// pin the guess; per cycle: frozen means, residual norm, stopping test,
+// V-cycle, pin.
+int solve_one(gr_grid g, int kind, double *phi, const gr_solve_opts &o, int *cycles_out, double *rel_out)
+{
+    hipStream_t s = g->stream;
+    const long N = g->N();
+    Level &F = g->lev[0];
+    F.phi = phi;
+    EqCtx E{kind, g->oc(), o.nu1, o.nu2};
+    if (kind != GR_KIND_POISSON)
+        for (int l = 1; l < g->nlev; ++l) launch_restrict(s, g->lev[l - 1].coef, g->lev[l - 1].n, g->lev[l].coef);
+    launch_set_scalar(s, g->scal + S_FBAR, 0.0);
+    launch_set_scalar(s, g->scal + S_FSHIFT, 0.0);
+    if (kind == GR_KIND_CMC) CHK(reduce_mean(g, F.f, nullptr, N, g->scal + S_FMEAN));
+    LAUNCHCHK();
+    CHK(pin_mean(g, phi, N));
+
+    int cyc = 0;
+    double rel = 0.0;
+    int st = GR_OK;
+    for (;;) {
+        if (kind == GR_KIND_HAMILTONIAN) {
+            launch_sum_ham_F(s, phi, F.f, F.coef, N, E.oc, g->partials);
+            launch_finalize(s, g->partials, 1, 1.0 / (double)N, nullptr, g->scal + S_FBAR);
+        } else if (kind == GR_KIND_CMC) {
+            launch_sum_prod(s, F.coef, phi, N, g->partials);
+            launch_finalize(s, g->partials, 1, 1.0 / (double)N, g->scal + S_FMEAN, g->scal + S_FSHIFT);
+        }
+        launch_res_norms(kind, s, phi, F.f, F.coef, F.n, F.h, E.oc, g->scal + S_FBAR, g->scal + S_FSHIFT,
+                         g->partials);
+        launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN);
+        LAUNCHCHK();
+        double hn[2];
+        HIPCHK(hipMemcpyAsync(hn, g->scal + S_RN, sizeof hn, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double rn = std::sqrt(hn[0]), fn = std::sqrt(hn[1]);
+        rel = rn / (fn > 0.0 ? fn : 1.0);
+        if (!std::isfinite(rel)) {
+            st = fail(GR_ENAN, "non-finite residual (kind %d, cycle %d)", kind, cyc);
+            break;
+        }
+        if (o.rtol > 0.0 && (rel <= o.rtol || rn == 0.0)) break;
+        if (cyc >= o.max_cycles) {
+            if (o.rtol > 0.0)
+                st = fail(GR_ENOTCONV, "kind %d: rel residual %.3e after %d cycles", kind, rel, cyc);
+            break;
+        }
+        CHK(vcycle(g, E, 0));
+        CHK(pin_mean(g, phi, N));
+        ++cyc;
+    }
+    *cycles_out = cyc;
+    *rel_out = rel;
+    return st;
+}
+
+int check_opts(const gr_solve_opts *o)
+{
+    if (!o) return fail(GR_EINVAL, "null opts");
+    if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 64 || o->nu2 > 64 || o->max_cycles < 0 || o->max_cycles > 100000)
+        return fail(GR_EINVAL, "bad cycle options");
+    if (!(o->rtol == o->rtol)) return fail(GR_EINVAL, "rtol is NaN");
+    if (o->precision != GR_FP64 && o->precision != GR_MIXED) return fail(GR_EINVAL, "bad precision");
+    if (o->guess != GR_GUESS_ZERO && o->guess != GR_GUESS_CURRENT) return fail(GR_EINVAL, "bad guess mode");
+    return GR_OK;
+}
+
+int check_bound(gr_grid g)
+{
+    if (!g) return fail(GR_EINVAL, "null grid");
+    if (!g->bound) return fail(GR_ESTATE, "grid not bound to a workspace");
+    return GR_OK;
+}
+
+double *slot_ptr(gr_grid g, int field)
+{
+    if (field >= 0 && field < 10) return g->field[field];
+    if (field >= GR_S0 && field <= GR_SM) return g->src[field - GR_S0];
+    if (field == GR_AA) return g->AA;
+    if (field == GR_RHS) return g->lev[0].f;
+    if (field == GR_COEF) return g->lev[0].coef;
+    return nullptr;
+}
+
+} // namespace
+
+// ===================================================================== ABI
+
+extern "C" {
+
+const char *gr_last_error(void) { return g_err.c_str(); }
+
+int gr_default_opts(gr_solve_opts *o)
+{
+    if (!o) return fail(GR_EINVAL, "null opts");
+    o->nu1 = 2;
+    o->nu2 = 2;
+    o->max_cycles = 100;
+    o->rtol = 1e-10;
+    o->precision = GR_FP64;
+    o->guess = GR_GUESS_ZERO;
+    o->field_mask = GR_ALL_FIELDS;
+    return GR_OK;
+}
+
+int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out)
+{
+    if (!desc || !prm || !out) return fail(GR_EINVAL, "null argument");
+    *out = nullptr;
+    const int n = desc->n;
+    if (n < 2 || (n & 1) || n > 1024) return fail(GR_EINVAL, "n = %d must be even, 2..1024", n);
+    if (!(desc->h > 0.0) || !std::isfinite(desc->h)) return fail(GR_EINVAL, "h must be positive");
+    if (!(prm->a > 0.0) || !(prm->c_tilde > 0.0) || !std::isfinite(prm->omega_m))
+        return fail(GR_EINVAL, "a and c_tilde must be positive");
+    gr_grid g = new (std::nothrow) gr_grid_s();
+    if (!g) return fail(GR_EINVAL, "out of host memory");
+    g->n = n;
+    g->h = desc->h;
+    g->prm = *prm;
+    g->nlev = num_levels(n);
+    if (g->nlev > kMaxLevels) {
+        delete g;
+        return fail(GR_EINVAL, "too many levels");
+    }
+    for (int l = 0; l < g->nlev; ++l) {
+        g->lev[l].n = n >> l;
+        g->lev[l].h = desc->h * (double)(1 << l);
+        g->lev[l].N = (long)g->lev[l].n * g->lev[l].n * g->lev[l].n;
+    }
+    g->ws_bytes = layout(g, nullptr);
+    *out = g;
+    return GR_OK;
+}
+
+int gr_workspace_bytes(gr_grid g, size_t *bytes)
+{
+    if (!g || !bytes) return fail(GR_EINVAL, "null argument");
+    *bytes = g->ws_bytes;
+    return GR_OK;
+}
+
+int gr_bind(gr_grid g, void *d_ws, size_t bytes, void *stream)
+{
+    if (!g || !d_ws) return fail(GR_EINVAL, "null argument");
+    if (bytes < g->ws_bytes) return fail(GR_EINVAL, "workspace %zu bytes < required %zu", bytes, g->ws_bytes);
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(GR_EINVAL, "workspace not 256-byte aligned");
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, d_ws) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return fail(GR_EINVAL, "workspace is not device memory");
+    }
+    g->stream = reinterpret_cast<hipStream_t>(stream);
+    layout(g, reinterpret_cast<char *>(d_ws));
+    launch_fill(g->stream, reinterpret_cast<double *>(d_ws), (long)(g->ws_bytes / sizeof(double)), 0.0);
+    LAUNCHCHK();
+    g->bound = true;
+    return GR_OK;
+}
+
+int gr_destroy_grid(gr_grid g)
+{
+    delete g;
+    return GR_OK;
+}
+
+int gr_deposit_sources(gr_grid g, const double *d_pos, const double *d_u, double mass, int64_t np)
+{
+    CHK(check_bound(g));
+    if (np < 0 || (np > 0 && (!d_pos || !d_u))) return fail(GR_EINVAL, "bad particle arrays");
+    if (!std::isfinite(mass)) return fail(GR_EINVAL, "mass not finite");
+    const long N = g->N();
+    for (int c = 0; c < 5; ++c) launch_fill(g->stream, g->src[c], N, 0.0);
+    launch_cic_deposit(g->stream, g->n, g->prm.a, g->prm.c_tilde, d_pos, d_u, mass, (long)np, g->field[GR_PSI],
+                       g->src[0], g->src[1], g->src[2], g->src[3], g->src[4]);
+    LAUNCHCHK();
+    return GR_OK;
+}
+
+int gr_set_field(gr_grid g, int field, const void *d_src, int dtype)
+{
+    CHK(check_bound(g));
+    double *dst = slot_ptr(g, field);
+    if (!dst) return fail(GR_EINVAL, "field %d cannot be set", field);
+    if (!d_src) return fail(GR_EINVAL, "null source");
+    if (dtype == GR_F64) launch_copy(g->stream, dst, static_cast<const double *>(d_src), g->N());
+    else if (dtype == GR_F32) launch_convert_f32_to_f64(g->stream, dst, static_cast<const float *>(d_src), g->N());
+    else return fail(GR_EINVAL, "bad dtype %d", dtype);
+    LAUNCHCHK();
+    return GR_OK;
+}
+
+int gr_get_field(gr_grid g, int field, void *d_dst, int dtype)
+{
+    CHK(check_bound(g));
+    if (!d_dst) return fail(GR_EINVAL, "null destination");
+    if (dtype != GR_F64 && dtype != GR_F32) return fail(GR_EINVAL, "bad dtype %d", dtype);
+    const long N = g->N();
+    const double *srcp = slot_ptr(g, field);
+    double *tmp = g->lev[0].tmp;
+    if (!srcp) {
+        if (field < GR_PHI || field > GR_BETAZ) return fail(GR_EINVAL, "unknown field %d", field);
+        const int which = field - GR_PHI; // 0 Phi, 1 alpha, 2 psi, 3..5 beta
+        const double *Bc = which >= 3 ? g->field[GR_BX + (which - 3)] : nullptr;
+        double *out = dtype == GR_F64 ? static_cast<double *>(d_dst) : tmp;
+        launch_derived(g->stream, which, out, g->field[GR_PSI], g->field[GR_XI], Bc, g->field[GR_BB], g->n, g->h,
+                       g->prm.a, g->prm.c_tilde);
+        if (dtype == GR_F32) launch_convert_f64_to_f32(g->stream, static_cast<float *>(d_dst), tmp, N);
+        LAUNCHCHK();
+        return GR_OK;
+    }
+    if (dtype == GR_F64) launch_copy(g->stream, static_cast<double *>(d_dst), srcp, N);
+    else launch_convert_f64_to_f32(g->stream, static_cast<float *>(d_dst), srcp, N);
+    LAUNCHCHK();
+    return GR_OK;
+}
+
+int gr_solve_equation(gr_grid g, int kind, int field, const gr_solve_opts *opts, gr_solve_report *rep)
+{
+    CHK(check_bound(g));
+    CHK(check_opts(opts));
+    if (kind < 0 || kind > 2) return fail(GR_EINVAL, "bad kind %d", kind);
+    if (field < 0 || field > 9) return fail(GR_EINVAL, "bad field %d", field);
+    auto t0 = std::chrono::steady_clock::now();
+    if (opts->guess == GR_GUESS_ZERO) launch_fill(g->stream, g->field[field], g->N(), 0.0);
+    int cyc = 0;
+    double rel = 0.0;
+    int st = solve_one(g, kind, g->field[field], *opts, &cyc, &rel);
+    if (st != GR_EDEVICE) {
+        hipError_t e = hipStreamSynchronize(g->stream);
+        if (e != hipSuccess) st = fail(GR_EDEVICE, "sync: %s", hipGetErrorString(e));
+    }
+    if (rep) {
+        std::memset(rep, 0, sizeof *rep);
+        rep->status = st;
+        rep->cycles[0] = cyc;
+        rep->rel_res[0] = rel;
+        rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return st;
+}
+
+int gr_solve_constraints(gr_grid g, const gr_solve_opts *opts, gr_solve_report *rep)
+{
+    CHK(check_bound(g));
+    CHK(check_opts(opts));
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = g->stream;
+    const long N = g->N();
+    const double a = g->prm.a, om = g->prm.omega_m, c = g->prm.c_tilde;
+    const unsigned mask = opts->field_mask;
+    gr_solve_report R;
+    std::memset(&R, 0, sizeof R);
+    int first_bad = GR_OK;
+    if (opts->guess == GR_GUESS_ZERO)
+        for (int f = 0; f < 10; ++f)
+            if (mask & (1u << f)) launch_fill(s, g->field[f], N, 0.0);
+    LAUNCHCHK();
+    double *fine_f = g->lev[0].f;
+    double *fine_c = g->lev[0].coef;
+
+    auto solve = [&](int fid, int kind) -> int {
+        if (!(mask & (1u << fid))) return GR_OK;
+        int st = solve_one(g, kind, g->field[fid], *opts, &R.cycles[fid], &R.rel_res[fid]);
+        if (st == GR_EDEVICE) return st;
+        if (st != GR_OK && first_bad == GR_OK) first_bad = st;
+        return GR_OK;
+    };
+
+    // 1. V_i: Lap V_i = 3 Om a (s_i - <s_i>)
+    for (int d = 0; d < 3; ++d) {
+        if (!(mask & (1u << (GR_VX + d)))) continue;
+        CHK(reduce_mean(g, g->src[1 + d], nullptr, N, g->scal + S_SCRATCH));
+        launch_shift_scale(s, fine_f, g->src[1 + d], N, 3.0 * om * a, g->scal + S_SCRATCH);
+        LAUNCHCHK();
+        CHK(solve(GR_VX + d, GR_KIND_POISSON));
+    }
+    // 2. U: Lap U = -1/4 d_j V^j
+    launch_div_quarter(s, fine_f, g->field[GR_VX], g->field[GR_VY], g->field[GR_VZ], g->n, g->h);
+    LAUNCHCHK();
+    CHK(solve(GR_U, GR_KIND_POISSON));
+    // 3. A_ij and AA
+    launch_build_Aij(s, g->A6, g->AA, g->field[GR_VX], g->field[GR_VY], g->field[GR_VZ], g->field[GR_U], g->n, g->h);
+    // 4. Psi: f = 3/2 a Om (s0 - 1), coefficient AA
+    launch_ham_rhs(s, fine_f, g->src[0], N, 1.5 * a * om);
+    launch_copy(s, fine_c, g->AA, N);
+    LAUNCHCHK();
+    CHK(solve(GR_PSI, GR_KIND_HAMILTONIAN));
+    // 5. xi: CMC with m2 and f from the solved Psi
+    launch_build_cmc(s, fine_c, fine_f, g->field[GR_PSI], g->src[0], g->src[4], g->AA, N, a, om, c);
+    LAUNCHCHK();
+    CHK(solve(GR_XI, GR_KIND_CMC));
+    // 6. B^i: Lap B^i = 2 d_j[alpha chi^-6 A^ij]
+    launch_shift_source(s, g->fB, g->field[GR_PSI], g->field[GR_XI], g->A6, g->n, g->h, a, c);
+    LAUNCHCHK();
+    for (int d = 0; d < 3; ++d) {
+        if (!(mask & (1u << (GR_BX + d)))) continue;
+        launch_copy(s, fine_f, g->fB[d], N);
+        LAUNCHCHK();
+        CHK(solve(GR_BX + d, GR_KIND_POISSON));
+    }
+    // 7. b: Lap b = -1/4 d_j B^j
+    launch_div_quarter(s, fine_f, g->field[GR_BX], g->field[GR_BY], g->field[GR_BZ], g->n, g->h);
+    LAUNCHCHK();
+    CHK(solve(GR_BB, GR_KIND_POISSON));
+    HIPCHK(hipStreamSynchronize(s));
+    R.status = first_bad;
+    R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = R;
+    if (first_bad != GR_OK && g_err.empty()) fail(first_bad, "a field did not converge");
+    return first_bad;
+}
+
+int gr_debug_sweep(gr_grid g, int kind, int field, double Fbar, double fshift, int nsweeps)
+{
+    CHK(check_bound(g));
+    if (kind < 0 || kind > 2 || field < 0 || field > 9 || nsweeps < 0) return fail(GR_EINVAL, "bad argument");
+    hipStream_t s = g->stream;
+    launch_set_scalar(s, g->scal + S_FBAR, Fbar);
+    launch_set_scalar(s, g->scal + S_FSHIFT, fshift);
+    Level &F = g->lev[0];
+    OpConst oc = g->oc();
+    for (int it = 0; it < nsweeps; ++it)
+        launch_rb_sweep(kind, s, g->field[field], F.f, F.coef, F.n, F.h, oc, g->scal + S_FBAR, g->scal + S_FSHIFT);
+    LAUNCHCHK();
+    return GR_OK;
+}
+
+int gr_debug_residual(gr_grid g, int kind, int field, double Fbar, double fshift, double *d_out)
+{
+    CHK(check_bound(g));
+    if (kind < 0 || kind > 2 || field < 0 || field > 9 || !d_out) return fail(GR_EINVAL, "bad argument");
+    hipStream_t s = g->stream;
+    launch_set_scalar(s, g->scal + S_FBAR, Fbar);
+    launch_set_scalar(s, g->scal + S_FSHIFT, fshift);
+    Level &F = g->lev[0];
+    launch_residual(kind, s, g->field[field], F.f, F.coef, F.n, F.h, g->oc(), g->scal + S_FBAR, g->scal + S_FSHIFT,
+                    d_out);
+    LAUNCHCHK();
+    return GR_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,289 @@
+// Source and coefficient builders for the ten field equations, the CIC
+// matter deposit, and the derived fields (paper sec. 4.1.2, 4.3, 4.5).
+#include "gr_internal.h"
+
+namespace grmg {
+
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+__device__ __forceinline__ long lin(int i, int j, int k, int n) { return ((long)k * n + j) * n + i; }
+
+// Central difference of g along `dir` at (i,j,k): (g_+ - g_-)/(2h).
+__device__ __forceinline__ double dcen(const double *__restrict__ g, int dir, int i, int j, int k, int n,
+                                       double inv2h)
+{
+    const int di = dir == 0, dj = dir == 1, dk = dir == 2;
+    return (g[lin(wrapi(i + di, n), wrapi(j + dj, n), wrapi(k + dk, n), n)]
+            - g[lin(wrapi(i - di, n), wrapi(j - dj, n), wrapi(k - dk, n), n)]) * inv2h;
+}
+
+__device__ __forceinline__ int wrap_any(long i, int n)
+{
+    long r = i % n;
+    return (int)(r < 0 ? r + n : r);
+}
+
+// ------------------------------------------------------------------- CIC
+
+// One thread per particle.  Cell-centred CIC: g = x/h - 1/2, i0 = floor(g),
+// t = g - i0, weights (1-t, t) on cells (i0, i0+1), periodic.  chi at the
+// particle from the CIC-interpolated Psi; W^2 = c^2 + a^-2 chi^-4 u.u.
+__global__ void __launch_bounds__(TPB) k_cic(int n, double a, double c, double kap, const double *__restrict__ pos,
+                                             const double *__restrict__ u, double mass, long np,
+                                             const double *__restrict__ psi, double *__restrict__ s0,
+                                             double *__restrict__ sx, double *__restrict__ sy,
+                                             double *__restrict__ sz, double *__restrict__ sm)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= np) return;
+    const double h = 1.0 / n;
+    int i0[3], i1[3];
+    double t[3];
+    for (int d = 0; d < 3; ++d) {
+        const double g = pos[3 * q + d] * n - 0.5;
+        const double fl = floor(g);
+        t[d] = g - fl;
+        // fl is finite for finite positions; wrap_any keeps any index in range
+        const long il = isfinite(fl) ? (long)fl : 0;
+        i0[d] = wrap_any(il, n);
+        i1[d] = wrap_any(il + 1, n);
+    }
+    double psi_p = 0.0;
+    for (int cc = 0; cc < 8; ++cc) {
+        const int ox = cc & 1, oy = (cc >> 1) & 1, oz = cc >> 2;
+        const double w = (ox ? t[0] : 1.0 - t[0]) * (oy ? t[1] : 1.0 - t[1]) * (oz ? t[2] : 1.0 - t[2]);
+        psi_p += w * psi[lin(ox ? i1[0] : i0[0], oy ? i1[1] : i0[1], oz ? i1[2] : i0[2], n)];
+    }
+    const double chi = 1.0 - kap * psi_p;
+    const double chi2 = chi * chi;
+    const double ux = u[3 * q], uy = u[3 * q + 1], uz = u[3 * q + 2];
+    const double u2 = ux * ux + uy * uy + uz * uz;
+    const double g_uu = u2 / (a * a * chi2 * chi2); // gamma^ij u_i u_j
+    const double W = sqrt(c * c + g_uu);
+    const double vol = h * h * h;
+    const double q0 = mass * W / (c * vol);
+    const double qx = mass * ux / (c * vol);
+    const double qy = mass * uy / (c * vol);
+    const double qz = mass * uz / (c * vol);
+    const double qm = mass * g_uu / (W * c * vol); // stress trace gamma^ij s_ij
+    for (int cc = 0; cc < 8; ++cc) {
+        const int ox = cc & 1, oy = (cc >> 1) & 1, oz = cc >> 2;
+        const double w = (ox ? t[0] : 1.0 - t[0]) * (oy ? t[1] : 1.0 - t[1]) * (oz ? t[2] : 1.0 - t[2]);
+        const long p = lin(ox ? i1[0] : i0[0], oy ? i1[1] : i0[1], oz ? i1[2] : i0[2], n);
+        unsafeAtomicAdd(s0 + p, w * q0);
+        unsafeAtomicAdd(sx + p, w * qx);
+        unsafeAtomicAdd(sy + p, w * qy);
+        unsafeAtomicAdd(sz + p, w * qz);
+        unsafeAtomicAdd(sm + p, w * qm);
+    }
+}
+
+// ----------------------------------------------------------------- builders
+
+__global__ void k_shift_scale(double *__restrict__ out, const double *__restrict__ in, long N, double scale,
+                              const double *__restrict__ mean)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < N) out[p] = scale * (in[p] - *mean);
+}
+
+// -1/4 d_j g^j
+__global__ void k_div_quarter(double *__restrict__ out, const double *__restrict__ gx,
+                              const double *__restrict__ gy, const double *__restrict__ gz, int n, double inv2h)
+{
+    const long N = (long)n * n * n;
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int i = (int)(p % n), j = (int)((p / n) % n), k = (int)(p / ((long)n * n));
+    out[p] = -0.25 * (dcen(gx, 0, i, j, k, n, inv2h) + dcen(gy, 1, i, j, k, n, inv2h) + dcen(gz, 2, i, j, k, n, inv2h));
+}
+
+struct A6Ptrs {
+    double *c[6];
+};
+
+// A_ij = d_iV_j + d_jV_i - 1/2 delta_ij d_kV^k + 2 d_i d_j U  (packed xx,yy,zz,xy,xz,yz)
+// diagonal d_i d_i U: 3-point; off-diagonal: 4-point diagonal-neighbour formula.
+__global__ void __launch_bounds__(TPB) k_build_Aij(A6Ptrs A6, double *__restrict__ AA,
+                                                   const double *__restrict__ Vx, const double *__restrict__ Vy,
+                                                   const double *__restrict__ Vz, const double *__restrict__ U,
+                                                   int n, double h)
+{
+    const long N = (long)n * n * n;
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int i = (int)(p % n), j = (int)((p / n) % n), k = (int)(p / ((long)n * n));
+    const double inv2h = 1.0 / (2.0 * h), invh2 = 1.0 / (h * h), inv4h2 = 1.0 / (4.0 * h * h);
+    const double *V[3] = {Vx, Vy, Vz};
+    double dV[3][3]; // dV[a][b] = d_a V_b
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) dV[a][b] = dcen(V[b], a, i, j, k, n, inv2h);
+    const double divV = dV[0][0] + dV[1][1] + dV[2][2];
+    const int ip = wrapi(i + 1, n), im = wrapi(i - 1, n), jp = wrapi(j + 1, n), jm = wrapi(j - 1, n);
+    const int kp = wrapi(k + 1, n), km = wrapi(k - 1, n);
+    const double u0 = U[p];
+    const double uxx = (U[lin(ip, j, k, n)] - 2.0 * u0 + U[lin(im, j, k, n)]) * invh2;
+    const double uyy = (U[lin(i, jp, k, n)] - 2.0 * u0 + U[lin(i, jm, k, n)]) * invh2;
+    const double uzz = (U[lin(i, j, kp, n)] - 2.0 * u0 + U[lin(i, j, km, n)]) * invh2;
+    const double uxy = (U[lin(ip, jp, k, n)] + U[lin(im, jm, k, n)] - U[lin(ip, jm, k, n)] - U[lin(im, jp, k, n)]) * inv4h2;
+    const double uxz = (U[lin(ip, j, kp, n)] + U[lin(im, j, km, n)] - U[lin(ip, j, km, n)] - U[lin(im, j, kp, n)]) * inv4h2;
+    const double uyz = (U[lin(i, jp, kp, n)] + U[lin(i, jm, km, n)] - U[lin(i, jp, km, n)] - U[lin(i, jm, kp, n)]) * inv4h2;
+    const double axx = 2.0 * dV[0][0] + 2.0 * uxx - 0.5 * divV;
+    const double ayy = 2.0 * dV[1][1] + 2.0 * uyy - 0.5 * divV;
+    const double azz = 2.0 * dV[2][2] + 2.0 * uzz - 0.5 * divV;
+    const double axy = dV[0][1] + dV[1][0] + 2.0 * uxy;
+    const double axz = dV[0][2] + dV[2][0] + 2.0 * uxz;
+    const double ayz = dV[1][2] + dV[2][1] + 2.0 * uyz;
+    A6.c[0][p] = axx;
+    A6.c[1][p] = ayy;
+    A6.c[2][p] = azz;
+    A6.c[3][p] = axy;
+    A6.c[4][p] = axz;
+    A6.c[5][p] = ayz;
+    AA[p] = axx * axx + ayy * ayy + azz * azz + 2.0 * (axy * axy + axz * axz + ayz * ayz);
+}
+
+__global__ void k_ham_rhs(double *__restrict__ f, const double *__restrict__ s0, long N, double A)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < N) f[p] = A * (s0[p] - 1.0);
+}
+
+// CMC coefficient m2 = chi^-1 Q/(a^2c^2) and source
+// f = 3/2 a Om chi^-1 [s0 - chi^6 + s_m] + AA chi^-7, with
+// Q = 3/4 a Om chi^-1 [s0 + 5 chi^6 + 2 s_m] + 7/8 AA chi^-7.
+__global__ void k_build_cmc(double *__restrict__ m2, double *__restrict__ f, const double *__restrict__ psi,
+                            const double *__restrict__ s0, const double *__restrict__ sm,
+                            const double *__restrict__ AA, long N, double a, double om, double c)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const double kap = 1.0 / (2.0 * a * a * c * c);
+    const double chi = 1.0 - kap * psi[p];
+    const double chi2 = chi * chi, chi6 = chi2 * chi2 * chi2;
+    const double chim7 = 1.0 / (chi6 * chi);
+    const double Q = 0.75 * a * om / chi * (s0[p] + 5.0 * chi6 + 2.0 * sm[p]) + 0.875 * AA[p] * chim7;
+    m2[p] = Q / (chi * a * a * c * c);
+    f[p] = 1.5 * a * om / chi * (s0[p] - chi6 + sm[p]) + AA[p] * chim7;
+}
+
+// f_B^i = 2 sum_j d_j[alpha chi^-6 A_ij], alpha = 1 + (xi/chi)/(a^2c^2).
+__global__ void __launch_bounds__(TPB) k_shift_source(double *__restrict__ fBx, double *__restrict__ fBy,
+                                                      double *__restrict__ fBz, const double *__restrict__ psi,
+                                                      const double *__restrict__ xi, A6Ptrs A6, int n, double h,
+                                                      double a, double c)
+{
+    const long N = (long)n * n * n;
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int i = (int)(p % n), j = (int)((p / n) % n), k = (int)(p / ((long)n * n));
+    const double kap = 1.0 / (2.0 * a * a * c * c), ia2c2 = 1.0 / (a * a * c * c), inv2h = 1.0 / (2.0 * h);
+    // (row, col) -> packed component
+    const int comp[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    double out[3] = {0.0, 0.0, 0.0};
+    for (int col = 0; col < 3; ++col) {
+        const int di = col == 0, dj = col == 1, dk = col == 2;
+        const long pp = lin(wrapi(i + di, n), wrapi(j + dj, n), wrapi(k + dk, n), n);
+        const long pm = lin(wrapi(i - di, n), wrapi(j - dj, n), wrapi(k - dk, n), n);
+        double g[2];
+        const long ps[2] = {pp, pm};
+        for (int s = 0; s < 2; ++s) {
+            const double chi = 1.0 - kap * psi[ps[s]];
+            const double chi2 = chi * chi, chi6 = chi2 * chi2 * chi2;
+            const double alpha = 1.0 + (xi[ps[s]] / chi) * ia2c2;
+            g[s] = alpha / chi6;
+        }
+        for (int row = 0; row < 3; ++row) {
+            const double *Ac = A6.c[comp[row][col]];
+            out[row] += (g[0] * Ac[pp] - g[1] * Ac[pm]) * inv2h;
+        }
+    }
+    fBx[p] = 2.0 * out[0];
+    fBy[p] = 2.0 * out[1];
+    fBz[p] = 2.0 * out[2];
+}
+
+// derived fields: 0 Phi = xi/chi, 1 alpha = 1 + Phi/(a^2c^2), 2 psi = a^(1/2) chi,
+// 3 beta component = B + d_dir b (dir passed as which-3)
+__global__ void k_derived(int which, double *__restrict__ out, const double *__restrict__ psi,
+                          const double *__restrict__ xi, const double *__restrict__ Bc,
+                          const double *__restrict__ b, int n, double h, double a, double c)
+{
+    const long N = (long)n * n * n;
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const double kap = 1.0 / (2.0 * a * a * c * c);
+    if (which <= 2) {
+        const double chi = 1.0 - kap * psi[p];
+        if (which == 0) out[p] = xi[p] / chi;
+        else if (which == 1) out[p] = 1.0 + (xi[p] / chi) / (a * a * c * c);
+        else out[p] = sqrt(a) * chi;
+    } else {
+        const int dir = which - 3;
+        const int i = (int)(p % n), j = (int)((p / n) % n), k = (int)(p / ((long)n * n));
+        out[p] = Bc[p] + dcen(b, dir, i, j, k, n, 1.0 / (2.0 * h));
+    }
+}
+
+inline unsigned blocks_for(long count) { return (unsigned)((count + TPB - 1) / TPB); }
+
+} // namespace
+
+void launch_cic_deposit(hipStream_t s, int n, double a, double c_tilde, const double *pos, const double *u,
+                        double mass, long np, const double *psi, double *s0, double *sx, double *sy, double *sz,
+                        double *sm)
+{
+    const double kap = 1.0 / (2.0 * a * a * c_tilde * c_tilde);
+    if (np > 0)
+        k_cic<<<blocks_for(np), TPB, 0, s>>>(n, a, c_tilde, kap, pos, u, mass, np, psi, s0, sx, sy, sz, sm);
+}
+
+void launch_shift_scale(hipStream_t s, double *out, const double *in, long N, double scale, const double *mean)
+{
+    k_shift_scale<<<blocks_for(N), TPB, 0, s>>>(out, in, N, scale, mean);
+}
+
+void launch_div_quarter(hipStream_t s, double *out, const double *gx, const double *gy, const double *gz, int n,
+                        double h)
+{
+    k_div_quarter<<<blocks_for((long)n * n * n), TPB, 0, s>>>(out, gx, gy, gz, n, 1.0 / (2.0 * h));
+}
+
+void launch_build_Aij(hipStream_t s, double *const A6[6], double *AA, const double *Vx, const double *Vy,
+                      const double *Vz, const double *U, int n, double h)
+{
+    A6Ptrs P;
+    for (int c = 0; c < 6; ++c) P.c[c] = A6[c];
+    k_build_Aij<<<blocks_for((long)n * n * n), TPB, 0, s>>>(P, AA, Vx, Vy, Vz, U, n, h);
+}
+
+void launch_ham_rhs(hipStream_t s, double *f, const double *s0, long N, double A)
+{
+    k_ham_rhs<<<blocks_for(N), TPB, 0, s>>>(f, s0, N, A);
+}
+
+void launch_build_cmc(hipStream_t s, double *m2, double *f, const double *psi, const double *s0, const double *sm,
+                      const double *AA, long N, double a, double om, double c_tilde)
+{
+    k_build_cmc<<<blocks_for(N), TPB, 0, s>>>(m2, f, psi, s0, sm, AA, N, a, om, c_tilde);
+}
+
+void launch_shift_source(hipStream_t s, double *fB[3], const double *psi, const double *xi, double *const A6[6],
+                         int n, double h, double a, double c_tilde)
+{
+    A6Ptrs P;
+    for (int c = 0; c < 6; ++c) P.c[c] = A6[c];
+    k_shift_source<<<blocks_for((long)n * n * n), TPB, 0, s>>>(fB[0], fB[1], fB[2], psi, xi, P, n, h, a, c_tilde);
+}
+
+void launch_derived(hipStream_t s, int which, double *out, const double *psi, const double *xi, const double *Bc,
+                    const double *b, int n, double h, double a, double c_tilde)
+{
+    k_derived<<<blocks_for((long)n * n * n), TPB, 0, s>>>(which, out, psi, xi, Bc, b, n, h, a, c_tilde);
+}
+
+} // namespace grmg

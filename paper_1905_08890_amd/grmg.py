@@ -1,0 +1,246 @@
+"""ctypes binding of libgrmg.so (C ABI in include/gr.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library.
+PyTorch supplies device memory (the workspace and the caller's tensors) and
+the HIP stream.  Importing this module does not touch the GPU; the library
+is loaded on first use and a missing library raises immediately - there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgrmg.so")
+
+# ---- constants mirrored from gr.h ----
+OK, EINVAL, EDEVICE, ENOTCONV, ENAN, ESTATE = 0, -1, -2, -3, -4, -6
+POISSON, HAMILTONIAN, CMC = 0, 1, 2
+(VX, VY, VZ, U, PSI, XI, BX, BY, BZ, BB, S0, SX, SY, SZ, SM, AA, PHI, ALPHA, CONF, BETAX, BETAY, BETAZ,
+ RHS, COEF) = range(24)
+F64, F32 = 0, 1
+FP64, MIXED = 0, 1
+GUESS_ZERO, GUESS_CURRENT = 0, 1
+ALL_FIELDS = 0x3FF
+SOLVED = ("Vx", "Vy", "Vz", "U", "Psi", "xi", "Bx", "By", "Bz", "b")
+FIELD_IDS = {name: i for i, name in enumerate(SOLVED)}
+FIELD_IDS.update(dict(s0=S0, sx=SX, sy=SY, sz=SZ, sm=SM, AA=AA, Phi=PHI, alpha=ALPHA, psi_conf=CONF,
+                      beta_x=BETAX, beta_y=BETAY, beta_z=BETAZ, rhs=RHS, coef=COEF))
+
+EXPORTS = ("gr_default_opts", "gr_create_grid", "gr_workspace_bytes", "gr_bind", "gr_deposit_sources",
+           "gr_set_field", "gr_get_field", "gr_solve_constraints", "gr_solve_equation", "gr_debug_sweep",
+           "gr_debug_residual", "gr_destroy_grid", "gr_last_error")
+
+
+class GrParams(C.Structure):
+    _fields_ = [("a", C.c_double), ("omega_m", C.c_double), ("c_tilde", C.c_double)]
+
+
+class GrGridDesc(C.Structure):
+    _fields_ = [("n", C.c_int), ("h", C.c_double)]
+
+
+class GrSolveOpts(C.Structure):
+    _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("max_cycles", C.c_int), ("rtol", C.c_double),
+                ("precision", C.c_int), ("guess", C.c_int), ("field_mask", C.c_uint)]
+
+
+class GrSolveReport(C.Structure):
+    _fields_ = [("status", C.c_int), ("cycles", C.c_int * 10), ("rel_res", C.c_double * 10),
+                ("seconds", C.c_double), ("fallback", C.c_int)]
+
+    def as_dict(self):
+        return dict(status=self.status, cycles=list(self.cycles), rel_res=list(self.rel_res),
+                    seconds=self.seconds, fallback=self.fallback)
+
+
+class GrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"gr error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgrmg.so and declare its signatures (no GPU work)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run __graft_entry__.build() (no CPU fallback exists)")
+    lib = C.CDLL(path)
+    vp, i64 = C.c_void_p, C.c_int64
+    sig = {
+        "gr_default_opts": [C.POINTER(GrSolveOpts)],
+        "gr_create_grid": [C.POINTER(GrGridDesc), C.POINTER(GrParams), C.POINTER(vp)],
+        "gr_workspace_bytes": [vp, C.POINTER(C.c_size_t)],
+        "gr_bind": [vp, vp, C.c_size_t, vp],
+        "gr_deposit_sources": [vp, vp, vp, C.c_double, i64],
+        "gr_set_field": [vp, C.c_int, vp, C.c_int],
+        "gr_get_field": [vp, C.c_int, vp, C.c_int],
+        "gr_solve_constraints": [vp, C.POINTER(GrSolveOpts), C.POINTER(GrSolveReport)],
+        "gr_solve_equation": [vp, C.c_int, C.c_int, C.POINTER(GrSolveOpts), C.POINTER(GrSolveReport)],
+        "gr_debug_sweep": [vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int],
+        "gr_debug_residual": [vp, C.c_int, C.c_int, C.c_double, C.c_double, vp],
+        "gr_destroy_grid": [vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    lib.gr_last_error.argtypes = []
+    lib.gr_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load_library().gr_last_error().decode()
+
+
+def _check(code: int, allow=(OK,)):
+    if code not in allow:
+        raise GrError(code, last_error())
+    return code
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+# ---- one function per ABI entry point ----
+
+def default_opts(**kw) -> GrSolveOpts:
+    o = GrSolveOpts()
+    _check(load_library().gr_default_opts(C.byref(o)))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": FP64, "mixed": MIXED}[v]
+        if k == "guess" and isinstance(v, str):
+            v = {"zero": GUESS_ZERO, "current": GUESS_CURRENT}[v]
+        setattr(o, k, v)
+    return o
+
+
+def create_grid(n: int, a: float, omega_m: float, c_tilde: float, h: float | None = None) -> int:
+    g = C.c_void_p()
+    _check(load_library().gr_create_grid(C.byref(GrGridDesc(n, h if h is not None else 1.0 / n)),
+                                         C.byref(GrParams(a, omega_m, c_tilde)), C.byref(g)))
+    return g.value
+
+
+def workspace_bytes(g: int) -> int:
+    b = C.c_size_t()
+    _check(load_library().gr_workspace_bytes(g, C.byref(b)))
+    return b.value
+
+
+def bind(g: int, workspace, stream: int) -> None:
+    _check(load_library().gr_bind(g, _ptr(workspace), workspace.numel() * workspace.element_size(), stream))
+
+
+def deposit_sources(g: int, pos, u, mass: float) -> None:
+    _check(load_library().gr_deposit_sources(g, _ptr(pos), _ptr(u), float(mass), int(pos.shape[0])))
+
+
+def set_field(g: int, field: int, src, dtype: int) -> None:
+    _check(load_library().gr_set_field(g, field, _ptr(src), dtype))
+
+
+def get_field(g: int, field: int, dst, dtype: int) -> None:
+    _check(load_library().gr_get_field(g, field, _ptr(dst), dtype))
+
+
+def solve_constraints(g: int, opts: GrSolveOpts, allow=(OK,)) -> GrSolveReport:
+    r = GrSolveReport()
+    _check(load_library().gr_solve_constraints(g, C.byref(opts), C.byref(r)), allow)
+    return r
+
+
+def solve_equation(g: int, kind: int, field: int, opts: GrSolveOpts, allow=(OK,)) -> GrSolveReport:
+    r = GrSolveReport()
+    _check(load_library().gr_solve_equation(g, kind, field, C.byref(opts), C.byref(r)), allow)
+    return r
+
+
+def debug_sweep(g: int, kind: int, field: int, Fbar: float, fshift: float, nsweeps: int) -> None:
+    _check(load_library().gr_debug_sweep(g, kind, field, Fbar, fshift, nsweeps))
+
+
+def debug_residual(g: int, kind: int, field: int, Fbar: float, fshift: float, out) -> None:
+    _check(load_library().gr_debug_residual(g, kind, field, Fbar, fshift, _ptr(out)))
+
+
+def destroy_grid(g: int) -> None:
+    _check(load_library().gr_destroy_grid(g))
+
+
+# ---- convenience owner of a grid + torch workspace ----
+
+class Grid:
+    """A periodic n^3 grid bound to a torch-allocated workspace on `device`."""
+
+    def __init__(self, n: int, a: float = 1.0, omega_m: float = 0.3072, c_tilde: float = 2997.92458 / 256.0,
+                 h: float | None = None, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.n = n
+        self.device = torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU device (no CPU fallback)")
+        self.handle = create_grid(n, a, omega_m, c_tilde, h)
+        nbytes = workspace_bytes(self.handle)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        bind(self.handle, self.workspace, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            destroy_grid(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, x, dtype):
+        t = self.torch
+        if not isinstance(x, t.Tensor):
+            x = t.as_tensor(x)
+        return x.to(device=self.device, dtype=dtype).contiguous()
+
+    def deposit_sources(self, pos, u, mass):
+        pos = self._dev(pos, self.torch.float64)
+        u = self._dev(u, self.torch.float64)
+        assert pos.shape == u.shape and pos.shape[-1] == 3
+        deposit_sources(self.handle, pos, u, mass)
+
+    def set_field(self, field, values):
+        fid = FIELD_IDS[field] if isinstance(field, str) else field
+        v = values if isinstance(values, self.torch.Tensor) else self.torch.as_tensor(values)
+        dt = F32 if v.dtype == self.torch.float32 else F64
+        v = self._dev(v, self.torch.float32 if dt == F32 else self.torch.float64)
+        assert v.numel() == self.n ** 3
+        set_field(self.handle, fid, v, dt)
+        self._keep = v  # keep alive until the stream has consumed it
+        return v
+
+    def get_field(self, field, dtype=None):
+        fid = FIELD_IDS[field] if isinstance(field, str) else field
+        dtype = dtype or self.torch.float64
+        out = self.torch.empty((self.n,) * 3, dtype=dtype, device=self.device)
+        get_field(self.handle, fid, out, F32 if dtype == self.torch.float32 else F64)
+        return out
+
+    def solve_constraints(self, allow=(OK,), **kw):
+        return solve_constraints(self.handle, default_opts(**kw), allow).as_dict()
+
+    def solve_equation(self, kind, field, allow=(OK,), **kw):
+        fid = FIELD_IDS[field] if isinstance(field, str) else field
+        return solve_equation(self.handle, kind, fid, default_opts(**kw), allow).as_dict()

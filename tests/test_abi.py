@@ -1,0 +1,68 @@
+"""CPU-side checks of the C ABI: the built library loads, exports every
+function declared in include/gr.h, and rejects bad host-side arguments
+without touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1905_08890_amd import grmg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "gr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gr_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = grmg.load_library()
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(grmg.EXPORTS)
+
+
+def test_create_grid_validation():
+    lib = grmg.load_library()
+    g = C.c_void_p()
+    prm = grmg.GrParams(1.0, 0.3, 11.7)
+    for n, h in [(7, 1 / 7), (0, 1.0), (2048, 1.0), (16, 0.0), (16, -1.0)]:
+        assert lib.gr_create_grid(C.byref(grmg.GrGridDesc(n, h)), C.byref(prm), C.byref(g)) == grmg.EINVAL
+    assert lib.gr_create_grid(C.byref(grmg.GrGridDesc(16, 1 / 16)), C.byref(grmg.GrParams(0.0, 0.3, 1.0)),
+                              C.byref(g)) == grmg.EINVAL
+    assert lib.gr_create_grid(None, C.byref(prm), C.byref(g)) == grmg.EINVAL
+
+
+def test_workspace_size_and_unbound_errors():
+    g = grmg.create_grid(32, 1.0, 0.3072, 11.7)
+    try:
+        nbytes = grmg.workspace_bytes(g)
+        # 25 fine arrays plus the level hierarchy
+        assert nbytes >= 25 * 8 * 32 ** 3
+        assert nbytes < 40 * 8 * 32 ** 3
+        lib = grmg.load_library()
+        rep = grmg.GrSolveReport()
+        assert lib.gr_solve_constraints(g, C.byref(grmg.default_opts()), C.byref(rep)) == grmg.ESTATE
+        assert lib.gr_deposit_sources(g, None, None, 1.0, 0) == grmg.ESTATE
+    finally:
+        grmg.destroy_grid(g)
+
+
+def test_default_options():
+    o = grmg.default_opts()
+    assert (o.nu1, o.nu2, o.max_cycles, o.rtol, o.precision, o.guess, o.field_mask) == \
+        (2, 2, 100, 1e-10, grmg.FP64, grmg.GUESS_ZERO, grmg.ALL_FIELDS)
+
+
+def test_no_cpu_fallback(monkeypatch):
+    """The binding refuses to run without a GPU device instead of falling back."""
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(RuntimeError):
+        grmg.Grid(8)
