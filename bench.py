@@ -77,6 +77,31 @@ def cpu_baseline(n, pos, u, mass, cycles):
     return est, sample_s
 
 
+def smoother_only(torch, grmg, n):
+    """Finest-level sweeps on seeded smooth data plus one plain copy of n^3
+    doubles (gr_set_field: reads 8 n^3 and writes 8 n^3 bytes), whose counter
+    readings calibrate the hardware byte counters."""
+    from paper_1905_08890_amd import synth
+
+    g = grmg.Grid(n, a=1.0, omega_m=synth.OMEGA_M, c_tilde=synth.C_TILDE, device="cuda:0")
+    gen = torch.Generator(device="cuda:0").manual_seed(0)
+    g.set_field("Psi", 1e-3 * torch.randn((n,) * 3, device="cuda:0", dtype=torch.float64, generator=gen))
+    g.set_field("rhs", torch.randn((n,) * 3, device="cuda:0", dtype=torch.float64, generator=gen))
+    g.set_field("coef", torch.rand((n,) * 3, device="cuda:0", dtype=torch.float64, generator=gen))
+    src = torch.zeros((n,) * 3, device="cuda:0", dtype=torch.float64)
+    torch.cuda.synchronize()
+    g.set_field("s0", src)                      # the calibration copy
+    torch.cuda.synchronize()
+    t_ham = time_sweeps(torch, grmg, g, grmg.HAMILTONIAN, 4, 3)
+    t_poi = time_sweeps(torch, grmg, g, grmg.POISSON, 4, 3)
+    N = n ** 3
+    print(json.dumps({"n": n, "copy_bytes": 16 * N,
+                      "hamiltonian_us_per_sweep": round(t_ham * 1e6, 2),
+                      "hamiltonian_GBps": round(SWEEP_BYTES["hamiltonian"] * N / t_ham / 1e9, 1),
+                      "poisson_us_per_sweep": round(t_poi * 1e6, 2),
+                      "poisson_GBps": round(SWEEP_BYTES["poisson"] * N / t_poi / 1e9, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +109,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--smoother-only", action="store_true",
+                    help="only the finest-level sweeps and a copy of known size (for hardware counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path (asked for {args.gpus})",
@@ -95,6 +122,9 @@ def main():
     from paper_1905_08890_amd import grmg, synth
 
     n = args.n
+    if args.smoother_only:
+        smoother_only(torch, grmg, n)
+        return
     seed, rms = (2, 1.0) if n == 256 else (1, 0.3)
     log(f"generating Zel'dovich particles n={n} seed={seed} rms={rms}")
     pos, u, mass = synth.zeldovich(n, seed, rms)

@@ -48,6 +48,25 @@ struct Level {
 // ---- stencil.hip launchers ----
 void launch_rb_sweep(int kind, hipStream_t s, double *phi, const double *f, const double *coef, int n,
                      double h, OpConst oc, const double *fbar, const double *fshift);
+// fused out-of-place sweep (both colours, one pass); used where fused_sweep_ok
+struct FusedCfg {
+    int min_n = 256;      // smallest level that uses it (smaller levels live in L2/MALL)
+    int tile = 1;         // 0: 64x8 tiles, 1: 32x16 tiles
+    int xcd_remap = 0;    // 1: XCD-contiguous workgroup order
+    int target_wgs = 1024;
+};
+bool fused_sweep_ok(int n, int min_n);
+void launch_rb_fused(int kind, hipStream_t s, const double *in, double *out, const double *f, const double *coef,
+                     int n, double h, OpConst oc, const double *fbar, const double *fshift, const FusedCfg &cfg);
+// The whole V-cycle from a small level down, in one single-workgroup launch.
+struct CoarseLevels {
+    int nl;                    // levels held (first = the level the cycle starts on)
+    int n[kMaxLevels];
+    double inv_h2[kMaxLevels];
+    double *phi[kMaxLevels], *phi0[kMaxLevels], *f[kMaxLevels], *coef[kMaxLevels], *tmp[kMaxLevels];
+};
+void launch_coarse_vcycle(int kind, hipStream_t s, const CoarseLevels &C, int nu1, int nu2, OpConst oc,
+                          const double *fbar0, const double *fshift0);
 void launch_residual_restrict(int kind, hipStream_t s, const double *phi, const double *f,
                               const double *coef, int n, double h, OpConst oc, const double *fbar,
                               const double *fshift, double *phi_c, double *phi0_c, double *rr_c);

@@ -6,6 +6,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -70,6 +72,9 @@ struct gr_grid_s {
     double *scal = nullptr;
     hipStream_t stream = nullptr;
     bool bound = false;
+    bool fused = true;     // fused tile smoother on large levels
+    FusedCfg fcfg;
+    int coarse_n = 16;     // levels with n <= coarse_n run in one single-workgroup launch
     size_t ws_bytes = 0;
 
     long N() const { return (long)n * n * n; }
@@ -153,10 +158,53 @@ struct EqCtx {
 const double *fbar_ptr(gr_grid g, int l) { return g->scal + (l == 0 ? S_FBAR : S_ZERO); }
 const double *fshift_ptr(gr_grid g, int l) { return g->scal + (l == 0 ? S_FSHIFT : S_ZERO); }
 
+// nsweeps red-black sweeps of level l on L.phi.  The fused kernel works out
+// of place, alternating between L.phi and L.tmp; an odd count ends with a copy
+// back so that the iterate always ends in L.phi.
+int smooth(gr_grid g, const EqCtx &E, int l, int nsweeps)
+{
+    Level &L = g->lev[l];
+    hipStream_t s = g->stream;
+    if (nsweeps <= 0) return GR_OK;
+    if (!g->fused || !fused_sweep_ok(L.n, g->fcfg.min_n)) {
+        for (int it = 0; it < nsweeps; ++it)
+            launch_rb_sweep(E.kind, s, L.phi, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l));
+        LAUNCHCHK();
+        return GR_OK;
+    }
+    double *a = L.phi, *b = L.tmp;
+    for (int it = 0; it < nsweeps; ++it) {
+        launch_rb_fused(E.kind, s, a, b, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l), g->fcfg);
+        double *t = a;
+        a = b;
+        b = t;
+    }
+    if (a != L.phi) launch_copy(s, L.phi, a, L.N);
+    LAUNCHCHK();
+    return GR_OK;
+}
+
 int vcycle(gr_grid g, const EqCtx &E, int l)
 {
     Level &L = g->lev[l];
     hipStream_t s = g->stream;
+    if (L.n <= g->coarse_n) {
+        CoarseLevels C;
+        C.nl = g->nlev - l;
+        for (int i = 0; i < C.nl; ++i) {
+            const Level &V = g->lev[l + i];
+            C.n[i] = V.n;
+            C.inv_h2[i] = 1.0 / (V.h * V.h);
+            C.phi[i] = V.phi;
+            C.phi0[i] = V.phi0;
+            C.f[i] = V.f;
+            C.coef[i] = V.coef;
+            C.tmp[i] = V.tmp;
+        }
+        launch_coarse_vcycle(E.kind, s, C, E.nu1, E.nu2, E.oc, fbar_ptr(g, l), fshift_ptr(g, l));
+        LAUNCHCHK();
+        return GR_OK;
+    }
     if (l == g->nlev - 1) {
         // coarsest: 32 sweeps, then remove the mean of the correction
         launch_copy(s, L.tmp, L.phi, L.N);
@@ -167,8 +215,7 @@ int vcycle(gr_grid g, const EqCtx &E, int l)
         LAUNCHCHK();
         return GR_OK;
     }
-    for (int it = 0; it < E.nu1; ++it)
-        launch_rb_sweep(E.kind, s, L.phi, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l));
+    CHK(smooth(g, E, l, E.nu1));
     Level &C = g->lev[l + 1];
     // R phi -> C.phi and C.phi0; R eps -> C.tmp; then f^H = L^H(R phi) - R eps
     launch_residual_restrict(E.kind, s, L.phi, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l),
@@ -177,10 +224,8 @@ int vcycle(gr_grid g, const EqCtx &E, int l)
     LAUNCHCHK();
     CHK(vcycle(g, E, l + 1));
     launch_prolong_correct(s, L.phi, L.n, C.phi, C.phi0);
-    for (int it = 0; it < E.nu2; ++it)
-        launch_rb_sweep(E.kind, s, L.phi, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l));
     LAUNCHCHK();
-    return GR_OK;
+    return smooth(g, E, l, E.nu2);
 }
 
 // Solve one equation for `phi` (fine), with fine source lev[0].f and fine
@@ -305,6 +350,20 @@ int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out)
     g->h = desc->h;
     g->prm = *prm;
     g->nlev = num_levels(n);
+    // tuning knobs (environment): GRMG_SMOOTHER=split|fused forces one smoother
+    // on every level it can run on; GRMG_FUSED_MIN (smallest level for the fused
+    // smoother), GRMG_FUSED_TILE (0: 64x8, 1: 32x16), GRMG_XCD_REMAP (0/1),
+    // GRMG_FUSED_WGS (target workgroups per fused launch), GRMG_COARSE_N (levels
+    // at or below this size run the rest of the V-cycle in one workgroup; 0: never)
+    if (const char *e = std::getenv("GRMG_SMOOTHER")) {
+        g->fused = std::strcmp(e, "split") != 0;
+        if (std::strcmp(e, "fused") == 0) g->fcfg.min_n = 64;
+    }
+    if (const char *e = std::getenv("GRMG_FUSED_MIN")) g->fcfg.min_n = std::atoi(e);
+    if (const char *e = std::getenv("GRMG_FUSED_TILE")) g->fcfg.tile = std::atoi(e) == 1 ? 1 : 0;
+    if (const char *e = std::getenv("GRMG_XCD_REMAP")) g->fcfg.xcd_remap = std::atoi(e) != 0;
+    if (const char *e = std::getenv("GRMG_FUSED_WGS")) g->fcfg.target_wgs = std::max(1, std::atoi(e));
+    if (const char *e = std::getenv("GRMG_COARSE_N")) g->coarse_n = std::atoi(e);
     if (g->nlev > kMaxLevels) {
         delete g;
         return fail(GR_EINVAL, "too many levels");
@@ -504,12 +563,9 @@ int gr_debug_sweep(gr_grid g, int kind, int field, double Fbar, double fshift, i
     hipStream_t s = g->stream;
     launch_set_scalar(s, g->scal + S_FBAR, Fbar);
     launch_set_scalar(s, g->scal + S_FSHIFT, fshift);
-    Level &F = g->lev[0];
-    OpConst oc = g->oc();
-    for (int it = 0; it < nsweeps; ++it)
-        launch_rb_sweep(kind, s, g->field[field], F.f, F.coef, F.n, F.h, oc, g->scal + S_FBAR, g->scal + S_FSHIFT);
-    LAUNCHCHK();
-    return GR_OK;
+    g->lev[0].phi = g->field[field];
+    EqCtx E{kind, g->oc(), 0, 0};
+    return smooth(g, E, 0, nsweeps);
 }
 
 int gr_debug_residual(gr_grid g, int kind, int field, double Fbar, double fshift, double *d_out)

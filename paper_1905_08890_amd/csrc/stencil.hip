@@ -56,33 +56,207 @@ __device__ __forceinline__ double op_point(double ph, double nbs, double inv_h2,
     }
 }
 
+// 3-D launch geometry for an nx x ny x nz domain: x across the threads of a
+// block (up to 64), y across threadIdx.y/blockIdx.y, z = blockIdx.z.
+struct Geo {
+    dim3 grid, block;
+};
+inline Geo geo3(int nx, int ny, int nz)
+{
+    const int bx = nx < 64 ? nx : 64;
+    int by = TPB / bx;
+    if (by > ny) by = ny;
+    Geo g;
+    g.block = dim3(bx, by, 1);
+    g.grid = dim3((nx + bx - 1) / bx, (ny + by - 1) / by, nz);
+    return g;
+}
+
+#define GEO_XYZ(nx, ny)                                                                               \
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;                                              \
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;                                              \
+    const int z = blockIdx.z;                                                                         \
+    if (x >= (nx) || y >= (ny)) return;
+
 // ----------------------------------------------------------------- smoother
 
 // One colour of a red-black sweep; one thread per point of that colour.
-// Colour c holds (i+j+k) % 2 == c; x is split so that consecutive threads
-// take consecutive same-colour points of one x-row.
+// Colour c holds (i+j+k) % 2 == c; consecutive threads take consecutive
+// same-colour points of one x-row.
 template <int KIND>
 __global__ void __launch_bounds__(TPB) k_rb_colour(double *__restrict__ phi, const double *__restrict__ f,
                                                    const double *__restrict__ coef, int n, double inv_h2,
                                                    int colour, OpConst oc, const double *__restrict__ fbar,
                                                    const double *__restrict__ fshift)
 {
-    const int half = n >> 1;
-    const long total = (long)n * n * half;
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total) return;
-    const int i2 = (int)(t % half);
-    const long r = t / half;
-    const int j = (int)(r % n);
-    const int k = (int)(r / n);
-    const int i = 2 * i2 + ((j + k + colour) & 1);
-    const long p = lin(i, j, k, n);
-    const double Fb = *fbar, fs = *fshift;
+    GEO_XYZ(n >> 1, n)
+    const int i = 2 * x + ((y + z + colour) & 1);
+    const long p = lin(i, y, z, n);
     const double ph = phi[p];
     double J;
-    const double L = op_point<KIND>(ph, nb_sum(phi, i, j, k, n), inv_h2,
-                                    KIND == GR_KIND_POISSON ? 0.0 : coef[p], oc, Fb, J);
-    phi[p] = ph - (L - (f[p] - fs)) / J;
+    const double L = op_point<KIND>(ph, nb_sum(phi, i, y, z, n), inv_h2,
+                                    KIND == GR_KIND_POISSON ? 0.0 : coef[p], oc, *fbar, J);
+    phi[p] = ph - (L - (f[p] - *fshift)) / J;
+}
+
+// Fused red-black sweep, out of place (in -> out), both colours in one pass.
+//
+// A workgroup owns a TX x TY tile of (x, y) and marches a chunk of zc planes
+// in z.  A 5-plane LDS ring holds `in` on the tile plus a 2-cell halo.  For
+// each newly stored plane z it
+//   1. updates the even (red) points of plane z-1 on the tile plus a 1-cell
+//      halo, in place in LDS (red points only read odd neighbours, all old);
+//   2. updates the odd (black) points of plane z-2 on the tile, whose
+//      neighbours are the new red values of planes z-3..z-1, and writes both
+//      colours of plane z-2 to `out` as 16-byte stores.
+// Red values on the halo are recomputed from old data by every tile that needs
+// them, so tiles never read each other's output: the result is exactly the
+// red-then-black sweep, with phi read once and written once per sweep.
+// All global reads of the next plane (phi, and the source/coefficient of the
+// points updated next) are issued into registers before the current plane's
+// updates, so their latency overlaps the LDS work.  Five ring slots let the
+// store of plane z+1 proceed without waiting for the black pass of z-2:
+// two barriers per plane.
+template <int KIND, int TX, int TY>
+__global__ void __launch_bounds__((TX / 2) * TY) k_rb_fused(
+    const double *__restrict__ in, double *__restrict__ out, const double *__restrict__ f,
+    const double *__restrict__ coef, int n, int zc, double inv_h2, OpConst oc, const double *__restrict__ fbar,
+    const double *__restrict__ fshift, int tiles_y, int xcd_remap)
+{
+    constexpr int NT = (TX / 2) * TY;
+    constexpr int W = TX + 4, H = TY + 4, PL = W * H;
+    constexpr int NLOAD = (PL + NT - 1) / NT;
+    constexpr int RPR = (TX + 2) / 2; // red points per row of tile + halo
+    constexpr int NRED = RPR * (TY + 2);
+    constexpr int NRP = (NRED + NT - 1) / NT;
+    constexpr bool HAS_COEF = KIND != GR_KIND_POISSON;
+    __shared__ __align__(16) double ring[5][PL];
+
+    const int tid = threadIdx.x;
+    int b = blockIdx.x;
+    const int G = gridDim.x;
+    if (xcd_remap && (G & 7) == 0) b = (b & 7) * (G >> 3) + (b >> 3); // one XCD gets a contiguous range
+    const int nz = n / zc;
+    const int zchunk = b % nz;
+    const int t2 = b / nz;
+    const int x0 = (t2 / tiles_y) * TX, y0 = (t2 % tiles_y) * TY, z0 = zchunk * zc;
+    const int plane = n * n;
+    const double Fb = *fbar, fs = *fshift;
+
+    // this thread's phi loads of a plane (tile + 2-halo)
+    int goff[NLOAD];
+    int lidx[NLOAD];
+#pragma unroll
+    for (int q = 0; q < NLOAD; ++q) {
+        const int idx = tid + q * NT;
+        lidx[q] = idx < PL ? idx : -1;
+        const int ly = idx / W, lx = idx - ly * W;
+        goff[q] = wrapi(y0 + ly - 2, n) * n + wrapi(x0 + lx - 2, n);
+    }
+    // this thread's red points (tile + 1-halo): row and pair index; lx depends on the plane parity
+    int rrow[NRP], rk[NRP];
+#pragma unroll
+    for (int q = 0; q < NRP; ++q) {
+        const int r = tid + q * NT;
+        rrow[q] = r < NRED ? r / RPR : -1;
+        rk[q] = r - (r / RPR) * RPR;
+    }
+    auto red_lx = [&](int q, int zr) { return 1 + 2 * rk[q] + ((2 + rrow[q] + zr) & 1); }; // (x+y+z) even
+    auto red_g = [&](int q, int zr) {
+        return (long)wrapi(zr, n) * plane + wrapi(y0 + rrow[q] - 1, n) * n + wrapi(x0 + red_lx(q, zr) - 2, n);
+    };
+    // this thread's black point: row bty, pair btx
+    const int btx = tid % (TX / 2), bty = tid / (TX / 2);
+    auto blk_o = [&](int zb) { return (2 + bty + zb + 1) & 1; }; // (x+y+z) odd
+    auto blk_g = [&](int zb) { return (long)wrapi(zb, n) * plane + (long)(y0 + bty) * n + x0 + 2 * btx; };
+
+    double pre[NLOAD];
+    double rf_c[NRP], rc_c[NRP], rf_n[NRP], rc_n[NRP];
+    double bf_c = 0.0, bc_c = 0.0, bf_n = 0.0, bc_n = 0.0;
+#pragma unroll
+    for (int q = 0; q < NRP; ++q) rf_c[q] = rc_c[q] = rf_n[q] = rc_n[q] = 0.0;
+    {
+        const double *src = in + (long)wrapi(z0 - 2, n) * plane;
+#pragma unroll
+        for (int q = 0; q < NLOAD; ++q)
+            if (lidx[q] >= 0) pre[q] = src[goff[q]];
+    }
+
+    int slot = 0; // slot of plane zz = z0 - 2 + it is it % 5
+    for (int it = 0; it < zc + 4; ++it) {
+        const int zz = z0 - 2 + it;
+        double *cur = ring[slot];
+#pragma unroll
+        for (int q = 0; q < NLOAD; ++q)
+            if (lidx[q] >= 0) cur[lidx[q]] = pre[q];
+        __syncthreads();
+        if (it + 1 < zc + 4) { // reads for the next iteration, in flight during this one
+            const double *src = in + (long)wrapi(zz + 1, n) * plane;
+#pragma unroll
+            for (int q = 0; q < NLOAD; ++q)
+                if (lidx[q] >= 0) pre[q] = src[goff[q]];
+            if (it + 1 >= 2) { // red of plane zz at it + 1
+#pragma unroll
+                for (int q = 0; q < NRP; ++q)
+                    if (rrow[q] >= 0) {
+                        const long gp = red_g(q, zz);
+                        rf_n[q] = f[gp];
+                        if (HAS_COEF) rc_n[q] = coef[gp];
+                    }
+            }
+            if (it + 1 >= 4) { // black of plane zz - 1 at it + 1
+                const long gp = blk_g(zz - 1) + blk_o(zz - 1);
+                bf_n = f[gp];
+                if (HAS_COEF) bc_n = coef[gp];
+            }
+        }
+        const int s1 = slot == 0 ? 4 : slot - 1, s2 = s1 == 0 ? 4 : s1 - 1, s3 = s2 == 0 ? 4 : s2 - 1;
+        if (it >= 2) { // red points of plane zr = zz - 1, tile + 1-cell halo
+            const int zr = zz - 1;
+            double *mid = ring[s1];
+            const double *lo = ring[s2];
+            const double *hi = ring[slot];
+#pragma unroll
+            for (int q = 0; q < NRP; ++q) {
+                if (rrow[q] < 0) continue;
+                const int c = (1 + rrow[q]) * W + red_lx(q, zr);
+                const double ph = mid[c];
+                const double nbs = mid[c - 1] + mid[c + 1] + mid[c - W] + mid[c + W] + lo[c] + hi[c];
+                double J;
+                const double L = op_point<KIND>(ph, nbs, inv_h2, rc_c[q], oc, Fb, J);
+                mid[c] = ph - (L - (rf_c[q] - fs)) / J;
+            }
+        }
+        __syncthreads();
+        if (it >= 4) { // black points of plane zb = zz - 2, tile only; write both colours
+            const int zb = zz - 2;
+            const double *mid = ring[s2];
+            const double *lo = ring[s3];
+            const double *hi = ring[s1];
+            const int ly = 2 + bty;
+            const int lxe = 2 + 2 * btx;
+            const int o = blk_o(zb);
+            const int c = ly * W + lxe + o;
+            const double ph = mid[c];
+            const double nbs = mid[c - 1] + mid[c + 1] + mid[c - W] + mid[c + W] + lo[c] + hi[c];
+            double J;
+            const double L = op_point<KIND>(ph, nbs, inv_h2, bc_c, oc, Fb, J);
+            const double nb = ph - (L - (bf_c - fs)) / J;
+            const double red = mid[ly * W + lxe + (1 - o)];
+            double2 v;
+            v.x = o ? red : nb;
+            v.y = o ? nb : red;
+            *reinterpret_cast<double2 *>(out + blk_g(zb)) = v;
+        }
+#pragma unroll
+        for (int q = 0; q < NRP; ++q) {
+            rf_c[q] = rf_n[q];
+            rc_c[q] = rc_n[q];
+        }
+        bf_c = bf_n;
+        bc_c = bc_n;
+        slot = slot == 4 ? 0 : slot + 1;
+    }
 }
 
 // ------------------------------------------------- residual and restriction
@@ -96,14 +270,11 @@ __global__ void __launch_bounds__(TPB) k_residual_restrict(
     double *__restrict__ phi_c, double *__restrict__ phi0_c, double *__restrict__ rr_c)
 {
     const int m = n >> 1;
-    const long M = (long)m * m * m;
-    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= M) return;
-    const int I = (int)(q % m), J = (int)((q / m) % m), K = (int)(q / ((long)m * m));
+    GEO_XYZ(m, m)
     const double Fb = *fbar, fs = *fshift;
     double sr = 0.0, sp = 0.0;
     for (int c = 0; c < 8; ++c) {
-        const int i = 2 * I + (c & 1), j = 2 * J + ((c >> 1) & 1), k = 2 * K + (c >> 2);
+        const int i = 2 * x + (c & 1), j = 2 * y + ((c >> 1) & 1), k = 2 * z + (c >> 2);
         const long p = lin(i, j, k, n);
         const double ph = phi[p];
         double Jd;
@@ -112,6 +283,7 @@ __global__ void __launch_bounds__(TPB) k_residual_restrict(
         sr += L - (f[p] - fs);
         sp += ph;
     }
+    const long q = lin(x, y, z, m);
     const double rp = sp / 8.0;
     phi_c[q] = rp;
     phi0_c[q] = rp;
@@ -125,12 +297,10 @@ __global__ void __launch_bounds__(TPB) k_coarse_rhs(const double *__restrict__ p
                                                     const double *__restrict__ rr_c, int m, double inv_H2,
                                                     OpConst oc, double *__restrict__ f_c)
 {
-    const long M = (long)m * m * m;
-    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= M) return;
-    const int I = (int)(q % m), J = (int)((q / m) % m), K = (int)(q / ((long)m * m));
+    GEO_XYZ(m, m)
+    const long q = lin(x, y, z, m);
     double Jd;
-    const double L = op_point<KIND>(phi_c[q], nb_sum(phi_c, I, J, K, m), inv_H2,
+    const double L = op_point<KIND>(phi_c[q], nb_sum(phi_c, x, y, z, m), inv_H2,
                                     KIND == GR_KIND_POISSON ? 0.0 : coef_c[q], oc, 0.0, Jd);
     f_c[q] = L - rr_c[q];
 }
@@ -142,12 +312,10 @@ __global__ void __launch_bounds__(TPB) k_residual(const double *__restrict__ phi
                                                   OpConst oc, const double *__restrict__ fbar,
                                                   const double *__restrict__ fshift, double *__restrict__ r)
 {
-    const long N = (long)n * n * n;
-    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= N) return;
-    const int i = (int)(p % n), j = (int)((p / n) % n), k = (int)(p / ((long)n * n));
+    GEO_XYZ(n, n)
+    const long p = lin(x, y, z, n);
     double Jd;
-    const double L = op_point<KIND>(phi[p], nb_sum(phi, i, j, k, n), inv_h2,
+    const double L = op_point<KIND>(phi[p], nb_sum(phi, x, y, z, n), inv_h2,
                                     KIND == GR_KIND_POISSON ? 0.0 : coef[p], oc, *fbar, Jd);
     r[p] = L - (f[p] - *fshift);
 }
@@ -157,41 +325,48 @@ __global__ void __launch_bounds__(TPB) k_restrict(const double *__restrict__ fin
                                                   double *__restrict__ coarse)
 {
     const int m = n >> 1;
-    const long M = (long)m * m * m;
-    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= M) return;
-    const int I = (int)(q % m), J = (int)((q / m) % m), K = (int)(q / ((long)m * m));
+    GEO_XYZ(m, m)
     double s = 0.0;
-    for (int c = 0; c < 8; ++c)
-        s += fine[lin(2 * I + (c & 1), 2 * J + ((c >> 1) & 1), 2 * K + (c >> 2), n)];
-    coarse[q] = s / 8.0;
+    for (int c = 0; c < 8; ++c) s += fine[lin(2 * x + (c & 1), 2 * y + ((c >> 1) & 1), 2 * z + (c >> 2), n)];
+    coarse[lin(x, y, z, m)] = s / 8.0;
 }
 
-// Cell-centred trilinear prolongation of the coarse correction, added in
-// place: fine cell 2I takes 3/4 of coarse cell I and 1/4 of I-1, fine cell
-// 2I+1 takes 3/4 of I and 1/4 of I+1 (per axis, periodic).
+// Cell-centred trilinear prolongation of the coarse correction e = phi_c -
+// phi0_c, added in place.  Fine cell 2I takes 3/4 of coarse cell I and 1/4 of
+// I-1, fine cell 2I+1 takes 3/4 of I and 1/4 of I+1 (per axis, periodic).
+// One thread per coarse cell writes its 8 children (x-pairs as 16-byte stores).
 __global__ void __launch_bounds__(TPB) k_prolong_correct(double *__restrict__ phi_f, int n,
                                                          const double *__restrict__ phi_c,
                                                          const double *__restrict__ phi0_c)
 {
-    const long N = (long)n * n * n;
-    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= N) return;
     const int m = n >> 1;
-    const int i = (int)(p % n), j = (int)((p / n) % n), k = (int)(p / ((long)n * n));
-    const int I = i >> 1, J = j >> 1, K = k >> 1;
-    const int I2 = wrapi(I + ((i & 1) ? 1 : -1), m);
-    const int J2 = wrapi(J + ((j & 1) ? 1 : -1), m);
-    const int K2 = wrapi(K + ((k & 1) ? 1 : -1), m);
-    const int Is[2] = {I, I2}, Js[2] = {J, J2}, Ks[2] = {K, K2};
-    double v = 0.0;
-    for (int c = 0; c < 8; ++c) {
-        const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
-        const double w = (ox ? 0.25 : 0.75) * (oy ? 0.25 : 0.75) * (oz ? 0.25 : 0.75);
-        const long q = lin(Is[ox], Js[oy], Ks[oz], m);
-        v += w * (phi_c[q] - phi0_c[q]);
-    }
-    phi_f[p] += v;
+    GEO_XYZ(m, m)
+    double e[3][3][3]; // e[dz+1][dy+1][dx+1]
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const long q = lin(wrapi(x + dx, m), wrapi(y + dy, m), wrapi(z + dz, m), m);
+                e[dz + 1][dy + 1][dx + 1] = phi_c[q] - phi0_c[q];
+            }
+    for (int cz = 0; cz < 2; ++cz)
+        for (int cy = 0; cy < 2; ++cy) {
+            double v[2];
+            for (int cx = 0; cx < 2; ++cx) {
+                const int sx = cx ? 1 : -1, sy = cy ? 1 : -1, sz = cz ? 1 : -1;
+                double a = 0.0;
+                for (int c = 0; c < 8; ++c) {
+                    const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+                    const double w = (ox ? 0.25 : 0.75) * (oy ? 0.25 : 0.75) * (oz ? 0.25 : 0.75);
+                    a += w * e[1 + oz * sz][1 + oy * sy][1 + ox * sx];
+                }
+                v[cx] = a;
+            }
+            double2 *dst = reinterpret_cast<double2 *>(phi_f + lin(2 * x, 2 * y + cy, 2 * z + cz, n));
+            double2 old = *dst;
+            old.x += v[0];
+            old.y += v[1];
+            *dst = old;
+        }
 }
 
 // ----------------------------------------------------------------- reductions
@@ -202,7 +377,8 @@ template <int NC>
 __device__ __forceinline__ void block_sum_store(double (&v)[NC], double *__restrict__ partials)
 {
     __shared__ double sh[NC][TPB / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         double x = v[c];
@@ -210,7 +386,7 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NC], double *__restr
         if (lane == 0) sh[c][wave] = x;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             double s = 0.0;
@@ -254,7 +430,8 @@ __global__ void __launch_bounds__(TPB) k_sum_ham_F(const double *__restrict__ ps
     block_sum_store<1>(v, partials);
 }
 
-// Sums of eps^2 and (f - fshift)^2 on one level.
+// Sums of eps^2 and (f - fshift)^2 on one level.  Blocks of 64 x 4 threads
+// walk x-rows (row r = (y, z)) in a grid-stride loop over the n^2 rows.
 template <int KIND>
 __global__ void __launch_bounds__(TPB) k_res_norms(const double *__restrict__ phi, const double *__restrict__ f,
                                                    const double *__restrict__ coef, int n, double inv_h2,
@@ -262,18 +439,21 @@ __global__ void __launch_bounds__(TPB) k_res_norms(const double *__restrict__ ph
                                                    const double *__restrict__ fshift,
                                                    double *__restrict__ partials)
 {
-    const long N = (long)n * n * n;
     const double Fb = *fbar, fs = *fshift;
     double v[2] = {0.0, 0.0};
-    for (long p = (long)blockIdx.x * TPB + threadIdx.x; p < N; p += (long)kReduceBlocks * TPB) {
-        const int i = (int)(p % n), j = (int)((p / n) % n), k = (int)(p / ((long)n * n));
-        double Jd;
-        const double L = op_point<KIND>(phi[p], nb_sum(phi, i, j, k, n), inv_h2,
-                                        KIND == GR_KIND_POISSON ? 0.0 : coef[p], oc, Fb, Jd);
-        const double fe = f[p] - fs;
-        const double e = L - fe;
-        v[0] += e * e;
-        v[1] += fe * fe;
+    const int rows = n * n;
+    for (int r = blockIdx.x * 4 + threadIdx.y; r < rows; r += kReduceBlocks * 4) {
+        const int y = r % n, z = r / n;
+        for (int x = threadIdx.x; x < n; x += 64) {
+            const long p = lin(x, y, z, n);
+            double Jd;
+            const double L = op_point<KIND>(phi[p], nb_sum(phi, x, y, z, n), inv_h2,
+                                            KIND == GR_KIND_POISSON ? 0.0 : coef[p], oc, Fb, Jd);
+            const double fe = f[p] - fs;
+            const double e = L - fe;
+            v[0] += e * e;
+            v[1] += fe * fe;
+        }
     }
     block_sum_store<2>(v, partials);
 }
@@ -295,6 +475,123 @@ __global__ void __launch_bounds__(TPB) k_finalize(const double *__restrict__ par
         }
         if (threadIdx.x == 0) out[c] = (add ? add[c] : 0.0) + scale * sh[0];
         __syncthreads();
+    }
+}
+
+// ------------------------------------------------- coarse levels, one block
+
+// The V-cycle below (and including) level ls, run by one workgroup: every
+// level is small enough to live in L2, so one launch with block barriers
+// replaces the ~10 launches per level of the multi-kernel path.  Same steps,
+// same order: nu1 sweeps, residual + restriction, FAS source, ..., 32 sweeps
+// and mean projection at the coarsest, prolongation, nu2 sweeps.
+constexpr int CTPB = 1024;
+
+template <int KIND>
+__device__ void cv_sweep(double *__restrict__ phi, const double *__restrict__ f, const double *__restrict__ coef,
+                         int n, double inv_h2, OpConst oc, double Fb, double fs)
+{
+    const int half = n >> 1, tot = n * n * half;
+    for (int colour = 0; colour < 2; ++colour) {
+        for (int t = threadIdx.x; t < tot; t += CTPB) {
+            const int x2 = t % half, r = t / half, y = r % n, z = r / n;
+            const int i = 2 * x2 + ((y + z + colour) & 1);
+            const long p = lin(i, y, z, n);
+            const double ph = phi[p];
+            double J;
+            const double L = op_point<KIND>(ph, nb_sum(phi, i, y, z, n), inv_h2,
+                                            KIND == GR_KIND_POISSON ? 0.0 : coef[p], oc, Fb, J);
+            phi[p] = ph - (L - (f[p] - fs)) / J;
+        }
+        __syncthreads();
+    }
+}
+
+__device__ double cv_block_sum(double v)
+{
+    __shared__ double sh[CTPB / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < CTPB / 64; ++w) s += sh[w];
+    __syncthreads();
+    return s; // every thread gets the same fixed-order sum
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(CTPB) k_coarse_vcycle(CoarseLevels C, int nu1, int nu2, OpConst oc,
+                                                        const double *__restrict__ fbar0,
+                                                        const double *__restrict__ fshift0)
+{
+    const int L = C.nl;
+    const double Fb0 = *fbar0, fs0 = *fshift0; // frozen scalars of C's first level (zero unless it is the finest)
+    for (int i = 0; i < L - 1; ++i) {
+        const int n = C.n[i], m = n >> 1;
+        const double Fb = i == 0 ? Fb0 : 0.0, fs = i == 0 ? fs0 : 0.0;
+        for (int it = 0; it < nu1; ++it) cv_sweep<KIND>(C.phi[i], C.f[i], C.coef[i], n, C.inv_h2[i], oc, Fb, fs);
+        const int M = m * m * m;
+        for (int q = threadIdx.x; q < M; q += CTPB) {
+            const int X = q % m, Y = (q / m) % m, Z = q / (m * m);
+            double sr = 0.0, sp = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                const int a = 2 * X + (c & 1), b = 2 * Y + ((c >> 1) & 1), d = 2 * Z + (c >> 2);
+                const long p = lin(a, b, d, n);
+                const double ph = C.phi[i][p];
+                double Jd;
+                const double Lv = op_point<KIND>(ph, nb_sum(C.phi[i], a, b, d, n), C.inv_h2[i],
+                                                 KIND == GR_KIND_POISSON ? 0.0 : C.coef[i][p], oc, Fb, Jd);
+                sr += Lv - (C.f[i][p] - fs);
+                sp += ph;
+            }
+            const double rp = sp / 8.0;
+            C.phi[i + 1][q] = rp;
+            C.phi0[i + 1][q] = rp;
+            C.tmp[i + 1][q] = sr / 8.0;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < M; q += CTPB) {
+            const int X = q % m, Y = (q / m) % m, Z = q / (m * m);
+            double Jd;
+            const double Lv = op_point<KIND>(C.phi[i + 1][q], nb_sum(C.phi[i + 1], X, Y, Z, m), C.inv_h2[i + 1],
+                                             KIND == GR_KIND_POISSON ? 0.0 : C.coef[i + 1][q], oc, 0.0, Jd);
+            C.f[i + 1][q] = Lv - C.tmp[i + 1][q];
+        }
+        __syncthreads();
+    }
+    { // coarsest: sweeps, then remove the mean of the correction
+        const int i = L - 1, n = C.n[i], N = n * n * n;
+        const double Fb = i == 0 ? Fb0 : 0.0, fs = i == 0 ? fs0 : 0.0;
+        for (int q = threadIdx.x; q < N; q += CTPB) C.tmp[i][q] = C.phi[i][q];
+        __syncthreads();
+        for (int it = 0; it < kCoarseSweeps; ++it) cv_sweep<KIND>(C.phi[i], C.f[i], C.coef[i], n, C.inv_h2[i], oc, Fb, fs);
+        double d = 0.0;
+        for (int q = threadIdx.x; q < N; q += CTPB) d += C.phi[i][q] - C.tmp[i][q];
+        const double mean = cv_block_sum(d) / (double)N;
+        for (int q = threadIdx.x; q < N; q += CTPB) C.phi[i][q] -= mean;
+        __syncthreads();
+    }
+    for (int i = L - 2; i >= 0; --i) {
+        const int n = C.n[i], m = n >> 1, N = n * n * n;
+        const double Fb = i == 0 ? Fb0 : 0.0, fs = i == 0 ? fs0 : 0.0;
+        for (int p = threadIdx.x; p < N; p += CTPB) {
+            const int a = p % n, b = (p / n) % n, d = p / (n * n);
+            const int I = a >> 1, J = b >> 1, K = d >> 1;
+            const int Is[2] = {I, wrapi(I + ((a & 1) ? 1 : -1), m)};
+            const int Js[2] = {J, wrapi(J + ((b & 1) ? 1 : -1), m)};
+            const int Ks[2] = {K, wrapi(K + ((d & 1) ? 1 : -1), m)};
+            double v = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+                const double w = (ox ? 0.25 : 0.75) * (oy ? 0.25 : 0.75) * (oz ? 0.25 : 0.75);
+                const long q = lin(Is[ox], Js[oy], Ks[oz], m);
+                v += w * (C.phi[i + 1][q] - C.phi0[i + 1][q]);
+            }
+            C.phi[i][p] += v;
+        }
+        __syncthreads();
+        for (int it = 0; it < nu2; ++it) cv_sweep<KIND>(C.phi[i], C.f[i], C.coef[i], n, C.inv_h2[i], oc, Fb, fs);
     }
 }
 
@@ -339,54 +636,101 @@ inline unsigned blocks_for(long count) { return (unsigned)((count + TPB - 1) / T
 
 } // namespace
 
-#define GR_DISPATCH_KIND(kind, KERNEL, grid, ...)                                                     \
+#define GR_DISPATCH_KIND_G(kind, KERNEL, G, ...)                                                      \
     do {                                                                                              \
-        if ((kind) == GR_KIND_POISSON) KERNEL<GR_KIND_POISSON><<<grid, TPB, 0, s>>>(__VA_ARGS__);     \
-        else if ((kind) == GR_KIND_HAMILTONIAN) KERNEL<GR_KIND_HAMILTONIAN><<<grid, TPB, 0, s>>>(__VA_ARGS__); \
-        else KERNEL<GR_KIND_CMC><<<grid, TPB, 0, s>>>(__VA_ARGS__);                                  \
+        if ((kind) == GR_KIND_POISSON) KERNEL<GR_KIND_POISSON><<<(G).grid, (G).block, 0, s>>>(__VA_ARGS__); \
+        else if ((kind) == GR_KIND_HAMILTONIAN)                                                       \
+            KERNEL<GR_KIND_HAMILTONIAN><<<(G).grid, (G).block, 0, s>>>(__VA_ARGS__);                  \
+        else KERNEL<GR_KIND_CMC><<<(G).grid, (G).block, 0, s>>>(__VA_ARGS__);                        \
     } while (0)
 
 void launch_rb_sweep(int kind, hipStream_t s, double *phi, const double *f, const double *coef, int n, double h,
                      OpConst oc, const double *fbar, const double *fshift)
 {
     const double inv_h2 = 1.0 / (h * h);
-    const unsigned g = blocks_for((long)n * n * (n / 2));
+    const Geo G = geo3(n / 2, n, n);
     for (int colour = 0; colour < 2; ++colour)
-        GR_DISPATCH_KIND(kind, k_rb_colour, g, phi, f, coef, n, inv_h2, colour, oc, fbar, fshift);
+        GR_DISPATCH_KIND_G(kind, k_rb_colour, G, phi, f, coef, n, inv_h2, colour, oc, fbar, fshift);
+}
+
+bool fused_sweep_ok(int n, int min_n) { return n >= min_n && n >= 64 && n % 64 == 0; }
+
+template <int TX, int TY>
+static void launch_fused_t(int kind, hipStream_t s, const double *in, double *out, const double *f,
+                           const double *coef, int n, double h, OpConst oc, const double *fbar,
+                           const double *fshift, int xcd_remap, int target_wgs)
+{
+    const int tiles_x = n / TX, tiles_y = n / TY;
+    const int tiles = tiles_x * tiles_y;
+    // z chunk: halve (keeping >= 8 planes and a divisor of n) until the grid
+    // reaches the target number of workgroups (one resident wave)
+    int zc = n;
+    while (zc % 2 == 0 && zc / 2 >= 8 && (long)tiles * (n / zc) < target_wgs) zc /= 2;
+    const unsigned grid = (unsigned)(tiles * (n / zc));
+    const double inv_h2 = 1.0 / (h * h);
+    constexpr int NT = (TX / 2) * TY;
+    if (kind == GR_KIND_POISSON)
+        k_rb_fused<GR_KIND_POISSON, TX, TY><<<grid, NT, 0, s>>>(in, out, f, coef, n, zc, inv_h2, oc, fbar, fshift,
+                                                                 tiles_y, xcd_remap);
+    else if (kind == GR_KIND_HAMILTONIAN)
+        k_rb_fused<GR_KIND_HAMILTONIAN, TX, TY><<<grid, NT, 0, s>>>(in, out, f, coef, n, zc, inv_h2, oc, fbar,
+                                                                     fshift, tiles_y, xcd_remap);
+    else
+        k_rb_fused<GR_KIND_CMC, TX, TY><<<grid, NT, 0, s>>>(in, out, f, coef, n, zc, inv_h2, oc, fbar, fshift,
+                                                             tiles_y, xcd_remap);
+}
+
+void launch_rb_fused(int kind, hipStream_t s, const double *in, double *out, const double *f, const double *coef,
+                     int n, double h, OpConst oc, const double *fbar, const double *fshift, const FusedCfg &cfg)
+{
+    if (cfg.tile == 1)
+        launch_fused_t<32, 16>(kind, s, in, out, f, coef, n, h, oc, fbar, fshift, cfg.xcd_remap, cfg.target_wgs);
+    else
+        launch_fused_t<64, 8>(kind, s, in, out, f, coef, n, h, oc, fbar, fshift, cfg.xcd_remap, cfg.target_wgs);
 }
 
 void launch_residual_restrict(int kind, hipStream_t s, const double *phi, const double *f, const double *coef,
                               int n, double h, OpConst oc, const double *fbar, const double *fshift,
                               double *phi_c, double *phi0_c, double *rr_c)
 {
-    const long m = n / 2;
-    GR_DISPATCH_KIND(kind, k_residual_restrict, blocks_for(m * m * m), phi, f, coef, n, 1.0 / (h * h), oc, fbar,
-                     fshift, phi_c, phi0_c, rr_c);
+    const int m = n / 2;
+    GR_DISPATCH_KIND_G(kind, k_residual_restrict, geo3(m, m, m), phi, f, coef, n, 1.0 / (h * h), oc, fbar, fshift,
+                       phi_c, phi0_c, rr_c);
 }
 
 void launch_coarse_rhs(int kind, hipStream_t s, const double *phi_c, const double *coef_c, const double *rr_c,
                        int m, double H, OpConst oc, double *f_c)
 {
-    GR_DISPATCH_KIND(kind, k_coarse_rhs, blocks_for((long)m * m * m), phi_c, coef_c, rr_c, m, 1.0 / (H * H), oc,
-                     f_c);
+    GR_DISPATCH_KIND_G(kind, k_coarse_rhs, geo3(m, m, m), phi_c, coef_c, rr_c, m, 1.0 / (H * H), oc, f_c);
 }
 
 void launch_residual(int kind, hipStream_t s, const double *phi, const double *f, const double *coef, int n,
                      double h, OpConst oc, const double *fbar, const double *fshift, double *r)
 {
-    GR_DISPATCH_KIND(kind, k_residual, blocks_for((long)n * n * n), phi, f, coef, n, 1.0 / (h * h), oc, fbar,
-                     fshift, r);
+    GR_DISPATCH_KIND_G(kind, k_residual, geo3(n, n, n), phi, f, coef, n, 1.0 / (h * h), oc, fbar, fshift, r);
 }
 
 void launch_prolong_correct(hipStream_t s, double *phi_f, int n, const double *phi_c, const double *phi0_c)
 {
-    k_prolong_correct<<<blocks_for((long)n * n * n), TPB, 0, s>>>(phi_f, n, phi_c, phi0_c);
+    const Geo G = geo3(n / 2, n / 2, n / 2);
+    k_prolong_correct<<<G.grid, G.block, 0, s>>>(phi_f, n, phi_c, phi0_c);
 }
 
 void launch_restrict(hipStream_t s, const double *fine, int n, double *coarse)
 {
-    const long m = n / 2;
-    k_restrict<<<blocks_for(m * m * m), TPB, 0, s>>>(fine, n, coarse);
+    const Geo G = geo3(n / 2, n / 2, n / 2);
+    k_restrict<<<G.grid, G.block, 0, s>>>(fine, n, coarse);
+}
+
+void launch_coarse_vcycle(int kind, hipStream_t s, const CoarseLevels &C, int nu1, int nu2, OpConst oc,
+                          const double *fbar0, const double *fshift0)
+{
+    if (kind == GR_KIND_POISSON)
+        k_coarse_vcycle<GR_KIND_POISSON><<<1, CTPB, 0, s>>>(C, nu1, nu2, oc, fbar0, fshift0);
+    else if (kind == GR_KIND_HAMILTONIAN)
+        k_coarse_vcycle<GR_KIND_HAMILTONIAN><<<1, CTPB, 0, s>>>(C, nu1, nu2, oc, fbar0, fshift0);
+    else
+        k_coarse_vcycle<GR_KIND_CMC><<<1, CTPB, 0, s>>>(C, nu1, nu2, oc, fbar0, fshift0);
 }
 
 void launch_sum(hipStream_t s, const double *x, const double *y, long N, double *partials)
@@ -408,8 +752,10 @@ void launch_sum_ham_F(hipStream_t s, const double *psi, const double *f, const d
 void launch_res_norms(int kind, hipStream_t s, const double *phi, const double *f, const double *coef, int n,
                       double h, OpConst oc, const double *fbar, const double *fshift, double *partials)
 {
-    GR_DISPATCH_KIND(kind, k_res_norms, kReduceBlocks, phi, f, coef, n, 1.0 / (h * h), oc, fbar, fshift,
-                     partials);
+    Geo G;
+    G.grid = dim3(kReduceBlocks);
+    G.block = dim3(64, 4);
+    GR_DISPATCH_KIND_G(kind, k_res_norms, G, phi, f, coef, n, 1.0 / (h * h), oc, fbar, fshift, partials);
 }
 
 void launch_finalize(hipStream_t s, const double *partials, int ncomp, double scale, const double *add, double *out)

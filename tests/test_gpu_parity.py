@@ -54,8 +54,14 @@ def random_problem(kind, n, seed):
 # ------------------------------------------------------------ single steps
 
 @pytest.mark.parametrize("kind", list(KINDS))
-@pytest.mark.parametrize("n", [24, 40])
-def test_sweep_matches_oracle(kind, n):
+@pytest.mark.parametrize("n,mode", [(24, "split"), (40, "split"), (64, "split"), (64, "fused"),
+                                    (128, "fused"), (128, "fused32x16")])
+def test_sweep_matches_oracle(kind, n, mode, monkeypatch):
+    """3 sweeps (odd: the out-of-place fused path ends with a copy back), with
+    the colour-split kernels and with the fused tile kernel (64x8 and 32x16
+    tiles, several z-chunks)."""
+    monkeypatch.setenv("GRMG_SMOOTHER", "split" if mode == "split" else "fused")
+    monkeypatch.setenv("GRMG_FUSED_TILE", "1" if mode == "fused32x16" else "0")
     k = KINDS[kind]
     phi, f, coef, prm = random_problem(k, n, 100 + n)
     Fbar, fshift = (0.37, 0.0) if k == O.HAMILTONIAN else ((0.0, 0.21) if k == O.CMC else (0.0, 0.0))
@@ -88,6 +94,43 @@ def test_residual_matches_oracle(kind):
     assert maxrel(r, ref) < 1e-13
 
 
+@pytest.mark.parametrize("kind", list(KINDS))
+def test_fused_and_split_smoothers_agree(kind, monkeypatch):
+    """A whole solve with the fused tile smoother equals the colour-split one."""
+    k = KINDS[kind]
+    n = 64
+    f, coef, prm = _manufactured(k, n)
+    outs = []
+    for mode in ("split", "fused"):
+        monkeypatch.setenv("GRMG_SMOOTHER", mode)
+        g = grid(n, prm)
+        g.set_field("rhs", f)
+        g.set_field("coef", coef)
+        rep = g.solve_equation(k, "b", rtol=0, max_cycles=5)
+        outs.append(g.get_field("b").cpu().numpy())
+    assert maxrel(outs[1], outs[0]) < 1e-13
+
+
+@pytest.mark.parametrize("kind", list(KINDS))
+def test_single_workgroup_coarse_cycle_agrees(kind, monkeypatch):
+    """The V-cycle below a size threshold runs in one single-workgroup launch;
+    whole solves agree for thresholds 0 (every level launched separately),
+    16 and 64 (the finest level itself inside the single launch)."""
+    k = KINDS[kind]
+    n = 64
+    f, coef, prm = _manufactured(k, n)
+    outs = []
+    for cn in ("0", "16", "64"):
+        monkeypatch.setenv("GRMG_COARSE_N", cn)
+        g = grid(n, prm)
+        g.set_field("rhs", f)
+        g.set_field("coef", coef)
+        g.solve_equation(k, "b", rtol=0, max_cycles=4)
+        outs.append(g.get_field("b").cpu().numpy())
+    assert maxrel(outs[1], outs[0]) < 1e-13
+    assert maxrel(outs[2], outs[0]) < 1e-13
+
+
 # ------------------------------------------------------- one-equation solves
 
 def _manufactured(kind, n):
@@ -105,7 +148,7 @@ def _manufactured(kind, n):
 
 
 @pytest.mark.parametrize("kind", list(KINDS))
-@pytest.mark.parametrize("n", [32, 48])
+@pytest.mark.parametrize("n", [32, 48, 96])
 def test_solve_equation_same_cycles(kind, n):
     """GPU to rtol 1e-10, then the oracle for exactly the same number of
     V-cycles from the same guess: fields agree to 1e-12."""
