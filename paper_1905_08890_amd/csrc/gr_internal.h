@@ -27,6 +27,16 @@ enum Slot {
     S_NUM = 32
 };
 
+// FP32 arrays of one level for the correction cycles: correction e, its
+// source b, coefficients a (Hamiltonian: chi) and c, and a scratch buffer.
+struct Level32 {
+    float *e, *b, *a, *c, *tmp;
+};
+
+// Linearised (correction) operators J e = a Lap e + c e of the three kinds,
+// used in FP32 by the inner cycles of mixed-precision refinement.
+constexpr int K_LIN_POISSON = 3, K_LIN_HAM = 4, K_LIN_CMC = 5;
+
 // Operator constants of one equation.
 struct OpConst {
     double kappa; // 1/(2 a^2 c^2)
@@ -59,14 +69,37 @@ bool fused_sweep_ok(int n, int min_n);
 void launch_rb_fused(int kind, hipStream_t s, const double *in, double *out, const double *f, const double *coef,
                      int n, double h, OpConst oc, const double *fbar, const double *fshift, const FusedCfg &cfg);
 // The whole V-cycle from a small level down, in one single-workgroup launch.
-struct CoarseLevels {
+// FAS kinds: phi/phi0/f/c1 = iterate, R phi, source, coefficient.  Linearised
+// kinds: phi = correction e, f = its source b, c1 = c, c2 = a.
+template <typename T> struct CoarseLevelsT {
     int nl;                    // levels held (first = the level the cycle starts on)
     int n[kMaxLevels];
     double inv_h2[kMaxLevels];
-    double *phi[kMaxLevels], *phi0[kMaxLevels], *f[kMaxLevels], *coef[kMaxLevels], *tmp[kMaxLevels];
+    T *phi[kMaxLevels], *phi0[kMaxLevels], *f[kMaxLevels], *c1[kMaxLevels], *c2[kMaxLevels], *tmp[kMaxLevels];
 };
-void launch_coarse_vcycle(int kind, hipStream_t s, const CoarseLevels &C, int nu1, int nu2, OpConst oc,
+void launch_coarse_vcycle(int kind, hipStream_t s, const CoarseLevelsT<double> &C, int nu1, int nu2, OpConst oc,
                           const double *fbar0, const double *fshift0);
+void launch_coarse_vcycle_f32(int kind, hipStream_t s, const CoarseLevelsT<float> &C, int nu1, int nu2, OpConst oc,
+                              const double *zero);
+
+// ---- FP32 correction-scheme kernels (mixed precision) ----
+void launch_rb_sweep_f32(int kind, hipStream_t s, float *e, const float *b, const float *c1, const float *c2, int n,
+                         double h, OpConst oc, const double *zero);
+void launch_rb_fused_f32(int kind, hipStream_t s, const float *in, float *out, const float *b, const float *c1,
+                         const float *c2, int n, double h, OpConst oc, const double *zero, const FusedCfg &cfg);
+void launch_lin_residual_restrict_f32(int kind, hipStream_t s, const float *e, const float *b, const float *c1,
+                                      const float *c2, int n, double h, OpConst oc, float *b_c, float *e_c);
+void launch_prolong_add_f32(hipStream_t s, float *e_f, int n, const float *e_c);
+void launch_restrict_f32(hipStream_t s, const float *fine, int n, float *coarse);
+void launch_ir_residual(int kind, hipStream_t s, const double *phi, const double *f, const double *coef, int n,
+                        double h, OpConst oc, const double *fbar, const double *fshift, float *b32, float *a32,
+                        float *c32, double *partials);
+void launch_neg_to_f32(hipStream_t s, float *dst, const double *src, long N);
+void launch_sum_f32(hipStream_t s, const float *x, long N, double *partials);
+void launch_ir_update(hipStream_t s, double *phi, const float *e, long N, const double *mean);
+void launch_fill_f32(hipStream_t s, float *x, long N);
+void launch_copy_f32(hipStream_t s, float *dst, const float *src, long N);
+
 void launch_residual_restrict(int kind, hipStream_t s, const double *phi, const double *f,
                               const double *coef, int n, double h, OpConst oc, const double *fbar,
                               const double *fshift, double *phi_c, double *phi0_c, double *rr_c);

@@ -62,6 +62,7 @@ struct gr_grid_s {
     gr_params prm{};
     int nlev = 0;
     Level lev[kMaxLevels]{};
+    Level32 lev32[kMaxLevels]{}; // FP32 correction-cycle arrays (mixed precision)
     // fine-level arrays
     double *field[10]{};
     double *src[5]{}; // s0, sx, sy, sz, sm
@@ -75,6 +76,8 @@ struct gr_grid_s {
     bool fused = true;     // fused tile smoother on large levels
     FusedCfg fcfg;
     int coarse_n = 16;     // levels with n <= coarse_n run in one single-workgroup launch
+    double stall_ratio = 0.5; // mixed precision: a refinement step that keeps more than this
+                              // fraction of the residual counts as stalled (two in a row: FP64)
     size_t ws_bytes = 0;
 
     long N() const { return (long)n * n * n; }
@@ -122,6 +125,15 @@ size_t layout(gr_grid g, char *base)
         L.f = take(lb);
         L.coef = take(lb);
         L.tmp = take(lb);
+    }
+    for (int l = 0; l < g->nlev; ++l) {
+        Level32 &V = g->lev32[l];
+        const size_t lb = sizeof(float) * (size_t)g->lev[l].N;
+        V.e = reinterpret_cast<float *>(take(lb));
+        V.b = reinterpret_cast<float *>(take(lb));
+        V.a = reinterpret_cast<float *>(take(lb));
+        V.c = reinterpret_cast<float *>(take(lb));
+        V.tmp = reinterpret_cast<float *>(take(lb));
     }
     g->partials = take(sizeof(double) * kReduceBlocks * 4);
     g->scal = take(sizeof(double) * S_NUM);
@@ -189,7 +201,7 @@ int vcycle(gr_grid g, const EqCtx &E, int l)
     Level &L = g->lev[l];
     hipStream_t s = g->stream;
     if (L.n <= g->coarse_n) {
-        CoarseLevels C;
+        CoarseLevelsT<double> C;
         C.nl = g->nlev - l;
         for (int i = 0; i < C.nl; ++i) {
             const Level &V = g->lev[l + i];
@@ -198,7 +210,8 @@ int vcycle(gr_grid g, const EqCtx &E, int l)
             C.phi[i] = V.phi;
             C.phi0[i] = V.phi0;
             C.f[i] = V.f;
-            C.coef[i] = V.coef;
+            C.c1[i] = V.coef;
+            C.c2[i] = nullptr;
             C.tmp[i] = V.tmp;
         }
         launch_coarse_vcycle(E.kind, s, C, E.nu1, E.nu2, E.oc, fbar_ptr(g, l), fshift_ptr(g, l));
@@ -286,6 +299,165 @@ int solve_one(gr_grid g, int kind, double *phi, const gr_solve_opts &o, int *cyc
     return st;
 }
 
+// ------------------------------------------------- mixed precision (FP32 inner)
+
+// nsweeps sweeps of the linearised FP32 correction equation on level l.
+int smooth32(gr_grid g, int lkind, int l, int nsweeps, OpConst oc)
+{
+    Level &L = g->lev[l];
+    Level32 &V = g->lev32[l];
+    hipStream_t s = g->stream;
+    const double *zero = g->scal + S_ZERO;
+    if (!g->fused || !fused_sweep_ok(L.n, g->fcfg.min_n)) {
+        for (int it = 0; it < nsweeps; ++it) launch_rb_sweep_f32(lkind, s, V.e, V.b, V.c, V.a, L.n, L.h, oc, zero);
+        LAUNCHCHK();
+        return GR_OK;
+    }
+    float *a = V.e, *b = V.tmp;
+    for (int it = 0; it < nsweeps; ++it) {
+        launch_rb_fused_f32(lkind, s, a, b, V.b, V.c, V.a, L.n, L.h, oc, zero, g->fcfg);
+        float *t = a;
+        a = b;
+        b = t;
+    }
+    if (a != V.e) launch_copy_f32(s, V.e, a, L.N);
+    LAUNCHCHK();
+    return GR_OK;
+}
+
+// Correction-scheme V-cycle for J e = b on levels l.. (e = 0 on entry at every
+// level): sweeps, b^H = R(b - J e), recursion, e += P e^H, sweeps; the
+// coarsest level (always inside the single-workgroup kernel) does 32 sweeps
+// and removes the mean of its correction.
+int vcycle32(gr_grid g, int lkind, int l, int nu1, int nu2, OpConst oc)
+{
+    Level &L = g->lev[l];
+    Level32 &V = g->lev32[l];
+    hipStream_t s = g->stream;
+    if (L.n <= std::max(g->coarse_n, 16) || l == g->nlev - 1) {
+        CoarseLevelsT<float> C;
+        C.nl = g->nlev - l;
+        for (int i = 0; i < C.nl; ++i) {
+            const Level &Q = g->lev[l + i];
+            const Level32 &W = g->lev32[l + i];
+            C.n[i] = Q.n;
+            C.inv_h2[i] = 1.0 / (Q.h * Q.h);
+            C.phi[i] = W.e;
+            C.phi0[i] = nullptr;
+            C.f[i] = W.b;
+            C.c1[i] = W.c;
+            C.c2[i] = W.a;
+            C.tmp[i] = W.tmp;
+        }
+        launch_coarse_vcycle_f32(lkind, s, C, nu1, nu2, oc, g->scal + S_ZERO);
+        LAUNCHCHK();
+        return GR_OK;
+    }
+    CHK(smooth32(g, lkind, l, nu1, oc));
+    Level32 &C = g->lev32[l + 1];
+    launch_lin_residual_restrict_f32(lkind, s, V.e, V.b, V.c, V.a, L.n, L.h, oc, C.b, C.e);
+    LAUNCHCHK();
+    CHK(vcycle32(g, lkind, l + 1, nu1, nu2, oc));
+    launch_prolong_add_f32(s, V.e, L.n, C.e);
+    LAUNCHCHK();
+    return smooth32(g, lkind, l, nu2, oc);
+}
+
+// Mixed-precision iterative refinement for one equation: each outer step
+// evaluates the FP64 residual (and stopping test) of the regularised fine
+// equation exactly as the FP64 cycle does, solves the linearised correction
+// J(phi) e = -r approximately by one FP32 V-cycle from e = 0, and updates
+// phi <- phi + e - <e> in FP64 (the zero-mean pin folded into the update).
+// If the FP64 residual stops falling (ratio above stall_ratio, 0.5 by default,
+// twice in a row) the field continues with FP64 FAS cycles.
+int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, int *cycles_out, double *rel_out,
+                    int *fell_back)
+{
+    hipStream_t s = g->stream;
+    const long N = g->N();
+    Level &F = g->lev[0];
+    Level32 &F32 = g->lev32[0];
+    F.phi = phi;
+    const OpConst oc = g->oc();
+    const int lkind = kind + K_LIN_POISSON;
+    *fell_back = 0;
+    launch_set_scalar(s, g->scal + S_FBAR, 0.0);
+    launch_set_scalar(s, g->scal + S_FSHIFT, 0.0);
+    if (kind == GR_KIND_CMC) {
+        CHK(reduce_mean(g, F.f, nullptr, N, g->scal + S_FMEAN));
+        launch_neg_to_f32(s, F32.c, F.coef, N);
+        for (int l = 1; l < g->nlev; ++l) launch_restrict_f32(s, g->lev32[l - 1].c, g->lev[l - 1].n, g->lev32[l].c);
+    }
+    LAUNCHCHK();
+    CHK(pin_mean(g, phi, N));
+
+    int cyc = 0, stall = 0;
+    double rel = 0.0, prev = HUGE_VAL;
+    int st = GR_OK;
+    for (;;) {
+        if (kind == GR_KIND_HAMILTONIAN) {
+            launch_sum_ham_F(s, phi, F.f, F.coef, N, oc, g->partials);
+            launch_finalize(s, g->partials, 1, 1.0 / (double)N, nullptr, g->scal + S_FBAR);
+        } else if (kind == GR_KIND_CMC) {
+            launch_sum_prod(s, F.coef, phi, N, g->partials);
+            launch_finalize(s, g->partials, 1, 1.0 / (double)N, g->scal + S_FMEAN, g->scal + S_FSHIFT);
+        }
+        launch_ir_residual(kind, s, phi, F.f, F.coef, F.n, F.h, oc, g->scal + S_FBAR, g->scal + S_FSHIFT, F32.b, F32.a,
+                           F32.c, g->partials);
+        launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN);
+        LAUNCHCHK();
+        double hn[2];
+        HIPCHK(hipMemcpyAsync(hn, g->scal + S_RN, sizeof hn, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double rn = std::sqrt(hn[0]), fn = std::sqrt(hn[1]);
+        rel = rn / (fn > 0.0 ? fn : 1.0);
+        if (!std::isfinite(rel)) {
+            st = fail(GR_ENAN, "non-finite residual (kind %d, refinement step %d)", kind, cyc);
+            break;
+        }
+        if (o.rtol > 0.0 && (rel <= o.rtol || rn == 0.0)) break;
+        if (cyc >= o.max_cycles) {
+            if (o.rtol > 0.0)
+                st = fail(GR_ENOTCONV, "kind %d: rel residual %.3e after %d refinement steps", kind, rel, cyc);
+            break;
+        }
+        stall = rel > g->stall_ratio * prev ? stall + 1 : 0;
+        prev = rel;
+        if (stall >= 2) { // FP32 corrections no longer help: finish in FP64
+            *fell_back = 1;
+            gr_solve_opts o2 = o;
+            o2.max_cycles = o.max_cycles - cyc;
+            int c2 = 0;
+            st = solve_one(g, kind, phi, o2, &c2, &rel);
+            cyc += c2;
+            break;
+        }
+        if (kind == GR_KIND_HAMILTONIAN)
+            for (int l = 1; l < g->nlev; ++l) {
+                launch_restrict_f32(s, g->lev32[l - 1].a, g->lev[l - 1].n, g->lev32[l].a);
+                launch_restrict_f32(s, g->lev32[l - 1].c, g->lev[l - 1].n, g->lev32[l].c);
+            }
+        launch_fill_f32(s, F32.e, N);
+        LAUNCHCHK();
+        CHK(vcycle32(g, lkind, 0, o.nu1, o.nu2, oc));
+        launch_sum_f32(s, F32.e, N, g->partials);
+        launch_finalize(s, g->partials, 1, 1.0 / (double)N, nullptr, g->scal + S_MEAN);
+        launch_ir_update(s, phi, F32.e, N, g->scal + S_MEAN);
+        LAUNCHCHK();
+        ++cyc;
+    }
+    *cycles_out = cyc;
+    *rel_out = rel;
+    return st;
+}
+
+int solve_field(gr_grid g, int kind, double *phi, const gr_solve_opts &o, int *cycles, double *rel, int *fell_back)
+{
+    *fell_back = 0;
+    if (o.precision == GR_MIXED) return solve_one_mixed(g, kind, phi, o, cycles, rel, fell_back);
+    return solve_one(g, kind, phi, o, cycles, rel);
+}
+
 int check_opts(const gr_solve_opts *o)
 {
     if (!o) return fail(GR_EINVAL, "null opts");
@@ -354,7 +526,8 @@ int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out)
     // on every level it can run on; GRMG_FUSED_MIN (smallest level for the fused
     // smoother), GRMG_FUSED_TILE (0: 64x8, 1: 32x16), GRMG_XCD_REMAP (0/1),
     // GRMG_FUSED_WGS (target workgroups per fused launch), GRMG_COARSE_N (levels
-    // at or below this size run the rest of the V-cycle in one workgroup; 0: never)
+    // at or below this size run the rest of the V-cycle in one workgroup; 0: never),
+    // GRMG_MIXED_STALL (mixed-precision stagnation ratio)
     if (const char *e = std::getenv("GRMG_SMOOTHER")) {
         g->fused = std::strcmp(e, "split") != 0;
         if (std::strcmp(e, "fused") == 0) g->fcfg.min_n = 64;
@@ -364,6 +537,7 @@ int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out)
     if (const char *e = std::getenv("GRMG_XCD_REMAP")) g->fcfg.xcd_remap = std::atoi(e) != 0;
     if (const char *e = std::getenv("GRMG_FUSED_WGS")) g->fcfg.target_wgs = std::max(1, std::atoi(e));
     if (const char *e = std::getenv("GRMG_COARSE_N")) g->coarse_n = std::atoi(e);
+    if (const char *e = std::getenv("GRMG_MIXED_STALL")) g->stall_ratio = std::atof(e);
     if (g->nlev > kMaxLevels) {
         delete g;
         return fail(GR_EINVAL, "too many levels");
@@ -470,7 +644,8 @@ int gr_solve_equation(gr_grid g, int kind, int field, const gr_solve_opts *opts,
     if (opts->guess == GR_GUESS_ZERO) launch_fill(g->stream, g->field[field], g->N(), 0.0);
     int cyc = 0;
     double rel = 0.0;
-    int st = solve_one(g, kind, g->field[field], *opts, &cyc, &rel);
+    int fb = 0;
+    int st = solve_field(g, kind, g->field[field], *opts, &cyc, &rel, &fb);
     if (st != GR_EDEVICE) {
         hipError_t e = hipStreamSynchronize(g->stream);
         if (e != hipSuccess) st = fail(GR_EDEVICE, "sync: %s", hipGetErrorString(e));
@@ -480,6 +655,7 @@ int gr_solve_equation(gr_grid g, int kind, int field, const gr_solve_opts *opts,
         rep->status = st;
         rep->cycles[0] = cyc;
         rep->rel_res[0] = rel;
+        rep->fallback = fb;
         rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
     return st;
@@ -506,7 +682,9 @@ int gr_solve_constraints(gr_grid g, const gr_solve_opts *opts, gr_solve_report *
 
     auto solve = [&](int fid, int kind) -> int {
         if (!(mask & (1u << fid))) return GR_OK;
-        int st = solve_one(g, kind, g->field[fid], *opts, &R.cycles[fid], &R.rel_res[fid]);
+        int fb = 0;
+        int st = solve_field(g, kind, g->field[fid], *opts, &R.cycles[fid], &R.rel_res[fid], &fb);
+        R.fallback += fb;
         if (st == GR_EDEVICE) return st;
         if (st != GR_OK && first_bad == GR_OK) first_bad = st;
         return GR_OK;

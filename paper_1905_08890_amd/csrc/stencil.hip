@@ -9,6 +9,13 @@
 //   CMC         L = Lap xi - m2 xi, source shifted by fshift = <f> + <m2 xi>
 // The Newton step per point is phi <- phi - (L - f)/(dL/dphi) with the
 // neighbours held fixed (exact Gauss-Seidel for the linear kinds).
+//
+// The same kernels, instantiated in FP32 with the linearised operators
+// J e = a Lap e + c e (kinds K_LIN_*), run the inner correction cycles of
+// mixed-precision iterative refinement: Poisson a = 1, c = 0; Hamiltonian
+// a = chi, c = dL/dPsi - chi dLap/dPsi; CMC a = 1, c = -m2.
+#include <type_traits>
+
 #include "gr_internal.h"
 
 namespace grmg {
@@ -22,7 +29,8 @@ __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >
 __device__ __forceinline__ long lin(int i, int j, int k, int n) { return ((long)k * n + j) * n + i; }
 
 // Sum of the six face neighbours of (i,j,k) with periodic wrap.
-__device__ __forceinline__ double nb_sum(const double *__restrict__ p, int i, int j, int k, int n)
+template <typename T>
+__device__ __forceinline__ T nb_sum(const T *__restrict__ p, int i, int j, int k, int n)
 {
     int ip = wrapi(i + 1, n), im = wrapi(i - 1, n);
     int jp = wrapi(j + 1, n), jm = wrapi(j - 1, n);
@@ -31,18 +39,30 @@ __device__ __forceinline__ double nb_sum(const double *__restrict__ p, int i, in
          + p[lin(i, j, kp, n)] + p[lin(i, j, km, n)];
 }
 
-// L(phi) at a point (without the source) and dL/dphi there.
-template <int KIND>
-__device__ __forceinline__ double op_point(double ph, double nbs, double inv_h2, double coef, OpConst oc,
-                                           double Fbar, double &J)
+// number of coefficient arrays an operator reads
+template <int KIND> constexpr int kNumCoef()
 {
-    const double lap = (nbs - 6.0 * ph) * inv_h2;
-    if constexpr (KIND == GR_KIND_POISSON) {
-        J = -6.0 * inv_h2;
+    return (KIND == GR_KIND_POISSON || KIND == K_LIN_POISSON) ? 0 : (KIND == K_LIN_HAM ? 2 : 1);
+}
+
+// L(phi) at a point (without the source) and dL/dphi there.
+// c1: AA (Hamiltonian), m2 (CMC), c (linearised kinds); c2: a (linearised Hamiltonian).
+template <int KIND, typename T>
+__device__ __forceinline__ T op_point(T ph, T nbs, T inv_h2, T c1, T c2, OpConst oc, T Fbar, T &J)
+{
+    const T lap = (nbs - T(6) * ph) * inv_h2;
+    if constexpr (KIND == GR_KIND_POISSON || KIND == K_LIN_POISSON) {
+        J = T(-6) * inv_h2;
         return lap;
     } else if constexpr (KIND == GR_KIND_CMC) {
-        J = -6.0 * inv_h2 - coef;
-        return lap - coef * ph;
+        J = T(-6) * inv_h2 - c1;
+        return lap - c1 * ph;
+    } else if constexpr (KIND == K_LIN_CMC) {
+        J = T(-6) * inv_h2 + c1;
+        return lap + c1 * ph;
+    } else if constexpr (KIND == K_LIN_HAM) {
+        J = T(-6) * c2 * inv_h2 + c1;
+        return c2 * lap + c1 * ph;
     } else {
         const double kap = oc.kappa, A = oc.A;
         const double chi = 1.0 - kap * ph;
@@ -51,9 +71,20 @@ __device__ __forceinline__ double op_point(double ph, double nbs, double inv_h2,
         const double chi6 = chi5 * chi;
         const double chim6 = 1.0 / chi6;
         const double chim7 = chim6 / chi;
-        J = -kap * lap - 6.0 * chi * inv_h2 - 6.0 * A * kap * chi5 - 1.5 * kap * coef * chim7 - kap * Fbar;
-        return chi * lap + A * (chi6 - 1.0) - 0.25 * coef * chim6 + Fbar * chi;
+        J = -kap * lap - 6.0 * chi * inv_h2 - 6.0 * A * kap * chi5 - 1.5 * kap * c1 * chim7 - kap * Fbar;
+        return chi * lap + A * (chi6 - 1.0) - 0.25 * c1 * chim6 + Fbar * chi;
     }
+}
+
+template <int KIND, typename T>
+__device__ __forceinline__ T load_c1(const T *__restrict__ c1, long p)
+{
+    return kNumCoef<KIND>() >= 1 ? c1[p] : T(0);
+}
+template <int KIND, typename T>
+__device__ __forceinline__ T load_c2(const T *__restrict__ c2, long p)
+{
+    return kNumCoef<KIND>() >= 2 ? c2[p] : T(0);
 }
 
 // 3-D launch geometry for an nx x ny x nz domain: x across the threads of a
@@ -83,20 +114,20 @@ inline Geo geo3(int nx, int ny, int nz)
 // One colour of a red-black sweep; one thread per point of that colour.
 // Colour c holds (i+j+k) % 2 == c; consecutive threads take consecutive
 // same-colour points of one x-row.
-template <int KIND>
-__global__ void __launch_bounds__(TPB) k_rb_colour(double *__restrict__ phi, const double *__restrict__ f,
-                                                   const double *__restrict__ coef, int n, double inv_h2,
-                                                   int colour, OpConst oc, const double *__restrict__ fbar,
+template <int KIND, typename T>
+__global__ void __launch_bounds__(TPB) k_rb_colour(T *__restrict__ phi, const T *__restrict__ f,
+                                                   const T *__restrict__ c1, const T *__restrict__ c2, int n,
+                                                   T inv_h2, int colour, OpConst oc, const double *__restrict__ fbar,
                                                    const double *__restrict__ fshift)
 {
     GEO_XYZ(n >> 1, n)
     const int i = 2 * x + ((y + z + colour) & 1);
     const long p = lin(i, y, z, n);
-    const double ph = phi[p];
-    double J;
-    const double L = op_point<KIND>(ph, nb_sum(phi, i, y, z, n), inv_h2,
-                                    KIND == GR_KIND_POISSON ? 0.0 : coef[p], oc, *fbar, J);
-    phi[p] = ph - (L - (f[p] - *fshift)) / J;
+    const T ph = phi[p];
+    T J;
+    const T L = op_point<KIND, T>(ph, nb_sum(phi, i, y, z, n), inv_h2, load_c1<KIND>(c1, p), load_c2<KIND>(c2, p),
+                                  oc, T(*fbar), J);
+    phi[p] = ph - (L - (f[p] - T(*fshift))) / J;
 }
 
 // Fused red-black sweep, out of place (in -> out), both colours in one pass.
@@ -117,10 +148,10 @@ __global__ void __launch_bounds__(TPB) k_rb_colour(double *__restrict__ phi, con
 // updates, so their latency overlaps the LDS work.  Five ring slots let the
 // store of plane z+1 proceed without waiting for the black pass of z-2:
 // two barriers per plane.
-template <int KIND, int TX, int TY>
+template <int KIND, typename T, int TX, int TY>
 __global__ void __launch_bounds__((TX / 2) * TY) k_rb_fused(
-    const double *__restrict__ in, double *__restrict__ out, const double *__restrict__ f,
-    const double *__restrict__ coef, int n, int zc, double inv_h2, OpConst oc, const double *__restrict__ fbar,
+    const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ f, const T *__restrict__ c1,
+    const T *__restrict__ c2, int n, int zc, T inv_h2, OpConst oc, const double *__restrict__ fbar,
     const double *__restrict__ fshift, int tiles_y, int xcd_remap)
 {
     constexpr int NT = (TX / 2) * TY;
@@ -129,8 +160,9 @@ __global__ void __launch_bounds__((TX / 2) * TY) k_rb_fused(
     constexpr int RPR = (TX + 2) / 2; // red points per row of tile + halo
     constexpr int NRED = RPR * (TY + 2);
     constexpr int NRP = (NRED + NT - 1) / NT;
-    constexpr bool HAS_COEF = KIND != GR_KIND_POISSON;
-    __shared__ __align__(16) double ring[5][PL];
+    constexpr int NC = kNumCoef<KIND>();
+    using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+    __shared__ __align__(16) T ring[5][PL];
 
     const int tid = threadIdx.x;
     int b = blockIdx.x;
@@ -141,7 +173,7 @@ __global__ void __launch_bounds__((TX / 2) * TY) k_rb_fused(
     const int t2 = b / nz;
     const int x0 = (t2 / tiles_y) * TX, y0 = (t2 % tiles_y) * TY, z0 = zchunk * zc;
     const int plane = n * n;
-    const double Fb = *fbar, fs = *fshift;
+    const T Fb = T(*fbar), fs = T(*fshift);
 
     // this thread's phi loads of a plane (tile + 2-halo)
     int goff[NLOAD];
@@ -170,13 +202,13 @@ __global__ void __launch_bounds__((TX / 2) * TY) k_rb_fused(
     auto blk_o = [&](int zb) { return (2 + bty + zb + 1) & 1; }; // (x+y+z) odd
     auto blk_g = [&](int zb) { return (long)wrapi(zb, n) * plane + (long)(y0 + bty) * n + x0 + 2 * btx; };
 
-    double pre[NLOAD];
-    double rf_c[NRP], rc_c[NRP], rf_n[NRP], rc_n[NRP];
-    double bf_c = 0.0, bc_c = 0.0, bf_n = 0.0, bc_n = 0.0;
+    T pre[NLOAD];
+    T rf_c[NRP], rc_c[NRP], ra_c[NRP], rf_n[NRP], rc_n[NRP], ra_n[NRP];
+    T bf_c = 0, bc_c = 0, ba_c = 0, bf_n = 0, bc_n = 0, ba_n = 0;
 #pragma unroll
-    for (int q = 0; q < NRP; ++q) rf_c[q] = rc_c[q] = rf_n[q] = rc_n[q] = 0.0;
+    for (int q = 0; q < NRP; ++q) rf_c[q] = rc_c[q] = ra_c[q] = rf_n[q] = rc_n[q] = ra_n[q] = T(0);
     {
-        const double *src = in + (long)wrapi(z0 - 2, n) * plane;
+        const T *src = in + (long)wrapi(z0 - 2, n) * plane;
 #pragma unroll
         for (int q = 0; q < NLOAD; ++q)
             if (lidx[q] >= 0) pre[q] = src[goff[q]];
@@ -185,13 +217,13 @@ __global__ void __launch_bounds__((TX / 2) * TY) k_rb_fused(
     int slot = 0; // slot of plane zz = z0 - 2 + it is it % 5
     for (int it = 0; it < zc + 4; ++it) {
         const int zz = z0 - 2 + it;
-        double *cur = ring[slot];
+        T *cur = ring[slot];
 #pragma unroll
         for (int q = 0; q < NLOAD; ++q)
             if (lidx[q] >= 0) cur[lidx[q]] = pre[q];
         __syncthreads();
         if (it + 1 < zc + 4) { // reads for the next iteration, in flight during this one
-            const double *src = in + (long)wrapi(zz + 1, n) * plane;
+            const T *src = in + (long)wrapi(zz + 1, n) * plane;
 #pragma unroll
             for (int q = 0; q < NLOAD; ++q)
                 if (lidx[q] >= 0) pre[q] = src[goff[q]];
@@ -201,60 +233,64 @@ __global__ void __launch_bounds__((TX / 2) * TY) k_rb_fused(
                     if (rrow[q] >= 0) {
                         const long gp = red_g(q, zz);
                         rf_n[q] = f[gp];
-                        if (HAS_COEF) rc_n[q] = coef[gp];
+                        if (NC >= 1) rc_n[q] = c1[gp];
+                        if (NC >= 2) ra_n[q] = c2[gp];
                     }
             }
             if (it + 1 >= 4) { // black of plane zz - 1 at it + 1
                 const long gp = blk_g(zz - 1) + blk_o(zz - 1);
                 bf_n = f[gp];
-                if (HAS_COEF) bc_n = coef[gp];
+                if (NC >= 1) bc_n = c1[gp];
+                if (NC >= 2) ba_n = c2[gp];
             }
         }
         const int s1 = slot == 0 ? 4 : slot - 1, s2 = s1 == 0 ? 4 : s1 - 1, s3 = s2 == 0 ? 4 : s2 - 1;
         if (it >= 2) { // red points of plane zr = zz - 1, tile + 1-cell halo
             const int zr = zz - 1;
-            double *mid = ring[s1];
-            const double *lo = ring[s2];
-            const double *hi = ring[slot];
+            T *mid = ring[s1];
+            const T *lo = ring[s2];
+            const T *hi = ring[slot];
 #pragma unroll
             for (int q = 0; q < NRP; ++q) {
                 if (rrow[q] < 0) continue;
                 const int c = (1 + rrow[q]) * W + red_lx(q, zr);
-                const double ph = mid[c];
-                const double nbs = mid[c - 1] + mid[c + 1] + mid[c - W] + mid[c + W] + lo[c] + hi[c];
-                double J;
-                const double L = op_point<KIND>(ph, nbs, inv_h2, rc_c[q], oc, Fb, J);
+                const T ph = mid[c];
+                const T nbs = mid[c - 1] + mid[c + 1] + mid[c - W] + mid[c + W] + lo[c] + hi[c];
+                T J;
+                const T L = op_point<KIND, T>(ph, nbs, inv_h2, rc_c[q], ra_c[q], oc, Fb, J);
                 mid[c] = ph - (L - (rf_c[q] - fs)) / J;
             }
         }
         __syncthreads();
         if (it >= 4) { // black points of plane zb = zz - 2, tile only; write both colours
             const int zb = zz - 2;
-            const double *mid = ring[s2];
-            const double *lo = ring[s3];
-            const double *hi = ring[s1];
+            const T *mid = ring[s2];
+            const T *lo = ring[s3];
+            const T *hi = ring[s1];
             const int ly = 2 + bty;
             const int lxe = 2 + 2 * btx;
             const int o = blk_o(zb);
             const int c = ly * W + lxe + o;
-            const double ph = mid[c];
-            const double nbs = mid[c - 1] + mid[c + 1] + mid[c - W] + mid[c + W] + lo[c] + hi[c];
-            double J;
-            const double L = op_point<KIND>(ph, nbs, inv_h2, bc_c, oc, Fb, J);
-            const double nb = ph - (L - (bf_c - fs)) / J;
-            const double red = mid[ly * W + lxe + (1 - o)];
-            double2 v;
+            const T ph = mid[c];
+            const T nbs = mid[c - 1] + mid[c + 1] + mid[c - W] + mid[c + W] + lo[c] + hi[c];
+            T J;
+            const T L = op_point<KIND, T>(ph, nbs, inv_h2, bc_c, ba_c, oc, Fb, J);
+            const T nb = ph - (L - (bf_c - fs)) / J;
+            const T red = mid[ly * W + lxe + (1 - o)];
+            T2 v;
             v.x = o ? red : nb;
             v.y = o ? nb : red;
-            *reinterpret_cast<double2 *>(out + blk_g(zb)) = v;
+            *reinterpret_cast<T2 *>(out + blk_g(zb)) = v;
         }
 #pragma unroll
         for (int q = 0; q < NRP; ++q) {
             rf_c[q] = rf_n[q];
             rc_c[q] = rc_n[q];
+            ra_c[q] = ra_n[q];
         }
         bf_c = bf_n;
         bc_c = bc_n;
+        ba_c = ba_n;
         slot = slot == 4 ? 0 : slot + 1;
     }
 }
@@ -278,8 +314,8 @@ __global__ void __launch_bounds__(TPB) k_residual_restrict(
         const long p = lin(i, j, k, n);
         const double ph = phi[p];
         double Jd;
-        const double L = op_point<KIND>(ph, nb_sum(phi, i, j, k, n), inv_h2,
-                                        KIND == GR_KIND_POISSON ? 0.0 : coef[p], oc, Fb, Jd);
+        const double L = op_point<KIND, double>(ph, nb_sum(phi, i, j, k, n), inv_h2, load_c1<KIND>(coef, p), 0.0,
+                                                oc, Fb, Jd);
         sr += L - (f[p] - fs);
         sp += ph;
     }
@@ -300,8 +336,8 @@ __global__ void __launch_bounds__(TPB) k_coarse_rhs(const double *__restrict__ p
     GEO_XYZ(m, m)
     const long q = lin(x, y, z, m);
     double Jd;
-    const double L = op_point<KIND>(phi_c[q], nb_sum(phi_c, x, y, z, m), inv_H2,
-                                    KIND == GR_KIND_POISSON ? 0.0 : coef_c[q], oc, 0.0, Jd);
+    const double L = op_point<KIND, double>(phi_c[q], nb_sum(phi_c, x, y, z, m), inv_H2, load_c1<KIND>(coef_c, q),
+                                            0.0, oc, 0.0, Jd);
     f_c[q] = L - rr_c[q];
 }
 
@@ -315,54 +351,79 @@ __global__ void __launch_bounds__(TPB) k_residual(const double *__restrict__ phi
     GEO_XYZ(n, n)
     const long p = lin(x, y, z, n);
     double Jd;
-    const double L = op_point<KIND>(phi[p], nb_sum(phi, x, y, z, n), inv_h2,
-                                    KIND == GR_KIND_POISSON ? 0.0 : coef[p], oc, *fbar, Jd);
+    const double L = op_point<KIND, double>(phi[p], nb_sum(phi, x, y, z, n), inv_h2, load_c1<KIND>(coef, p), 0.0,
+                                            oc, *fbar, Jd);
     r[p] = L - (f[p] - *fshift);
 }
 
 // Restriction of an arbitrary array: mean of the 8 children.
-__global__ void __launch_bounds__(TPB) k_restrict(const double *__restrict__ fine, int n,
-                                                  double *__restrict__ coarse)
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_restrict(const T *__restrict__ fine, int n, T *__restrict__ coarse)
 {
     const int m = n >> 1;
     GEO_XYZ(m, m)
-    double s = 0.0;
+    T s = 0;
     for (int c = 0; c < 8; ++c) s += fine[lin(2 * x + (c & 1), 2 * y + ((c >> 1) & 1), 2 * z + (c >> 2), n)];
-    coarse[lin(x, y, z, m)] = s / 8.0;
+    coarse[lin(x, y, z, m)] = s / T(8);
 }
 
-// Cell-centred trilinear prolongation of the coarse correction e = phi_c -
-// phi0_c, added in place.  Fine cell 2I takes 3/4 of coarse cell I and 1/4 of
-// I-1, fine cell 2I+1 takes 3/4 of I and 1/4 of I+1 (per axis, periodic).
-// One thread per coarse cell writes its 8 children (x-pairs as 16-byte stores).
-__global__ void __launch_bounds__(TPB) k_prolong_correct(double *__restrict__ phi_f, int n,
-                                                         const double *__restrict__ phi_c,
-                                                         const double *__restrict__ phi0_c)
+// Linear correction scheme: coarse source b^H = R(b - J e) and coarse e^H = 0.
+template <int KIND, typename T>
+__global__ void __launch_bounds__(TPB) k_lin_residual_restrict(const T *__restrict__ e, const T *__restrict__ b,
+                                                               const T *__restrict__ c1, const T *__restrict__ c2,
+                                                               int n, T inv_h2, OpConst oc, T *__restrict__ b_c,
+                                                               T *__restrict__ e_c)
 {
     const int m = n >> 1;
     GEO_XYZ(m, m)
-    double e[3][3][3]; // e[dz+1][dy+1][dx+1]
+    T sr = 0;
+    for (int c = 0; c < 8; ++c) {
+        const int i = 2 * x + (c & 1), j = 2 * y + ((c >> 1) & 1), k = 2 * z + (c >> 2);
+        const long p = lin(i, j, k, n);
+        T Jd;
+        const T L = op_point<KIND, T>(e[p], nb_sum(e, i, j, k, n), inv_h2, load_c1<KIND>(c1, p), load_c2<KIND>(c2, p),
+                                      oc, T(0), Jd);
+        sr += b[p] - L;
+    }
+    const long q = lin(x, y, z, m);
+    b_c[q] = sr / T(8);
+    e_c[q] = T(0);
+}
+
+// Cell-centred trilinear prolongation of the coarse correction, added in
+// place: e = phi_c - phi0_c (FAS) or e = phi_c (correction scheme).  Fine cell
+// 2I takes 3/4 of coarse cell I and 1/4 of I-1, fine cell 2I+1 takes 3/4 of I
+// and 1/4 of I+1 (per axis, periodic).  One thread per coarse cell writes its
+// 8 children (x-pairs as one vector store).
+template <typename T, bool FAS>
+__global__ void __launch_bounds__(TPB) k_prolong_correct(T *__restrict__ phi_f, int n, const T *__restrict__ phi_c,
+                                                         const T *__restrict__ phi0_c)
+{
+    using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+    const int m = n >> 1;
+    GEO_XYZ(m, m)
+    T e[3][3][3]; // e[dz+1][dy+1][dx+1]
     for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
                 const long q = lin(wrapi(x + dx, m), wrapi(y + dy, m), wrapi(z + dz, m), m);
-                e[dz + 1][dy + 1][dx + 1] = phi_c[q] - phi0_c[q];
+                e[dz + 1][dy + 1][dx + 1] = FAS ? phi_c[q] - phi0_c[q] : phi_c[q];
             }
     for (int cz = 0; cz < 2; ++cz)
         for (int cy = 0; cy < 2; ++cy) {
-            double v[2];
+            T v[2];
             for (int cx = 0; cx < 2; ++cx) {
                 const int sx = cx ? 1 : -1, sy = cy ? 1 : -1, sz = cz ? 1 : -1;
-                double a = 0.0;
+                T a = 0;
                 for (int c = 0; c < 8; ++c) {
                     const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
-                    const double w = (ox ? 0.25 : 0.75) * (oy ? 0.25 : 0.75) * (oz ? 0.25 : 0.75);
+                    const T w = (ox ? T(0.25) : T(0.75)) * (oy ? T(0.25) : T(0.75)) * (oz ? T(0.25) : T(0.75));
                     a += w * e[1 + oz * sz][1 + oy * sy][1 + ox * sx];
                 }
                 v[cx] = a;
             }
-            double2 *dst = reinterpret_cast<double2 *>(phi_f + lin(2 * x, 2 * y + cy, 2 * z + cz, n));
-            double2 old = *dst;
+            T2 *dst = reinterpret_cast<T2 *>(phi_f + lin(2 * x, 2 * y + cy, 2 * z + cz, n));
+            T2 old = *dst;
             old.x += v[0];
             old.y += v[1];
             *dst = old;
@@ -447,8 +508,8 @@ __global__ void __launch_bounds__(TPB) k_res_norms(const double *__restrict__ ph
         for (int x = threadIdx.x; x < n; x += 64) {
             const long p = lin(x, y, z, n);
             double Jd;
-            const double L = op_point<KIND>(phi[p], nb_sum(phi, x, y, z, n), inv_h2,
-                                            KIND == GR_KIND_POISSON ? 0.0 : coef[p], oc, Fb, Jd);
+            const double L = op_point<KIND, double>(phi[p], nb_sum(phi, x, y, z, n), inv_h2, load_c1<KIND>(coef, p),
+                                                    0.0, oc, Fb, Jd);
             const double fe = f[p] - fs;
             const double e = L - fe;
             v[0] += e * e;
@@ -483,13 +544,15 @@ __global__ void __launch_bounds__(TPB) k_finalize(const double *__restrict__ par
 // The V-cycle below (and including) level ls, run by one workgroup: every
 // level is small enough to live in L2, so one launch with block barriers
 // replaces the ~10 launches per level of the multi-kernel path.  Same steps,
-// same order: nu1 sweeps, residual + restriction, FAS source, ..., 32 sweeps
-// and mean projection at the coarsest, prolongation, nu2 sweeps.
+// same order: nu1 sweeps, residual + restriction, coarse source, ..., 32
+// sweeps and mean projection at the coarsest, prolongation, nu2 sweeps.
+// FAS kinds: phi0 = R phi, f^H = L^H(R phi) - R eps.  Linearised kinds
+// (correction scheme): b^H = R(b - J e), e^H = 0.
 constexpr int CTPB = 1024;
 
-template <int KIND>
-__device__ void cv_sweep(double *__restrict__ phi, const double *__restrict__ f, const double *__restrict__ coef,
-                         int n, double inv_h2, OpConst oc, double Fb, double fs)
+template <int KIND, typename T>
+__device__ void cv_sweep(T *__restrict__ phi, const T *__restrict__ f, const T *__restrict__ c1,
+                         const T *__restrict__ c2, int n, T inv_h2, OpConst oc, T Fb, T fs)
 {
     const int half = n >> 1, tot = n * n * half;
     for (int colour = 0; colour < 2; ++colour) {
@@ -497,10 +560,10 @@ __device__ void cv_sweep(double *__restrict__ phi, const double *__restrict__ f,
             const int x2 = t % half, r = t / half, y = r % n, z = r / n;
             const int i = 2 * x2 + ((y + z + colour) & 1);
             const long p = lin(i, y, z, n);
-            const double ph = phi[p];
-            double J;
-            const double L = op_point<KIND>(ph, nb_sum(phi, i, y, z, n), inv_h2,
-                                            KIND == GR_KIND_POISSON ? 0.0 : coef[p], oc, Fb, J);
+            const T ph = phi[p];
+            T J;
+            const T L = op_point<KIND, T>(ph, nb_sum(phi, i, y, z, n), inv_h2, load_c1<KIND>(c1, p),
+                                          load_c2<KIND>(c2, p), oc, Fb, J);
             phi[p] = ph - (L - (f[p] - fs)) / J;
         }
         __syncthreads();
@@ -520,79 +583,156 @@ __device__ double cv_block_sum(double v)
     return s; // every thread gets the same fixed-order sum
 }
 
-template <int KIND>
-__global__ void __launch_bounds__(CTPB) k_coarse_vcycle(CoarseLevels C, int nu1, int nu2, OpConst oc,
+template <int KIND, typename T>
+__global__ void __launch_bounds__(CTPB) k_coarse_vcycle(CoarseLevelsT<T> C, int nu1, int nu2, OpConst oc,
                                                         const double *__restrict__ fbar0,
                                                         const double *__restrict__ fshift0)
 {
+    constexpr bool LIN = KIND >= K_LIN_POISSON;
     const int L = C.nl;
-    const double Fb0 = *fbar0, fs0 = *fshift0; // frozen scalars of C's first level (zero unless it is the finest)
+    const T Fb0 = T(*fbar0), fs0 = T(*fshift0); // frozen scalars of C's first level (zero unless the finest)
     for (int i = 0; i < L - 1; ++i) {
         const int n = C.n[i], m = n >> 1;
-        const double Fb = i == 0 ? Fb0 : 0.0, fs = i == 0 ? fs0 : 0.0;
-        for (int it = 0; it < nu1; ++it) cv_sweep<KIND>(C.phi[i], C.f[i], C.coef[i], n, C.inv_h2[i], oc, Fb, fs);
+        const T inv_h2 = T(C.inv_h2[i]);
+        const T Fb = i == 0 ? Fb0 : T(0), fs = i == 0 ? fs0 : T(0);
+        for (int it = 0; it < nu1; ++it) cv_sweep<KIND, T>(C.phi[i], C.f[i], C.c1[i], C.c2[i], n, inv_h2, oc, Fb, fs);
         const int M = m * m * m;
         for (int q = threadIdx.x; q < M; q += CTPB) {
             const int X = q % m, Y = (q / m) % m, Z = q / (m * m);
-            double sr = 0.0, sp = 0.0;
+            T sr = 0, sp = 0;
             for (int c = 0; c < 8; ++c) {
                 const int a = 2 * X + (c & 1), b = 2 * Y + ((c >> 1) & 1), d = 2 * Z + (c >> 2);
                 const long p = lin(a, b, d, n);
-                const double ph = C.phi[i][p];
-                double Jd;
-                const double Lv = op_point<KIND>(ph, nb_sum(C.phi[i], a, b, d, n), C.inv_h2[i],
-                                                 KIND == GR_KIND_POISSON ? 0.0 : C.coef[i][p], oc, Fb, Jd);
+                const T ph = C.phi[i][p];
+                T Jd;
+                const T Lv = op_point<KIND, T>(ph, nb_sum(C.phi[i], a, b, d, n), inv_h2, load_c1<KIND>(C.c1[i], p),
+                                               load_c2<KIND>(C.c2[i], p), oc, Fb, Jd);
                 sr += Lv - (C.f[i][p] - fs);
                 sp += ph;
             }
-            const double rp = sp / 8.0;
-            C.phi[i + 1][q] = rp;
-            C.phi0[i + 1][q] = rp;
-            C.tmp[i + 1][q] = sr / 8.0;
+            if constexpr (LIN) {
+                C.f[i + 1][q] = -sr / T(8);
+                C.phi[i + 1][q] = T(0);
+            } else {
+                const T rp = sp / T(8);
+                C.phi[i + 1][q] = rp;
+                C.phi0[i + 1][q] = rp;
+                C.tmp[i + 1][q] = sr / T(8);
+            }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < M; q += CTPB) {
-            const int X = q % m, Y = (q / m) % m, Z = q / (m * m);
-            double Jd;
-            const double Lv = op_point<KIND>(C.phi[i + 1][q], nb_sum(C.phi[i + 1], X, Y, Z, m), C.inv_h2[i + 1],
-                                             KIND == GR_KIND_POISSON ? 0.0 : C.coef[i + 1][q], oc, 0.0, Jd);
-            C.f[i + 1][q] = Lv - C.tmp[i + 1][q];
+        if constexpr (!LIN) {
+            const T inv_H2 = T(C.inv_h2[i + 1]);
+            for (int q = threadIdx.x; q < M; q += CTPB) {
+                const int X = q % m, Y = (q / m) % m, Z = q / (m * m);
+                T Jd;
+                const T Lv = op_point<KIND, T>(C.phi[i + 1][q], nb_sum(C.phi[i + 1], X, Y, Z, m), inv_H2,
+                                               load_c1<KIND>(C.c1[i + 1], q), load_c2<KIND>(C.c2[i + 1], q), oc, T(0),
+                                               Jd);
+                C.f[i + 1][q] = Lv - C.tmp[i + 1][q];
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     { // coarsest: sweeps, then remove the mean of the correction
         const int i = L - 1, n = C.n[i], N = n * n * n;
-        const double Fb = i == 0 ? Fb0 : 0.0, fs = i == 0 ? fs0 : 0.0;
+        const T inv_h2 = T(C.inv_h2[i]);
+        const T Fb = i == 0 ? Fb0 : T(0), fs = i == 0 ? fs0 : T(0);
         for (int q = threadIdx.x; q < N; q += CTPB) C.tmp[i][q] = C.phi[i][q];
         __syncthreads();
-        for (int it = 0; it < kCoarseSweeps; ++it) cv_sweep<KIND>(C.phi[i], C.f[i], C.coef[i], n, C.inv_h2[i], oc, Fb, fs);
+        for (int it = 0; it < kCoarseSweeps; ++it)
+            cv_sweep<KIND, T>(C.phi[i], C.f[i], C.c1[i], C.c2[i], n, inv_h2, oc, Fb, fs);
         double d = 0.0;
-        for (int q = threadIdx.x; q < N; q += CTPB) d += C.phi[i][q] - C.tmp[i][q];
-        const double mean = cv_block_sum(d) / (double)N;
+        for (int q = threadIdx.x; q < N; q += CTPB) d += (double)(C.phi[i][q] - C.tmp[i][q]);
+        const T mean = T(cv_block_sum(d) / (double)N);
         for (int q = threadIdx.x; q < N; q += CTPB) C.phi[i][q] -= mean;
         __syncthreads();
     }
     for (int i = L - 2; i >= 0; --i) {
         const int n = C.n[i], m = n >> 1, N = n * n * n;
-        const double Fb = i == 0 ? Fb0 : 0.0, fs = i == 0 ? fs0 : 0.0;
+        const T inv_h2 = T(C.inv_h2[i]);
+        const T Fb = i == 0 ? Fb0 : T(0), fs = i == 0 ? fs0 : T(0);
         for (int p = threadIdx.x; p < N; p += CTPB) {
             const int a = p % n, b = (p / n) % n, d = p / (n * n);
             const int I = a >> 1, J = b >> 1, K = d >> 1;
             const int Is[2] = {I, wrapi(I + ((a & 1) ? 1 : -1), m)};
             const int Js[2] = {J, wrapi(J + ((b & 1) ? 1 : -1), m)};
             const int Ks[2] = {K, wrapi(K + ((d & 1) ? 1 : -1), m)};
-            double v = 0.0;
+            T v = 0;
             for (int c = 0; c < 8; ++c) {
                 const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
-                const double w = (ox ? 0.25 : 0.75) * (oy ? 0.25 : 0.75) * (oz ? 0.25 : 0.75);
+                const T w = (ox ? T(0.25) : T(0.75)) * (oy ? T(0.25) : T(0.75)) * (oz ? T(0.25) : T(0.75));
                 const long q = lin(Is[ox], Js[oy], Ks[oz], m);
-                v += w * (C.phi[i + 1][q] - C.phi0[i + 1][q]);
+                v += w * (LIN ? C.phi[i + 1][q] : C.phi[i + 1][q] - C.phi0[i + 1][q]);
             }
             C.phi[i][p] += v;
         }
         __syncthreads();
-        for (int it = 0; it < nu2; ++it) cv_sweep<KIND>(C.phi[i], C.f[i], C.coef[i], n, C.inv_h2[i], oc, Fb, fs);
+        for (int it = 0; it < nu2; ++it) cv_sweep<KIND, T>(C.phi[i], C.f[i], C.c1[i], C.c2[i], n, inv_h2, oc, Fb, fs);
     }
+}
+
+// ------------------------------------------------ mixed-precision outer steps
+
+// FP64 fine residual r = L(phi) - (f - fshift) of a FAS kind; writes the
+// FP32 correction source b = -r and, for the Hamiltonian, the frozen
+// linearisation a = chi and c = dL/dPsi + 6 chi/h^2; accumulates sums of
+// r^2 and (f - fshift)^2 for the stopping test.
+template <int KIND>
+__global__ void __launch_bounds__(TPB) k_ir_residual(const double *__restrict__ phi, const double *__restrict__ f,
+                                                     const double *__restrict__ coef, int n, double inv_h2,
+                                                     OpConst oc, const double *__restrict__ fbar,
+                                                     const double *__restrict__ fshift, float *__restrict__ b32,
+                                                     float *__restrict__ a32, float *__restrict__ c32,
+                                                     double *__restrict__ partials)
+{
+    const double Fb = *fbar, fs = *fshift;
+    double v[2] = {0.0, 0.0};
+    const int rows = n * n;
+    for (int r = blockIdx.x * 4 + threadIdx.y; r < rows; r += kReduceBlocks * 4) {
+        const int y = r % n, z = r / n;
+        for (int x = threadIdx.x; x < n; x += 64) {
+            const long p = lin(x, y, z, n);
+            const double ph = phi[p];
+            double J;
+            const double L = op_point<KIND, double>(ph, nb_sum(phi, x, y, z, n), inv_h2, load_c1<KIND>(coef, p), 0.0,
+                                                    oc, Fb, J);
+            const double fe = f[p] - fs;
+            const double e = L - fe;
+            v[0] += e * e;
+            v[1] += fe * fe;
+            b32[p] = (float)(-e);
+            if constexpr (KIND == GR_KIND_HAMILTONIAN) {
+                const double chi = 1.0 - oc.kappa * ph;
+                a32[p] = (float)chi;
+                c32[p] = (float)(J + 6.0 * chi * inv_h2);
+            }
+        }
+    }
+    block_sum_store<2>(v, partials);
+}
+
+// c = -m2 in FP32 (linearised CMC coefficient; fixed for the whole solve)
+__global__ void k_neg_to_f32(float *__restrict__ d, const double *__restrict__ s, long N)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < N) d[p] = (float)(-s[p]);
+}
+
+__global__ void __launch_bounds__(TPB) k_sum_f32(const float *__restrict__ x, long N, double *__restrict__ partials)
+{
+    double v[1] = {0.0};
+    for (long p = (long)blockIdx.x * TPB + threadIdx.x; p < N; p += (long)kReduceBlocks * TPB) v[0] += (double)x[p];
+    block_sum_store<1>(v, partials);
+}
+
+// phi += e - <e>: the correction, with the zero-mean pin folded in
+// (phi is pinned before the step, so <phi + e> = <e>).
+__global__ void k_ir_update(double *__restrict__ phi, const float *__restrict__ e, long N,
+                            const double *__restrict__ mean)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < N) phi[p] += (double)e[p] - *mean;
 }
 
 // -------------------------------------------------------------------- utility
@@ -601,6 +741,18 @@ __global__ void k_fill(double *__restrict__ x, long N, double v)
 {
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < N) x[p] = v;
+}
+
+__global__ void k_fill_f32(float *__restrict__ x, long N)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < N) x[p] = 0.0f;
+}
+
+__global__ void k_copy_f32(float *__restrict__ d, const float *__restrict__ s, long N)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < N) d[p] = s[p];
 }
 
 __global__ void k_copy(double *__restrict__ d, const double *__restrict__ s, long N)
@@ -644,21 +796,47 @@ inline unsigned blocks_for(long count) { return (unsigned)((count + TPB - 1) / T
         else KERNEL<GR_KIND_CMC><<<(G).grid, (G).block, 0, s>>>(__VA_ARGS__);                        \
     } while (0)
 
+// dispatch over all six kinds, with a scalar type T
+#define GR_DISPATCH_KT(kind, T, KERNEL, GRID, BLOCK, ...)                                              \
+    do {                                                                                              \
+        switch (kind) {                                                                               \
+        case GR_KIND_POISSON: KERNEL<GR_KIND_POISSON, T><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); break;  \
+        case GR_KIND_HAMILTONIAN: KERNEL<GR_KIND_HAMILTONIAN, T><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); break; \
+        case GR_KIND_CMC: KERNEL<GR_KIND_CMC, T><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); break;          \
+        case K_LIN_POISSON: KERNEL<K_LIN_POISSON, T><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); break;      \
+        case K_LIN_HAM: KERNEL<K_LIN_HAM, T><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); break;              \
+        default: KERNEL<K_LIN_CMC, T><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); break;                     \
+        }                                                                                             \
+    } while (0)
+
+template <typename T>
+void launch_rb_sweep_t(int kind, hipStream_t s, T *phi, const T *f, const T *c1, const T *c2, int n, double h,
+                       OpConst oc, const double *fbar, const double *fshift)
+{
+    const T inv_h2 = T(1.0 / (h * h));
+    const Geo G = geo3(n / 2, n, n);
+    for (int colour = 0; colour < 2; ++colour)
+        GR_DISPATCH_KT(kind, T, k_rb_colour, G.grid, G.block, phi, f, c1, c2, n, inv_h2, colour, oc, fbar, fshift);
+}
+
 void launch_rb_sweep(int kind, hipStream_t s, double *phi, const double *f, const double *coef, int n, double h,
                      OpConst oc, const double *fbar, const double *fshift)
 {
-    const double inv_h2 = 1.0 / (h * h);
-    const Geo G = geo3(n / 2, n, n);
-    for (int colour = 0; colour < 2; ++colour)
-        GR_DISPATCH_KIND_G(kind, k_rb_colour, G, phi, f, coef, n, inv_h2, colour, oc, fbar, fshift);
+    launch_rb_sweep_t<double>(kind, s, phi, f, coef, nullptr, n, h, oc, fbar, fshift);
+}
+
+void launch_rb_sweep_f32(int kind, hipStream_t s, float *e, const float *b, const float *c1, const float *c2, int n,
+                         double h, OpConst oc, const double *zero)
+{
+    launch_rb_sweep_t<float>(kind, s, e, b, c1, c2, n, h, oc, zero, zero);
 }
 
 bool fused_sweep_ok(int n, int min_n) { return n >= min_n && n >= 64 && n % 64 == 0; }
 
-template <int TX, int TY>
-static void launch_fused_t(int kind, hipStream_t s, const double *in, double *out, const double *f,
-                           const double *coef, int n, double h, OpConst oc, const double *fbar,
-                           const double *fshift, int xcd_remap, int target_wgs)
+template <typename T, int TX, int TY>
+static void launch_fused_t(int kind, hipStream_t s, const T *in, T *out, const T *f, const T *c1, const T *c2, int n,
+                           double h, OpConst oc, const double *fbar, const double *fshift, int xcd_remap,
+                           int target_wgs)
 {
     const int tiles_x = n / TX, tiles_y = n / TY;
     const int tiles = tiles_x * tiles_y;
@@ -667,26 +845,56 @@ static void launch_fused_t(int kind, hipStream_t s, const double *in, double *ou
     int zc = n;
     while (zc % 2 == 0 && zc / 2 >= 8 && (long)tiles * (n / zc) < target_wgs) zc /= 2;
     const unsigned grid = (unsigned)(tiles * (n / zc));
-    const double inv_h2 = 1.0 / (h * h);
+    const T inv_h2 = T(1.0 / (h * h));
     constexpr int NT = (TX / 2) * TY;
-    if (kind == GR_KIND_POISSON)
-        k_rb_fused<GR_KIND_POISSON, TX, TY><<<grid, NT, 0, s>>>(in, out, f, coef, n, zc, inv_h2, oc, fbar, fshift,
-                                                                 tiles_y, xcd_remap);
-    else if (kind == GR_KIND_HAMILTONIAN)
-        k_rb_fused<GR_KIND_HAMILTONIAN, TX, TY><<<grid, NT, 0, s>>>(in, out, f, coef, n, zc, inv_h2, oc, fbar,
-                                                                     fshift, tiles_y, xcd_remap);
+    switch (kind) {
+    case GR_KIND_POISSON:
+        k_rb_fused<GR_KIND_POISSON, T, TX, TY><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,
+                                                                    tiles_y, xcd_remap);
+        break;
+    case GR_KIND_HAMILTONIAN:
+        k_rb_fused<GR_KIND_HAMILTONIAN, T, TX, TY><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar,
+                                                                        fshift, tiles_y, xcd_remap);
+        break;
+    case GR_KIND_CMC:
+        k_rb_fused<GR_KIND_CMC, T, TX, TY><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,
+                                                                tiles_y, xcd_remap);
+        break;
+    case K_LIN_POISSON:
+        k_rb_fused<K_LIN_POISSON, T, TX, TY><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,
+                                                                  tiles_y, xcd_remap);
+        break;
+    case K_LIN_HAM:
+        k_rb_fused<K_LIN_HAM, T, TX, TY><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,
+                                                              tiles_y, xcd_remap);
+        break;
+    default:
+        k_rb_fused<K_LIN_CMC, T, TX, TY><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,
+                                                              tiles_y, xcd_remap);
+        break;
+    }
+}
+
+template <typename T>
+static void launch_fused_any(int kind, hipStream_t s, const T *in, T *out, const T *f, const T *c1, const T *c2,
+                             int n, double h, OpConst oc, const double *fbar, const double *fshift, const FusedCfg &cfg)
+{
+    if (cfg.tile == 1)
+        launch_fused_t<T, 32, 16>(kind, s, in, out, f, c1, c2, n, h, oc, fbar, fshift, cfg.xcd_remap, cfg.target_wgs);
     else
-        k_rb_fused<GR_KIND_CMC, TX, TY><<<grid, NT, 0, s>>>(in, out, f, coef, n, zc, inv_h2, oc, fbar, fshift,
-                                                             tiles_y, xcd_remap);
+        launch_fused_t<T, 64, 8>(kind, s, in, out, f, c1, c2, n, h, oc, fbar, fshift, cfg.xcd_remap, cfg.target_wgs);
 }
 
 void launch_rb_fused(int kind, hipStream_t s, const double *in, double *out, const double *f, const double *coef,
                      int n, double h, OpConst oc, const double *fbar, const double *fshift, const FusedCfg &cfg)
 {
-    if (cfg.tile == 1)
-        launch_fused_t<32, 16>(kind, s, in, out, f, coef, n, h, oc, fbar, fshift, cfg.xcd_remap, cfg.target_wgs);
-    else
-        launch_fused_t<64, 8>(kind, s, in, out, f, coef, n, h, oc, fbar, fshift, cfg.xcd_remap, cfg.target_wgs);
+    launch_fused_any<double>(kind, s, in, out, f, coef, nullptr, n, h, oc, fbar, fshift, cfg);
+}
+
+void launch_rb_fused_f32(int kind, hipStream_t s, const float *in, float *out, const float *b, const float *c1,
+                         const float *c2, int n, double h, OpConst oc, const double *zero, const FusedCfg &cfg)
+{
+    launch_fused_any<float>(kind, s, in, out, b, c1, c2, n, h, oc, zero, zero, cfg);
 }
 
 void launch_residual_restrict(int kind, hipStream_t s, const double *phi, const double *f, const double *coef,
@@ -696,6 +904,15 @@ void launch_residual_restrict(int kind, hipStream_t s, const double *phi, const 
     const int m = n / 2;
     GR_DISPATCH_KIND_G(kind, k_residual_restrict, geo3(m, m, m), phi, f, coef, n, 1.0 / (h * h), oc, fbar, fshift,
                        phi_c, phi0_c, rr_c);
+}
+
+void launch_lin_residual_restrict_f32(int kind, hipStream_t s, const float *e, const float *b, const float *c1,
+                                      const float *c2, int n, double h, OpConst oc, float *b_c, float *e_c)
+{
+    const int m = n / 2;
+    const Geo G = geo3(m, m, m);
+    const float inv_h2 = float(1.0 / (h * h));
+    GR_DISPATCH_KT(kind, float, k_lin_residual_restrict, G.grid, G.block, e, b, c1, c2, n, inv_h2, oc, b_c, e_c);
 }
 
 void launch_coarse_rhs(int kind, hipStream_t s, const double *phi_c, const double *coef_c, const double *rr_c,
@@ -713,24 +930,68 @@ void launch_residual(int kind, hipStream_t s, const double *phi, const double *f
 void launch_prolong_correct(hipStream_t s, double *phi_f, int n, const double *phi_c, const double *phi0_c)
 {
     const Geo G = geo3(n / 2, n / 2, n / 2);
-    k_prolong_correct<<<G.grid, G.block, 0, s>>>(phi_f, n, phi_c, phi0_c);
+    k_prolong_correct<double, true><<<G.grid, G.block, 0, s>>>(phi_f, n, phi_c, phi0_c);
+}
+
+void launch_prolong_add_f32(hipStream_t s, float *e_f, int n, const float *e_c)
+{
+    const Geo G = geo3(n / 2, n / 2, n / 2);
+    k_prolong_correct<float, false><<<G.grid, G.block, 0, s>>>(e_f, n, e_c, nullptr);
 }
 
 void launch_restrict(hipStream_t s, const double *fine, int n, double *coarse)
 {
     const Geo G = geo3(n / 2, n / 2, n / 2);
-    k_restrict<<<G.grid, G.block, 0, s>>>(fine, n, coarse);
+    k_restrict<double><<<G.grid, G.block, 0, s>>>(fine, n, coarse);
 }
 
-void launch_coarse_vcycle(int kind, hipStream_t s, const CoarseLevels &C, int nu1, int nu2, OpConst oc,
+void launch_restrict_f32(hipStream_t s, const float *fine, int n, float *coarse)
+{
+    const Geo G = geo3(n / 2, n / 2, n / 2);
+    k_restrict<float><<<G.grid, G.block, 0, s>>>(fine, n, coarse);
+}
+
+void launch_coarse_vcycle(int kind, hipStream_t s, const CoarseLevelsT<double> &C, int nu1, int nu2, OpConst oc,
                           const double *fbar0, const double *fshift0)
 {
-    if (kind == GR_KIND_POISSON)
-        k_coarse_vcycle<GR_KIND_POISSON><<<1, CTPB, 0, s>>>(C, nu1, nu2, oc, fbar0, fshift0);
-    else if (kind == GR_KIND_HAMILTONIAN)
-        k_coarse_vcycle<GR_KIND_HAMILTONIAN><<<1, CTPB, 0, s>>>(C, nu1, nu2, oc, fbar0, fshift0);
-    else
-        k_coarse_vcycle<GR_KIND_CMC><<<1, CTPB, 0, s>>>(C, nu1, nu2, oc, fbar0, fshift0);
+    GR_DISPATCH_KT(kind, double, k_coarse_vcycle, 1, CTPB, C, nu1, nu2, oc, fbar0, fshift0);
+}
+
+void launch_coarse_vcycle_f32(int kind, hipStream_t s, const CoarseLevelsT<float> &C, int nu1, int nu2, OpConst oc,
+                              const double *zero)
+{
+    GR_DISPATCH_KT(kind, float, k_coarse_vcycle, 1, CTPB, C, nu1, nu2, oc, zero, zero);
+}
+
+void launch_ir_residual(int kind, hipStream_t s, const double *phi, const double *f, const double *coef, int n,
+                        double h, OpConst oc, const double *fbar, const double *fshift, float *b32, float *a32,
+                        float *c32, double *partials)
+{
+    Geo G;
+    G.grid = dim3(kReduceBlocks);
+    G.block = dim3(64, 4);
+    GR_DISPATCH_KIND_G(kind, k_ir_residual, G, phi, f, coef, n, 1.0 / (h * h), oc, fbar, fshift, b32, a32, c32,
+                       partials);
+}
+
+void launch_neg_to_f32(hipStream_t s, float *dst, const double *src, long N)
+{
+    if (N > 0) k_neg_to_f32<<<blocks_for(N), TPB, 0, s>>>(dst, src, N);
+}
+
+void launch_sum_f32(hipStream_t s, const float *x, long N, double *partials)
+{
+    k_sum_f32<<<kReduceBlocks, TPB, 0, s>>>(x, N, partials);
+}
+
+void launch_ir_update(hipStream_t s, double *phi, const float *e, long N, const double *mean)
+{
+    if (N > 0) k_ir_update<<<blocks_for(N), TPB, 0, s>>>(phi, e, N, mean);
+}
+
+void launch_fill_f32(hipStream_t s, float *x, long N)
+{
+    if (N > 0) k_fill_f32<<<blocks_for(N), TPB, 0, s>>>(x, N);
 }
 
 void launch_sum(hipStream_t s, const double *x, const double *y, long N, double *partials)
@@ -771,6 +1032,11 @@ void launch_fill(hipStream_t s, double *x, long N, double v)
 void launch_copy(hipStream_t s, double *dst, const double *src, long N)
 {
     if (N > 0) k_copy<<<blocks_for(N), TPB, 0, s>>>(dst, src, N);
+}
+
+void launch_copy_f32(hipStream_t s, float *dst, const float *src, long N)
+{
+    if (N > 0) k_copy_f32<<<blocks_for(N), TPB, 0, s>>>(dst, src, N);
 }
 
 void launch_sub_scalar(hipStream_t s, double *x, long N, const double *scal)
