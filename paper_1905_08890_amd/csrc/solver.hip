@@ -302,20 +302,24 @@ int solve_one(gr_grid g, int kind, double *phi, const gr_solve_opts &o, int *cyc
 // ------------------------------------------------- mixed precision (FP32 inner)
 
 // nsweeps sweeps of the linearised FP32 correction equation on level l.
-int smooth32(gr_grid g, int lkind, int l, int nsweeps, OpConst oc)
+// e_is_zero: the correction is identically zero on entry (not yet written).
+int smooth32(gr_grid g, int lkind, int l, int nsweeps, OpConst oc, bool e_is_zero)
 {
     Level &L = g->lev[l];
     Level32 &V = g->lev32[l];
     hipStream_t s = g->stream;
     const double *zero = g->scal + S_ZERO;
     if (!g->fused || !fused_sweep_ok(L.n, g->fcfg.min_n)) {
+        if (e_is_zero) launch_fill_f32(s, V.e, L.N);
         for (int it = 0; it < nsweeps; ++it) launch_rb_sweep_f32(lkind, s, V.e, V.b, V.c, V.a, L.n, L.h, oc, zero);
         LAUNCHCHK();
         return GR_OK;
     }
+    if (e_is_zero && nsweeps == 0) launch_fill_f32(s, V.e, L.N);
     float *a = V.e, *b = V.tmp;
     for (int it = 0; it < nsweeps; ++it) {
-        launch_rb_fused_f32(lkind, s, a, b, V.b, V.c, V.a, L.n, L.h, oc, zero, g->fcfg);
+        launch_rb_fused_f32(lkind, s, (it == 0 && e_is_zero) ? nullptr : a, b, V.b, V.c, V.a, L.n, L.h, oc, zero,
+                            g->fcfg);
         float *t = a;
         a = b;
         b = t;
@@ -326,15 +330,16 @@ int smooth32(gr_grid g, int lkind, int l, int nsweeps, OpConst oc)
 }
 
 // Correction-scheme V-cycle for J e = b on levels l.. (e = 0 on entry at every
-// level): sweeps, b^H = R(b - J e), recursion, e += P e^H, sweeps; the
-// coarsest level (always inside the single-workgroup kernel) does 32 sweeps
-// and removes the mean of its correction.
-int vcycle32(gr_grid g, int lkind, int l, int nu1, int nu2, OpConst oc)
+// level; on level l it may be unwritten when e_unset): sweeps, b^H = R(b - J e),
+// recursion, e += P e^H, sweeps; the coarsest level (always inside the
+// single-workgroup kernel) does 32 sweeps and removes the mean of its correction.
+int vcycle32(gr_grid g, int lkind, int l, int nu1, int nu2, OpConst oc, bool e_unset)
 {
     Level &L = g->lev[l];
     Level32 &V = g->lev32[l];
     hipStream_t s = g->stream;
     if (L.n <= std::max(g->coarse_n, 16) || l == g->nlev - 1) {
+        if (e_unset) launch_fill_f32(s, V.e, L.N);
         CoarseLevelsT<float> C;
         C.nl = g->nlev - l;
         for (int i = 0; i < C.nl; ++i) {
@@ -353,14 +358,14 @@ int vcycle32(gr_grid g, int lkind, int l, int nu1, int nu2, OpConst oc)
         LAUNCHCHK();
         return GR_OK;
     }
-    CHK(smooth32(g, lkind, l, nu1, oc));
+    CHK(smooth32(g, lkind, l, nu1, oc, e_unset));
     Level32 &C = g->lev32[l + 1];
     launch_lin_residual_restrict_f32(lkind, s, V.e, V.b, V.c, V.a, L.n, L.h, oc, C.b, C.e);
     LAUNCHCHK();
-    CHK(vcycle32(g, lkind, l + 1, nu1, nu2, oc));
+    CHK(vcycle32(g, lkind, l + 1, nu1, nu2, oc, false));
     launch_prolong_add_f32(s, V.e, L.n, C.e);
     LAUNCHCHK();
-    return smooth32(g, lkind, l, nu2, oc);
+    return smooth32(g, lkind, l, nu2, oc, false);
 }
 
 // Mixed-precision iterative refinement for one equation: each outer step
@@ -437,9 +442,7 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
                 launch_restrict_f32(s, g->lev32[l - 1].a, g->lev[l - 1].n, g->lev32[l].a);
                 launch_restrict_f32(s, g->lev32[l - 1].c, g->lev[l - 1].n, g->lev32[l].c);
             }
-        launch_fill_f32(s, F32.e, N);
-        LAUNCHCHK();
-        CHK(vcycle32(g, lkind, 0, o.nu1, o.nu2, oc));
+        CHK(vcycle32(g, lkind, 0, o.nu1, o.nu2, oc, true));
         launch_sum_f32(s, F32.e, N, g->partials);
         launch_finalize(s, g->partials, 1, 1.0 / (double)N, nullptr, g->scal + S_MEAN);
         launch_ir_update(s, phi, F32.e, N, g->scal + S_MEAN);
