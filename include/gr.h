@@ -185,6 +185,34 @@ int gr_debug_sweep(gr_grid g, int kind, int field, double Fbar, double fshift, i
  * d_out (n^3 float64). */
 int gr_debug_residual(gr_grid g, int kind, int field, double Fbar, double fshift, double *d_out);
 
+/* ---- batched solve of many independent boxes ----
+ * Many periodic boxes of uneven size (each an n^3 unit box, n even) solved
+ * together: every phase of the cycle runs as one launch over all boxes, each
+ * box stops on its own residual test (the single-grid criterion), and each
+ * cycle's launch sequence is captured once per field in a hipGraph (only on a
+ * non-null stream; GRMG_BATCH_GRAPH=0 disables it) and replayed.  FP64 only.
+ * Same memory rules as a single grid: the caller allocates
+ * gr_batch_workspace_bytes() of device memory. */
+typedef struct gr_batch_s *gr_batch;
+
+/* Create a batch of `count` (1..4096) boxes described by descs[count], all
+ * with the same code-unit parameters.  Host memory only. */
+int gr_create_batch(const gr_grid_desc *descs, int count, const gr_params *prm, gr_batch *out);
+int gr_batch_workspace_bytes(gr_batch b, size_t *bytes);
+/* Bind caller-owned device memory and a hipStream_t; zero-fills everything. */
+int gr_batch_bind(gr_batch b, void *d_workspace, size_t bytes, void *hip_stream);
+/* Copy one box's field (ids 0..15 as for a grid) from / to device memory. */
+int gr_batch_set_field(gr_batch b, int item, int field, const void *d_src, int dtype);
+int gr_batch_get_field(gr_batch b, int item, int field, void *d_dst, int dtype);
+/* Solve the ten equations of every box from its sources (same order and
+ * equations as gr_solve_constraints).  Optional host outputs:
+ * cycles[count*10], rel_res[count*10] and item_seconds[count] (device-clock
+ * time from the start of each field's solve until the box met its tolerance,
+ * summed over the fields).  Returns the first non-OK box status. */
+int gr_batch_solve(gr_batch b, const gr_solve_opts *opts, int *cycles, double *rel_res, double *item_seconds);
+int gr_destroy_batch(gr_batch b);
+const char *gr_batch_last_error(void);
+
 /* Destroy a handle (the workspace stays the caller's). NULL is accepted. */
 int gr_destroy_grid(gr_grid g);
 

@@ -1,0 +1,1025 @@
+// Batched solve of many independent periodic boxes of uneven size.
+//
+// Every phase of the multigrid cycle is one launch over all boxes: a prefix
+// table maps each block to its box, and each box's slice of the launch works
+// on that box's own arrays.  Stopping is decided per box on the device (a
+// converged box's blocks return at once), so the host only reads one word per
+// cycle ("is any box still active?"), and the whole per-cycle sequence is
+// captured once per field in a hipGraph and replayed.  The arithmetic of
+// every step is the single-grid arithmetic (shared device functions), so each
+// box gets exactly the cycle of the single-grid solver.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sources_ops.h"
+
+using namespace grmg;
+using namespace grmg::detail;
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int CTPB = 1024;
+constexpr int kMaxBoxes = 4096;
+
+// device-side description of one box
+struct BoxLev {
+    int n;
+    double h;
+    double *phi, *phi0, *f, *coef, *tmp; // phi of level 0 is the current field array
+};
+struct BoxDev {
+    int nlev;
+    int centry; // first level handled by the single-workgroup coarse cycle
+    double *field[10];
+    double *src[5];
+    double *A6[6];
+    double *AA;
+    double *fB[3];
+    BoxLev lev[kMaxLevels];
+};
+
+// per-box scalars (device)
+enum BoxScal { B_FBAR, B_FSHIFT, B_FMEAN, B_MEAN, B_RN, B_FN, B_REL, B_TMP, B_NSCAL };
+
+struct BatchDev {
+    const BoxDev *box;
+    double *scal;   // [nbox][B_NSCAL]
+    int *active;    // [nbox]
+    int *cycles;    // [nbox][10]
+    int *status;    // [nbox]
+    unsigned long long *t_done; // [nbox][10] device clock at convergence
+    unsigned long long *t_start; // [10]
+    int *any_active;
+    double *partials;
+    int nbox;
+};
+
+__device__ __forceinline__ int find_box(const int *__restrict__ start, int nbox, int blk)
+{
+    int lo = 0, hi = nbox;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= blk) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// decode item t of an nx x ny x nz domain (x fastest)
+__device__ __forceinline__ void decode3(int t, int nx, int ny, int &x, int &y, int &z)
+{
+    x = t % nx;
+    const int r = t / nx;
+    y = r % ny;
+    z = r / ny;
+}
+
+#define BOX_PROLOGUE(tab)                                                                             \
+    const int b = find_box(tab, D.nbox, blockIdx.x);                                                 \
+    const BoxDev &X = D.box[b];                                                                       \
+    const int t = (blockIdx.x - tab[b]) * TPB + threadIdx.x;
+
+// ----------------------------------------------------------- multigrid phases
+
+template <int KIND>
+__global__ void __launch_bounds__(TPB) kb_colour(BatchDev D, const int *__restrict__ tab, int d, int fid, int colour,
+                                                 OpConst oc)
+{
+    BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
+    const BoxLev &L = X.lev[d];
+    const int n = L.n, half = n >> 1;
+    if (t >= n * n * half) return;
+    int x2, y, z;
+    decode3(t, half, n, x2, y, z);
+    const int i = 2 * x2 + ((y + z + colour) & 1);
+    double *phi = d == 0 ? X.field[fid] : L.phi;
+    const long p = lin(i, y, z, n);
+    const double Fb = d == 0 ? D.scal[b * B_NSCAL + B_FBAR] : 0.0;
+    const double fs = d == 0 ? D.scal[b * B_NSCAL + B_FSHIFT] : 0.0;
+    const double ph = phi[p];
+    double J;
+    const double Lv = op_point<KIND, double>(ph, nb_sum(phi, i, y, z, n), 1.0 / (L.h * L.h), load_c1<KIND>(L.coef, p),
+                                             0.0, oc, Fb, J);
+    phi[p] = ph - (Lv - (L.f[p] - fs)) / J;
+}
+
+// R phi, R eps at level d+1 (one thread per coarse cell), then the FAS source.
+template <int KIND>
+__global__ void __launch_bounds__(TPB) kb_residual_restrict(BatchDev D, const int *__restrict__ tab, int d, int fid,
+                                                            OpConst oc)
+{
+    BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
+    const BoxLev &L = X.lev[d], &C = X.lev[d + 1];
+    const int n = L.n, m = C.n;
+    if (t >= m * m * m) return;
+    int I, J, K;
+    decode3(t, m, m, I, J, K);
+    const double *phi = d == 0 ? X.field[fid] : L.phi;
+    const double Fb = d == 0 ? D.scal[b * B_NSCAL + B_FBAR] : 0.0;
+    const double fs = d == 0 ? D.scal[b * B_NSCAL + B_FSHIFT] : 0.0;
+    const double inv_h2 = 1.0 / (L.h * L.h);
+    double sr = 0.0, sp = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        const int i = 2 * I + (c & 1), j = 2 * J + ((c >> 1) & 1), k = 2 * K + (c >> 2);
+        const long p = lin(i, j, k, n);
+        const double ph = phi[p];
+        double Jd;
+        const double Lv = op_point<KIND, double>(ph, nb_sum(phi, i, j, k, n), inv_h2, load_c1<KIND>(L.coef, p), 0.0,
+                                                 oc, Fb, Jd);
+        sr += Lv - (L.f[p] - fs);
+        sp += ph;
+    }
+    const double rp = sp / 8.0;
+    C.phi[t] = rp;
+    C.phi0[t] = rp;
+    C.tmp[t] = sr / 8.0;
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(TPB) kb_coarse_rhs(BatchDev D, const int *__restrict__ tab, int d, OpConst oc)
+{
+    BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
+    const BoxLev &C = X.lev[d + 1];
+    const int m = C.n;
+    if (t >= m * m * m) return;
+    int I, J, K;
+    decode3(t, m, m, I, J, K);
+    double Jd;
+    const double Lv = op_point<KIND, double>(C.phi[t], nb_sum(C.phi, I, J, K, m), 1.0 / (C.h * C.h),
+                                             load_c1<KIND>(C.coef, t), 0.0, oc, 0.0, Jd);
+    C.f[t] = Lv - C.tmp[t];
+}
+
+// phi_d += P(phi_{d+1} - phi0_{d+1}); one thread per fine point
+__global__ void __launch_bounds__(TPB) kb_prolong(BatchDev D, const int *__restrict__ tab, int d, int fid)
+{
+    BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
+    const BoxLev &L = X.lev[d], &C = X.lev[d + 1];
+    const int n = L.n, m = C.n;
+    if (t >= n * n * n) return;
+    int a, bb, cc;
+    decode3(t, n, n, a, bb, cc);
+    double *phi = d == 0 ? X.field[fid] : L.phi;
+    const int I = a >> 1, J = bb >> 1, K = cc >> 1;
+    const int Is[2] = {I, wrapi(I + ((a & 1) ? 1 : -1), m)};
+    const int Js[2] = {J, wrapi(J + ((bb & 1) ? 1 : -1), m)};
+    const int Ks[2] = {K, wrapi(K + ((cc & 1) ? 1 : -1), m)};
+    double v = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+        const double w = (ox ? 0.25 : 0.75) * (oy ? 0.25 : 0.75) * (oz ? 0.25 : 0.75);
+        const long q = lin(Is[ox], Js[oy], Ks[oz], m);
+        v += w * (C.phi[q] - C.phi0[q]);
+    }
+    phi[t] += v;
+}
+
+// coefficient restriction level d -> d+1 (once per solve of an equation)
+__global__ void __launch_bounds__(TPB) kb_restrict_coef(BatchDev D, const int *__restrict__ tab, int d)
+{
+    BOX_PROLOGUE(tab)
+    const BoxLev &L = X.lev[d], &C = X.lev[d + 1];
+    const int m = C.n, n = L.n;
+    if (t >= m * m * m) return;
+    int I, J, K;
+    decode3(t, m, m, I, J, K);
+    double s = 0.0;
+    for (int c = 0; c < 8; ++c) s += L.coef[lin(2 * I + (c & 1), 2 * J + ((c >> 1) & 1), 2 * K + (c >> 2), n)];
+    C.coef[t] = s / 8.0;
+}
+
+// the rest of the V-cycle of each active box from its entry level, one workgroup per box
+template <int KIND>
+__global__ void __launch_bounds__(CTPB) kb_coarse_vcycle(BatchDev D, int fid, int nu1, int nu2, OpConst oc);
+
+// ------------------------------------------------------------- reductions
+
+// per-block partial sums (fixed order) of the fine level of each box
+template <int NC>
+__device__ __forceinline__ void block_store(double (&v)[NC], double *__restrict__ partials, int total_blocks)
+{
+    __shared__ double sh[NC][TPB / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double x = v[c];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) sh[c][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double s = 0.0;
+            for (int w = 0; w < TPB / 64; ++w) s += sh[c][w];
+            partials[c * total_blocks + blockIdx.x] = s;
+        }
+    }
+}
+
+// what: 0 sum(phi), 1 sum F (Hamiltonian), 2 sum(m2 phi), 3 sum(f), 4..6 sum(s_x..s_z)
+__global__ void __launch_bounds__(TPB) kb_sum(BatchDev D, const int *__restrict__ tab, int fid, int what, OpConst oc,
+                                              int active_only)
+{
+    BOX_PROLOGUE(tab)
+    const int total = tab[D.nbox];
+    double v[1] = {0.0};
+    const BoxLev &L = X.lev[0];
+    const int N = L.n * L.n * L.n;
+    if (t < N && (!active_only || D.active[b])) {
+        const double ph = X.field[fid][t];
+        if (what == 0) v[0] = ph;
+        else if (what == 1) {
+            const double chi = 1.0 - oc.kappa * ph;
+            const double chi2 = chi * chi;
+            const double chi6 = chi2 * chi2 * chi2;
+            const double chim7 = 1.0 / (chi6 * chi);
+            v[0] = (L.f[t] - oc.A * (chi6 - 1.0)) / chi + 0.25 * L.coef[t] * chim7;
+        } else if (what == 2) v[0] = L.coef[t] * ph;
+        else if (what == 3) v[0] = L.f[t];
+        else v[0] = X.src[what - 3][t];
+    }
+    block_store<1>(v, D.partials, total);
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(TPB) kb_res_norms(BatchDev D, const int *__restrict__ tab, int fid, OpConst oc)
+{
+    BOX_PROLOGUE(tab)
+    const int total = tab[D.nbox];
+    double v[2] = {0.0, 0.0};
+    const BoxLev &L = X.lev[0];
+    const int n = L.n;
+    if (t < n * n * n && D.active[b]) {
+        int x, y, z;
+        decode3(t, n, n, x, y, z);
+        const double *phi = X.field[fid];
+        double Jd;
+        const double Lv = op_point<KIND, double>(phi[t], nb_sum(phi, x, y, z, n), 1.0 / (L.h * L.h),
+                                                 load_c1<KIND>(L.coef, t), 0.0, oc, D.scal[b * B_NSCAL + B_FBAR], Jd);
+        const double fe = L.f[t] - D.scal[b * B_NSCAL + B_FSHIFT];
+        const double e = Lv - fe;
+        v[0] = e * e;
+        v[1] = fe * fe;
+    }
+    block_store<2>(v, D.partials, total);
+}
+
+// per box: slot[c] = add_slot + scale/N * sum of the box's block partials of component c
+__global__ void __launch_bounds__(TPB) kb_finalize(BatchDev D, const int *__restrict__ tab, int ncomp, int slot,
+                                                   int add_slot, int active_only)
+{
+    const int b = blockIdx.x;
+    if (active_only && !D.active[b]) return;
+    const int total = tab[D.nbox];
+    const int n = D.box[b].lev[0].n;
+    const double invN = 1.0 / ((double)n * n * n);
+    __shared__ double sh[TPB];
+    for (int c = 0; c < ncomp; ++c) {
+        double s = 0.0;
+        for (int k = tab[b] + threadIdx.x; k < tab[b + 1]; k += TPB) s += D.partials[c * total + k];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = TPB / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+            D.scal[b * B_NSCAL + slot + c] = (add_slot >= 0 ? D.scal[b * B_NSCAL + add_slot] : 0.0) + invN * sh[0];
+        __syncthreads();
+    }
+}
+
+// phi -= box mean (B_MEAN)
+__global__ void __launch_bounds__(TPB) kb_sub_mean(BatchDev D, const int *__restrict__ tab, int fid, int active_only)
+{
+    BOX_PROLOGUE(tab)
+    if (active_only && !D.active[b]) return;
+    const int n = X.lev[0].n;
+    if (t < n * n * n) X.field[fid][t] -= D.scal[b * B_NSCAL + B_MEAN];
+}
+
+// Stopping test per box (same criterion as the single-grid solver) and the
+// cycle count; marks converged boxes inactive with the device clock time.
+__global__ void kb_control(BatchDev D, int fid, double rtol, int max_cycles)
+{
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int b = threadIdx.x; b < D.nbox; b += blockDim.x) {
+        if (!D.active[b]) continue;
+        double *s = D.scal + b * B_NSCAL;
+        const double rn = sqrt(s[B_RN]), fn = sqrt(s[B_FN]);
+        const double rel = rn / (fn > 0.0 ? fn : 1.0);
+        s[B_REL] = rel;
+        int stop = 0;
+        if (!isfinite(rel)) {
+            D.status[b] = GR_ENAN;
+            stop = 1;
+        } else if (rtol > 0.0 && (rel <= rtol || rn == 0.0)) {
+            stop = 1;
+        } else if (D.cycles[b * 10 + fid] >= max_cycles) {
+            if (rtol > 0.0) D.status[b] = GR_ENOTCONV;
+            stop = 1;
+        }
+        if (stop) {
+            D.active[b] = 0;
+            D.t_done[b * 10 + fid] = wall_clock64();
+        } else {
+            D.cycles[b * 10 + fid] += 1;
+            atomicOr(&any, 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *D.any_active = any;
+}
+
+__global__ void kb_begin_field(BatchDev D, int fid)
+{
+    for (int b = threadIdx.x; b < D.nbox; b += blockDim.x) {
+        D.active[b] = 1;
+        D.cycles[b * 10 + fid] = 0;
+        double *s = D.scal + b * B_NSCAL;
+        s[B_FBAR] = 0.0;
+        s[B_FSHIFT] = 0.0;
+    }
+    if (threadIdx.x == 0) D.t_start[fid] = wall_clock64();
+}
+
+// ------------------------------------------------------------- builders
+
+// what: 0 V_i source (s_i - <s_i>) * 3 Om a with <s_i> in B_TMP, 1 -1/4 d.V,
+// 2 A_ij/AA + Hamiltonian source + coefficient, 3 CMC coefficient/source,
+// 4 shift sources, 5 -1/4 d.B, 6 copy fB[comp] to f
+__global__ void __launch_bounds__(TPB) kb_build(BatchDev D, const int *__restrict__ tab, int what, int comp, double a,
+                                                double om, double c)
+{
+    BOX_PROLOGUE(tab)
+    const BoxLev &L = X.lev[0];
+    const int n = L.n;
+    if (t >= n * n * n) return;
+    int x, y, z;
+    decode3(t, n, n, x, y, z);
+    const double inv2h = 1.0 / (2.0 * L.h);
+    switch (what) {
+    case 0: L.f[t] = (3.0 * om * a) * (X.src[1 + comp][t] - D.scal[b * B_NSCAL + B_TMP]); break;
+    case 1: L.f[t] = div_quarter_point(X.field[GR_VX], X.field[GR_VY], X.field[GR_VZ], x, y, z, n, inv2h); break;
+    case 2: {
+        double A[6];
+        const double aa = aij_point(X.field[GR_VX], X.field[GR_VY], X.field[GR_VZ], X.field[GR_U], x, y, z, n, L.h, A);
+        for (int k = 0; k < 6; ++k) X.A6[k][t] = A[k];
+        X.AA[t] = aa;
+        L.coef[t] = aa;
+        L.f[t] = (1.5 * a * om) * (X.src[0][t] - 1.0);
+        break;
+    }
+    case 3: cmc_point(X.field[GR_PSI][t], X.src[0][t], X.src[4][t], X.AA[t], a, om, c, L.coef[t], L.f[t]); break;
+    case 4: {
+        double out[3];
+        shift_source_point(X.field[GR_PSI], X.field[GR_XI], X.A6, x, y, z, n, L.h, a, c, out);
+        X.fB[0][t] = out[0];
+        X.fB[1][t] = out[1];
+        X.fB[2][t] = out[2];
+        break;
+    }
+    case 5: L.f[t] = div_quarter_point(X.field[GR_BX], X.field[GR_BY], X.field[GR_BZ], x, y, z, n, inv2h); break;
+    default: L.f[t] = X.fB[comp][t]; break;
+    }
+}
+
+__global__ void __launch_bounds__(TPB) kb_fill_field(BatchDev D, const int *__restrict__ tab, int fid)
+{
+    BOX_PROLOGUE(tab)
+    const int n = X.lev[0].n;
+    if (t < n * n * n) X.field[fid][t] = 0.0;
+}
+
+// ----------------------------------------------------- coarse cycle per box
+
+template <int KIND>
+__device__ void cvb_sweep(double *__restrict__ phi, const double *__restrict__ f, const double *__restrict__ coef, int n,
+                          double inv_h2, OpConst oc, double Fb, double fs)
+{
+    const int half = n >> 1, tot = n * n * half;
+    for (int colour = 0; colour < 2; ++colour) {
+        for (int t = threadIdx.x; t < tot; t += CTPB) {
+            const int x2 = t % half, r = t / half, y = r % n, z = r / n;
+            const int i = 2 * x2 + ((y + z + colour) & 1);
+            const long p = lin(i, y, z, n);
+            const double ph = phi[p];
+            double J;
+            const double L = op_point<KIND, double>(ph, nb_sum(phi, i, y, z, n), inv_h2, load_c1<KIND>(coef, p), 0.0,
+                                                    oc, Fb, J);
+            phi[p] = ph - (L - (f[p] - fs)) / J;
+        }
+        __syncthreads();
+    }
+}
+
+__device__ double cvb_block_sum(double v)
+{
+    __shared__ double sh[CTPB / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < CTPB / 64; ++w) s += sh[w];
+    __syncthreads();
+    return s;
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(CTPB) kb_coarse_vcycle(BatchDev D, int fid, int nu1, int nu2, OpConst oc)
+{
+    const int b = blockIdx.x;
+    if (!D.active[b]) return;
+    const BoxDev &X = D.box[b];
+    const int l0 = X.centry, L = X.nlev;
+    auto PHI = [&](int i) { return i == 0 ? X.field[fid] : X.lev[i].phi; };
+    const double Fb0 = l0 == 0 ? D.scal[b * B_NSCAL + B_FBAR] : 0.0;
+    const double fs0 = l0 == 0 ? D.scal[b * B_NSCAL + B_FSHIFT] : 0.0;
+    for (int i = l0; i < L - 1; ++i) {
+        const BoxLev &V = X.lev[i], &C = X.lev[i + 1];
+        const int n = V.n, m = C.n;
+        double *phi = PHI(i);
+        const double inv_h2 = 1.0 / (V.h * V.h);
+        const double Fb = i == 0 ? Fb0 : 0.0, fs = i == 0 ? fs0 : 0.0;
+        for (int it = 0; it < nu1; ++it) cvb_sweep<KIND>(phi, V.f, V.coef, n, inv_h2, oc, Fb, fs);
+        const int M = m * m * m;
+        for (int q = threadIdx.x; q < M; q += CTPB) {
+            const int Xc = q % m, Yc = (q / m) % m, Zc = q / (m * m);
+            double sr = 0.0, sp = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                const int a = 2 * Xc + (c & 1), bb = 2 * Yc + ((c >> 1) & 1), dd = 2 * Zc + (c >> 2);
+                const long p = lin(a, bb, dd, n);
+                const double ph = phi[p];
+                double Jd;
+                const double Lv = op_point<KIND, double>(ph, nb_sum(phi, a, bb, dd, n), inv_h2,
+                                                         load_c1<KIND>(V.coef, p), 0.0, oc, Fb, Jd);
+                sr += Lv - (V.f[p] - fs);
+                sp += ph;
+            }
+            const double rp = sp / 8.0;
+            C.phi[q] = rp;
+            C.phi0[q] = rp;
+            C.tmp[q] = sr / 8.0;
+        }
+        __syncthreads();
+        const double inv_H2 = 1.0 / (C.h * C.h);
+        for (int q = threadIdx.x; q < M; q += CTPB) {
+            const int Xc = q % m, Yc = (q / m) % m, Zc = q / (m * m);
+            double Jd;
+            const double Lv = op_point<KIND, double>(C.phi[q], nb_sum(C.phi, Xc, Yc, Zc, m), inv_H2,
+                                                     load_c1<KIND>(C.coef, q), 0.0, oc, 0.0, Jd);
+            C.f[q] = Lv - C.tmp[q];
+        }
+        __syncthreads();
+    }
+    {
+        const int i = L - 1;
+        const BoxLev &V = X.lev[i];
+        const int n = V.n, N = n * n * n;
+        double *phi = PHI(i);
+        const double inv_h2 = 1.0 / (V.h * V.h);
+        const double Fb = i == 0 ? Fb0 : 0.0, fs = i == 0 ? fs0 : 0.0;
+        for (int q = threadIdx.x; q < N; q += CTPB) V.tmp[q] = phi[q];
+        __syncthreads();
+        for (int it = 0; it < kCoarseSweeps; ++it) cvb_sweep<KIND>(phi, V.f, V.coef, n, inv_h2, oc, Fb, fs);
+        double dsum = 0.0;
+        for (int q = threadIdx.x; q < N; q += CTPB) dsum += phi[q] - V.tmp[q];
+        const double mean = cvb_block_sum(dsum) / (double)N;
+        for (int q = threadIdx.x; q < N; q += CTPB) phi[q] -= mean;
+        __syncthreads();
+    }
+    for (int i = L - 2; i >= l0; --i) {
+        const BoxLev &V = X.lev[i], &C = X.lev[i + 1];
+        const int n = V.n, m = C.n, N = n * n * n;
+        double *phi = PHI(i);
+        const double inv_h2 = 1.0 / (V.h * V.h);
+        const double Fb = i == 0 ? Fb0 : 0.0, fs = i == 0 ? fs0 : 0.0;
+        for (int p = threadIdx.x; p < N; p += CTPB) {
+            const int a = p % n, bb = (p / n) % n, dd = p / (n * n);
+            const int I = a >> 1, J = bb >> 1, K = dd >> 1;
+            const int Is[2] = {I, wrapi(I + ((a & 1) ? 1 : -1), m)};
+            const int Js[2] = {J, wrapi(J + ((bb & 1) ? 1 : -1), m)};
+            const int Ks[2] = {K, wrapi(K + ((dd & 1) ? 1 : -1), m)};
+            double v = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+                const double w = (ox ? 0.25 : 0.75) * (oy ? 0.25 : 0.75) * (oz ? 0.25 : 0.75);
+                const long q = lin(Is[ox], Js[oy], Ks[oz], m);
+                v += w * (C.phi[q] - C.phi0[q]);
+            }
+            phi[p] += v;
+        }
+        __syncthreads();
+        for (int it = 0; it < nu2; ++it) cvb_sweep<KIND>(phi, V.f, V.coef, n, inv_h2, oc, Fb, fs);
+    }
+}
+
+// ------------------------------------------------------------------- host
+
+thread_local std::string b_err;
+
+int bfail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int bfail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    b_err = buf;
+    return code;
+}
+
+#define BHIP(expr)                                                                                    \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess) return bfail(GR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+#define BLAUNCH()                                                                                     \
+    do {                                                                                              \
+        hipError_t e_ = hipGetLastError();                                                            \
+        if (e_ != hipSuccess) return bfail(GR_EDEVICE, "kernel launch: %s", hipGetErrorString(e_));   \
+    } while (0)
+#define BCHK(expr)                                                                                    \
+    do {                                                                                              \
+        int st_ = (expr);                                                                             \
+        if (st_ != GR_OK) return st_;                                                                 \
+    } while (0)
+
+int num_levels(int n)
+{
+    int L = 1;
+    while (n % 4 == 0) {
+        n /= 2;
+        ++L;
+    }
+    return L;
+}
+
+size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+} // namespace
+
+// prefix table of blocks per box for one launch shape
+struct Tab {
+    std::vector<int> start; // host copy
+    int *dev = nullptr;
+    int total() const { return start.back(); }
+};
+
+struct gr_batch_s {
+    int nbox = 0;
+    gr_params prm{};
+    int coarse_n = 16;
+    std::vector<BoxDev> host;   // pointers into the workspace
+    int maxdepth = 0;           // deepest multigrid level handled by grouped launches
+    Tab fine;                   // fine level of every box
+    std::vector<Tab> colour, cdom, prol, coefr; // per depth
+    BatchDev D{};
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    bool use_graph = true;
+    hipGraphExec_t graph[10]{};     // per field: the captured cycle sequence
+    gr_solve_opts graph_opts[10]{}; // options it was captured with
+    std::vector<double> rel_hist;   // [nbox][10] final relative residual per field
+    double clock_khz = 0.0;
+    long total_points = 0;
+};
+
+namespace {
+
+unsigned blocks_of(long items) { return (unsigned)((items + TPB - 1) / TPB); }
+
+// workspace layout (base == nullptr: count only)
+size_t batch_layout(gr_batch B, char *base)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    };
+    auto takeD = [&](size_t count) { return reinterpret_cast<double *>(take(sizeof(double) * count)); };
+    for (int b = 0; b < B->nbox; ++b) {
+        BoxDev &X = B->host[b];
+        const long N = (long)X.lev[0].n * X.lev[0].n * X.lev[0].n;
+        for (int f = 0; f < 10; ++f) X.field[f] = takeD(N);
+        for (int s = 0; s < 5; ++s) X.src[s] = takeD(N);
+        for (int c = 0; c < 6; ++c) X.A6[c] = takeD(N);
+        X.AA = takeD(N);
+        for (int c = 0; c < 3; ++c) X.fB[c] = takeD(N);
+        for (int l = 0; l < X.nlev; ++l) {
+            BoxLev &L = X.lev[l];
+            const long M = (long)L.n * L.n * L.n;
+            L.phi = l == 0 ? nullptr : takeD(M);
+            L.phi0 = takeD(M);
+            L.f = takeD(M);
+            L.coef = takeD(M);
+            L.tmp = takeD(M);
+        }
+    }
+    auto takeI = [&](size_t count) { return reinterpret_cast<int *>(take(sizeof(int) * count)); };
+    B->D.box = reinterpret_cast<const BoxDev *>(take(sizeof(BoxDev) * B->nbox));
+    B->D.scal = takeD((size_t)B->nbox * B_NSCAL);
+    B->D.active = takeI(B->nbox);
+    B->D.cycles = takeI((size_t)B->nbox * 10);
+    B->D.status = takeI(B->nbox);
+    B->D.t_done = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * B->nbox * 10));
+    B->D.t_start = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * 10));
+    B->D.any_active = takeI(1);
+    B->D.partials = takeD((size_t)B->fine.total() * 2 + 16);
+    B->fine.dev = takeI(B->nbox + 1);
+    for (int d = 0; d < B->maxdepth; ++d) {
+        B->colour[d].dev = takeI(B->nbox + 1);
+        B->cdom[d].dev = takeI(B->nbox + 1);
+        B->prol[d].dev = takeI(B->nbox + 1);
+    }
+    for (size_t d = 0; d < B->coefr.size(); ++d) B->coefr[d].dev = takeI(B->nbox + 1);
+    return off;
+}
+
+void make_tab(Tab &T, int nbox, const std::function<long(int)> &items)
+{
+    T.start.assign(nbox + 1, 0);
+    for (int b = 0; b < nbox; ++b) T.start[b + 1] = T.start[b] + (int)blocks_of(items(b));
+}
+
+#define KDISPATCH(kind, KERNEL, GRID, BLOCK, ...)                                                      \
+    do {                                                                                              \
+        if ((kind) == GR_KIND_POISSON) KERNEL<GR_KIND_POISSON><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__);  \
+        else if ((kind) == GR_KIND_HAMILTONIAN) KERNEL<GR_KIND_HAMILTONIAN><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); \
+        else KERNEL<GR_KIND_CMC><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__);                                \
+    } while (0)
+
+OpConst opc(gr_batch B)
+{
+    OpConst o;
+    o.kappa = 1.0 / (2.0 * B->prm.a * B->prm.a * B->prm.c_tilde * B->prm.c_tilde);
+    o.A = 1.5 * B->prm.a * B->prm.omega_m;
+    return o;
+}
+
+// pin (all boxes or active ones): mean then subtract
+int batch_pin(gr_batch B, int fid, int active_only)
+{
+    hipStream_t s = B->stream;
+    kb_sum<<<B->fine.total(), TPB, 0, s>>>(B->D, B->fine.dev, fid, 0, opc(B), active_only);
+    kb_finalize<<<B->nbox, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_MEAN, -1, active_only);
+    kb_sub_mean<<<B->fine.total(), TPB, 0, s>>>(B->D, B->fine.dev, fid, active_only);
+    BLAUNCH();
+    return GR_OK;
+}
+
+// one cycle of the batch: frozen means, norms, control, V-cycle, pin
+int batch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
+{
+    hipStream_t s = B->stream;
+    const OpConst oc = opc(B);
+    const int FT = B->fine.total();
+    if (kind == GR_KIND_HAMILTONIAN) {
+        kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid, 1, oc, 1);
+        kb_finalize<<<B->nbox, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FBAR, -1, 1);
+    } else if (kind == GR_KIND_CMC) {
+        kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid, 2, oc, 1);
+        kb_finalize<<<B->nbox, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FSHIFT, B_FMEAN, 1);
+    }
+    KDISPATCH(kind, kb_res_norms, FT, TPB, B->D, B->fine.dev, fid, oc);
+    kb_finalize<<<B->nbox, TPB, 0, s>>>(B->D, B->fine.dev, 2, B_RN, -1, 1);
+    kb_control<<<1, 1024, 0, s>>>(B->D, fid, o.rtol, o.max_cycles);
+    // descent through the levels handled by grouped launches
+    for (int d = 0; d < B->maxdepth; ++d) {
+        const Tab &TC = B->colour[d], &TD = B->cdom[d];
+        if (TC.total() == 0) continue;
+        for (int it = 0; it < o.nu1; ++it)
+            for (int colour = 0; colour < 2; ++colour)
+                KDISPATCH(kind, kb_colour, TC.total(), TPB, B->D, TC.dev, d, fid, colour, oc);
+        KDISPATCH(kind, kb_residual_restrict, TD.total(), TPB, B->D, TD.dev, d, fid, oc);
+        KDISPATCH(kind, kb_coarse_rhs, TD.total(), TPB, B->D, TD.dev, d, oc);
+    }
+    KDISPATCH(kind, kb_coarse_vcycle, B->nbox, CTPB, B->D, fid, o.nu1, o.nu2, oc);
+    for (int d = B->maxdepth - 1; d >= 0; --d) {
+        const Tab &TC = B->colour[d], &TD = B->cdom[d];
+        if (TC.total() == 0) continue;
+        kb_prolong<<<B->prol[d].total(), TPB, 0, s>>>(B->D, B->prol[d].dev, d, fid);
+        for (int it = 0; it < o.nu2; ++it)
+            for (int colour = 0; colour < 2; ++colour)
+                KDISPATCH(kind, kb_colour, TC.total(), TPB, B->D, TC.dev, d, fid, colour, oc);
+        (void)TD;
+    }
+    BCHK(batch_pin(B, fid, 1));
+    BLAUNCH();
+    return GR_OK;
+}
+
+} // namespace
+
+namespace {
+
+int batch_field(gr_batch B, int kind, int fid, const gr_solve_opts &o)
+{
+    hipStream_t s = B->stream;
+    const OpConst oc = opc(B);
+    kb_begin_field<<<1, 1024, 0, s>>>(B->D, fid);
+    if (kind != GR_KIND_POISSON)
+        for (size_t d = 0; d < B->coefr.size(); ++d)
+            if (B->coefr[d].total())
+                kb_restrict_coef<<<B->coefr[d].total(), TPB, 0, s>>>(B->D, B->coefr[d].dev, (int)d);
+    if (kind == GR_KIND_CMC) {
+        kb_sum<<<B->fine.total(), TPB, 0, s>>>(B->D, B->fine.dev, fid, 3, oc, 0);
+        kb_finalize<<<B->nbox, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FMEAN, -1, 0);
+    }
+    BLAUNCH();
+    BCHK(batch_pin(B, fid, 0));
+    const bool graph = B->use_graph && s != nullptr;
+    hipGraphExec_t &ge = B->graph[fid];
+    const gr_solve_opts &go = B->graph_opts[fid];
+    if (ge && (go.nu1 != o.nu1 || go.nu2 != o.nu2 || go.max_cycles != o.max_cycles || go.rtol != o.rtol)) {
+        (void)hipGraphExecDestroy(ge);
+        ge = nullptr;
+    }
+    for (int it = 0;; ++it) {
+        if (graph) {
+            if (!ge) {
+                hipGraph_t gr;
+                BHIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+                int st = batch_cycle(B, kind, fid, o);
+                hipError_t e = hipStreamEndCapture(s, &gr);
+                if (st != GR_OK) return st;
+                if (e != hipSuccess) return bfail(GR_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+                e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                if (e != hipSuccess) return bfail(GR_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+                B->graph_opts[fid] = o;
+            }
+            BHIP(hipGraphLaunch(ge, s));
+        } else {
+            BCHK(batch_cycle(B, kind, fid, o));
+        }
+        int any = 0;
+        BHIP(hipMemcpyAsync(&any, B->D.any_active, sizeof any, hipMemcpyDeviceToHost, s));
+        BHIP(hipStreamSynchronize(s));
+        if (!any) break;
+        if (it > o.max_cycles + 2) return bfail(GR_EDEVICE, "batch control did not stop");
+    }
+    std::vector<double> sc((size_t)B->nbox * B_NSCAL);
+    BHIP(hipMemcpyAsync(sc.data(), B->D.scal, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, s));
+    BHIP(hipStreamSynchronize(s));
+    for (int b = 0; b < B->nbox; ++b) B->rel_hist[(size_t)b * 10 + fid] = sc[(size_t)b * B_NSCAL + B_REL];
+    return GR_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *gr_batch_last_error(void) { return b_err.c_str(); }
+
+int gr_create_batch(const gr_grid_desc *descs, int count, const gr_params *prm, gr_batch *out)
+{
+    if (!descs || !prm || !out) return bfail(GR_EINVAL, "null argument");
+    *out = nullptr;
+    if (count < 1 || count > kMaxBoxes) return bfail(GR_EINVAL, "count %d outside 1..%d", count, kMaxBoxes);
+    if (!(prm->a > 0.0) || !(prm->c_tilde > 0.0) || !std::isfinite(prm->omega_m))
+        return bfail(GR_EINVAL, "a and c_tilde must be positive");
+    gr_batch B = new (std::nothrow) gr_batch_s();
+    if (!B) return bfail(GR_EINVAL, "out of host memory");
+    B->nbox = count;
+    B->prm = *prm;
+    if (const char *e = std::getenv("GRMG_COARSE_N")) B->coarse_n = std::max(2, std::atoi(e));
+    if (const char *e = std::getenv("GRMG_BATCH_GRAPH")) B->use_graph = std::atoi(e) != 0;
+    B->host.resize(count);
+    int maxd = 0, maxc = 0;
+    for (int b = 0; b < count; ++b) {
+        const int n = descs[b].n;
+        if (n < 2 || (n & 1) || n > 1024 || !(descs[b].h > 0.0)) {
+            delete B;
+            return bfail(GR_EINVAL, "item %d: n = %d must be even, 2..1024, h > 0", b, n);
+        }
+        BoxDev &X = B->host[b];
+        std::memset(&X, 0, sizeof X);
+        X.nlev = num_levels(n);
+        X.centry = X.nlev - 1;
+        for (int l = 0; l < X.nlev; ++l) {
+            X.lev[l].n = n >> l;
+            X.lev[l].h = descs[b].h * (double)(1 << l);
+            if ((n >> l) <= B->coarse_n && X.centry == X.nlev - 1 && l < X.centry) X.centry = l;
+        }
+        maxd = std::max(maxd, X.centry);
+        maxc = std::max(maxc, X.nlev - 1);
+        B->total_points += (long)n * n * n;
+    }
+    B->maxdepth = maxd;
+    const int nb = count;
+    auto &H = B->host;
+    make_tab(B->fine, nb, [&](int b) { long n = H[b].lev[0].n; return n * n * n; });
+    B->colour.resize(maxd);
+    B->cdom.resize(maxd);
+    B->prol.resize(maxd);
+    for (int d = 0; d < maxd; ++d) {
+        make_tab(B->colour[d], nb, [&](int b) { long n = H[b].lev[d].n; return d < H[b].centry ? n * n * n / 2 : 0L; });
+        make_tab(B->cdom[d], nb, [&](int b) { long m = d < H[b].centry ? H[b].lev[d + 1].n : 0; return m * m * m; });
+        make_tab(B->prol[d], nb, [&](int b) { long n = H[b].lev[d].n; return d < H[b].centry ? n * n * n : 0L; });
+    }
+    B->coefr.resize(maxc);
+    for (int d = 0; d < maxc; ++d)
+        make_tab(B->coefr[d], nb, [&](int b) { long m = d + 1 < H[b].nlev ? H[b].lev[d + 1].n : 0; return m * m * m; });
+    B->ws_bytes = batch_layout(B, nullptr);
+    *out = B;
+    return GR_OK;
+}
+
+int gr_batch_workspace_bytes(gr_batch B, size_t *bytes)
+{
+    if (!B || !bytes) return bfail(GR_EINVAL, "null argument");
+    *bytes = B->ws_bytes;
+    return GR_OK;
+}
+
+int gr_batch_bind(gr_batch B, void *d_ws, size_t bytes, void *stream)
+{
+    if (!B || !d_ws) return bfail(GR_EINVAL, "null argument");
+    if (bytes < B->ws_bytes) return bfail(GR_EINVAL, "workspace %zu bytes < required %zu", bytes, B->ws_bytes);
+    if (reinterpret_cast<uintptr_t>(d_ws) % 256) return bfail(GR_EINVAL, "workspace not 256-byte aligned");
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, d_ws) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+        (void)hipGetLastError();
+        return bfail(GR_EINVAL, "workspace is not device memory");
+    }
+    for (auto &ge : B->graph)
+        if (ge) {
+            (void)hipGraphExecDestroy(ge);
+            ge = nullptr;
+        }
+    B->stream = reinterpret_cast<hipStream_t>(stream);
+    batch_layout(B, reinterpret_cast<char *>(d_ws));
+    hipStream_t s = B->stream;
+    // zero the whole workspace, then upload the box table and the block tables
+    const long nd = (long)(B->ws_bytes / sizeof(double));
+    launch_fill(s, reinterpret_cast<double *>(d_ws), nd, 0.0);
+    BLAUNCH();
+    BHIP(hipMemcpyAsync(const_cast<BoxDev *>(B->D.box), B->host.data(), sizeof(BoxDev) * B->nbox,
+                        hipMemcpyHostToDevice, s));
+    auto up = [&](Tab &T) {
+        return hipMemcpyAsync(T.dev, T.start.data(), sizeof(int) * T.start.size(), hipMemcpyHostToDevice, s);
+    };
+    BHIP(up(B->fine));
+    for (int d = 0; d < B->maxdepth; ++d) {
+        BHIP(up(B->colour[d]));
+        BHIP(up(B->cdom[d]));
+        BHIP(up(B->prol[d]));
+    }
+    for (auto &T : B->coefr) BHIP(up(T));
+    BHIP(hipStreamSynchronize(s)); // host tables must outlive the copies
+    B->D.nbox = B->nbox;
+    int dev = 0, khz = 0;
+    BHIP(hipGetDevice(&dev));
+    BHIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    B->clock_khz = khz > 0 ? khz : 100000.0;
+    B->bound = true;
+    return GR_OK;
+}
+
+int gr_destroy_batch(gr_batch B)
+{
+    if (!B) return GR_OK;
+    for (auto &ge : B->graph)
+        if (ge) (void)hipGraphExecDestroy(ge);
+    delete B;
+    return GR_OK;
+}
+
+static double *batch_slot(gr_batch B, int item, int field)
+{
+    if (item < 0 || item >= B->nbox) return nullptr;
+    BoxDev &X = B->host[item];
+    if (field >= 0 && field < 10) return X.field[field];
+    if (field >= GR_S0 && field <= GR_SM) return X.src[field - GR_S0];
+    if (field == GR_AA) return X.AA;
+    return nullptr;
+}
+
+int gr_batch_set_field(gr_batch B, int item, int field, const void *d_src, int dtype)
+{
+    if (!B || !B->bound) return bfail(B ? GR_ESTATE : GR_EINVAL, "batch not bound");
+    double *dst = batch_slot(B, item, field);
+    if (!dst || !d_src) return bfail(GR_EINVAL, "bad item %d / field %d / source", item, field);
+    const long n = B->host[item].lev[0].n, N = n * n * n;
+    if (dtype == GR_F64) launch_copy(B->stream, dst, static_cast<const double *>(d_src), N);
+    else if (dtype == GR_F32) launch_convert_f32_to_f64(B->stream, dst, static_cast<const float *>(d_src), N);
+    else return bfail(GR_EINVAL, "bad dtype %d", dtype);
+    BLAUNCH();
+    return GR_OK;
+}
+
+int gr_batch_get_field(gr_batch B, int item, int field, void *d_dst, int dtype)
+{
+    if (!B || !B->bound) return bfail(B ? GR_ESTATE : GR_EINVAL, "batch not bound");
+    double *src = batch_slot(B, item, field);
+    if (!src || !d_dst) return bfail(GR_EINVAL, "bad item %d / field %d / destination", item, field);
+    const long n = B->host[item].lev[0].n, N = n * n * n;
+    if (dtype == GR_F64) launch_copy(B->stream, static_cast<double *>(d_dst), src, N);
+    else if (dtype == GR_F32) launch_convert_f64_to_f32(B->stream, static_cast<float *>(d_dst), src, N);
+    else return bfail(GR_EINVAL, "bad dtype %d", dtype);
+    BLAUNCH();
+    return GR_OK;
+}
+
+int gr_batch_solve(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_res, double *item_seconds)
+{
+    if (!B || !o) return bfail(GR_EINVAL, "null argument");
+    if (!B->bound) return bfail(GR_ESTATE, "batch not bound");
+    if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 64 || o->nu2 > 64 || o->max_cycles < 0 || o->max_cycles > 100000)
+        return bfail(GR_EINVAL, "bad cycle options");
+    if (o->precision != GR_FP64) return bfail(GR_EINVAL, "the batched solve runs in FP64 only");
+    if (o->guess != GR_GUESS_ZERO && o->guess != GR_GUESS_CURRENT) return bfail(GR_EINVAL, "bad guess mode");
+    hipStream_t s = B->stream;
+    const gr_params &P = B->prm;
+    const unsigned mask = o->field_mask;
+    const OpConst oc = opc(B);
+    const int FT = B->fine.total();
+    B->rel_hist.assign((size_t)B->nbox * 10, 0.0);
+    std::vector<int> zero(B->nbox, 0);
+    BHIP(hipMemcpyAsync(B->D.status, zero.data(), sizeof(int) * B->nbox, hipMemcpyHostToDevice, s));
+    std::vector<unsigned long long> tz((size_t)B->nbox * 10, 0ull);
+    BHIP(hipMemcpyAsync(B->D.t_done, tz.data(), sizeof(unsigned long long) * tz.size(), hipMemcpyHostToDevice, s));
+    if (o->guess == GR_GUESS_ZERO)
+        for (int f = 0; f < 10; ++f)
+            if (mask & (1u << f)) kb_fill_field<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, f);
+    BLAUNCH();
+    auto build = [&](int what, int comp) {
+        kb_build<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, what, comp, P.a, P.omega_m, P.c_tilde);
+    };
+    for (int d = 0; d < 3; ++d) {
+        if (!(mask & (1u << d))) continue;
+        kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, 0, 4 + d, oc, 0);
+        kb_finalize<<<B->nbox, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_TMP, -1, 0);
+        build(0, d);
+        BLAUNCH();
+        BCHK(batch_field(B, GR_KIND_POISSON, GR_VX + d, *o));
+    }
+    build(1, 0);
+    if (mask & (1u << GR_U)) BCHK(batch_field(B, GR_KIND_POISSON, GR_U, *o));
+    build(2, 0);
+    if (mask & (1u << GR_PSI)) BCHK(batch_field(B, GR_KIND_HAMILTONIAN, GR_PSI, *o));
+    build(3, 0);
+    if (mask & (1u << GR_XI)) BCHK(batch_field(B, GR_KIND_CMC, GR_XI, *o));
+    build(4, 0);
+    for (int d = 0; d < 3; ++d) {
+        if (!(mask & (1u << (GR_BX + d)))) continue;
+        build(6, d);
+        BLAUNCH();
+        BCHK(batch_field(B, GR_KIND_POISSON, GR_BX + d, *o));
+    }
+    build(5, 0);
+    if (mask & (1u << GR_BB)) BCHK(batch_field(B, GR_KIND_POISSON, GR_BB, *o));
+    BLAUNCH();
+    // results
+    std::vector<int> st(B->nbox), cyc((size_t)B->nbox * 10);
+    std::vector<unsigned long long> td((size_t)B->nbox * 10), t0(10);
+    BHIP(hipMemcpyAsync(st.data(), B->D.status, sizeof(int) * st.size(), hipMemcpyDeviceToHost, s));
+    BHIP(hipMemcpyAsync(cyc.data(), B->D.cycles, sizeof(int) * cyc.size(), hipMemcpyDeviceToHost, s));
+    BHIP(hipMemcpyAsync(td.data(), B->D.t_done, sizeof(unsigned long long) * td.size(), hipMemcpyDeviceToHost, s));
+    BHIP(hipMemcpyAsync(t0.data(), B->D.t_start, sizeof(unsigned long long) * 10, hipMemcpyDeviceToHost, s));
+    BHIP(hipStreamSynchronize(s));
+    if (cycles) std::memcpy(cycles, cyc.data(), sizeof(int) * cyc.size());
+    if (item_seconds)
+        for (int b = 0; b < B->nbox; ++b) {
+            double sum = 0.0;
+            for (int f = 0; f < 10; ++f)
+                if ((mask & (1u << f)) && td[b * 10 + f] >= t0[f]) sum += (double)(td[b * 10 + f] - t0[f]);
+            item_seconds[b] = sum / (B->clock_khz * 1e3);
+        }
+    if (rel_res) {
+        for (int b = 0; b < B->nbox; ++b)
+            for (int f = 0; f < 10; ++f) rel_res[b * 10 + f] = B->rel_hist[(size_t)b * 10 + f];
+    }
+    int first_bad = GR_OK;
+    for (int b = 0; b < B->nbox; ++b)
+        if (st[b] != GR_OK) {
+            first_bad = st[b];
+            bfail(st[b], "item %d did not converge (status %d)", b, st[b]);
+            break;
+        }
+    return first_bad;
+}
+
+} // extern "C"

@@ -1,25 +1,13 @@
 // Source and coefficient builders for the ten field equations, the CIC
 // matter deposit, and the derived fields (paper sec. 4.1.2, 4.3, 4.5).
-#include "gr_internal.h"
+#include "sources_ops.h"
 
 namespace grmg {
 
 namespace {
 
 constexpr int TPB = 256;
-
-__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
-
-__device__ __forceinline__ long lin(int i, int j, int k, int n) { return ((long)k * n + j) * n + i; }
-
-// Central difference of g along `dir` at (i,j,k): (g_+ - g_-)/(2h).
-__device__ __forceinline__ double dcen(const double *__restrict__ g, int dir, int i, int j, int k, int n,
-                                       double inv2h)
-{
-    const int di = dir == 0, dj = dir == 1, dk = dir == 2;
-    return (g[lin(wrapi(i + di, n), wrapi(j + dj, n), wrapi(k + dk, n), n)]
-            - g[lin(wrapi(i - di, n), wrapi(j - dj, n), wrapi(k - dk, n), n)]) * inv2h;
-}
+using namespace detail;
 
 __device__ __forceinline__ int wrap_any(long i, int n)
 {
@@ -99,15 +87,14 @@ __global__ void k_div_quarter(double *__restrict__ out, const double *__restrict
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int i = (int)(p % n), j = (int)((p / n) % n), k = (int)(p / ((long)n * n));
-    out[p] = -0.25 * (dcen(gx, 0, i, j, k, n, inv2h) + dcen(gy, 1, i, j, k, n, inv2h) + dcen(gz, 2, i, j, k, n, inv2h));
+    out[p] = div_quarter_point(gx, gy, gz, i, j, k, n, inv2h);
 }
 
 struct A6Ptrs {
     double *c[6];
 };
 
-// A_ij = d_iV_j + d_jV_i - 1/2 delta_ij d_kV^k + 2 d_i d_j U  (packed xx,yy,zz,xy,xz,yz)
-// diagonal d_i d_i U: 3-point; off-diagonal: 4-point diagonal-neighbour formula.
+// A_ij and A_ijA^ij at every point
 __global__ void __launch_bounds__(TPB) k_build_Aij(A6Ptrs A6, double *__restrict__ AA,
                                                    const double *__restrict__ Vx, const double *__restrict__ Vy,
                                                    const double *__restrict__ Vz, const double *__restrict__ U,
@@ -117,34 +104,9 @@ __global__ void __launch_bounds__(TPB) k_build_Aij(A6Ptrs A6, double *__restrict
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int i = (int)(p % n), j = (int)((p / n) % n), k = (int)(p / ((long)n * n));
-    const double inv2h = 1.0 / (2.0 * h), invh2 = 1.0 / (h * h), inv4h2 = 1.0 / (4.0 * h * h);
-    const double *V[3] = {Vx, Vy, Vz};
-    double dV[3][3]; // dV[a][b] = d_a V_b
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) dV[a][b] = dcen(V[b], a, i, j, k, n, inv2h);
-    const double divV = dV[0][0] + dV[1][1] + dV[2][2];
-    const int ip = wrapi(i + 1, n), im = wrapi(i - 1, n), jp = wrapi(j + 1, n), jm = wrapi(j - 1, n);
-    const int kp = wrapi(k + 1, n), km = wrapi(k - 1, n);
-    const double u0 = U[p];
-    const double uxx = (U[lin(ip, j, k, n)] - 2.0 * u0 + U[lin(im, j, k, n)]) * invh2;
-    const double uyy = (U[lin(i, jp, k, n)] - 2.0 * u0 + U[lin(i, jm, k, n)]) * invh2;
-    const double uzz = (U[lin(i, j, kp, n)] - 2.0 * u0 + U[lin(i, j, km, n)]) * invh2;
-    const double uxy = (U[lin(ip, jp, k, n)] + U[lin(im, jm, k, n)] - U[lin(ip, jm, k, n)] - U[lin(im, jp, k, n)]) * inv4h2;
-    const double uxz = (U[lin(ip, j, kp, n)] + U[lin(im, j, km, n)] - U[lin(ip, j, km, n)] - U[lin(im, j, kp, n)]) * inv4h2;
-    const double uyz = (U[lin(i, jp, kp, n)] + U[lin(i, jm, km, n)] - U[lin(i, jp, km, n)] - U[lin(i, jm, kp, n)]) * inv4h2;
-    const double axx = 2.0 * dV[0][0] + 2.0 * uxx - 0.5 * divV;
-    const double ayy = 2.0 * dV[1][1] + 2.0 * uyy - 0.5 * divV;
-    const double azz = 2.0 * dV[2][2] + 2.0 * uzz - 0.5 * divV;
-    const double axy = dV[0][1] + dV[1][0] + 2.0 * uxy;
-    const double axz = dV[0][2] + dV[2][0] + 2.0 * uxz;
-    const double ayz = dV[1][2] + dV[2][1] + 2.0 * uyz;
-    A6.c[0][p] = axx;
-    A6.c[1][p] = ayy;
-    A6.c[2][p] = azz;
-    A6.c[3][p] = axy;
-    A6.c[4][p] = axz;
-    A6.c[5][p] = ayz;
-    AA[p] = axx * axx + ayy * ayy + azz * azz + 2.0 * (axy * axy + axz * axz + ayz * ayz);
+    double A[6];
+    AA[p] = aij_point(Vx, Vy, Vz, U, i, j, k, n, h, A);
+    for (int c = 0; c < 6; ++c) A6.c[c][p] = A[c];
 }
 
 __global__ void k_ham_rhs(double *__restrict__ f, const double *__restrict__ s0, long N, double A)
@@ -153,25 +115,17 @@ __global__ void k_ham_rhs(double *__restrict__ f, const double *__restrict__ s0,
     if (p < N) f[p] = A * (s0[p] - 1.0);
 }
 
-// CMC coefficient m2 = chi^-1 Q/(a^2c^2) and source
-// f = 3/2 a Om chi^-1 [s0 - chi^6 + s_m] + AA chi^-7, with
-// Q = 3/4 a Om chi^-1 [s0 + 5 chi^6 + 2 s_m] + 7/8 AA chi^-7.
+// CMC coefficient m2 and source f at every point
 __global__ void k_build_cmc(double *__restrict__ m2, double *__restrict__ f, const double *__restrict__ psi,
                             const double *__restrict__ s0, const double *__restrict__ sm,
                             const double *__restrict__ AA, long N, double a, double om, double c)
 {
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
-    const double kap = 1.0 / (2.0 * a * a * c * c);
-    const double chi = 1.0 - kap * psi[p];
-    const double chi2 = chi * chi, chi6 = chi2 * chi2 * chi2;
-    const double chim7 = 1.0 / (chi6 * chi);
-    const double Q = 0.75 * a * om / chi * (s0[p] + 5.0 * chi6 + 2.0 * sm[p]) + 0.875 * AA[p] * chim7;
-    m2[p] = Q / (chi * a * a * c * c);
-    f[p] = 1.5 * a * om / chi * (s0[p] - chi6 + sm[p]) + AA[p] * chim7;
+    cmc_point(psi[p], s0[p], sm[p], AA[p], a, om, c, m2[p], f[p]);
 }
 
-// f_B^i = 2 sum_j d_j[alpha chi^-6 A_ij], alpha = 1 + (xi/chi)/(a^2c^2).
+// sources of the three B^i equations at every point
 __global__ void __launch_bounds__(TPB) k_shift_source(double *__restrict__ fBx, double *__restrict__ fBy,
                                                       double *__restrict__ fBz, const double *__restrict__ psi,
                                                       const double *__restrict__ xi, A6Ptrs A6, int n, double h,
@@ -181,30 +135,11 @@ __global__ void __launch_bounds__(TPB) k_shift_source(double *__restrict__ fBx, 
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
     const int i = (int)(p % n), j = (int)((p / n) % n), k = (int)(p / ((long)n * n));
-    const double kap = 1.0 / (2.0 * a * a * c * c), ia2c2 = 1.0 / (a * a * c * c), inv2h = 1.0 / (2.0 * h);
-    // (row, col) -> packed component
-    const int comp[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
-    double out[3] = {0.0, 0.0, 0.0};
-    for (int col = 0; col < 3; ++col) {
-        const int di = col == 0, dj = col == 1, dk = col == 2;
-        const long pp = lin(wrapi(i + di, n), wrapi(j + dj, n), wrapi(k + dk, n), n);
-        const long pm = lin(wrapi(i - di, n), wrapi(j - dj, n), wrapi(k - dk, n), n);
-        double g[2];
-        const long ps[2] = {pp, pm};
-        for (int s = 0; s < 2; ++s) {
-            const double chi = 1.0 - kap * psi[ps[s]];
-            const double chi2 = chi * chi, chi6 = chi2 * chi2 * chi2;
-            const double alpha = 1.0 + (xi[ps[s]] / chi) * ia2c2;
-            g[s] = alpha / chi6;
-        }
-        for (int row = 0; row < 3; ++row) {
-            const double *Ac = A6.c[comp[row][col]];
-            out[row] += (g[0] * Ac[pp] - g[1] * Ac[pm]) * inv2h;
-        }
-    }
-    fBx[p] = 2.0 * out[0];
-    fBy[p] = 2.0 * out[1];
-    fBz[p] = 2.0 * out[2];
+    double out[3];
+    shift_source_point(psi, xi, A6.c, i, j, k, n, h, a, c, out);
+    fBx[p] = out[0];
+    fBy[p] = out[1];
+    fBz[p] = out[2];
 }
 
 // derived fields: 0 Phi = xi/chi, 1 alpha = 1 + Phi/(a^2c^2), 2 psi = a^(1/2) chi,

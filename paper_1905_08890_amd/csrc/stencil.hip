@@ -16,76 +16,14 @@
 // a = chi, c = dL/dPsi - chi dLap/dPsi; CMC a = 1, c = -m2.
 #include <type_traits>
 
-#include "gr_internal.h"
+#include "stencil_ops.h"
 
 namespace grmg {
 
 namespace {
 
 constexpr int TPB = 256;
-
-__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
-
-__device__ __forceinline__ long lin(int i, int j, int k, int n) { return ((long)k * n + j) * n + i; }
-
-// Sum of the six face neighbours of (i,j,k) with periodic wrap.
-template <typename T>
-__device__ __forceinline__ T nb_sum(const T *__restrict__ p, int i, int j, int k, int n)
-{
-    int ip = wrapi(i + 1, n), im = wrapi(i - 1, n);
-    int jp = wrapi(j + 1, n), jm = wrapi(j - 1, n);
-    int kp = wrapi(k + 1, n), km = wrapi(k - 1, n);
-    return p[lin(ip, j, k, n)] + p[lin(im, j, k, n)] + p[lin(i, jp, k, n)] + p[lin(i, jm, k, n)]
-         + p[lin(i, j, kp, n)] + p[lin(i, j, km, n)];
-}
-
-// number of coefficient arrays an operator reads
-template <int KIND> constexpr int kNumCoef()
-{
-    return (KIND == GR_KIND_POISSON || KIND == K_LIN_POISSON) ? 0 : (KIND == K_LIN_HAM ? 2 : 1);
-}
-
-// L(phi) at a point (without the source) and dL/dphi there.
-// c1: AA (Hamiltonian), m2 (CMC), c (linearised kinds); c2: a (linearised Hamiltonian).
-template <int KIND, typename T>
-__device__ __forceinline__ T op_point(T ph, T nbs, T inv_h2, T c1, T c2, OpConst oc, T Fbar, T &J)
-{
-    const T lap = (nbs - T(6) * ph) * inv_h2;
-    if constexpr (KIND == GR_KIND_POISSON || KIND == K_LIN_POISSON) {
-        J = T(-6) * inv_h2;
-        return lap;
-    } else if constexpr (KIND == GR_KIND_CMC) {
-        J = T(-6) * inv_h2 - c1;
-        return lap - c1 * ph;
-    } else if constexpr (KIND == K_LIN_CMC) {
-        J = T(-6) * inv_h2 + c1;
-        return lap + c1 * ph;
-    } else if constexpr (KIND == K_LIN_HAM) {
-        J = T(-6) * c2 * inv_h2 + c1;
-        return c2 * lap + c1 * ph;
-    } else {
-        const double kap = oc.kappa, A = oc.A;
-        const double chi = 1.0 - kap * ph;
-        const double chi2 = chi * chi;
-        const double chi5 = chi2 * chi2 * chi;
-        const double chi6 = chi5 * chi;
-        const double chim6 = 1.0 / chi6;
-        const double chim7 = chim6 / chi;
-        J = -kap * lap - 6.0 * chi * inv_h2 - 6.0 * A * kap * chi5 - 1.5 * kap * c1 * chim7 - kap * Fbar;
-        return chi * lap + A * (chi6 - 1.0) - 0.25 * c1 * chim6 + Fbar * chi;
-    }
-}
-
-template <int KIND, typename T>
-__device__ __forceinline__ T load_c1(const T *__restrict__ c1, long p)
-{
-    return kNumCoef<KIND>() >= 1 ? c1[p] : T(0);
-}
-template <int KIND, typename T>
-__device__ __forceinline__ T load_c2(const T *__restrict__ c2, long p)
-{
-    return kNumCoef<KIND>() >= 2 ? c2[p] : T(0);
-}
+using namespace detail;
 
 // 3-D launch geometry for an nx x ny x nz domain: x across the threads of a
 // block (up to 64), y across threadIdx.y/blockIdx.y, z = blockIdx.z.

@@ -30,7 +30,9 @@ FIELD_IDS.update(dict(s0=S0, sx=SX, sy=SY, sz=SZ, sm=SM, AA=AA, Phi=PHI, alpha=A
 
 EXPORTS = ("gr_default_opts", "gr_create_grid", "gr_workspace_bytes", "gr_bind", "gr_deposit_sources",
            "gr_set_field", "gr_get_field", "gr_solve_constraints", "gr_solve_equation", "gr_debug_sweep",
-           "gr_debug_residual", "gr_destroy_grid", "gr_last_error")
+           "gr_debug_residual", "gr_destroy_grid", "gr_last_error", "gr_create_batch", "gr_batch_workspace_bytes",
+           "gr_batch_bind", "gr_batch_set_field", "gr_batch_get_field", "gr_batch_solve", "gr_destroy_batch",
+           "gr_batch_last_error")
 
 
 class GrParams(C.Structure):
@@ -86,6 +88,14 @@ def load_library(path: str = LIB_PATH):
         "gr_debug_sweep": [vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int],
         "gr_debug_residual": [vp, C.c_int, C.c_int, C.c_double, C.c_double, vp],
         "gr_destroy_grid": [vp],
+        "gr_create_batch": [C.POINTER(GrGridDesc), C.c_int, C.POINTER(GrParams), C.POINTER(vp)],
+        "gr_batch_workspace_bytes": [vp, C.POINTER(C.c_size_t)],
+        "gr_batch_bind": [vp, vp, C.c_size_t, vp],
+        "gr_batch_set_field": [vp, C.c_int, C.c_int, vp, C.c_int],
+        "gr_batch_get_field": [vp, C.c_int, C.c_int, vp, C.c_int],
+        "gr_batch_solve": [vp, C.POINTER(GrSolveOpts), C.POINTER(C.c_int), C.POINTER(C.c_double),
+                           C.POINTER(C.c_double)],
+        "gr_destroy_batch": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -93,6 +103,8 @@ def load_library(path: str = LIB_PATH):
         fn.restype = C.c_int
     lib.gr_last_error.argtypes = []
     lib.gr_last_error.restype = C.c_char_p
+    lib.gr_batch_last_error.argtypes = []
+    lib.gr_batch_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -104,6 +116,16 @@ def last_error() -> str:
 def _check(code: int, allow=(OK,)):
     if code not in allow:
         raise GrError(code, last_error())
+    return code
+
+
+def batch_last_error() -> str:
+    return load_library().gr_batch_last_error().decode()
+
+
+def _bcheck(code: int, allow=(OK,)):
+    if code not in allow:
+        raise GrError(code, batch_last_error())
     return code
 
 
@@ -244,3 +266,99 @@ class Grid:
     def solve_equation(self, kind, field, allow=(OK,), **kw):
         fid = FIELD_IDS[field] if isinstance(field, str) else field
         return solve_equation(self.handle, kind, fid, default_opts(**kw), allow).as_dict()
+
+
+# ---- batched solve ----
+
+def create_batch(ns, a: float, omega_m: float, c_tilde: float) -> int:
+    descs = (GrGridDesc * len(ns))(*[GrGridDesc(int(n), 1.0 / int(n)) for n in ns])
+    g = C.c_void_p()
+    _bcheck(load_library().gr_create_batch(descs, len(ns), C.byref(GrParams(a, omega_m, c_tilde)), C.byref(g)))
+    return g.value
+
+
+def batch_workspace_bytes(b: int) -> int:
+    v = C.c_size_t()
+    _bcheck(load_library().gr_batch_workspace_bytes(b, C.byref(v)))
+    return v.value
+
+
+def batch_bind(b: int, workspace, stream: int) -> None:
+    _bcheck(load_library().gr_batch_bind(b, _ptr(workspace), workspace.numel() * workspace.element_size(), stream))
+
+
+def batch_set_field(b: int, item: int, field: int, src, dtype: int) -> None:
+    _bcheck(load_library().gr_batch_set_field(b, item, field, _ptr(src), dtype))
+
+
+def batch_get_field(b: int, item: int, field: int, dst, dtype: int) -> None:
+    _bcheck(load_library().gr_batch_get_field(b, item, field, _ptr(dst), dtype))
+
+
+def batch_solve(b: int, count: int, opts: GrSolveOpts, allow=(OK,)):
+    cyc = (C.c_int * (10 * count))()
+    rel = (C.c_double * (10 * count))()
+    sec = (C.c_double * count)()
+    st = _bcheck(load_library().gr_batch_solve(b, C.byref(opts), cyc, rel, sec), allow)
+    return st, [list(cyc[10 * i:10 * i + 10]) for i in range(count)], \
+        [list(rel[10 * i:10 * i + 10]) for i in range(count)], list(sec)
+
+
+def destroy_batch(b: int) -> None:
+    _bcheck(load_library().gr_destroy_batch(b))
+
+
+class Batch:
+    """Many periodic boxes (sides ns) solved together on `device`.  Uses its own
+    non-default stream so that each cycle can be captured in a hipGraph."""
+
+    def __init__(self, ns, a: float = 1.0, omega_m: float = 0.3072, c_tilde: float = 2997.92458 / 256.0,
+                 device="cuda"):
+        import torch
+
+        self.torch = torch
+        self.ns = [int(n) for n in ns]
+        self.device = torch.device(device)
+        if self.device.type != "cuda" or not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU device (no CPU fallback)")
+        self.handle = create_batch(self.ns, a, omega_m, c_tilde)
+        self.workspace = torch.empty(batch_workspace_bytes(self.handle), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()
+        batch_bind(self.handle, self.workspace, self.stream.cuda_stream)
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "handle", None):
+            destroy_batch(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_field(self, item, field, values):
+        t = self.torch
+        fid = FIELD_IDS[field] if isinstance(field, str) else field
+        v = values if isinstance(values, t.Tensor) else t.as_tensor(values)
+        v = v.to(device=self.device, dtype=t.float64).contiguous()
+        assert v.numel() == self.ns[item] ** 3
+        t.cuda.current_stream(self.device).synchronize()
+        batch_set_field(self.handle, item, fid, v, F64)
+        self._keep.append(v)
+
+    def get_field(self, item, field):
+        t = self.torch
+        fid = FIELD_IDS[field] if isinstance(field, str) else field
+        n = self.ns[item]
+        out = t.empty((n, n, n), dtype=t.float64, device=self.device)
+        batch_get_field(self.handle, item, fid, out, F64)
+        self.stream.synchronize()
+        return out
+
+    def solve(self, allow=(OK,), **kw):
+        st, cyc, rel, sec = batch_solve(self.handle, len(self.ns), default_opts(**kw), allow)
+        self._keep.clear()
+        return dict(status=st, cycles=cyc, rel_res=rel, item_seconds=sec)

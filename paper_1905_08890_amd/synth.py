@@ -88,3 +88,26 @@ WORKLOADS = {
     "zeldovich128": (128, 1, 0.3),
     "zeldovich256": (256, 2, 1.0),
 }
+
+
+BATCH_SIDES = (32, 48, 64, 96, 128)
+
+
+def batch_item(seed: int, sides=BATCH_SIDES, sigma_range=(0.05, 1.0)):
+    """One box of the batched workload: side drawn from `sides`, density
+    contrast sigma log-uniform in sigma_range, delta a k^-2 GRF (seed `seed`),
+    s0 = 1 + delta, longitudinal momentum s_i = -d_i Lap^-1 delta rescaled to
+    rms |s| = 1e-3, s_m = 0.  Returns (n, (s0, sx, sy, sz, sm))."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.choice(np.asarray(sides)))
+    sigma = float(np.exp(rng.uniform(np.log(sigma_range[0]), np.log(sigma_range[1]))))
+    delta = grf(n, seed, -2.0, sigma)
+    D = np.fft.fftn(delta)
+    k1 = 2.0 * np.pi * np.fft.fftfreq(n, d=1.0 / n)
+    kz, ky, kx = np.meshgrid(k1, k1, k1, indexing="ij")
+    k2 = kx * kx + ky * ky + kz * kz
+    k2[0, 0, 0] = 1.0
+    mom = [np.real(np.fft.ifftn(1j * kk / k2 * D)) for kk in (kx, ky, kz)]
+    rms = np.sqrt(np.mean(mom[0] ** 2 + mom[1] ** 2 + mom[2] ** 2))
+    mom = [np.ascontiguousarray(m * (1e-3 / rms)) for m in mom]
+    return n, (1.0 + delta, mom[0], mom[1], mom[2], np.zeros((n, n, n)))

@@ -1,0 +1,85 @@
+"""Batched solve of uneven periodic boxes: every box equals its single-grid
+solve and the oracle at identical cycle counts; graph replays equal eager
+launches."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1905_08890_amd import grmg, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+PRM = dict(a=1.0, omega_m=synth.OMEGA_M, c_tilde=synth.C_TILDE)
+SIDES = (8, 12, 16, 24, 32, 48)
+
+
+def maxrel(x, ref):
+    x = x.cpu().numpy() if hasattr(x, "cpu") else x
+    return float(np.abs(x - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+def make_items(count, seed0):
+    return [synth.batch_item(seed0 + i, sides=SIDES, sigma_range=(0.05, 0.5)) for i in range(count)]
+
+
+def load(batch, items):
+    for i, (n, src) in enumerate(items):
+        for name, x in zip(("s0", "sx", "sy", "sz", "sm"), src):
+            batch.set_field(i, name, x)
+
+
+def test_batch_matches_single_grid_and_oracle():
+    items = make_items(7, 300)
+    print("[gpu] batch sides", [n for n, _ in items], flush=True)
+    B = grmg.Batch([n for n, _ in items], **PRM)
+    load(B, items)
+    rep = B.solve(rtol=1e-10)
+    assert rep["status"] == 0
+    p = O.params(**PRM)
+    for i, (n, src) in enumerate(items):
+        g = grmg.Grid(n, **PRM)
+        for name, x in zip(("s0", "sx", "sy", "sz", "sm"), src):
+            g.set_field(name, x)
+        single = g.solve_constraints(rtol=1e-10)
+        assert single["cycles"] == rep["cycles"][i], i
+        fields, st, cyc, rel, AA = O.solve_all(*src, prm=p, rtol=0, max_cycles=rep["cycles"][i])
+        for name in O.FIELDS:
+            out = B.get_field(i, name)
+            assert maxrel(out, g.get_field(name).cpu().numpy()) < 1e-13, (i, name)
+            assert maxrel(out, fields[name]) < 1e-12, (i, name)
+        assert max(rep["rel_res"][i]) <= 1e-10
+        assert rep["item_seconds"][i] > 0
+
+
+def test_batch_graph_replays_equal_eager(monkeypatch):
+    """The per-cycle graph, replayed 1..4 times (with the solver's own eager
+    launches and synchronisations between replays), gives the same fields as
+    launching the same sequence eagerly."""
+    items = make_items(5, 400)
+    results = {}
+    for use_graph in ("1", "0"):
+        monkeypatch.setenv("GRMG_BATCH_GRAPH", use_graph)
+        B = grmg.Batch([n for n, _ in items], **PRM)
+        load(B, items)
+        per_k = []
+        for k in (1, 2, 3, 4):
+            rep = B.solve(rtol=0, max_cycles=k)
+            per_k.append([[B.get_field(i, f).cpu().numpy() for f in ("Vx", "Psi", "xi", "b")]
+                          for i in range(len(items))])
+        results[use_graph] = per_k
+    for k in range(4):
+        for i in range(len(items)):
+            for a, b in zip(results["1"][k][i], results["0"][k][i]):
+                assert np.array_equal(a, b), (k, i)
+
+
+def test_batch_rejects_bad_input():
+    with pytest.raises(grmg.GrError):
+        grmg.create_batch([16, 7], 1.0, 0.3, 11.7)
+    B = grmg.Batch([8, 16], **PRM)
+    with pytest.raises(grmg.GrError):
+        grmg.batch_solve(B.handle, 2, grmg.default_opts(precision="mixed"))
+    x = torch.zeros((8, 8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(grmg.GrError):
+        grmg.batch_set_field(B.handle, 5, grmg.S0, x, grmg.F64)
