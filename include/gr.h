@@ -213,6 +213,41 @@ int gr_batch_solve(gr_batch b, const gr_solve_opts *opts, int *cycles, double *r
 int gr_destroy_batch(gr_batch b);
 const char *gr_batch_last_error(void);
 
+/* ---- learned initial guess: a small 3-D U-Net ----
+ * Levels with c[0..3] channels (c[0] = 16; c[1..3] in 16..64, multiples of
+ * 16): two 3^3 convolutions + ReLU per level, 2x2x2 average pooling down,
+ * nearest upsampling up with skip concatenation, and a 1x1 head.  Periodic
+ * boundaries.  Convolutions run on BF16 matrix cores with FP32 accumulation;
+ * parameters, gradients and Adam moments are FP32.  Inputs/outputs are planar
+ * FP32 [channel][n^3] device arrays (x fastest), n a multiple of 32 up to
+ * max_n.  Parameter vector order: per convolution (e0a, e0b, e1a, e1b, e2a,
+ * e2b, e3a, e3b, d2a, d2b, d1a, d1b, d0a, d0b) weights [cout][27][cin]
+ * (taps (dz,dy,dx) in {-1,0,1}^3, dx fastest) then bias [cout]; then the head
+ * [out_ch][c0] and its bias. */
+typedef struct gr_unet_s *gr_unet;
+typedef struct {
+    int in_ch, out_ch;
+    int c[4];
+} gr_unet_desc;
+
+int gr_unet_create(const gr_unet_desc *desc, int max_n, gr_unet *out);
+int gr_unet_workspace_bytes(gr_unet u, size_t *bytes);
+int gr_unet_param_count(gr_unet u, int64_t *count);
+int gr_unet_bind(gr_unet u, void *d_workspace, size_t bytes, void *hip_stream);
+/* He-normal weights from a counter-based generator (splitmix64 of seed and index). */
+int gr_unet_init(gr_unet u, uint64_t seed);
+int gr_unet_set_params(gr_unet u, const float *d_src);
+int gr_unet_get_params(gr_unet u, float *d_dst);
+/* d_out[out_ch][n^3] = network(d_in[in_ch][n^3]) */
+int gr_unet_forward(gr_unet u, int n, const float *d_in, float *d_out);
+/* Mean-square loss against d_target and its parameter gradient (copied to
+ * d_grad[param_count] when not NULL); *h_loss (host) receives the loss. */
+int gr_unet_loss_grad(gr_unet u, int n, const float *d_in, const float *d_target, float *d_grad, double *h_loss);
+/* One Adam step (beta 0.9/0.999, eps 1e-8) with learning rate lr. */
+int gr_unet_train_step(gr_unet u, int n, const float *d_in, const float *d_target, float lr, double *h_loss);
+int gr_destroy_unet(gr_unet u);
+const char *gr_unet_last_error(void);
+
 /* Destroy a handle (the workspace stays the caller's). NULL is accepted. */
 int gr_destroy_grid(gr_grid g);
 

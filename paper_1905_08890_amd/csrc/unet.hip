@@ -1,0 +1,829 @@
+// Learned initial guess: a small 3-D U-Net (levels with c0/c1/c2/c3 channels,
+// two 3^3 convolutions + ReLU per level, 2x2x2 average pooling down, nearest
+// upsampling up, skip concatenation, 1x1 head), trained and run on the GPU by
+// the kernels below.
+//
+// Layout: activations channels-last [z][y][x][C] in BF16, periodic boundaries
+// (the fields live on a periodic box).  Convolutions are implicit GEMMs on the
+// BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation):
+// M = 16 voxels per wave, N = output channels (16 per tile), K = 27 taps x
+// input channels, padded to a multiple of 32; each lane feeds 8 consecutive
+// input channels of one tap (a 16-byte load).  The input-gradient of a
+// convolution is the same kernel applied to the output-gradient with the
+// weights flipped in space and transposed in channels.  Weight gradients
+// accumulate in FP32; Adam keeps FP32 master weights.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gr_internal.h"
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ __forceinline__ int wrapn(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// ------------------------------------------------------------ convolution
+
+// out[v][ocoff + co] = act(bias[co] + sum_k in[v + off(tap)][icoff + ci] w[co][k]),
+// k = tap * cin + ci, taps ordered (dz, dy, dx) in {-1,0,1}^3 with dx fastest.
+// One wave: 16 consecutive voxels x all COUT channels.  n^3 must be a multiple
+// of 64 (4 waves per block).
+template <int COUT, bool RELU, bool BIAS>
+__global__ void __launch_bounds__(256) k_conv3(const bf16 *__restrict__ in, int cin, int icstride, int icoff,
+                                               const bf16 *__restrict__ w, int kpad, const float *__restrict__ bias,
+                                               bf16 *__restrict__ out, int ocstride, int ocoff, int n)
+{
+    constexpr int NT = COUT / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int v0 = (blockIdx.x * 4 + wave) * 16;
+    const int i = lane & 15, g = lane >> 4;
+    const int v = v0 + i;
+    const int x = v % n, y = (v / n) % n, z = v / (n * n);
+    floatx4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const int ktot = 27 * cin;
+    for (int k0c = 0; k0c < kpad; k0c += 32) {
+        const int k0 = k0c + 8 * g;
+        bf16x8 a;
+        if (k0 < ktot) {
+            const int tap = k0 / cin, ci = k0 - tap * cin;
+            const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+            const long nv = ((long)wrapn(z + dz, n) * n + wrapn(y + dy, n)) * n + wrapn(x + dx, n);
+            a = *reinterpret_cast<const bf16x8 *>(in + nv * icstride + icoff + ci);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) a[j] = (bf16)0.0f;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(w + (long)(16 * t + i) * kpad + k0);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[t], 0, 0, 0);
+        }
+    }
+    // lane holds D[4g + j][i]: voxel v0 + 4g + j, channel 16t + i
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int co = 16 * t + i;
+        const float b = BIAS ? bias[co] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float r = acc[t][j] + b;
+            if (RELU) r = r > 0.0f ? r : 0.0f;
+            out[(long)(v0 + 4 * g + j) * ocstride + ocoff + co] = (bf16)r;
+        }
+    }
+}
+
+// dW[co][tap*cin + ci] += sum_v g[v][gcoff + co] in[v + off(tap)][icoff + ci]; db[co] += sum_v g[v][co].
+// Block: one tap, a chunk of voxels; 256 threads each own up to 32 (co, ci)
+// accumulators (co = tid % cout, ci = tid / cout + 8-stride loop).
+constexpr int WG_VOX = 32;
+__global__ void __launch_bounds__(TPB) k_conv3_wgrad(const bf16 *__restrict__ g, int cout, int gcstride, int gcoff,
+                                                     const bf16 *__restrict__ in, int cin, int icstride, int icoff,
+                                                     float *__restrict__ dw, int kpad, float *__restrict__ db, int n,
+                                                     int vox_per_block)
+{
+    __shared__ float sg[WG_VOX][128];
+    __shared__ float si[WG_VOX][128];
+    const int tap = blockIdx.y;
+    const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+    const int N = n * n * n;
+    const int vbeg = blockIdx.x * vox_per_block, vend = min(N, vbeg + vox_per_block);
+    const int npair = cout * cin;
+    float acc[32];
+#pragma unroll
+    for (int q = 0; q < 32; ++q) acc[q] = 0.0f;
+    float bacc = 0.0f;
+    for (int vb = vbeg; vb < vend; vb += WG_VOX) {
+        const int nv = min(WG_VOX, vend - vb);
+        for (int e = threadIdx.x; e < WG_VOX * 128; e += TPB) {
+            const int r = e / 128, c = e % 128;
+            float gv = 0.0f, iv = 0.0f;
+            if (r < nv) {
+                const int v = vb + r;
+                if (c < cout) gv = (float)g[(long)v * gcstride + gcoff + c];
+                if (c < cin) {
+                    const int x = v % n, y = (v / n) % n, z = v / (n * n);
+                    const long q = ((long)wrapn(z + dz, n) * n + wrapn(y + dy, n)) * n + wrapn(x + dx, n);
+                    iv = (float)in[q * icstride + icoff + c];
+                }
+            }
+            sg[r][c] = gv;
+            si[r][c] = iv;
+        }
+        __syncthreads();
+        for (int r = 0; r < nv; ++r) {
+#pragma unroll
+            for (int q = 0; q < 32; ++q) {
+                const int pidx = threadIdx.x + q * TPB;
+                if (pidx < npair) acc[q] += sg[r][pidx % cout] * si[r][pidx / cout];
+            }
+            if (tap == 13 && threadIdx.x < cout) bacc += sg[r][threadIdx.x];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+        const int pidx = threadIdx.x + q * TPB;
+        if (pidx < npair) {
+            const int co = pidx % cout, ci = pidx / cout;
+            atomicAdd(dw + (long)co * kpad + tap * cin + ci, acc[q]);
+        }
+    }
+    if (tap == 13 && threadIdx.x < cout && db) atomicAdd(db + threadIdx.x, bacc);
+}
+
+// ------------------------------------------------------------ elementwise
+
+// planar FP32 [cin][n^3] -> channels-last BF16 [n^3][16] (zero channels above cin)
+__global__ void k_pack_input(const float *__restrict__ src, int cin, bf16 *__restrict__ dst, long N)
+{
+    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    for (int c = 0; c < 16; ++c) dst[v * 16 + c] = (bf16)(c < cin ? src[c * N + v] : 0.0f);
+}
+
+// 2x2x2 average of channels [coff, coff + c) -> [m^3][c]
+__global__ void k_pool(const bf16 *__restrict__ in, int cstride, int coff, int c, bf16 *__restrict__ out, int n)
+{
+    const int m = n / 2;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long)m * m * m * c) return;
+    const int ch = (int)(q % c);
+    const long V = q / c;
+    const int X = (int)(V % m), Y = (int)((V / m) % m), Z = (int)(V / ((long)m * m));
+    float s = 0.0f;
+    for (int k = 0; k < 8; ++k) {
+        const long v = ((long)(2 * Z + (k >> 2)) * n + 2 * Y + ((k >> 1) & 1)) * n + 2 * X + (k & 1);
+        s += (float)in[v * cstride + coff + ch];
+    }
+    out[V * c + ch] = (bf16)(0.125f * s);
+}
+
+// gradient of the pooling, added to channels [coff, coff + c) of gin
+__global__ void k_pool_bwd_add(const bf16 *__restrict__ gout, int c, bf16 *__restrict__ gin, int cstride, int coff,
+                               int n)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long)n * n * n * c) return;
+    const int ch = (int)(q % c);
+    const long v = q / c;
+    const int x = (int)(v % n), y = (int)((v / n) % n), z = (int)(v / ((long)n * n));
+    const int m = n / 2;
+    const long V = ((long)(z / 2) * m + y / 2) * m + x / 2;
+    const long d = v * cstride + coff + ch;
+    gin[d] = (bf16)((float)gin[d] + 0.125f * (float)gout[V * c + ch]);
+}
+
+// nearest upsampling of [m^3][c] into channels [0, c) of out [n^3][cstride]
+__global__ void k_upsample(const bf16 *__restrict__ in, int c, bf16 *__restrict__ out, int cstride, int n)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long)n * n * n * c) return;
+    const int ch = (int)(q % c);
+    const long v = q / c;
+    const int x = (int)(v % n), y = (int)((v / n) % n), z = (int)(v / ((long)n * n));
+    const int m = n / 2;
+    out[v * cstride + ch] = in[(((long)(z / 2) * m + y / 2) * m + x / 2) * c + ch];
+}
+
+// gradient of the upsampling: sum of the 8 children's channels [0, c)
+__global__ void k_upsample_bwd(const bf16 *__restrict__ gout, int cstride, int c, bf16 *__restrict__ gin, int n)
+{
+    const int m = n / 2;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long)m * m * m * c) return;
+    const int ch = (int)(q % c);
+    const long V = q / c;
+    const int X = (int)(V % m), Y = (int)((V / m) % m), Z = (int)(V / ((long)m * m));
+    float s = 0.0f;
+    for (int k = 0; k < 8; ++k) {
+        const long v = ((long)(2 * Z + (k >> 2)) * n + 2 * Y + ((k >> 1) & 1)) * n + 2 * X + (k & 1);
+        s += (float)gout[v * cstride + ch];
+    }
+    gin[V * c + ch] = (bf16)s;
+}
+
+// g = g * (a > 0) on channels [coff, coff + c) of both (ReLU gradient)
+__global__ void k_relu_bwd(bf16 *__restrict__ g, int gcstride, int gcoff, const bf16 *__restrict__ a, int acstride,
+                           int acoff, int c, long N)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N * c) return;
+    const int ch = (int)(q % c);
+    const long v = q / c;
+    if (!((float)a[v * acstride + acoff + ch] > 0.0f)) g[v * gcstride + gcoff + ch] = (bf16)0.0f;
+}
+
+// 1x1 head: y[o][v] = b[o] + sum_c w[o][c] h[v][c]   (FP32 planar output)
+__global__ void k_head(const bf16 *__restrict__ h, int c, const float *__restrict__ w, const float *__restrict__ b,
+                       float *__restrict__ y, int cout, long N)
+{
+    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    float hv[16];
+    for (int k = 0; k < c; ++k) hv[k] = (float)h[v * c + k];
+    for (int o = 0; o < cout; ++o) {
+        float s = b[o];
+        for (int k = 0; k < c; ++k) s += w[o * c + k] * hv[k];
+        y[o * N + v] = s;
+    }
+}
+
+// MSE loss pieces: gy = 2 (y - t) / (cout N); per-block partial sums of (y - t)^2
+__global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, float *__restrict__ gy, long total,
+                      float *__restrict__ partial)
+{
+    __shared__ float sh[TPB];
+    float s = 0.0f;
+    for (long q = (long)blockIdx.x * TPB + threadIdx.x; q < total; q += (long)gridDim.x * TPB) {
+        const float d = y[q] - t[q];
+        gy[q] = 2.0f * d / (float)total;
+        s += d * d;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = TPB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+// head backward: gh[v][c] = sum_o w[o][c] gy[o][v]; dW, db accumulated per block then atomically
+__global__ void k_head_bwd(const float *__restrict__ gy, const bf16 *__restrict__ h, int c, const float *__restrict__ w,
+                           int cout, bf16 *__restrict__ gh, float *__restrict__ dw, float *__restrict__ db, long N)
+{
+    __shared__ float sdw[16 * 16 + 16];
+    for (int e = threadIdx.x; e < cout * c + cout; e += TPB) sdw[e] = 0.0f;
+    __syncthreads();
+    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < N) {
+        float hv[16];
+        for (int k = 0; k < c; ++k) hv[k] = (float)h[v * c + k];
+        for (int k = 0; k < c; ++k) {
+            float s = 0.0f;
+            for (int o = 0; o < cout; ++o) s += w[o * c + k] * gy[o * N + v];
+            gh[v * c + k] = (bf16)s;
+        }
+        for (int o = 0; o < cout; ++o) {
+            const float go = gy[o * N + v];
+            for (int k = 0; k < c; ++k) atomicAdd(&sdw[o * c + k], go * hv[k]);
+            atomicAdd(&sdw[cout * c + o], go);
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < cout * c; e += TPB) atomicAdd(dw + e, sdw[e]);
+    for (int e = threadIdx.x; e < cout; e += TPB) atomicAdd(db + e, sdw[cout * c + e]);
+}
+
+// FP32 master weights -> BF16 forward layout [co][kpad] and the flipped /
+// transposed layout [ci][kpad'] used for input gradients.
+__global__ void k_prep_weights(const float *__restrict__ w, int cout, int cin, int kpad, int kpadT,
+                               bf16 *__restrict__ wf, bf16 *__restrict__ wt)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long tot = (long)cout * kpad;
+    if (q < tot) {
+        const int co = (int)(q / kpad), k = (int)(q % kpad);
+        wf[q] = (bf16)(k < 27 * cin ? w[(long)co * 27 * cin + k] : 0.0f);
+    }
+    const long totT = (long)cin * kpadT;
+    if (q < totT) {
+        const int ci = (int)(q / kpadT), k = (int)(q % kpadT);
+        float val = 0.0f;
+        if (k < 27 * cout) {
+            const int tapT = k / cout, co = k % cout;
+            const int tap = 26 - tapT; // off(tapT) = -off(tap)
+            val = w[(long)co * 27 * cin + tap * cin + ci];
+        }
+        wt[q] = (bf16)val;
+    }
+}
+
+// Adam (FP32): p -= lr * mhat / (sqrt(vhat) + eps)
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+                       long N, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    const float gq = g[q];
+    const float mq = b1 * m[q] + (1.0f - b1) * gq;
+    const float vq = b2 * v[q] + (1.0f - b2) * gq * gq;
+    m[q] = mq;
+    v[q] = vq;
+    p[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+// He-normal initialisation from a counter-based generator: splitmix64 of
+// (seed, index) -> two uniforms -> Box-Muller.
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+__global__ void k_init_normal(float *__restrict__ p, long N, float stddev, unsigned long long seed)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    const unsigned long long r = splitmix64(seed ^ splitmix64((unsigned long long)q));
+    const double u1 = ((r >> 11) + 1.0) * (1.0 / 9007199254740993.0);
+    const double u2 = (splitmix64(r) >> 11) * (1.0 / 9007199254740992.0);
+    p[q] = (float)(stddev * sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+}
+
+__global__ void k_zero_f32(float *__restrict__ p, long N)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < N) p[q] = 0.0f;
+}
+__global__ void k_zero_bf16(bf16 *__restrict__ p, long N)
+{
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < N) p[q] = (bf16)0.0f;
+}
+
+unsigned nb(long count) { return (unsigned)((count + TPB - 1) / TPB); }
+
+thread_local std::string u_err;
+int ufail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int ufail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    u_err = buf;
+    return code;
+}
+#define UHIP(expr)                                                                                    \
+    do {                                                                                              \
+        hipError_t e_ = (expr);                                                                       \
+        if (e_ != hipSuccess) return ufail(GR_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+#define ULAUNCH()                                                                                     \
+    do {                                                                                              \
+        hipError_t e_ = hipGetLastError();                                                            \
+        if (e_ != hipSuccess) return ufail(GR_EDEVICE, "kernel launch: %s", hipGetErrorString(e_));   \
+    } while (0)
+
+int pad32(int k) { return (k + 31) / 32 * 32; }
+
+template <bool RELU, bool BIAS>
+bool launch_conv_t(hipStream_t s, int cout, const bf16 *in, int cin, int ics, int icoff, const bf16 *w, int kpad,
+                   const float *bias, bf16 *out, int ocs, int ocoff, int n)
+{
+    const long N = (long)n * n * n;
+    const unsigned grid = (unsigned)(N / 64);
+#define CONV_CASE(C)                                                                                  \
+    case C: k_conv3<C, RELU, BIAS><<<grid, 256, 0, s>>>(in, cin, ics, icoff, w, kpad, bias, out, ocs, ocoff, n); break;
+    switch (cout) {
+        CONV_CASE(16)
+        CONV_CASE(32)
+        CONV_CASE(48)
+        CONV_CASE(64)
+        CONV_CASE(96)
+        CONV_CASE(128)
+    default: return false;
+    }
+#undef CONV_CASE
+    return true;
+}
+
+} // namespace
+
+// ------------------------------------------------------------------ network
+
+struct ConvLayer {
+    int cin, cout, kpad, kpadT;
+    long w_off, b_off; // offsets into the FP32 parameter vector
+    bf16 *wf = nullptr, *wt = nullptr;
+};
+
+struct Act { // one channels-last BF16 tensor
+    bf16 *p = nullptr;
+    int n = 0, c = 0;
+};
+
+struct gr_unet_s {
+    gr_unet_desc d{};
+    int max_n = 0;
+    int c[4];
+    ConvLayer conv[14]; // e0a e0b e1a e1b e2a e2b e3a e3b d2a d2b d1a d1b d0a d0b
+    long head_w = 0, head_b = 0;
+    long nparam = 0;
+    // device
+    float *param = nullptr, *grad = nullptr, *adam_m = nullptr, *adam_v = nullptr;
+    float *loss_partial = nullptr, *y = nullptr, *gy = nullptr;
+    bf16 *x0 = nullptr;
+    Act ea[4], eb3, cat[3], p[3], da[3], db[3];       // forward
+    Act g_ea[4], g_eb3, g_cat[3], g_p[3], g_da[3], g_db[3], g_x; // backward
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    long step = 0;
+};
+
+namespace {
+
+enum { E0A, E0B, E1A, E1B, E2A, E2B, E3A, E3B, D2A, D2B, D1A, D1B, D0A, D0B };
+
+size_t unet_layout(gr_unet U, char *base)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    auto takeF = [&](size_t n) { return reinterpret_cast<float *>(take(sizeof(float) * n)); };
+    auto takeB = [&](size_t n) { return reinterpret_cast<bf16 *>(take(sizeof(bf16) * n)); };
+    U->param = takeF(U->nparam);
+    U->grad = takeF(U->nparam);
+    U->adam_m = takeF(U->nparam);
+    U->adam_v = takeF(U->nparam);
+    for (auto &L : U->conv) {
+        L.wf = takeB((size_t)L.cout * L.kpad);
+        L.wt = takeB((size_t)L.cin * L.kpadT);
+    }
+    const int n = U->max_n;
+    const long N = (long)n * n * n;
+    U->loss_partial = takeF(1024);
+    U->y = takeF((size_t)U->d.out_ch * N);
+    U->gy = takeF((size_t)U->d.out_ch * N);
+    U->x0 = takeB((size_t)N * 16);
+    auto act = [&](Act &a, int lvl, int ch) {
+        a.n = n >> lvl;
+        a.c = ch;
+        a.p = takeB((size_t)a.n * a.n * a.n * ch);
+    };
+    const int *c = U->c;
+    for (int k = 0; k < 4; ++k) act(U->ea[k], k, c[k]);
+    act(U->eb3, 3, c[3]);
+    for (int k = 0; k < 3; ++k) {
+        act(U->cat[k], k, c[k + 1] + c[k]);
+        act(U->p[k], k + 1, c[k]);
+        act(U->da[k], k, c[k]);
+        act(U->db[k], k, c[k]);
+        act(U->g_cat[k], k, c[k + 1] + c[k]);
+        act(U->g_p[k], k + 1, c[k]);
+        act(U->g_da[k], k, c[k]);
+        act(U->g_db[k], k, c[k]);
+    }
+    for (int k = 0; k < 4; ++k) act(U->g_ea[k], k, c[k]);
+    act(U->g_eb3, 3, c[3]);
+    act(U->g_x, 0, 16);
+    return off;
+}
+
+int conv_fwd(gr_unet U, int li, const bf16 *in, int ics, int icoff, bf16 *out, int ocs, int ocoff, int n)
+{
+    const ConvLayer &L = U->conv[li];
+    if (!launch_conv_t<true, true>(U->stream, L.cout, in, L.cin, ics, icoff, L.wf, L.kpad, U->param + L.b_off, out,
+                                   ocs, ocoff, n))
+        return ufail(GR_EINVAL, "unsupported channel count %d", L.cout);
+    ULAUNCH();
+    return GR_OK;
+}
+
+// input gradient of layer li: gin = conv(gout, flipped/transposed weights)
+int conv_dgrad(gr_unet U, int li, const bf16 *gout, int gcs, int gcoff, bf16 *gin, int n)
+{
+    const ConvLayer &L = U->conv[li];
+    if (!launch_conv_t<false, false>(U->stream, L.cin, gout, L.cout, gcs, gcoff, L.wt, L.kpadT, nullptr, gin, L.cin,
+                                     0, n))
+        return ufail(GR_EINVAL, "unsupported channel count %d", L.cin);
+    ULAUNCH();
+    return GR_OK;
+}
+
+int conv_wgrad(gr_unet U, int li, const bf16 *gout, int gcs, int gcoff, const bf16 *in, int ics, int icoff, int n)
+{
+    const ConvLayer &L = U->conv[li];
+    const long N = (long)n * n * n;
+    const int vpb = (int)std::max<long>(WG_VOX, std::min<long>(2048, N / 16));
+    dim3 grid((unsigned)((N + vpb - 1) / vpb), 27);
+    k_conv3_wgrad<<<grid, TPB, 0, U->stream>>>(gout, L.cout, gcs, gcoff, in, L.cin, ics, icoff, U->grad + L.w_off, 27 * L.cin,
+                                              U->grad + L.b_off, n, vpb);
+    ULAUNCH();
+    return GR_OK;
+}
+
+int relu_bwd(gr_unet U, bf16 *g, int gcs, int gcoff, const bf16 *a, int acs, int acoff, int c, int n)
+{
+    const long N = (long)n * n * n;
+    k_relu_bwd<<<nb(N * c), TPB, 0, U->stream>>>(g, gcs, gcoff, a, acs, acoff, c, N);
+    ULAUNCH();
+    return GR_OK;
+}
+
+#define UCHK(expr)                                                                                    \
+    do {                                                                                              \
+        int st_ = (expr);                                                                             \
+        if (st_ != GR_OK) return st_;                                                                 \
+    } while (0)
+
+int refresh_weights(gr_unet U)
+{
+    for (auto &L : U->conv) {
+        const long tot = std::max((long)L.cout * L.kpad, (long)L.cin * L.kpadT);
+        k_prep_weights<<<nb(tot), TPB, 0, U->stream>>>(U->param + L.w_off, L.cout, L.cin, L.kpad, L.kpadT, L.wf, L.wt);
+    }
+    ULAUNCH();
+    return GR_OK;
+}
+
+// forward pass for an n^3 input (planar FP32 [in_ch][n^3]) -> U->y
+int forward(gr_unet U, int n, const float *d_in)
+{
+    hipStream_t s = U->stream;
+    const long N = (long)n * n * n;
+    const int *c = U->c;
+    k_pack_input<<<nb(N), TPB, 0, s>>>(d_in, U->d.in_ch, U->x0, N);
+    ULAUNCH();
+    // encoder
+    UCHK(conv_fwd(U, E0A, U->x0, 16, 0, U->ea[0].p, c[0], 0, n));
+    UCHK(conv_fwd(U, E0B, U->ea[0].p, c[0], 0, U->cat[0].p, c[1] + c[0], c[1], n));
+    const bf16 *prev = nullptr;
+    for (int k = 0; k < 3; ++k) {
+        const int nk = n >> k, nk1 = nk >> 1;
+        // pool the skip channels of cat[k]
+        k_pool<<<nb((long)nk1 * nk1 * nk1 * c[k]), TPB, 0, s>>>(U->cat[k].p, c[k + 1] + c[k], c[k + 1], c[k], U->p[k].p, nk);
+        ULAUNCH();
+        const int la = E1A + 2 * k, lb = E1B + 2 * k;
+        UCHK(conv_fwd(U, la, U->p[k].p, c[k], 0, U->ea[k + 1].p, c[k + 1], 0, nk1));
+        if (k < 2) UCHK(conv_fwd(U, lb, U->ea[k + 1].p, c[k + 1], 0, U->cat[k + 1].p, c[k + 2] + c[k + 1], c[k + 2], nk1));
+        else UCHK(conv_fwd(U, lb, U->ea[3].p, c[3], 0, U->eb3.p, c[3], 0, nk1));
+    }
+    (void)prev;
+    // decoder
+    for (int k = 2; k >= 0; --k) {
+        const int nk = n >> k;
+        const Act &src = (k == 2) ? U->eb3 : U->db[k + 1];
+        k_upsample<<<nb((long)nk * nk * nk * src.c), TPB, 0, s>>>(src.p, src.c, U->cat[k].p, c[k + 1] + c[k], nk);
+        ULAUNCH();
+        const int la = D2A + 2 * (2 - k), lb = D2B + 2 * (2 - k);
+        UCHK(conv_fwd(U, la, U->cat[k].p, c[k + 1] + c[k], 0, U->da[k].p, c[k], 0, nk));
+        UCHK(conv_fwd(U, lb, U->da[k].p, c[k], 0, U->db[k].p, c[k], 0, nk));
+    }
+    k_head<<<nb(N), TPB, 0, s>>>(U->db[0].p, c[0], U->param + U->head_w, U->param + U->head_b, U->y, U->d.out_ch, N);
+    ULAUNCH();
+    return GR_OK;
+}
+
+// backward pass (after forward and k_mse filled U->gy): accumulates U->grad
+int backward(gr_unet U, int n)
+{
+    hipStream_t s = U->stream;
+    const long N = (long)n * n * n;
+    const int *c = U->c;
+    k_head_bwd<<<nb(N), TPB, 0, s>>>(U->gy, U->db[0].p, c[0], U->param + U->head_w, U->d.out_ch, U->g_db[0].p,
+                                     U->grad + U->head_w, U->grad + U->head_b, N);
+    ULAUNCH();
+    // decoder, fine to coarse: each level's concat gradient feeds the next coarser output
+    for (int k = 0; k <= 2; ++k) {
+        const int nk = n >> k;
+        const int la = D2A + 2 * (2 - k), lb = D2B + 2 * (2 - k);
+        const int C = c[k + 1] + c[k];
+        UCHK(relu_bwd(U, U->g_db[k].p, c[k], 0, U->db[k].p, c[k], 0, c[k], nk));
+        UCHK(conv_wgrad(U, lb, U->g_db[k].p, c[k], 0, U->da[k].p, c[k], 0, nk));
+        UCHK(conv_dgrad(U, lb, U->g_db[k].p, c[k], 0, U->g_da[k].p, nk));
+        UCHK(relu_bwd(U, U->g_da[k].p, c[k], 0, U->da[k].p, c[k], 0, c[k], nk));
+        UCHK(conv_wgrad(U, la, U->g_da[k].p, c[k], 0, U->cat[k].p, C, 0, nk));
+        UCHK(conv_dgrad(U, la, U->g_da[k].p, c[k], 0, U->g_cat[k].p, nk));
+        // upsampled channels [0, c[k+1]) -> gradient of the coarser output
+        const int m = nk / 2;
+        bf16 *dst = (k == 2) ? U->g_eb3.p : U->g_db[k + 1].p;
+        k_upsample_bwd<<<nb((long)m * m * m * c[k + 1]), TPB, 0, s>>>(U->g_cat[k].p, C, c[k + 1], dst, nk);
+        ULAUNCH();
+    }
+    // bottleneck
+    {
+        const int n3 = n >> 3;
+        UCHK(relu_bwd(U, U->g_eb3.p, c[3], 0, U->eb3.p, c[3], 0, c[3], n3));
+        UCHK(conv_wgrad(U, E3B, U->g_eb3.p, c[3], 0, U->ea[3].p, c[3], 0, n3));
+        UCHK(conv_dgrad(U, E3B, U->g_eb3.p, c[3], 0, U->g_ea[3].p, n3));
+        UCHK(relu_bwd(U, U->g_ea[3].p, c[3], 0, U->ea[3].p, c[3], 0, c[3], n3));
+        UCHK(conv_wgrad(U, E3A, U->g_ea[3].p, c[3], 0, U->p[2].p, c[2], 0, n3));
+        UCHK(conv_dgrad(U, E3A, U->g_ea[3].p, c[3], 0, U->g_p[2].p, n3));
+    }
+    // encoder, coarse to fine: skip gradient = decoder part (in g_cat) + pooling part
+    for (int k = 2; k >= 0; --k) {
+        const int nk = n >> k;
+        const int C = c[k + 1] + c[k];
+        k_pool_bwd_add<<<nb((long)nk * nk * nk * c[k]), TPB, 0, s>>>(U->g_p[k].p, c[k], U->g_cat[k].p, C, c[k + 1], nk);
+        ULAUNCH();
+        const int la = E0A + 2 * k, lb = E0B + 2 * k;
+        UCHK(relu_bwd(U, U->g_cat[k].p, C, c[k + 1], U->cat[k].p, C, c[k + 1], c[k], nk));
+        UCHK(conv_wgrad(U, lb, U->g_cat[k].p, C, c[k + 1], U->ea[k].p, c[k], 0, nk));
+        UCHK(conv_dgrad(U, lb, U->g_cat[k].p, C, c[k + 1], U->g_ea[k].p, nk));
+        UCHK(relu_bwd(U, U->g_ea[k].p, c[k], 0, U->ea[k].p, c[k], 0, c[k], nk));
+        if (k > 0) {
+            UCHK(conv_wgrad(U, la, U->g_ea[k].p, c[k], 0, U->p[k - 1].p, c[k - 1], 0, nk));
+            UCHK(conv_dgrad(U, la, U->g_ea[k].p, c[k], 0, U->g_p[k - 1].p, nk));
+        } else {
+            UCHK(conv_wgrad(U, la, U->g_ea[0].p, c[0], 0, U->x0, 16, 0, nk));
+        }
+    }
+    return GR_OK;
+}
+
+// forward + MSE loss + backward; loss (mean square) returned on the host
+int loss_and_grad(gr_unet U, int n, const float *d_in, const float *d_target, double *h_loss)
+{
+    const long N = (long)n * n * n;
+    k_zero_f32<<<nb(U->nparam), TPB, 0, U->stream>>>(U->grad, U->nparam);
+    ULAUNCH();
+    UCHK(forward(U, n, d_in));
+    const long tot = (long)U->d.out_ch * N;
+    const int nbk = (int)std::min<long>(1024, (tot + TPB - 1) / TPB);
+    k_mse<<<nbk, TPB, 0, U->stream>>>(U->y, d_target, U->gy, tot, U->loss_partial);
+    ULAUNCH();
+    UCHK(backward(U, n));
+    if (h_loss) {
+        std::vector<float> part(nbk);
+        UHIP(hipMemcpyAsync(part.data(), U->loss_partial, sizeof(float) * nbk, hipMemcpyDeviceToHost, U->stream));
+        UHIP(hipStreamSynchronize(U->stream));
+        double acc = 0.0;
+        for (float v : part) acc += v;
+        *h_loss = acc / (double)tot;
+    }
+    return GR_OK;
+}
+
+int check_n(gr_unet U, int n)
+{
+    if (!U || !U->bound) return ufail(U ? GR_ESTATE : GR_EINVAL, "network not bound");
+    if (n < 32 || n % 32 || n > U->max_n) return ufail(GR_EINVAL, "n = %d must be a multiple of 32, <= %d", n, U->max_n);
+    return GR_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *gr_unet_last_error(void) { return u_err.c_str(); }
+
+int gr_unet_create(const gr_unet_desc *d, int max_n, gr_unet *out)
+{
+    if (!d || !out) return ufail(GR_EINVAL, "null argument");
+    *out = nullptr;
+    if (d->in_ch < 1 || d->in_ch > 16 || d->out_ch < 1 || d->out_ch > 16)
+        return ufail(GR_EINVAL, "in_ch and out_ch must be 1..16");
+    if (d->c[0] != 16) return ufail(GR_EINVAL, "c[0] must be 16");
+    for (int k = 1; k < 4; ++k)
+        if (d->c[k] < 16 || d->c[k] > 64 || d->c[k] % 16) return ufail(GR_EINVAL, "c[%d] must be 16, 32, 48 or 64", k);
+    if (max_n < 32 || max_n % 32 || max_n > 512) return ufail(GR_EINVAL, "max_n must be a multiple of 32 up to 512");
+    gr_unet U = new (std::nothrow) gr_unet_s();
+    if (!U) return ufail(GR_EINVAL, "out of host memory");
+    U->d = *d;
+    U->max_n = max_n;
+    for (int k = 0; k < 4; ++k) U->c[k] = d->c[k];
+    const int *c = U->c;
+    const int io[14][2] = {{16, c[0]}, {c[0], c[0]}, {c[0], c[1]}, {c[1], c[1]}, {c[1], c[2]}, {c[2], c[2]},
+                           {c[2], c[3]}, {c[3], c[3]}, {c[3] + c[2], c[2]}, {c[2], c[2]}, {c[2] + c[1], c[1]},
+                           {c[1], c[1]}, {c[1] + c[0], c[0]}, {c[0], c[0]}};
+    long off = 0;
+    for (int l = 0; l < 14; ++l) {
+        ConvLayer &L = U->conv[l];
+        L.cin = io[l][0];
+        L.cout = io[l][1];
+        L.kpad = pad32(27 * L.cin);
+        L.kpadT = pad32(27 * L.cout);
+        L.w_off = off;
+        off += (long)L.cout * 27 * L.cin;
+        L.b_off = off;
+        off += L.cout;
+    }
+    U->head_w = off;
+    off += (long)d->out_ch * c[0];
+    U->head_b = off;
+    off += d->out_ch;
+    U->nparam = off;
+    U->ws_bytes = unet_layout(U, nullptr);
+    *out = U;
+    return GR_OK;
+}
+
+int gr_unet_workspace_bytes(gr_unet U, size_t *bytes)
+{
+    if (!U || !bytes) return ufail(GR_EINVAL, "null argument");
+    *bytes = U->ws_bytes;
+    return GR_OK;
+}
+
+int gr_unet_param_count(gr_unet U, int64_t *count)
+{
+    if (!U || !count) return ufail(GR_EINVAL, "null argument");
+    *count = U->nparam;
+    return GR_OK;
+}
+
+int gr_unet_bind(gr_unet U, void *d_ws, size_t bytes, void *stream)
+{
+    if (!U || !d_ws) return ufail(GR_EINVAL, "null argument");
+    if (bytes < U->ws_bytes) return ufail(GR_EINVAL, "workspace %zu bytes < required %zu", bytes, U->ws_bytes);
+    if (reinterpret_cast<uintptr_t>(d_ws) % 256) return ufail(GR_EINVAL, "workspace not 256-byte aligned");
+    U->stream = reinterpret_cast<hipStream_t>(stream);
+    unet_layout(U, reinterpret_cast<char *>(d_ws));
+    const long nw = (long)(U->ws_bytes / sizeof(float));
+    k_zero_f32<<<nb(nw), TPB, 0, U->stream>>>(reinterpret_cast<float *>(d_ws), nw);
+    ULAUNCH();
+    U->bound = true;
+    U->step = 0;
+    return GR_OK;
+}
+
+// He-normal weights (std sqrt(2 / fan_in)), zero biases, zero Adam moments.
+int gr_unet_init(gr_unet U, uint64_t seed)
+{
+    if (!U || !U->bound) return ufail(U ? GR_ESTATE : GR_EINVAL, "network not bound");
+    hipStream_t s = U->stream;
+    k_zero_f32<<<nb(U->nparam), TPB, 0, s>>>(U->param, U->nparam);
+    k_zero_f32<<<nb(U->nparam), TPB, 0, s>>>(U->adam_m, U->nparam);
+    k_zero_f32<<<nb(U->nparam), TPB, 0, s>>>(U->adam_v, U->nparam);
+    for (int l = 0; l < 14; ++l) {
+        const ConvLayer &L = U->conv[l];
+        const long cnt = (long)L.cout * 27 * L.cin;
+        k_init_normal<<<nb(cnt), TPB, 0, s>>>(U->param + L.w_off, cnt, std::sqrt(2.0f / (27.0f * L.cin)),
+                                             seed * 1000003ull + l);
+    }
+    const long hc = (long)U->d.out_ch * U->c[0];
+    k_init_normal<<<nb(hc), TPB, 0, s>>>(U->param + U->head_w, hc, std::sqrt(1.0f / U->c[0]), seed * 1000003ull + 99);
+    ULAUNCH();
+    U->step = 0;
+    return refresh_weights(U);
+}
+
+int gr_unet_set_params(gr_unet U, const float *d_src)
+{
+    if (!U || !U->bound || !d_src) return ufail(GR_EINVAL, "bad argument");
+    UHIP(hipMemcpyAsync(U->param, d_src, sizeof(float) * U->nparam, hipMemcpyDeviceToDevice, U->stream));
+    return refresh_weights(U);
+}
+
+int gr_unet_get_params(gr_unet U, float *d_dst)
+{
+    if (!U || !U->bound || !d_dst) return ufail(GR_EINVAL, "bad argument");
+    UHIP(hipMemcpyAsync(d_dst, U->param, sizeof(float) * U->nparam, hipMemcpyDeviceToDevice, U->stream));
+    return GR_OK;
+}
+
+int gr_unet_forward(gr_unet U, int n, const float *d_in, float *d_out)
+{
+    int st = check_n(U, n);
+    if (st) return st;
+    if (!d_in || !d_out) return ufail(GR_EINVAL, "null tensor");
+    UCHK(forward(U, n, d_in));
+    const long N = (long)n * n * n;
+    UHIP(hipMemcpyAsync(d_out, U->y, sizeof(float) * U->d.out_ch * N, hipMemcpyDeviceToDevice, U->stream));
+    return GR_OK;
+}
+
+int gr_unet_loss_grad(gr_unet U, int n, const float *d_in, const float *d_target, float *d_grad, double *h_loss)
+{
+    int st = check_n(U, n);
+    if (st) return st;
+    if (!d_in || !d_target) return ufail(GR_EINVAL, "null tensor");
+    UCHK(loss_and_grad(U, n, d_in, d_target, h_loss));
+    if (d_grad)
+        UHIP(hipMemcpyAsync(d_grad, U->grad, sizeof(float) * U->nparam, hipMemcpyDeviceToDevice, U->stream));
+    return GR_OK;
+}
+
+int gr_unet_train_step(gr_unet U, int n, const float *d_in, const float *d_target, float lr, double *h_loss)
+{
+    int st = check_n(U, n);
+    if (st) return st;
+    if (!d_in || !d_target || !(lr > 0.0f)) return ufail(GR_EINVAL, "bad argument");
+    UCHK(loss_and_grad(U, n, d_in, d_target, h_loss));
+    ++U->step;
+    const float b1 = 0.9f, b2 = 0.999f;
+    k_adam<<<nb(U->nparam), TPB, 0, U->stream>>>(U->param, U->grad, U->adam_m, U->adam_v, U->nparam, lr, b1, b2, 1e-8f,
+                                                1.0f - std::pow(b1, (float)U->step), 1.0f - std::pow(b2, (float)U->step));
+    ULAUNCH();
+    return refresh_weights(U);
+}
+
+int gr_destroy_unet(gr_unet U)
+{
+    delete U;
+    return GR_OK;
+}
+
+} // extern "C"

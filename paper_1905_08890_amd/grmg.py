@@ -32,7 +32,9 @@ EXPORTS = ("gr_default_opts", "gr_create_grid", "gr_workspace_bytes", "gr_bind",
            "gr_set_field", "gr_get_field", "gr_solve_constraints", "gr_solve_equation", "gr_debug_sweep",
            "gr_debug_residual", "gr_destroy_grid", "gr_last_error", "gr_create_batch", "gr_batch_workspace_bytes",
            "gr_batch_bind", "gr_batch_set_field", "gr_batch_get_field", "gr_batch_solve", "gr_destroy_batch",
-           "gr_batch_last_error")
+           "gr_batch_last_error", "gr_unet_create", "gr_unet_workspace_bytes", "gr_unet_param_count", "gr_unet_bind",
+           "gr_unet_init", "gr_unet_set_params", "gr_unet_get_params", "gr_unet_forward", "gr_unet_loss_grad",
+           "gr_unet_train_step", "gr_destroy_unet", "gr_unet_last_error")
 
 
 class GrParams(C.Structure):
@@ -46,6 +48,10 @@ class GrGridDesc(C.Structure):
 class GrSolveOpts(C.Structure):
     _fields_ = [("nu1", C.c_int), ("nu2", C.c_int), ("max_cycles", C.c_int), ("rtol", C.c_double),
                 ("precision", C.c_int), ("guess", C.c_int), ("field_mask", C.c_uint)]
+
+
+class GrUnetDesc(C.Structure):
+    _fields_ = [("in_ch", C.c_int), ("out_ch", C.c_int), ("c", C.c_int * 4)]
 
 
 class GrSolveReport(C.Structure):
@@ -96,6 +102,17 @@ def load_library(path: str = LIB_PATH):
         "gr_batch_solve": [vp, C.POINTER(GrSolveOpts), C.POINTER(C.c_int), C.POINTER(C.c_double),
                            C.POINTER(C.c_double)],
         "gr_destroy_batch": [vp],
+        "gr_unet_create": [C.POINTER(GrUnetDesc), C.c_int, C.POINTER(vp)],
+        "gr_unet_workspace_bytes": [vp, C.POINTER(C.c_size_t)],
+        "gr_unet_param_count": [vp, C.POINTER(C.c_int64)],
+        "gr_unet_bind": [vp, vp, C.c_size_t, vp],
+        "gr_unet_init": [vp, C.c_uint64],
+        "gr_unet_set_params": [vp, vp],
+        "gr_unet_get_params": [vp, vp],
+        "gr_unet_forward": [vp, C.c_int, vp, vp],
+        "gr_unet_loss_grad": [vp, C.c_int, vp, vp, vp, C.POINTER(C.c_double)],
+        "gr_unet_train_step": [vp, C.c_int, vp, vp, C.c_float, C.POINTER(C.c_double)],
+        "gr_destroy_unet": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -105,6 +122,8 @@ def load_library(path: str = LIB_PATH):
     lib.gr_last_error.restype = C.c_char_p
     lib.gr_batch_last_error.argtypes = []
     lib.gr_batch_last_error.restype = C.c_char_p
+    lib.gr_unet_last_error.argtypes = []
+    lib.gr_unet_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -362,3 +381,93 @@ class Batch:
         st, cyc, rel, sec = batch_solve(self.handle, len(self.ns), default_opts(**kw), allow)
         self._keep.clear()
         return dict(status=st, cycles=cyc, rel_res=rel, item_seconds=sec)
+
+
+# ---- learned initial guess network ----
+
+def unet_last_error() -> str:
+    return load_library().gr_unet_last_error().decode()
+
+
+def _ucheck(code: int):
+    if code != OK:
+        raise GrError(code, unet_last_error())
+    return code
+
+
+class UNet:
+    """The U-Net of the learned guess (see gr.h); device memory from torch."""
+
+    def __init__(self, in_ch: int, out_ch: int, channels=(16, 32, 64, 64), max_n: int = 64, device="cuda",
+                 stream=None):
+        import torch
+
+        self.torch = torch
+        self.in_ch, self.out_ch, self.channels = in_ch, out_ch, tuple(channels)
+        self.device = torch.device(device)
+        lib = load_library()
+        h = C.c_void_p()
+        _ucheck(lib.gr_unet_create(C.byref(GrUnetDesc(in_ch, out_ch, (C.c_int * 4)(*channels))), max_n, C.byref(h)))
+        self.handle = h.value
+        nbytes, cnt = C.c_size_t(), C.c_int64()
+        _ucheck(lib.gr_unet_workspace_bytes(self.handle, C.byref(nbytes)))
+        _ucheck(lib.gr_unet_param_count(self.handle, C.byref(cnt)))
+        self.nparam = cnt.value
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _ucheck(lib.gr_unet_bind(self.handle, self.workspace.data_ptr(), nbytes.value, self.stream.cuda_stream))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().gr_destroy_unet(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _f32(self, x):
+        t = self.torch
+        x = x if isinstance(x, t.Tensor) else t.as_tensor(x)
+        return x.to(device=self.device, dtype=t.float32).contiguous()
+
+    def init(self, seed: int):
+        _ucheck(load_library().gr_unet_init(self.handle, seed))
+
+    def get_params(self):
+        out = self.torch.empty(self.nparam, dtype=self.torch.float32, device=self.device)
+        _ucheck(load_library().gr_unet_get_params(self.handle, out.data_ptr()))
+        self.stream.synchronize()
+        return out
+
+    def set_params(self, p):
+        p = self._f32(p)
+        assert p.numel() == self.nparam
+        _ucheck(load_library().gr_unet_set_params(self.handle, p.data_ptr()))
+        self.stream.synchronize()
+
+    def forward(self, x):
+        x = self._f32(x)
+        n = x.shape[-1]
+        out = self.torch.empty((self.out_ch, n, n, n), dtype=self.torch.float32, device=self.device)
+        _ucheck(load_library().gr_unet_forward(self.handle, n, x.data_ptr(), out.data_ptr()))
+        self.stream.synchronize()
+        return out
+
+    def loss_grad(self, x, t):
+        x, t = self._f32(x), self._f32(t)
+        g = self.torch.empty(self.nparam, dtype=self.torch.float32, device=self.device)
+        loss = C.c_double()
+        _ucheck(load_library().gr_unet_loss_grad(self.handle, x.shape[-1], x.data_ptr(), t.data_ptr(), g.data_ptr(),
+                                                 C.byref(loss)))
+        self.stream.synchronize()
+        return loss.value, g
+
+    def train_step(self, x, t, lr: float) -> float:
+        x, t = self._f32(x), self._f32(t)
+        loss = C.c_double()
+        _ucheck(load_library().gr_unet_train_step(self.handle, x.shape[-1], x.data_ptr(), t.data_ptr(), lr,
+                                                  C.byref(loss)))
+        return loss.value
