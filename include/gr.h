@@ -84,6 +84,12 @@ enum {
 
 #define GR_GUESS_ZERO 0     /* start every solved field from 0                 */
 #define GR_GUESS_CURRENT 1  /* start from the values held (previous step / set_field) */
+#define GR_GUESS_CHECKED 2  /* as CURRENT, but per field take the saved alternative
+                               (previous-step values saved by gr_set_guess) unless the
+                               held guess has the strictly smaller FP64 residual (a
+                               non-finite held guess never does); ties take the
+                               alternative.  Any solve of a field uses up its saved
+                               alternative. */
 
 #define GR_ALL_FIELDS 0x3FFu
 
@@ -126,6 +132,7 @@ typedef struct {
     double rel_res[10]; /* final rms(eps)/rms(f) per field                     */
     double seconds;     /* host wall time of the call                          */
     int fallback;       /* mixed precision: fields that fell back to FP64      */
+    int guess_fallback; /* GR_GUESS_CHECKED: fields that used the alternative   */
 } gr_solve_report;
 
 /* Fill *o with the defaults above. */
@@ -174,6 +181,24 @@ int gr_solve_constraints(gr_grid g, const gr_solve_opts *opts, gr_solve_report *
  * cycles[0] / rel_res[0] of the report. */
 int gr_solve_equation(gr_grid g, int kind, int field, const gr_solve_opts *opts,
                       gr_solve_report *host_report);
+
+/* Learned-guess support (the network itself is gr_unet_*).  gr_features: for each of `count` field ids (solved
+ * fields, sources, GR_AA), restrict it to multigrid level `level` (mean of
+ * the 8 children, applied level by level; level 0 = the grid itself) and write
+ * (value - offset[c]) * scale[c] as FP32 to d_dst[c][n_level^3].
+ * gr_set_guess: for each of `count` solved fields, take d_src[c][n_level^3]
+ * times scale[c], prolong it to the finest level (cell-centred trilinear,
+ * level by level) and, with add != 0, add it to the held field after saving
+ * the held values as that field's alternative guess (see GR_GUESS_CHECKED);
+ * with add == 0 it replaces the field (and clears the alternative).
+ * Both run on the grid's stream, read and write device memory only, and
+ * return GR_EINVAL for a bad level, count, field id or null pointer (nothing
+ * is launched then).  d_dst / d_src hold count * n_level^3 floats, owned by
+ * the caller. */
+int gr_features(gr_grid g, int level, int count, const int *fields, const double *offset, const double *scale,
+                float *d_dst);
+int gr_set_guess(gr_grid g, int level, int count, const int *fields, const double *scale, const float *d_src,
+                 int add);
 
 /* Low level, for step-by-step comparisons: `nsweeps` red-black Newton sweeps
  * of the finest level (even colour first) on field slot `field` with source

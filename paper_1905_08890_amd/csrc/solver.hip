@@ -69,6 +69,8 @@ struct gr_grid_s {
     double *A6[6]{};
     double *AA = nullptr;
     double *fB[3]{}; // sources of B^i (kept for the three solves)
+    double *alt[10]{}; // alternative (previous-step) guesses, saved by gr_set_guess
+    bool alt_valid[10]{};
     double *partials = nullptr;
     double *scal = nullptr;
     hipStream_t stream = nullptr;
@@ -117,6 +119,7 @@ size_t layout(gr_grid g, char *base)
     for (int c = 0; c < 6; ++c) g->A6[c] = take(fb);
     g->AA = take(fb);
     for (int c = 0; c < 3; ++c) g->fB[c] = take(fb);
+    for (int f = 0; f < 10; ++f) g->alt[f] = take(fb);
     for (int l = 0; l < g->nlev; ++l) {
         Level &L = g->lev[l];
         const size_t lb = sizeof(double) * (size_t)L.N;
@@ -461,6 +464,55 @@ int solve_field(gr_grid g, int kind, double *phi, const gr_solve_opts &o, int *c
     return solve_one(g, kind, phi, o, cycles, rel);
 }
 
+// The stopping quantity rms(eps)/rms(f) of an iterate phi (pinned here), with
+// the frozen means evaluated from it, exactly as at the start of a cycle.
+// Uses the fine source and coefficient already in place.
+int guess_residual(gr_grid g, int kind, double *phi, double *rel_out)
+{
+    hipStream_t s = g->stream;
+    const long N = g->N();
+    Level &F = g->lev[0];
+    const OpConst oc = g->oc();
+    CHK(pin_mean(g, phi, N));
+    launch_set_scalar(s, g->scal + S_FBAR, 0.0);
+    launch_set_scalar(s, g->scal + S_FSHIFT, 0.0);
+    if (kind == GR_KIND_HAMILTONIAN) {
+        launch_sum_ham_F(s, phi, F.f, F.coef, N, oc, g->partials);
+        launch_finalize(s, g->partials, 1, 1.0 / (double)N, nullptr, g->scal + S_FBAR);
+    } else if (kind == GR_KIND_CMC) {
+        CHK(reduce_mean(g, F.f, nullptr, N, g->scal + S_FMEAN));
+        launch_sum_prod(s, F.coef, phi, N, g->partials);
+        launch_finalize(s, g->partials, 1, 1.0 / (double)N, g->scal + S_FMEAN, g->scal + S_FSHIFT);
+    }
+    launch_res_norms(kind, s, phi, F.f, F.coef, F.n, F.h, oc, g->scal + S_FBAR, g->scal + S_FSHIFT, g->partials);
+    launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN);
+    LAUNCHCHK();
+    double hn[2];
+    HIPCHK(hipMemcpyAsync(hn, g->scal + S_RN, sizeof hn, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double rn = std::sqrt(hn[0]), fn = std::sqrt(hn[1]);
+    *rel_out = rn / (fn > 0.0 ? fn : 1.0);
+    return GR_OK;
+}
+
+// GR_GUESS_CHECKED: keep the held guess unless the saved alternative (the
+// previous-step field) has a smaller stopping quantity, or the held guess is
+// not finite; returns 1 when the alternative was taken.
+int choose_guess(gr_grid g, int kind, int fid, int *took_alt)
+{
+    *took_alt = 0;
+    if (!g->alt_valid[fid]) return GR_OK;
+    double r_held = 0.0, r_alt = 0.0;
+    CHK(guess_residual(g, kind, g->field[fid], &r_held));
+    CHK(guess_residual(g, kind, g->alt[fid], &r_alt));
+    if (!(r_held < r_alt)) {
+        launch_copy(g->stream, g->field[fid], g->alt[fid], g->N());
+        LAUNCHCHK();
+        *took_alt = 1;
+    }
+    return GR_OK;
+}
+
 int check_opts(const gr_solve_opts *o)
 {
     if (!o) return fail(GR_EINVAL, "null opts");
@@ -468,7 +520,8 @@ int check_opts(const gr_solve_opts *o)
         return fail(GR_EINVAL, "bad cycle options");
     if (!(o->rtol == o->rtol)) return fail(GR_EINVAL, "rtol is NaN");
     if (o->precision != GR_FP64 && o->precision != GR_MIXED) return fail(GR_EINVAL, "bad precision");
-    if (o->guess != GR_GUESS_ZERO && o->guess != GR_GUESS_CURRENT) return fail(GR_EINVAL, "bad guess mode");
+    if (o->guess != GR_GUESS_ZERO && o->guess != GR_GUESS_CURRENT && o->guess != GR_GUESS_CHECKED)
+        return fail(GR_EINVAL, "bad guess mode");
     return GR_OK;
 }
 
@@ -685,6 +738,12 @@ int gr_solve_constraints(gr_grid g, const gr_solve_opts *opts, gr_solve_report *
 
     auto solve = [&](int fid, int kind) -> int {
         if (!(mask & (1u << fid))) return GR_OK;
+        if (opts->guess == GR_GUESS_CHECKED) {
+            int took = 0;
+            CHK(choose_guess(g, kind, fid, &took));
+            R.guess_fallback += took;
+        }
+        g->alt_valid[fid] = false; // a saved alternative serves one solve only
         int fb = 0;
         int st = solve_field(g, kind, g->field[fid], *opts, &R.cycles[fid], &R.rel_res[fid], &fb);
         R.fallback += fb;
@@ -735,6 +794,64 @@ int gr_solve_constraints(gr_grid g, const gr_solve_opts *opts, gr_solve_report *
     if (rep) *rep = R;
     if (first_bad != GR_OK && g_err.empty()) fail(first_bad, "a field did not converge");
     return first_bad;
+}
+
+int gr_features(gr_grid g, int level, int count, const int *fields, const double *offset, const double *scale,
+                float *d_dst)
+{
+    CHK(check_bound(g));
+    if (level < 0 || level >= g->nlev || count < 1 || count > 32 || !fields || !offset || !scale || !d_dst)
+        return fail(GR_EINVAL, "bad argument");
+    for (int c = 0; c < count; ++c)
+        if (!slot_ptr(g, fields[c]) || fields[c] == GR_RHS || fields[c] == GR_COEF)
+            return fail(GR_EINVAL, "field %d", fields[c]);
+    hipStream_t s = g->stream;
+    const long M = g->lev[level].N;
+    for (int c = 0; c < count; ++c) {
+        const double *src = slot_ptr(g, fields[c]);
+        for (int l = 1; l <= level; ++l) {
+            launch_restrict(s, src, g->lev[l - 1].n, g->lev[l].tmp);
+            src = g->lev[l].tmp;
+        }
+        launch_affine_to_f32(s, d_dst + c * M, src, M, offset[c], scale[c]);
+    }
+    LAUNCHCHK();
+    return GR_OK;
+}
+
+int gr_set_guess(gr_grid g, int level, int count, const int *fields, const double *scale, const float *d_src, int add)
+{
+    CHK(check_bound(g));
+    if (level < 0 || level >= g->nlev || count < 1 || count > 10 || !fields || !scale || !d_src)
+        return fail(GR_EINVAL, "bad argument");
+    for (int c = 0; c < count; ++c)
+        if (fields[c] < 0 || fields[c] > 9) return fail(GR_EINVAL, "field %d is not a solved field", fields[c]);
+    hipStream_t s = g->stream;
+    const long N = g->N();
+    for (int c = 0; c < count; ++c) {
+        const int f = fields[c];
+        const long M = g->lev[level].N;
+        // prediction (times scale) into level `level`, then prolonged to the finest level
+        double *cur = level == 0 ? g->lev[0].tmp : g->lev[level].tmp;
+        launch_f32_scaled_to_f64(s, cur, d_src + c * M, M, scale[c]);
+        for (int l = level; l >= 1; --l) {
+            Level &C = g->lev[l], &F = g->lev[l - 1];
+            launch_fill(s, C.phi0, C.N, 0.0);
+            launch_fill(s, F.tmp, F.N, 0.0);
+            launch_prolong_correct(s, F.tmp, F.n, cur, C.phi0);
+            cur = F.tmp;
+        }
+        if (add) {
+            launch_copy(s, g->alt[f], g->field[f], N);
+            g->alt_valid[f] = true;
+            launch_axpy(s, g->field[f], cur, N);
+        } else {
+            launch_copy(s, g->field[f], cur, N);
+            g->alt_valid[f] = false;
+        }
+    }
+    LAUNCHCHK();
+    return GR_OK;
 }
 
 int gr_debug_sweep(gr_grid g, int kind, int field, double Fbar, double fshift, int nsweeps)

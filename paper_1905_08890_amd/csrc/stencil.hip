@@ -724,6 +724,24 @@ __global__ void k_f64_to_f32(float *__restrict__ d, const double *__restrict__ s
     if (p < N) d[p] = (float)s[p];
 }
 
+__global__ void k_affine_to_f32(float *__restrict__ d, const double *__restrict__ s, long N, double off, double sc)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < N) d[p] = (float)((s[p] - off) * sc);
+}
+
+__global__ void k_f32_scaled_to_f64(double *__restrict__ d, const float *__restrict__ s, long N, double sc)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < N) d[p] = (double)s[p] * sc;
+}
+
+__global__ void k_axpy(double *__restrict__ y, const double *__restrict__ x, long N)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < N) y[p] += x[p];
+}
+
 __global__ void k_set_scalar(double *slot, double v)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *slot = v;
@@ -1000,5 +1018,20 @@ void launch_convert_f64_to_f32(hipStream_t s, float *dst, const double *src, lon
 }
 
 void launch_set_scalar(hipStream_t s, double *slot, double v) { k_set_scalar<<<1, 64, 0, s>>>(slot, v); }
+
+void launch_affine_to_f32(hipStream_t s, float *dst, const double *src, long N, double off, double scale)
+{
+    if (N > 0) k_affine_to_f32<<<blocks_for(N), TPB, 0, s>>>(dst, src, N, off, scale);
+}
+
+void launch_f32_scaled_to_f64(hipStream_t s, double *dst, const float *src, long N, double scale)
+{
+    if (N > 0) k_f32_scaled_to_f64<<<blocks_for(N), TPB, 0, s>>>(dst, src, N, scale);
+}
+
+void launch_axpy(hipStream_t s, double *y, const double *x, long N)
+{
+    if (N > 0) k_axpy<<<blocks_for(N), TPB, 0, s>>>(y, x, N);
+}
 
 } // namespace grmg

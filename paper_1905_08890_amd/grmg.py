@@ -21,7 +21,7 @@ POISSON, HAMILTONIAN, CMC = 0, 1, 2
  RHS, COEF) = range(24)
 F64, F32 = 0, 1
 FP64, MIXED = 0, 1
-GUESS_ZERO, GUESS_CURRENT = 0, 1
+GUESS_ZERO, GUESS_CURRENT, GUESS_CHECKED = 0, 1, 2
 ALL_FIELDS = 0x3FF
 SOLVED = ("Vx", "Vy", "Vz", "U", "Psi", "xi", "Bx", "By", "Bz", "b")
 FIELD_IDS = {name: i for i, name in enumerate(SOLVED)}
@@ -30,7 +30,7 @@ FIELD_IDS.update(dict(s0=S0, sx=SX, sy=SY, sz=SZ, sm=SM, AA=AA, Phi=PHI, alpha=A
 
 EXPORTS = ("gr_default_opts", "gr_create_grid", "gr_workspace_bytes", "gr_bind", "gr_deposit_sources",
            "gr_set_field", "gr_get_field", "gr_solve_constraints", "gr_solve_equation", "gr_debug_sweep",
-           "gr_debug_residual", "gr_destroy_grid", "gr_last_error", "gr_create_batch", "gr_batch_workspace_bytes",
+           "gr_debug_residual", "gr_destroy_grid", "gr_last_error", "gr_features", "gr_set_guess", "gr_create_batch", "gr_batch_workspace_bytes",
            "gr_batch_bind", "gr_batch_set_field", "gr_batch_get_field", "gr_batch_solve", "gr_destroy_batch",
            "gr_batch_last_error", "gr_unet_create", "gr_unet_workspace_bytes", "gr_unet_param_count", "gr_unet_bind",
            "gr_unet_init", "gr_unet_set_params", "gr_unet_get_params", "gr_unet_forward", "gr_unet_loss_grad",
@@ -56,11 +56,11 @@ class GrUnetDesc(C.Structure):
 
 class GrSolveReport(C.Structure):
     _fields_ = [("status", C.c_int), ("cycles", C.c_int * 10), ("rel_res", C.c_double * 10),
-                ("seconds", C.c_double), ("fallback", C.c_int)]
+                ("seconds", C.c_double), ("fallback", C.c_int), ("guess_fallback", C.c_int)]
 
     def as_dict(self):
         return dict(status=self.status, cycles=list(self.cycles), rel_res=list(self.rel_res),
-                    seconds=self.seconds, fallback=self.fallback)
+                    seconds=self.seconds, fallback=self.fallback, guess_fallback=self.guess_fallback)
 
 
 class GrError(RuntimeError):
@@ -94,6 +94,8 @@ def load_library(path: str = LIB_PATH):
         "gr_debug_sweep": [vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int],
         "gr_debug_residual": [vp, C.c_int, C.c_int, C.c_double, C.c_double, vp],
         "gr_destroy_grid": [vp],
+        "gr_features": [vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double), vp],
+        "gr_set_guess": [vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), vp, C.c_int],
         "gr_create_batch": [C.POINTER(GrGridDesc), C.c_int, C.POINTER(GrParams), C.POINTER(vp)],
         "gr_batch_workspace_bytes": [vp, C.POINTER(C.c_size_t)],
         "gr_batch_bind": [vp, vp, C.c_size_t, vp],
@@ -161,7 +163,7 @@ def default_opts(**kw) -> GrSolveOpts:
         if k == "precision" and isinstance(v, str):
             v = {"fp64": FP64, "mixed": MIXED}[v]
         if k == "guess" and isinstance(v, str):
-            v = {"zero": GUESS_ZERO, "current": GUESS_CURRENT}[v]
+            v = {"zero": GUESS_ZERO, "current": GUESS_CURRENT, "checked": GUESS_CHECKED}[v]
         setattr(o, k, v)
     return o
 
@@ -213,6 +215,18 @@ def debug_sweep(g: int, kind: int, field: int, Fbar: float, fshift: float, nswee
 
 def debug_residual(g: int, kind: int, field: int, Fbar: float, fshift: float, out) -> None:
     _check(load_library().gr_debug_residual(g, kind, field, Fbar, fshift, _ptr(out)))
+
+
+def features(g: int, level: int, fields, offset, scale, out) -> None:
+    k = len(fields)
+    _check(load_library().gr_features(g, level, k, (C.c_int * k)(*fields), (C.c_double * k)(*offset),
+                                      (C.c_double * k)(*scale), _ptr(out)))
+
+
+def set_guess(g: int, level: int, fields, scale, src, add: int) -> None:
+    k = len(fields)
+    _check(load_library().gr_set_guess(g, level, k, (C.c_int * k)(*fields), (C.c_double * k)(*scale), _ptr(src),
+                                       add))
 
 
 def destroy_grid(g: int) -> None:

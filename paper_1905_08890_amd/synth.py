@@ -111,3 +111,36 @@ def batch_item(seed: int, sides=BATCH_SIDES, sigma_range=(0.05, 1.0)):
     rms = np.sqrt(np.mean(mom[0] ** 2 + mom[1] ** 2 + mom[2] ** 2))
     mom = [np.ascontiguousarray(m * (1e-3 / rms)) for m in mom]
     return n, (1.0 + delta, mom[0], mom[1], mom[2], np.zeros((n, n, n)))
+
+
+def zeldovich_trajectory(n: int, seed: int, rms_cells_list, lam: float = 1.0):
+    """The same Zel'dovich displacement pattern (seed) at a sequence of rms
+    amplitudes: a growing trajectory standing in for consecutive time steps.
+    Yields (pos, u, mass) per amplitude; the FFTs are done once."""
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((n, n, n))
+    W = np.fft.rfftn(w)
+    kz, ky, kx = _kgrid(n)
+    k = np.sqrt(kx * kx + ky * ky + kz * kz)
+    k[0, 0, 0] = 1.0
+    phik = W * k ** (-5.0 / 2.0)
+    phik[0, 0, 0] = 0.0
+    nyq = n // 2
+    phik[nyq, :, :] = 0.0
+    phik[:, nyq, :] = 0.0
+    phik[:, :, -1] = 0.0
+    disp = [np.fft.irfftn(-1j * kk * phik, s=(n, n, n), axes=(0, 1, 2)).ravel() for kk in (kx, ky, kz)]
+    rms = np.sqrt(np.mean(disp[0] ** 2 + disp[1] ** 2 + disp[2] ** 2))
+    h = 1.0 / n
+    cz, cy, cx = np.meshgrid(*(np.arange(n) + 0.5,) * 3, indexing="ij")
+    centres = [c.ravel() * h for c in (cx, cy, cz)]
+    for r in rms_cells_list:
+        scale = (r / n) / rms
+        pos = np.empty((n ** 3, 3))
+        u = np.empty((n ** 3, 3))
+        for c in range(3):
+            d = disp[c] * scale
+            pos[:, c] = np.mod(centres[c] + d, 1.0)
+            u[:, c] = lam * d
+        pos[pos >= 1.0] = 0.0
+        yield pos, u, 1.0 / n ** 3

@@ -1,0 +1,164 @@
+"""GPU checks of the learned-guess plumbing: level features (restriction),
+guess prolongation, and the residual-checked choice between a supplied guess
+and the previous-step fields.
+
+Restriction and prolongation are compared with the oracle's (FP32 output:
+relative 2e-6 of the largest value; FP64 prolongation: 1e-13).  The checked
+choice is compared with the plain previous-step solve, which it must
+reproduce (up to the rounding of one more mean removal) whenever it falls
+back.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1905_08890_amd import grmg, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+PRM = dict(a=1.0, omega_m=synth.OMEGA_M, c_tilde=synth.C_TILDE)
+
+
+def maxrel(x, ref):
+    return float(np.abs(x - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+@pytest.mark.parametrize("n,level", [(32, 0), (32, 1), (32, 2), (48, 1), (64, 3)])
+def test_features_match_oracle_restriction(n, level):
+    print(f"[gpu] features n={n} level={level}", flush=True)
+    g = grmg.Grid(n, **PRM)
+    rng = np.random.default_rng(n + level)
+    fields = [grmg.VX, grmg.PSI, grmg.S0, grmg.AA]
+    vals = [rng.standard_normal((n, n, n)) * (1 + i) + i for i in range(len(fields))]
+    for f, v in zip(fields, vals):
+        g.set_field(f, v)
+    off = [0.5, -1.0, 2.0, 0.0]
+    sc = [2.0, 0.25, -1.0, 3.0]
+    m = n >> level
+    out = torch.empty((len(fields), m, m, m), dtype=torch.float32, device="cuda")
+    grmg.features(g.handle, level, fields, off, sc, out)
+    got = out.cpu().numpy().astype(np.float64)
+    for c, v in enumerate(vals):
+        r = v
+        for _ in range(level):
+            r = O.restrict(r)
+        ref = (r - off[c]) * sc[c]
+        assert maxrel(got[c], ref) < 2e-6, c
+
+
+@pytest.mark.parametrize("n,level", [(32, 0), (32, 1), (32, 2), (48, 1), (64, 3)])
+@pytest.mark.parametrize("add", [0, 1])
+def test_set_guess_matches_oracle_prolongation(n, level, add):
+    print(f"[gpu] set_guess n={n} level={level} add={add}", flush=True)
+    g = grmg.Grid(n, **PRM)
+    rng = np.random.default_rng(7 * n + level)
+    m = n >> level
+    fields = [grmg.VY, grmg.XI, grmg.BB]
+    base = [rng.standard_normal((n, n, n)) for _ in fields]
+    for f, b in zip(fields, base):
+        g.set_field(f, b)
+    src = rng.standard_normal((len(fields), m, m, m)).astype(np.float32)
+    sc = [1.5, -0.5, 4.0]
+    grmg.set_guess(g.handle, level, fields, sc, torch.tensor(src, device="cuda"), add)
+    for c, f in enumerate(fields):
+        e = src[c].astype(np.float64) * sc[c]
+        for _ in range(level):
+            e = O.prolong_add(e, np.zeros((2 * e.shape[0],) * 3))
+        ref = e + (base[c] if add else 0.0)
+        got = g.get_field(f).cpu().numpy()
+        assert maxrel(got, ref) < 1e-13, f
+
+
+def test_features_and_set_guess_reject_bad_arguments():
+    g = grmg.Grid(16, **PRM)
+    out = torch.empty(16 ** 3, dtype=torch.float32, device="cuda")
+    lib = grmg.load_library()
+    for level in (-1, 9):
+        with pytest.raises(grmg.GrError):
+            grmg.features(g.handle, level, [0], [0.0], [1.0], out)
+        with pytest.raises(grmg.GrError):
+            grmg.set_guess(g.handle, level, [0], [1.0], out, 1)
+    for bad in ([grmg.FIELD_IDS["rhs"]], [99]):
+        with pytest.raises(grmg.GrError):
+            grmg.features(g.handle, 0, bad, [0.0], [1.0], out)
+    with pytest.raises(grmg.GrError):
+        grmg.set_guess(g.handle, 0, [grmg.S0], [1.0], out, 1)
+    assert lib.gr_features(g.handle, 0, 1, None, None, None, None) == grmg.EINVAL
+
+
+# ------------------------------------------------ checked guess vs fallback
+
+N = 32
+
+
+def _state(g):
+    return [g.get_field(f).clone() for f in range(10)]
+
+
+def _load(g, fields):
+    for f, v in enumerate(fields):
+        g.set_field(f, v)
+
+
+@pytest.fixture(scope="module")
+def trajectory():
+    """Step A solved from zero, step B's sources, and step B solved from A."""
+    print("[gpu] checked-guess trajectory n=32", flush=True)
+    g = grmg.Grid(N, **PRM)
+    steps = list(synth.zeldovich_trajectory(N, 21, [0.8, 1.0]))
+    g.deposit_sources(*steps[0])
+    rep = g.solve_constraints(rtol=1e-10)
+    assert rep["status"] == grmg.OK
+    prev = _state(g)
+    g.deposit_sources(*steps[1])
+    rep_cur = g.solve_constraints(rtol=1e-10, guess="current")
+    assert rep_cur["status"] == grmg.OK
+    return g, prev, rep_cur, _state(g)
+
+
+def _checked_solve(g, prev, pred):
+    _load(g, prev)
+    grmg.set_guess(g.handle, 1, list(range(10)), [1.0] * 10, pred, 1)
+    return g.solve_constraints(rtol=1e-10, guess="checked")
+
+
+@pytest.mark.parametrize("pred", ["zero", "nan", "garbage"])
+def test_checked_guess_falls_back_to_previous_step(trajectory, pred):
+    g, prev, rep_cur, cur = trajectory
+    m = N // 2
+    p = torch.zeros((10, m, m, m), dtype=torch.float32, device="cuda")
+    if pred == "nan":
+        p[:, 3, 4, 5] = float("nan")
+    elif pred == "garbage":
+        p.normal_(generator=torch.Generator(device="cuda").manual_seed(3)).mul_(10.0)
+    rep = _checked_solve(g, prev, p)
+    assert rep["status"] == grmg.OK
+    assert rep["guess_fallback"] == 10
+    assert rep["cycles"] == rep_cur["cycles"]
+    for f in range(10):
+        # the residual check pins the mean of the alternative once more: rounding only
+        assert maxrel(g.get_field(f).cpu().numpy(), cur[f].cpu().numpy()) < 1e-12, f
+
+
+def test_checked_guess_keeps_a_better_prediction(trajectory):
+    """The increment itself (restricted to level 1) as the prediction: kept for
+    most fields, and the solve needs fewer cycles than from the previous step."""
+    g, prev, rep_cur, cur = trajectory
+    m = N // 2
+    fa = torch.empty((10, m, m, m), dtype=torch.float32, device="cuda")
+    fb = torch.empty_like(fa)
+    _load(g, cur)
+    grmg.features(g.handle, 1, list(range(10)), [0.0] * 10, [1.0] * 10, fb)
+    _load(g, prev)
+    grmg.features(g.handle, 1, list(range(10)), [0.0] * 10, [1.0] * 10, fa)
+    rep = _checked_solve(g, prev, (fb - fa).contiguous())
+    print("cycles checked", rep["cycles"], "previous-step", rep_cur["cycles"], "fallbacks", rep["guess_fallback"])
+    assert rep["status"] == grmg.OK
+    assert rep["guess_fallback"] <= 2
+    assert sum(rep["cycles"]) < sum(rep_cur["cycles"])
+    assert max(rep["rel_res"]) <= 1e-10
+    # a second solve without a new prediction has no alternative left: plain CURRENT
+    rep2 = g.solve_constraints(rtol=1e-10, guess="checked")
+    assert rep2["guess_fallback"] == 0
