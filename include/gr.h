@@ -133,6 +133,8 @@ typedef struct {
     double seconds;     /* host wall time of the call                          */
     int fallback;       /* mixed precision: fields that fell back to FP64      */
     int guess_fallback; /* GR_GUESS_CHECKED: fields that used the alternative   */
+    double guess_rel[10]; /* GR_GUESS_CHECKED: stopping quantity of the held guess  */
+    double alt_rel[10];   /* ... and of the saved alternative (both 0 when none)    */
 } gr_solve_report;
 
 /* Fill *o with the defaults above. */
@@ -182,23 +184,32 @@ int gr_solve_constraints(gr_grid g, const gr_solve_opts *opts, gr_solve_report *
 int gr_solve_equation(gr_grid g, int kind, int field, const gr_solve_opts *opts,
                       gr_solve_report *host_report);
 
-/* Learned-guess support (the network itself is gr_unet_*).  gr_features: for each of `count` field ids (solved
- * fields, sources, GR_AA), restrict it to multigrid level `level` (mean of
- * the 8 children, applied level by level; level 0 = the grid itself) and write
- * (value - offset[c]) * scale[c] as FP32 to d_dst[c][n_level^3].
+/* Learned-guess support (the network itself is gr_unet_*).  gr_features: for
+ * each of `count` field ids (solved fields, sources, GR_AA), restrict it to
+ * multigrid level `level` (mean of the 8 children, applied level by level;
+ * level 0 = the grid itself) and write (value - offset[c]) * scale[c] as FP32
+ * to d_dst[c][n_level^3]; with GR_FEAT_ACCUMULATE in flags the value is added
+ * to what d_dst holds (e.g. a snapshot taken with scale -1 before a deposit
+ * gives the change of a source).
  * gr_set_guess: for each of `count` solved fields, take d_src[c][n_level^3]
- * times scale[c], prolong it to the finest level (cell-centred trilinear,
- * level by level) and, with add != 0, add it to the held field after saving
- * the held values as that field's alternative guess (see GR_GUESS_CHECKED);
- * with add == 0 it replaces the field (and clears the alternative).
+ * times scale[c] and bring it to the finest level, level by level, with the
+ * multigrid prolongation (cell-centred trilinear) or, with GR_SET_CUBIC in
+ * flags, with 4-point Lagrange cubic interpolation per dimension (its
+ * discrete Laplacian shows far smaller interpolation kinks).  With GR_SET_ADD it
+ * is added to the held field after the held values are saved as that field's
+ * alternative guess (see GR_GUESS_CHECKED); without, it replaces the field
+ * (and clears the alternative).
  * Both run on the grid's stream, read and write device memory only, and
- * return GR_EINVAL for a bad level, count, field id or null pointer (nothing
- * is launched then).  d_dst / d_src hold count * n_level^3 floats, owned by
- * the caller. */
+ * return GR_EINVAL for a bad level, count, field id, flag or null pointer
+ * (nothing is launched then).  d_dst / d_src hold count * n_level^3 floats,
+ * owned by the caller. */
+#define GR_SET_ADD 1
+#define GR_SET_CUBIC 2
+#define GR_FEAT_ACCUMULATE 1
 int gr_features(gr_grid g, int level, int count, const int *fields, const double *offset, const double *scale,
-                float *d_dst);
+                float *d_dst, int flags);
 int gr_set_guess(gr_grid g, int level, int count, const int *fields, const double *scale, const float *d_src,
-                 int add);
+                 int flags);
 
 /* Low level, for step-by-step comparisons: `nsweeps` red-black Newton sweeps
  * of the finest level (even colour first) on field slot `field` with source

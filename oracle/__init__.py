@@ -59,6 +59,7 @@ def lib():
                                       C.c_double, P, P, P, P]
         _lib.orc_restrict.argtypes = [C.c_int, P, P]
         _lib.orc_prolong_add.argtypes = [C.c_int, P, P]
+        _lib.orc_interp_cubic.argtypes = [C.c_int, P, P]
         _lib.orc_cic_deposit.argtypes = [C.c_int, C.POINTER(_Params), C.c_long, P, P, C.c_double, P,
                                          P, P, P, P, P]
         _lib.orc_build_Aij.argtypes = [C.c_int, P, P, P, P, P, P]
@@ -140,6 +141,16 @@ def prolong_add(e, fine):
     fine = _f64(fine).copy()
     lib().orc_prolong_add(e.shape[0], _p(e), _p(fine))
     return fine
+
+
+def interp_cubic(coarse):
+    """Cubic (Lagrange, 4 points per dimension) interpolation of a coarse m^3
+    field to (2m)^3 cell centres (periodic)."""
+    coarse = _f64(coarse)
+    m = coarse.shape[0]
+    out = np.empty((2 * m,) * 3)
+    lib().orc_interp_cubic(m, _p(coarse), _p(out))
+    return out
 
 
 def cic_deposit(n, pos, u, mass, psi=None, prm=None):

@@ -237,6 +237,52 @@ static void prolong_add(const double *e, int m, double *fine)
             }
 }
 
+/* Cubic interpolation of a coarse m^3 field to the (2m)^3 cell-centred grid,
+ * used only to spread a coarse-level initial guess (it is not the multigrid
+ * prolongation).  Per dimension, a fine centre lies a quarter coarse cell
+ * from the nearest coarse centre; the value there is the Lagrange cubic
+ * through the four nearest coarse centres (periodic), and the 3-D value the
+ * tensor product of the three 1-D rules, summed directly over 64 points. */
+static void cubic_weights(int fine_index, int *first, double w[4])
+{
+    /* nodes at coarse centres first .. first+3, evaluation point t in node units */
+    int I = fine_index / 2;
+    double t;
+    if (fine_index & 1) {
+        *first = I - 1;
+        t = 1.25; /* I + 1/4 */
+    } else {
+        *first = I - 2;
+        t = 1.75; /* I - 1/4 */
+    }
+    for (int j = 0; j < 4; ++j) {
+        double v = 1.0;
+        for (int k = 0; k < 4; ++k)
+            if (k != j) v *= (t - k) / (double)(j - k);
+        w[j] = v;
+    }
+}
+
+void orc_interp_cubic(int m, const double *coarse, double *fine)
+{
+    int n = 2 * m;
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                int fi, fj, fk;
+                double wi[4], wj[4], wk[4];
+                cubic_weights(i, &fi, wi);
+                cubic_weights(j, &fj, wj);
+                cubic_weights(k, &fk, wk);
+                double v = 0.0;
+                for (int c = 0; c < 4; ++c)
+                    for (int b = 0; b < 4; ++b)
+                        for (int a = 0; a < 4; ++a)
+                            v += wi[a] * wj[b] * wk[c] * coarse[at(m, fi + a, fj + b, fk + c)];
+                fine[at(n, i, j, k)] = v;
+            }
+}
+
 /* --------------------------------------------------------------- multigrid */
 
 #define ORC_MAXLEV 24

@@ -128,9 +128,10 @@ void launch_sub_scalar(hipStream_t s, double *x, long N, const double *scal);
 void launch_convert_f32_to_f64(hipStream_t s, double *dst, const float *src, long N);
 void launch_convert_f64_to_f32(hipStream_t s, float *dst, const double *src, long N);
 void launch_set_scalar(hipStream_t s, double *slot, double v);
-void launch_affine_to_f32(hipStream_t s, float *dst, const double *src, long N, double off, double scale);
+void launch_affine_to_f32(hipStream_t s, float *dst, const double *src, long N, double off, double scale, bool acc);
 void launch_f32_scaled_to_f64(hipStream_t s, double *dst, const float *src, long N, double scale);
 void launch_axpy(hipStream_t s, double *y, const double *x, long N);
+void launch_cubic_pass(hipStream_t s, const double *in, int nx, int ny, int nz, int dim, double *out);
 
 // ---- sources.hip launchers ----
 void launch_cic_deposit(hipStream_t s, int n, double a, double c_tilde, const double *pos, const double *u,

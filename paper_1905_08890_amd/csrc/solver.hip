@@ -71,6 +71,7 @@ struct gr_grid_s {
     double *fB[3]{}; // sources of B^i (kept for the three solves)
     double *alt[10]{}; // alternative (previous-step) guesses, saved by gr_set_guess
     bool alt_valid[10]{};
+    double *gtmp = nullptr; // 3/4 of a fine array: cubic guess interpolation passes
     double *partials = nullptr;
     double *scal = nullptr;
     hipStream_t stream = nullptr;
@@ -120,6 +121,7 @@ size_t layout(gr_grid g, char *base)
     g->AA = take(fb);
     for (int c = 0; c < 3; ++c) g->fB[c] = take(fb);
     for (int f = 0; f < 10; ++f) g->alt[f] = take(fb);
+    g->gtmp = take(3 * fb / 4);
     for (int l = 0; l < g->nlev; ++l) {
         Level &L = g->lev[l];
         const size_t lb = sizeof(double) * (size_t)L.N;
@@ -498,13 +500,15 @@ int guess_residual(gr_grid g, int kind, double *phi, double *rel_out)
 // GR_GUESS_CHECKED: keep the held guess unless the saved alternative (the
 // previous-step field) has a smaller stopping quantity, or the held guess is
 // not finite; returns 1 when the alternative was taken.
-int choose_guess(gr_grid g, int kind, int fid, int *took_alt)
+int choose_guess(gr_grid g, int kind, int fid, int *took_alt, double *rel_held, double *rel_alt)
 {
     *took_alt = 0;
     if (!g->alt_valid[fid]) return GR_OK;
     double r_held = 0.0, r_alt = 0.0;
     CHK(guess_residual(g, kind, g->field[fid], &r_held));
     CHK(guess_residual(g, kind, g->alt[fid], &r_alt));
+    *rel_held = r_held;
+    *rel_alt = r_alt;
     if (!(r_held < r_alt)) {
         launch_copy(g->stream, g->field[fid], g->alt[fid], g->N());
         LAUNCHCHK();
@@ -740,7 +744,7 @@ int gr_solve_constraints(gr_grid g, const gr_solve_opts *opts, gr_solve_report *
         if (!(mask & (1u << fid))) return GR_OK;
         if (opts->guess == GR_GUESS_CHECKED) {
             int took = 0;
-            CHK(choose_guess(g, kind, fid, &took));
+            CHK(choose_guess(g, kind, fid, &took, &R.guess_rel[fid], &R.alt_rel[fid]));
             R.guess_fallback += took;
         }
         g->alt_valid[fid] = false; // a saved alternative serves one solve only
@@ -797,10 +801,11 @@ int gr_solve_constraints(gr_grid g, const gr_solve_opts *opts, gr_solve_report *
 }
 
 int gr_features(gr_grid g, int level, int count, const int *fields, const double *offset, const double *scale,
-                float *d_dst)
+                float *d_dst, int flags)
 {
     CHK(check_bound(g));
-    if (level < 0 || level >= g->nlev || count < 1 || count > 32 || !fields || !offset || !scale || !d_dst)
+    if (level < 0 || level >= g->nlev || count < 1 || count > 32 || !fields || !offset || !scale || !d_dst ||
+        (flags & ~GR_FEAT_ACCUMULATE))
         return fail(GR_EINVAL, "bad argument");
     for (int c = 0; c < count; ++c)
         if (!slot_ptr(g, fields[c]) || fields[c] == GR_RHS || fields[c] == GR_COEF)
@@ -813,35 +818,45 @@ int gr_features(gr_grid g, int level, int count, const int *fields, const double
             launch_restrict(s, src, g->lev[l - 1].n, g->lev[l].tmp);
             src = g->lev[l].tmp;
         }
-        launch_affine_to_f32(s, d_dst + c * M, src, M, offset[c], scale[c]);
+        launch_affine_to_f32(s, d_dst + c * M, src, M, offset[c], scale[c], (flags & GR_FEAT_ACCUMULATE) != 0);
     }
     LAUNCHCHK();
     return GR_OK;
 }
 
-int gr_set_guess(gr_grid g, int level, int count, const int *fields, const double *scale, const float *d_src, int add)
+int gr_set_guess(gr_grid g, int level, int count, const int *fields, const double *scale, const float *d_src,
+                 int flags)
 {
     CHK(check_bound(g));
-    if (level < 0 || level >= g->nlev || count < 1 || count > 10 || !fields || !scale || !d_src)
+    if (level < 0 || level >= g->nlev || count < 1 || count > 10 || !fields || !scale || !d_src ||
+        (flags & ~(GR_SET_ADD | GR_SET_CUBIC)))
         return fail(GR_EINVAL, "bad argument");
     for (int c = 0; c < count; ++c)
         if (fields[c] < 0 || fields[c] > 9) return fail(GR_EINVAL, "field %d is not a solved field", fields[c]);
     hipStream_t s = g->stream;
     const long N = g->N();
+    const long M = g->lev[level].N;
     for (int c = 0; c < count; ++c) {
         const int f = fields[c];
-        const long M = g->lev[level].N;
-        // prediction (times scale) into level `level`, then prolonged to the finest level
-        double *cur = level == 0 ? g->lev[0].tmp : g->lev[level].tmp;
+        // prediction (times scale) into level `level`, then interpolated level by level to the finest
+        double *cur = g->lev[level].tmp;
         launch_f32_scaled_to_f64(s, cur, d_src + c * M, M, scale[c]);
         for (int l = level; l >= 1; --l) {
             Level &C = g->lev[l], &F = g->lev[l - 1];
-            launch_fill(s, C.phi0, C.N, 0.0);
-            launch_fill(s, F.tmp, F.N, 0.0);
-            launch_prolong_correct(s, F.tmp, F.n, cur, C.phi0);
+            if (flags & GR_SET_CUBIC) {
+                const int m = C.n;
+                double *X = g->gtmp, *Y = g->gtmp + N / 4; // (m,m,2m) then (m,2m,2m)
+                launch_cubic_pass(s, cur, m, m, m, 0, X);
+                launch_cubic_pass(s, X, 2 * m, m, m, 1, Y);
+                launch_cubic_pass(s, Y, 2 * m, 2 * m, m, 2, F.tmp);
+            } else {
+                launch_fill(s, C.phi0, C.N, 0.0);
+                launch_fill(s, F.tmp, F.N, 0.0);
+                launch_prolong_correct(s, F.tmp, F.n, cur, C.phi0);
+            }
             cur = F.tmp;
         }
-        if (add) {
+        if (flags & GR_SET_ADD) {
             launch_copy(s, g->alt[f], g->field[f], N);
             g->alt_valid[f] = true;
             launch_axpy(s, g->field[f], cur, N);

@@ -724,10 +724,11 @@ __global__ void k_f64_to_f32(float *__restrict__ d, const double *__restrict__ s
     if (p < N) d[p] = (float)s[p];
 }
 
-__global__ void k_affine_to_f32(float *__restrict__ d, const double *__restrict__ s, long N, double off, double sc)
+__global__ void k_affine_to_f32(float *__restrict__ d, const double *__restrict__ s, long N, double off, double sc,
+                                int acc)
 {
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < N) d[p] = (float)((s[p] - off) * sc);
+    if (p < N) d[p] = acc ? (float)((double)d[p] + (s[p] - off) * sc) : (float)((s[p] - off) * sc);
 }
 
 __global__ void k_f32_scaled_to_f64(double *__restrict__ d, const float *__restrict__ s, long N, double sc)
@@ -740,6 +741,30 @@ __global__ void k_axpy(double *__restrict__ y, const double *__restrict__ x, lon
 {
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < N) y[p] += x[p];
+}
+
+// One dimension of the cubic guess interpolation: `in` is nx x ny x nz
+// (x fastest); the output doubles dimension `dim` (0 = x, 1 = y, 2 = z).  A
+// fine centre a quarter coarse cell above coarse centre I takes the 4-point
+// Lagrange weights (-7, 105, 35, -5)/128 on I-1..I+2; a quarter below, the
+// mirror image (-5, 35, 105, -7)/128 on I-2..I+1 (periodic).
+__global__ void k_cubic_pass(const double *__restrict__ in, int nx, int ny, int nz, int dim,
+                             double *__restrict__ out)
+{
+    const int ox = dim == 0 ? 2 * nx : nx, oy = dim == 1 ? 2 * ny : ny, oz = dim == 2 ? 2 * nz : nz;
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (long)ox * oy * oz) return;
+    const int x = (int)(p % ox), y = (int)((p / ox) % oy), z = (int)(p / ((long)ox * oy));
+    const int f = dim == 0 ? x : (dim == 1 ? y : z);
+    const int nd = dim == 0 ? nx : (dim == 1 ? ny : nz);
+    const int I = f >> 1;
+    const int first = (f & 1) ? I - 1 : I - 2;
+    const double w0 = (f & 1) ? -7.0 : -5.0, w1 = (f & 1) ? 105.0 : 35.0, w2 = (f & 1) ? 35.0 : 105.0,
+                 w3 = (f & 1) ? -5.0 : -7.0;
+    const long stride = dim == 0 ? 1 : (dim == 1 ? (long)nx : (long)nx * ny);
+    const long base = dim == 0 ? ((long)z * ny + y) * nx : (dim == 1 ? (long)z * ny * nx + x : (long)y * nx + x);
+    auto at = [&](int k) { return in[base + (long)wrapi(first + k, nd) * stride]; };
+    out[p] = (w0 * at(0) + w1 * at(1) + w2 * at(2) + w3 * at(3)) * (1.0 / 128.0);
 }
 
 __global__ void k_set_scalar(double *slot, double v)
@@ -1019,14 +1044,20 @@ void launch_convert_f64_to_f32(hipStream_t s, float *dst, const double *src, lon
 
 void launch_set_scalar(hipStream_t s, double *slot, double v) { k_set_scalar<<<1, 64, 0, s>>>(slot, v); }
 
-void launch_affine_to_f32(hipStream_t s, float *dst, const double *src, long N, double off, double scale)
+void launch_affine_to_f32(hipStream_t s, float *dst, const double *src, long N, double off, double scale, bool acc)
 {
-    if (N > 0) k_affine_to_f32<<<blocks_for(N), TPB, 0, s>>>(dst, src, N, off, scale);
+    if (N > 0) k_affine_to_f32<<<blocks_for(N), TPB, 0, s>>>(dst, src, N, off, scale, acc ? 1 : 0);
 }
 
 void launch_f32_scaled_to_f64(hipStream_t s, double *dst, const float *src, long N, double scale)
 {
     if (N > 0) k_f32_scaled_to_f64<<<blocks_for(N), TPB, 0, s>>>(dst, src, N, scale);
+}
+
+void launch_cubic_pass(hipStream_t s, const double *in, int nx, int ny, int nz, int dim, double *out)
+{
+    const long M = 2L * nx * ny * nz;
+    if (M > 0) k_cubic_pass<<<blocks_for(M), TPB, 0, s>>>(in, nx, ny, nz, dim, out);
 }
 
 void launch_axpy(hipStream_t s, double *y, const double *x, long N)

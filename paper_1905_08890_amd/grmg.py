@@ -22,6 +22,8 @@ POISSON, HAMILTONIAN, CMC = 0, 1, 2
 F64, F32 = 0, 1
 FP64, MIXED = 0, 1
 GUESS_ZERO, GUESS_CURRENT, GUESS_CHECKED = 0, 1, 2
+SET_ADD, SET_CUBIC = 1, 2
+FEAT_ACCUMULATE = 1
 ALL_FIELDS = 0x3FF
 SOLVED = ("Vx", "Vy", "Vz", "U", "Psi", "xi", "Bx", "By", "Bz", "b")
 FIELD_IDS = {name: i for i, name in enumerate(SOLVED)}
@@ -56,11 +58,13 @@ class GrUnetDesc(C.Structure):
 
 class GrSolveReport(C.Structure):
     _fields_ = [("status", C.c_int), ("cycles", C.c_int * 10), ("rel_res", C.c_double * 10),
-                ("seconds", C.c_double), ("fallback", C.c_int), ("guess_fallback", C.c_int)]
+                ("seconds", C.c_double), ("fallback", C.c_int), ("guess_fallback", C.c_int),
+                ("guess_rel", C.c_double * 10), ("alt_rel", C.c_double * 10)]
 
     def as_dict(self):
         return dict(status=self.status, cycles=list(self.cycles), rel_res=list(self.rel_res),
-                    seconds=self.seconds, fallback=self.fallback, guess_fallback=self.guess_fallback)
+                    seconds=self.seconds, fallback=self.fallback, guess_fallback=self.guess_fallback,
+                    guess_rel=list(self.guess_rel), alt_rel=list(self.alt_rel))
 
 
 class GrError(RuntimeError):
@@ -217,16 +221,16 @@ def debug_residual(g: int, kind: int, field: int, Fbar: float, fshift: float, ou
     _check(load_library().gr_debug_residual(g, kind, field, Fbar, fshift, _ptr(out)))
 
 
-def features(g: int, level: int, fields, offset, scale, out) -> None:
+def features(g: int, level: int, fields, offset, scale, out, flags: int = 0) -> None:
     k = len(fields)
     _check(load_library().gr_features(g, level, k, (C.c_int * k)(*fields), (C.c_double * k)(*offset),
-                                      (C.c_double * k)(*scale), _ptr(out)))
+                                      (C.c_double * k)(*scale), _ptr(out), flags))
 
 
-def set_guess(g: int, level: int, fields, scale, src, add: int) -> None:
+def set_guess(g: int, level: int, fields, scale, src, flags: int) -> None:
     k = len(fields)
     _check(load_library().gr_set_guess(g, level, k, (C.c_int * k)(*fields), (C.c_double * k)(*scale), _ptr(src),
-                                       add))
+                                       flags))
 
 
 def destroy_grid(g: int) -> None:

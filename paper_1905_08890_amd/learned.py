@@ -1,11 +1,12 @@
 """Learned initial guess for the constraint solve.
 
 The network (gr_unet_*) sees, at multigrid level `level` (the fields
-restricted by averaging), the new matter sources and the previous step's ten
-solved fields, and predicts each field's increment.  The prediction is
-prolonged back to the finest level and added to the previous-step field;
-solving with GR_GUESS_CHECKED then keeps, per field, whichever of the learned
-and the previous-step guess has the smaller FP64 residual (the fallback).
+restricted by averaging), the change of the matter sources s0, s_i over the
+step, the new s0, and the previous step's ten solved fields, and predicts
+each field's increment.  The prediction is interpolated back to the finest
+level and added to the previous-step field; solving with GR_GUESS_CHECKED
+then keeps, per field, whichever of the learned and the previous-step guess
+has the smaller FP64 residual (the fallback).
 
 Training data come from the solver itself: for each seed, a Zel'dovich
 displacement pattern at amplitudes growing 25 % per step stands in for
@@ -25,7 +26,9 @@ from . import grmg, synth
 
 SOURCES = (grmg.S0, grmg.SX, grmg.SY, grmg.SZ)
 SOLVED = tuple(range(10))
-IN_FIELDS = SOURCES + SOLVED
+# input channels: [change of s0, s_x, s_y, s_z] + [new s0] + previous solved fields
+NOW_FIELDS = (grmg.S0,) + SOLVED
+IN_CH = len(SOURCES) + len(NOW_FIELDS)
 OUT_FIELDS = SOLVED
 CHANNELS = (16, 32, 64, 64)
 
@@ -50,31 +53,56 @@ class Normaliser:
         return dict(in_mean=self.in_mean.tolist(), in_std=self.in_std.tolist(), out_std=self.out_std.tolist())
 
 
-def raw_features(grid, level, torch):
-    """Unnormalised inputs and previous-field features at `level`: [14][m^3]."""
-    m = grid.n >> level
-    out = torch.empty((len(IN_FIELDS), m, m, m), dtype=torch.float32, device=grid.device)
-    k = len(IN_FIELDS)
-    grmg.features(grid.handle, level, IN_FIELDS, [0.0] * k, [1.0] * k, out)
-    return out
+class Features:
+    """Network inputs at one level, built by the library's restriction kernels:
+    `before_deposit` snapshots the old sources, `after_deposit` completes the
+    inputs from the new sources and the held (previous-step) fields (it may be
+    called again for the same step)."""
+
+    def __init__(self, level, m, torch, device, norm=None):
+        self.level = level
+        self.k = len(SOURCES)
+        self.snap = torch.empty((self.k, m, m, m), dtype=torch.float32, device=device)
+        self.buf = torch.empty((IN_CH, m, m, m), dtype=torch.float32, device=device)
+        if norm is None:
+            self.mean, self.inv = np.zeros(IN_CH), np.ones(IN_CH)
+        else:
+            self.mean, self.inv = norm.in_mean, 1.0 / norm.in_std
+
+    def before_deposit(self, grid):
+        k = self.k
+        grmg.features(grid.handle, self.level, SOURCES, [0.0] * k, list(-self.inv[:k]), self.snap)
+
+    def after_deposit(self, grid):
+        k = self.k
+        self.buf[:k].copy_(self.snap)
+        # adds (new - mean) * inv to -old * inv: (new - old - mean) * inv
+        grmg.features(grid.handle, self.level, SOURCES, list(self.mean[:k]), list(self.inv[:k]), self.buf,
+                      grmg.FEAT_ACCUMULATE)
+        grmg.features(grid.handle, self.level, NOW_FIELDS, list(self.mean[k:]), list(self.inv[k:]), self.buf[k:])
+        return self.buf
 
 
 def generate(n, seeds, steps, r0, level, torch, device="cuda", precision="mixed"):
-    """Solve trajectories; returns lists of raw inputs [14][m^3] and increments [10][m^3] (device FP32)."""
+    """Solve trajectories; returns lists of raw inputs [IN_CH][m^3] and increments [10][m^3] (device FP32)."""
     grid = grmg.Grid(n, a=1.0, omega_m=synth.OMEGA_M, c_tilde=synth.C_TILDE, device=device)
+    m = n >> level
+    feats = Features(level, m, torch, device)
+    new = torch.empty((len(SOLVED), m, m, m), dtype=torch.float32, device=device)
     xs, ys = [], []
     for seed in seeds:
         t0 = time.time()
         for s, (pos, u, mass) in enumerate(synth.zeldovich_trajectory(n, seed, trajectory_amplitudes(r0, steps))):
+            if s > 0:
+                feats.before_deposit(grid)
             grid.deposit_sources(pos, u, mass)
-            guess = "zero" if s == 0 else "current"
             if s > 0:
-                x = raw_features(grid, level, torch)
-            rep = grid.solve_constraints(rtol=1e-10, precision=precision, guess=guess)
+                x = feats.after_deposit(grid).clone()
+            rep = grid.solve_constraints(rtol=1e-10, precision=precision, guess="zero" if s == 0 else "current")
             if s > 0:
-                new = raw_features(grid, level, torch)[len(SOURCES):]
+                grmg.features(grid.handle, level, SOLVED, [0.0] * 10, [1.0] * 10, new)
                 xs.append(x)
-                ys.append((new - x[len(SOURCES):]).contiguous())
+                ys.append((new - x[IN_CH - len(SOLVED):]).contiguous())
         log(f"seed {seed}: {steps} steps in {time.time() - t0:.1f} s (last cycles {rep['cycles']})")
     grid.close()
     return xs, ys
@@ -106,15 +134,16 @@ def normalise(xs, ys, norm, torch):
 
 
 def train(xs, ys, m, epochs, lr, seed, torch, device="cuda", channels=CHANNELS):
-    net = grmg.UNet(len(IN_FIELDS), len(OUT_FIELDS), channels, max_n=m, device=device)
+    net = grmg.UNet(IN_CH, len(OUT_FIELDS), channels, max_n=m, device=device)
     net.init(seed)
     rng = np.random.default_rng(seed)
     losses = []
     for ep in range(epochs):
+        t0 = time.time()
         order = rng.permutation(len(xs))
         ep_loss = [net.train_step(xs[i], ys[i], lr * (0.5 ** (ep // max(1, epochs // 3)))) for i in order]
         losses.append(float(np.mean(ep_loss)))
-        log(f"epoch {ep}: loss {losses[-1]:.4e}")
+        log(f"epoch {ep}: loss {losses[-1]:.4e} ({time.time() - t0:.1f} s)")
     return net, losses
 
 
@@ -126,7 +155,8 @@ def save(path, net, norm, level, meta):
 
 
 class LearnedGuess:
-    """A trained network bound to grids of one size; `apply` sets the guesses."""
+    """A trained network bound to grids of one size.  Per step:
+    `before_deposit(grid)`, deposit the new sources, then `apply(grid)`."""
 
     def __init__(self, path, n, torch, device="cuda"):
         z = np.load(path, allow_pickle=False)
@@ -134,17 +164,32 @@ class LearnedGuess:
         self.norm = Normaliser(z["in_mean"], z["in_std"], z["out_std"])
         self.m = n >> self.level
         self.torch = torch
-        self.net = grmg.UNet(len(IN_FIELDS), len(OUT_FIELDS), tuple(int(c) for c in z["channels"]), max_n=self.m,
+        self.net = grmg.UNet(IN_CH, len(OUT_FIELDS), tuple(int(c) for c in z["channels"]), max_n=self.m,
                              device=device)
         self.net.set_params(z["params"])
-        self.buf = torch.empty((len(IN_FIELDS), self.m, self.m, self.m), dtype=torch.float32, device=device)
+        self.features = Features(self.level, self.m, torch, device, self.norm)
         self.meta = json.loads(bytes(z["meta"]).decode())
 
-    def apply(self, grid):
+    def before_deposit(self, grid):
+        self.features.before_deposit(grid)
+
+    def apply(self, grid, cubic=True):
         """Network guess for every solved field (previous-step values kept as the alternative)."""
-        grmg.features(grid.handle, self.level, IN_FIELDS, self.norm.in_mean, 1.0 / self.norm.in_std, self.buf)
-        pred = self.net.forward(self.buf)
-        grmg.set_guess(grid.handle, self.level, OUT_FIELDS, self.norm.out_std, pred, 1)
+        pred = self.net.forward(self.features.after_deposit(grid))
+        flags = grmg.SET_ADD | (grmg.SET_CUBIC if cubic else 0)
+        grmg.set_guess(grid.handle, self.level, OUT_FIELDS, self.norm.out_std, pred, flags)
+
+
+class ExactIncrement:
+    """Diagnostic stand-in for the network: the true increment (from a solve
+    of the same step) restricted to the network's level."""
+
+    def __init__(self, level, pred):
+        self.level, self.pred = level, pred
+
+    def apply(self, grid, cubic=True):
+        flags = grmg.SET_ADD | (grmg.SET_CUBIC if cubic else 0)
+        grmg.set_guess(grid.handle, self.level, OUT_FIELDS, [1.0] * len(OUT_FIELDS), self.pred, flags)
 
 
 def _timed_solve(grid, torch, **kw):
@@ -156,7 +201,8 @@ def _timed_solve(grid, torch, **kw):
     return rep
 
 
-def evaluate(guess, n, seeds, steps, r0, torch, device="cuda", rtol=1e-10, control=None):
+def evaluate(guess, n, seeds, steps, r0, torch, device="cuda", rtol=1e-10, control=None, cubic=True,
+             exact=True):
     """Per step after the first, solve the same sources to `rtol` from
       zero_fp64     : zero guess, FP64 cycles
       prev_fp64     : previous-step fields, FP64
@@ -164,9 +210,17 @@ def evaluate(guess, n, seeds, steps, r0, torch, device="cuda", rtol=1e-10, contr
       learned_mixed : previous step + network increment (checked), mixed; the
                       network's own time is included
       control_mixed : as learned_mixed with `control` (e.g. an untrained net)
-    and return per-variant lists of (ms, total cycles, guess fallbacks)."""
+      exact_mixed   : as learned_mixed with the true increment restricted to
+                      the network's level (the best a level guess can do)
+    and return per-variant rows (ms, cycles, guess fallbacks, per-field
+    stopping quantities of both guesses)."""
     grid = grmg.Grid(n, a=1.0, omega_m=synth.OMEGA_M, c_tilde=synth.C_TILDE, device=device)
-    res = {k: [] for k in ("zero_fp64", "prev_fp64", "prev_mixed", "learned_mixed", "control_mixed")}
+    names = ("zero_fp64", "prev_fp64", "prev_mixed", "learned_mixed", "control_mixed", "exact_mixed")
+    res = {k: [] for k in names}
+    level = guess.level
+    m = n >> level
+    fa = torch.empty((len(OUT_FIELDS), m, m, m), dtype=torch.float32, device=device)
+    fb = torch.empty_like(fa)
 
     def load(vals):
         for f, v in enumerate(vals):
@@ -175,6 +229,10 @@ def evaluate(guess, n, seeds, steps, r0, torch, device="cuda", rtol=1e-10, contr
     for seed in seeds:
         prev = None
         for s, (pos, u, mass) in enumerate(synth.zeldovich_trajectory(n, seed, trajectory_amplitudes(r0, steps))):
+            if prev is not None:
+                for gs in (guess, control):
+                    if gs is not None:
+                        gs.before_deposit(grid)
             grid.deposit_sources(pos, u, mass)
             if prev is None:
                 grid.solve_constraints(rtol=rtol)
@@ -186,18 +244,30 @@ def evaluate(guess, n, seeds, steps, r0, torch, device="cuda", rtol=1e-10, contr
                         ("learned_mixed", dict(precision="mixed", guess="checked"), guess)]
             if control is not None:
                 variants.append(("control_mixed", dict(precision="mixed", guess="checked"), control))
+            if exact:
+                variants.append(("exact_mixed", dict(precision="mixed", guess="checked"), "exact"))
+            sol = None
             for name, kw, net in variants:
                 load(prev)
+                if net == "exact":
+                    grmg.features(grid.handle, level, OUT_FIELDS, [0.0] * 10, [1.0] * 10, fa)
+                    load(sol)
+                    grmg.features(grid.handle, level, OUT_FIELDS, [0.0] * 10, [1.0] * 10, fb)
+                    load(prev)
+                    net = ExactIncrement(level, (fb - fa).contiguous())
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 if net is not None:
-                    net.apply(grid)
+                    net.apply(grid, cubic=cubic)
                 rep = _timed_solve(grid, torch, rtol=rtol, **kw)
                 ms = (time.perf_counter() - t0) * 1e3
                 res[name].append(dict(ms=ms, solve_ms=rep["ms"], cycles=sum(rep["cycles"]),
-                                      fallback=rep["guess_fallback"], status=rep["status"]))
+                                      field_cycles=rep["cycles"], fallback=rep["guess_fallback"],
+                                      status=rep["status"], guess_rel=rep["guess_rel"], alt_rel=rep["alt_rel"]))
+                if name == "prev_fp64":
+                    sol = [grid.get_field(f).clone() for f in SOLVED]
             # the trajectory continues from this step's own solution
-            prev = [grid.get_field(f).clone() for f in SOLVED]
+            prev = sol
     grid.close()
     return {k: v for k, v in res.items() if v}
 
@@ -205,10 +275,16 @@ def evaluate(guess, n, seeds, steps, r0, torch, device="cuda", rtol=1e-10, contr
 def summarise(res):
     out = {}
     for k, rows in res.items():
-        out[k] = dict(ms=float(np.median([r["ms"] for r in rows])),
-                      cycles=float(np.mean([r["cycles"] for r in rows])),
-                      fallback=float(np.mean([r["fallback"] for r in rows])),
-                      all_ok=all(r["status"] == grmg.OK for r in rows), samples=len(rows))
+        d = dict(ms=float(np.median([r["ms"] for r in rows])),
+                 cycles=float(np.mean([r["cycles"] for r in rows])),
+                 fallback=float(np.mean([r["fallback"] for r in rows])),
+                 all_ok=all(r["status"] == grmg.OK for r in rows), samples=len(rows))
+        if any(r["alt_rel"][0] > 0 for r in rows):
+            # per field: median of (held guess / previous step) stopping quantities
+            d["rel_ratio"] = [float(np.median([r["guess_rel"][f] / max(r["alt_rel"][f], 1e-300) for r in rows]))
+                              for f in range(10)]
+            d["field_cycles"] = [float(np.mean([r["field_cycles"][f] for r in rows])) for f in range(10)]
+        out[k] = d
     return out
 
 
@@ -228,7 +304,9 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--out", required=True)
     ap.add_argument("--eval-seeds", type=int, default=2)
-    ap.add_argument("--eval-seed0", type=int, default=9000)
+    ap.add_argument("--eval-seed0", type=int, default=2000)
+    ap.add_argument("--eval-json", default="")
+    ap.add_argument("--trilinear", action="store_true", help="spread the guess with the multigrid prolongation")
     a = ap.parse_args(argv)
     t0 = time.time()
     xs, ys = generate(a.n, range(a.seed0, a.seed0 + a.seeds), a.steps, a.r0, a.level, torch)
@@ -244,8 +322,12 @@ def main(argv=None):
         g = LearnedGuess(a.out, a.n, torch)
         ctl = LearnedGuess(a.out, a.n, torch)
         ctl.net.init(a.seed0 + 777)  # same normaliser, untrained weights
-        res = evaluate(g, a.n, range(a.eval_seed0, a.eval_seed0 + a.eval_seeds), a.steps, a.r0, torch, control=ctl)
+        res = evaluate(g, a.n, range(a.eval_seed0, a.eval_seed0 + a.eval_seeds), a.steps, a.r0, torch, control=ctl,
+                       cubic=not a.trilinear)
         print(json.dumps(summarise(res)), flush=True)
+        if a.eval_json:
+            with open(a.eval_json, "w") as fh:
+                json.dump(dict(summary=summarise(res), rows=res), fh, indent=1)
 
 
 if __name__ == "__main__":

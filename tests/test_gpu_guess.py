@@ -3,7 +3,8 @@ guess prolongation, and the residual-checked choice between a supplied guess
 and the previous-step fields.
 
 Restriction and prolongation are compared with the oracle's (FP32 output:
-relative 2e-6 of the largest value; FP64 prolongation: 1e-13).  The checked
+relative 2e-6 of the largest value; FP64 prolongation and cubic guess
+interpolation: 1e-13).  The checked
 choice is compared with the plain previous-step solve, which it must
 reproduce (up to the rounding of one more mean removal) whenever it falls
 back.
@@ -40,18 +41,27 @@ def test_features_match_oracle_restriction(n, level):
     out = torch.empty((len(fields), m, m, m), dtype=torch.float32, device="cuda")
     grmg.features(g.handle, level, fields, off, sc, out)
     got = out.cpu().numpy().astype(np.float64)
+    refs = []
     for c, v in enumerate(vals):
         r = v
         for _ in range(level):
             r = O.restrict(r)
+        refs.append(r)
         ref = (r - off[c]) * sc[c]
         assert maxrel(got[c], ref) < 2e-6, c
+    # accumulate: adds (value - offset) * scale to what the buffer holds
+    grmg.features(g.handle, level, fields, [1.0] * 4, [-0.5] * 4, out, grmg.FEAT_ACCUMULATE)
+    got = out.cpu().numpy().astype(np.float64)
+    for c, r in enumerate(refs):
+        ref = (r - off[c]) * sc[c] + (r - 1.0) * -0.5
+        assert maxrel(got[c], ref) < 4e-6, c
 
 
 @pytest.mark.parametrize("n,level", [(32, 0), (32, 1), (32, 2), (48, 1), (64, 3)])
 @pytest.mark.parametrize("add", [0, 1])
-def test_set_guess_matches_oracle_prolongation(n, level, add):
-    print(f"[gpu] set_guess n={n} level={level} add={add}", flush=True)
+@pytest.mark.parametrize("cubic", [0, 1])
+def test_set_guess_matches_oracle_prolongation(n, level, add, cubic):
+    print(f"[gpu] set_guess n={n} level={level} add={add} cubic={cubic}", flush=True)
     g = grmg.Grid(n, **PRM)
     rng = np.random.default_rng(7 * n + level)
     m = n >> level
@@ -61,11 +71,12 @@ def test_set_guess_matches_oracle_prolongation(n, level, add):
         g.set_field(f, b)
     src = rng.standard_normal((len(fields), m, m, m)).astype(np.float32)
     sc = [1.5, -0.5, 4.0]
-    grmg.set_guess(g.handle, level, fields, sc, torch.tensor(src, device="cuda"), add)
+    flags = (grmg.SET_ADD if add else 0) | (grmg.SET_CUBIC if cubic else 0)
+    grmg.set_guess(g.handle, level, fields, sc, torch.tensor(src, device="cuda"), flags)
     for c, f in enumerate(fields):
         e = src[c].astype(np.float64) * sc[c]
         for _ in range(level):
-            e = O.prolong_add(e, np.zeros((2 * e.shape[0],) * 3))
+            e = O.interp_cubic(e) if cubic else O.prolong_add(e, np.zeros((2 * e.shape[0],) * 3))
         ref = e + (base[c] if add else 0.0)
         got = g.get_field(f).cpu().numpy()
         assert maxrel(got, ref) < 1e-13, f
@@ -85,6 +96,8 @@ def test_features_and_set_guess_reject_bad_arguments():
             grmg.features(g.handle, 0, bad, [0.0], [1.0], out)
     with pytest.raises(grmg.GrError):
         grmg.set_guess(g.handle, 0, [grmg.S0], [1.0], out, 1)
+    with pytest.raises(grmg.GrError):
+        grmg.set_guess(g.handle, 0, [0], [1.0], out, 4)
     assert lib.gr_features(g.handle, 0, 1, None, None, None, None) == grmg.EINVAL
 
 

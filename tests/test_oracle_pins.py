@@ -133,6 +133,34 @@ def test_prolongation_is_separable_trilinear():
     assert maxrel(O.prolong_add(e, base) - base, ref) < 1e-14
 
 
+def test_cubic_guess_interpolation_reproduces_cubics():
+    """Where the 4-point stencils do not wrap, a cubic polynomial in (x, y, z)
+    sampled at coarse centres is reproduced exactly at the fine centres."""
+    m = 12
+    X = (np.arange(m) + 0.5) * 2.0                    # coarse centres in fine units
+    x = np.arange(2 * m) + 0.5                        # fine centres
+    poly = lambda z, y, xx: 0.3 * xx ** 3 - 2 * xx * y * z + y ** 2 - 0.7 * z ** 3 + 5.0
+    Z3, Y3, X3 = np.meshgrid(X, X, X, indexing="ij")
+    fine = O.interp_cubic(poly(Z3, Y3, X3))
+    z3, y3, x3 = np.meshgrid(x, x, x, indexing="ij")
+    ref = poly(z3, y3, x3)
+    inner = slice(4, 2 * m - 4)                        # stencils of these points stay inside
+    assert maxrel(fine[inner, inner, inner], ref[inner, inner, inner]) < 1e-13
+
+
+def test_cubic_guess_interpolation_fourth_order():
+    """A smooth periodic field: interpolation error falls 16x per halving of H."""
+    errs = []
+    for m in (8, 16, 32):
+        c = (np.arange(m) + 0.5) / m
+        f = (np.arange(2 * m) + 0.5) / (2 * m)
+        fun = lambda z, y, x: np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y) + np.sin(2 * np.pi * z)
+        coarse = fun(*np.meshgrid(c, c, c, indexing="ij"))
+        ref = fun(*np.meshgrid(f, f, f, indexing="ij"))
+        errs.append(np.abs(O.interp_cubic(coarse) - ref).max())
+    assert 14.0 < errs[0] / errs[1] < 18.0 and 14.0 < errs[1] / errs[2] < 18.0
+
+
 # ------------------------------------------------------------- Hamiltonian
 
 @pytest.mark.parametrize("prm,amp", [(STRESS, 0.5), (DEFAULT, 100.0)])
