@@ -159,7 +159,9 @@ int gr_bind(gr_grid g, void *d_workspace, size_t bytes, void *hip_stream);
  * Psi currently held (the previous step's Psi^n, sec. 4.5), CIC-interpolated
  * to the particle.  Overwrites s0, s_i and the stress trace s_m
  * (s_m = gamma^ij s_ij += w m a^-2 chi^-4 u_i u_i/(W c h^3)).  Positions
- * outside [0,1) are wrapped. */
+ * outside [0,1) are wrapped.  Up to n^3 particles are deposited in cell order
+ * (counting sort by cloud corner, then one sum per grid point, no
+ * floating-point atomics); more particles fall back to an atomic scatter. */
 int gr_deposit_sources(gr_grid g, const double *d_pos, const double *d_u, double mass,
                        int64_t n_particles);
 

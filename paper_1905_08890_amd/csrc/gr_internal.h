@@ -134,6 +134,11 @@ void launch_axpy(hipStream_t s, double *y, const double *x, long N);
 void launch_cubic_pass(hipStream_t s, const double *in, int nx, int ny, int nz, int dim, double *out);
 
 // ---- sources.hip launchers ----
+// cell-ordered deposit for up to `cap` particles; scratch of cic_sorted_bytes(N, cap)
+size_t cic_sorted_bytes(long N, long cap);
+void launch_cic_sorted(hipStream_t s, int n, double a, double c_tilde, const double *pos, const double *u,
+                       double mass, long np, const double *psi, void *scratch, double *s0, double *sx, double *sy,
+                       double *sz, double *sm);
 void launch_cic_deposit(hipStream_t s, int n, double a, double c_tilde, const double *pos, const double *u,
                         double mass, long np, const double *psi, double *s0, double *sx, double *sy,
                         double *sz, double *sm);

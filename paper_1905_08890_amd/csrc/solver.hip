@@ -72,6 +72,7 @@ struct gr_grid_s {
     double *alt[10]{}; // alternative (previous-step) guesses, saved by gr_set_guess
     bool alt_valid[10]{};
     double *gtmp = nullptr; // 3/4 of a fine array: cubic guess interpolation passes
+    void *cic = nullptr;    // cell-ordered deposit scratch for up to n^3 particles
     double *partials = nullptr;
     double *scal = nullptr;
     hipStream_t stream = nullptr;
@@ -122,6 +123,7 @@ size_t layout(gr_grid g, char *base)
     for (int c = 0; c < 3; ++c) g->fB[c] = take(fb);
     for (int f = 0; f < 10; ++f) g->alt[f] = take(fb);
     g->gtmp = take(3 * fb / 4);
+    g->cic = take(cic_sorted_bytes(g->N(), g->N()));
     for (int l = 0; l < g->nlev; ++l) {
         Level &L = g->lev[l];
         const size_t lb = sizeof(double) * (size_t)L.N;
@@ -296,9 +298,14 @@ int solve_one(gr_grid g, int kind, double *phi, const gr_solve_opts &o, int *cyc
             break;
         }
         CHK(vcycle(g, E, 0));
-        CHK(pin_mean(g, phi, N));
+        // The Poisson V-cycle commutes with adding a constant (the Laplacian, the
+        // smoother, R and P all do, and the coarsest level removes the mean of
+        // its correction), and so does the stopping quantity: pinning once at the
+        // end gives the per-cycle pinned iterate up to rounding.
+        if (kind != GR_KIND_POISSON) CHK(pin_mean(g, phi, N));
         ++cyc;
     }
+    if (kind == GR_KIND_POISSON && cyc > 0) CHK(pin_mean(g, phi, N));
     *cycles_out = cyc;
     *rel_out = rel;
     return st;
@@ -448,12 +455,17 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
                 launch_restrict_f32(s, g->lev32[l - 1].c, g->lev[l - 1].n, g->lev32[l].c);
             }
         CHK(vcycle32(g, lkind, 0, o.nu1, o.nu2, oc, true));
-        launch_sum_f32(s, F32.e, N, g->partials);
-        launch_finalize(s, g->partials, 1, 1.0 / (double)N, nullptr, g->scal + S_MEAN);
-        launch_ir_update(s, phi, F32.e, N, g->scal + S_MEAN);
+        if (kind == GR_KIND_POISSON) { // shift-invariant: one pin at the end (as in the FP64 cycle)
+            launch_ir_update(s, phi, F32.e, N, g->scal + S_ZERO);
+        } else {
+            launch_sum_f32(s, F32.e, N, g->partials);
+            launch_finalize(s, g->partials, 1, 1.0 / (double)N, nullptr, g->scal + S_MEAN);
+            launch_ir_update(s, phi, F32.e, N, g->scal + S_MEAN);
+        }
         LAUNCHCHK();
         ++cyc;
     }
+    if (kind == GR_KIND_POISSON && cyc > 0 && !*fell_back) CHK(pin_mean(g, phi, N));
     *cycles_out = cyc;
     *rel_out = rel;
     return st;
@@ -649,9 +661,14 @@ int gr_deposit_sources(gr_grid g, const double *d_pos, const double *d_u, double
     if (np < 0 || (np > 0 && (!d_pos || !d_u))) return fail(GR_EINVAL, "bad particle arrays");
     if (!std::isfinite(mass)) return fail(GR_EINVAL, "mass not finite");
     const long N = g->N();
-    for (int c = 0; c < 5; ++c) launch_fill(g->stream, g->src[c], N, 0.0);
-    launch_cic_deposit(g->stream, g->n, g->prm.a, g->prm.c_tilde, d_pos, d_u, mass, (long)np, g->field[GR_PSI],
-                       g->src[0], g->src[1], g->src[2], g->src[3], g->src[4]);
+    if (np <= N) {
+        launch_cic_sorted(g->stream, g->n, g->prm.a, g->prm.c_tilde, d_pos, d_u, mass, (long)np, g->field[GR_PSI],
+                          g->cic, g->src[0], g->src[1], g->src[2], g->src[3], g->src[4]);
+    } else { // more particles than cells: scatter with floating-point atomics
+        for (int c = 0; c < 5; ++c) launch_fill(g->stream, g->src[c], N, 0.0);
+        launch_cic_deposit(g->stream, g->n, g->prm.a, g->prm.c_tilde, d_pos, d_u, mass, (long)np,
+                           g->field[GR_PSI], g->src[0], g->src[1], g->src[2], g->src[3], g->src[4]);
+    }
     LAUNCHCHK();
     return GR_OK;
 }

@@ -184,13 +184,25 @@ def test_tiny_and_single_level_grids(n):
 
 # ---------------------------------------------------------------- CIC
 
-def test_cic_matches_oracle():
+@pytest.mark.parametrize("mode", ["cell_ordered", "clustered", "atomic"])
+def test_cic_matches_oracle(mode):
+    """Up to n^3 particles take the cell-ordered deposit, more the atomic one."""
     n = 32
+    print(f"[gpu] cic {mode}", flush=True)
     pos, u, mass = synth.zeldovich(n, 3, 0.7)
     rng = np.random.default_rng(5)
-    extra = rng.uniform(0, 1, (4097, 3))                   # ragged count, arbitrary positions
-    pos = np.concatenate([pos, extra])
-    u = np.concatenate([u, 1e-2 * rng.standard_normal((4097, 3))])
+    if mode == "atomic":
+        extra = rng.uniform(0, 1, (4097, 3))               # ragged count, arbitrary positions
+        pos = np.concatenate([pos, extra])
+        u = np.concatenate([u, 1e-2 * rng.standard_normal((4097, 3))])
+    elif mode == "cell_ordered":
+        pos, u = pos[:-37].copy(), u[:-37].copy()           # ragged count below n^3
+        pos[:5] = [[0.0, 0.0, 0.0], [1.0, 0.5, 0.5], [-0.3, 1.7, 0.2], [0.5 / n, 0.5 / n, 0.5 / n],
+                   [1.0 - 1e-12, 1e-12, 0.5]]               # boundaries, wrapped positions, cell centres
+    else:
+        # a third of the particles piled into a few cells (long per-cell lists)
+        k = n ** 3 // 3
+        pos[:k] = 0.25 + 1e-3 * rng.standard_normal((k, 3))
     psi = 40.0 * synth.grf(n, 9, -3.0, 1.0)
     g = grid(n, DEFAULT)
     g.set_field("Psi", psi)
