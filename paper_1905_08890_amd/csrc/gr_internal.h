@@ -64,6 +64,7 @@ struct FusedCfg {
     int tile = 1;         // 0: 64x8 tiles, 1: 32x16 tiles
     int xcd_remap = 0;    // 1: XCD-contiguous workgroup order
     int target_wgs = 1024;
+    int pf = 0;           // operand prefetch depth in planes (1 or 2; 0: per-kind default)
 };
 bool fused_sweep_ok(int n, int min_n);
 void launch_rb_fused(int kind, hipStream_t s, const double *in, double *out, const double *f, const double *coef,

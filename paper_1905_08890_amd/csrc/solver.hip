@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "gr_internal.h"
 
@@ -83,6 +84,31 @@ struct gr_grid_s {
     double stall_ratio = 0.5; // mixed precision: a refinement step that keeps more than this
                               // fraction of the residual counts as stalled (two in a row: FP64)
     size_t ws_bytes = 0;
+    // Solves run on a private stream (joined to the caller's by events) so that
+    // each cycle body can be captured once into a hipGraph and replayed.
+    hipStream_t user_stream = nullptr;
+    hipStream_t work = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    bool use_graph = true;
+    struct GraphEntry {
+        int prec, kind, nu1, nu2;
+        const double *phi;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+
+    void drop_graphs()
+    {
+        for (auto &e : graphs) (void)hipGraphExecDestroy(e.exec);
+        graphs.clear();
+    }
+    ~gr_grid_s()
+    {
+        drop_graphs();
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (work) (void)hipStreamDestroy(work);
+    }
 
     long N() const { return (long)n * n * n; }
     OpConst oc() const
@@ -165,6 +191,57 @@ int pin_mean(gr_grid g, double *phi, long N)
     LAUNCHCHK();
     return GR_OK;
 }
+
+// ------------------------------------------------------ graphs and streams
+
+// Run `body` (kernel launches only, no host synchronisation) on the work
+// stream: captured into a hipGraph on first use for this key, replayed after.
+template <class F>
+int run_captured(gr_grid g, int prec, int kind, int nu1, int nu2, const double *phi, F body)
+{
+    if (!g->use_graph) return body();
+    hipGraphExec_t exec = nullptr;
+    for (auto &e : g->graphs)
+        if (e.prec == prec && e.kind == kind && e.nu1 == nu1 && e.nu2 == nu2 && e.phi == phi) exec = e.exec;
+    if (!exec) {
+        hipGraph_t gr;
+        HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+        const int st = body();
+        hipError_t e = hipStreamEndCapture(g->stream, &gr);
+        if (st != GR_OK) {
+            if (e == hipSuccess) (void)hipGraphDestroy(gr);
+            return st;
+        }
+        if (e != hipSuccess) return fail(GR_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) return fail(GR_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+        g->graphs.push_back({prec, kind, nu1, nu2, phi, exec});
+    }
+    HIPCHK(hipGraphLaunch(exec, g->stream));
+    return GR_OK;
+}
+
+// Moves a solve onto the work stream: it starts after the work already queued
+// on the caller's stream, and the caller's stream waits for it at the end.
+struct WorkScope {
+    gr_grid g;
+    bool ok = false;
+    explicit WorkScope(gr_grid g_) : g(g_)
+    {
+        if (hipEventRecord(g->ev_in, g->user_stream) != hipSuccess) return;
+        if (hipStreamWaitEvent(g->work, g->ev_in, 0) != hipSuccess) return;
+        g->stream = g->work;
+        ok = true;
+    }
+    ~WorkScope()
+    {
+        if (!ok) return;
+        (void)hipEventRecord(g->ev_out, g->work);
+        (void)hipStreamWaitEvent(g->user_stream, g->ev_out, 0);
+        g->stream = g->user_stream;
+    }
+};
 
 // ------------------------------------------------------------ V-cycle
 
@@ -254,23 +331,22 @@ int vcycle(gr_grid g, const EqCtx &E, int l)
 // V-cycle, pin.
 int solve_one(gr_grid g, int kind, double *phi, const gr_solve_opts &o, int *cycles_out, double *rel_out)
 {
-    hipStream_t s = g->stream;
     const long N = g->N();
     Level &F = g->lev[0];
     F.phi = phi;
     EqCtx E{kind, g->oc(), o.nu1, o.nu2};
     if (kind != GR_KIND_POISSON)
-        for (int l = 1; l < g->nlev; ++l) launch_restrict(s, g->lev[l - 1].coef, g->lev[l - 1].n, g->lev[l].coef);
-    launch_set_scalar(s, g->scal + S_FBAR, 0.0);
-    launch_set_scalar(s, g->scal + S_FSHIFT, 0.0);
+        for (int l = 1; l < g->nlev; ++l)
+            launch_restrict(g->stream, g->lev[l - 1].coef, g->lev[l - 1].n, g->lev[l].coef);
+    launch_set_scalar(g->stream, g->scal + S_FBAR, 0.0);
+    launch_set_scalar(g->stream, g->scal + S_FSHIFT, 0.0);
     if (kind == GR_KIND_CMC) CHK(reduce_mean(g, F.f, nullptr, N, g->scal + S_FMEAN));
     LAUNCHCHK();
     CHK(pin_mean(g, phi, N));
 
-    int cyc = 0;
-    double rel = 0.0;
-    int st = GR_OK;
-    for (;;) {
+    // frozen means of this iterate, then the two norms of the stopping test
+    auto measure = [&]() -> int {
+        hipStream_t s = g->stream;
         if (kind == GR_KIND_HAMILTONIAN) {
             launch_sum_ham_F(s, phi, F.f, F.coef, N, E.oc, g->partials);
             launch_finalize(s, g->partials, 1, 1.0 / (double)N, nullptr, g->scal + S_FBAR);
@@ -282,9 +358,27 @@ int solve_one(gr_grid g, int kind, double *phi, const gr_solve_opts &o, int *cyc
                          g->partials);
         launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN);
         LAUNCHCHK();
+        return GR_OK;
+    };
+    // one V-cycle (pinned for the nonlinear kinds), then the next measurement
+    auto cycle = [&]() -> int {
+        CHK(vcycle(g, E, 0));
+        // The Poisson V-cycle commutes with adding a constant (the Laplacian, the
+        // smoother, R and P all do, and the coarsest level removes the mean of
+        // its correction), and so does the stopping quantity: pinning once at the
+        // end gives the per-cycle pinned iterate up to rounding.
+        if (kind != GR_KIND_POISSON) CHK(pin_mean(g, phi, N));
+        return measure();
+    };
+
+    CHK(measure());
+    int cyc = 0;
+    double rel = 0.0;
+    int st = GR_OK;
+    for (;;) {
         double hn[2];
-        HIPCHK(hipMemcpyAsync(hn, g->scal + S_RN, sizeof hn, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(hipMemcpyAsync(hn, g->scal + S_RN, sizeof hn, hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(hipStreamSynchronize(g->stream));
         const double rn = std::sqrt(hn[0]), fn = std::sqrt(hn[1]);
         rel = rn / (fn > 0.0 ? fn : 1.0);
         if (!std::isfinite(rel)) {
@@ -297,12 +391,7 @@ int solve_one(gr_grid g, int kind, double *phi, const gr_solve_opts &o, int *cyc
                 st = fail(GR_ENOTCONV, "kind %d: rel residual %.3e after %d cycles", kind, rel, cyc);
             break;
         }
-        CHK(vcycle(g, E, 0));
-        // The Poisson V-cycle commutes with adding a constant (the Laplacian, the
-        // smoother, R and P all do, and the coarsest level removes the mean of
-        // its correction), and so does the stopping quantity: pinning once at the
-        // end gives the per-cycle pinned iterate up to rounding.
-        if (kind != GR_KIND_POISSON) CHK(pin_mean(g, phi, N));
+        CHK(run_captured(g, GR_FP64, kind, o.nu1, o.nu2, phi, cycle));
         ++cyc;
     }
     if (kind == GR_KIND_POISSON && cyc > 0) CHK(pin_mean(g, phi, N));
@@ -408,10 +497,8 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
     LAUNCHCHK();
     CHK(pin_mean(g, phi, N));
 
-    int cyc = 0, stall = 0;
-    double rel = 0.0, prev = HUGE_VAL;
-    int st = GR_OK;
-    for (;;) {
+    // frozen means, FP64 residual (as FP32 right-hand side) and the stopping norms
+    auto measure = [&]() -> int {
         if (kind == GR_KIND_HAMILTONIAN) {
             launch_sum_ham_F(s, phi, F.f, F.coef, N, oc, g->partials);
             launch_finalize(s, g->partials, 1, 1.0 / (double)N, nullptr, g->scal + S_FBAR);
@@ -423,6 +510,32 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
                            F32.c, g->partials);
         launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN);
         LAUNCHCHK();
+        return GR_OK;
+    };
+    // one FP32 correction cycle and the FP64 update, then the next measurement
+    auto step = [&]() -> int {
+        if (kind == GR_KIND_HAMILTONIAN)
+            for (int l = 1; l < g->nlev; ++l) {
+                launch_restrict_f32(s, g->lev32[l - 1].a, g->lev[l - 1].n, g->lev32[l].a);
+                launch_restrict_f32(s, g->lev32[l - 1].c, g->lev[l - 1].n, g->lev32[l].c);
+            }
+        CHK(vcycle32(g, lkind, 0, o.nu1, o.nu2, oc, true));
+        if (kind == GR_KIND_POISSON) { // shift-invariant: one pin at the end (as in the FP64 cycle)
+            launch_ir_update(s, phi, F32.e, N, g->scal + S_ZERO);
+        } else {
+            launch_sum_f32(s, F32.e, N, g->partials);
+            launch_finalize(s, g->partials, 1, 1.0 / (double)N, nullptr, g->scal + S_MEAN);
+            launch_ir_update(s, phi, F32.e, N, g->scal + S_MEAN);
+        }
+        LAUNCHCHK();
+        return measure();
+    };
+
+    CHK(measure());
+    int cyc = 0, stall = 0;
+    double rel = 0.0, prev = HUGE_VAL;
+    int st = GR_OK;
+    for (;;) {
         double hn[2];
         HIPCHK(hipMemcpyAsync(hn, g->scal + S_RN, sizeof hn, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -449,20 +562,7 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
             cyc += c2;
             break;
         }
-        if (kind == GR_KIND_HAMILTONIAN)
-            for (int l = 1; l < g->nlev; ++l) {
-                launch_restrict_f32(s, g->lev32[l - 1].a, g->lev[l - 1].n, g->lev32[l].a);
-                launch_restrict_f32(s, g->lev32[l - 1].c, g->lev[l - 1].n, g->lev32[l].c);
-            }
-        CHK(vcycle32(g, lkind, 0, o.nu1, o.nu2, oc, true));
-        if (kind == GR_KIND_POISSON) { // shift-invariant: one pin at the end (as in the FP64 cycle)
-            launch_ir_update(s, phi, F32.e, N, g->scal + S_ZERO);
-        } else {
-            launch_sum_f32(s, F32.e, N, g->partials);
-            launch_finalize(s, g->partials, 1, 1.0 / (double)N, nullptr, g->scal + S_MEAN);
-            launch_ir_update(s, phi, F32.e, N, g->scal + S_MEAN);
-        }
-        LAUNCHCHK();
+        CHK(run_captured(g, GR_MIXED, kind, o.nu1, o.nu2, phi, step));
         ++cyc;
     }
     if (kind == GR_KIND_POISSON && cyc > 0 && !*fell_back) CHK(pin_mean(g, phi, N));
@@ -597,9 +697,11 @@ int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out)
     // tuning knobs (environment): GRMG_SMOOTHER=split|fused forces one smoother
     // on every level it can run on; GRMG_FUSED_MIN (smallest level for the fused
     // smoother), GRMG_FUSED_TILE (0: 64x8, 1: 32x16), GRMG_XCD_REMAP (0/1),
-    // GRMG_FUSED_WGS (target workgroups per fused launch), GRMG_COARSE_N (levels
+    // GRMG_FUSED_WGS (target workgroups per fused launch), GRMG_FUSED_PF (prefetch
+    // depth 1 or 2 planes), GRMG_COARSE_N (levels
     // at or below this size run the rest of the V-cycle in one workgroup; 0: never),
-    // GRMG_MIXED_STALL (mixed-precision stagnation ratio)
+    // GRMG_MIXED_STALL (mixed-precision stagnation ratio), GRMG_GRAPH (0: launch
+    // every cycle's kernels one by one instead of replaying a captured graph)
     if (const char *e = std::getenv("GRMG_SMOOTHER")) {
         g->fused = std::strcmp(e, "split") != 0;
         if (std::strcmp(e, "fused") == 0) g->fcfg.min_n = 64;
@@ -608,8 +710,10 @@ int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out)
     if (const char *e = std::getenv("GRMG_FUSED_TILE")) g->fcfg.tile = std::atoi(e) == 1 ? 1 : 0;
     if (const char *e = std::getenv("GRMG_XCD_REMAP")) g->fcfg.xcd_remap = std::atoi(e) != 0;
     if (const char *e = std::getenv("GRMG_FUSED_WGS")) g->fcfg.target_wgs = std::max(1, std::atoi(e));
+    if (const char *e = std::getenv("GRMG_FUSED_PF")) g->fcfg.pf = std::atoi(e) == 2 ? 2 : (std::atoi(e) == 1 ? 1 : 0);
     if (const char *e = std::getenv("GRMG_COARSE_N")) g->coarse_n = std::atoi(e);
     if (const char *e = std::getenv("GRMG_MIXED_STALL")) g->stall_ratio = std::atof(e);
+    if (const char *e = std::getenv("GRMG_GRAPH")) g->use_graph = std::atoi(e) != 0;
     if (g->nlev > kMaxLevels) {
         delete g;
         return fail(GR_EINVAL, "too many levels");
@@ -641,7 +745,14 @@ int gr_bind(gr_grid g, void *d_ws, size_t bytes, void *stream)
         (void)hipGetLastError();
         return fail(GR_EINVAL, "workspace is not device memory");
     }
-    g->stream = reinterpret_cast<hipStream_t>(stream);
+    g->user_stream = reinterpret_cast<hipStream_t>(stream);
+    g->stream = g->user_stream;
+    g->drop_graphs();
+    if (!g->work) {
+        HIPCHK(hipStreamCreateWithFlags(&g->work, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&g->ev_in, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&g->ev_out, hipEventDisableTiming));
+    }
     layout(g, reinterpret_cast<char *>(d_ws));
     launch_fill(g->stream, reinterpret_cast<double *>(d_ws), (long)(g->ws_bytes / sizeof(double)), 0.0);
     LAUNCHCHK();
@@ -717,6 +828,8 @@ int gr_solve_equation(gr_grid g, int kind, int field, const gr_solve_opts *opts,
     CHK(check_opts(opts));
     if (kind < 0 || kind > 2) return fail(GR_EINVAL, "bad kind %d", kind);
     if (field < 0 || field > 9) return fail(GR_EINVAL, "bad field %d", field);
+    WorkScope ws(g);
+    if (!ws.ok) return fail(GR_EDEVICE, "cannot join the work stream");
     auto t0 = std::chrono::steady_clock::now();
     if (opts->guess == GR_GUESS_ZERO) launch_fill(g->stream, g->field[field], g->N(), 0.0);
     int cyc = 0;
@@ -742,6 +855,8 @@ int gr_solve_constraints(gr_grid g, const gr_solve_opts *opts, gr_solve_report *
 {
     CHK(check_bound(g));
     CHK(check_opts(opts));
+    WorkScope ws(g);
+    if (!ws.ok) return fail(GR_EDEVICE, "cannot join the work stream");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = g->stream;
     const long N = g->N();

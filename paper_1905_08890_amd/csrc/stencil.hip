@@ -81,12 +81,18 @@ __global__ void __launch_bounds__(TPB) k_rb_colour(T *__restrict__ phi, const T 
 // Red values on the halo are recomputed from old data by every tile that needs
 // them, so tiles never read each other's output: the result is exactly the
 // red-then-black sweep, with phi read once and written once per sweep.
-// All global reads of the next plane (phi, and the source/coefficient of the
-// points updated next) are issued into registers before the current plane's
-// updates, so their latency overlaps the LDS work.  Five ring slots let the
-// store of plane z+1 proceed without waiting for the black pass of z-2:
-// two barriers per plane.
-template <int KIND, typename T, int TX, int TY>
+//
+// Each thread owns one (even, odd) pair of x-points of a tile row: its red
+// update is the red member of the pair, its black update the black member,
+// and its source/coefficient values arrive as one 16-byte load per array that
+// serves both (the black half waits one plane in registers), so every cache
+// line of f and the coefficients is read once.  The 1-cell halo ring of red
+// points (TX + TY + 2 per plane) is spread over the first threads with scalar
+// loads.  All global reads of the next plane are issued into registers before
+// the current plane's updates, so their latency overlaps the LDS work.  Five
+// ring slots let the store of plane z+1 proceed without waiting for the black
+// pass of z-2: two barriers per plane.
+template <int KIND, typename T, int TX, int TY, int PF>
 __global__ void __launch_bounds__((TX / 2) * TY) k_rb_fused(
     const T *__restrict__ in, T *__restrict__ out, const T *__restrict__ f, const T *__restrict__ c1,
     const T *__restrict__ c2, int n, int zc, T inv_h2, OpConst oc, const double *__restrict__ fbar,
@@ -95,9 +101,8 @@ __global__ void __launch_bounds__((TX / 2) * TY) k_rb_fused(
     constexpr int NT = (TX / 2) * TY;
     constexpr int W = TX + 4, H = TY + 4, PL = W * H;
     constexpr int NLOAD = (PL + NT - 1) / NT;
-    constexpr int RPR = (TX + 2) / 2; // red points per row of tile + halo
-    constexpr int NRED = RPR * (TY + 2);
-    constexpr int NRP = (NRED + NT - 1) / NT;
+    constexpr int HALO = TX + TY + 2; // red points of the 1-cell halo ring, per plane
+    static_assert(HALO <= NT, "halo ring larger than the workgroup");
     constexpr int NC = kNumCoef<KIND>();
     using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
     __shared__ __align__(16) T ring[5][PL];
@@ -123,120 +128,142 @@ __global__ void __launch_bounds__((TX / 2) * TY) k_rb_fused(
         const int ly = idx / W, lx = idx - ly * W;
         goff[q] = wrapi(y0 + ly - 2, n) * n + wrapi(x0 + lx - 2, n);
     }
-    // this thread's red points (tile + 1-halo): row and pair index; lx depends on the plane parity
-    int rrow[NRP], rk[NRP];
-#pragma unroll
-    for (int q = 0; q < NRP; ++q) {
-        const int r = tid + q * NT;
-        rrow[q] = r < NRED ? r / RPR : -1;
-        rk[q] = r - (r / RPR) * RPR;
-    }
-    auto red_lx = [&](int q, int zr) { return 1 + 2 * rk[q] + ((2 + rrow[q] + zr) & 1); }; // (x+y+z) even
-    auto red_g = [&](int q, int zr) {
-        return (long)wrapi(zr, n) * plane + wrapi(y0 + rrow[q] - 1, n) * n + wrapi(x0 + red_lx(q, zr) - 2, n);
-    };
-    // this thread's black point: row bty, pair btx
+    // this thread's pair: LDS row ly, even LDS column lxe; red member (x+y+z even) at lxe + ((ly + z) & 1)
     const int btx = tid % (TX / 2), bty = tid / (TX / 2);
-    auto blk_o = [&](int zb) { return (2 + bty + zb + 1) & 1; }; // (x+y+z) odd
-    auto blk_g = [&](int zb) { return (long)wrapi(zb, n) * plane + (long)(y0 + bty) * n + x0 + 2 * btx; };
+    const int ly = 2 + bty, lxe = 2 + 2 * btx;
+    const long pair_off = (long)(y0 + bty) * n + x0 + 2 * btx;
+    // halo ring point h = tid (tid < HALO): LDS row/column for a plane z
+    auto halo_pos = [&](int z, int &hy, int &hx) {
+        const int h = tid;
+        if (h < TX + 2) { // rows 1 and TY + 2, (TX + 2) / 2 red points each
+            hy = h < (TX + 2) / 2 ? 1 : TY + 2;
+            const int k = h < (TX + 2) / 2 ? h : h - (TX + 2) / 2;
+            hx = 1 + ((hy + z + 1) & 1) + 2 * k;
+        } else { // columns 1 and TX + 2 of rows 2..TY+1: one of the two is red
+            hy = 2 + (h - (TX + 2));
+            hx = ((1 + hy + z) & 1) == 0 ? 1 : TX + 2;
+        }
+    };
+    auto halo_g = [&](int z, int hy, int hx) {
+        return (long)wrapi(z, n) * plane + wrapi(y0 + hy - 2, n) * n + wrapi(x0 + hx - 2, n);
+    };
 
-    T pre[NLOAD];
-    T rf_c[NRP], rc_c[NRP], ra_c[NRP], rf_n[NRP], rc_n[NRP], ra_n[NRP];
-    T bf_c = 0, bc_c = 0, ba_c = 0, bf_n = 0, bc_n = 0, ba_n = 0;
-#pragma unroll
-    for (int q = 0; q < NRP; ++q) rf_c[q] = rc_c[q] = ra_c[q] = rf_n[q] = rc_n[q] = ra_n[q] = T(0);
+    // Operands travel PF (1 or 2) planes ahead, in PF alternating register
+    // sets: the iterate plane stored at iteration it was loaded at it - PF, and
+    // so were the pair and halo values used by the red pass at it.
+    struct Set {
+        T pre[NLOAD];
+        T2 f, c, a;
+        T hf, hc, ha;
+    };
+    Set A, B;
     // in == nullptr: the incoming iterate is identically zero (first sweep of a
     // correction cycle), so the plane loads are skipped
     const bool zero_in = in == nullptr;
+    auto load_plane = [&](Set &S, int z) {
 #pragma unroll
-    for (int q = 0; q < NLOAD; ++q) pre[q] = T(0);
-    if (!zero_in) {
-        const T *src = in + (long)wrapi(z0 - 2, n) * plane;
+        for (int q = 0; q < NLOAD; ++q) S.pre[q] = T(0);
+        if (!zero_in) {
+            const T *src = in + (long)wrapi(z, n) * plane;
 #pragma unroll
-        for (int q = 0; q < NLOAD; ++q)
-            if (lidx[q] >= 0) pre[q] = src[goff[q]];
-    }
+            for (int q = 0; q < NLOAD; ++q)
+                if (lidx[q] >= 0) S.pre[q] = src[goff[q]];
+        }
+    };
+    auto load_operands = [&](Set &S, int z) {
+        const long gp = (long)wrapi(z, n) * plane + pair_off;
+        S.f = *reinterpret_cast<const T2 *>(f + gp);
+        if (NC >= 1) S.c = *reinterpret_cast<const T2 *>(c1 + gp);
+        if (NC >= 2) S.a = *reinterpret_cast<const T2 *>(c2 + gp);
+        if (tid < HALO) {
+            int hy, hx;
+            halo_pos(z, hy, hx);
+            const long hg = halo_g(z, hy, hx);
+            S.hf = f[hg];
+            if (NC >= 1) S.hc = c1[hg];
+            if (NC >= 2) S.ha = c2[hg];
+        }
+    };
+    A.f.x = A.f.y = A.c.x = A.c.y = A.a.x = A.a.y = A.hf = A.hc = A.ha = T(0);
+    B.f = A.f;
+    B.c = A.c;
+    B.a = A.a;
+    B.hf = B.hc = B.ha = T(0);
+    load_plane(A, z0 - 2);
+    if (PF == 2) load_plane(B, z0 - 1);
+    T fbk = 0, cbk = 0, abk = 0; // black half of the pair for the black pass of the next iteration
 
     int slot = 0; // slot of plane zz = z0 - 2 + it is it % 5
-    for (int it = 0; it < zc + 4; ++it) {
+    auto body = [&](const int it, Set &S) {
         const int zz = z0 - 2 + it;
         T *cur = ring[slot];
 #pragma unroll
         for (int q = 0; q < NLOAD; ++q)
-            if (lidx[q] >= 0) cur[lidx[q]] = pre[q];
+            if (lidx[q] >= 0) cur[lidx[q]] = S.pre[q];
         __syncthreads();
-        if (it + 1 < zc + 4) { // reads for the next iteration, in flight during this one
-            if (!zero_in) {
-                const T *src = in + (long)wrapi(zz + 1, n) * plane;
-#pragma unroll
-                for (int q = 0; q < NLOAD; ++q)
-                    if (lidx[q] >= 0) pre[q] = src[goff[q]];
-            }
-            if (it + 1 >= 2) { // red of plane zz at it + 1
-#pragma unroll
-                for (int q = 0; q < NRP; ++q)
-                    if (rrow[q] >= 0) {
-                        const long gp = red_g(q, zz);
-                        rf_n[q] = f[gp];
-                        if (NC >= 1) rc_n[q] = c1[gp];
-                        if (NC >= 2) ra_n[q] = c2[gp];
-                    }
-            }
-            if (it + 1 >= 4) { // black of plane zz - 1 at it + 1
-                const long gp = blk_g(zz - 1) + blk_o(zz - 1);
-                bf_n = f[gp];
-                if (NC >= 1) bc_n = c1[gp];
-                if (NC >= 2) ba_n = c2[gp];
-            }
-        }
+        const bool ahead = it + PF < zc + 4;
+        if (ahead) load_plane(S, zz + PF);
         const int s1 = slot == 0 ? 4 : slot - 1, s2 = s1 == 0 ? 4 : s1 - 1, s3 = s2 == 0 ? 4 : s2 - 1;
         if (it >= 2) { // red points of plane zr = zz - 1, tile + 1-cell halo
             const int zr = zz - 1;
             T *mid = ring[s1];
             const T *lo = ring[s2];
             const T *hi = ring[slot];
-#pragma unroll
-            for (int q = 0; q < NRP; ++q) {
-                if (rrow[q] < 0) continue;
-                const int c = (1 + rrow[q]) * W + red_lx(q, zr);
+            const int o = (ly + zr) & 1; // red member of the pair
+            {
+                const int c = ly * W + lxe + o;
                 const T ph = mid[c];
                 const T nbs = mid[c - 1] + mid[c + 1] + mid[c - W] + mid[c + W] + lo[c] + hi[c];
                 T J;
-                const T L = op_point<KIND, T>(ph, nbs, inv_h2, rc_c[q], ra_c[q], oc, Fb, J);
-                mid[c] = ph - (L - (rf_c[q] - fs)) / J;
+                const T L = op_point<KIND, T>(ph, nbs, inv_h2, o ? S.c.y : S.c.x, o ? S.a.y : S.a.x, oc, Fb, J);
+                mid[c] = ph - (L - ((o ? S.f.y : S.f.x) - fs)) / J;
+            }
+            if (tid < HALO) {
+                int hy, hx;
+                halo_pos(zr, hy, hx);
+                const int c = hy * W + hx;
+                const T ph = mid[c];
+                const T nbs = mid[c - 1] + mid[c + 1] + mid[c - W] + mid[c + W] + lo[c] + hi[c];
+                T J;
+                const T L = op_point<KIND, T>(ph, nbs, inv_h2, S.hc, S.ha, oc, Fb, J);
+                mid[c] = ph - (L - (S.hf - fs)) / J;
             }
         }
+        // plane zz - 1 had its red pass now; its black half is used at it + 1
+        const int ob = (ly + zz) & 1;
+        const T nfb = ob ? S.f.y : S.f.x, ncb = ob ? S.c.y : S.c.x, nab = ob ? S.a.y : S.a.x;
+        if (ahead) load_operands(S, zz + PF - 1); // red pass of plane zz + PF - 1 at it + PF
         __syncthreads();
         if (it >= 4) { // black points of plane zb = zz - 2, tile only; write both colours
             const int zb = zz - 2;
             const T *mid = ring[s2];
             const T *lo = ring[s3];
             const T *hi = ring[s1];
-            const int ly = 2 + bty;
-            const int lxe = 2 + 2 * btx;
-            const int o = blk_o(zb);
+            const int o = (ly + zb + 1) & 1; // black member of the pair
             const int c = ly * W + lxe + o;
             const T ph = mid[c];
             const T nbs = mid[c - 1] + mid[c + 1] + mid[c - W] + mid[c + W] + lo[c] + hi[c];
             T J;
-            const T L = op_point<KIND, T>(ph, nbs, inv_h2, bc_c, ba_c, oc, Fb, J);
-            const T nb = ph - (L - (bf_c - fs)) / J;
+            const T L = op_point<KIND, T>(ph, nbs, inv_h2, cbk, abk, oc, Fb, J);
+            const T nb = ph - (L - (fbk - fs)) / J;
             const T red = mid[ly * W + lxe + (1 - o)];
             T2 v;
             v.x = o ? red : nb;
             v.y = o ? nb : red;
-            *reinterpret_cast<T2 *>(out + blk_g(zb)) = v;
+            *reinterpret_cast<T2 *>(out + (long)wrapi(zb, n) * plane + pair_off) = v;
         }
-#pragma unroll
-        for (int q = 0; q < NRP; ++q) {
-            rf_c[q] = rf_n[q];
-            rc_c[q] = rc_n[q];
-            ra_c[q] = ra_n[q];
-        }
-        bf_c = bf_n;
-        bc_c = bc_n;
-        ba_c = ba_n;
+        fbk = nfb;
+        cbk = ncb;
+        abk = nab;
         slot = slot == 4 ? 0 : slot + 1;
+    };
+    if (PF == 2) {
+        for (int it = 0; it < zc + 4; it += 2) {
+            body(it, A);
+            if (it + 1 < zc + 4) body(it + 1, B);
+        }
+    } else {
+        for (int it = 0; it < zc + 4; ++it) body(it, A);
     }
 }
 
@@ -821,46 +848,53 @@ void launch_rb_sweep_f32(int kind, hipStream_t s, float *e, const float *b, cons
 
 bool fused_sweep_ok(int n, int min_n) { return n >= min_n && n >= 64 && n % 64 == 0; }
 
+template <int KIND, typename T, int TX, int TY>
+static void launch_fused_k(int pf, unsigned grid, hipStream_t s, const T *in, T *out, const T *f, const T *c1,
+                           const T *c2, int n, int zc, T inv_h2, OpConst oc, const double *fbar,
+                           const double *fshift, int tiles_y, int xcd_remap)
+{
+    constexpr int NT = (TX / 2) * TY;
+    // default prefetch depth (measured at 256^3): two planes, except for the
+    // FP64 Hamiltonian and CMC sweeps, whose extra registers would cost a
+    // resident workgroup per CU
+    if (pf <= 0) pf = (sizeof(T) == 4 || KIND == GR_KIND_POISSON) ? 2 : 1;
+    if (pf == 2)
+        k_rb_fused<KIND, T, TX, TY, 2><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,
+                                                             tiles_y, xcd_remap);
+    else
+        k_rb_fused<KIND, T, TX, TY, 1><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,
+                                                             tiles_y, xcd_remap);
+}
+
 template <typename T, int TX, int TY>
 static void launch_fused_t(int kind, hipStream_t s, const T *in, T *out, const T *f, const T *c1, const T *c2, int n,
-                           double h, OpConst oc, const double *fbar, const double *fshift, int xcd_remap,
-                           int target_wgs)
+                           double h, OpConst oc, const double *fbar, const double *fshift, const FusedCfg &cfg)
 {
     const int tiles_x = n / TX, tiles_y = n / TY;
     const int tiles = tiles_x * tiles_y;
     // z chunk: halve (keeping >= 8 planes and a divisor of n) until the grid
     // reaches the target number of workgroups (one resident wave)
     int zc = n;
-    while (zc % 2 == 0 && zc / 2 >= 8 && (long)tiles * (n / zc) < target_wgs) zc /= 2;
+    while (zc % 2 == 0 && zc / 2 >= 8 && (long)tiles * (n / zc) < cfg.target_wgs) zc /= 2;
     const unsigned grid = (unsigned)(tiles * (n / zc));
     const T inv_h2 = T(1.0 / (h * h));
-    constexpr int NT = (TX / 2) * TY;
+#define GR_FUSED_CASE(K)                                                                                      \
+    case K:                                                                                                   \
+        launch_fused_k<K, T, TX, TY>(cfg.pf, grid, s, in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,    \
+                                     tiles_y, cfg.xcd_remap);                                                 \
+        break;
     switch (kind) {
-    case GR_KIND_POISSON:
-        k_rb_fused<GR_KIND_POISSON, T, TX, TY><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,
-                                                                    tiles_y, xcd_remap);
-        break;
-    case GR_KIND_HAMILTONIAN:
-        k_rb_fused<GR_KIND_HAMILTONIAN, T, TX, TY><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar,
-                                                                        fshift, tiles_y, xcd_remap);
-        break;
-    case GR_KIND_CMC:
-        k_rb_fused<GR_KIND_CMC, T, TX, TY><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,
-                                                                tiles_y, xcd_remap);
-        break;
-    case K_LIN_POISSON:
-        k_rb_fused<K_LIN_POISSON, T, TX, TY><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,
-                                                                  tiles_y, xcd_remap);
-        break;
-    case K_LIN_HAM:
-        k_rb_fused<K_LIN_HAM, T, TX, TY><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,
-                                                              tiles_y, xcd_remap);
-        break;
+        GR_FUSED_CASE(GR_KIND_POISSON)
+        GR_FUSED_CASE(GR_KIND_HAMILTONIAN)
+        GR_FUSED_CASE(GR_KIND_CMC)
+        GR_FUSED_CASE(K_LIN_POISSON)
+        GR_FUSED_CASE(K_LIN_HAM)
     default:
-        k_rb_fused<K_LIN_CMC, T, TX, TY><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,
-                                                              tiles_y, xcd_remap);
+        launch_fused_k<K_LIN_CMC, T, TX, TY>(cfg.pf, grid, s, in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,
+                                             tiles_y, cfg.xcd_remap);
         break;
     }
+#undef GR_FUSED_CASE
 }
 
 template <typename T>
@@ -868,9 +902,9 @@ static void launch_fused_any(int kind, hipStream_t s, const T *in, T *out, const
                              int n, double h, OpConst oc, const double *fbar, const double *fshift, const FusedCfg &cfg)
 {
     if (cfg.tile == 1)
-        launch_fused_t<T, 32, 16>(kind, s, in, out, f, c1, c2, n, h, oc, fbar, fshift, cfg.xcd_remap, cfg.target_wgs);
+        launch_fused_t<T, 32, 16>(kind, s, in, out, f, c1, c2, n, h, oc, fbar, fshift, cfg);
     else
-        launch_fused_t<T, 64, 8>(kind, s, in, out, f, c1, c2, n, h, oc, fbar, fshift, cfg.xcd_remap, cfg.target_wgs);
+        launch_fused_t<T, 64, 8>(kind, s, in, out, f, c1, c2, n, h, oc, fbar, fshift, cfg);
 }
 
 void launch_rb_fused(int kind, hipStream_t s, const double *in, double *out, const double *f, const double *coef,
