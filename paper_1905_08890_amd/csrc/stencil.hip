@@ -14,6 +14,7 @@
 // J e = a Lap e + c e (kinds K_LIN_*), run the inner correction cycles of
 // mixed-precision iterative refinement: Poisson a = 1, c = 0; Hamiltonian
 // a = chi, c = dL/dPsi - chi dLap/dPsi; CMC a = 1, c = -m2.
+#include <cstdlib>
 #include <type_traits>
 
 #include "stencil_ops.h"
@@ -511,6 +512,146 @@ __global__ void __launch_bounds__(TPB) k_finalize(const double *__restrict__ par
     }
 }
 
+// ------------------------------------------ plane-marching residual kernels
+//
+// A workgroup of 32 x 8 threads owns one (x, y) point each of a 32 x 8 tile
+// and marches a chunk of zc planes in z.  Each plane of the iterate, with a
+// 1-cell halo ring, goes to one of two LDS buffers (one barrier per plane);
+// the z-neighbours stay in registers.  All reads of a plane are issued two
+// planes ahead, in two alternating register sets.  Per point the iterate is
+// read once from memory (plus the halo ring, mostly from L2), the source and
+// coefficients once.  Modes:
+//   M_NORMS        sums of eps^2 and (f - fshift)^2 (stopping test)
+//   M_IR           as M_NORMS, plus the FP32 correction source b = -eps and,
+//                  for the Hamiltonian, a = chi and c = dL/dPsi + 6 chi/h^2
+//   M_RESTRICT     FAS: R eps, R phi (also as phi0) on the coarse level
+//   M_RESTRICT_LIN correction scheme: R(b - J e) and a zero coarse e
+// The restriction modes sum z pairs in registers and x / y pairs across lanes.
+enum { M_NORMS = 0, M_IR = 1, M_RESTRICT = 2, M_RESTRICT_LIN = 3 };
+constexpr int MTX = 32, MTY = 8, MNT = MTX * MTY;
+constexpr int MHALO = 2 * (MTX + 2) + 2 * MTY; // halo ring of a plane
+
+template <int MODE, int KIND, typename T>
+__global__ void __launch_bounds__(MNT) k_march(const T *__restrict__ phi, const T *__restrict__ f,
+                                               const T *__restrict__ c1, const T *__restrict__ c2, int n, int zc,
+                                               T inv_h2, OpConst oc, const double *__restrict__ fbar,
+                                               const double *__restrict__ fshift, double *__restrict__ partials,
+                                               T *__restrict__ o1, T *__restrict__ o2, T *__restrict__ o3,
+                                               float *__restrict__ b32, float *__restrict__ a32,
+                                               float *__restrict__ c32)
+{
+    constexpr int FW = MTX + 2, FH = MTY + 2;
+    constexpr int NC = kNumCoef<KIND>();
+    __shared__ T buf[2][FH * FW];
+    const int tid = threadIdx.x;
+    const int tx = tid % MTX, ty = tid / MTX;
+    const int tiles_y = n / MTY;
+    const int nzc = n / zc;
+    const int tile = blockIdx.x / nzc, zchunk = blockIdx.x % nzc;
+    const int x0 = (tile / tiles_y) * MTX, y0 = (tile % tiles_y) * MTY, z0 = zchunk * zc;
+    const long plane = (long)n * n;
+    const long own = (long)(y0 + ty) * n + x0 + tx;
+    const T Fb = (MODE == M_RESTRICT_LIN) ? T(0) : T(*fbar);
+    const T fs = (MODE == M_RESTRICT_LIN) ? T(0) : T(*fshift);
+    // halo ring position of this thread (tid < MHALO): frame row / column
+    int hr = 0, hc = 0;
+    if (tid < 2 * (MTX + 2)) {
+        hr = tid < MTX + 2 ? 0 : FH - 1;
+        hc = tid < MTX + 2 ? tid : tid - (MTX + 2);
+    } else if (tid < MHALO) {
+        const int k = tid - 2 * (MTX + 2);
+        hr = 1 + k / 2;
+        hc = (k & 1) ? FW - 1 : 0;
+    }
+    const long hoff = (long)wrapi(y0 + hr - 1, n) * n + wrapi(x0 + hc - 1, n);
+    const int fo = (ty + 1) * FW + tx + 1; // own frame index
+
+    struct Set {
+        T own, halo, f, c, a;
+    };
+    auto load = [&](Set &S, int z) {
+        const long zo = (long)wrapi(z, n) * plane;
+        S.own = phi[zo + own];
+        if (tid < MHALO) S.halo = phi[zo + hoff];
+        S.f = f[zo + own];
+        if (NC >= 1) S.c = c1[zo + own];
+        if (NC >= 2) S.a = c2[zo + own];
+    };
+    Set A, B;
+    A.own = A.halo = A.f = A.c = A.a = T(0);
+    B = A;
+    T below = phi[(long)wrapi(z0 - 1, n) * plane + own];
+    load(A, z0);
+    load(B, z0 + 1);
+    double v0 = 0.0, v1 = 0.0; // norm sums
+    T sr = 0, sp = 0;          // restriction sums over a z pair
+
+    auto body = [&](const int z, Set &S, const Set &Nx) {
+        T *pl = buf[z & 1];
+        pl[fo] = S.own;
+        if (tid < MHALO) pl[hr * FW + hc] = S.halo;
+        __syncthreads();
+        const T ph = S.own;
+        const T nbs = pl[fo - 1] + pl[fo + 1] + pl[fo - FW] + pl[fo + FW] + below + Nx.own;
+        T J;
+        const T L = op_point<KIND, T>(ph, nbs, inv_h2, S.c, S.a, oc, Fb, J);
+        const long p = (long)z * plane + own;
+        if constexpr (MODE == M_NORMS || MODE == M_IR) {
+            const double fe = (double)S.f - (double)fs;
+            const double e = (double)L - fe;
+            v0 += e * e;
+            v1 += fe * fe;
+            if constexpr (MODE == M_IR) {
+                b32[p] = (float)(-e);
+                if constexpr (KIND == GR_KIND_HAMILTONIAN) {
+                    const double chi = 1.0 - oc.kappa * (double)ph;
+                    a32[p] = (float)chi;
+                    c32[p] = (float)((double)J + 6.0 * chi * (double)inv_h2);
+                }
+            }
+        } else {
+            sr += (MODE == M_RESTRICT) ? L - (S.f - fs) : S.f - L;
+            sp += ph;
+            if (z & 1) { // a z pair is complete: add the x and y pairs across lanes
+                T r2 = sr + __shfl_xor(sr, 1, 64);
+                T p2 = sp + __shfl_xor(sp, 1, 64);
+                r2 += __shfl_xor(r2, 32, 64);
+                p2 += __shfl_xor(p2, 32, 64);
+                if (((tx | ty) & 1) == 0) {
+                    const int m = n >> 1;
+                    const long q = ((long)(z >> 1) * m + ((y0 + ty) >> 1)) * m + ((x0 + tx) >> 1);
+                    if constexpr (MODE == M_RESTRICT) {
+                        o1[q] = p2 / T(8); // R phi
+                        o2[q] = p2 / T(8); // phi0
+                        o3[q] = r2 / T(8); // R eps
+                    } else {
+                        o1[q] = r2 / T(8); // coarse b
+                        o2[q] = T(0);      // coarse e
+                    }
+                }
+                sr = 0;
+                sp = 0;
+            }
+        }
+        below = ph;
+        if (z + 2 < z0 + zc) load(S, z + 2);
+        else if (z + 2 == z0 + zc) S.own = phi[(long)wrapi(z + 2, n) * plane + own]; // last plane's z + 1
+    };
+    for (int z = z0; z < z0 + zc; z += 2) {
+        body(z, A, B);
+        body(z + 1, B, A);
+    }
+    if constexpr (MODE == M_NORMS || MODE == M_IR) {
+        double v[2] = {v0, v1};
+        block_sum_store<2>(v, partials);
+        if (blockIdx.x == 0) // unused partial slots of a smaller grid
+            for (int b2 = gridDim.x + tid; b2 < kReduceBlocks; b2 += MNT) {
+                partials[b2] = 0.0;
+                partials[kReduceBlocks + b2] = 0.0;
+            }
+    }
+}
+
 // ------------------------------------------------- coarse levels, one block
 
 // The V-cycle below (and including) level ls, run by one workgroup: every
@@ -919,10 +1060,65 @@ void launch_rb_fused_f32(int kind, hipStream_t s, const float *in, float *out, c
     launch_fused_any<float>(kind, s, in, out, b, c1, c2, n, h, oc, zero, zero, cfg);
 }
 
+// Plane-marching kernels serve levels with n a multiple of 32 and n >= 64
+// (GRMG_MARCH=0 keeps the one-thread-per-point kernels everywhere).  The z
+// chunk is halved (even, >= 8 planes) while the grid stays within max_blocks.
+bool march_ok(int n)
+{
+    static const bool on = [] {
+        const char *e = std::getenv("GRMG_MARCH");
+        return !(e && std::atoi(e) == 0);
+    }();
+    return on && n >= 64 && n % MTX == 0;
+}
+
+int march_grid(int n, long max_blocks, int *zc_out)
+{
+    const long tiles = (long)(n / MTX) * (n / MTY);
+    if (tiles > max_blocks) return 0;
+    int zc = n;
+    while (zc % 4 == 0 && zc / 2 >= 8 && tiles * (n / (zc / 2)) <= max_blocks) zc /= 2;
+    *zc_out = zc;
+    return (int)(tiles * (n / zc));
+}
+
+#define GR_MARCH_KIND(MODE, T, kind, grid, ...)                                                       \
+    do {                                                                                              \
+        switch (kind) {                                                                               \
+        case GR_KIND_POISSON: k_march<MODE, GR_KIND_POISSON, T><<<grid, MNT, 0, s>>>(__VA_ARGS__); break; \
+        case GR_KIND_HAMILTONIAN: k_march<MODE, GR_KIND_HAMILTONIAN, T><<<grid, MNT, 0, s>>>(__VA_ARGS__); break; \
+        case GR_KIND_CMC: k_march<MODE, GR_KIND_CMC, T><<<grid, MNT, 0, s>>>(__VA_ARGS__); break;          \
+        case K_LIN_POISSON: k_march<MODE, K_LIN_POISSON, T><<<grid, MNT, 0, s>>>(__VA_ARGS__); break;      \
+        case K_LIN_HAM: k_march<MODE, K_LIN_HAM, T><<<grid, MNT, 0, s>>>(__VA_ARGS__); break;              \
+        default: k_march<MODE, K_LIN_CMC, T><<<grid, MNT, 0, s>>>(__VA_ARGS__); break;                     \
+        }                                                                                             \
+    } while (0)
+
 void launch_residual_restrict(int kind, hipStream_t s, const double *phi, const double *f, const double *coef,
                               int n, double h, OpConst oc, const double *fbar, const double *fshift,
                               double *phi_c, double *phi0_c, double *rr_c)
 {
+    int zc = 0, grid = 0;
+    if (march_ok(n) && (grid = march_grid(n, 4096, &zc)) > 0) {
+        switch (kind) {
+        case GR_KIND_POISSON:
+            k_march<M_RESTRICT, GR_KIND_POISSON, double><<<grid, MNT, 0, s>>>(
+                phi, f, coef, nullptr, n, zc, 1.0 / (h * h), oc, fbar, fshift, nullptr, phi_c, phi0_c, rr_c, nullptr,
+                nullptr, nullptr);
+            break;
+        case GR_KIND_HAMILTONIAN:
+            k_march<M_RESTRICT, GR_KIND_HAMILTONIAN, double><<<grid, MNT, 0, s>>>(
+                phi, f, coef, nullptr, n, zc, 1.0 / (h * h), oc, fbar, fshift, nullptr, phi_c, phi0_c, rr_c, nullptr,
+                nullptr, nullptr);
+            break;
+        default:
+            k_march<M_RESTRICT, GR_KIND_CMC, double><<<grid, MNT, 0, s>>>(
+                phi, f, coef, nullptr, n, zc, 1.0 / (h * h), oc, fbar, fshift, nullptr, phi_c, phi0_c, rr_c, nullptr,
+                nullptr, nullptr);
+            break;
+        }
+        return;
+    }
     const int m = n / 2;
     GR_DISPATCH_KIND_G(kind, k_residual_restrict, geo3(m, m, m), phi, f, coef, n, 1.0 / (h * h), oc, fbar, fshift,
                        phi_c, phi0_c, rr_c);
@@ -931,9 +1127,15 @@ void launch_residual_restrict(int kind, hipStream_t s, const double *phi, const 
 void launch_lin_residual_restrict_f32(int kind, hipStream_t s, const float *e, const float *b, const float *c1,
                                       const float *c2, int n, double h, OpConst oc, float *b_c, float *e_c)
 {
+    const float inv_h2 = float(1.0 / (h * h));
+    int zc = 0, grid = 0;
+    if (march_ok(n) && (grid = march_grid(n, 4096, &zc)) > 0) {
+        GR_MARCH_KIND(M_RESTRICT_LIN, float, kind, grid, e, b, c1, c2, n, zc, inv_h2, oc, nullptr, nullptr, nullptr,
+                      b_c, e_c, nullptr, nullptr, nullptr, nullptr);
+        return;
+    }
     const int m = n / 2;
     const Geo G = geo3(m, m, m);
-    const float inv_h2 = float(1.0 / (h * h));
     GR_DISPATCH_KT(kind, float, k_lin_residual_restrict, G.grid, G.block, e, b, c1, c2, n, inv_h2, oc, b_c, e_c);
 }
 
@@ -989,6 +1191,23 @@ void launch_ir_residual(int kind, hipStream_t s, const double *phi, const double
                         double h, OpConst oc, const double *fbar, const double *fshift, float *b32, float *a32,
                         float *c32, double *partials)
 {
+    int zc = 0, grid = 0;
+    if (march_ok(n) && (grid = march_grid(n, kReduceBlocks, &zc)) > 0) {
+        const double ih2 = 1.0 / (h * h);
+        if (kind == GR_KIND_POISSON)
+            k_march<M_IR, GR_KIND_POISSON, double><<<grid, MNT, 0, s>>>(phi, f, coef, nullptr, n, zc, ih2, oc, fbar,
+                                                                       fshift, partials, nullptr, nullptr, nullptr,
+                                                                       b32, a32, c32);
+        else if (kind == GR_KIND_HAMILTONIAN)
+            k_march<M_IR, GR_KIND_HAMILTONIAN, double><<<grid, MNT, 0, s>>>(phi, f, coef, nullptr, n, zc, ih2, oc,
+                                                                           fbar, fshift, partials, nullptr, nullptr,
+                                                                           nullptr, b32, a32, c32);
+        else
+            k_march<M_IR, GR_KIND_CMC, double><<<grid, MNT, 0, s>>>(phi, f, coef, nullptr, n, zc, ih2, oc, fbar,
+                                                                   fshift, partials, nullptr, nullptr, nullptr, b32,
+                                                                   a32, c32);
+        return;
+    }
     Geo G;
     G.grid = dim3(kReduceBlocks);
     G.block = dim3(64, 4);
@@ -1035,6 +1254,23 @@ void launch_sum_ham_F(hipStream_t s, const double *psi, const double *f, const d
 void launch_res_norms(int kind, hipStream_t s, const double *phi, const double *f, const double *coef, int n,
                       double h, OpConst oc, const double *fbar, const double *fshift, double *partials)
 {
+    int zc = 0, grid = 0;
+    if (march_ok(n) && (grid = march_grid(n, kReduceBlocks, &zc)) > 0) {
+        const double ih2 = 1.0 / (h * h);
+        if (kind == GR_KIND_POISSON)
+            k_march<M_NORMS, GR_KIND_POISSON, double><<<grid, MNT, 0, s>>>(phi, f, coef, nullptr, n, zc, ih2, oc, fbar,
+                                                                          fshift, partials, nullptr, nullptr,
+                                                                          nullptr, nullptr, nullptr, nullptr);
+        else if (kind == GR_KIND_HAMILTONIAN)
+            k_march<M_NORMS, GR_KIND_HAMILTONIAN, double><<<grid, MNT, 0, s>>>(
+                phi, f, coef, nullptr, n, zc, ih2, oc, fbar, fshift, partials, nullptr, nullptr, nullptr, nullptr,
+                nullptr, nullptr);
+        else
+            k_march<M_NORMS, GR_KIND_CMC, double><<<grid, MNT, 0, s>>>(phi, f, coef, nullptr, n, zc, ih2, oc, fbar,
+                                                                      fshift, partials, nullptr, nullptr, nullptr,
+                                                                      nullptr, nullptr, nullptr);
+        return;
+    }
     Geo G;
     G.grid = dim3(kReduceBlocks);
     G.block = dim3(64, 4);
