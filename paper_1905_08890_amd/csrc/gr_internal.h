@@ -60,7 +60,7 @@ void launch_rb_sweep(int kind, hipStream_t s, double *phi, const double *f, cons
                      double h, OpConst oc, const double *fbar, const double *fshift);
 // fused out-of-place sweep (both colours, one pass); used where fused_sweep_ok
 struct FusedCfg {
-    int min_n = 256;      // smallest level that uses it (smaller levels live in L2/MALL)
+    int min_n = 128;      // smallest level that uses it (smaller levels: one kernel per colour)
     int tile = 1;         // 0: 64x8 tiles, 1: 32x16 tiles
     int xcd_remap = 0;    // 1: XCD-contiguous workgroup order
     int target_wgs = 1024;

@@ -80,7 +80,8 @@ struct gr_grid_s {
     bool bound = false;
     bool fused = true;     // fused tile smoother on large levels
     FusedCfg fcfg;
-    int coarse_n = 16;     // levels with n <= coarse_n run in one single-workgroup launch
+    int coarse_n = 8;      // levels with n <= coarse_n run in one single-workgroup launch
+    int coarse_n32 = 8;    // the same for the FP32 correction cycles
     double stall_ratio = 0.5; // mixed precision: a refinement step that keeps more than this
                               // fraction of the residual counts as stalled (two in a row: FP64)
     size_t ws_bytes = 0;
@@ -439,7 +440,7 @@ int vcycle32(gr_grid g, int lkind, int l, int nu1, int nu2, OpConst oc, bool e_u
     Level &L = g->lev[l];
     Level32 &V = g->lev32[l];
     hipStream_t s = g->stream;
-    if (L.n <= std::max(g->coarse_n, 16) || l == g->nlev - 1) {
+    if (L.n <= g->coarse_n32 || l == g->nlev - 1) {
         if (e_unset) launch_fill_f32(s, V.e, L.N);
         CoarseLevelsT<float> C;
         C.nl = g->nlev - l;
@@ -699,7 +700,8 @@ int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out)
     // smoother), GRMG_FUSED_TILE (0: 64x8, 1: 32x16), GRMG_XCD_REMAP (0/1),
     // GRMG_FUSED_WGS (target workgroups per fused launch), GRMG_FUSED_PF (prefetch
     // depth 1 or 2 planes), GRMG_COARSE_N (levels
-    // at or below this size run the rest of the V-cycle in one workgroup; 0: never),
+    // at or below this size run the rest of the V-cycle in one workgroup; 0: never;
+    // GRMG_COARSE_N32 likewise for the FP32 correction cycles),
     // GRMG_MIXED_STALL (mixed-precision stagnation ratio), GRMG_GRAPH (0: launch
     // every cycle's kernels one by one instead of replaying a captured graph)
     if (const char *e = std::getenv("GRMG_SMOOTHER")) {
@@ -712,6 +714,7 @@ int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out)
     if (const char *e = std::getenv("GRMG_FUSED_WGS")) g->fcfg.target_wgs = std::max(1, std::atoi(e));
     if (const char *e = std::getenv("GRMG_FUSED_PF")) g->fcfg.pf = std::atoi(e) == 2 ? 2 : (std::atoi(e) == 1 ? 1 : 0);
     if (const char *e = std::getenv("GRMG_COARSE_N")) g->coarse_n = std::atoi(e);
+    if (const char *e = std::getenv("GRMG_COARSE_N32")) g->coarse_n32 = std::atoi(e);
     if (const char *e = std::getenv("GRMG_MIXED_STALL")) g->stall_ratio = std::atof(e);
     if (const char *e = std::getenv("GRMG_GRAPH")) g->use_graph = std::atoi(e) != 0;
     if (g->nlev > kMaxLevels) {

@@ -747,7 +747,43 @@ __global__ void __launch_bounds__(CTPB) k_coarse_vcycle(CoarseLevelsT<T> C, int 
             __syncthreads();
         }
     }
-    { // coarsest: sweeps, then remove the mean of the correction
+    if (C.n[L - 1] * C.n[L - 1] * C.n[L - 1] <= 64) {
+        // coarsest level of at most 64 points: one wavefront, one point per lane,
+        // neighbours by lane shuffles (no block barriers between the sweeps)
+        const int i = L - 1, n = C.n[i], N = n * n * n;
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            const bool on = lane < N;
+            const int a = lane % n, b = (lane / n) % n, d = lane / (n * n);
+            const int xp = (int)lin(wrapi(a + 1, n), b, d, n), xm = (int)lin(wrapi(a - 1, n), b, d, n);
+            const int yp = (int)lin(a, wrapi(b + 1, n), d, n), ym = (int)lin(a, wrapi(b - 1, n), d, n);
+            const int zp = (int)lin(a, b, wrapi(d + 1, n), n), zm = (int)lin(a, b, wrapi(d - 1, n), n);
+            const T inv_h2 = T(C.inv_h2[i]);
+            const T Fb = i == 0 ? Fb0 : T(0), fs = i == 0 ? fs0 : T(0);
+            T ph = on ? C.phi[i][lane] : T(0);
+            const T fv = on ? C.f[i][lane] : T(0);
+            const T cv1 = on ? load_c1<KIND>(C.c1[i], lane) : T(0);
+            const T cv2 = on ? load_c2<KIND>(C.c2[i], lane) : T(0);
+            const T old = ph;
+            const int par = (a + b + d) & 1;
+            for (int it = 0; it < kCoarseSweeps; ++it)
+                for (int colour = 0; colour < 2; ++colour) {
+                    const T nbs = __shfl(ph, on ? xp : lane, 64) + __shfl(ph, on ? xm : lane, 64) +
+                                  __shfl(ph, on ? yp : lane, 64) + __shfl(ph, on ? ym : lane, 64) +
+                                  __shfl(ph, on ? zp : lane, 64) + __shfl(ph, on ? zm : lane, 64);
+                    if (on && par == colour) {
+                        T J;
+                        const T Lv = op_point<KIND, T>(ph, nbs, inv_h2, cv1, cv2, oc, Fb, J);
+                        ph = ph - (Lv - (fv - fs)) / J;
+                    }
+                }
+            double dsum = on ? (double)(ph - old) : 0.0;
+            for (int off = 1; off < 64; off <<= 1) dsum += __shfl_xor(dsum, off, 64);
+            ph -= T(dsum / (double)N);
+            if (on) C.phi[i][lane] = ph;
+        }
+        __syncthreads();
+    } else { // coarsest: sweeps, then remove the mean of the correction
         const int i = L - 1, n = C.n[i], N = n * n * n;
         const T inv_h2 = T(C.inv_h2[i]);
         const T Fb = i == 0 ? Fb0 : T(0), fs = i == 0 ? fs0 : T(0);
