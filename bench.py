@@ -49,6 +49,27 @@ def time_sweeps(torch, grmg, g, kind, nsweeps, reps):
     return best * 1e-3  # seconds per sweep
 
 
+def pmc_traffic(n):
+    """HBM bytes per launch of the FP64 Hamiltonian sweep at 256^3 from the
+    committed counter summary, scaled by its copy-kernel calibration; None if
+    the smoother source changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "rb_fused_hamiltonian_fp64_256_pmc.md")
+    src = os.path.join(ROOT, "paper_1905_08890_amd", "csrc", "stencil.hip")
+    if n != 256 or not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if vals.get("stencil.hip sha256") != sha:
+        return None
+    return int(vals["traffic bytes per launch"])
+
+
 def cpu_baseline(n, pos, u, mass, cycles):
     """Oracle timed on the host on a bounded sample: one V(2,2) cycle of each
     equation kind at n^3 plus the CIC deposit, scaled by the GPU run's
@@ -102,6 +123,66 @@ def smoother_only(torch, grmg, n):
                       "poisson_GBps": round(SWEEP_BYTES["poisson"] * N / t_poi / 1e9, 1)}), flush=True)
 
 
+def c1_workload(torch, grmg, synth):
+    """The 32^3 Hamiltonian-only solve (s0 = 1 + k^-2 GRF, sigma 0.1, seed 0;
+    V(2,2) from Psi = 0 to 1e-10): launch-latency bound on the GPU."""
+    n = 32
+    g = grmg.Grid(n, a=1.0, omega_m=synth.OMEGA_M, c_tilde=synth.C_TILDE, device="cuda:0")
+    src = synth.hamiltonian_only_sources(n, 0, 0.1)
+    for name, x in zip(("s0", "sx", "sy", "sz", "sm"), src):
+        g.set_field(name, x)
+    times = []
+    for _ in range(6):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = g.solve_constraints(field_mask=1 << grmg.PSI, rtol=1e-10)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    cyc = rep["cycles"][grmg.PSI]
+    g.close()
+    return {"workload": "32^3 Hamiltonian only, s0 = 1 + GRF(k^-2, sigma 0.1, seed 0), FP64, rtol 1e-10",
+            "ms": round(sorted(times[1:])[len(times[1:]) // 2] * 1e3, 3), "cycles": cyc,
+            "factor_per_cycle": round(rep["rel_res"][grmg.PSI] ** (1.0 / max(cyc, 1)), 4)}, src
+
+
+def c1_oracle_seconds(src, cycles):
+    import numpy as np
+
+    import oracle as O
+    from paper_1905_08890_amd import synth
+
+    f = 1.5 * synth.OMEGA_M * (src[0] - 1.0)
+    t0 = time.perf_counter()
+    O.solve_equation(O.HAMILTONIAN, np.zeros_like(f), f, np.zeros_like(f),
+                     prm=O.params(1.0, synth.OMEGA_M, synth.C_TILDE), rtol=0, max_cycles=cycles)
+    return time.perf_counter() - t0
+
+
+def bench_learned(torch, grmg, synth, n):
+    """Held-out trajectory (seed 2000, amplitudes 1.0, 1.25, 1.5 cells): per
+    step, time to 1e-10 from (i) zero guess FP64, (ii) previous step FP64,
+    (iii) previous step mixed, (iv) previous step + network increment, mixed,
+    judged per field by the FP64 residual (network time included), and the
+    same with untrained weights (control)."""
+    from paper_1905_08890_amd import learned
+
+    path = os.path.join(ROOT, "paper_1905_08890_amd", "weights", "unet_level1_zeldovich256.npz")
+    gs = learned.LearnedGuess(path, n, torch)
+    ctl = learned.LearnedGuess(path, n, torch)
+    ctl.net.init(4242)
+    res = learned.evaluate(gs, n, [2000], 3, 1.0, torch, control=ctl, exact=False)
+    summ = learned.summarise(res)
+    out = {"workload": f"{n}^3 Zel'dovich trajectory, held-out seed 2000, 2 steps after the first; "
+                       f"network on level 1 ({n // 2}^3), weights {os.path.basename(path)}"}
+    for k, v in summ.items():
+        out[k] = {"ms": round(v["ms"], 3), "cycles": v["cycles"], "fallback_fields": v["fallback"]}
+    z, l = summ["zero_fp64"]["ms"], summ["learned_mixed"]["ms"]
+    out["speedup_learned_mixed_vs_zero_fp64"] = round(z / l, 3)
+    out["speedup_learned_mixed_vs_prev_fp64"] = round(summ["prev_fp64"]["ms"] / l, 3)
+    out["speedup_prev_mixed_vs_zero_fp64"] = round(z / summ["prev_mixed"]["ms"], 3)
+    return out
+
+
 def bench_batch(torch, grmg, synth, steps):
     """96 periodic boxes with sides drawn from {32,48,64,96,128} (seeds
     100..195), s0 = 1 + delta with sigma log-uniform in [0.05, 1], longitudinal
@@ -145,6 +226,7 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 96-box batched workload")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess trajectory")
     ap.add_argument("--batch-only", action="store_true", help="only the 96-box batched workload")
     ap.add_argument("--smoother-only", action="store_true",
                     help="only the finest-level sweeps and a copy of known size (for hardware counters)")
@@ -236,6 +318,16 @@ def main():
                      "frac": round(gbps_ham / HBM_PEAK_GBPS, 4), "traffic": None,
                      "kernel": "red-black Newton sweep, Hamiltonian, FP64, finest level (32 B/point/sweep)"},
     }
+    traffic = pmc_traffic(n)
+    if traffic is not None:
+        out["roofline"]["traffic"] = traffic
+    g.close()
+    del d_pos, d_u
+    c1, c1_src = c1_workload(torch, grmg, synth)
+    out["c1"] = c1
+    if not args.no_learned and n == 256:
+        log("learned guess: held-out trajectory")
+        out["learned"] = bench_learned(torch, grmg, synth, n)
     if not args.no_batch:
         out["batch"] = bench_batch(torch, grmg, synth, max(1, min(args.steps, 2)))
     if not args.no_cpu_baseline:
@@ -243,7 +335,8 @@ def main():
         est, sample_s = cpu_baseline(n, pos, u, mass, cycles)
         out["cpu_baseline"] = {"value": round(est * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
                                "sample": f"CIC + one V(2,2) cycle of each equation kind at {n}^3 "
-                                         f"({sample_s:.1f} s measured), scaled by the GPU per-field cycle counts"}
+                                         f"({sample_s:.1f} s measured), scaled by the GPU per-field cycle counts",
+                               "c1_oracle_ms": round(c1_oracle_seconds(c1_src, c1["cycles"]) * 1e3, 1)}
     print(json.dumps(out), flush=True)
 
 

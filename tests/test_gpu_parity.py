@@ -255,6 +255,25 @@ def test_all_fields_same_cycles(n, cycles):
         assert maxrel(g.get_field(name), ref) < 1e-12, name
 
 
+@pytest.mark.timeout(300)
+def test_c2_workload_128_all_fields():
+    """128^3 particles (Zel'dovich seed 1, 0.3 cells), CIC with Psi^n = 0, all ten
+    fields from zero guesses to 1e-10 in FP64: the oracle, run for the GPU's
+    per-field cycle counts, agrees to 1e-12 (about a minute of oracle time)."""
+    n = 128
+    print("[gpu] C2 workload n=128", flush=True)
+    pos, u, mass = _sources_from_particles(n, 1, 0.3)
+    g = grid(n, DEFAULT)
+    g.deposit_sources(pos, u, mass)
+    rep = g.solve_constraints(rtol=1e-10)
+    assert rep["status"] == 0 and max(rep["rel_res"]) <= 1e-10
+    p = O.params(**DEFAULT)
+    src = O.cic_deposit(n, pos, u, mass, prm=p)
+    fields, st, cyc, rel, AA = O.solve_all(*src, prm=p, rtol=0, max_cycles=rep["cycles"])
+    for name in O.FIELDS:
+        assert maxrel(g.get_field(name), fields[name]) < 1e-12, name
+
+
 def test_hamiltonian_only_32_workload():
     """32^3, s0 = 1 + k^-2 GRF (sigma 0.1, seed 0), A_ij = 0, Psi from 0 by
     V(2,2) to 1e-10: GPU equals the oracle at the same cycle count."""
