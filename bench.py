@@ -255,6 +255,10 @@ def main():
     d_pos = torch.as_tensor(pos, device=dev)
     d_u = torch.as_tensor(u, device=dev)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tune_report = grmg.autotune(g.handle)
+    tune_s = time.perf_counter() - t0
+    log(f"autotune ({tune_s:.2f} s):\n{tune_report}")
 
     def step(precision):
         grmg.deposit_sources(g.handle, d_pos, d_u, mass)
@@ -312,6 +316,7 @@ def main():
         "refinement_steps_mixed": rep["cycles"],
         "mixed_fallback_fields": rep["fallback"],
         "points_cycles_per_s_fp64": round(N * sum(rep64["cycles"]) / dt64, 1),
+        "autotune": {"seconds": round(tune_s, 3), "choices": tune_report.strip().splitlines()},
         "smoother": {"hamiltonian_us_per_sweep": round(t_ham * 1e6, 2), "hamiltonian_GBps": round(gbps_ham, 1),
                      "poisson_us_per_sweep": round(t_poi * 1e6, 2), "poisson_GBps": round(gbps_poi, 1)},
         "roofline": {"bound": "hbm", "achieved": round(gbps_ham, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",

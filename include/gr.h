@@ -213,6 +213,17 @@ int gr_features(gr_grid g, int level, int count, const int *fields, const double
 int gr_set_guess(gr_grid g, int level, int count, const int *fields, const double *scale, const float *d_src,
                  int flags);
 
+/* Autotuner of the fused red-black sweep (sec. 4.3.1 smoother): for every
+ * level that uses it and each of the six operator kinds (FP64 Poisson,
+ * Hamiltonian, CMC; their FP32 linearised forms), times every candidate launch
+ * configuration (tile 32x16 or 64x8, 512/1024/2048 workgroups, operand
+ * prefetch 1 or 2 planes) on workspace scratch and keeps the fastest for this
+ * grid; results are cached per process by (n, kind).  Results of the sweeps
+ * do not depend on the configuration.  Writes one line per (level, kind) to
+ * report (may be NULL).  Must not overlap a deposit on the same grid (it uses
+ * the deposit's scratch).  Errors: GR_ESTATE if unbound, GR_EDEVICE. */
+int gr_autotune(gr_grid g, char *report, size_t report_bytes);
+
 /* Low level, for step-by-step comparisons: `nsweeps` red-black Newton sweeps
  * of the finest level (even colour first) on field slot `field` with source
  * GR_RHS, coefficient GR_COEF and frozen scalars Fbar (Hamiltonian

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "gr_internal.h"
@@ -80,6 +81,8 @@ struct gr_grid_s {
     bool bound = false;
     bool fused = true;     // fused tile smoother on large levels
     FusedCfg fcfg;
+    FusedCfg tuned[kMaxLevels][6]; // per level and kind (0-2 FP64, 3-5 FP32), set by gr_autotune
+    bool tuned_ok[kMaxLevels][6]{};
     int coarse_n = 8;      // levels with n <= coarse_n run in one single-workgroup launch
     int coarse_n32 = 8;    // the same for the FP32 correction cycles
     double stall_ratio = 0.5; // mixed precision: a refinement step that keeps more than this
@@ -255,6 +258,12 @@ struct EqCtx {
 const double *fbar_ptr(gr_grid g, int l) { return g->scal + (l == 0 ? S_FBAR : S_ZERO); }
 const double *fshift_ptr(gr_grid g, int l) { return g->scal + (l == 0 ? S_FSHIFT : S_ZERO); }
 
+// launch configuration of the fused sweep on level l for a kind (0..5)
+const FusedCfg &fused_cfg(gr_grid g, int l, int kind)
+{
+    return g->tuned_ok[l][kind] ? g->tuned[l][kind] : g->fcfg;
+}
+
 // nsweeps red-black sweeps of level l on L.phi.  The fused kernel works out
 // of place, alternating between L.phi and L.tmp; an odd count ends with a copy
 // back so that the iterate always ends in L.phi.
@@ -271,7 +280,8 @@ int smooth(gr_grid g, const EqCtx &E, int l, int nsweeps)
     }
     double *a = L.phi, *b = L.tmp;
     for (int it = 0; it < nsweeps; ++it) {
-        launch_rb_fused(E.kind, s, a, b, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l), g->fcfg);
+        launch_rb_fused(E.kind, s, a, b, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l),
+                        fused_cfg(g, l, E.kind));
         double *t = a;
         a = b;
         b = t;
@@ -421,7 +431,7 @@ int smooth32(gr_grid g, int lkind, int l, int nsweeps, OpConst oc, bool e_is_zer
     float *a = V.e, *b = V.tmp;
     for (int it = 0; it < nsweeps; ++it) {
         launch_rb_fused_f32(lkind, s, (it == 0 && e_is_zero) ? nullptr : a, b, V.b, V.c, V.a, L.n, L.h, oc, zero,
-                            g->fcfg);
+                            fused_cfg(g, l, lkind));
         float *t = a;
         a = b;
         b = t;
@@ -662,6 +672,16 @@ double *slot_ptr(gr_grid g, int field)
 } // namespace
 
 // ===================================================================== ABI
+
+namespace {
+struct TuneEntry {
+    int n, kind;
+    FusedCfg cfg;
+    float us;
+};
+std::vector<TuneEntry> g_tune_cache;
+std::mutex g_tune_mu;
+} // namespace
 
 extern "C" {
 
@@ -1002,6 +1022,98 @@ int gr_set_guess(gr_grid g, int level, int count, const int *fields, const doubl
     }
     LAUNCHCHK();
     return GR_OK;
+}
+
+// Autotuner of the fused sweep: for every fused level and kind, time each
+// candidate (tile shape x workgroup target x prefetch depth) on scratch
+// arrays and keep the fastest.  Results are cached per process by (n, kind)
+// so later grids of the same size reuse them.  The sweep's result does not
+// depend on the configuration (same per-point arithmetic, exact red-black
+// order), only its speed does.
+
+int gr_autotune(gr_grid g, char *report, size_t report_bytes)
+{
+    CHK(check_bound(g));
+    WorkScope ws(g);
+    if (!ws.ok) return fail(GR_EDEVICE, "cannot join the work stream");
+    hipStream_t s = g->stream;
+    std::string rep;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const OpConst oc = g->oc();
+    const double *zero = g->scal + S_ZERO;
+    int st = GR_OK;
+    for (int l = 0; l < g->nlev && st == GR_OK; ++l) {
+        const Level &L = g->lev[l];
+        if (!g->fused || !fused_sweep_ok(L.n, g->fcfg.min_n)) continue;
+        const long M = L.N;
+        double *d = static_cast<double *>(g->cic); // scratch: 8 n^3 doubles
+        float *fl = static_cast<float *>(g->cic);
+        for (int kind = 0; kind < 6 && st == GR_OK; ++kind) {
+            FusedCfg best = g->fcfg;
+            float best_us = -1.f;
+            {
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                for (auto &e : g_tune_cache)
+                    if (e.n == L.n && e.kind == kind) {
+                        best = e.cfg;
+                        best_us = e.us;
+                    }
+            }
+            if (best_us < 0.f) {
+                for (int tile = 0; tile < 2; ++tile)
+                    for (int wgs : {512, 1024, 2048})
+                        for (int pf = 1; pf <= 2; ++pf) {
+                            FusedCfg c = g->fcfg;
+                            c.tile = tile;
+                            c.target_wgs = wgs;
+                            c.pf = pf;
+                            auto sweep = [&]() {
+                                if (kind < 3)
+                                    launch_rb_fused(kind, s, d, d + M, d + 2 * M, d + 3 * M, L.n, L.h, oc, zero,
+                                                    zero, c);
+                                else
+                                    launch_rb_fused_f32(kind, s, fl, fl + M, fl + 2 * M, fl + 3 * M, fl + 4 * M, L.n,
+                                                        L.h, oc, zero, c);
+                            };
+                            sweep();
+                            (void)hipEventRecord(e0, s);
+                            for (int r = 0; r < 4; ++r) sweep();
+                            (void)hipEventRecord(e1, s);
+                            hipError_t he = hipEventSynchronize(e1);
+                            if (he != hipSuccess) {
+                                st = fail(GR_EDEVICE, "autotune: %s", hipGetErrorString(he));
+                                break;
+                            }
+                            float ms = 0.f;
+                            (void)hipEventElapsedTime(&ms, e0, e1);
+                            const float us = ms * 1e3f / 4.f;
+                            if (best_us < 0.f || us < best_us) {
+                                best_us = us;
+                                best = c;
+                            }
+                        }
+                if (st != GR_OK) break;
+                std::lock_guard<std::mutex> lk(g_tune_mu);
+                g_tune_cache.push_back({L.n, kind, best, best_us});
+            }
+            g->tuned[l][kind] = best;
+            g->tuned_ok[l][kind] = true;
+            char line[160];
+            std::snprintf(line, sizeof line, "n=%d kind=%d tile=%s wgs=%d pf=%d us=%.2f\n", L.n, kind,
+                          best.tile ? "32x16" : "64x8", best.target_wgs, best.pf, best_us);
+            rep += line;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    LAUNCHCHK();
+    g->drop_graphs(); // captured cycles hold the old launch shapes
+    if (report && report_bytes) {
+        std::snprintf(report, report_bytes, "%s", rep.c_str());
+    }
+    return st;
 }
 
 int gr_debug_sweep(gr_grid g, int kind, int field, double Fbar, double fshift, int nsweeps)

@@ -98,7 +98,7 @@ def test_features_and_set_guess_reject_bad_arguments():
         grmg.set_guess(g.handle, 0, [grmg.S0], [1.0], out, 1)
     with pytest.raises(grmg.GrError):
         grmg.set_guess(g.handle, 0, [0], [1.0], out, 4)
-    assert lib.gr_features(g.handle, 0, 1, None, None, None, None) == grmg.EINVAL
+    assert lib.gr_features(g.handle, 0, 1, None, None, None, None, 0) == grmg.EINVAL
 
 
 # ------------------------------------------------ checked guess vs fallback
