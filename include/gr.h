@@ -224,6 +224,15 @@ int gr_set_guess(gr_grid g, int level, int count, const int *fields, const doubl
  * the deposit's scratch).  Errors: GR_ESTATE if unbound, GR_EDEVICE. */
 int gr_autotune(gr_grid g, char *report, size_t report_bytes);
 
+/* Timing of the finest-level fused sweeps (measurement support): with
+ * enable != 0, later solves bracket every finest-level fused sweep launch with
+ * HIP events on the solve's stream (cycle graphs are off meanwhile);
+ * enable == 0 waits for those events, writes the summed milliseconds and the
+ * launch counts per kind (0-2 FP64 Poisson, Hamiltonian, CMC; 3-5 their FP32
+ * linearised forms) to ms_sum[6] / count[6] (host arrays) and restores graph
+ * replay.  Errors: GR_ESTATE if unbound, GR_EINVAL for null outputs. */
+int gr_sweep_timing(gr_grid g, int enable, double *ms_sum, int *count);
+
 /* Low level, for step-by-step comparisons: `nsweeps` red-black Newton sweeps
  * of the finest level (even colour first) on field slot `field` with source
  * GR_RHS, coefficient GR_COEF and frozen scalars Fbar (Hamiltonian

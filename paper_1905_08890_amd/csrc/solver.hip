@@ -85,6 +85,7 @@ struct gr_grid_s {
     bool tuned_ok[kMaxLevels][6]{};
     int coarse_n = 8;      // levels with n <= coarse_n run in one single-workgroup launch
     int coarse_n32 = 8;    // the same for the FP32 correction cycles
+    int skew = 0;          // workspace array skew in bytes (see layout)
     double stall_ratio = 0.5; // mixed precision: a refinement step that keeps more than this
                               // fraction of the residual counts as stalled (two in a row: FP64)
     size_t ws_bytes = 0;
@@ -100,6 +101,14 @@ struct gr_grid_s {
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
+    // optional timing of finest-level fused sweeps (gr_sweep_timing)
+    bool timing = false, graph_saved = true;
+    struct SweepEv {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<SweepEv> sweep_ev;
+    std::vector<hipEvent_t> ev_free;
 
     void drop_graphs()
     {
@@ -109,6 +118,11 @@ struct gr_grid_s {
     ~gr_grid_s()
     {
         drop_graphs();
+        for (auto &e : sweep_ev) {
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+        for (auto e : ev_free) (void)hipEventDestroy(e);
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
         if (work) (void)hipStreamDestroy(work);
@@ -140,9 +154,13 @@ int num_levels(int n)
 size_t layout(gr_grid g, char *base)
 {
     size_t off = 0;
+    int count = 0;
+    // Arrays of one size would otherwise start at identical address bits modulo
+    // their (power-of-two) length; a rotating skew of `skew` bytes per array
+    // keeps the streams of one kernel from hitting the same HBM channels in step.
     auto take = [&](size_t bytes) -> double * {
         double *p = base ? reinterpret_cast<double *>(base + off) : nullptr;
-        off += align_up(bytes);
+        off += align_up(bytes) + align_up((size_t)g->skew * (size_t)(count++ % 8));
         return p;
     };
     const size_t fb = sizeof(double) * (size_t)g->N();
@@ -264,6 +282,37 @@ const FusedCfg &fused_cfg(gr_grid g, int l, int kind)
     return g->tuned_ok[l][kind] ? g->tuned[l][kind] : g->fcfg;
 }
 
+hipEvent_t pooled_event(gr_grid g)
+{
+    if (!g->ev_free.empty()) {
+        hipEvent_t e = g->ev_free.back();
+        g->ev_free.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs one finest-level fused sweep launch, bracketed by events when timing.
+template <class F>
+void timed_sweep(gr_grid g, int l, int kind, F launch)
+{
+    if (!g->timing || l != 0) {
+        launch();
+        return;
+    }
+    hipEvent_t a = pooled_event(g), b = pooled_event(g);
+    if (!a || !b) {
+        launch();
+        return;
+    }
+    (void)hipEventRecord(a, g->stream);
+    launch();
+    (void)hipEventRecord(b, g->stream);
+    g->sweep_ev.push_back({kind, a, b});
+}
+
 // nsweeps red-black sweeps of level l on L.phi.  The fused kernel works out
 // of place, alternating between L.phi and L.tmp; an odd count ends with a copy
 // back so that the iterate always ends in L.phi.
@@ -280,8 +329,10 @@ int smooth(gr_grid g, const EqCtx &E, int l, int nsweeps)
     }
     double *a = L.phi, *b = L.tmp;
     for (int it = 0; it < nsweeps; ++it) {
-        launch_rb_fused(E.kind, s, a, b, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l),
-                        fused_cfg(g, l, E.kind));
+        timed_sweep(g, l, E.kind, [&] {
+            launch_rb_fused(E.kind, s, a, b, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l),
+                            fused_cfg(g, l, E.kind));
+        });
         double *t = a;
         a = b;
         b = t;
@@ -430,8 +481,10 @@ int smooth32(gr_grid g, int lkind, int l, int nsweeps, OpConst oc, bool e_is_zer
     if (e_is_zero && nsweeps == 0) launch_fill_f32(s, V.e, L.N);
     float *a = V.e, *b = V.tmp;
     for (int it = 0; it < nsweeps; ++it) {
-        launch_rb_fused_f32(lkind, s, (it == 0 && e_is_zero) ? nullptr : a, b, V.b, V.c, V.a, L.n, L.h, oc, zero,
-                            fused_cfg(g, l, lkind));
+        timed_sweep(g, l, lkind, [&] {
+            launch_rb_fused_f32(lkind, s, (it == 0 && e_is_zero) ? nullptr : a, b, V.b, V.c, V.a, L.n, L.h, oc, zero,
+                                fused_cfg(g, l, lkind));
+        });
         float *t = a;
         a = b;
         b = t;
@@ -737,6 +790,7 @@ int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out)
     if (const char *e = std::getenv("GRMG_COARSE_N32")) g->coarse_n32 = std::atoi(e);
     if (const char *e = std::getenv("GRMG_MIXED_STALL")) g->stall_ratio = std::atof(e);
     if (const char *e = std::getenv("GRMG_GRAPH")) g->use_graph = std::atoi(e) != 0;
+    if (const char *e = std::getenv("GRMG_SKEW")) g->skew = std::max(0, std::atoi(e));
     if (g->nlev > kMaxLevels) {
         delete g;
         return fail(GR_EINVAL, "too many levels");
@@ -1114,6 +1168,40 @@ int gr_autotune(gr_grid g, char *report, size_t report_bytes)
         std::snprintf(report, report_bytes, "%s", rep.c_str());
     }
     return st;
+}
+
+int gr_sweep_timing(gr_grid g, int enable, double *ms_sum, int *count)
+{
+    CHK(check_bound(g));
+    if (enable) {
+        if (!g->timing) g->graph_saved = g->use_graph;
+        for (auto &e : g->sweep_ev) {
+            g->ev_free.push_back(e.a);
+            g->ev_free.push_back(e.b);
+        }
+        g->sweep_ev.clear();
+        g->timing = true;
+        g->use_graph = false; // launches bracketed by events are issued one by one
+        return GR_OK;
+    }
+    if (!ms_sum || !count) return fail(GR_EINVAL, "null output");
+    for (int k = 0; k < 6; ++k) {
+        ms_sum[k] = 0.0;
+        count[k] = 0;
+    }
+    for (auto &e : g->sweep_ev) {
+        HIPCHK(hipEventSynchronize(e.b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e.a, e.b));
+        ms_sum[e.kind] += ms;
+        count[e.kind] += 1;
+        g->ev_free.push_back(e.a);
+        g->ev_free.push_back(e.b);
+    }
+    g->sweep_ev.clear();
+    if (g->timing) g->use_graph = g->graph_saved;
+    g->timing = false;
+    return GR_OK;
 }
 
 int gr_debug_sweep(gr_grid g, int kind, int field, double Fbar, double fshift, int nsweeps)

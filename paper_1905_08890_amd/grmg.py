@@ -32,7 +32,7 @@ FIELD_IDS.update(dict(s0=S0, sx=SX, sy=SY, sz=SZ, sm=SM, AA=AA, Phi=PHI, alpha=A
 
 EXPORTS = ("gr_default_opts", "gr_create_grid", "gr_workspace_bytes", "gr_bind", "gr_deposit_sources",
            "gr_set_field", "gr_get_field", "gr_solve_constraints", "gr_solve_equation", "gr_debug_sweep",
-           "gr_debug_residual", "gr_destroy_grid", "gr_last_error", "gr_features", "gr_set_guess", "gr_autotune", "gr_create_batch", "gr_batch_workspace_bytes",
+           "gr_debug_residual", "gr_destroy_grid", "gr_last_error", "gr_features", "gr_set_guess", "gr_autotune", "gr_sweep_timing", "gr_create_batch", "gr_batch_workspace_bytes",
            "gr_batch_bind", "gr_batch_set_field", "gr_batch_get_field", "gr_batch_solve", "gr_destroy_batch",
            "gr_batch_last_error", "gr_unet_create", "gr_unet_workspace_bytes", "gr_unet_param_count", "gr_unet_bind",
            "gr_unet_init", "gr_unet_set_params", "gr_unet_get_params", "gr_unet_forward", "gr_unet_loss_grad",
@@ -101,6 +101,7 @@ def load_library(path: str = LIB_PATH):
         "gr_features": [vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double), vp,
                         C.c_int],
         "gr_autotune": [vp, C.c_char_p, C.c_size_t],
+        "gr_sweep_timing": [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)],
         "gr_set_guess": [vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), vp, C.c_int],
         "gr_create_batch": [C.POINTER(GrGridDesc), C.c_int, C.POINTER(GrParams), C.POINTER(vp)],
         "gr_batch_workspace_bytes": [vp, C.POINTER(C.c_size_t)],
@@ -239,6 +240,17 @@ def autotune(g: int) -> str:
     buf = C.create_string_buffer(8192)
     _check(load_library().gr_autotune(g, buf, len(buf)))
     return buf.value.decode()
+
+
+def sweep_timing(g: int, enable: bool):
+    """Start (enable=True) or stop timing of finest-level fused sweeps; on stop
+    returns {kind: (launches, mean ms)}."""
+    ms = (C.c_double * 6)()
+    cnt = (C.c_int * 6)()
+    _check(load_library().gr_sweep_timing(g, 1 if enable else 0, ms, cnt))
+    if enable:
+        return None
+    return {k: (cnt[k], ms[k] / cnt[k]) for k in range(6) if cnt[k] > 0}
 
 
 def destroy_grid(g: int) -> None:
