@@ -382,7 +382,10 @@ int vcycle(gr_grid g, const EqCtx &E, int l)
     launch_coarse_rhs(E.kind, s, C.phi, C.coef, C.tmp, C.n, C.h, E.oc, C.f);
     LAUNCHCHK();
     CHK(vcycle(g, E, l + 1));
-    launch_prolong_correct(s, L.phi, L.n, C.phi, C.phi0);
+    // coarse correction e = phi^H - R phi (into C.tmp, free once the coarse
+    // source is built), then phi += P e: one coarse array per fine point
+    launch_sub_arrays(s, C.tmp, C.phi, C.phi0, C.N);
+    launch_prolong_add_f64(s, L.phi, L.n, C.tmp);
     LAUNCHCHK();
     return smooth(g, E, l, E.nu2);
 }

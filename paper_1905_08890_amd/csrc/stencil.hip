@@ -697,13 +697,11 @@ __device__ double cv_block_sum(double v)
 }
 
 template <int KIND, typename T>
-__global__ void __launch_bounds__(CTPB) k_coarse_vcycle(CoarseLevelsT<T> C, int nu1, int nu2, OpConst oc,
-                                                        const double *__restrict__ fbar0,
-                                                        const double *__restrict__ fshift0)
+__device__ void coarse_vcycle_body(const CoarseLevelsT<T> &C, int nu1, int nu2, OpConst oc, const T Fb0,
+                                   const T fs0) // frozen scalars of C's first level (zero unless the finest)
 {
     constexpr bool LIN = KIND >= K_LIN_POISSON;
     const int L = C.nl;
-    const T Fb0 = T(*fbar0), fs0 = T(*fshift0); // frozen scalars of C's first level (zero unless the finest)
     for (int i = 0; i < L - 1; ++i) {
         const int n = C.n[i], m = n >> 1;
         const T inv_h2 = T(C.inv_h2[i]);
@@ -819,6 +817,82 @@ __global__ void __launch_bounds__(CTPB) k_coarse_vcycle(CoarseLevelsT<T> C, int 
         __syncthreads();
         for (int it = 0; it < nu2; ++it) cv_sweep<KIND, T>(C.phi[i], C.f[i], C.c1[i], C.c2[i], n, inv_h2, oc, Fb, fs);
     }
+}
+
+template <int KIND, typename T>
+__global__ void __launch_bounds__(CTPB) k_coarse_vcycle(CoarseLevelsT<T> C, int nu1, int nu2, OpConst oc,
+                                                        const double *__restrict__ fbar0,
+                                                        const double *__restrict__ fshift0)
+{
+    coarse_vcycle_body<KIND, T>(C, nu1, nu2, oc, T(*fbar0), T(*fshift0));
+}
+
+// The same cycle with every level held in LDS (levels up to 16^3 fit): the
+// first level's iterate, source and all levels' coefficients are copied in,
+// the first level's iterate is copied back; barriers then cost LDS latency
+// instead of L2 round trips.
+constexpr size_t kCoarseLdsBytes = 150 * 1024;
+
+template <int KIND, typename T>
+__host__ __device__ size_t coarse_lds_layout(const CoarseLevelsT<T> &G, CoarseLevelsT<T> *S, T *base)
+{
+    constexpr bool LIN = KIND >= K_LIN_POISSON;
+    constexpr int NC = kNumCoef<KIND>();
+    size_t off = 0;
+    auto take = [&](long count) -> T * {
+        T *p = base ? base + off : nullptr;
+        off += (size_t)count;
+        return p;
+    };
+    for (int i = 0; i < G.nl; ++i) {
+        const long N = (long)G.n[i] * G.n[i] * G.n[i];
+        T *phi = take(N);
+        T *phi0 = (i >= 1 && !LIN) ? take(N) : nullptr;
+        T *f = take(N);
+        T *c1 = NC >= 1 ? take(N) : nullptr;
+        T *c2 = NC >= 2 ? take(N) : nullptr;
+        T *tmp = (i >= 1 || G.nl == 1) ? take(N) : nullptr;
+        if (S) {
+            S->n[i] = G.n[i];
+            S->inv_h2[i] = G.inv_h2[i];
+            S->phi[i] = phi;
+            S->phi0[i] = phi0;
+            S->f[i] = f;
+            S->c1[i] = c1;
+            S->c2[i] = c2;
+            S->tmp[i] = tmp;
+        }
+    }
+    if (S) S->nl = G.nl;
+    return off * sizeof(T);
+}
+
+template <int KIND, typename T>
+__global__ void __launch_bounds__(CTPB) k_coarse_vcycle_lds(CoarseLevelsT<T> G, int nu1, int nu2, OpConst oc,
+                                                            const double *__restrict__ fbar0,
+                                                            const double *__restrict__ fshift0)
+{
+    constexpr int NC = kNumCoef<KIND>();
+    __shared__ T lds[kCoarseLdsBytes / sizeof(T)];
+    __shared__ CoarseLevelsT<T> S; // level table, read by every thread (kept out of private memory)
+    if (threadIdx.x == 0) coarse_lds_layout<KIND, T>(G, &S, lds);
+    __syncthreads();
+    const long N0 = (long)G.n[0] * G.n[0] * G.n[0];
+    for (long q = threadIdx.x; q < N0; q += CTPB) {
+        S.phi[0][q] = G.phi[0][q];
+        S.f[0][q] = G.f[0][q];
+    }
+    for (int i = 0; i < G.nl; ++i) {
+        const long N = (long)G.n[i] * G.n[i] * G.n[i];
+        for (long q = threadIdx.x; q < N; q += CTPB) {
+            if (NC >= 1) S.c1[i][q] = G.c1[i][q];
+            if (NC >= 2) S.c2[i][q] = G.c2[i][q];
+        }
+    }
+    __syncthreads();
+    coarse_vcycle_body<KIND, T>(S, nu1, nu2, oc, T(*fbar0), T(*fshift0));
+    __syncthreads();
+    for (long q = threadIdx.x; q < N0; q += CTPB) G.phi[0][q] = S.phi[0][q];
 }
 
 // ------------------------------------------------ mixed-precision outer steps
@@ -939,6 +1013,13 @@ __global__ void k_f32_scaled_to_f64(double *__restrict__ d, const float *__restr
 {
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < N) d[p] = (double)s[p] * sc;
+}
+
+__global__ void k_sub_arrays(double *__restrict__ d, const double *__restrict__ a, const double *__restrict__ b,
+                             long N)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < N) d[p] = a[p] - b[p];
 }
 
 __global__ void k_axpy(double *__restrict__ y, const double *__restrict__ x, long N)
@@ -1193,6 +1274,17 @@ void launch_prolong_correct(hipStream_t s, double *phi_f, int n, const double *p
     k_prolong_correct<double, true><<<G.grid, G.block, 0, s>>>(phi_f, n, phi_c, phi0_c);
 }
 
+void launch_prolong_add_f64(hipStream_t s, double *phi_f, int n, const double *e_c)
+{
+    const Geo G = geo3(n / 2, n / 2, n / 2);
+    k_prolong_correct<double, false><<<G.grid, G.block, 0, s>>>(phi_f, n, e_c, nullptr);
+}
+
+void launch_sub_arrays(hipStream_t s, double *d, const double *a, const double *b, long N)
+{
+    if (N > 0) k_sub_arrays<<<blocks_for(N), TPB, 0, s>>>(d, a, b, N);
+}
+
 void launch_prolong_add_f32(hipStream_t s, float *e_f, int n, const float *e_c)
 {
     const Geo G = geo3(n / 2, n / 2, n / 2);
@@ -1211,15 +1303,43 @@ void launch_restrict_f32(hipStream_t s, const float *fine, int n, float *coarse)
     k_restrict<float><<<G.grid, G.block, 0, s>>>(fine, n, coarse);
 }
 
+template <typename T>
+static bool coarse_lds_fits(int kind, const CoarseLevelsT<T> &C)
+{
+    static const bool on = [] {
+        const char *e = std::getenv("GRMG_COARSE_LDS");
+        return !(e && std::atoi(e) == 0);
+    }();
+    if (!on) return false;
+    size_t b = 0;
+    switch (kind) {
+    case GR_KIND_POISSON: b = coarse_lds_layout<GR_KIND_POISSON, T>(C, nullptr, nullptr); break;
+    case GR_KIND_HAMILTONIAN: b = coarse_lds_layout<GR_KIND_HAMILTONIAN, T>(C, nullptr, nullptr); break;
+    case GR_KIND_CMC: b = coarse_lds_layout<GR_KIND_CMC, T>(C, nullptr, nullptr); break;
+    case K_LIN_POISSON: b = coarse_lds_layout<K_LIN_POISSON, T>(C, nullptr, nullptr); break;
+    case K_LIN_HAM: b = coarse_lds_layout<K_LIN_HAM, T>(C, nullptr, nullptr); break;
+    default: b = coarse_lds_layout<K_LIN_CMC, T>(C, nullptr, nullptr); break;
+    }
+    return b <= kCoarseLdsBytes;
+}
+
 void launch_coarse_vcycle(int kind, hipStream_t s, const CoarseLevelsT<double> &C, int nu1, int nu2, OpConst oc,
                           const double *fbar0, const double *fshift0)
 {
+    if (coarse_lds_fits<double>(kind, C)) {
+        GR_DISPATCH_KT(kind, double, k_coarse_vcycle_lds, 1, CTPB, C, nu1, nu2, oc, fbar0, fshift0);
+        return;
+    }
     GR_DISPATCH_KT(kind, double, k_coarse_vcycle, 1, CTPB, C, nu1, nu2, oc, fbar0, fshift0);
 }
 
 void launch_coarse_vcycle_f32(int kind, hipStream_t s, const CoarseLevelsT<float> &C, int nu1, int nu2, OpConst oc,
                               const double *zero)
 {
+    if (coarse_lds_fits<float>(kind, C)) {
+        GR_DISPATCH_KT(kind, float, k_coarse_vcycle_lds, 1, CTPB, C, nu1, nu2, oc, zero, zero);
+        return;
+    }
     GR_DISPATCH_KT(kind, float, k_coarse_vcycle, 1, CTPB, C, nu1, nu2, oc, zero, zero);
 }
 
