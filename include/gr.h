@@ -286,6 +286,8 @@ typedef struct gr_unet_s *gr_unet;
 typedef struct {
     int in_ch, out_ch;
     int c[4];
+    float lap_weight; /* loss = mean (y-t)^2 + lap_weight * mean (Lap(y-t))^2 (7-point,
+                         periodic, unit spacing, per channel); 0: plain MSE */
 } gr_unet_desc;
 
 int gr_unet_create(const gr_unet_desc *desc, int max_n, gr_unet *out);

@@ -6,7 +6,9 @@ its forward pass and its hand-written backward pass.  Architecture: four
 levels with c[0..3] channels; per level two 3^3 convolutions (periodic
 padding) each followed by ReLU; 2x2x2 average pooling between encoder
 levels; nearest x2 upsampling, concatenated [upsampled | skip] on the way up;
-a 1x1 head; mean-square loss.  The input is zero-padded to 16 channels.
+a 1x1 head; mean-square loss, optionally plus a weighted mean square of the
+7-point periodic Laplacian of the error.  The input is zero-padded to 16
+channels.
 """
 from __future__ import annotations
 
@@ -71,13 +73,19 @@ def forward(p, x, c, out_ch):
     return y[0]
 
 
-def loss_and_grad(p_np, x_np, t_np, c, out_ch):
-    """Mean-square loss and its gradient with respect to the parameter vector."""
+def laplacian(d):
+    """7-point periodic Laplacian of unit spacing of each channel of d [ch, n, n, n]."""
+    return sum(torch.roll(d, s, dims=a) for a in (1, 2, 3) for s in (1, -1)) - 6.0 * d
+
+
+def loss_and_grad(p_np, x_np, t_np, c, out_ch, lap_weight=0.0):
+    """Loss mean((y-t)^2) + lap_weight * mean(Lap(y-t)^2) and its gradient with
+    respect to the parameter vector."""
     p = torch.tensor(np.asarray(p_np, dtype=np.float64), requires_grad=True)
     x = torch.tensor(np.asarray(x_np, dtype=np.float64))
     t = torch.tensor(np.asarray(t_np, dtype=np.float64))
     y = forward(p, x, c, out_ch)
-    loss = torch.mean((y - t) ** 2)
+    loss = torch.mean((y - t) ** 2) + lap_weight * torch.mean(laplacian(y - t) ** 2)
     loss.backward()
     return float(loss.detach()), p.grad.detach().numpy()
 

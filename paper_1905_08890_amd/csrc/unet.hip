@@ -262,6 +262,65 @@ __global__ void k_mse(const float *__restrict__ y, const float *__restrict__ t, 
     if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
 }
 
+// Optional smoothness term of the loss, lambda * mean((Lap d)^2) with d = y - t
+// and Lap the 7-point periodic Laplacian of unit spacing, per channel: the
+// judge of a guess is a residual, which weights errors by Lap.  Pass 1:
+// q = Lap d and partial sums of q^2; pass 2: gy += 2 lambda Lap q / total
+// (Lap is symmetric).
+__device__ __forceinline__ long lap_nb(int x, int y, int z, int n, int dx, int dy, int dz)
+{
+    x += dx;
+    y += dy;
+    z += dz;
+    x = x < 0 ? x + n : (x >= n ? x - n : x);
+    y = y < 0 ? y + n : (y >= n ? y - n : y);
+    z = z < 0 ? z + n : (z >= n ? z - n : z);
+    return ((long)z * n + y) * n + x;
+}
+
+template <bool FROM_DIFF>
+__device__ __forceinline__ float lap_at(const float *__restrict__ a, const float *__restrict__ b, long base, int x,
+                                        int y, int z, int n)
+{
+    auto v = [&](long q) { return FROM_DIFF ? a[base + q] - b[base + q] : a[base + q]; };
+    const float c = v(((long)z * n + y) * n + x);
+    return v(lap_nb(x, y, z, n, 1, 0, 0)) + v(lap_nb(x, y, z, n, -1, 0, 0)) + v(lap_nb(x, y, z, n, 0, 1, 0)) +
+           v(lap_nb(x, y, z, n, 0, -1, 0)) + v(lap_nb(x, y, z, n, 0, 0, 1)) + v(lap_nb(x, y, z, n, 0, 0, -1)) -
+           6.0f * c;
+}
+
+__global__ void k_lap_loss1(const float *__restrict__ y, const float *__restrict__ t, float *__restrict__ q, int n,
+                            long total, float *__restrict__ partial)
+{
+    __shared__ float sh[TPB];
+    const long N = (long)n * n * n;
+    float s = 0.0f;
+    for (long p = (long)blockIdx.x * TPB + threadIdx.x; p < total; p += (long)gridDim.x * TPB) {
+        const long ch = p / N, v = p - ch * N;
+        const int x = (int)(v % n), yy = (int)((v / n) % n), z = (int)(v / ((long)n * n));
+        const float l = lap_at<true>(y, t, ch * N, x, yy, z, n);
+        q[p] = l;
+        s += l * l;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = TPB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void k_lap_loss2(const float *__restrict__ q, float *__restrict__ gy, int n, long total, float lam)
+{
+    const long N = (long)n * n * n;
+    for (long p = (long)blockIdx.x * TPB + threadIdx.x; p < total; p += (long)gridDim.x * TPB) {
+        const long ch = p / N, v = p - ch * N;
+        const int x = (int)(v % n), yy = (int)((v / n) % n), z = (int)(v / ((long)n * n));
+        gy[p] += 2.0f * lam * lap_at<false>(q, nullptr, ch * N, x, yy, z, n) / (float)total;
+    }
+}
+
 // head backward: gh[v][c] = sum_o w[o][c] gy[o][v]; dW, db accumulated per block then atomically
 __global__ void k_head_bwd(const float *__restrict__ gy, const bf16 *__restrict__ h, int c, const float *__restrict__ w,
                            int cout, bf16 *__restrict__ gh, float *__restrict__ dw, float *__restrict__ db, long N)
@@ -429,7 +488,7 @@ struct gr_unet_s {
     long nparam = 0;
     // device
     float *param = nullptr, *grad = nullptr, *adam_m = nullptr, *adam_v = nullptr;
-    float *loss_partial = nullptr, *y = nullptr, *gy = nullptr;
+    float *loss_partial = nullptr, *y = nullptr, *gy = nullptr, *lq = nullptr;
     bf16 *x0 = nullptr;
     Act ea[4], eb3, cat[3], p[3], da[3], db[3];       // forward
     Act g_ea[4], g_eb3, g_cat[3], g_p[3], g_da[3], g_db[3], g_x; // backward
@@ -463,9 +522,10 @@ size_t unet_layout(gr_unet U, char *base)
     }
     const int n = U->max_n;
     const long N = (long)n * n * n;
-    U->loss_partial = takeF(1024);
+    U->loss_partial = takeF(2048);
     U->y = takeF((size_t)U->d.out_ch * N);
     U->gy = takeF((size_t)U->d.out_ch * N);
+    U->lq = takeF((size_t)U->d.out_ch * N);
     U->x0 = takeB((size_t)N * 16);
     auto act = [&](Act &a, int lvl, int ch) {
         a.n = n >> lvl;
@@ -653,15 +713,26 @@ int loss_and_grad(gr_unet U, int n, const float *d_in, const float *d_target, do
     const long tot = (long)U->d.out_ch * N;
     const int nbk = (int)std::min<long>(1024, (tot + TPB - 1) / TPB);
     k_mse<<<nbk, TPB, 0, U->stream>>>(U->y, d_target, U->gy, tot, U->loss_partial);
+    const float lam = U->d.lap_weight;
+    if (lam > 0.0f) {
+        k_lap_loss1<<<nbk, TPB, 0, U->stream>>>(U->y, d_target, U->lq, n, tot, U->loss_partial + 1024);
+        k_lap_loss2<<<nbk, TPB, 0, U->stream>>>(U->lq, U->gy, n, tot, lam);
+    }
     ULAUNCH();
     UCHK(backward(U, n));
     if (h_loss) {
-        std::vector<float> part(nbk);
+        std::vector<float> part(2 * 1024, 0.0f);
         UHIP(hipMemcpyAsync(part.data(), U->loss_partial, sizeof(float) * nbk, hipMemcpyDeviceToHost, U->stream));
+        if (lam > 0.0f)
+            UHIP(hipMemcpyAsync(part.data() + 1024, U->loss_partial + 1024, sizeof(float) * nbk,
+                                hipMemcpyDeviceToHost, U->stream));
         UHIP(hipStreamSynchronize(U->stream));
-        double acc = 0.0;
-        for (float v : part) acc += v;
-        *h_loss = acc / (double)tot;
+        double acc = 0.0, accl = 0.0;
+        for (int i = 0; i < nbk; ++i) {
+            acc += part[i];
+            accl += part[1024 + i];
+        }
+        *h_loss = (acc + (double)lam * accl) / (double)tot;
     }
     return GR_OK;
 }
@@ -685,6 +756,8 @@ int gr_unet_create(const gr_unet_desc *d, int max_n, gr_unet *out)
     *out = nullptr;
     if (d->in_ch < 1 || d->in_ch > 16 || d->out_ch < 1 || d->out_ch > 16)
         return ufail(GR_EINVAL, "in_ch and out_ch must be 1..16");
+    if (!(d->lap_weight >= 0.0f) || !std::isfinite(d->lap_weight))
+        return ufail(GR_EINVAL, "lap_weight must be finite and >= 0");
     if (d->c[0] != 16) return ufail(GR_EINVAL, "c[0] must be 16");
     for (int k = 1; k < 4; ++k)
         if (d->c[k] < 16 || d->c[k] > 64 || d->c[k] % 16) return ufail(GR_EINVAL, "c[%d] must be 16, 32, 48 or 64", k);

@@ -53,7 +53,7 @@ class GrSolveOpts(C.Structure):
 
 
 class GrUnetDesc(C.Structure):
-    _fields_ = [("in_ch", C.c_int), ("out_ch", C.c_int), ("c", C.c_int * 4)]
+    _fields_ = [("in_ch", C.c_int), ("out_ch", C.c_int), ("c", C.c_int * 4), ("lap_weight", C.c_float)]
 
 
 class GrSolveReport(C.Structure):
@@ -437,7 +437,7 @@ class UNet:
     """The U-Net of the learned guess (see gr.h); device memory from torch."""
 
     def __init__(self, in_ch: int, out_ch: int, channels=(16, 32, 64, 64), max_n: int = 64, device="cuda",
-                 stream=None):
+                 stream=None, lap_weight: float = 0.0):
         import torch
 
         self.torch = torch
@@ -445,7 +445,9 @@ class UNet:
         self.device = torch.device(device)
         lib = load_library()
         h = C.c_void_p()
-        _ucheck(lib.gr_unet_create(C.byref(GrUnetDesc(in_ch, out_ch, (C.c_int * 4)(*channels))), max_n, C.byref(h)))
+        _ucheck(lib.gr_unet_create(C.byref(GrUnetDesc(in_ch, out_ch, (C.c_int * 4)(*channels), lap_weight)), max_n,
+                                   C.byref(h)))
+        self.lap_weight = lap_weight
         self.handle = h.value
         nbytes, cnt = C.c_size_t(), C.c_int64()
         _ucheck(lib.gr_unet_workspace_bytes(self.handle, C.byref(nbytes)))

@@ -133,8 +133,8 @@ def normalise(xs, ys, norm, torch):
     return [((x - im) / isd).contiguous() for x in xs], [(y / osd).contiguous() for y in ys]
 
 
-def train(xs, ys, m, epochs, lr, seed, torch, device="cuda", channels=CHANNELS):
-    net = grmg.UNet(IN_CH, len(OUT_FIELDS), channels, max_n=m, device=device)
+def train(xs, ys, m, epochs, lr, seed, torch, device="cuda", channels=CHANNELS, lap_weight=0.0):
+    net = grmg.UNet(IN_CH, len(OUT_FIELDS), channels, max_n=m, device=device, lap_weight=lap_weight)
     net.init(seed)
     rng = np.random.default_rng(seed)
     losses = []
@@ -302,6 +302,8 @@ def main(argv=None):
     ap.add_argument("--r0", type=float, default=1.0)
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lap-weight", type=float, default=1.0,
+                    help="weight of mean (Lap error)^2 in the loss (the residual judge weights errors by Lap)")
     ap.add_argument("--out", required=True)
     ap.add_argument("--eval-seeds", type=int, default=2)
     ap.add_argument("--eval-seed0", type=int, default=2000)
@@ -313,9 +315,9 @@ def main(argv=None):
     norm = fit_normaliser(xs, ys)
     xs, ys = normalise(xs, ys, norm, torch)
     log(f"{len(xs)} samples in {time.time() - t0:.0f} s; training")
-    net, losses = train(xs, ys, a.n >> a.level, a.epochs, a.lr, a.seed0, torch)
+    net, losses = train(xs, ys, a.n >> a.level, a.epochs, a.lr, a.seed0, torch, lap_weight=a.lap_weight)
     meta = dict(n=a.n, level=a.level, seeds=[a.seed0, a.seed0 + a.seeds], steps=a.steps, r0=a.r0,
-                epochs=a.epochs, lr=a.lr, samples=len(xs), losses=losses)
+                epochs=a.epochs, lr=a.lr, lap_weight=a.lap_weight, samples=len(xs), losses=losses)
     save(a.out, net, norm, a.level, meta)
     log(f"saved {a.out} after {time.time() - t0:.0f} s")
     if a.eval_seeds > 0:

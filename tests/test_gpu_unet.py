@@ -48,16 +48,17 @@ def test_forward_matches_reference():
     assert rel(y, ref) < 3e-2
 
 
-def test_gradient_matches_reference():
+@pytest.mark.parametrize("lap_weight", [0.0, 0.3])
+def test_gradient_matches_reference(lap_weight):
     rng = np.random.default_rng(1)
-    net = grmg.UNet(4, 3, CH, max_n=32)
+    net = grmg.UNet(4, 3, CH, max_n=32, lap_weight=lap_weight)
     net.init(11)
     p = net.get_params().cpu().numpy().astype(np.float64)
     x = smooth_field(rng, (4, 32, 32, 32))
     t = smooth_field(rng, (3, 32, 32, 32))
     loss, g = net.loss_grad(x, t)
     g = g.cpu().numpy().astype(np.float64)
-    rloss, rg = R.loss_and_grad(p, x, t, CH, 3)
+    rloss, rg = R.loss_and_grad(p, x, t, CH, 3, lap_weight)
     assert abs(loss - rloss) < 3e-2 * rloss
     cos = float(g @ rg / (np.linalg.norm(g) * np.linalg.norm(rg)))
     assert cos > 0.998, cos
