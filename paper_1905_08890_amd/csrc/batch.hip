@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "sources_ops.h"
+#include "fused_sweep.h"
 
 using namespace grmg;
 using namespace grmg::detail;
@@ -112,6 +113,32 @@ __global__ void __launch_bounds__(TPB) kb_colour(BatchDev D, const int *__restri
     const double Lv = op_point<KIND, double>(ph, nb_sum(phi, i, y, z, n), 1.0 / (L.h * L.h), load_c1<KIND>(L.coef, p),
                                              0.0, oc, Fb, J);
     phi[p] = ph - (Lv - (L.f[p] - fs)) / J;
+}
+
+// Fused red-black sweeps (rb_fused_tile) of the boxes whose level d takes
+// 32x16 tiles: one workgroup per tile x 16-plane chunk, the box from the
+// block prefix table.  Out of place: even sweeps phi -> tmp, odd tmp -> phi.
+constexpr int kFZ = 16; // z-chunk of the batched fused sweep
+
+template <int KIND>
+__global__ void __launch_bounds__(TPB) kb_fused(BatchDev D, const int *__restrict__ tab, int d, int fid, int sweep,
+                                                OpConst oc)
+{
+    const int b = find_box(tab, D.nbox, blockIdx.x);
+    if (!D.active[b]) return;
+    const BoxDev &X = D.box[b];
+    const BoxLev &L = X.lev[d];
+    const int n = L.n, lb = blockIdx.x - tab[b];
+    const int nz = n / kFZ, tiles_y = n / 16;
+    const int zchunk = lb % nz, t2 = lb / nz;
+    double *phi = d == 0 ? X.field[fid] : L.phi;
+    const double *in = (sweep & 1) ? L.tmp : phi;
+    double *out = (sweep & 1) ? phi : L.tmp;
+    const double Fb = d == 0 ? D.scal[b * B_NSCAL + B_FBAR] : 0.0;
+    const double fs = d == 0 ? D.scal[b * B_NSCAL + B_FSHIFT] : 0.0;
+    constexpr int PF = KIND == GR_KIND_POISSON ? 2 : 1;
+    rb_fused_tile<KIND, double, 32, 16, PF>(in, out, L.f, L.coef, nullptr, n, kFZ, 1.0 / (L.h * L.h), oc, Fb, fs,
+                                            (t2 / tiles_y) * 32, (t2 % tiles_y) * 16, zchunk * kFZ);
 }
 
 // R phi, R eps at level d+1 (one thread per coarse cell), then the FAS source.
@@ -593,6 +620,8 @@ struct gr_batch_s {
     int maxdepth = 0;           // deepest multigrid level handled by grouped launches
     Tab fine;                   // fine level of every box
     std::vector<Tab> colour, cdom, prol, coefr; // per depth
+    std::vector<Tab> fz, colour_nf;             // per depth: fused boxes, the other boxes' colour passes
+    bool use_fused = true;
     BatchDev D{};
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
@@ -652,6 +681,8 @@ size_t batch_layout(gr_batch B, char *base)
         B->colour[d].dev = takeI(B->nbox + 1);
         B->cdom[d].dev = takeI(B->nbox + 1);
         B->prol[d].dev = takeI(B->nbox + 1);
+        B->fz[d].dev = takeI(B->nbox + 1);
+        B->colour_nf[d].dev = takeI(B->nbox + 1);
     }
     for (size_t d = 0; d < B->coefr.size(); ++d) B->coefr[d].dev = takeI(B->nbox + 1);
     return off;
@@ -690,6 +721,22 @@ int batch_pin(gr_batch B, int fid, int active_only)
 }
 
 // one cycle of the batch: frozen means, norms, control, V-cycle, pin
+// nu sweeps of level d of every box: fused (out of place, an even count ends
+// in phi) for the boxes that take 32x16 tiles, one launch per colour for the rest
+void batch_smooth(gr_batch B, int kind, int d, int fid, int nu)
+{
+    hipStream_t s = B->stream;
+    const OpConst oc = opc(B);
+    const bool fused = B->use_fused && nu % 2 == 0 && B->fz[d].total() > 0;
+    const Tab &TC = fused ? B->colour_nf[d] : B->colour[d];
+    for (int it = 0; it < nu; ++it) {
+        if (fused) KDISPATCH(kind, kb_fused, B->fz[d].total(), TPB, B->D, B->fz[d].dev, d, fid, it, oc);
+        if (TC.total() > 0)
+            for (int colour = 0; colour < 2; ++colour)
+                KDISPATCH(kind, kb_colour, TC.total(), TPB, B->D, TC.dev, d, fid, colour, oc);
+    }
+}
+
 int batch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
 {
     hipStream_t s = B->stream;
@@ -709,9 +756,7 @@ int batch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
     for (int d = 0; d < B->maxdepth; ++d) {
         const Tab &TC = B->colour[d], &TD = B->cdom[d];
         if (TC.total() == 0) continue;
-        for (int it = 0; it < o.nu1; ++it)
-            for (int colour = 0; colour < 2; ++colour)
-                KDISPATCH(kind, kb_colour, TC.total(), TPB, B->D, TC.dev, d, fid, colour, oc);
+        batch_smooth(B, kind, d, fid, o.nu1);
         KDISPATCH(kind, kb_residual_restrict, TD.total(), TPB, B->D, TD.dev, d, fid, oc);
         KDISPATCH(kind, kb_coarse_rhs, TD.total(), TPB, B->D, TD.dev, d, oc);
     }
@@ -720,9 +765,7 @@ int batch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
         const Tab &TC = B->colour[d], &TD = B->cdom[d];
         if (TC.total() == 0) continue;
         kb_prolong<<<B->prol[d].total(), TPB, 0, s>>>(B->D, B->prol[d].dev, d, fid);
-        for (int it = 0; it < o.nu2; ++it)
-            for (int colour = 0; colour < 2; ++colour)
-                KDISPATCH(kind, kb_colour, TC.total(), TPB, B->D, TC.dev, d, fid, colour, oc);
+        batch_smooth(B, kind, d, fid, o.nu2);
         (void)TD;
     }
     BCHK(batch_pin(B, fid, 1));
@@ -834,8 +877,23 @@ int gr_create_batch(const gr_grid_desc *descs, int count, const gr_params *prm, 
     B->colour.resize(maxd);
     B->cdom.resize(maxd);
     B->prol.resize(maxd);
+    B->fz.resize(maxd);
+    B->colour_nf.resize(maxd);
+    if (const char *e = std::getenv("GRMG_BATCH_FUSED")) B->use_fused = std::atoi(e) != 0;
+    auto fusable = [&](int b, int d) {
+        const int n = H[b].lev[d].n;
+        return d < H[b].centry && n >= 64 && n % 32 == 0;
+    };
     for (int d = 0; d < maxd; ++d) {
         make_tab(B->colour[d], nb, [&](int b) { long n = H[b].lev[d].n; return d < H[b].centry ? n * n * n / 2 : 0L; });
+        make_tab(B->fz[d], nb, [&](int b) {
+            const long n = H[b].lev[d].n;
+            return fusable(b, d) ? (n / 32) * (n / 16) * (n / kFZ) * TPB : 0L; // workgroups x threads
+        });
+        make_tab(B->colour_nf[d], nb, [&](int b) {
+            long n = H[b].lev[d].n;
+            return d < H[b].centry && !fusable(b, d) ? n * n * n / 2 : 0L;
+        });
         make_tab(B->cdom[d], nb, [&](int b) { long m = d < H[b].centry ? H[b].lev[d + 1].n : 0; return m * m * m; });
         make_tab(B->prol[d], nb, [&](int b) { long n = H[b].lev[d].n; return d < H[b].centry ? n * n * n : 0L; });
     }
@@ -886,6 +944,8 @@ int gr_batch_bind(gr_batch B, void *d_ws, size_t bytes, void *stream)
         BHIP(up(B->colour[d]));
         BHIP(up(B->cdom[d]));
         BHIP(up(B->prol[d]));
+        BHIP(up(B->fz[d]));
+        BHIP(up(B->colour_nf[d]));
     }
     for (auto &T : B->coefr) BHIP(up(T));
     BHIP(hipStreamSynchronize(s)); // host tables must outlive the copies

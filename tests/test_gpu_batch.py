@@ -52,6 +52,29 @@ def test_batch_matches_single_grid_and_oracle():
         assert rep["item_seconds"][i] > 0
 
 
+@pytest.mark.parametrize("fused", ["1", "0"])
+def test_batch_fused_boxes_match_single_grids(fused, monkeypatch):
+    """Boxes of 64^3 and 96^3 take the batched fused sweep (32x16 tiles), 48^3
+    the colour kernels, in the same launches; every box equals its single-grid
+    solve at identical cycle counts."""
+    monkeypatch.setenv("GRMG_BATCH_FUSED", fused)
+    items = [synth.batch_item(500 + i, sides=(side,), sigma_range=(0.05, 0.5)) for i, side in
+             enumerate((64, 48, 96, 64))]
+    print(f"[gpu] batch fused={fused} sides", [n for n, _ in items], flush=True)
+    B = grmg.Batch([n for n, _ in items], **PRM)
+    load(B, items)
+    rep = B.solve(rtol=1e-10)
+    assert rep["status"] == 0
+    for i, (n, src) in enumerate(items):
+        g = grmg.Grid(n, **PRM)
+        for name, x in zip(("s0", "sx", "sy", "sz", "sm"), src):
+            g.set_field(name, x)
+        single = g.solve_constraints(rtol=1e-10)
+        assert single["cycles"] == rep["cycles"][i], i
+        for name in O.FIELDS:
+            assert maxrel(B.get_field(i, name), g.get_field(name).cpu().numpy()) < 1e-12, (i, name)
+
+
 def test_batch_graph_replays_equal_eager(monkeypatch):
     """The per-cycle graph, replayed 1..4 times (with the solver's own eager
     launches and synchronisations between replays), gives the same fields as
