@@ -190,29 +190,56 @@ __global__ void __launch_bounds__(TPB) kb_coarse_rhs(BatchDev D, const int *__re
     C.f[t] = Lv - C.tmp[t];
 }
 
-// phi_d += P(phi_{d+1} - phi0_{d+1}); one thread per fine point
-__global__ void __launch_bounds__(TPB) kb_prolong(BatchDev D, const int *__restrict__ tab, int d, int fid)
+
+// coarse correction e = phi^H - R phi into level d+1's tmp (free once the
+// coarse source is built), one thread per coarse cell
+__global__ void __launch_bounds__(TPB) kb_coarse_diff(BatchDev D, const int *__restrict__ tab, int d)
+{
+    BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
+    const BoxLev &C = X.lev[d + 1];
+    const int m = C.n;
+    if (t >= m * m * m) return;
+    C.tmp[t] = C.phi[t] - C.phi0[t];
+}
+
+// phi += P e from level d+1's tmp: one thread per coarse cell writes its 8
+// children (x-pairs as 16-byte read-modify-writes); same weights and order
+// as the single-point form
+__global__ void __launch_bounds__(TPB) kb_prolong_cell(BatchDev D, const int *__restrict__ tab, int d, int fid)
 {
     BOX_PROLOGUE(tab)
     if (!D.active[b]) return;
     const BoxLev &L = X.lev[d], &C = X.lev[d + 1];
     const int n = L.n, m = C.n;
-    if (t >= n * n * n) return;
-    int a, bb, cc;
-    decode3(t, n, n, a, bb, cc);
+    if (t >= m * m * m) return;
+    int x, y, z;
+    decode3(t, m, m, x, y, z);
     double *phi = d == 0 ? X.field[fid] : L.phi;
-    const int I = a >> 1, J = bb >> 1, K = cc >> 1;
-    const int Is[2] = {I, wrapi(I + ((a & 1) ? 1 : -1), m)};
-    const int Js[2] = {J, wrapi(J + ((bb & 1) ? 1 : -1), m)};
-    const int Ks[2] = {K, wrapi(K + ((cc & 1) ? 1 : -1), m)};
-    double v = 0.0;
-    for (int c = 0; c < 8; ++c) {
-        const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
-        const double w = (ox ? 0.25 : 0.75) * (oy ? 0.25 : 0.75) * (oz ? 0.25 : 0.75);
-        const long q = lin(Is[ox], Js[oy], Ks[oz], m);
-        v += w * (C.phi[q] - C.phi0[q]);
-    }
-    phi[t] += v;
+    double e[3][3][3];
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx)
+                e[dz + 1][dy + 1][dx + 1] = C.tmp[lin(wrapi(x + dx, m), wrapi(y + dy, m), wrapi(z + dz, m), m)];
+    for (int cz = 0; cz < 2; ++cz)
+        for (int cy = 0; cy < 2; ++cy) {
+            double v[2];
+            for (int cx = 0; cx < 2; ++cx) {
+                const int sx = cx ? 1 : -1, sy = cy ? 1 : -1, sz = cz ? 1 : -1;
+                double a = 0.0;
+                for (int c = 0; c < 8; ++c) {
+                    const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+                    const double w = (ox ? 0.25 : 0.75) * (oy ? 0.25 : 0.75) * (oz ? 0.25 : 0.75);
+                    a += w * e[1 + oz * sz][1 + oy * sy][1 + ox * sx];
+                }
+                v[cx] = a;
+            }
+            double2 *dst = reinterpret_cast<double2 *>(phi + lin(2 * x, 2 * y + cy, 2 * z + cz, n));
+            double2 old = *dst;
+            old.x += v[0];
+            old.y += v[1];
+            *dst = old;
+        }
 }
 
 // coefficient restriction level d -> d+1 (once per solve of an equation)
@@ -619,7 +646,7 @@ struct gr_batch_s {
     std::vector<BoxDev> host;   // pointers into the workspace
     int maxdepth = 0;           // deepest multigrid level handled by grouped launches
     Tab fine;                   // fine level of every box
-    std::vector<Tab> colour, cdom, prol, coefr; // per depth
+    std::vector<Tab> colour, cdom, coefr; // per depth
     std::vector<Tab> fz, colour_nf;             // per depth: fused boxes, the other boxes' colour passes
     bool use_fused = true;
     BatchDev D{};
@@ -680,7 +707,6 @@ size_t batch_layout(gr_batch B, char *base)
     for (int d = 0; d < B->maxdepth; ++d) {
         B->colour[d].dev = takeI(B->nbox + 1);
         B->cdom[d].dev = takeI(B->nbox + 1);
-        B->prol[d].dev = takeI(B->nbox + 1);
         B->fz[d].dev = takeI(B->nbox + 1);
         B->colour_nf[d].dev = takeI(B->nbox + 1);
     }
@@ -764,11 +790,14 @@ int batch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
     for (int d = B->maxdepth - 1; d >= 0; --d) {
         const Tab &TC = B->colour[d], &TD = B->cdom[d];
         if (TC.total() == 0) continue;
-        kb_prolong<<<B->prol[d].total(), TPB, 0, s>>>(B->D, B->prol[d].dev, d, fid);
+        kb_coarse_diff<<<TD.total(), TPB, 0, s>>>(B->D, TD.dev, d);
+        kb_prolong_cell<<<TD.total(), TPB, 0, s>>>(B->D, TD.dev, d, fid);
         batch_smooth(B, kind, d, fid, o.nu2);
         (void)TD;
     }
-    BCHK(batch_pin(B, fid, 1));
+    // the Poisson cycle commutes with adding a constant: those fields are pinned
+    // once after the loop (batch_field), the nonlinear kinds after every cycle
+    if (kind != GR_KIND_POISSON) BCHK(batch_pin(B, fid, 1));
     BLAUNCH();
     return GR_OK;
 }
@@ -823,6 +852,7 @@ int batch_field(gr_batch B, int kind, int fid, const gr_solve_opts &o)
         if (!any) break;
         if (it > o.max_cycles + 2) return bfail(GR_EDEVICE, "batch control did not stop");
     }
+    if (kind == GR_KIND_POISSON) BCHK(batch_pin(B, fid, 0));
     std::vector<double> sc((size_t)B->nbox * B_NSCAL);
     BHIP(hipMemcpyAsync(sc.data(), B->D.scal, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, s));
     BHIP(hipStreamSynchronize(s));
@@ -876,7 +906,6 @@ int gr_create_batch(const gr_grid_desc *descs, int count, const gr_params *prm, 
     make_tab(B->fine, nb, [&](int b) { long n = H[b].lev[0].n; return n * n * n; });
     B->colour.resize(maxd);
     B->cdom.resize(maxd);
-    B->prol.resize(maxd);
     B->fz.resize(maxd);
     B->colour_nf.resize(maxd);
     if (const char *e = std::getenv("GRMG_BATCH_FUSED")) B->use_fused = std::atoi(e) != 0;
@@ -895,7 +924,6 @@ int gr_create_batch(const gr_grid_desc *descs, int count, const gr_params *prm, 
             return d < H[b].centry && !fusable(b, d) ? n * n * n / 2 : 0L;
         });
         make_tab(B->cdom[d], nb, [&](int b) { long m = d < H[b].centry ? H[b].lev[d + 1].n : 0; return m * m * m; });
-        make_tab(B->prol[d], nb, [&](int b) { long n = H[b].lev[d].n; return d < H[b].centry ? n * n * n : 0L; });
     }
     B->coefr.resize(maxc);
     for (int d = 0; d < maxc; ++d)
@@ -943,7 +971,6 @@ int gr_batch_bind(gr_batch B, void *d_ws, size_t bytes, void *stream)
     for (int d = 0; d < B->maxdepth; ++d) {
         BHIP(up(B->colour[d]));
         BHIP(up(B->cdom[d]));
-        BHIP(up(B->prol[d]));
         BHIP(up(B->fz[d]));
         BHIP(up(B->colour_nf[d]));
     }
