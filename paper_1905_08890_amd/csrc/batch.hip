@@ -22,6 +22,7 @@
 
 #include "sources_ops.h"
 #include "fused_sweep.h"
+#include "march.h"
 
 using namespace grmg;
 using namespace grmg::detail;
@@ -141,38 +142,6 @@ __global__ void __launch_bounds__(TPB) kb_fused(BatchDev D, const int *__restric
                                             (t2 / tiles_y) * 32, (t2 % tiles_y) * 16, zchunk * kFZ);
 }
 
-// R phi, R eps at level d+1 (one thread per coarse cell), then the FAS source.
-template <int KIND>
-__global__ void __launch_bounds__(TPB) kb_residual_restrict(BatchDev D, const int *__restrict__ tab, int d, int fid,
-                                                            OpConst oc)
-{
-    BOX_PROLOGUE(tab)
-    if (!D.active[b]) return;
-    const BoxLev &L = X.lev[d], &C = X.lev[d + 1];
-    const int n = L.n, m = C.n;
-    if (t >= m * m * m) return;
-    int I, J, K;
-    decode3(t, m, m, I, J, K);
-    const double *phi = d == 0 ? X.field[fid] : L.phi;
-    const double Fb = d == 0 ? D.scal[b * B_NSCAL + B_FBAR] : 0.0;
-    const double fs = d == 0 ? D.scal[b * B_NSCAL + B_FSHIFT] : 0.0;
-    const double inv_h2 = 1.0 / (L.h * L.h);
-    double sr = 0.0, sp = 0.0;
-    for (int c = 0; c < 8; ++c) {
-        const int i = 2 * I + (c & 1), j = 2 * J + ((c >> 1) & 1), k = 2 * K + (c >> 2);
-        const long p = lin(i, j, k, n);
-        const double ph = phi[p];
-        double Jd;
-        const double Lv = op_point<KIND, double>(ph, nb_sum(phi, i, j, k, n), inv_h2, load_c1<KIND>(L.coef, p), 0.0,
-                                                 oc, Fb, Jd);
-        sr += Lv - (L.f[p] - fs);
-        sp += ph;
-    }
-    const double rp = sp / 8.0;
-    C.phi[t] = rp;
-    C.phi0[t] = rp;
-    C.tmp[t] = sr / 8.0;
-}
 
 template <int KIND>
 __global__ void __launch_bounds__(TPB) kb_coarse_rhs(BatchDev D, const int *__restrict__ tab, int d, OpConst oc)
@@ -310,27 +279,91 @@ __global__ void __launch_bounds__(TPB) kb_sum(BatchDev D, const int *__restrict_
     block_store<1>(v, D.partials, total);
 }
 
+
+// Plane-marching forms (march_tile, 16-plane chunks) for boxes whose level
+// takes 32 x 8 tiles, the one-thread-per-point forms for the others, in one
+// launch: the table gives each box its blocks for whichever form it takes.
+constexpr int kMZ = 16;
+
+__host__ __device__ inline bool marchable(int n) { return n >= 64 && n % 32 == 0; }
+__host__ __device__ inline long march_blocks(int n) { return (long)(n / MTX) * (n / MTY) * (n / kMZ); }
+
 template <int KIND>
-__global__ void __launch_bounds__(TPB) kb_res_norms(BatchDev D, const int *__restrict__ tab, int fid, OpConst oc)
+__global__ void __launch_bounds__(TPB) kb_norms_m(BatchDev D, const int *__restrict__ tab, int fid, OpConst oc)
 {
-    BOX_PROLOGUE(tab)
+    const int b = find_box(tab, D.nbox, blockIdx.x);
+    const BoxDev &X = D.box[b];
     const int total = tab[D.nbox];
-    double v[2] = {0.0, 0.0};
+    const int lb = blockIdx.x - tab[b];
     const BoxLev &L = X.lev[0];
     const int n = L.n;
-    if (t < n * n * n && D.active[b]) {
-        int x, y, z;
-        decode3(t, n, n, x, y, z);
+    const double Fb = D.scal[b * B_NSCAL + B_FBAR], fs = D.scal[b * B_NSCAL + B_FSHIFT];
+    double v[2] = {0.0, 0.0};
+    if (D.active[b]) {
         const double *phi = X.field[fid];
-        double Jd;
-        const double Lv = op_point<KIND, double>(phi[t], nb_sum(phi, x, y, z, n), 1.0 / (L.h * L.h),
-                                                 load_c1<KIND>(L.coef, t), 0.0, oc, D.scal[b * B_NSCAL + B_FBAR], Jd);
-        const double fe = L.f[t] - D.scal[b * B_NSCAL + B_FSHIFT];
-        const double e = Lv - fe;
-        v[0] = e * e;
-        v[1] = fe * fe;
+        if (marchable(n)) {
+            const int nzc = n / kMZ, tiles_y = n / MTY, tile = lb / nzc, zchunk = lb % nzc;
+            march_tile<M_NORMS, KIND, double>(phi, L.f, L.coef, nullptr, n, kMZ, 1.0 / (L.h * L.h), oc, Fb, fs,
+                                              (tile / tiles_y) * MTX, (tile % tiles_y) * MTY, zchunk * kMZ, nullptr,
+                                              nullptr, nullptr, nullptr, nullptr, nullptr, v);
+        } else {
+            const int t = lb * TPB + threadIdx.x;
+            if (t < n * n * n) {
+                int x, y, z;
+                decode3(t, n, n, x, y, z);
+                double Jd;
+                const double Lv = op_point<KIND, double>(phi[t], nb_sum(phi, x, y, z, n), 1.0 / (L.h * L.h),
+                                                         load_c1<KIND>(L.coef, t), 0.0, oc, Fb, Jd);
+                const double fe = L.f[t] - fs;
+                const double e = Lv - fe;
+                v[0] = e * e;
+                v[1] = fe * fe;
+            }
+        }
     }
     block_store<2>(v, D.partials, total);
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(TPB) kb_rr_m(BatchDev D, const int *__restrict__ tab, int d, int fid, OpConst oc)
+{
+    const int b = find_box(tab, D.nbox, blockIdx.x);
+    if (!D.active[b]) return;
+    const BoxDev &X = D.box[b];
+    const int lb = blockIdx.x - tab[b];
+    const BoxLev &L = X.lev[d], &C = X.lev[d + 1];
+    const int n = L.n;
+    const double *phi = d == 0 ? X.field[fid] : L.phi;
+    const double Fb = d == 0 ? D.scal[b * B_NSCAL + B_FBAR] : 0.0;
+    const double fs = d == 0 ? D.scal[b * B_NSCAL + B_FSHIFT] : 0.0;
+    if (marchable(n)) {
+        const int nzc = n / kMZ, tiles_y = n / MTY, tile = lb / nzc, zchunk = lb % nzc;
+        double v[2];
+        march_tile<M_RESTRICT, KIND, double>(phi, L.f, L.coef, nullptr, n, kMZ, 1.0 / (L.h * L.h), oc, Fb, fs,
+                                             (tile / tiles_y) * MTX, (tile % tiles_y) * MTY, zchunk * kMZ, C.phi,
+                                             C.phi0, C.tmp, nullptr, nullptr, nullptr, v);
+        return;
+    }
+    const int m = C.n, t = lb * TPB + threadIdx.x;
+    if (t >= m * m * m) return;
+    int I, J, K;
+    decode3(t, m, m, I, J, K);
+    const double inv_h2 = 1.0 / (L.h * L.h);
+    double sr = 0.0, sp = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        const int i = 2 * I + (c & 1), j = 2 * J + ((c >> 1) & 1), k = 2 * K + (c >> 2);
+        const long p = lin(i, j, k, n);
+        const double ph = phi[p];
+        double Jd;
+        const double Lv = op_point<KIND, double>(ph, nb_sum(phi, i, j, k, n), inv_h2, load_c1<KIND>(L.coef, p), 0.0,
+                                                 oc, Fb, Jd);
+        sr += Lv - (L.f[p] - fs);
+        sp += ph;
+    }
+    const double rp = sp / 8.0;
+    C.phi[t] = rp;
+    C.phi0[t] = rp;
+    C.tmp[t] = sr / 8.0;
 }
 
 // per box: slot[c] = add_slot + scale/N * sum of the box's block partials of component c
@@ -648,6 +681,9 @@ struct gr_batch_s {
     Tab fine;                   // fine level of every box
     std::vector<Tab> colour, cdom, coefr; // per depth
     std::vector<Tab> fz, colour_nf;             // per depth: fused boxes, the other boxes' colour passes
+    std::vector<Tab> rr;                        // per depth: residual + restriction (marching or per cell)
+    Tab norms;                                  // stopping norms of the fine level
+    bool use_march = true;
     bool use_fused = true;
     BatchDev D{};
     size_t ws_bytes = 0;
@@ -704,10 +740,12 @@ size_t batch_layout(gr_batch B, char *base)
     B->D.any_active = takeI(1);
     B->D.partials = takeD((size_t)B->fine.total() * 2 + 16);
     B->fine.dev = takeI(B->nbox + 1);
+    B->norms.dev = takeI(B->nbox + 1);
     for (int d = 0; d < B->maxdepth; ++d) {
         B->colour[d].dev = takeI(B->nbox + 1);
         B->cdom[d].dev = takeI(B->nbox + 1);
         B->fz[d].dev = takeI(B->nbox + 1);
+        B->rr[d].dev = takeI(B->nbox + 1);
         B->colour_nf[d].dev = takeI(B->nbox + 1);
     }
     for (size_t d = 0; d < B->coefr.size(); ++d) B->coefr[d].dev = takeI(B->nbox + 1);
@@ -775,15 +813,15 @@ int batch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
         kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid, 2, oc, 1);
         kb_finalize<<<B->nbox, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FSHIFT, B_FMEAN, 1);
     }
-    KDISPATCH(kind, kb_res_norms, FT, TPB, B->D, B->fine.dev, fid, oc);
-    kb_finalize<<<B->nbox, TPB, 0, s>>>(B->D, B->fine.dev, 2, B_RN, -1, 1);
+    KDISPATCH(kind, kb_norms_m, B->norms.total(), TPB, B->D, B->norms.dev, fid, oc);
+    kb_finalize<<<B->nbox, TPB, 0, s>>>(B->D, B->norms.dev, 2, B_RN, -1, 1);
     kb_control<<<1, 1024, 0, s>>>(B->D, fid, o.rtol, o.max_cycles);
     // descent through the levels handled by grouped launches
     for (int d = 0; d < B->maxdepth; ++d) {
         const Tab &TC = B->colour[d], &TD = B->cdom[d];
         if (TC.total() == 0) continue;
         batch_smooth(B, kind, d, fid, o.nu1);
-        KDISPATCH(kind, kb_residual_restrict, TD.total(), TPB, B->D, TD.dev, d, fid, oc);
+        KDISPATCH(kind, kb_rr_m, B->rr[d].total(), TPB, B->D, B->rr[d].dev, d, fid, oc);
         KDISPATCH(kind, kb_coarse_rhs, TD.total(), TPB, B->D, TD.dev, d, oc);
     }
     KDISPATCH(kind, kb_coarse_vcycle, B->nbox, CTPB, B->D, fid, o.nu1, o.nu2, oc);
@@ -907,6 +945,12 @@ int gr_create_batch(const gr_grid_desc *descs, int count, const gr_params *prm, 
     B->colour.resize(maxd);
     B->cdom.resize(maxd);
     B->fz.resize(maxd);
+    B->rr.resize(maxd);
+    if (const char *e = std::getenv("GRMG_MARCH")) B->use_march = std::atoi(e) != 0;
+    make_tab(B->norms, nb, [&](int b) {
+        const long n = H[b].lev[0].n;
+        return B->use_march && marchable((int)n) ? march_blocks((int)n) * TPB : n * n * n;
+    });
     B->colour_nf.resize(maxd);
     if (const char *e = std::getenv("GRMG_BATCH_FUSED")) B->use_fused = std::atoi(e) != 0;
     auto fusable = [&](int b, int d) {
@@ -918,6 +962,11 @@ int gr_create_batch(const gr_grid_desc *descs, int count, const gr_params *prm, 
         make_tab(B->fz[d], nb, [&](int b) {
             const long n = H[b].lev[d].n;
             return fusable(b, d) ? (n / 32) * (n / 16) * (n / kFZ) * TPB : 0L; // workgroups x threads
+        });
+        make_tab(B->rr[d], nb, [&](int b) {
+            if (d >= H[b].centry) return 0L;
+            const long n = H[b].lev[d].n, m = H[b].lev[d + 1].n;
+            return B->use_march && marchable((int)n) ? march_blocks((int)n) * TPB : m * m * m;
         });
         make_tab(B->colour_nf[d], nb, [&](int b) {
             long n = H[b].lev[d].n;
@@ -968,10 +1017,12 @@ int gr_batch_bind(gr_batch B, void *d_ws, size_t bytes, void *stream)
         return hipMemcpyAsync(T.dev, T.start.data(), sizeof(int) * T.start.size(), hipMemcpyHostToDevice, s);
     };
     BHIP(up(B->fine));
+    BHIP(up(B->norms));
     for (int d = 0; d < B->maxdepth; ++d) {
         BHIP(up(B->colour[d]));
         BHIP(up(B->cdom[d]));
         BHIP(up(B->fz[d]));
+        BHIP(up(B->rr[d]));
         BHIP(up(B->colour_nf[d]));
     }
     for (auto &T : B->coefr) BHIP(up(T));

@@ -1,0 +1,137 @@
+// Plane-marching residual kernels: one tile x z-chunk as a device function
+// (shared by the single-grid kernels and the batched kernels).
+#pragma once
+
+#include "stencil_ops.h"
+
+namespace grmg {
+namespace detail {
+
+// A workgroup of 32 x 8 threads owns one (x, y) point each of a 32 x 8 tile
+// and marches a chunk of zc planes in z.  Each plane of the iterate, with a
+// 1-cell halo ring, goes to one of two LDS buffers (one barrier per plane);
+// the z-neighbours stay in registers.  All reads of a plane are issued two
+// planes ahead, in two alternating register sets.  Per point the iterate is
+// read once from memory (plus the halo ring, mostly from L2), the source and
+// coefficients once.  Modes:
+//   M_NORMS        sums of eps^2 and (f - fshift)^2 (stopping test)
+//   M_IR           as M_NORMS, plus the FP32 correction source b = -eps and,
+//                  for the Hamiltonian, a = chi and c = dL/dPsi + 6 chi/h^2
+//   M_RESTRICT     FAS: R eps, R phi (also as phi0) on the coarse level
+//   M_RESTRICT_LIN correction scheme: R(b - J e) and a zero coarse e
+// The restriction modes sum z pairs in registers and x / y pairs across lanes.
+enum { M_NORMS = 0, M_IR = 1, M_RESTRICT = 2, M_RESTRICT_LIN = 3 };
+constexpr int MTX = 32, MTY = 8, MNT = MTX * MTY;
+constexpr int MHALO = 2 * (MTX + 2) + 2 * MTY; // halo ring of a plane
+
+// One workgroup's tile (x0, y0) and z-chunk [z0, z0 + zc); norm[0..1] get this
+// thread's sums of eps^2 and (f - fshift)^2 (norm modes).
+template <int MODE, int KIND, typename T>
+__device__ __forceinline__ void march_tile(const T *__restrict__ phi, const T *__restrict__ f,
+                                           const T *__restrict__ c1, const T *__restrict__ c2, const int n,
+                                           const int zc, const T inv_h2, OpConst oc, const T Fb, const T fs,
+                                           const int x0, const int y0, const int z0, T *__restrict__ o1,
+                                           T *__restrict__ o2, T *__restrict__ o3, float *__restrict__ b32,
+                                           float *__restrict__ a32, float *__restrict__ c32, double *norm)
+{
+    constexpr int FW = MTX + 2, FH = MTY + 2;
+    constexpr int NC = kNumCoef<KIND>();
+    __shared__ T buf[2][FH * FW];
+    const int tid = threadIdx.x;
+    const int tx = tid % MTX, ty = tid / MTX;
+    const long plane = (long)n * n;
+    const long own = (long)(y0 + ty) * n + x0 + tx;
+    // halo ring position of this thread (tid < MHALO): frame row / column
+    int hr = 0, hc = 0;
+    if (tid < 2 * (MTX + 2)) {
+        hr = tid < MTX + 2 ? 0 : FH - 1;
+        hc = tid < MTX + 2 ? tid : tid - (MTX + 2);
+    } else if (tid < MHALO) {
+        const int k = tid - 2 * (MTX + 2);
+        hr = 1 + k / 2;
+        hc = (k & 1) ? FW - 1 : 0;
+    }
+    const long hoff = (long)wrapi(y0 + hr - 1, n) * n + wrapi(x0 + hc - 1, n);
+    const int fo = (ty + 1) * FW + tx + 1; // own frame index
+
+    struct Set {
+        T own, halo, f, c, a;
+    };
+    auto load = [&](Set &S, int z) {
+        const long zo = (long)wrapi(z, n) * plane;
+        S.own = phi[zo + own];
+        if (tid < MHALO) S.halo = phi[zo + hoff];
+        S.f = f[zo + own];
+        if (NC >= 1) S.c = c1[zo + own];
+        if (NC >= 2) S.a = c2[zo + own];
+    };
+    Set A, B;
+    A.own = A.halo = A.f = A.c = A.a = T(0);
+    B = A;
+    T below = phi[(long)wrapi(z0 - 1, n) * plane + own];
+    load(A, z0);
+    load(B, z0 + 1);
+    double v0 = 0.0, v1 = 0.0; // norm sums
+    T sr = 0, sp = 0;          // restriction sums over a z pair
+
+    auto body = [&](const int z, Set &S, const Set &Nx) {
+        T *pl = buf[z & 1];
+        pl[fo] = S.own;
+        if (tid < MHALO) pl[hr * FW + hc] = S.halo;
+        __syncthreads();
+        const T ph = S.own;
+        const T nbs = pl[fo - 1] + pl[fo + 1] + pl[fo - FW] + pl[fo + FW] + below + Nx.own;
+        T J;
+        const T L = op_point<KIND, T>(ph, nbs, inv_h2, S.c, S.a, oc, Fb, J);
+        const long p = (long)z * plane + own;
+        if constexpr (MODE == M_NORMS || MODE == M_IR) {
+            const double fe = (double)S.f - (double)fs;
+            const double e = (double)L - fe;
+            v0 += e * e;
+            v1 += fe * fe;
+            if constexpr (MODE == M_IR) {
+                b32[p] = (float)(-e);
+                if constexpr (KIND == GR_KIND_HAMILTONIAN) {
+                    const double chi = 1.0 - oc.kappa * (double)ph;
+                    a32[p] = (float)chi;
+                    c32[p] = (float)((double)J + 6.0 * chi * (double)inv_h2);
+                }
+            }
+        } else {
+            sr += (MODE == M_RESTRICT) ? L - (S.f - fs) : S.f - L;
+            sp += ph;
+            if (z & 1) { // a z pair is complete: add the x and y pairs across lanes
+                T r2 = sr + __shfl_xor(sr, 1, 64);
+                T p2 = sp + __shfl_xor(sp, 1, 64);
+                r2 += __shfl_xor(r2, 32, 64);
+                p2 += __shfl_xor(p2, 32, 64);
+                if (((tx | ty) & 1) == 0) {
+                    const int m = n >> 1;
+                    const long q = ((long)(z >> 1) * m + ((y0 + ty) >> 1)) * m + ((x0 + tx) >> 1);
+                    if constexpr (MODE == M_RESTRICT) {
+                        o1[q] = p2 / T(8); // R phi
+                        o2[q] = p2 / T(8); // phi0
+                        o3[q] = r2 / T(8); // R eps
+                    } else {
+                        o1[q] = r2 / T(8); // coarse b
+                        o2[q] = T(0);      // coarse e
+                    }
+                }
+                sr = 0;
+                sp = 0;
+            }
+        }
+        below = ph;
+        if (z + 2 < z0 + zc) load(S, z + 2);
+        else if (z + 2 == z0 + zc) S.own = phi[(long)wrapi(z + 2, n) * plane + own]; // last plane's z + 1
+    };
+    for (int z = z0; z < z0 + zc; z += 2) {
+        body(z, A, B);
+        body(z + 1, B, A);
+    }
+    norm[0] = v0;
+    norm[1] = v1;
+}
+
+} // namespace detail
+} // namespace grmg
