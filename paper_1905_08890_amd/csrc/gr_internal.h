@@ -93,6 +93,9 @@ void launch_lin_residual_restrict_f32(int kind, hipStream_t s, const float *e, c
 void launch_prolong_add_f32(hipStream_t s, float *e_f, int n, const float *e_c);
 void launch_prolong_add_f64(hipStream_t s, double *phi_f, int n, const double *e_c);
 void launch_sub_arrays(hipStream_t s, double *d, const double *a, const double *b, long N);
+void launch_ir_update_residual(hipStream_t s, const double *phi, const float *e, double *phi_out, const double *f,
+                               int n, double h, OpConst oc, const double *fbar, const double *fshift, float *b32,
+                               double *partials);
 void launch_restrict_f32(hipStream_t s, const float *fine, int n, float *coarse);
 void launch_ir_residual(int kind, hipStream_t s, const double *phi, const double *f, const double *coef, int n,
                         double h, OpConst oc, const double *fbar, const double *fshift, float *b32, float *a32,

@@ -19,8 +19,11 @@ namespace detail {
 //                  for the Hamiltonian, a = chi and c = dL/dPsi + 6 chi/h^2
 //   M_RESTRICT     FAS: R eps, R phi (also as phi0) on the coarse level
 //   M_RESTRICT_LIN correction scheme: R(b - J e) and a zero coarse e
+//   M_IRU          Poisson refinement step: the iterate read is phi + e (the
+//                  FP32 correction, e32), written to o1 (out of place), then
+//                  as M_IR for that updated iterate
 // The restriction modes sum z pairs in registers and x / y pairs across lanes.
-enum { M_NORMS = 0, M_IR = 1, M_RESTRICT = 2, M_RESTRICT_LIN = 3 };
+enum { M_NORMS = 0, M_IR = 1, M_RESTRICT = 2, M_RESTRICT_LIN = 3, M_IRU = 4 };
 constexpr int MTX = 32, MTY = 8, MNT = MTX * MTY;
 constexpr int MHALO = 2 * (MTX + 2) + 2 * MTY; // halo ring of a plane
 
@@ -32,7 +35,8 @@ __device__ __forceinline__ void march_tile(const T *__restrict__ phi, const T *_
                                            const int zc, const T inv_h2, OpConst oc, const T Fb, const T fs,
                                            const int x0, const int y0, const int z0, T *__restrict__ o1,
                                            T *__restrict__ o2, T *__restrict__ o3, float *__restrict__ b32,
-                                           float *__restrict__ a32, float *__restrict__ c32, double *norm)
+                                           float *__restrict__ a32, float *__restrict__ c32, double *norm,
+                                           const float *__restrict__ e32 = nullptr)
 {
     constexpr int FW = MTX + 2, FH = MTY + 2;
     constexpr int NC = kNumCoef<KIND>();
@@ -57,10 +61,12 @@ __device__ __forceinline__ void march_tile(const T *__restrict__ phi, const T *_
     struct Set {
         T own, halo, f, c, a;
     };
+    // the iterate at a point (M_IRU: updated by the correction on the fly)
+    auto it_at = [&](long q) { return MODE == M_IRU ? phi[q] + T(e32[q]) : phi[q]; };
     auto load = [&](Set &S, int z) {
         const long zo = (long)wrapi(z, n) * plane;
-        S.own = phi[zo + own];
-        if (tid < MHALO) S.halo = phi[zo + hoff];
+        S.own = it_at(zo + own);
+        if (tid < MHALO) S.halo = it_at(zo + hoff);
         S.f = f[zo + own];
         if (NC >= 1) S.c = c1[zo + own];
         if (NC >= 2) S.a = c2[zo + own];
@@ -68,7 +74,7 @@ __device__ __forceinline__ void march_tile(const T *__restrict__ phi, const T *_
     Set A, B;
     A.own = A.halo = A.f = A.c = A.a = T(0);
     B = A;
-    T below = phi[(long)wrapi(z0 - 1, n) * plane + own];
+    T below = it_at((long)wrapi(z0 - 1, n) * plane + own);
     load(A, z0);
     load(B, z0 + 1);
     double v0 = 0.0, v1 = 0.0; // norm sums
@@ -84,11 +90,15 @@ __device__ __forceinline__ void march_tile(const T *__restrict__ phi, const T *_
         T J;
         const T L = op_point<KIND, T>(ph, nbs, inv_h2, S.c, S.a, oc, Fb, J);
         const long p = (long)z * plane + own;
-        if constexpr (MODE == M_NORMS || MODE == M_IR) {
+        if constexpr (MODE == M_NORMS || MODE == M_IR || MODE == M_IRU) {
             const double fe = (double)S.f - (double)fs;
             const double e = (double)L - fe;
             v0 += e * e;
             v1 += fe * fe;
+            if constexpr (MODE == M_IRU) {
+                o1[p] = ph;
+                b32[p] = (float)(-e);
+            }
             if constexpr (MODE == M_IR) {
                 b32[p] = (float)(-e);
                 if constexpr (KIND == GR_KIND_HAMILTONIAN) {
@@ -123,7 +133,7 @@ __device__ __forceinline__ void march_tile(const T *__restrict__ phi, const T *_
         }
         below = ph;
         if (z + 2 < z0 + zc) load(S, z + 2);
-        else if (z + 2 == z0 + zc) S.own = phi[(long)wrapi(z + 2, n) * plane + own]; // last plane's z + 1
+        else if (z + 2 == z0 + zc) S.own = it_at((long)wrapi(z + 2, n) * plane + own); // last plane's z + 1
     };
     for (int z = z0; z < z0 + zc; z += 2) {
         body(z, A, B);

@@ -12,6 +12,7 @@
 #include <new>
 #include <string>
 #include <mutex>
+#include <utility>
 #include <vector>
 
 #include "gr_internal.h"
@@ -564,6 +565,11 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
     LAUNCHCHK();
     CHK(pin_mean(g, phi, N));
 
+    // Poisson: the update phi + e and the next residual are one pass, out of
+    // place, alternating between the field and the finest level's scratch
+    // array (the iterate is copied back to the field at the end)
+    const bool fuse_update = kind == GR_KIND_POISSON;
+    double *cur = phi, *other = F.tmp;
     // frozen means, FP64 residual (as FP32 right-hand side) and the stopping norms
     auto measure = [&]() -> int {
         if (kind == GR_KIND_HAMILTONIAN) {
@@ -573,7 +579,7 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
             launch_sum_prod(s, F.coef, phi, N, g->partials);
             launch_finalize(s, g->partials, 1, 1.0 / (double)N, g->scal + S_FMEAN, g->scal + S_FSHIFT);
         }
-        launch_ir_residual(kind, s, phi, F.f, F.coef, F.n, F.h, oc, g->scal + S_FBAR, g->scal + S_FSHIFT, F32.b, F32.a,
+        launch_ir_residual(kind, s, cur, F.f, F.coef, F.n, F.h, oc, g->scal + S_FBAR, g->scal + S_FSHIFT, F32.b, F32.a,
                            F32.c, g->partials);
         launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN);
         LAUNCHCHK();
@@ -587,8 +593,12 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
                 launch_restrict_f32(s, g->lev32[l - 1].c, g->lev[l - 1].n, g->lev32[l].c);
             }
         CHK(vcycle32(g, lkind, 0, o.nu1, o.nu2, oc, true));
-        if (kind == GR_KIND_POISSON) { // shift-invariant: one pin at the end (as in the FP64 cycle)
-            launch_ir_update(s, phi, F32.e, N, g->scal + S_ZERO);
+        if (fuse_update) { // shift-invariant: one pin at the end (as in the FP64 cycle)
+            launch_ir_update_residual(s, cur, F32.e, other, F.f, F.n, F.h, oc, g->scal + S_FBAR, g->scal + S_FSHIFT,
+                                      F32.b, g->partials);
+            launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN);
+            LAUNCHCHK();
+            return GR_OK;
         } else {
             launch_sum_f32(s, F32.e, N, g->partials);
             launch_finalize(s, g->partials, 1, 1.0 / (double)N, nullptr, g->scal + S_MEAN);
@@ -622,6 +632,11 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
         prev = rel;
         if (stall >= 2) { // FP32 corrections no longer help: finish in FP64
             *fell_back = 1;
+            if (cur != phi) {
+                launch_copy(s, phi, cur, N);
+                LAUNCHCHK();
+                cur = phi;
+            }
             gr_solve_opts o2 = o;
             o2.max_cycles = o.max_cycles - cyc;
             int c2 = 0;
@@ -629,8 +644,14 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
             cyc += c2;
             break;
         }
-        CHK(run_captured(g, GR_MIXED, kind, o.nu1, o.nu2, phi, step));
+        // graphs keyed by the field and by which array holds the iterate
+        CHK(run_captured(g, GR_MIXED, kind + (cur != phi ? 16 : 0), o.nu1, o.nu2, phi, step));
+        if (fuse_update) std::swap(cur, other);
         ++cyc;
+    }
+    if (cur != phi) {
+        launch_copy(s, phi, cur, N);
+        LAUNCHCHK();
     }
     if (kind == GR_KIND_POISSON && cyc > 0 && !*fell_back) CHK(pin_mean(g, phi, N));
     *cycles_out = cyc;

@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(MNT) k_march(const T *__restrict__ phi, const 
                                                const double *__restrict__ fshift, double *__restrict__ partials,
                                                T *__restrict__ o1, T *__restrict__ o2, T *__restrict__ o3,
                                                float *__restrict__ b32, float *__restrict__ a32,
-                                               float *__restrict__ c32)
+                                               float *__restrict__ c32, const float *__restrict__ e32)
 {
     const int tiles_y = n / MTY;
     const int nzc = n / zc;
@@ -351,8 +351,8 @@ __global__ void __launch_bounds__(MNT) k_march(const T *__restrict__ phi, const 
     const T fs = (MODE == M_RESTRICT_LIN) ? T(0) : T(*fshift);
     double v[2] = {0.0, 0.0};
     march_tile<MODE, KIND, T>(phi, f, c1, c2, n, zc, inv_h2, oc, Fb, fs, (tile / tiles_y) * MTX,
-                              (tile % tiles_y) * MTY, zchunk * zc, o1, o2, o3, b32, a32, c32, v);
-    if constexpr (MODE == M_NORMS || MODE == M_IR) {
+                              (tile % tiles_y) * MTY, zchunk * zc, o1, o2, o3, b32, a32, c32, v, e32);
+    if constexpr (MODE == M_NORMS || MODE == M_IR || MODE == M_IRU) {
         block_sum_store<2>(v, partials);
         if (blockIdx.x == 0) // unused partial slots of a smaller grid
             for (int b2 = gridDim.x + threadIdx.x; b2 < kReduceBlocks; b2 += MNT) {
@@ -732,6 +732,13 @@ __global__ void k_sub_arrays(double *__restrict__ d, const double *__restrict__ 
     if (p < N) d[p] = a[p] - b[p];
 }
 
+__global__ void k_add_f32_out(double *__restrict__ d, const double *__restrict__ a, const float *__restrict__ e,
+                              long N)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < N) d[p] = a[p] + (double)e[p];
+}
+
 __global__ void k_axpy(double *__restrict__ y, const double *__restrict__ x, long N)
 {
     const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -912,12 +919,12 @@ int march_grid(int n, long max_blocks, int *zc_out)
 #define GR_MARCH_KIND(MODE, T, kind, grid, ...)                                                       \
     do {                                                                                              \
         switch (kind) {                                                                               \
-        case GR_KIND_POISSON: k_march<MODE, GR_KIND_POISSON, T><<<grid, MNT, 0, s>>>(__VA_ARGS__); break; \
-        case GR_KIND_HAMILTONIAN: k_march<MODE, GR_KIND_HAMILTONIAN, T><<<grid, MNT, 0, s>>>(__VA_ARGS__); break; \
-        case GR_KIND_CMC: k_march<MODE, GR_KIND_CMC, T><<<grid, MNT, 0, s>>>(__VA_ARGS__); break;          \
-        case K_LIN_POISSON: k_march<MODE, K_LIN_POISSON, T><<<grid, MNT, 0, s>>>(__VA_ARGS__); break;      \
-        case K_LIN_HAM: k_march<MODE, K_LIN_HAM, T><<<grid, MNT, 0, s>>>(__VA_ARGS__); break;              \
-        default: k_march<MODE, K_LIN_CMC, T><<<grid, MNT, 0, s>>>(__VA_ARGS__); break;                     \
+        case GR_KIND_POISSON: k_march<MODE, GR_KIND_POISSON, T><<<grid, MNT, 0, s>>>(__VA_ARGS__, nullptr); break; \
+        case GR_KIND_HAMILTONIAN: k_march<MODE, GR_KIND_HAMILTONIAN, T><<<grid, MNT, 0, s>>>(__VA_ARGS__, nullptr); break; \
+        case GR_KIND_CMC: k_march<MODE, GR_KIND_CMC, T><<<grid, MNT, 0, s>>>(__VA_ARGS__, nullptr); break;          \
+        case K_LIN_POISSON: k_march<MODE, K_LIN_POISSON, T><<<grid, MNT, 0, s>>>(__VA_ARGS__, nullptr); break;      \
+        case K_LIN_HAM: k_march<MODE, K_LIN_HAM, T><<<grid, MNT, 0, s>>>(__VA_ARGS__, nullptr); break;              \
+        default: k_march<MODE, K_LIN_CMC, T><<<grid, MNT, 0, s>>>(__VA_ARGS__, nullptr); break;                     \
         }                                                                                             \
     } while (0)
 
@@ -931,17 +938,17 @@ void launch_residual_restrict(int kind, hipStream_t s, const double *phi, const 
         case GR_KIND_POISSON:
             k_march<M_RESTRICT, GR_KIND_POISSON, double><<<grid, MNT, 0, s>>>(
                 phi, f, coef, nullptr, n, zc, 1.0 / (h * h), oc, fbar, fshift, nullptr, phi_c, phi0_c, rr_c, nullptr,
-                nullptr, nullptr);
+                nullptr, nullptr, nullptr);
             break;
         case GR_KIND_HAMILTONIAN:
             k_march<M_RESTRICT, GR_KIND_HAMILTONIAN, double><<<grid, MNT, 0, s>>>(
                 phi, f, coef, nullptr, n, zc, 1.0 / (h * h), oc, fbar, fshift, nullptr, phi_c, phi0_c, rr_c, nullptr,
-                nullptr, nullptr);
+                nullptr, nullptr, nullptr);
             break;
         default:
             k_march<M_RESTRICT, GR_KIND_CMC, double><<<grid, MNT, 0, s>>>(
                 phi, f, coef, nullptr, n, zc, 1.0 / (h * h), oc, fbar, fshift, nullptr, phi_c, phi0_c, rr_c, nullptr,
-                nullptr, nullptr);
+                nullptr, nullptr, nullptr);
             break;
         }
         return;
@@ -1063,21 +1070,41 @@ void launch_ir_residual(int kind, hipStream_t s, const double *phi, const double
         if (kind == GR_KIND_POISSON)
             k_march<M_IR, GR_KIND_POISSON, double><<<grid, MNT, 0, s>>>(phi, f, coef, nullptr, n, zc, ih2, oc, fbar,
                                                                        fshift, partials, nullptr, nullptr, nullptr,
-                                                                       b32, a32, c32);
+                                                                       b32, a32, c32, nullptr);
         else if (kind == GR_KIND_HAMILTONIAN)
             k_march<M_IR, GR_KIND_HAMILTONIAN, double><<<grid, MNT, 0, s>>>(phi, f, coef, nullptr, n, zc, ih2, oc,
                                                                            fbar, fshift, partials, nullptr, nullptr,
-                                                                           nullptr, b32, a32, c32);
+                                                                           nullptr, b32, a32, c32, nullptr);
         else
             k_march<M_IR, GR_KIND_CMC, double><<<grid, MNT, 0, s>>>(phi, f, coef, nullptr, n, zc, ih2, oc, fbar,
                                                                    fshift, partials, nullptr, nullptr, nullptr, b32,
-                                                                   a32, c32);
+                                                                   a32, c32, nullptr);
         return;
     }
     Geo G;
     G.grid = dim3(kReduceBlocks);
     G.block = dim3(64, 4);
     GR_DISPATCH_KIND_G(kind, k_ir_residual, G, phi, f, coef, n, 1.0 / (h * h), oc, fbar, fshift, b32, a32, c32,
+                       partials);
+}
+
+// phi_out = phi + e and, for phi_out, the Poisson FP64 residual as FP32 b =
+// -eps and the stopping norms (one plane-marching pass when the level allows,
+// else an update pass and the residual pass)
+void launch_ir_update_residual(hipStream_t s, const double *phi, const float *e, double *phi_out, const double *f,
+                               int n, double h, OpConst oc, const double *fbar, const double *fshift, float *b32,
+                               double *partials)
+{
+    int zc = 0, grid = 0;
+    if (march_ok(n) && (grid = march_grid(n, kReduceBlocks, &zc)) > 0) {
+        k_march<M_IRU, GR_KIND_POISSON, double><<<grid, MNT, 0, s>>>(phi, f, nullptr, nullptr, n, zc, 1.0 / (h * h),
+                                                                    oc, fbar, fshift, partials, phi_out, nullptr,
+                                                                    nullptr, b32, nullptr, nullptr, e);
+        return;
+    }
+    const long N = (long)n * n * n;
+    k_add_f32_out<<<blocks_for(N), TPB, 0, s>>>(phi_out, phi, e, N);
+    launch_ir_residual(GR_KIND_POISSON, s, phi_out, f, nullptr, n, h, oc, fbar, fshift, b32, nullptr, nullptr,
                        partials);
 }
 
@@ -1126,15 +1153,15 @@ void launch_res_norms(int kind, hipStream_t s, const double *phi, const double *
         if (kind == GR_KIND_POISSON)
             k_march<M_NORMS, GR_KIND_POISSON, double><<<grid, MNT, 0, s>>>(phi, f, coef, nullptr, n, zc, ih2, oc, fbar,
                                                                           fshift, partials, nullptr, nullptr,
-                                                                          nullptr, nullptr, nullptr, nullptr);
+                                                                          nullptr, nullptr, nullptr, nullptr, nullptr);
         else if (kind == GR_KIND_HAMILTONIAN)
             k_march<M_NORMS, GR_KIND_HAMILTONIAN, double><<<grid, MNT, 0, s>>>(
                 phi, f, coef, nullptr, n, zc, ih2, oc, fbar, fshift, partials, nullptr, nullptr, nullptr, nullptr,
-                nullptr, nullptr);
+                nullptr, nullptr, nullptr);
         else
             k_march<M_NORMS, GR_KIND_CMC, double><<<grid, MNT, 0, s>>>(phi, f, coef, nullptr, n, zc, ih2, oc, fbar,
                                                                       fshift, partials, nullptr, nullptr, nullptr,
-                                                                      nullptr, nullptr, nullptr);
+                                                                      nullptr, nullptr, nullptr, nullptr);
         return;
     }
     Geo G;
