@@ -84,6 +84,7 @@ struct gr_grid_s {
     FusedCfg fcfg;
     FusedCfg tuned[kMaxLevels][6]; // per level and kind (0-2 FP64, 3-5 FP32), set by gr_autotune
     bool tuned_ok[kMaxLevels][6]{};
+    bool tuned_split[kMaxLevels][6]{}; // the tuner found one launch per colour faster
     int coarse_n = 8;      // levels with n <= coarse_n run in one single-workgroup launch
     int coarse_n32 = 8;    // the same for the FP32 correction cycles
     int skew = 0;          // workspace array skew in bytes (see layout)
@@ -283,6 +284,14 @@ const FusedCfg &fused_cfg(gr_grid g, int l, int kind)
     return g->tuned_ok[l][kind] ? g->tuned[l][kind] : g->fcfg;
 }
 
+// fused or one launch per colour on level l: the tuner's choice, else by size
+bool use_fused(gr_grid g, int l, int kind)
+{
+    if (!g->fused) return false;
+    if (g->tuned_ok[l][kind]) return !g->tuned_split[l][kind];
+    return fused_sweep_ok(g->lev[l].n, g->fcfg.min_n);
+}
+
 hipEvent_t pooled_event(gr_grid g)
 {
     if (!g->ev_free.empty()) {
@@ -322,7 +331,7 @@ int smooth(gr_grid g, const EqCtx &E, int l, int nsweeps)
     Level &L = g->lev[l];
     hipStream_t s = g->stream;
     if (nsweeps <= 0) return GR_OK;
-    if (!g->fused || !fused_sweep_ok(L.n, g->fcfg.min_n)) {
+    if (!use_fused(g, l, E.kind)) {
         for (int it = 0; it < nsweeps; ++it)
             launch_rb_sweep(E.kind, s, L.phi, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l));
         LAUNCHCHK();
@@ -476,7 +485,7 @@ int smooth32(gr_grid g, int lkind, int l, int nsweeps, OpConst oc, bool e_is_zer
     Level32 &V = g->lev32[l];
     hipStream_t s = g->stream;
     const double *zero = g->scal + S_ZERO;
-    if (!g->fused || !fused_sweep_ok(L.n, g->fcfg.min_n)) {
+    if (!use_fused(g, l, lkind)) {
         if (e_is_zero) launch_fill_f32(s, V.e, L.N);
         for (int it = 0; it < nsweeps; ++it) launch_rb_sweep_f32(lkind, s, V.e, V.b, V.c, V.a, L.n, L.h, oc, zero);
         LAUNCHCHK();
@@ -755,6 +764,7 @@ struct TuneEntry {
     int n, kind;
     FusedCfg cfg;
     float us;
+    bool split;
 };
 std::vector<TuneEntry> g_tune_cache;
 std::mutex g_tune_mu;
@@ -1124,19 +1134,22 @@ int gr_autotune(gr_grid g, char *report, size_t report_bytes)
     int st = GR_OK;
     for (int l = 0; l < g->nlev && st == GR_OK; ++l) {
         const Level &L = g->lev[l];
-        if (!g->fused || !fused_sweep_ok(L.n, g->fcfg.min_n)) continue;
+        // every level the fused sweep can tile (the size threshold is for untuned grids)
+        if (!g->fused || !fused_sweep_ok(L.n, 64)) continue;
         const long M = L.N;
         double *d = static_cast<double *>(g->cic); // scratch: 8 n^3 doubles
         float *fl = static_cast<float *>(g->cic);
         for (int kind = 0; kind < 6 && st == GR_OK; ++kind) {
             FusedCfg best = g->fcfg;
             float best_us = -1.f;
+            bool split = false;
             {
                 std::lock_guard<std::mutex> lk(g_tune_mu);
                 for (auto &e : g_tune_cache)
                     if (e.n == L.n && e.kind == kind) {
                         best = e.cfg;
                         best_us = e.us;
+                        split = e.split;
                     }
             }
             if (best_us < 0.f) {
@@ -1173,14 +1186,42 @@ int gr_autotune(gr_grid g, char *report, size_t report_bytes)
                             }
                         }
                 if (st != GR_OK) break;
+                { // one in-place launch per colour, for comparison
+                    auto sweep = [&]() {
+                        if (kind < 3)
+                            launch_rb_sweep(kind, s, d, d + 2 * M, d + 3 * M, L.n, L.h, oc, zero, zero);
+                        else
+                            launch_rb_sweep_f32(kind, s, fl, fl + 2 * M, fl + 3 * M, fl + 4 * M, L.n, L.h, oc, zero);
+                    };
+                    sweep();
+                    (void)hipEventRecord(e0, s);
+                    for (int r = 0; r < 4; ++r) sweep();
+                    (void)hipEventRecord(e1, s);
+                    hipError_t he = hipEventSynchronize(e1);
+                    if (he != hipSuccess) {
+                        st = fail(GR_EDEVICE, "autotune: %s", hipGetErrorString(he));
+                        break;
+                    }
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    const float us = ms * 1e3f / 4.f;
+                    if (us < best_us) {
+                        best_us = us;
+                        split = true;
+                    }
+                }
                 std::lock_guard<std::mutex> lk(g_tune_mu);
-                g_tune_cache.push_back({L.n, kind, best, best_us});
+                g_tune_cache.push_back({L.n, kind, best, best_us, split});
             }
             g->tuned[l][kind] = best;
             g->tuned_ok[l][kind] = true;
+            g->tuned_split[l][kind] = split;
             char line[160];
-            std::snprintf(line, sizeof line, "n=%d kind=%d tile=%s wgs=%d pf=%d us=%.2f\n", L.n, kind,
-                          best.tile ? "32x16" : "64x8", best.target_wgs, best.pf, best_us);
+            if (split)
+                std::snprintf(line, sizeof line, "n=%d kind=%d split us=%.2f\n", L.n, kind, best_us);
+            else
+                std::snprintf(line, sizeof line, "n=%d kind=%d tile=%s wgs=%d pf=%d us=%.2f\n", L.n, kind,
+                              best.tile ? "32x16" : "64x8", best.target_wgs, best.pf, best_us);
             rep += line;
         }
     }
