@@ -11,7 +11,9 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <functional>
 #include <mutex>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -75,6 +77,10 @@ struct gr_grid_s {
     double *alt[10]{}; // alternative (previous-step) guesses, saved by gr_set_guess
     bool alt_valid[10]{};
     double *gtmp = nullptr; // 3/4 of a fine array: cubic guess interpolation passes
+    // Helper hierarchies (levels, FP32 levels, reductions, stream) that solve
+    // components 1 and 2 of a vector equation concurrently with component 0.
+    bool solver_only = false;
+    gr_grid_s *sub[2]{};
     void *cic = nullptr;    // cell-ordered deposit scratch for up to n^3 particles
     double *partials = nullptr;
     double *scal = nullptr;
@@ -119,6 +125,7 @@ struct gr_grid_s {
     }
     ~gr_grid_s()
     {
+        for (auto *h : sub) delete h;
         drop_graphs();
         for (auto &e : sweep_ev) {
             (void)hipEventDestroy(e.a);
@@ -166,14 +173,16 @@ size_t layout(gr_grid g, char *base)
         return p;
     };
     const size_t fb = sizeof(double) * (size_t)g->N();
-    for (int f = 0; f < 10; ++f) g->field[f] = take(fb);
-    for (int s = 0; s < 5; ++s) g->src[s] = take(fb);
-    for (int c = 0; c < 6; ++c) g->A6[c] = take(fb);
-    g->AA = take(fb);
-    for (int c = 0; c < 3; ++c) g->fB[c] = take(fb);
-    for (int f = 0; f < 10; ++f) g->alt[f] = take(fb);
-    g->gtmp = take(3 * fb / 4);
-    g->cic = take(cic_sorted_bytes(g->N(), g->N()));
+    if (!g->solver_only) {
+        for (int f = 0; f < 10; ++f) g->field[f] = take(fb);
+        for (int s = 0; s < 5; ++s) g->src[s] = take(fb);
+        for (int c = 0; c < 6; ++c) g->A6[c] = take(fb);
+        g->AA = take(fb);
+        for (int c = 0; c < 3; ++c) g->fB[c] = take(fb);
+        for (int f = 0; f < 10; ++f) g->alt[f] = take(fb);
+        g->gtmp = take(3 * fb / 4);
+        g->cic = take(cic_sorted_bytes(g->N(), g->N()));
+    }
     for (int l = 0; l < g->nlev; ++l) {
         Level &L = g->lev[l];
         const size_t lb = sizeof(double) * (size_t)L.N;
@@ -194,6 +203,8 @@ size_t layout(gr_grid g, char *base)
     }
     g->partials = take(sizeof(double) * kReduceBlocks * 4);
     g->scal = take(sizeof(double) * S_NUM);
+    for (auto *h : g->sub)
+        if (h) off += align_up(layout(h, base ? base + off : nullptr));
     return off;
 }
 
@@ -709,21 +720,28 @@ int guess_residual(gr_grid g, int kind, double *phi, double *rel_out)
 // GR_GUESS_CHECKED: keep the held guess unless the saved alternative (the
 // previous-step field) has a smaller stopping quantity, or the held guess is
 // not finite; returns 1 when the alternative was taken.
-int choose_guess(gr_grid g, int kind, int fid, int *took_alt, double *rel_held, double *rel_alt)
+// on hierarchy h (whose fine source and coefficient are in place)
+int choose_guess_on(gr_grid h, int kind, double *phi, double *alt, bool valid, int *took_alt, double *rel_held,
+                    double *rel_alt)
 {
     *took_alt = 0;
-    if (!g->alt_valid[fid]) return GR_OK;
+    if (!valid) return GR_OK;
     double r_held = 0.0, r_alt = 0.0;
-    CHK(guess_residual(g, kind, g->field[fid], &r_held));
-    CHK(guess_residual(g, kind, g->alt[fid], &r_alt));
+    CHK(guess_residual(h, kind, phi, &r_held));
+    CHK(guess_residual(h, kind, alt, &r_alt));
     *rel_held = r_held;
     *rel_alt = r_alt;
     if (!(r_held < r_alt)) {
-        launch_copy(g->stream, g->field[fid], g->alt[fid], g->N());
+        launch_copy(h->stream, phi, alt, h->N());
         LAUNCHCHK();
         *took_alt = 1;
     }
     return GR_OK;
+}
+
+int choose_guess(gr_grid g, int kind, int fid, int *took_alt, double *rel_held, double *rel_alt)
+{
+    return choose_guess_on(g, kind, g->field[fid], g->alt[fid], g->alt_valid[fid], took_alt, rel_held, rel_alt);
 }
 
 int check_opts(const gr_solve_opts *o)
@@ -834,6 +852,34 @@ int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out)
         g->lev[l].h = desc->h * (double)(1 << l);
         g->lev[l].N = (long)g->lev[l].n * g->lev[l].n * g->lev[l].n;
     }
+    // GRMG_CONCURRENT=0: solve the components of vector equations one after another
+    bool conc = n >= 64;
+    if (const char *e = std::getenv("GRMG_CONCURRENT")) conc = conc && std::atoi(e) != 0;
+    if (conc)
+        for (auto &h : g->sub) {
+            h = new (std::nothrow) gr_grid_s();
+            if (!h) {
+                delete g;
+                return fail(GR_EINVAL, "out of host memory");
+            }
+            h->solver_only = true;
+            h->n = g->n;
+            h->h = g->h;
+            h->prm = g->prm;
+            h->nlev = g->nlev;
+            for (int l = 0; l < g->nlev; ++l) {
+                h->lev[l].n = g->lev[l].n;
+                h->lev[l].h = g->lev[l].h;
+                h->lev[l].N = g->lev[l].N;
+            }
+            h->fused = g->fused;
+            h->fcfg = g->fcfg;
+            h->coarse_n = g->coarse_n;
+            h->coarse_n32 = g->coarse_n32;
+            h->stall_ratio = g->stall_ratio;
+            h->use_graph = g->use_graph;
+            h->skew = g->skew;
+        }
     g->ws_bytes = layout(g, nullptr);
     *out = g;
     return GR_OK;
@@ -863,6 +909,18 @@ int gr_bind(gr_grid g, void *d_ws, size_t bytes, void *stream)
         HIPCHK(hipStreamCreateWithFlags(&g->work, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&g->ev_in, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&g->ev_out, hipEventDisableTiming));
+    }
+    for (auto *h : g->sub) {
+        if (!h) continue;
+        h->drop_graphs();
+        if (!h->work) {
+            HIPCHK(hipStreamCreateWithFlags(&h->work, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
+        }
+        h->user_stream = g->user_stream;
+        h->stream = g->user_stream;
+        h->bound = true;
     }
     layout(g, reinterpret_cast<char *>(d_ws));
     launch_fill(g->stream, reinterpret_cast<double *>(d_ws), (long)(g->ws_bytes / sizeof(double)), 0.0);
@@ -999,14 +1057,82 @@ int gr_solve_constraints(gr_grid g, const gr_solve_opts *opts, gr_solve_report *
         return GR_OK;
     };
 
+    // The three components of a vector equation: with helper hierarchies, each
+    // component's solve runs on its own stream and host thread (the small,
+    // latency-bound levels of the three V-cycles overlap); build(d, f) writes
+    // component d's source on this grid's stream.
+    auto solve3 = [&](int fid0, const std::function<int(int, double *)> &build) -> int {
+        gr_grid H[3] = {g, g->sub[0], g->sub[1]};
+        if (!g->sub[0] || !g->sub[1]) {
+            for (int d = 0; d < 3; ++d) {
+                if (!(mask & (1u << (fid0 + d)))) continue;
+                CHK(build(d, fine_f));
+                CHK(solve(fid0 + d, GR_KIND_POISSON));
+            }
+            return GR_OK;
+        }
+        for (int d = 0; d < 3; ++d)
+            if (mask & (1u << (fid0 + d))) CHK(build(d, H[d]->lev[0].f));
+        for (int d = 1; d < 3; ++d) { // helpers start after the sources
+            HIPCHK(hipEventRecord(H[d]->ev_in, s));
+            HIPCHK(hipStreamWaitEvent(H[d]->work, H[d]->ev_in, 0));
+            H[d]->stream = H[d]->work;
+        }
+        struct Out {
+            int st = GR_OK, cyc = 0, fb = 0, took = 0;
+            double rel = 0.0, grel = 0.0, arel = 0.0;
+            std::string err;
+        } out[3];
+        auto run = [&](int d) {
+            const int fid = fid0 + d;
+            if (!(mask & (1u << fid))) return;
+            gr_grid h = H[d];
+            Out &o = out[d];
+            o.st = [&]() -> int {
+                if (opts->guess == GR_GUESS_CHECKED)
+                    CHK(choose_guess_on(h, GR_KIND_POISSON, g->field[fid], g->alt[fid], g->alt_valid[fid], &o.took,
+                                        &o.grel, &o.arel));
+                return solve_field(h, GR_KIND_POISSON, g->field[fid], *opts, &o.cyc, &o.rel, &o.fb);
+            }();
+            if (o.st != GR_OK) o.err = g_err;
+        };
+        std::thread t1(run, 1), t2(run, 2);
+        run(0);
+        t1.join();
+        t2.join();
+        for (int d = 1; d < 3; ++d) { // this grid's stream waits for the helpers
+            (void)hipEventRecord(H[d]->ev_out, H[d]->work);
+            (void)hipStreamWaitEvent(s, H[d]->ev_out, 0);
+            H[d]->stream = H[d]->user_stream;
+        }
+        int dev = GR_OK;
+        for (int d = 0; d < 3; ++d) {
+            const int fid = fid0 + d;
+            if (!(mask & (1u << fid))) continue;
+            const Out &o = out[d];
+            R.cycles[fid] = o.cyc;
+            R.rel_res[fid] = o.rel;
+            R.fallback += o.fb;
+            R.guess_fallback += o.took;
+            R.guess_rel[fid] = o.grel;
+            R.alt_rel[fid] = o.arel;
+            g->alt_valid[fid] = false;
+            if (o.st != GR_OK) {
+                g_err = o.err;
+                if (o.st == GR_EDEVICE) dev = GR_EDEVICE;
+                else if (first_bad == GR_OK) first_bad = o.st;
+            }
+        }
+        return dev;
+    };
+
     // 1. V_i: Lap V_i = 3 Om a (s_i - <s_i>)
-    for (int d = 0; d < 3; ++d) {
-        if (!(mask & (1u << (GR_VX + d)))) continue;
-        CHK(reduce_mean(g, g->src[1 + d], nullptr, N, g->scal + S_SCRATCH));
-        launch_shift_scale(s, fine_f, g->src[1 + d], N, 3.0 * om * a, g->scal + S_SCRATCH);
+    CHK(solve3(GR_VX, [&](int d, double *f) -> int {
+        CHK(reduce_mean(g, g->src[1 + d], nullptr, N, g->scal + S_SCRATCH + d));
+        launch_shift_scale(s, f, g->src[1 + d], N, 3.0 * om * a, g->scal + S_SCRATCH + d);
         LAUNCHCHK();
-        CHK(solve(GR_VX + d, GR_KIND_POISSON));
-    }
+        return GR_OK;
+    }));
     // 2. U: Lap U = -1/4 d_j V^j
     launch_div_quarter(s, fine_f, g->field[GR_VX], g->field[GR_VY], g->field[GR_VZ], g->n, g->h);
     LAUNCHCHK();
@@ -1025,12 +1151,11 @@ int gr_solve_constraints(gr_grid g, const gr_solve_opts *opts, gr_solve_report *
     // 6. B^i: Lap B^i = 2 d_j[alpha chi^-6 A^ij]
     launch_shift_source(s, g->fB, g->field[GR_PSI], g->field[GR_XI], g->A6, g->n, g->h, a, c);
     LAUNCHCHK();
-    for (int d = 0; d < 3; ++d) {
-        if (!(mask & (1u << (GR_BX + d)))) continue;
-        launch_copy(s, fine_f, g->fB[d], N);
+    CHK(solve3(GR_BX, [&](int d, double *f) -> int {
+        launch_copy(s, f, g->fB[d], N);
         LAUNCHCHK();
-        CHK(solve(GR_BX + d, GR_KIND_POISSON));
-    }
+        return GR_OK;
+    }));
     // 7. b: Lap b = -1/4 d_j B^j
     launch_div_quarter(s, fine_f, g->field[GR_BX], g->field[GR_BY], g->field[GR_BZ], g->n, g->h);
     LAUNCHCHK();
@@ -1229,6 +1354,13 @@ int gr_autotune(gr_grid g, char *report, size_t report_bytes)
     (void)hipEventDestroy(e1);
     LAUNCHCHK();
     g->drop_graphs(); // captured cycles hold the old launch shapes
+    for (auto *h : g->sub)
+        if (h) {
+            std::memcpy(h->tuned, g->tuned, sizeof g->tuned);
+            std::memcpy(h->tuned_ok, g->tuned_ok, sizeof g->tuned_ok);
+            std::memcpy(h->tuned_split, g->tuned_split, sizeof g->tuned_split);
+            h->drop_graphs();
+        }
     if (report && report_bytes) {
         std::snprintf(report, report_bytes, "%s", rep.c_str());
     }

@@ -11,15 +11,17 @@ __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >
 
 __device__ __forceinline__ long lin(int i, int j, int k, int n) { return ((long)k * n + j) * n + i; }
 
-// Sum of the six face neighbours of (i,j,k) with periodic wrap.
+// Sum of the six face neighbours of (i,j,k) with periodic wrap, added as
+// x-, x+, y-, y+, z-, z+: the order of the LDS-tiled sweeps and residuals, so
+// every smoother launch shape rounds alike.
 template <typename T>
 __device__ __forceinline__ T nb_sum(const T *__restrict__ p, int i, int j, int k, int n)
 {
     int ip = wrapi(i + 1, n), im = wrapi(i - 1, n);
     int jp = wrapi(j + 1, n), jm = wrapi(j - 1, n);
     int kp = wrapi(k + 1, n), km = wrapi(k - 1, n);
-    return p[lin(ip, j, k, n)] + p[lin(im, j, k, n)] + p[lin(i, jp, k, n)] + p[lin(i, jm, k, n)]
-         + p[lin(i, j, kp, n)] + p[lin(i, j, km, n)];
+    return p[lin(im, j, k, n)] + p[lin(ip, j, k, n)] + p[lin(i, jm, k, n)] + p[lin(i, jp, k, n)]
+         + p[lin(i, j, km, n)] + p[lin(i, j, kp, n)];
 }
 
 // number of coefficient arrays an operator reads
