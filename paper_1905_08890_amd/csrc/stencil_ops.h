@@ -54,8 +54,11 @@ __device__ __forceinline__ T op_point(T ph, T nbs, T inv_h2, T c1, T c2, OpConst
         const double chi2 = chi * chi;
         const double chi5 = chi2 * chi2 * chi;
         const double chi6 = chi5 * chi;
-        const double chim6 = 1.0 / chi6;
-        const double chim7 = chim6 / chi;
+        // one FP64 division per point: negative powers from 1/chi by products
+        const double r = 1.0 / chi;
+        const double r2 = r * r;
+        const double chim6 = r2 * r2 * r2;
+        const double chim7 = chim6 * r;
         J = -kap * lap - 6.0 * chi * inv_h2 - 6.0 * A * kap * chi5 - 1.5 * kap * c1 * chim7 - kap * Fbar;
         return chi * lap + A * (chi6 - 1.0) - 0.25 * c1 * chim6 + Fbar * chi;
     }
