@@ -256,6 +256,38 @@ typedef struct gr_batch_s *gr_batch;
 /* Create a batch of `count` (1..4096) boxes described by descs[count], all
  * with the same code-unit parameters.  Host memory only. */
 int gr_create_batch(const gr_grid_desc *descs, int count, const gr_params *prm, gr_batch *out);
+
+/* A Dirichlet refinement patch (the refined levels of sec. 3, whose boundary
+ * values come from the coarser level): n^3 cells (3 <= n <= 512) of spacing
+ * h (0 < h <= 1e3) whose lower corner sits at origin[x,y,z] (box units,
+ * |origin| <= 1e6) in the frame of the periodic box `parent` of the same
+ * batch.  Anything else: GR_EINVAL.
+ * Readings: levels halve while n is even and n/2 >= 3 (24..80 in steps of 8
+ * end at 3, 4, 5, 3, 7, 4, 9, 5 cells); on every level the boundary value of
+ * each boundary face is the parent's solved field at the face centre by
+ * cell-centred trilinear interpolation (periodic in the parent), and the
+ * 7-point stencil of a boundary cell takes 2b - phi_cell across that face;
+ * the equations are the plain discrete ones (no regularisation terms, no
+ * mean removed from the momentum sources, no zero-mean pin: those exist for
+ * the periodic boundary, sec. 4.3.1-4.3.2); the coarsest level gets 32
+ * red-black sweeps with no mean projection; the prolonged correction is odd
+ * across every face.  Difference stencils of the source builders that reach
+ * outside the patch read the parent's fields (and its A_ij) at those cells'
+ * centres. */
+typedef struct {
+    int n;
+    double h;
+    int parent;
+    double origin[3];
+} gr_patch_desc;
+
+/* A batch of nbox periodic boxes (items 0..nbox-1) and npatch patches (items
+ * nbox..nbox+npatch-1), nbox + npatch <= 4096.  gr_batch_solve solves each
+ * field of the patches right after that field of the boxes.  set/get_field
+ * on a patch item move dense n^3 arrays (solved fields are stored padded
+ * internally). */
+int gr_create_batch_patches(const gr_grid_desc *boxes, int nbox, const gr_patch_desc *patches, int npatch,
+                            const gr_params *prm, gr_batch *out);
 int gr_batch_workspace_bytes(gr_batch b, size_t *bytes);
 /* Bind caller-owned device memory and a hipStream_t; zero-fills everything. */
 int gr_batch_bind(gr_batch b, void *d_workspace, size_t bytes, void *hip_stream);
@@ -268,6 +300,11 @@ int gr_batch_get_field(gr_batch b, int item, int field, void *d_dst, int dtype);
  * time from the start of each field's solve until the box met its tolerance,
  * summed over the fields).  Returns the first non-OK box status. */
 int gr_batch_solve(gr_batch b, const gr_solve_opts *opts, int *cycles, double *rel_res, double *item_seconds);
+/* Low level, for checks of the boundary values: writes the boundary values of
+ * every level of every patch from their parents' current `field`, then copies
+ * level `level` of patch `item`'s iterate, padded ((n_l+2)^3, x fastest; the
+ * cells across the faces hold the boundary values) to d_dst. */
+int gr_batch_debug_boundary(gr_batch b, int item, int field, int level, double *d_dst);
 int gr_destroy_batch(gr_batch b);
 const char *gr_batch_last_error(void);
 

@@ -1,4 +1,6 @@
-// Batched solve of many independent periodic boxes of uneven size.
+// Batched solve of many independent periodic boxes of uneven size, and of
+// Dirichlet refinement patches whose boundary values come from a box of the
+// same batch (patch_ops.h).
 //
 // Every phase of the multigrid cycle is one launch over all boxes: a prefix
 // table maps each block to its box, and each box's slice of the launch works
@@ -21,6 +23,7 @@
 #include <vector>
 
 #include "sources_ops.h"
+#include "patch_ops.h"
 #include "fused_sweep.h"
 #include "march.h"
 
@@ -42,6 +45,9 @@ struct BoxLev {
 struct BoxDev {
     int nlev;
     int centry; // first level handled by the single-workgroup coarse cycle
+    int patch;  // 1: Dirichlet patch (padded iterate arrays), 0: periodic box
+    int parent; // patch: index of the periodic box its boundary values come from
+    double origin[3]; // patch: lower corner in the parent's frame (box units)
     double *field[10];
     double *src[5];
     double *A6[6];
@@ -60,7 +66,7 @@ struct BatchDev {
     int *cycles;    // [nbox][10]
     int *status;    // [nbox]
     unsigned long long *t_done; // [nbox][10] device clock at convergence
-    unsigned long long *t_start; // [10]
+    unsigned long long *t_start; // [20]: periodic boxes' fields, then patches' fields
     int *any_active;
     double *partials;
     int nbox;
@@ -366,11 +372,11 @@ __global__ void __launch_bounds__(TPB) kb_rr_m(BatchDev D, const int *__restrict
     C.tmp[t] = sr / 8.0;
 }
 
-// per box: slot[c] = add_slot + scale/N * sum of the box's block partials of component c
+// per item b0 + blockIdx.x: slot[c] = add_slot + 1/N * sum of its block partials of component c
 __global__ void __launch_bounds__(TPB) kb_finalize(BatchDev D, const int *__restrict__ tab, int ncomp, int slot,
-                                                   int add_slot, int active_only)
+                                                   int add_slot, int active_only, int b0)
 {
-    const int b = blockIdx.x;
+    const int b = b0 + blockIdx.x;
     if (active_only && !D.active[b]) return;
     const int total = tab[D.nbox];
     const int n = D.box[b].lev[0].n;
@@ -400,14 +406,15 @@ __global__ void __launch_bounds__(TPB) kb_sub_mean(BatchDev D, const int *__rest
     if (t < n * n * n) X.field[fid][t] -= D.scal[b * B_NSCAL + B_MEAN];
 }
 
-// Stopping test per box (same criterion as the single-grid solver) and the
-// cycle count; marks converged boxes inactive with the device clock time.
-__global__ void kb_control(BatchDev D, int fid, double rtol, int max_cycles)
+// Stopping test per item of [b0, b1) (same criterion as the single-grid
+// solver) and the cycle count; marks converged items inactive with the device
+// clock time.
+__global__ void kb_control(BatchDev D, int fid, double rtol, int max_cycles, int b0, int b1)
 {
     __shared__ int any;
     if (threadIdx.x == 0) any = 0;
     __syncthreads();
-    for (int b = threadIdx.x; b < D.nbox; b += blockDim.x) {
+    for (int b = b0 + threadIdx.x; b < b1; b += blockDim.x) {
         if (!D.active[b]) continue;
         double *s = D.scal + b * B_NSCAL;
         const double rn = sqrt(s[B_RN]), fn = sqrt(s[B_FN]);
@@ -435,16 +442,17 @@ __global__ void kb_control(BatchDev D, int fid, double rtol, int max_cycles)
     if (threadIdx.x == 0) *D.any_active = any;
 }
 
-__global__ void kb_begin_field(BatchDev D, int fid)
+// items [b0, b1) start solving field fid; clock slot ts (fid or 10 + fid)
+__global__ void kb_begin_field(BatchDev D, int fid, int b0, int b1, int ts)
 {
-    for (int b = threadIdx.x; b < D.nbox; b += blockDim.x) {
+    for (int b = b0 + threadIdx.x; b < b1; b += blockDim.x) {
         D.active[b] = 1;
         D.cycles[b * 10 + fid] = 0;
         double *s = D.scal + b * B_NSCAL;
         s[B_FBAR] = 0.0;
         s[B_FSHIFT] = 0.0;
     }
-    if (threadIdx.x == 0) D.t_start[fid] = wall_clock64();
+    if (threadIdx.x == 0) D.t_start[ts] = wall_clock64();
 }
 
 // ------------------------------------------------------------- builders
@@ -619,6 +627,332 @@ __global__ void __launch_bounds__(CTPB) kb_coarse_vcycle(BatchDev D, int fid, in
     }
 }
 
+// ------------------------------------------------- Dirichlet patches
+//
+// Same phases as the periodic boxes, one launch per phase over all patches
+// (prefix tables over the patch items), one thread per cell.  Iterate arrays
+// are padded (patch_ops.h); everything else is dense n^3.
+
+__device__ __forceinline__ double *patch_phi(const BoxDev &X, int d, int fid)
+{
+    return d == 0 ? X.field[fid] : X.lev[d].phi;
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(TPB) kp_colour(BatchDev D, const int *__restrict__ tab, int d, int fid, int colour,
+                                                 OpConst oc)
+{
+    BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
+    const BoxLev &L = X.lev[d];
+    const int n = L.n;
+    if (t >= n * n * n) return;
+    int i, j, k;
+    decode3(t, n, n, i, j, k);
+    if (((i + j + k) & 1) != colour) return;
+    double *phi = patch_phi(X, d, fid);
+    double J;
+    const double Lv = patch_op<KIND>(phi, i, j, k, n, 1.0 / (L.h * L.h), load_c1<KIND>(L.coef, t), oc, J);
+    const long p = pidx(i, j, k, n);
+    phi[p] = phi[p] - (Lv - L.f[t]) / J;
+}
+
+// residual at the 8 children, its mean, and the children's mean of phi (R phi,
+// also kept as phi0): one thread per interior cell of level d+1
+template <int KIND>
+__global__ void __launch_bounds__(TPB) kp_rr(BatchDev D, const int *__restrict__ tab, int d, int fid, OpConst oc)
+{
+    BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
+    const BoxLev &V = X.lev[d], &C = X.lev[d + 1];
+    const int n = V.n, m = C.n;
+    if (t >= m * m * m) return;
+    int I, J, K;
+    decode3(t, m, m, I, J, K);
+    const double *phi = patch_phi(X, d, fid);
+    const double inv_h2 = 1.0 / (V.h * V.h);
+    double sr = 0.0, sp = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        const int i = 2 * I + (c & 1), j = 2 * J + ((c >> 1) & 1), k = 2 * K + (c >> 2);
+        const long q = lin(i, j, k, n);
+        double Jd;
+        sr += patch_op<KIND>(phi, i, j, k, n, inv_h2, load_c1<KIND>(V.coef, q), oc, Jd) - V.f[q];
+        sp += phi[pidx(i, j, k, n)];
+    }
+    const double rp = sp / 8.0;
+    C.phi[pidx(I, J, K, m)] = rp;
+    C.phi0[t] = rp;
+    C.tmp[t] = sr / 8.0;
+}
+
+// FAS source of level d+1: f^H = L^H(R phi) - R eps, with the level's face values
+template <int KIND>
+__global__ void __launch_bounds__(TPB) kp_coarse_rhs(BatchDev D, const int *__restrict__ tab, int d, OpConst oc)
+{
+    BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
+    const BoxLev &C = X.lev[d + 1];
+    const int m = C.n;
+    if (t >= m * m * m) return;
+    int I, J, K;
+    decode3(t, m, m, I, J, K);
+    double Jd;
+    C.f[t] = patch_op<KIND>(C.phi, I, J, K, m, 1.0 / (C.h * C.h), load_c1<KIND>(C.coef, t), oc, Jd) - C.tmp[t];
+}
+
+// phi^h += P(phi^H - R phi), the correction odd across every face: one
+// thread per interior cell of level d
+__global__ void __launch_bounds__(TPB) kp_prolong(BatchDev D, const int *__restrict__ tab, int d, int fid)
+{
+    BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
+    const BoxLev &V = X.lev[d], &C = X.lev[d + 1];
+    const int n = V.n, m = C.n;
+    if (t >= n * n * n) return;
+    int i, j, k;
+    decode3(t, n, n, i, j, k);
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const int Is[2] = {I, I + ((i & 1) ? 1 : -1)};
+    const int Js[2] = {J, J + ((j & 1) ? 1 : -1)};
+    const int Ks[2] = {K, K + ((k & 1) ? 1 : -1)};
+    double v = 0.0;
+    for (int c = 0; c < 8; ++c) {
+        const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+        const double w = (ox ? 0.25 : 0.75) * (oy ? 0.25 : 0.75) * (oz ? 0.25 : 0.75);
+        double sign = 1.0;
+        const int x = reflect_in(Is[ox], m, sign), y = reflect_in(Js[oy], m, sign), z = reflect_in(Ks[oz], m, sign);
+        v += w * (sign * (C.phi[pidx(x, y, z, m)] - C.phi0[lin(x, y, z, m)]));
+    }
+    patch_phi(X, d, fid)[pidx(i, j, k, n)] += v;
+}
+
+// coefficient restriction level d -> d+1 (once per solve of an equation)
+__global__ void __launch_bounds__(TPB) kp_restrict_coef(BatchDev D, const int *__restrict__ tab, int d)
+{
+    BOX_PROLOGUE(tab)
+    const BoxLev &V = X.lev[d], &C = X.lev[d + 1];
+    const int m = C.n, n = V.n;
+    if (t >= m * m * m) return;
+    int I, J, K;
+    decode3(t, m, m, I, J, K);
+    double s = 0.0;
+    for (int c = 0; c < 8; ++c) s += V.coef[lin(2 * I + (c & 1), 2 * J + ((c >> 1) & 1), 2 * K + (c >> 2), n)];
+    C.coef[t] = s / 8.0;
+}
+
+// stopping norms of the finest level: block partials of eps^2 and f^2
+template <int KIND>
+__global__ void __launch_bounds__(TPB) kp_norms(BatchDev D, const int *__restrict__ tab, int fid, OpConst oc)
+{
+    BOX_PROLOGUE(tab)
+    const int total = tab[D.nbox];
+    const BoxLev &L = X.lev[0];
+    const int n = L.n;
+    double v[2] = {0.0, 0.0};
+    if (D.active[b] && t < n * n * n) {
+        int i, j, k;
+        decode3(t, n, n, i, j, k);
+        double Jd;
+        const double e = patch_op<KIND>(X.field[fid], i, j, k, n, 1.0 / (L.h * L.h), load_c1<KIND>(L.coef, t), oc,
+                                        Jd) - L.f[t];
+        v[0] = e * e;
+        v[1] = L.f[t] * L.f[t];
+    }
+    block_store<2>(v, D.partials, total);
+}
+
+// boundary values of level d of every patch: the parent's field `fid` at the
+// face centres, one thread per padded cell (face cells written; edge and
+// corner cells are never read)
+__global__ void __launch_bounds__(TPB) kp_faces(BatchDev D, const int *__restrict__ tab, int d, int fid)
+{
+    BOX_PROLOGUE(tab)
+    const BoxLev &L = X.lev[d];
+    const int n = L.n, W = n + 2;
+    if (t >= W * W * W) return;
+    int a, bb, c;
+    decode3(t, W, W, a, bb, c);
+    const int i = a - 1, j = bb - 1, k = c - 1;
+    const int out = (i < 0 || i >= n) + (j < 0 || j >= n) + (k < 0 || k >= n);
+    if (out != 1) return;
+    auto u = [n](int q) { return q < 0 ? 0.0 : (q >= n ? (double)n : q + 0.5); }; // face-clamped coordinate
+    const BoxDev &P = D.box[X.parent];
+    const double val = sample_periodic(P.field[fid], P.lev[0].n, P.lev[0].h, X.origin[0] + u(i) * L.h,
+                                       X.origin[1] + u(j) * L.h, X.origin[2] + u(k) * L.h);
+    patch_phi(X, d, fid)[t] = val;
+}
+
+// interior := 0 (zero guess)
+__global__ void __launch_bounds__(TPB) kp_fill_field(BatchDev D, const int *__restrict__ tab, int fid)
+{
+    BOX_PROLOGUE(tab)
+    const int n = X.lev[0].n;
+    if (t >= n * n * n) return;
+    int i, j, k;
+    decode3(t, n, n, i, j, k);
+    X.field[fid][pidx(i, j, k, n)] = 0.0;
+}
+
+// Source builders of the patches, the periodic builders' arithmetic through
+// patch field accessors (outside the patch: the parent's field at the cell
+// centre).  what: 0 V_i source 3 Om a s_i (no mean removed), 1 -1/4 d.V,
+// 2 A_ij/AA + Hamiltonian source + coefficient, 3 CMC coefficient/source,
+// 4 shift sources, 5 -1/4 d.B, 6 copy fB[comp] to f
+__global__ void __launch_bounds__(TPB) kp_build(BatchDev D, const int *__restrict__ tab, int what, int comp, double a,
+                                                double om, double c)
+{
+    BOX_PROLOGUE(tab)
+    const BoxLev &L = X.lev[0];
+    const int n = L.n;
+    if (t >= n * n * n) return;
+    int x, y, z;
+    decode3(t, n, n, x, y, z);
+    const BoxDev &P = D.box[X.parent];
+    auto F = [&](const double *mine, int padded, const double *theirs) {
+        return PatchField{mine, padded, n, L.h, X.origin[0], X.origin[1], X.origin[2], theirs, P.lev[0].n, P.lev[0].h};
+    };
+    auto FF = [&](int f) { return F(X.field[f], 1, P.field[f]); };
+    const double inv2h = 1.0 / (2.0 * L.h);
+    switch (what) {
+    case 0: L.f[t] = (3.0 * om * a) * X.src[1 + comp][t]; break;
+    case 1: L.f[t] = div_quarter_f(FF(GR_VX), FF(GR_VY), FF(GR_VZ), x, y, z, inv2h); break;
+    case 2: {
+        double A[6];
+        const double aa = aij_f(FF(GR_VX), FF(GR_VY), FF(GR_VZ), FF(GR_U), x, y, z, L.h, A);
+        for (int k = 0; k < 6; ++k) X.A6[k][t] = A[k];
+        X.AA[t] = aa;
+        L.coef[t] = aa;
+        L.f[t] = (1.5 * a * om) * (X.src[0][t] - 1.0);
+        break;
+    }
+    case 3:
+        cmc_point(X.field[GR_PSI][pidx(x, y, z, n)], X.src[0][t], X.src[4][t], X.AA[t], a, om, c, L.coef[t], L.f[t]);
+        break;
+    case 4: {
+        const PatchField A[6] = {F(X.A6[0], 0, P.A6[0]), F(X.A6[1], 0, P.A6[1]), F(X.A6[2], 0, P.A6[2]),
+                                 F(X.A6[3], 0, P.A6[3]), F(X.A6[4], 0, P.A6[4]), F(X.A6[5], 0, P.A6[5])};
+        double out[3];
+        shift_source_f(FF(GR_PSI), FF(GR_XI), A, x, y, z, L.h, a, c, out);
+        X.fB[0][t] = out[0];
+        X.fB[1][t] = out[1];
+        X.fB[2][t] = out[2];
+        break;
+    }
+    case 5: L.f[t] = div_quarter_f(FF(GR_BX), FF(GR_BY), FF(GR_BZ), x, y, z, inv2h); break;
+    default: L.f[t] = X.fB[comp][t]; break;
+    }
+}
+
+// dense n^3 <-> interior of a padded (n+2)^3 array
+template <typename T>
+__global__ void __launch_bounds__(TPB) kp_pad_in(double *__restrict__ dst, const T *__restrict__ src, int n)
+{
+    const long t = (long)blockIdx.x * TPB + threadIdx.x;
+    if (t >= (long)n * n * n) return;
+    int i, j, k;
+    decode3((int)t, n, n, i, j, k);
+    dst[pidx(i, j, k, n)] = (double)src[t];
+}
+template <typename T>
+__global__ void __launch_bounds__(TPB) kp_pad_out(T *__restrict__ dst, const double *__restrict__ src, int n)
+{
+    const long t = (long)blockIdx.x * TPB + threadIdx.x;
+    if (t >= (long)n * n * n) return;
+    int i, j, k;
+    decode3((int)t, n, n, i, j, k);
+    dst[t] = (T)src[pidx(i, j, k, n)];
+}
+
+// The rest of the V-cycle of each active patch from its entry level, one
+// workgroup per patch (item b0 + blockIdx.x).
+template <int KIND>
+__device__ void cvp_sweep(double *__restrict__ phi, const double *__restrict__ f, const double *__restrict__ coef,
+                          int n, double inv_h2, OpConst oc)
+{
+    const int N = n * n * n;
+    for (int colour = 0; colour < 2; ++colour) {
+        for (int t = threadIdx.x; t < N; t += CTPB) {
+            const int i = t % n, j = (t / n) % n, k = t / (n * n);
+            if (((i + j + k) & 1) != colour) continue;
+            double J;
+            const double Lv = patch_op<KIND>(phi, i, j, k, n, inv_h2, load_c1<KIND>(coef, t), oc, J);
+            const long p = pidx(i, j, k, n);
+            phi[p] = phi[p] - (Lv - f[t]) / J;
+        }
+        __syncthreads();
+    }
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(CTPB) kp_coarse_vcycle(BatchDev D, int fid, int nu1, int nu2, OpConst oc, int b0)
+{
+    const int b = b0 + blockIdx.x;
+    if (!D.active[b]) return;
+    const BoxDev &X = D.box[b];
+    const int l0 = X.centry, L = X.nlev;
+    for (int i = l0; i < L - 1; ++i) {
+        const BoxLev &V = X.lev[i], &C = X.lev[i + 1];
+        const int n = V.n, m = C.n, M = m * m * m;
+        double *phi = patch_phi(X, i, fid);
+        const double inv_h2 = 1.0 / (V.h * V.h);
+        for (int it = 0; it < nu1; ++it) cvp_sweep<KIND>(phi, V.f, V.coef, n, inv_h2, oc);
+        for (int q = threadIdx.x; q < M; q += CTPB) {
+            const int I = q % m, J = (q / m) % m, K = q / (m * m);
+            double sr = 0.0, sp = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                const int a = 2 * I + (c & 1), bb = 2 * J + ((c >> 1) & 1), dd = 2 * K + (c >> 2);
+                const long r = lin(a, bb, dd, n);
+                double Jd;
+                sr += patch_op<KIND>(phi, a, bb, dd, n, inv_h2, load_c1<KIND>(V.coef, r), oc, Jd) - V.f[r];
+                sp += phi[pidx(a, bb, dd, n)];
+            }
+            const double rp = sp / 8.0;
+            C.phi[pidx(I, J, K, m)] = rp;
+            C.phi0[q] = rp;
+            C.tmp[q] = sr / 8.0;
+        }
+        __syncthreads();
+        const double inv_H2 = 1.0 / (C.h * C.h);
+        for (int q = threadIdx.x; q < M; q += CTPB) {
+            const int I = q % m, J = (q / m) % m, K = q / (m * m);
+            double Jd;
+            C.f[q] = patch_op<KIND>(C.phi, I, J, K, m, inv_H2, load_c1<KIND>(C.coef, q), oc, Jd) - C.tmp[q];
+        }
+        __syncthreads();
+    }
+    {
+        const BoxLev &V = X.lev[L - 1];
+        double *phi = patch_phi(X, L - 1, fid);
+        const double inv_h2 = 1.0 / (V.h * V.h);
+        for (int it = 0; it < kCoarseSweeps; ++it) cvp_sweep<KIND>(phi, V.f, V.coef, V.n, inv_h2, oc);
+    }
+    for (int i = L - 2; i >= l0; --i) {
+        const BoxLev &V = X.lev[i], &C = X.lev[i + 1];
+        const int n = V.n, m = C.n, N = n * n * n;
+        double *phi = patch_phi(X, i, fid);
+        const double inv_h2 = 1.0 / (V.h * V.h);
+        for (int p = threadIdx.x; p < N; p += CTPB) {
+            const int a = p % n, bb = (p / n) % n, dd = p / (n * n);
+            const int I = a >> 1, J = bb >> 1, K = dd >> 1;
+            const int Is[2] = {I, I + ((a & 1) ? 1 : -1)};
+            const int Js[2] = {J, J + ((bb & 1) ? 1 : -1)};
+            const int Ks[2] = {K, K + ((dd & 1) ? 1 : -1)};
+            double v = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+                const double w = (ox ? 0.25 : 0.75) * (oy ? 0.25 : 0.75) * (oz ? 0.25 : 0.75);
+                double sign = 1.0;
+                const int x = reflect_in(Is[ox], m, sign), y = reflect_in(Js[oy], m, sign),
+                          z = reflect_in(Ks[oz], m, sign);
+                v += w * (sign * (C.phi[pidx(x, y, z, m)] - C.phi0[lin(x, y, z, m)]));
+            }
+            phi[pidx(a, bb, dd, n)] += v;
+        }
+        __syncthreads();
+        for (int it = 0; it < nu2; ++it) cvp_sweep<KIND>(phi, V.f, V.coef, n, inv_h2, oc);
+    }
+}
+
 // ------------------------------------------------------------------- host
 
 thread_local std::string b_err;
@@ -673,7 +1007,8 @@ struct Tab {
 };
 
 struct gr_batch_s {
-    int nbox = 0;
+    int nbox = 0;               // items: periodic boxes [0, nper), then patches [nper, nbox)
+    int nper = 0, npatch = 0;
     gr_params prm{};
     int coarse_n = 16;
     std::vector<BoxDev> host;   // pointers into the workspace
@@ -690,8 +1025,15 @@ struct gr_batch_s {
     hipStream_t stream = nullptr;
     bool bound = false;
     bool use_graph = true;
-    hipGraphExec_t graph[10]{};     // per field: the captured cycle sequence
-    gr_solve_opts graph_opts[10]{}; // options it was captured with
+    hipGraphExec_t graph[20]{};     // per field: the captured cycle sequence (10 + field: patches)
+    gr_solve_opts graph_opts[20]{}; // options it was captured with
+    // patches: levels handled by grouped launches (depth < pmaxdepth), all levels (< pmaxlev)
+    int pmaxdepth = 0, pmaxlev = 0;
+    Tab pfine;                                  // interior cells of level 0
+    std::vector<Tab> pcell;                     // per level: interior cells (levels below a patch's entry)
+    std::vector<Tab> pcoarse;                   // per depth d: interior cells of level d + 1 (grouped levels)
+    std::vector<Tab> pcoefr;                    // per depth d: interior cells of level d + 1 (all levels)
+    std::vector<Tab> pfaces;                    // per level: padded cells
     std::vector<double> rel_hist;   // [nbox][10] final relative residual per field
     double clock_khz = 0.0;
     long total_points = 0;
@@ -714,7 +1056,9 @@ size_t batch_layout(gr_batch B, char *base)
     for (int b = 0; b < B->nbox; ++b) {
         BoxDev &X = B->host[b];
         const long N = (long)X.lev[0].n * X.lev[0].n * X.lev[0].n;
-        for (int f = 0; f < 10; ++f) X.field[f] = takeD(N);
+        // iterate arrays of a patch carry a one-cell padding for the boundary values
+        auto iter_len = [&](int n) { const long w = X.patch ? n + 2 : n; return w * w * w; };
+        for (int f = 0; f < 10; ++f) X.field[f] = takeD(iter_len(X.lev[0].n));
         for (int s = 0; s < 5; ++s) X.src[s] = takeD(N);
         for (int c = 0; c < 6; ++c) X.A6[c] = takeD(N);
         X.AA = takeD(N);
@@ -722,7 +1066,7 @@ size_t batch_layout(gr_batch B, char *base)
         for (int l = 0; l < X.nlev; ++l) {
             BoxLev &L = X.lev[l];
             const long M = (long)L.n * L.n * L.n;
-            L.phi = l == 0 ? nullptr : takeD(M);
+            L.phi = l == 0 ? nullptr : takeD(iter_len(L.n));
             L.phi0 = takeD(M);
             L.f = takeD(M);
             L.coef = takeD(M);
@@ -736,9 +1080,9 @@ size_t batch_layout(gr_batch B, char *base)
     B->D.cycles = takeI((size_t)B->nbox * 10);
     B->D.status = takeI(B->nbox);
     B->D.t_done = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * B->nbox * 10));
-    B->D.t_start = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * 10));
+    B->D.t_start = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * 20));
     B->D.any_active = takeI(1);
-    B->D.partials = takeD((size_t)B->fine.total() * 2 + 16);
+    B->D.partials = takeD((size_t)std::max(B->fine.total(), B->pfine.total()) * 2 + 16);
     B->fine.dev = takeI(B->nbox + 1);
     B->norms.dev = takeI(B->nbox + 1);
     for (int d = 0; d < B->maxdepth; ++d) {
@@ -749,6 +1093,9 @@ size_t batch_layout(gr_batch B, char *base)
         B->colour_nf[d].dev = takeI(B->nbox + 1);
     }
     for (size_t d = 0; d < B->coefr.size(); ++d) B->coefr[d].dev = takeI(B->nbox + 1);
+    B->pfine.dev = takeI(B->nbox + 1);
+    for (auto *v : {&B->pcell, &B->pcoarse, &B->pcoefr, &B->pfaces})
+        for (auto &T : *v) T.dev = takeI(B->nbox + 1);
     return off;
 }
 
@@ -778,7 +1125,7 @@ int batch_pin(gr_batch B, int fid, int active_only)
 {
     hipStream_t s = B->stream;
     kb_sum<<<B->fine.total(), TPB, 0, s>>>(B->D, B->fine.dev, fid, 0, opc(B), active_only);
-    kb_finalize<<<B->nbox, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_MEAN, -1, active_only);
+    kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_MEAN, -1, active_only, 0);
     kb_sub_mean<<<B->fine.total(), TPB, 0, s>>>(B->D, B->fine.dev, fid, active_only);
     BLAUNCH();
     return GR_OK;
@@ -808,14 +1155,14 @@ int batch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
     const int FT = B->fine.total();
     if (kind == GR_KIND_HAMILTONIAN) {
         kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid, 1, oc, 1);
-        kb_finalize<<<B->nbox, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FBAR, -1, 1);
+        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FBAR, -1, 1, 0);
     } else if (kind == GR_KIND_CMC) {
         kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid, 2, oc, 1);
-        kb_finalize<<<B->nbox, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FSHIFT, B_FMEAN, 1);
+        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FSHIFT, B_FMEAN, 1, 0);
     }
     KDISPATCH(kind, kb_norms_m, B->norms.total(), TPB, B->D, B->norms.dev, fid, oc);
-    kb_finalize<<<B->nbox, TPB, 0, s>>>(B->D, B->norms.dev, 2, B_RN, -1, 1);
-    kb_control<<<1, 1024, 0, s>>>(B->D, fid, o.rtol, o.max_cycles);
+    kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->norms.dev, 2, B_RN, -1, 1, 0);
+    kb_control<<<1, 1024, 0, s>>>(B->D, fid, o.rtol, o.max_cycles, 0, B->nper);
     // descent through the levels handled by grouped launches
     for (int d = 0; d < B->maxdepth; ++d) {
         const Tab &TC = B->colour[d], &TD = B->cdom[d];
@@ -824,7 +1171,7 @@ int batch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
         KDISPATCH(kind, kb_rr_m, B->rr[d].total(), TPB, B->D, B->rr[d].dev, d, fid, oc);
         KDISPATCH(kind, kb_coarse_rhs, TD.total(), TPB, B->D, TD.dev, d, oc);
     }
-    KDISPATCH(kind, kb_coarse_vcycle, B->nbox, CTPB, B->D, fid, o.nu1, o.nu2, oc);
+    KDISPATCH(kind, kb_coarse_vcycle, B->nper, CTPB, B->D, fid, o.nu1, o.nu2, oc);
     for (int d = B->maxdepth - 1; d >= 0; --d) {
         const Tab &TC = B->colour[d], &TD = B->cdom[d];
         if (TC.total() == 0) continue;
@@ -844,24 +1191,16 @@ int batch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
 
 namespace {
 
-int batch_field(gr_batch B, int kind, int fid, const gr_solve_opts &o)
+// Replays (or captures, then replays) one cycle of items [b0, b1) until the
+// device control reports no active item; graph slot `slot`.  Then reads the
+// final relative residuals of those items for field fid.
+template <class Body>
+int run_cycles(gr_batch B, int slot, int fid, int b0, int b1, const gr_solve_opts &o, Body cycle)
 {
     hipStream_t s = B->stream;
-    const OpConst oc = opc(B);
-    kb_begin_field<<<1, 1024, 0, s>>>(B->D, fid);
-    if (kind != GR_KIND_POISSON)
-        for (size_t d = 0; d < B->coefr.size(); ++d)
-            if (B->coefr[d].total())
-                kb_restrict_coef<<<B->coefr[d].total(), TPB, 0, s>>>(B->D, B->coefr[d].dev, (int)d);
-    if (kind == GR_KIND_CMC) {
-        kb_sum<<<B->fine.total(), TPB, 0, s>>>(B->D, B->fine.dev, fid, 3, oc, 0);
-        kb_finalize<<<B->nbox, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FMEAN, -1, 0);
-    }
-    BLAUNCH();
-    BCHK(batch_pin(B, fid, 0));
     const bool graph = B->use_graph && s != nullptr;
-    hipGraphExec_t &ge = B->graph[fid];
-    const gr_solve_opts &go = B->graph_opts[fid];
+    hipGraphExec_t &ge = B->graph[slot];
+    const gr_solve_opts &go = B->graph_opts[slot];
     if (ge && (go.nu1 != o.nu1 || go.nu2 != o.nu2 || go.max_cycles != o.max_cycles || go.rtol != o.rtol)) {
         (void)hipGraphExecDestroy(ge);
         ge = nullptr;
@@ -871,18 +1210,18 @@ int batch_field(gr_batch B, int kind, int fid, const gr_solve_opts &o)
             if (!ge) {
                 hipGraph_t gr;
                 BHIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-                int st = batch_cycle(B, kind, fid, o);
+                int st = cycle();
                 hipError_t e = hipStreamEndCapture(s, &gr);
                 if (st != GR_OK) return st;
                 if (e != hipSuccess) return bfail(GR_EDEVICE, "graph capture: %s", hipGetErrorString(e));
                 e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
                 (void)hipGraphDestroy(gr);
                 if (e != hipSuccess) return bfail(GR_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
-                B->graph_opts[fid] = o;
+                B->graph_opts[slot] = o;
             }
             BHIP(hipGraphLaunch(ge, s));
         } else {
-            BCHK(batch_cycle(B, kind, fid, o));
+            BCHK(cycle());
         }
         int any = 0;
         BHIP(hipMemcpyAsync(&any, B->D.any_active, sizeof any, hipMemcpyDeviceToHost, s));
@@ -890,12 +1229,95 @@ int batch_field(gr_batch B, int kind, int fid, const gr_solve_opts &o)
         if (!any) break;
         if (it > o.max_cycles + 2) return bfail(GR_EDEVICE, "batch control did not stop");
     }
-    if (kind == GR_KIND_POISSON) BCHK(batch_pin(B, fid, 0));
+    return GR_OK;
+}
+
+int read_rel(gr_batch B, int fid, int b0, int b1)
+{
+    hipStream_t s = B->stream;
     std::vector<double> sc((size_t)B->nbox * B_NSCAL);
     BHIP(hipMemcpyAsync(sc.data(), B->D.scal, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, s));
     BHIP(hipStreamSynchronize(s));
-    for (int b = 0; b < B->nbox; ++b) B->rel_hist[(size_t)b * 10 + fid] = sc[(size_t)b * B_NSCAL + B_REL];
+    for (int b = b0; b < b1; ++b) B->rel_hist[(size_t)b * 10 + fid] = sc[(size_t)b * B_NSCAL + B_REL];
     return GR_OK;
+}
+
+int batch_field(gr_batch B, int kind, int fid, const gr_solve_opts &o)
+{
+    hipStream_t s = B->stream;
+    const OpConst oc = opc(B);
+    kb_begin_field<<<1, 1024, 0, s>>>(B->D, fid, 0, B->nper, fid);
+    if (kind != GR_KIND_POISSON)
+        for (size_t d = 0; d < B->coefr.size(); ++d)
+            if (B->coefr[d].total())
+                kb_restrict_coef<<<B->coefr[d].total(), TPB, 0, s>>>(B->D, B->coefr[d].dev, (int)d);
+    if (kind == GR_KIND_CMC) {
+        kb_sum<<<B->fine.total(), TPB, 0, s>>>(B->D, B->fine.dev, fid, 3, oc, 0);
+        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FMEAN, -1, 0, 0);
+    }
+    BLAUNCH();
+    BCHK(batch_pin(B, fid, 0));
+    BCHK(run_cycles(B, fid, fid, 0, B->nper, o, [&] { return batch_cycle(B, kind, fid, o); }));
+    if (kind == GR_KIND_POISSON) BCHK(batch_pin(B, fid, 0));
+    return read_rel(B, fid, 0, B->nper);
+}
+
+// ------------------------------------------------------------ patch cycle
+
+void patch_smooth(gr_batch B, int kind, int d, int fid, int nu)
+{
+    hipStream_t s = B->stream;
+    const OpConst oc = opc(B);
+    const Tab &T = B->pcell[d];
+    for (int it = 0; it < nu; ++it)
+        for (int colour = 0; colour < 2; ++colour) KDISPATCH(kind, kp_colour, T.total(), TPB, B->D, T.dev, d, fid, colour, oc);
+}
+
+// one cycle of every patch: norms, control, V-cycle (no pin, no frozen means)
+int patch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
+{
+    hipStream_t s = B->stream;
+    const OpConst oc = opc(B);
+    KDISPATCH(kind, kp_norms, B->pfine.total(), TPB, B->D, B->pfine.dev, fid, oc);
+    kb_finalize<<<B->npatch, TPB, 0, s>>>(B->D, B->pfine.dev, 2, B_RN, -1, 1, B->nper);
+    kb_control<<<1, 1024, 0, s>>>(B->D, fid, o.rtol, o.max_cycles, B->nper, B->nbox);
+    for (int d = 0; d < B->pmaxdepth; ++d) {
+        if (B->pcell[d].total() == 0) continue;
+        patch_smooth(B, kind, d, fid, o.nu1);
+        const Tab &TC = B->pcoarse[d];
+        KDISPATCH(kind, kp_rr, TC.total(), TPB, B->D, TC.dev, d, fid, oc);
+        KDISPATCH(kind, kp_coarse_rhs, TC.total(), TPB, B->D, TC.dev, d, oc);
+    }
+    KDISPATCH(kind, kp_coarse_vcycle, B->npatch, CTPB, B->D, fid, o.nu1, o.nu2, oc, B->nper);
+    for (int d = B->pmaxdepth - 1; d >= 0; --d) {
+        if (B->pcell[d].total() == 0) continue;
+        kp_prolong<<<B->pcell[d].total(), TPB, 0, s>>>(B->D, B->pcell[d].dev, d, fid);
+        patch_smooth(B, kind, d, fid, o.nu2);
+    }
+    BLAUNCH();
+    return GR_OK;
+}
+
+// boundary values of every level of every patch from the parents' field fid
+void patch_faces(gr_batch B, int fid)
+{
+    hipStream_t s = B->stream;
+    for (int l = 0; l < B->pmaxlev; ++l)
+        if (B->pfaces[l].total()) kp_faces<<<B->pfaces[l].total(), TPB, 0, s>>>(B->D, B->pfaces[l].dev, l, fid);
+}
+
+int patch_field(gr_batch B, int kind, int fid, const gr_solve_opts &o)
+{
+    hipStream_t s = B->stream;
+    kb_begin_field<<<1, 1024, 0, s>>>(B->D, fid, B->nper, B->nbox, 10 + fid);
+    if (kind != GR_KIND_POISSON)
+        for (size_t d = 0; d < B->pcoefr.size(); ++d)
+            if (B->pcoefr[d].total())
+                kp_restrict_coef<<<B->pcoefr[d].total(), TPB, 0, s>>>(B->D, B->pcoefr[d].dev, (int)d);
+    patch_faces(B, fid);
+    BLAUNCH();
+    BCHK(run_cycles(B, 10 + fid, fid, B->nper, B->nbox, o, [&] { return patch_cycle(B, kind, fid, o); }));
+    return read_rel(B, fid, B->nper, B->nbox);
 }
 
 } // namespace
@@ -904,20 +1326,49 @@ extern "C" {
 
 const char *gr_batch_last_error(void) { return b_err.c_str(); }
 
-int gr_create_batch(const gr_grid_desc *descs, int count, const gr_params *prm, gr_batch *out)
+} // extern "C"
+
+namespace {
+
+// Levels of a patch: halve while n is even and n/2 >= 3.
+int patch_levels(int n)
 {
-    if (!descs || !prm || !out) return bfail(GR_EINVAL, "null argument");
+    int L = 1;
+    while (n % 2 == 0 && n / 2 >= 3) {
+        n /= 2;
+        ++L;
+    }
+    return L;
+}
+
+constexpr int kPatchCoarseN = 16; // patch levels at or below this size: single-workgroup cycle
+
+int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patches, int npatch,
+                 const gr_params *prm, gr_batch *out)
+{
+    if (!descs || !prm || !out || (npatch > 0 && !patches)) return bfail(GR_EINVAL, "null argument");
     *out = nullptr;
-    if (count < 1 || count > kMaxBoxes) return bfail(GR_EINVAL, "count %d outside 1..%d", count, kMaxBoxes);
+    if (count < 1 || npatch < 0 || count + npatch > kMaxBoxes)
+        return bfail(GR_EINVAL, "%d boxes + %d patches outside 1..%d items", count, npatch, kMaxBoxes);
     if (!(prm->a > 0.0) || !(prm->c_tilde > 0.0) || !std::isfinite(prm->omega_m))
         return bfail(GR_EINVAL, "a and c_tilde must be positive");
+    for (int j = 0; j < npatch; ++j) {
+        const gr_patch_desc &q = patches[j];
+        const bool origin_ok = std::fabs(q.origin[0]) <= 1e6 && std::fabs(q.origin[1]) <= 1e6 &&
+                               std::fabs(q.origin[2]) <= 1e6; // false for NaN
+        if (q.n < 3 || q.n > 512 || !(q.h > 0.0) || !(q.h <= 1e3) || q.parent < 0 || q.parent >= count || !origin_ok)
+            return bfail(GR_EINVAL, "patch %d: n = %d must be 3..512, 0 < h <= 1e3, parent a box index, |origin| <= 1e6",
+                         j, q.n);
+    }
     gr_batch B = new (std::nothrow) gr_batch_s();
     if (!B) return bfail(GR_EINVAL, "out of host memory");
-    B->nbox = count;
+    B->nbox = count + npatch;
+    B->nper = count;
+    B->npatch = npatch;
     B->prm = *prm;
     if (const char *e = std::getenv("GRMG_COARSE_N")) B->coarse_n = std::max(2, std::atoi(e));
     if (const char *e = std::getenv("GRMG_BATCH_GRAPH")) B->use_graph = std::atoi(e) != 0;
-    B->host.resize(count);
+    B->host.resize(count + npatch);
     int maxd = 0, maxc = 0;
     for (int b = 0; b < count; ++b) {
         const int n = descs[b].n;
@@ -939,15 +1390,38 @@ int gr_create_batch(const gr_grid_desc *descs, int count, const gr_params *prm, 
         B->total_points += (long)n * n * n;
     }
     B->maxdepth = maxd;
-    const int nb = count;
+    int pmaxd = 0, pmaxl = 0;
+    for (int j = 0; j < npatch; ++j) {
+        const gr_patch_desc &q = patches[j];
+        BoxDev &X = B->host[count + j];
+        std::memset(&X, 0, sizeof X);
+        X.patch = 1;
+        X.parent = q.parent;
+        for (int a = 0; a < 3; ++a) X.origin[a] = q.origin[a];
+        X.nlev = patch_levels(q.n);
+        X.centry = X.nlev - 1;
+        for (int l = 0; l < X.nlev; ++l) {
+            X.lev[l].n = q.n >> l;
+            X.lev[l].h = q.h * (double)(1 << l);
+            if ((q.n >> l) <= kPatchCoarseN && X.centry == X.nlev - 1 && l < X.centry) X.centry = l;
+        }
+        pmaxd = std::max(pmaxd, X.centry);
+        pmaxl = std::max(pmaxl, X.nlev);
+        B->total_points += (long)q.n * q.n * q.n;
+    }
+    B->pmaxdepth = pmaxd;
+    B->pmaxlev = pmaxl;
+    const int nb = count + npatch;
     auto &H = B->host;
-    make_tab(B->fine, nb, [&](int b) { long n = H[b].lev[0].n; return n * n * n; });
+    // periodic tables: no blocks for patches
+    make_tab(B->fine, nb, [&](int b) { long n = H[b].patch ? 0 : H[b].lev[0].n; return n * n * n; });
     B->colour.resize(maxd);
     B->cdom.resize(maxd);
     B->fz.resize(maxd);
     B->rr.resize(maxd);
     if (const char *e = std::getenv("GRMG_MARCH")) B->use_march = std::atoi(e) != 0;
     make_tab(B->norms, nb, [&](int b) {
+        if (H[b].patch) return 0L;
         const long n = H[b].lev[0].n;
         return B->use_march && marchable((int)n) ? march_blocks((int)n) * TPB : n * n * n;
     });
@@ -955,31 +1429,67 @@ int gr_create_batch(const gr_grid_desc *descs, int count, const gr_params *prm, 
     if (const char *e = std::getenv("GRMG_BATCH_FUSED")) B->use_fused = std::atoi(e) != 0;
     auto fusable = [&](int b, int d) {
         const int n = H[b].lev[d].n;
-        return d < H[b].centry && n >= 64 && n % 32 == 0;
+        return !H[b].patch && d < H[b].centry && n >= 64 && n % 32 == 0;
     };
+    auto grouped = [&](int b, int d) { return !H[b].patch && d < H[b].centry; };
     for (int d = 0; d < maxd; ++d) {
-        make_tab(B->colour[d], nb, [&](int b) { long n = H[b].lev[d].n; return d < H[b].centry ? n * n * n / 2 : 0L; });
+        make_tab(B->colour[d], nb, [&](int b) { long n = H[b].lev[d].n; return grouped(b, d) ? n * n * n / 2 : 0L; });
         make_tab(B->fz[d], nb, [&](int b) {
             const long n = H[b].lev[d].n;
             return fusable(b, d) ? (n / 32) * (n / 16) * (n / kFZ) * TPB : 0L; // workgroups x threads
         });
         make_tab(B->rr[d], nb, [&](int b) {
-            if (d >= H[b].centry) return 0L;
+            if (!grouped(b, d)) return 0L;
             const long n = H[b].lev[d].n, m = H[b].lev[d + 1].n;
             return B->use_march && marchable((int)n) ? march_blocks((int)n) * TPB : m * m * m;
         });
         make_tab(B->colour_nf[d], nb, [&](int b) {
             long n = H[b].lev[d].n;
-            return d < H[b].centry && !fusable(b, d) ? n * n * n / 2 : 0L;
+            return grouped(b, d) && !fusable(b, d) ? n * n * n / 2 : 0L;
         });
-        make_tab(B->cdom[d], nb, [&](int b) { long m = d < H[b].centry ? H[b].lev[d + 1].n : 0; return m * m * m; });
+        make_tab(B->cdom[d], nb, [&](int b) { long m = grouped(b, d) ? H[b].lev[d + 1].n : 0; return m * m * m; });
     }
     B->coefr.resize(maxc);
     for (int d = 0; d < maxc; ++d)
-        make_tab(B->coefr[d], nb, [&](int b) { long m = d + 1 < H[b].nlev ? H[b].lev[d + 1].n : 0; return m * m * m; });
+        make_tab(B->coefr[d], nb, [&](int b) {
+            long m = !H[b].patch && d + 1 < H[b].nlev ? H[b].lev[d + 1].n : 0;
+            return m * m * m;
+        });
+    // patch tables: no blocks for periodic boxes
+    auto cells = [&](int b, int l) { long n = H[b].patch && l < H[b].nlev ? H[b].lev[l].n : 0; return n * n * n; };
+    make_tab(B->pfine, nb, [&](int b) { return cells(b, 0); });
+    B->pcell.resize(pmaxd);
+    B->pcoarse.resize(pmaxd);
+    for (int d = 0; d < pmaxd; ++d) {
+        make_tab(B->pcell[d], nb, [&](int b) { return d < H[b].centry ? cells(b, d) : 0L; });
+        make_tab(B->pcoarse[d], nb, [&](int b) { return d < H[b].centry ? cells(b, d + 1) : 0L; });
+    }
+    B->pcoefr.resize(std::max(pmaxl - 1, 0));
+    for (int d = 0; d + 1 < pmaxl; ++d) make_tab(B->pcoefr[d], nb, [&](int b) { return cells(b, d + 1); });
+    B->pfaces.resize(pmaxl);
+    for (int l = 0; l < pmaxl; ++l)
+        make_tab(B->pfaces[l], nb, [&](int b) {
+            long w = H[b].patch && l < H[b].nlev ? H[b].lev[l].n + 2 : 0;
+            return w * w * w;
+        });
     B->ws_bytes = batch_layout(B, nullptr);
     *out = B;
     return GR_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int gr_create_batch(const gr_grid_desc *descs, int count, const gr_params *prm, gr_batch *out)
+{
+    return create_batch(descs, count, nullptr, 0, prm, out);
+}
+
+int gr_create_batch_patches(const gr_grid_desc *boxes, int nbox, const gr_patch_desc *patches, int npatch,
+                            const gr_params *prm, gr_batch *out)
+{
+    return create_batch(boxes, nbox, patches, npatch, prm, out);
 }
 
 int gr_batch_workspace_bytes(gr_batch B, size_t *bytes)
@@ -1026,6 +1536,9 @@ int gr_batch_bind(gr_batch B, void *d_ws, size_t bytes, void *stream)
         BHIP(up(B->colour_nf[d]));
     }
     for (auto &T : B->coefr) BHIP(up(T));
+    BHIP(up(B->pfine));
+    for (auto *v : {&B->pcell, &B->pcoarse, &B->pcoefr, &B->pfaces})
+        for (auto &T : *v) BHIP(up(T));
     BHIP(hipStreamSynchronize(s)); // host tables must outlive the copies
     B->D.nbox = B->nbox;
     int dev = 0, khz = 0;
@@ -1061,6 +1574,14 @@ int gr_batch_set_field(gr_batch B, int item, int field, const void *d_src, int d
     double *dst = batch_slot(B, item, field);
     if (!dst || !d_src) return bfail(GR_EINVAL, "bad item %d / field %d / source", item, field);
     const long n = B->host[item].lev[0].n, N = n * n * n;
+    if (B->host[item].patch && field < 10) { // interior of the padded iterate
+        const unsigned g = (unsigned)((N + TPB - 1) / TPB);
+        if (dtype == GR_F64) kp_pad_in<double><<<g, TPB, 0, B->stream>>>(dst, static_cast<const double *>(d_src), (int)n);
+        else if (dtype == GR_F32) kp_pad_in<float><<<g, TPB, 0, B->stream>>>(dst, static_cast<const float *>(d_src), (int)n);
+        else return bfail(GR_EINVAL, "bad dtype %d", dtype);
+        BLAUNCH();
+        return GR_OK;
+    }
     if (dtype == GR_F64) launch_copy(B->stream, dst, static_cast<const double *>(d_src), N);
     else if (dtype == GR_F32) launch_convert_f32_to_f64(B->stream, dst, static_cast<const float *>(d_src), N);
     else return bfail(GR_EINVAL, "bad dtype %d", dtype);
@@ -1074,9 +1595,32 @@ int gr_batch_get_field(gr_batch B, int item, int field, void *d_dst, int dtype)
     double *src = batch_slot(B, item, field);
     if (!src || !d_dst) return bfail(GR_EINVAL, "bad item %d / field %d / destination", item, field);
     const long n = B->host[item].lev[0].n, N = n * n * n;
+    if (B->host[item].patch && field < 10) {
+        const unsigned g = (unsigned)((N + TPB - 1) / TPB);
+        if (dtype == GR_F64) kp_pad_out<double><<<g, TPB, 0, B->stream>>>(static_cast<double *>(d_dst), src, (int)n);
+        else if (dtype == GR_F32) kp_pad_out<float><<<g, TPB, 0, B->stream>>>(static_cast<float *>(d_dst), src, (int)n);
+        else return bfail(GR_EINVAL, "bad dtype %d", dtype);
+        BLAUNCH();
+        return GR_OK;
+    }
     if (dtype == GR_F64) launch_copy(B->stream, static_cast<double *>(d_dst), src, N);
     else if (dtype == GR_F32) launch_convert_f64_to_f32(B->stream, static_cast<float *>(d_dst), src, N);
     else return bfail(GR_EINVAL, "bad dtype %d", dtype);
+    BLAUNCH();
+    return GR_OK;
+}
+
+int gr_batch_debug_boundary(gr_batch B, int item, int field, int level, double *d_dst)
+{
+    if (!B || !B->bound) return bfail(B ? GR_ESTATE : GR_EINVAL, "batch not bound");
+    if (item < B->nper || item >= B->nbox || field < 0 || field >= 10 || !d_dst)
+        return bfail(GR_EINVAL, "bad patch item %d / field %d / destination", item, field);
+    const BoxDev &X = B->host[item];
+    if (level < 0 || level >= X.nlev) return bfail(GR_EINVAL, "level %d outside 0..%d", level, X.nlev - 1);
+    hipStream_t s = B->stream;
+    patch_faces(B, field);
+    const long w = X.lev[level].n + 2;
+    launch_copy(s, d_dst, level == 0 ? X.field[field] : X.lev[level].phi, w * w * w);
     BLAUNCH();
     return GR_OK;
 }
@@ -1099,51 +1643,75 @@ int gr_batch_solve(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_
     BHIP(hipMemcpyAsync(B->D.status, zero.data(), sizeof(int) * B->nbox, hipMemcpyHostToDevice, s));
     std::vector<unsigned long long> tz((size_t)B->nbox * 10, 0ull);
     BHIP(hipMemcpyAsync(B->D.t_done, tz.data(), sizeof(unsigned long long) * tz.size(), hipMemcpyHostToDevice, s));
+    const int PT = B->pfine.total();
     if (o->guess == GR_GUESS_ZERO)
         for (int f = 0; f < 10; ++f)
-            if (mask & (1u << f)) kb_fill_field<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, f);
+            if (mask & (1u << f)) {
+                kb_fill_field<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, f);
+                if (PT) kp_fill_field<<<PT, TPB, 0, s>>>(B->D, B->pfine.dev, f);
+            }
     BLAUNCH();
     auto build = [&](int what, int comp) {
         kb_build<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, what, comp, P.a, P.omega_m, P.c_tilde);
     };
+    auto pbuild = [&](int what, int comp) {
+        if (PT) kp_build<<<PT, TPB, 0, s>>>(B->D, B->pfine.dev, what, comp, P.a, P.omega_m, P.c_tilde);
+    };
+    // every field of the patches right after their parents' (their boundary
+    // values and outside stencil values are the parents' solved fields)
+    auto field = [&](int kind, int fid, const std::function<void()> &pre_patch) -> int {
+        if (!(mask & (1u << fid))) return GR_OK;
+        BCHK(batch_field(B, kind, fid, *o));
+        if (B->npatch) {
+            pre_patch();
+            BLAUNCH();
+            BCHK(patch_field(B, kind, fid, *o));
+        }
+        return GR_OK;
+    };
     for (int d = 0; d < 3; ++d) {
         if (!(mask & (1u << d))) continue;
         kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, 0, 4 + d, oc, 0);
-        kb_finalize<<<B->nbox, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_TMP, -1, 0);
+        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_TMP, -1, 0, 0);
         build(0, d);
         BLAUNCH();
-        BCHK(batch_field(B, GR_KIND_POISSON, GR_VX + d, *o));
+        BCHK(field(GR_KIND_POISSON, GR_VX + d, [&] { pbuild(0, d); }));
     }
     build(1, 0);
-    if (mask & (1u << GR_U)) BCHK(batch_field(B, GR_KIND_POISSON, GR_U, *o));
+    BCHK(field(GR_KIND_POISSON, GR_U, [&] { pbuild(1, 0); }));
     build(2, 0);
-    if (mask & (1u << GR_PSI)) BCHK(batch_field(B, GR_KIND_HAMILTONIAN, GR_PSI, *o));
+    BCHK(field(GR_KIND_HAMILTONIAN, GR_PSI, [&] { pbuild(2, 0); }));
     build(3, 0);
-    if (mask & (1u << GR_XI)) BCHK(batch_field(B, GR_KIND_CMC, GR_XI, *o));
+    BCHK(field(GR_KIND_CMC, GR_XI, [&] { pbuild(3, 0); }));
     build(4, 0);
+    bool pB = false; // patch shift sources built (needs the patches' Psi, xi and A_ij)
     for (int d = 0; d < 3; ++d) {
-        if (!(mask & (1u << (GR_BX + d)))) continue;
         build(6, d);
         BLAUNCH();
-        BCHK(batch_field(B, GR_KIND_POISSON, GR_BX + d, *o));
+        BCHK(field(GR_KIND_POISSON, GR_BX + d, [&] {
+            if (!pB) pbuild(4, 0);
+            pB = true;
+            pbuild(6, d);
+        }));
     }
     build(5, 0);
-    if (mask & (1u << GR_BB)) BCHK(batch_field(B, GR_KIND_POISSON, GR_BB, *o));
+    BCHK(field(GR_KIND_POISSON, GR_BB, [&] { pbuild(5, 0); }));
     BLAUNCH();
     // results
     std::vector<int> st(B->nbox), cyc((size_t)B->nbox * 10);
-    std::vector<unsigned long long> td((size_t)B->nbox * 10), t0(10);
+    std::vector<unsigned long long> td((size_t)B->nbox * 10), t0(20);
     BHIP(hipMemcpyAsync(st.data(), B->D.status, sizeof(int) * st.size(), hipMemcpyDeviceToHost, s));
     BHIP(hipMemcpyAsync(cyc.data(), B->D.cycles, sizeof(int) * cyc.size(), hipMemcpyDeviceToHost, s));
     BHIP(hipMemcpyAsync(td.data(), B->D.t_done, sizeof(unsigned long long) * td.size(), hipMemcpyDeviceToHost, s));
-    BHIP(hipMemcpyAsync(t0.data(), B->D.t_start, sizeof(unsigned long long) * 10, hipMemcpyDeviceToHost, s));
+    BHIP(hipMemcpyAsync(t0.data(), B->D.t_start, sizeof(unsigned long long) * 20, hipMemcpyDeviceToHost, s));
     BHIP(hipStreamSynchronize(s));
     if (cycles) std::memcpy(cycles, cyc.data(), sizeof(int) * cyc.size());
     if (item_seconds)
         for (int b = 0; b < B->nbox; ++b) {
             double sum = 0.0;
+            const int ts = B->host[b].patch ? 10 : 0;
             for (int f = 0; f < 10; ++f)
-                if ((mask & (1u << f)) && td[b * 10 + f] >= t0[f]) sum += (double)(td[b * 10 + f] - t0[f]);
+                if ((mask & (1u << f)) && td[b * 10 + f] >= t0[ts + f]) sum += (double)(td[b * 10 + f] - t0[ts + f]);
             item_seconds[b] = sum / (B->clock_khz * 1e3);
         }
     if (rel_res) {

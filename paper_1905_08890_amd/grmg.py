@@ -32,7 +32,8 @@ FIELD_IDS.update(dict(s0=S0, sx=SX, sy=SY, sz=SZ, sm=SM, AA=AA, Phi=PHI, alpha=A
 
 EXPORTS = ("gr_default_opts", "gr_create_grid", "gr_workspace_bytes", "gr_bind", "gr_deposit_sources",
            "gr_set_field", "gr_get_field", "gr_solve_constraints", "gr_solve_equation", "gr_debug_sweep",
-           "gr_debug_residual", "gr_destroy_grid", "gr_last_error", "gr_features", "gr_set_guess", "gr_autotune", "gr_sweep_timing", "gr_create_batch", "gr_batch_workspace_bytes",
+           "gr_debug_residual", "gr_destroy_grid", "gr_last_error", "gr_features", "gr_set_guess", "gr_autotune", "gr_sweep_timing", "gr_create_batch", "gr_create_batch_patches",
+           "gr_batch_debug_boundary", "gr_batch_workspace_bytes",
            "gr_batch_bind", "gr_batch_set_field", "gr_batch_get_field", "gr_batch_solve", "gr_destroy_batch",
            "gr_batch_last_error", "gr_unet_create", "gr_unet_workspace_bytes", "gr_unet_param_count", "gr_unet_bind",
            "gr_unet_init", "gr_unet_set_params", "gr_unet_get_params", "gr_unet_forward", "gr_unet_loss_grad",
@@ -45,6 +46,10 @@ class GrParams(C.Structure):
 
 class GrGridDesc(C.Structure):
     _fields_ = [("n", C.c_int), ("h", C.c_double)]
+
+
+class GrPatchDesc(C.Structure):
+    _fields_ = [("n", C.c_int), ("h", C.c_double), ("parent", C.c_int), ("origin", C.c_double * 3)]
 
 
 class GrSolveOpts(C.Structure):
@@ -104,6 +109,9 @@ def load_library(path: str = LIB_PATH):
         "gr_sweep_timing": [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)],
         "gr_set_guess": [vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), vp, C.c_int],
         "gr_create_batch": [C.POINTER(GrGridDesc), C.c_int, C.POINTER(GrParams), C.POINTER(vp)],
+        "gr_create_batch_patches": [C.POINTER(GrGridDesc), C.c_int, C.POINTER(GrPatchDesc), C.c_int,
+                                    C.POINTER(GrParams), C.POINTER(vp)],
+        "gr_batch_debug_boundary": [vp, C.c_int, C.c_int, C.c_int, vp],
         "gr_batch_workspace_bytes": [vp, C.POINTER(C.c_size_t)],
         "gr_batch_bind": [vp, vp, C.c_size_t, vp],
         "gr_batch_set_field": [vp, C.c_int, C.c_int, vp, C.c_int],
@@ -327,10 +335,17 @@ class Grid:
 
 # ---- batched solve ----
 
-def create_batch(ns, a: float, omega_m: float, c_tilde: float) -> int:
+def create_batch(ns, a: float, omega_m: float, c_tilde: float, patches=()) -> int:
+    """Periodic unit boxes of sides ns, then patches given as (n, h, parent, (ox, oy, oz))."""
     descs = (GrGridDesc * len(ns))(*[GrGridDesc(int(n), 1.0 / int(n)) for n in ns])
     g = C.c_void_p()
-    _bcheck(load_library().gr_create_batch(descs, len(ns), C.byref(GrParams(a, omega_m, c_tilde)), C.byref(g)))
+    prm = C.byref(GrParams(a, omega_m, c_tilde))
+    if patches:
+        pd = (GrPatchDesc * len(patches))(*[GrPatchDesc(int(n), float(h), int(par), (C.c_double * 3)(*map(float, o)))
+                                            for n, h, par, o in patches])
+        _bcheck(load_library().gr_create_batch_patches(descs, len(ns), pd, len(patches), prm, C.byref(g)))
+    else:
+        _bcheck(load_library().gr_create_batch(descs, len(ns), prm, C.byref(g)))
     return g.value
 
 
@@ -352,6 +367,10 @@ def batch_get_field(b: int, item: int, field: int, dst, dtype: int) -> None:
     _bcheck(load_library().gr_batch_get_field(b, item, field, _ptr(dst), dtype))
 
 
+def batch_debug_boundary(b: int, item: int, field: int, level: int, dst) -> None:
+    _bcheck(load_library().gr_batch_debug_boundary(b, item, field, level, _ptr(dst)))
+
+
 def batch_solve(b: int, count: int, opts: GrSolveOpts, allow=(OK,)):
     cyc = (C.c_int * (10 * count))()
     rel = (C.c_double * (10 * count))()
@@ -366,19 +385,23 @@ def destroy_batch(b: int) -> None:
 
 
 class Batch:
-    """Many periodic boxes (sides ns) solved together on `device`.  Uses its own
-    non-default stream so that each cycle can be captured in a hipGraph."""
+    """Many periodic boxes (sides ns) and Dirichlet refinement patches
+    (n, h, parent, origin) solved together on `device`; items are the boxes,
+    then the patches.  Uses its own non-default stream so that each cycle can
+    be captured in a hipGraph."""
 
     def __init__(self, ns, a: float = 1.0, omega_m: float = 0.3072, c_tilde: float = 2997.92458 / 256.0,
-                 device="cuda"):
+                 device="cuda", patches=()):
         import torch
 
         self.torch = torch
-        self.ns = [int(n) for n in ns]
+        self.patches = [(int(n), float(h), int(p), tuple(map(float, o))) for n, h, p, o in patches]
+        self.nbox = len(ns)
+        self.ns = [int(n) for n in ns] + [q[0] for q in self.patches]
         self.device = torch.device(device)
         if self.device.type != "cuda" or not torch.cuda.is_available():
             raise RuntimeError("the HIP library needs a GPU device (no CPU fallback)")
-        self.handle = create_batch(self.ns, a, omega_m, c_tilde)
+        self.handle = create_batch(self.ns[:self.nbox], a, omega_m, c_tilde, self.patches)
         self.workspace = torch.empty(batch_workspace_bytes(self.handle), dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.Stream(device=self.device)
         torch.cuda.current_stream(self.device).synchronize()
@@ -412,6 +435,17 @@ class Batch:
         n = self.ns[item]
         out = t.empty((n, n, n), dtype=t.float64, device=self.device)
         batch_get_field(self.handle, item, fid, out, F64)
+        self.stream.synchronize()
+        return out
+
+    def debug_boundary(self, item, field, level):
+        """Padded level `level` of patch `item` after writing its boundary values
+        from the parent's current field."""
+        t = self.torch
+        fid = FIELD_IDS[field] if isinstance(field, str) else field
+        m = self.ns[item] >> level
+        out = t.empty((m + 2, m + 2, m + 2), dtype=t.float64, device=self.device)
+        batch_debug_boundary(self.handle, item, fid, level, out)
         self.stream.synchronize()
         return out
 

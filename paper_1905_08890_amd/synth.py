@@ -101,6 +101,12 @@ def batch_item(seed: int, sides=BATCH_SIDES, sigma_range=(0.05, 1.0)):
     rng = np.random.default_rng(seed)
     n = int(rng.choice(np.asarray(sides)))
     sigma = float(np.exp(rng.uniform(np.log(sigma_range[0]), np.log(sigma_range[1]))))
+    return n, _matter_sources(n, seed, sigma)
+
+
+def _matter_sources(n: int, seed: int, sigma: float):
+    """s0 = 1 + delta (k^-2 GRF of std sigma), longitudinal momentum
+    -d_i Lap^-1 delta rescaled to rms |s| = 1e-3, s_m = 0."""
     delta = grf(n, seed, -2.0, sigma)
     D = np.fft.fftn(delta)
     k1 = 2.0 * np.pi * np.fft.fftfreq(n, d=1.0 / n)
@@ -110,7 +116,32 @@ def batch_item(seed: int, sides=BATCH_SIDES, sigma_range=(0.05, 1.0)):
     mom = [np.real(np.fft.ifftn(1j * kk / k2 * D)) for kk in (kx, ky, kz)]
     rms = np.sqrt(np.mean(mom[0] ** 2 + mom[1] ** 2 + mom[2] ** 2))
     mom = [np.ascontiguousarray(m * (1e-3 / rms)) for m in mom]
-    return n, (1.0 + delta, mom[0], mom[1], mom[2], np.zeros((n, n, n)))
+    return (1.0 + delta, mom[0], mom[1], mom[2], np.zeros((n, n, n)))
+
+
+PATCH_SIDES = tuple(range(24, 81, 8))
+
+
+def patch_item(j: int, box_sides, first_seed: int = 196, sides=PATCH_SIDES, sigma_range=(0.05, 1.0)):
+    """Refinement patch j of the batched workload (seed first_seed + j): side
+    from `sides`, spacing half its parent's, parent = the first box from box j
+    on (cyclically) with n_parent >= side/2 + 4, lower corner at a random
+    whole parent cell, its own sources as for a box (sigma log-uniform).
+    box_sides: the periodic boxes' sides (unit boxes).  Returns
+    ((n, h, parent, origin), (s0, sx, sy, sz, sm))."""
+    seed = first_seed + j
+    rng = np.random.default_rng(seed)
+    n = int(rng.choice(np.asarray(sides)))
+    sigma = float(np.exp(rng.uniform(np.log(sigma_range[0]), np.log(sigma_range[1]))))
+    nb = len(box_sides)
+    parent = next((b % nb for b in range(j, j + nb) if box_sides[b % nb] >= n // 2 + 4), None)
+    if parent is None:
+        raise ValueError(f"no box can hold a patch of side {n}")
+    N = box_sides[parent]
+    H = 1.0 / N
+    span = N - n // 2
+    off = [int(rng.integers(2, span - 1)) if span > 4 else 0 for _ in range(3)]
+    return (n, H / 2.0, parent, tuple(o * H for o in off)), _matter_sources(n, seed, sigma)
 
 
 def zeldovich_trajectory(n: int, seed: int, rms_cells_list, lam: float = 1.0):

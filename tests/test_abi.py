@@ -69,3 +69,35 @@ def test_no_cpu_fallback(monkeypatch):
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         grmg.Grid(8)
+
+
+def test_batch_with_patches_host_side():
+    """Patch descriptors are checked on the host; the workspace holds the
+    patches' padded iterate arrays."""
+    lib = grmg.load_library()
+    prm = grmg.GrParams(1.0, 0.3072, 11.7)
+    boxes = (grmg.GrGridDesc * 1)(grmg.GrGridDesc(16, 1 / 16))
+    b = C.c_void_p()
+
+    def make(n, h, parent, origin):
+        pd = (grmg.GrPatchDesc * 1)(grmg.GrPatchDesc(n, h, parent, (C.c_double * 3)(*origin)))
+        return lib.gr_create_batch_patches(boxes, 1, pd, 1, C.byref(prm), C.byref(b))
+
+    for bad in [(2, 0.01, 0, (0, 0, 0)), (600, 0.01, 0, (0, 0, 0)), (8, 0.0, 0, (0, 0, 0)),
+                (8, 0.01, 1, (0, 0, 0)), (8, 0.01, -1, (0, 0, 0)), (8, 0.01, 0, (float("nan"), 0, 0)),
+                (8, 0.01, 0, (0, 2e6, 0))]:
+        assert make(*bad) == grmg.EINVAL, bad
+    assert lib.gr_create_batch_patches(boxes, 1, None, 1, C.byref(prm), C.byref(b)) == grmg.EINVAL
+    sizes = {}
+    for npatch in (0, 1):
+        h = grmg.create_batch([16], 1.0, 0.3072, 11.7, [(24, 1 / 32, 0, (0.1, 0.2, 0.3))] * npatch)
+        try:
+            sizes[npatch] = grmg.batch_workspace_bytes(h)
+        finally:
+            grmg.destroy_batch(h)
+    # ten padded 26^3 fields, sources/A_ij/AA/shift sources and level 0's four
+    # work arrays dense 24^3, and the levels 12, 6, 3 (padded iterate + four
+    # dense arrays each)
+    extra = sizes[1] - sizes[0]
+    assert extra >= 8 * (10 * 26 ** 3 + 19 * 24 ** 3)
+    assert extra < 8 * (10 * 26 ** 3 + 19 * 24 ** 3 + 5 * 14 ** 3 + 5 * 8 ** 3 + 5 * 5 ** 3) + 64 * 1024
