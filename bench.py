@@ -188,13 +188,19 @@ def bench_learned(torch, grmg, synth, n):
 def bench_batch(torch, grmg, synth, steps):
     """96 periodic boxes with sides drawn from {32,48,64,96,128} (seeds
     100..195), s0 = 1 + delta with sigma log-uniform in [0.05, 1], longitudinal
-    momentum; all ten fields of every box to rtol 1e-10 in one batched solve."""
+    momentum, and 32 Dirichlet refinement patches (seeds 196..227: sides
+    24..80 in steps of 8 at half their parent's spacing, own sources, boundary
+    values from the parent); all ten fields of every item to rtol 1e-10 in one
+    batched solve."""
     import numpy as np
 
-    log("batch: generating 96 boxes")
+    log("batch: generating 96 boxes + 32 patches")
     items = [synth.batch_item(100 + b) for b in range(96)]
-    B = grmg.Batch([n for n, _ in items], a=1.0, omega_m=synth.OMEGA_M, c_tilde=synth.C_TILDE, device="cuda:0")
-    for i, (n, src) in enumerate(items):
+    sides = [n for n, _ in items]
+    pitems = [synth.patch_item(j, sides) for j in range(32)]
+    B = grmg.Batch(sides, a=1.0, omega_m=synth.OMEGA_M, c_tilde=synth.C_TILDE, device="cuda:0",
+                   patches=[d for d, _ in pitems])
+    for i, src in enumerate([src for _, src in items] + [src for _, src in pitems]):
         for name, x in zip(("s0", "sx", "sy", "sz", "sm"), src):
             B.set_field(i, name, x)
     torch.cuda.synchronize()
@@ -205,16 +211,21 @@ def bench_batch(torch, grmg, synth, steps):
         rep = B.solve(rtol=1e-10)
         times.append(time.perf_counter() - t0)
     dt = min(times)
-    pts = np.array([n ** 3 for n, _ in items], dtype=np.float64)
+    pts = np.array([n ** 3 for n in sides] + [d[0] ** 3 for d, _ in pitems], dtype=np.float64)
     cyc = np.array(rep["cycles"], dtype=np.float64)
     secs = np.array(rep["item_seconds"]) * 1e3
-    out = {"workload": "96 periodic boxes, sides {32,48,64,96,128}, seeds 100-195, all ten fields to rtol 1e-10, "
-                       "FP64, one grouped launch per phase, hipGraph per cycle",
-           "status": rep["status"], "points": int(pts.sum()), "seconds": round(dt, 4),
+    npb = len(sides)
+    out = {"workload": "96 periodic boxes (sides {32,48,64,96,128}, seeds 100-195) + 32 Dirichlet patches (sides "
+                       "24-80, seeds 196-227, half the parent's spacing), all ten fields to rtol 1e-10, FP64, one "
+                       "grouped launch per phase, hipGraph per cycle",
+           "status": rep["status"], "points": int(pts.sum()), "patch_points": int(pts[npb:].sum()),
+           "seconds": round(dt, 4),
            "points_cycles_per_s": round(float((pts[:, None] * cyc).sum() / dt), 1),
            "item_ms_p50": round(float(np.percentile(secs, 50)), 3),
            "item_ms_p99": round(float(np.percentile(secs, 99)), 3),
-           "cycles_min_max": [int(cyc.sum(1).min()), int(cyc.sum(1).max())]}
+           "patch_item_ms_p50": round(float(np.percentile(secs[npb:], 50)), 3),
+           "cycles_min_max": [int(cyc.sum(1).min()), int(cyc.sum(1).max())],
+           "patch_cycles_min_max": [int(cyc[npb:].sum(1).min()), int(cyc[npb:].sum(1).max())]}
     log(f"batch: {out}")
     B.close()
     return out
@@ -227,9 +238,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batch", action="store_true", help="skip the 96-box batched workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload (96 boxes + 32 patches)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess trajectory")
-    ap.add_argument("--batch-only", action="store_true", help="only the 96-box batched workload")
+    ap.add_argument("--batch-only", action="store_true", help="only the batched workload (96 boxes + 32 patches)")
     ap.add_argument("--smoother-only", action="store_true",
                     help="only the finest-level sweeps and a copy of known size (for hardware counters)")
     args = ap.parse_args()

@@ -19,7 +19,11 @@
 #include <cstring>
 #include <functional>
 #include <new>
+#include <atomic>
+#include <condition_variable>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "sources_ops.h"
@@ -645,16 +649,17 @@ __global__ void __launch_bounds__(TPB) kp_colour(BatchDev D, const int *__restri
     BOX_PROLOGUE(tab)
     if (!D.active[b]) return;
     const BoxLev &L = X.lev[d];
-    const int n = L.n;
-    if (t >= n * n * n) return;
-    int i, j, k;
-    decode3(t, n, n, i, j, k);
-    if (((i + j + k) & 1) != colour) return;
+    const int n = L.n, half = n >> 1; // grouped patch levels have even n
+    if (t >= n * n * half) return;
+    int x2, j, k;
+    decode3(t, half, n, x2, j, k);
+    const int i = 2 * x2 + ((j + k + colour) & 1);
     double *phi = patch_phi(X, d, fid);
     double J;
-    const double Lv = patch_op<KIND>(phi, i, j, k, n, 1.0 / (L.h * L.h), load_c1<KIND>(L.coef, t), oc, J);
+    const long q = lin(i, j, k, n);
+    const double Lv = patch_op<KIND>(phi, i, j, k, n, 1.0 / (L.h * L.h), load_c1<KIND>(L.coef, q), oc, J);
     const long p = pidx(i, j, k, n);
-    phi[p] = phi[p] - (Lv - L.f[t]) / J;
+    phi[p] = phi[p] - (Lv - L.f[q]) / J;
 }
 
 // residual at the 8 children, its mean, and the children's mean of phi (R phi,
@@ -1030,10 +1035,20 @@ struct gr_batch_s {
     // patches: levels handled by grouped launches (depth < pmaxdepth), all levels (< pmaxlev)
     int pmaxdepth = 0, pmaxlev = 0;
     Tab pfine;                                  // interior cells of level 0
-    std::vector<Tab> pcell;                     // per level: interior cells (levels below a patch's entry)
+    std::vector<Tab> pcell;                     // per level above a patch's entry: half its cells (colour passes)
+    std::vector<Tab> pcellf;                    // per level above a patch's entry: its cells (prolongation)
     std::vector<Tab> pcoarse;                   // per depth d: interior cells of level d + 1 (grouped levels)
     std::vector<Tab> pcoefr;                    // per depth d: interior cells of level d + 1 (all levels)
     std::vector<Tab> pfaces;                    // per level: padded cells
+    // patches run on their own stream and host thread, each field as soon as
+    // the boxes' solve of that field is done (GRMG_BATCH_CONCURRENT=0: after
+    // it on the batch's stream); own reduction scratch and activity flag
+    BatchDev Dp{};
+    double *p_partials = nullptr;
+    int *p_any = nullptr;
+    hipStream_t pstream = nullptr;
+    hipEvent_t pdone = nullptr;
+    bool conc = true;
     std::vector<double> rel_hist;   // [nbox][10] final relative residual per field
     double clock_khz = 0.0;
     long total_points = 0;
@@ -1082,7 +1097,9 @@ size_t batch_layout(gr_batch B, char *base)
     B->D.t_done = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * B->nbox * 10));
     B->D.t_start = reinterpret_cast<unsigned long long *>(take(sizeof(unsigned long long) * 20));
     B->D.any_active = takeI(1);
-    B->D.partials = takeD((size_t)std::max(B->fine.total(), B->pfine.total()) * 2 + 16);
+    B->D.partials = takeD((size_t)B->fine.total() * 2 + 16);
+    B->p_partials = takeD((size_t)B->pfine.total() * 2 + 16);
+    B->p_any = takeI(1);
     B->fine.dev = takeI(B->nbox + 1);
     B->norms.dev = takeI(B->nbox + 1);
     for (int d = 0; d < B->maxdepth; ++d) {
@@ -1094,7 +1111,7 @@ size_t batch_layout(gr_batch B, char *base)
     }
     for (size_t d = 0; d < B->coefr.size(); ++d) B->coefr[d].dev = takeI(B->nbox + 1);
     B->pfine.dev = takeI(B->nbox + 1);
-    for (auto *v : {&B->pcell, &B->pcoarse, &B->pcoefr, &B->pfaces})
+    for (auto *v : {&B->pcell, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces})
         for (auto &T : *v) T.dev = takeI(B->nbox + 1);
     return off;
 }
@@ -1195,9 +1212,8 @@ namespace {
 // device control reports no active item; graph slot `slot`.  Then reads the
 // final relative residuals of those items for field fid.
 template <class Body>
-int run_cycles(gr_batch B, int slot, int fid, int b0, int b1, const gr_solve_opts &o, Body cycle)
+int run_cycles(gr_batch B, hipStream_t s, const int *any_dev, int slot, const gr_solve_opts &o, Body cycle)
 {
-    hipStream_t s = B->stream;
     const bool graph = B->use_graph && s != nullptr;
     hipGraphExec_t &ge = B->graph[slot];
     const gr_solve_opts &go = B->graph_opts[slot];
@@ -1224,7 +1240,7 @@ int run_cycles(gr_batch B, int slot, int fid, int b0, int b1, const gr_solve_opt
             BCHK(cycle());
         }
         int any = 0;
-        BHIP(hipMemcpyAsync(&any, B->D.any_active, sizeof any, hipMemcpyDeviceToHost, s));
+        BHIP(hipMemcpyAsync(&any, any_dev, sizeof any, hipMemcpyDeviceToHost, s));
         BHIP(hipStreamSynchronize(s));
         if (!any) break;
         if (it > o.max_cycles + 2) return bfail(GR_EDEVICE, "batch control did not stop");
@@ -1232,9 +1248,8 @@ int run_cycles(gr_batch B, int slot, int fid, int b0, int b1, const gr_solve_opt
     return GR_OK;
 }
 
-int read_rel(gr_batch B, int fid, int b0, int b1)
+int read_rel(gr_batch B, hipStream_t s, int fid, int b0, int b1)
 {
-    hipStream_t s = B->stream;
     std::vector<double> sc((size_t)B->nbox * B_NSCAL);
     BHIP(hipMemcpyAsync(sc.data(), B->D.scal, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, s));
     BHIP(hipStreamSynchronize(s));
@@ -1257,67 +1272,64 @@ int batch_field(gr_batch B, int kind, int fid, const gr_solve_opts &o)
     }
     BLAUNCH();
     BCHK(batch_pin(B, fid, 0));
-    BCHK(run_cycles(B, fid, fid, 0, B->nper, o, [&] { return batch_cycle(B, kind, fid, o); }));
+    BCHK(run_cycles(B, s, B->D.any_active, fid, o, [&] { return batch_cycle(B, kind, fid, o); }));
     if (kind == GR_KIND_POISSON) BCHK(batch_pin(B, fid, 0));
-    return read_rel(B, fid, 0, B->nper);
+    return read_rel(B, s, fid, 0, B->nper);
 }
 
 // ------------------------------------------------------------ patch cycle
 
-void patch_smooth(gr_batch B, int kind, int d, int fid, int nu)
+void patch_smooth(gr_batch B, hipStream_t s, int kind, int d, int fid, int nu)
 {
-    hipStream_t s = B->stream;
     const OpConst oc = opc(B);
     const Tab &T = B->pcell[d];
     for (int it = 0; it < nu; ++it)
-        for (int colour = 0; colour < 2; ++colour) KDISPATCH(kind, kp_colour, T.total(), TPB, B->D, T.dev, d, fid, colour, oc);
+        for (int colour = 0; colour < 2; ++colour)
+            KDISPATCH(kind, kp_colour, T.total(), TPB, B->Dp, T.dev, d, fid, colour, oc);
 }
 
 // one cycle of every patch: norms, control, V-cycle (no pin, no frozen means)
-int patch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
+int patch_cycle(gr_batch B, hipStream_t s, int kind, int fid, const gr_solve_opts &o)
 {
-    hipStream_t s = B->stream;
     const OpConst oc = opc(B);
-    KDISPATCH(kind, kp_norms, B->pfine.total(), TPB, B->D, B->pfine.dev, fid, oc);
-    kb_finalize<<<B->npatch, TPB, 0, s>>>(B->D, B->pfine.dev, 2, B_RN, -1, 1, B->nper);
-    kb_control<<<1, 1024, 0, s>>>(B->D, fid, o.rtol, o.max_cycles, B->nper, B->nbox);
+    KDISPATCH(kind, kp_norms, B->pfine.total(), TPB, B->Dp, B->pfine.dev, fid, oc);
+    kb_finalize<<<B->npatch, TPB, 0, s>>>(B->Dp, B->pfine.dev, 2, B_RN, -1, 1, B->nper);
+    kb_control<<<1, 1024, 0, s>>>(B->Dp, fid, o.rtol, o.max_cycles, B->nper, B->nbox);
     for (int d = 0; d < B->pmaxdepth; ++d) {
         if (B->pcell[d].total() == 0) continue;
-        patch_smooth(B, kind, d, fid, o.nu1);
+        patch_smooth(B, s, kind, d, fid, o.nu1);
         const Tab &TC = B->pcoarse[d];
-        KDISPATCH(kind, kp_rr, TC.total(), TPB, B->D, TC.dev, d, fid, oc);
-        KDISPATCH(kind, kp_coarse_rhs, TC.total(), TPB, B->D, TC.dev, d, oc);
+        KDISPATCH(kind, kp_rr, TC.total(), TPB, B->Dp, TC.dev, d, fid, oc);
+        KDISPATCH(kind, kp_coarse_rhs, TC.total(), TPB, B->Dp, TC.dev, d, oc);
     }
-    KDISPATCH(kind, kp_coarse_vcycle, B->npatch, CTPB, B->D, fid, o.nu1, o.nu2, oc, B->nper);
+    KDISPATCH(kind, kp_coarse_vcycle, B->npatch, CTPB, B->Dp, fid, o.nu1, o.nu2, oc, B->nper);
     for (int d = B->pmaxdepth - 1; d >= 0; --d) {
         if (B->pcell[d].total() == 0) continue;
-        kp_prolong<<<B->pcell[d].total(), TPB, 0, s>>>(B->D, B->pcell[d].dev, d, fid);
-        patch_smooth(B, kind, d, fid, o.nu2);
+        kp_prolong<<<B->pcellf[d].total(), TPB, 0, s>>>(B->Dp, B->pcellf[d].dev, d, fid);
+        patch_smooth(B, s, kind, d, fid, o.nu2);
     }
     BLAUNCH();
     return GR_OK;
 }
 
 // boundary values of every level of every patch from the parents' field fid
-void patch_faces(gr_batch B, int fid)
+void patch_faces(gr_batch B, hipStream_t s, int fid)
 {
-    hipStream_t s = B->stream;
     for (int l = 0; l < B->pmaxlev; ++l)
-        if (B->pfaces[l].total()) kp_faces<<<B->pfaces[l].total(), TPB, 0, s>>>(B->D, B->pfaces[l].dev, l, fid);
+        if (B->pfaces[l].total()) kp_faces<<<B->pfaces[l].total(), TPB, 0, s>>>(B->Dp, B->pfaces[l].dev, l, fid);
 }
 
-int patch_field(gr_batch B, int kind, int fid, const gr_solve_opts &o)
+int patch_field(gr_batch B, hipStream_t s, int kind, int fid, const gr_solve_opts &o)
 {
-    hipStream_t s = B->stream;
-    kb_begin_field<<<1, 1024, 0, s>>>(B->D, fid, B->nper, B->nbox, 10 + fid);
+    kb_begin_field<<<1, 1024, 0, s>>>(B->Dp, fid, B->nper, B->nbox, 10 + fid);
     if (kind != GR_KIND_POISSON)
         for (size_t d = 0; d < B->pcoefr.size(); ++d)
             if (B->pcoefr[d].total())
-                kp_restrict_coef<<<B->pcoefr[d].total(), TPB, 0, s>>>(B->D, B->pcoefr[d].dev, (int)d);
-    patch_faces(B, fid);
+                kp_restrict_coef<<<B->pcoefr[d].total(), TPB, 0, s>>>(B->Dp, B->pcoefr[d].dev, (int)d);
+    patch_faces(B, s, fid);
     BLAUNCH();
-    BCHK(run_cycles(B, 10 + fid, fid, B->nper, B->nbox, o, [&] { return patch_cycle(B, kind, fid, o); }));
-    return read_rel(B, fid, B->nper, B->nbox);
+    BCHK(run_cycles(B, s, B->Dp.any_active, 10 + fid, o, [&] { return patch_cycle(B, s, kind, fid, o); }));
+    return read_rel(B, s, fid, B->nper, B->nbox);
 }
 
 } // namespace
@@ -1368,6 +1380,7 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
     B->prm = *prm;
     if (const char *e = std::getenv("GRMG_COARSE_N")) B->coarse_n = std::max(2, std::atoi(e));
     if (const char *e = std::getenv("GRMG_BATCH_GRAPH")) B->use_graph = std::atoi(e) != 0;
+    if (const char *e = std::getenv("GRMG_BATCH_CONCURRENT")) B->conc = std::atoi(e) != 0;
     B->host.resize(count + npatch);
     int maxd = 0, maxc = 0;
     for (int b = 0; b < count; ++b) {
@@ -1459,9 +1472,12 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
     auto cells = [&](int b, int l) { long n = H[b].patch && l < H[b].nlev ? H[b].lev[l].n : 0; return n * n * n; };
     make_tab(B->pfine, nb, [&](int b) { return cells(b, 0); });
     B->pcell.resize(pmaxd);
+    B->pcellf.resize(pmaxd);
     B->pcoarse.resize(pmaxd);
     for (int d = 0; d < pmaxd; ++d) {
-        make_tab(B->pcell[d], nb, [&](int b) { return d < H[b].centry ? cells(b, d) : 0L; });
+        // levels above the entry have n > 16 and even n (they were halved)
+        make_tab(B->pcell[d], nb, [&](int b) { return d < H[b].centry ? cells(b, d) / 2 : 0L; });
+        make_tab(B->pcellf[d], nb, [&](int b) { return d < H[b].centry ? cells(b, d) : 0L; });
         make_tab(B->pcoarse[d], nb, [&](int b) { return d < H[b].centry ? cells(b, d + 1) : 0L; });
     }
     B->pcoefr.resize(std::max(pmaxl - 1, 0));
@@ -1537,10 +1553,17 @@ int gr_batch_bind(gr_batch B, void *d_ws, size_t bytes, void *stream)
     }
     for (auto &T : B->coefr) BHIP(up(T));
     BHIP(up(B->pfine));
-    for (auto *v : {&B->pcell, &B->pcoarse, &B->pcoefr, &B->pfaces})
+    for (auto *v : {&B->pcell, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces})
         for (auto &T : *v) BHIP(up(T));
     BHIP(hipStreamSynchronize(s)); // host tables must outlive the copies
     B->D.nbox = B->nbox;
+    B->Dp = B->D;
+    B->Dp.partials = B->p_partials;
+    B->Dp.any_active = B->p_any;
+    if (B->npatch && !B->pstream) {
+        BHIP(hipStreamCreateWithFlags(&B->pstream, hipStreamNonBlocking));
+        BHIP(hipEventCreateWithFlags(&B->pdone, hipEventDisableTiming));
+    }
     int dev = 0, khz = 0;
     BHIP(hipGetDevice(&dev));
     BHIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
@@ -1554,6 +1577,8 @@ int gr_destroy_batch(gr_batch B)
     if (!B) return GR_OK;
     for (auto &ge : B->graph)
         if (ge) (void)hipGraphExecDestroy(ge);
+    if (B->pdone) (void)hipEventDestroy(B->pdone);
+    if (B->pstream) (void)hipStreamDestroy(B->pstream);
     delete B;
     return GR_OK;
 }
@@ -1618,7 +1643,7 @@ int gr_batch_debug_boundary(gr_batch B, int item, int field, int level, double *
     const BoxDev &X = B->host[item];
     if (level < 0 || level >= X.nlev) return bfail(GR_EINVAL, "level %d outside 0..%d", level, X.nlev - 1);
     hipStream_t s = B->stream;
-    patch_faces(B, field);
+    patch_faces(B, s, field);
     const long w = X.lev[level].n + 2;
     launch_copy(s, d_dst, level == 0 ? X.field[field] : X.lev[level].phi, w * w * w);
     BLAUNCH();
@@ -1648,54 +1673,141 @@ int gr_batch_solve(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_
         for (int f = 0; f < 10; ++f)
             if (mask & (1u << f)) {
                 kb_fill_field<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, f);
-                if (PT) kp_fill_field<<<PT, TPB, 0, s>>>(B->D, B->pfine.dev, f);
+                if (PT) kp_fill_field<<<PT, TPB, 0, s>>>(B->Dp, B->pfine.dev, f);
             }
     BLAUNCH();
+    // the patches' stream: their own, joined to the batch's by events, or the batch's
+    const bool conc = B->npatch && B->conc && B->pstream && s != nullptr;
+    hipStream_t ps = conc ? B->pstream : s;
     auto build = [&](int what, int comp) {
         kb_build<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, what, comp, P.a, P.omega_m, P.c_tilde);
     };
     auto pbuild = [&](int what, int comp) {
-        if (PT) kp_build<<<PT, TPB, 0, s>>>(B->D, B->pfine.dev, what, comp, P.a, P.omega_m, P.c_tilde);
+        if (PT) kp_build<<<PT, TPB, 0, ps>>>(B->Dp, B->pfine.dev, what, comp, P.a, P.omega_m, P.c_tilde);
     };
-    // every field of the patches right after their parents' (their boundary
-    // values and outside stencil values are the parents' solved fields)
-    auto field = [&](int kind, int fid, const std::function<void()> &pre_patch) -> int {
-        if (!(mask & (1u << fid))) return GR_OK;
-        BCHK(batch_field(B, kind, fid, *o));
-        if (B->npatch) {
-            pre_patch();
-            BLAUNCH();
-            BCHK(patch_field(B, kind, fid, *o));
-        }
+    // the ten solves in the order of the solution scheme; the patches' builders
+    // and solve of each field read their parents' solved field (and A_ij)
+    struct Step {
+        int kind, fid;
+        std::function<void()> pre_box, pre_patch;
+    };
+    const std::vector<Step> steps = {
+        {GR_KIND_POISSON, GR_VX, [&] {
+             kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, 0, 4, oc, 0);
+             kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_TMP, -1, 0, 0);
+             build(0, 0);
+         }, [&] { pbuild(0, 0); }},
+        {GR_KIND_POISSON, GR_VY, [&] {
+             kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, 0, 5, oc, 0);
+             kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_TMP, -1, 0, 0);
+             build(0, 1);
+         }, [&] { pbuild(0, 1); }},
+        {GR_KIND_POISSON, GR_VZ, [&] {
+             kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, 0, 6, oc, 0);
+             kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_TMP, -1, 0, 0);
+             build(0, 2);
+         }, [&] { pbuild(0, 2); }},
+        {GR_KIND_POISSON, GR_U, [&] { build(1, 0); }, [&] { pbuild(1, 0); }},
+        {GR_KIND_HAMILTONIAN, GR_PSI, [&] { build(2, 0); }, [&] { pbuild(2, 0); }},
+        {GR_KIND_CMC, GR_XI, [&] { build(3, 0); }, [&] { pbuild(3, 0); }},
+        {GR_KIND_POISSON, GR_BX, [&] {
+             build(4, 0);
+             build(6, 0);
+         }, [&] {
+             pbuild(4, 0);
+             pbuild(6, 0);
+         }},
+        {GR_KIND_POISSON, GR_BY, [&] { build(6, 1); }, [&] { pbuild(6, 1); }},
+        {GR_KIND_POISSON, GR_BZ, [&] { build(6, 2); }, [&] { pbuild(6, 2); }},
+        {GR_KIND_POISSON, GR_BB, [&] { build(5, 0); }, [&] { pbuild(5, 0); }},
+    };
+    auto patch_step = [&](const Step &S) -> int {
+        S.pre_patch();
+        BLAUNCH();
+        if (mask & (1u << S.fid)) BCHK(patch_field(B, ps, S.kind, S.fid, *o));
         return GR_OK;
     };
-    for (int d = 0; d < 3; ++d) {
-        if (!(mask & (1u << d))) continue;
-        kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, 0, 4 + d, oc, 0);
-        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_TMP, -1, 0, 0);
-        build(0, d);
-        BLAUNCH();
-        BCHK(field(GR_KIND_POISSON, GR_VX + d, [&] { pbuild(0, d); }));
+    // concurrent patches: a host thread follows the boxes field by field.  A
+    // box solve returns after synchronising the batch's stream, so once a step
+    // is marked ready its fields are complete on the device and the patches'
+    // stream needs no device-side wait (an event wait could also collide with
+    // the box thread's graph capture of its next field)
+    std::mutex mu;
+    std::condition_variable cv;
+    int ready = -1;      // last step whose box work is complete
+    bool abort = false;  // the box thread failed
+    int pstatus = GR_OK;
+    std::string perr;
+    std::thread worker;
+    int dev = 0;
+    BHIP(hipGetDevice(&dev));
+    if (conc) {
+        worker = std::thread([&] {
+            if (hipSetDevice(dev) != hipSuccess) {
+                pstatus = GR_EDEVICE;
+                perr = "patch thread: hipSetDevice failed";
+                return;
+            }
+            for (size_t k = 0; k < steps.size(); ++k) {
+                {
+                    std::unique_lock<std::mutex> lk(mu);
+                    cv.wait(lk, [&] { return ready >= (int)k || abort; });
+                    if (abort) return;
+                }
+                const int st = patch_step(steps[k]);
+                if (st != GR_OK) {
+                    pstatus = st;
+                    perr = b_err;
+                    return;
+                }
+            }
+            if (hipEventRecord(B->pdone, ps) != hipSuccess) {
+                pstatus = GR_EDEVICE;
+                perr = "patch stream: event record failed";
+            }
+        });
     }
-    build(1, 0);
-    BCHK(field(GR_KIND_POISSON, GR_U, [&] { pbuild(1, 0); }));
-    build(2, 0);
-    BCHK(field(GR_KIND_HAMILTONIAN, GR_PSI, [&] { pbuild(2, 0); }));
-    build(3, 0);
-    BCHK(field(GR_KIND_CMC, GR_XI, [&] { pbuild(3, 0); }));
-    build(4, 0);
-    bool pB = false; // patch shift sources built (needs the patches' Psi, xi and A_ij)
-    for (int d = 0; d < 3; ++d) {
-        build(6, d);
-        BLAUNCH();
-        BCHK(field(GR_KIND_POISSON, GR_BX + d, [&] {
-            if (!pB) pbuild(4, 0);
-            pB = true;
-            pbuild(6, d);
-        }));
+    int bstatus = GR_OK;
+    for (size_t k = 0; k < steps.size() && bstatus == GR_OK; ++k) {
+        const Step &S = steps[k];
+        S.pre_box();
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) bstatus = bfail(GR_EDEVICE, "kernel launch: %s", hipGetErrorString(e));
+        if (bstatus == GR_OK && (mask & (1u << S.fid))) bstatus = batch_field(B, S.kind, S.fid, *o);
+        if (bstatus != GR_OK) break;
+        if (conc) {
+            if (!(mask & (1u << S.fid))) { // no solve synchronised the stream
+                e = hipStreamSynchronize(s);
+                if (e != hipSuccess) {
+                    bstatus = bfail(GR_EDEVICE, "stream sync: %s", hipGetErrorString(e));
+                    break;
+                }
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            ready = (int)k;
+            cv.notify_all();
+        } else if (B->npatch) {
+            bstatus = patch_step(S);
+        }
     }
-    build(5, 0);
-    BCHK(field(GR_KIND_POISSON, GR_BB, [&] { pbuild(5, 0); }));
+    if (conc) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (bstatus != GR_OK) abort = true;
+            cv.notify_all();
+        }
+        worker.join();
+        if (bstatus != GR_OK || pstatus != GR_OK) {
+            (void)hipStreamSynchronize(ps); // nothing of the patches may still run on return
+            if (bstatus == GR_OK) {
+                b_err = perr;
+                return pstatus;
+            }
+        } else {
+            BHIP(hipStreamWaitEvent(s, B->pdone, 0));
+        }
+    }
+    if (bstatus != GR_OK) return bstatus;
     BLAUNCH();
     // results
     std::vector<int> st(B->nbox), cyc((size_t)B->nbox * 10);

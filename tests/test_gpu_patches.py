@@ -127,6 +127,26 @@ def test_patch_solve_converges_and_graphs_replay_eager(monkeypatch):
                 assert torch.equal(E.get_field(item, f), G.get_field(item, f)), (rep, j, f)
 
 
+def test_concurrent_patches_match_sequential(monkeypatch):
+    """Patches on their own stream, each field started as soon as the boxes'
+    solve of it is done, give the sequential order's result bit for bit."""
+    boxes, patches, box_src, patch_src = _patch_case()
+    print("[gpu] concurrent vs sequential patches", flush=True)
+    monkeypatch.setenv("GRMG_BATCH_CONCURRENT", "0")
+    S = grmg.Batch(boxes, **PRM, patches=patches)
+    monkeypatch.delenv("GRMG_BATCH_CONCURRENT")
+    Cc = grmg.Batch(boxes, **PRM, patches=patches)
+    for B in (S, Cc):
+        _load(B, boxes, box_src, patch_src)
+    rs = S.solve(rtol=1e-10)
+    rc = Cc.solve(rtol=1e-10)
+    assert rs["status"] == rc["status"] == grmg.OK
+    assert rs["cycles"] == rc["cycles"] and rs["rel_res"] == rc["rel_res"]
+    for item in range(len(boxes) + len(patches)):
+        for f in range(10):
+            assert torch.equal(S.get_field(item, f), Cc.get_field(item, f)), (item, f)
+
+
 def test_patches_with_odd_coarsest_levels_converge():
     """Sides whose hierarchies end at 7^3 and 9^3 (56, 72) and 5^3 (40) on a
     64^3 parent."""
