@@ -54,22 +54,33 @@ def time_sweeps(torch, grmg, g, kind, nsweeps, reps):
 def pmc_traffic(n):
     """HBM bytes per launch of the FP64 Hamiltonian sweep at 256^3 from the
     committed counter summary, scaled by its copy-kernel calibration; None if
-    the smoother source changed since the counters were taken."""
-    import hashlib
-
+    the smoother sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "rb_fused_hamiltonian_fp64_256_pmc.md")
-    src = os.path.join(ROOT, "paper_1905_08890_amd", "csrc", "stencil.hip")
     if n != 256 or not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].split(": ", 1)
-            vals[k.strip()] = v.strip().strip("`")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if vals.get("stencil.hip sha256") != sha:
+            v = v.strip()
+            vals[k.strip()] = v[1:v.index("`", 1)] if v.startswith("`") else v
+    if vals.get("kernel sources sha256") != kernel_sources_sha():
         return None
     return int(vals["traffic bytes per launch"])
+
+
+SWEEP_SOURCES = ("stencil.hip", "fused_sweep.h", "stencil_ops.h", "gr_internal.h")
+
+
+def kernel_sources_sha():
+    """sha256 over the sources that define the fused sweep and its launch
+    configuration, in a fixed order."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in SWEEP_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1905_08890_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
 
 
 def cpu_baseline(n, pos, u, mass, cycles):

@@ -822,7 +822,7 @@ int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out)
     g->nlev = num_levels(n);
     // tuning knobs (environment): GRMG_SMOOTHER=split|fused forces one smoother
     // on every level it can run on; GRMG_FUSED_MIN (smallest level for the fused
-    // smoother), GRMG_FUSED_TILE (0: 64x8, 1: 32x16), GRMG_XCD_REMAP (0/1),
+    // smoother), GRMG_FUSED_TILE (0: 64x8, 1: 32x16, 2: 64x16), GRMG_XCD_REMAP (0/1),
     // GRMG_FUSED_WGS (target workgroups per fused launch), GRMG_FUSED_PF (prefetch
     // depth 1 or 2 planes), GRMG_COARSE_N (levels
     // at or below this size run the rest of the V-cycle in one workgroup; 0: never;
@@ -834,7 +834,7 @@ int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out)
         if (std::strcmp(e, "fused") == 0) g->fcfg.min_n = 64;
     }
     if (const char *e = std::getenv("GRMG_FUSED_MIN")) g->fcfg.min_n = std::atoi(e);
-    if (const char *e = std::getenv("GRMG_FUSED_TILE")) g->fcfg.tile = std::atoi(e) == 1 ? 1 : 0;
+    if (const char *e = std::getenv("GRMG_FUSED_TILE")) g->fcfg.tile = std::min(2, std::max(0, std::atoi(e)));
     if (const char *e = std::getenv("GRMG_XCD_REMAP")) g->fcfg.xcd_remap = std::atoi(e) != 0;
     if (const char *e = std::getenv("GRMG_FUSED_WGS")) g->fcfg.target_wgs = std::max(1, std::atoi(e));
     if (const char *e = std::getenv("GRMG_FUSED_PF")) g->fcfg.pf = std::atoi(e) == 2 ? 2 : (std::atoi(e) == 1 ? 1 : 0);
@@ -1244,6 +1244,8 @@ int gr_set_guess(gr_grid g, int level, int count, const int *fields, const doubl
 // depend on the configuration (same per-point arithmetic, exact red-black
 // order), only its speed does.
 
+const char *const kTileName[3] = {"64x8", "32x16", "64x16"};
+
 int gr_autotune(gr_grid g, char *report, size_t report_bytes)
 {
     CHK(check_bound(g));
@@ -1278,8 +1280,8 @@ int gr_autotune(gr_grid g, char *report, size_t report_bytes)
                     }
             }
             if (best_us < 0.f) {
-                for (int tile = 0; tile < 2; ++tile)
-                    for (int wgs : {512, 1024, 2048})
+                for (int tile = 0; tile < 3; ++tile)
+                    for (int wgs : {256, 512, 1024, 2048})
                         for (int pf = 1; pf <= 2; ++pf) {
                             FusedCfg c = g->fcfg;
                             c.tile = tile;
@@ -1346,7 +1348,8 @@ int gr_autotune(gr_grid g, char *report, size_t report_bytes)
                 std::snprintf(line, sizeof line, "n=%d kind=%d split us=%.2f\n", L.n, kind, best_us);
             else
                 std::snprintf(line, sizeof line, "n=%d kind=%d tile=%s wgs=%d pf=%d us=%.2f\n", L.n, kind,
-                              best.tile ? "32x16" : "64x8", best.target_wgs, best.pf, best_us);
+                              kTileName[best.tile], best.target_wgs, best.pf,
+                              best_us);
             rep += line;
         }
     }

@@ -830,9 +830,9 @@ static void launch_fused_k(int pf, unsigned grid, hipStream_t s, const T *in, T 
 {
     constexpr int NT = (TX / 2) * TY;
     // default prefetch depth (measured at 256^3): two planes, except for the
-    // FP64 Hamiltonian and CMC sweeps, whose extra registers would cost a
-    // resident workgroup per CU
-    if (pf <= 0) pf = (sizeof(T) == 4 || KIND == GR_KIND_POISSON) ? 2 : 1;
+    // FP64 Hamiltonian and CMC sweeps in tiles under 64x16, whose extra
+    // registers would cost a resident workgroup per CU
+    if (pf <= 0) pf = (TX * TY >= 1024 || sizeof(T) == 4 || KIND == GR_KIND_POISSON) ? 2 : 1;
     if (pf == 2)
         k_rb_fused<KIND, T, TX, TY, 2><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,
                                                              tiles_y, xcd_remap);
@@ -878,6 +878,8 @@ static void launch_fused_any(int kind, hipStream_t s, const T *in, T *out, const
 {
     if (cfg.tile == 1)
         launch_fused_t<T, 32, 16>(kind, s, in, out, f, c1, c2, n, h, oc, fbar, fshift, cfg);
+    else if (cfg.tile == 2)
+        launch_fused_t<T, 64, 16>(kind, s, in, out, f, c1, c2, n, h, oc, fbar, fshift, cfg);
     else
         launch_fused_t<T, 64, 8>(kind, s, in, out, f, c1, c2, n, h, oc, fbar, fshift, cfg);
 }
