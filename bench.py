@@ -51,6 +51,28 @@ def time_sweeps(torch, grmg, g, kind, nsweeps, reps):
     return best * 1e-3  # seconds per sweep
 
 
+def copy_probe(torch, grmg, g, n, reps=7):
+    """A plain device copy of n^3 doubles through the library (gr_set_field:
+    reads and writes 8 n^3 bytes), timed with HIP events on the grid's
+    stream: the practical HBM rate beside the 8 TB/s peak."""
+    src = torch.zeros((n,) * 3, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    fid = grmg.FIELD_IDS["rhs"]
+    grmg.set_field(g.handle, fid, src, grmg.F64)
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(g.stream)
+        for _ in range(4):
+            grmg.set_field(g.handle, fid, src, grmg.F64)
+        e1.record(g.stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 4)
+    times.sort()
+    return 16.0 * n ** 3 / (times[len(times) // 2] * 1e-3) / 1e9
+
+
 def pmc_traffic(n):
     """HBM bytes per launch of the FP64 Hamiltonian sweep at 256^3 from the
     committed counter summary, scaled by its copy-kernel calibration; None if
@@ -325,6 +347,9 @@ def main():
     log(f"smoother sweep: hamiltonian {t_ham * 1e6:.1f} us ({gbps_ham:.0f} GB/s), "
         f"poisson {t_poi * 1e6:.1f} us ({gbps_poi:.0f} GB/s)")
 
+    copy_gbps = copy_probe(torch, grmg, g, n)
+    log(f"copy probe: {copy_gbps:.0f} GB/s")
+
     ham_in_solve = SWEEP_BYTES["hamiltonian"] * N / (in_solve[1][1] * 1e-3) / 1e9
     out = {
         "metric": "time-to-residual 1e-10 and smoother GB/s at 256^3; learned+mixed vs plain FP64",
@@ -354,6 +379,7 @@ def main():
                      "poisson_us_per_sweep": round(t_poi * 1e6, 2), "poisson_GBps": round(gbps_poi, 1)},
         "roofline": {"bound": "hbm", "achieved": round(ham_in_solve, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(ham_in_solve / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "copy_probe_GBps": round(copy_gbps, 1),
                      "kernel": f"fused red-black Newton sweep, Hamiltonian, FP64, finest level: 32 B/point/sweep x "
                                f"{n}^3 points per launch, mean of {in_solve[1][0]} launches in one FP64 solve step "
                                f"({in_solve[1][1] * 1e3:.2f} us)"},
