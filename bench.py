@@ -237,6 +237,10 @@ def bench_batch(torch, grmg, synth, steps):
         for name, x in zip(("s0", "sx", "sy", "sz", "sm"), src):
             B.set_field(i, name, x)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tune = B.autotune()
+    tune_s = time.perf_counter() - t0
+    log(f"batch autotune ({tune_s:.2f} s):\n{tune}")
     rep = B.solve(rtol=1e-10)  # warm-up (also captures the per-cycle graphs)
     times = []
     for _ in range(steps):
@@ -249,8 +253,8 @@ def bench_batch(torch, grmg, synth, steps):
     secs = np.array(rep["item_seconds"]) * 1e3
     npb = len(sides)
     out = {"workload": "96 periodic boxes (sides {32,48,64,96,128}, seeds 100-195) + 32 Dirichlet patches (sides "
-                       "24-80, seeds 196-227, half the parent's spacing), all ten fields to rtol 1e-10, FP64, one "
-                       "grouped launch per phase, hipGraph per cycle",
+                       "24-80, seeds 196-227, half the parent's spacing), all ten fields to rtol 1e-10, FP64, autotuned "
+                       "smoothing forms, one grouped launch per phase, hipGraph per cycle",
            "status": rep["status"], "points": int(pts.sum()), "patch_points": int(pts[npb:].sum()),
            "seconds": round(dt, 4),
            "points_cycles_per_s": round(float((pts[:, None] * cyc).sum() / dt), 1),
@@ -258,7 +262,8 @@ def bench_batch(torch, grmg, synth, steps):
            "item_ms_p99": round(float(np.percentile(secs, 99)), 3),
            "patch_item_ms_p50": round(float(np.percentile(secs[npb:], 50)), 3),
            "cycles_min_max": [int(cyc.sum(1).min()), int(cyc.sum(1).max())],
-           "patch_cycles_min_max": [int(cyc[npb:].sum(1).min()), int(cyc[npb:].sum(1).max())]}
+           "patch_cycles_min_max": [int(cyc[npb:].sum(1).min()), int(cyc[npb:].sum(1).max())],
+           "autotune": {"seconds": round(tune_s, 3), "choices": tune.strip().splitlines()}}
     log(f"batch: {out}")
     B.close()
     return out

@@ -300,6 +300,14 @@ int gr_batch_get_field(gr_batch b, int item, int field, void *d_dst, int dtype);
  * time from the start of each field's solve until the box met its tolerance,
  * summed over the fields).  Returns the first non-OK box status. */
 int gr_batch_solve(gr_batch b, const gr_solve_opts *opts, int *cycles, double *rel_res, double *item_seconds);
+/* Tunes how each level of the periodic boxes is smoothed: for every depth
+ * handled by grouped launches and every box side there with n >= 64 and
+ * n % 32 == 0 it times one launch per colour, fused 32x16 tiles and (n % 64
+ * == 0) fused 64x16 tiles on that side's boxes, and keeps the fastest.  All
+ * forms compute the same bits.  Uses field b of the boxes as scratch and
+ * restores it; drops the captured cycle graphs.  Writes one line per (depth,
+ * side) to `report` (may be NULL).  Errors: GR_ESTATE if unbound. */
+int gr_batch_autotune(gr_batch b, char *report, size_t report_bytes);
 /* Low level, for checks of the boundary values: writes the boundary values of
  * every level of every patch from their parents' current `field`, then copies
  * level `level` of patch `item`'s iterate, padded ((n_l+2)^3, x fastest; the

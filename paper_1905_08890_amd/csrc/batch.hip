@@ -127,20 +127,21 @@ __global__ void __launch_bounds__(TPB) kb_colour(BatchDev D, const int *__restri
 }
 
 // Fused red-black sweeps (rb_fused_tile) of the boxes whose level d takes
-// 32x16 tiles: one workgroup per tile x 16-plane chunk, the box from the
-// block prefix table.  Out of place: even sweeps phi -> tmp, odd tmp -> phi.
+// TX x TY tiles (32x16 or 64x16): one workgroup per tile x 16-plane chunk, the
+// box from the block prefix table.  Out of place: even sweeps phi -> tmp, odd
+// tmp -> phi.
 constexpr int kFZ = 16; // z-chunk of the batched fused sweep
 
-template <int KIND>
-__global__ void __launch_bounds__(TPB) kb_fused(BatchDev D, const int *__restrict__ tab, int d, int fid, int sweep,
-                                                OpConst oc)
+template <int KIND, int TX, int TY>
+__global__ void __launch_bounds__((TX / 2) * TY) kb_fused(BatchDev D, const int *__restrict__ tab, int d, int fid,
+                                                          int sweep, OpConst oc)
 {
     const int b = find_box(tab, D.nbox, blockIdx.x);
     if (!D.active[b]) return;
     const BoxDev &X = D.box[b];
     const BoxLev &L = X.lev[d];
     const int n = L.n, lb = blockIdx.x - tab[b];
-    const int nz = n / kFZ, tiles_y = n / 16;
+    const int nz = n / kFZ, tiles_y = n / TY;
     const int zchunk = lb % nz, t2 = lb / nz;
     double *phi = d == 0 ? X.field[fid] : L.phi;
     const double *in = (sweep & 1) ? L.tmp : phi;
@@ -148,8 +149,8 @@ __global__ void __launch_bounds__(TPB) kb_fused(BatchDev D, const int *__restric
     const double Fb = d == 0 ? D.scal[b * B_NSCAL + B_FBAR] : 0.0;
     const double fs = d == 0 ? D.scal[b * B_NSCAL + B_FSHIFT] : 0.0;
     constexpr int PF = KIND == GR_KIND_POISSON ? 2 : 1;
-    rb_fused_tile<KIND, double, 32, 16, PF>(in, out, L.f, L.coef, nullptr, n, kFZ, 1.0 / (L.h * L.h), oc, Fb, fs,
-                                            (t2 / tiles_y) * 32, (t2 % tiles_y) * 16, zchunk * kFZ);
+    rb_fused_tile<KIND, double, TX, TY, PF>(in, out, L.f, L.coef, nullptr, n, kFZ, 1.0 / (L.h * L.h), oc, Fb, fs,
+                                            (t2 / tiles_y) * TX, (t2 % tiles_y) * TY, zchunk * kFZ);
 }
 
 
@@ -1020,7 +1021,11 @@ struct gr_batch_s {
     int maxdepth = 0;           // deepest multigrid level handled by grouped launches
     Tab fine;                   // fine level of every box
     std::vector<Tab> colour, cdom, coefr; // per depth
-    std::vector<Tab> fz, colour_nf;             // per depth: fused boxes, the other boxes' colour passes
+    std::vector<Tab> fz, fz64, colour_nf;       // per depth: fused boxes (32x16, 64x16 tiles), the others' colour passes
+    // per depth and box: how level d is smoothed: 0 one launch per colour,
+    // 1 fused 32x16, 2 fused 64x16, -1 not at all (only while tuning)
+    std::vector<std::vector<signed char>> form;
+    std::string tune_report;
     std::vector<Tab> rr;                        // per depth: residual + restriction (marching or per cell)
     Tab norms;                                  // stopping norms of the fine level
     bool use_march = true;
@@ -1106,6 +1111,7 @@ size_t batch_layout(gr_batch B, char *base)
         B->colour[d].dev = takeI(B->nbox + 1);
         B->cdom[d].dev = takeI(B->nbox + 1);
         B->fz[d].dev = takeI(B->nbox + 1);
+        B->fz64[d].dev = takeI(B->nbox + 1);
         B->rr[d].dev = takeI(B->nbox + 1);
         B->colour_nf[d].dev = takeI(B->nbox + 1);
     }
@@ -1151,18 +1157,43 @@ int batch_pin(gr_batch B, int fid, int active_only)
 // one cycle of the batch: frozen means, norms, control, V-cycle, pin
 // nu sweeps of level d of every box: fused (out of place, an even count ends
 // in phi) for the boxes that take 32x16 tiles, one launch per colour for the rest
+template <int TX, int TY>
+void launch_kb_fused(hipStream_t s, int kind, const Tab &T, BatchDev D, int d, int fid, int it, OpConst oc)
+{
+    constexpr int NT = (TX / 2) * TY;
+    if (kind == GR_KIND_POISSON) kb_fused<GR_KIND_POISSON, TX, TY><<<T.total(), NT, 0, s>>>(D, T.dev, d, fid, it, oc);
+    else if (kind == GR_KIND_HAMILTONIAN)
+        kb_fused<GR_KIND_HAMILTONIAN, TX, TY><<<T.total(), NT, 0, s>>>(D, T.dev, d, fid, it, oc);
+    else kb_fused<GR_KIND_CMC, TX, TY><<<T.total(), NT, 0, s>>>(D, T.dev, d, fid, it, oc);
+}
+
 void batch_smooth(gr_batch B, int kind, int d, int fid, int nu)
 {
     hipStream_t s = B->stream;
     const OpConst oc = opc(B);
-    const bool fused = B->use_fused && nu % 2 == 0 && B->fz[d].total() > 0;
+    // the fused forms work out of place in pairs of sweeps
+    const bool fused = nu % 2 == 0 && (B->fz[d].total() > 0 || B->fz64[d].total() > 0);
     const Tab &TC = fused ? B->colour_nf[d] : B->colour[d];
     for (int it = 0; it < nu; ++it) {
-        if (fused) KDISPATCH(kind, kb_fused, B->fz[d].total(), TPB, B->D, B->fz[d].dev, d, fid, it, oc);
+        if (fused && B->fz[d].total()) launch_kb_fused<32, 16>(s, kind, B->fz[d], B->D, d, fid, it, oc);
+        if (fused && B->fz64[d].total()) launch_kb_fused<64, 16>(s, kind, B->fz64[d], B->D, d, fid, it, oc);
         if (TC.total() > 0)
             for (int colour = 0; colour < 2; ++colour)
                 KDISPATCH(kind, kb_colour, TC.total(), TPB, B->D, TC.dev, d, fid, colour, oc);
     }
+}
+
+// smoothing tables of depth d from the boxes' forms
+void smooth_tabs(gr_batch B, int d)
+{
+    const auto &H = B->host;
+    const auto &F = B->form[d];
+    const int nb = B->nbox;
+    auto blocks = [&](int b, int tx, int ty) { const long n = H[b].lev[d].n; return (n / tx) * (n / ty) * (n / kFZ); };
+    // block counts for the 512-thread 64x16 launches, as items of TPB threads
+    make_tab(B->fz[d], nb, [&](int b) { return F[b] == 1 ? blocks(b, 32, 16) * TPB : 0L; });
+    make_tab(B->fz64[d], nb, [&](int b) { return F[b] == 2 ? blocks(b, 64, 16) * TPB : 0L; });
+    make_tab(B->colour_nf[d], nb, [&](int b) { long n = H[b].lev[d].n; return F[b] == 0 ? n * n * n / 2 : 0L; });
 }
 
 int batch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
@@ -1431,6 +1462,7 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
     B->colour.resize(maxd);
     B->cdom.resize(maxd);
     B->fz.resize(maxd);
+    B->fz64.resize(maxd);
     B->rr.resize(maxd);
     if (const char *e = std::getenv("GRMG_MARCH")) B->use_march = std::atoi(e) != 0;
     make_tab(B->norms, nb, [&](int b) {
@@ -1447,20 +1479,21 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
     auto grouped = [&](int b, int d) { return !H[b].patch && d < H[b].centry; };
     for (int d = 0; d < maxd; ++d) {
         make_tab(B->colour[d], nb, [&](int b) { long n = H[b].lev[d].n; return grouped(b, d) ? n * n * n / 2 : 0L; });
-        make_tab(B->fz[d], nb, [&](int b) {
-            const long n = H[b].lev[d].n;
-            return fusable(b, d) ? (n / 32) * (n / 16) * (n / kFZ) * TPB : 0L; // workgroups x threads
-        });
+
         make_tab(B->rr[d], nb, [&](int b) {
             if (!grouped(b, d)) return 0L;
             const long n = H[b].lev[d].n, m = H[b].lev[d + 1].n;
             return B->use_march && marchable((int)n) ? march_blocks((int)n) * TPB : m * m * m;
         });
-        make_tab(B->colour_nf[d], nb, [&](int b) {
-            long n = H[b].lev[d].n;
-            return grouped(b, d) && !fusable(b, d) ? n * n * n / 2 : 0L;
-        });
+
         make_tab(B->cdom[d], nb, [&](int b) { long m = grouped(b, d) ? H[b].lev[d + 1].n : 0; return m * m * m; });
+    }
+    // untuned forms: 32x16 fused sweeps where they tile, else one launch per colour
+    B->form.assign(maxd, std::vector<signed char>(nb, 0));
+    for (int d = 0; d < maxd; ++d) {
+        for (int b = 0; b < nb; ++b)
+            B->form[d][b] = !grouped(b, d) ? -1 : (B->use_fused && fusable(b, d) ? 1 : 0);
+        smooth_tabs(B, d);
     }
     B->coefr.resize(maxc);
     for (int d = 0; d < maxc; ++d)
@@ -1548,6 +1581,7 @@ int gr_batch_bind(gr_batch B, void *d_ws, size_t bytes, void *stream)
         BHIP(up(B->colour[d]));
         BHIP(up(B->cdom[d]));
         BHIP(up(B->fz[d]));
+        BHIP(up(B->fz64[d]));
         BHIP(up(B->rr[d]));
         BHIP(up(B->colour_nf[d]));
     }
@@ -1633,6 +1667,99 @@ int gr_batch_get_field(gr_batch B, int item, int field, void *d_dst, int dtype)
     else return bfail(GR_EINVAL, "bad dtype %d", dtype);
     BLAUNCH();
     return GR_OK;
+}
+
+int gr_batch_autotune(gr_batch B, char *report, size_t report_bytes)
+{
+    if (!B || !B->bound) return bfail(B ? GR_ESTATE : GR_EINVAL, "batch not bound");
+    hipStream_t s = B->stream;
+    const auto &H = B->host;
+    // the sweeps run on field b of the boxes and their level scratch: keep b in
+    // the (then unused) first shift-source array and restore it afterwards
+    for (int b = 0; b < B->nper; ++b) launch_copy(s, H[b].fB[0], H[b].field[GR_BB], (long)H[b].lev[0].n * H[b].lev[0].n * H[b].lev[0].n);
+    kb_begin_field<<<1, 1024, 0, s>>>(B->D, GR_BB, 0, B->nper, GR_BB); // every box active
+    BLAUNCH();
+    hipEvent_t e0, e1;
+    BHIP(hipEventCreate(&e0));
+    BHIP(hipEventCreate(&e1));
+    auto upload = [&](int d) {
+        hipError_t e = hipSuccess;
+        for (Tab *T : {&B->fz[d], &B->fz64[d], &B->colour_nf[d]})
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(T->dev, T->start.data(), sizeof(int) * T->start.size(), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s); // the host tables change next
+        return e;
+    };
+    std::string rep;
+    int st = GR_OK;
+    for (int d = 0; d < B->maxdepth && st == GR_OK; ++d) {
+        std::vector<signed char> base = B->form[d];
+        std::vector<int> sides;
+        for (int b = 0; b < B->nper; ++b)
+            if (base[b] >= 0) {
+                const int n = H[b].lev[d].n;
+                if (n >= 64 && n % 32 == 0 && std::find(sides.begin(), sides.end(), n) == sides.end()) sides.push_back(n);
+            }
+        std::sort(sides.begin(), sides.end());
+        std::vector<signed char> best = base;
+        for (int n : sides) {
+            int best_form = -1;
+            float best_us = 0.f;
+            for (int form = 0; form <= 2 && st == GR_OK; ++form) {
+                if (form == 2 && n % 64) continue;
+                auto &F = B->form[d];
+                for (int b = 0; b < B->nper; ++b) F[b] = (base[b] >= 0 && H[b].lev[d].n == n) ? form : -1;
+                for (int b = B->nper; b < B->nbox; ++b) F[b] = -1;
+                smooth_tabs(B, d);
+                hipError_t e = upload(d);
+                if (e != hipSuccess) {
+                    st = bfail(GR_EDEVICE, "batch autotune: %s", hipGetErrorString(e));
+                    break;
+                }
+                batch_smooth(B, GR_KIND_POISSON, d, GR_BB, 2);
+                (void)hipEventRecord(e0, s);
+                for (int r = 0; r < 3; ++r) batch_smooth(B, GR_KIND_POISSON, d, GR_BB, 2);
+                (void)hipEventRecord(e1, s);
+                e = hipEventSynchronize(e1);
+                if (e != hipSuccess) {
+                    st = bfail(GR_EDEVICE, "batch autotune: %s", hipGetErrorString(e));
+                    break;
+                }
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                const float us = ms * 1e3f / 3.f;
+                if (best_form < 0 || us < best_us) {
+                    best_form = form;
+                    best_us = us;
+                }
+            }
+            if (st != GR_OK) break;
+            for (int b = 0; b < B->nper; ++b)
+                if (base[b] >= 0 && H[b].lev[d].n == n) best[b] = (signed char)best_form;
+            static const char *const names[3] = {"colour", "fused32x16", "fused64x16"};
+            char line[128];
+            std::snprintf(line, sizeof line, "depth=%d n=%d form=%s us=%.2f\n", d, n, names[best_form], best_us);
+            rep += line;
+        }
+        B->form[d] = best;
+        smooth_tabs(B, d);
+        if (st == GR_OK) {
+            hipError_t e = upload(d);
+            if (e != hipSuccess) st = bfail(GR_EDEVICE, "batch autotune: %s", hipGetErrorString(e));
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (int b = 0; b < B->nper; ++b) launch_copy(s, H[b].field[GR_BB], H[b].fB[0], (long)H[b].lev[0].n * H[b].lev[0].n * H[b].lev[0].n);
+    BLAUNCH();
+    for (int f = 0; f < 10; ++f) // captured cycles hold the old launch shapes
+        if (B->graph[f]) {
+            (void)hipGraphExecDestroy(B->graph[f]);
+            B->graph[f] = nullptr;
+        }
+    B->tune_report = rep;
+    if (report && report_bytes) std::snprintf(report, report_bytes, "%s", rep.c_str());
+    return st;
 }
 
 int gr_batch_debug_boundary(gr_batch B, int item, int field, int level, double *d_dst)

@@ -33,7 +33,7 @@ FIELD_IDS.update(dict(s0=S0, sx=SX, sy=SY, sz=SZ, sm=SM, AA=AA, Phi=PHI, alpha=A
 EXPORTS = ("gr_default_opts", "gr_create_grid", "gr_workspace_bytes", "gr_bind", "gr_deposit_sources",
            "gr_set_field", "gr_get_field", "gr_solve_constraints", "gr_solve_equation", "gr_debug_sweep",
            "gr_debug_residual", "gr_destroy_grid", "gr_last_error", "gr_features", "gr_set_guess", "gr_autotune", "gr_sweep_timing", "gr_create_batch", "gr_create_batch_patches",
-           "gr_batch_debug_boundary", "gr_batch_workspace_bytes",
+           "gr_batch_debug_boundary", "gr_batch_autotune", "gr_batch_workspace_bytes",
            "gr_batch_bind", "gr_batch_set_field", "gr_batch_get_field", "gr_batch_solve", "gr_destroy_batch",
            "gr_batch_last_error", "gr_unet_create", "gr_unet_workspace_bytes", "gr_unet_param_count", "gr_unet_bind",
            "gr_unet_init", "gr_unet_set_params", "gr_unet_get_params", "gr_unet_forward", "gr_unet_loss_grad",
@@ -112,6 +112,7 @@ def load_library(path: str = LIB_PATH):
         "gr_create_batch_patches": [C.POINTER(GrGridDesc), C.c_int, C.POINTER(GrPatchDesc), C.c_int,
                                     C.POINTER(GrParams), C.POINTER(vp)],
         "gr_batch_debug_boundary": [vp, C.c_int, C.c_int, C.c_int, vp],
+        "gr_batch_autotune": [vp, C.c_char_p, C.c_size_t],
         "gr_batch_workspace_bytes": [vp, C.POINTER(C.c_size_t)],
         "gr_batch_bind": [vp, vp, C.c_size_t, vp],
         "gr_batch_set_field": [vp, C.c_int, C.c_int, vp, C.c_int],
@@ -367,6 +368,12 @@ def batch_get_field(b: int, item: int, field: int, dst, dtype: int) -> None:
     _bcheck(load_library().gr_batch_get_field(b, item, field, _ptr(dst), dtype))
 
 
+def batch_autotune(b: int) -> str:
+    buf = C.create_string_buffer(8192)
+    _bcheck(load_library().gr_batch_autotune(b, buf, len(buf)))
+    return buf.value.decode()
+
+
 def batch_debug_boundary(b: int, item: int, field: int, level: int, dst) -> None:
     _bcheck(load_library().gr_batch_debug_boundary(b, item, field, level, _ptr(dst)))
 
@@ -437,6 +444,12 @@ class Batch:
         batch_get_field(self.handle, item, fid, out, F64)
         self.stream.synchronize()
         return out
+
+    def autotune(self) -> str:
+        """Choose each (level, box side)'s smoothing form by timing them."""
+        rep = batch_autotune(self.handle)
+        self.stream.synchronize()
+        return rep
 
     def debug_boundary(self, item, field, level):
         """Padded level `level` of patch `item` after writing its boundary values

@@ -106,3 +106,31 @@ def test_batch_rejects_bad_input():
     x = torch.zeros((8, 8, 8), dtype=torch.float64, device="cuda")
     with pytest.raises(grmg.GrError):
         grmg.batch_set_field(B.handle, 5, grmg.S0, x, grmg.F64)
+
+
+def test_batch_autotune_keeps_the_solve_bit_identical():
+    """The batch autotuner only changes which launch form smooths each
+    (level, box side); the solve after tuning equals the untuned one exactly,
+    and field b (its scratch while tuning) is restored."""
+    sides = [64, 128, 96, 64, 32]
+    print(f"[gpu] batch autotune {sides}", flush=True)
+    A = grmg.Batch(sides, **PRM)
+    T = grmg.Batch(sides, **PRM)
+    srcs = [synth._matter_sources(n, 700 + i, 0.3) for i, n in enumerate(sides)]
+    for B in (A, T):
+        for i, src in enumerate(srcs):
+            for name, v in zip(("s0", "sx", "sy", "sz", "sm"), src):
+                B.set_field(i, name, v)
+    b_before = [T.get_field(i, "b").clone() for i in range(len(sides))]
+    rep = T.autotune()
+    lines = [ln for ln in rep.splitlines() if ln.startswith("depth=")]
+    assert lines and all("form=" in ln and "us=" in ln for ln in lines), rep
+    for i in range(len(sides)):
+        assert torch.equal(T.get_field(i, "b"), b_before[i])
+    ra = A.solve(rtol=1e-10)
+    rt = T.solve(rtol=1e-10)
+    assert ra["status"] == rt["status"] == grmg.OK
+    assert ra["cycles"] == rt["cycles"]
+    for i in range(len(sides)):
+        for f in range(10):
+            assert torch.equal(A.get_field(i, f), T.get_field(i, f)), (i, f)
