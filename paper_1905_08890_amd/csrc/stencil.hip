@@ -540,11 +540,13 @@ __global__ void __launch_bounds__(CTPB) k_coarse_vcycle(CoarseLevelsT<T> C, int 
 // The same cycle with every level held in LDS (levels up to 16^3 fit): the
 // first level's iterate, source and all levels' coefficients are copied in,
 // the first level's iterate is copied back; barriers then cost LDS latency
-// instead of L2 round trips.
+// instead of L2 round trips.  TG is the type of the arrays in global memory,
+// TC the type the cycle computes in (FP64 also for the FP32 correction
+// cycles: their coarsest levels and mean constraint are solved in FP64).
 constexpr size_t kCoarseLdsBytes = 150 * 1024;
 
-template <int KIND, typename T>
-__host__ __device__ size_t coarse_lds_layout(const CoarseLevelsT<T> &G, CoarseLevelsT<T> *S, T *base)
+template <int KIND, typename TG, typename T>
+__host__ __device__ size_t coarse_lds_layout(const CoarseLevelsT<TG> &G, CoarseLevelsT<T> *S, T *base)
 {
     constexpr bool LIN = KIND >= K_LIN_POISSON;
     constexpr int NC = kNumCoef<KIND>();
@@ -577,32 +579,32 @@ __host__ __device__ size_t coarse_lds_layout(const CoarseLevelsT<T> &G, CoarseLe
     return off * sizeof(T);
 }
 
-template <int KIND, typename T>
-__global__ void __launch_bounds__(CTPB) k_coarse_vcycle_lds(CoarseLevelsT<T> G, int nu1, int nu2, OpConst oc,
+template <int KIND, typename TG, typename T>
+__global__ void __launch_bounds__(CTPB) k_coarse_vcycle_lds(CoarseLevelsT<TG> G, int nu1, int nu2, OpConst oc,
                                                             const double *__restrict__ fbar0,
                                                             const double *__restrict__ fshift0)
 {
     constexpr int NC = kNumCoef<KIND>();
     __shared__ T lds[kCoarseLdsBytes / sizeof(T)];
     __shared__ CoarseLevelsT<T> S; // level table, read by every thread (kept out of private memory)
-    if (threadIdx.x == 0) coarse_lds_layout<KIND, T>(G, &S, lds);
+    if (threadIdx.x == 0) coarse_lds_layout<KIND, TG, T>(G, &S, lds);
     __syncthreads();
     const long N0 = (long)G.n[0] * G.n[0] * G.n[0];
     for (long q = threadIdx.x; q < N0; q += CTPB) {
-        S.phi[0][q] = G.phi[0][q];
-        S.f[0][q] = G.f[0][q];
+        S.phi[0][q] = T(G.phi[0][q]);
+        S.f[0][q] = T(G.f[0][q]);
     }
     for (int i = 0; i < G.nl; ++i) {
         const long N = (long)G.n[i] * G.n[i] * G.n[i];
         for (long q = threadIdx.x; q < N; q += CTPB) {
-            if (NC >= 1) S.c1[i][q] = G.c1[i][q];
-            if (NC >= 2) S.c2[i][q] = G.c2[i][q];
+            if (NC >= 1) S.c1[i][q] = T(G.c1[i][q]);
+            if (NC >= 2) S.c2[i][q] = T(G.c2[i][q]);
         }
     }
     __syncthreads();
     coarse_vcycle_body<KIND, T>(S, nu1, nu2, oc, T(*fbar0), T(*fshift0));
     __syncthreads();
-    for (long q = threadIdx.x; q < N0; q += CTPB) G.phi[0][q] = S.phi[0][q];
+    for (long q = threadIdx.x; q < N0; q += CTPB) G.phi[0][q] = TG(S.phi[0][q]);
 }
 
 // ------------------------------------------------ mixed-precision outer steps
@@ -796,6 +798,18 @@ inline unsigned blocks_for(long count) { return (unsigned)((count + TPB - 1) / T
         case K_LIN_POISSON: KERNEL<K_LIN_POISSON, T><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); break;      \
         case K_LIN_HAM: KERNEL<K_LIN_HAM, T><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); break;              \
         default: KERNEL<K_LIN_CMC, T><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); break;                     \
+        }                                                                                             \
+    } while (0)
+
+#define GR_DISPATCH_K2T(kind, TG, T, KERNEL, GRID, BLOCK, ...)                                          \
+    do {                                                                                              \
+        switch (kind) {                                                                               \
+        case GR_KIND_POISSON: KERNEL<GR_KIND_POISSON, TG, T><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); break; \
+        case GR_KIND_HAMILTONIAN: KERNEL<GR_KIND_HAMILTONIAN, TG, T><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); break; \
+        case GR_KIND_CMC: KERNEL<GR_KIND_CMC, TG, T><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); break;      \
+        case K_LIN_POISSON: KERNEL<K_LIN_POISSON, TG, T><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); break;  \
+        case K_LIN_HAM: KERNEL<K_LIN_HAM, TG, T><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); break;          \
+        default: KERNEL<K_LIN_CMC, TG, T><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); break;                 \
         }                                                                                             \
     } while (0)
 
@@ -1022,8 +1036,8 @@ void launch_restrict_f32(hipStream_t s, const float *fine, int n, float *coarse)
     k_restrict<float><<<G.grid, G.block, 0, s>>>(fine, n, coarse);
 }
 
-template <typename T>
-static bool coarse_lds_fits(int kind, const CoarseLevelsT<T> &C)
+template <typename TG, typename T>
+static bool coarse_lds_fits(int kind, const CoarseLevelsT<TG> &C)
 {
     static const bool on = [] {
         const char *e = std::getenv("GRMG_COARSE_LDS");
@@ -1032,12 +1046,12 @@ static bool coarse_lds_fits(int kind, const CoarseLevelsT<T> &C)
     if (!on) return false;
     size_t b = 0;
     switch (kind) {
-    case GR_KIND_POISSON: b = coarse_lds_layout<GR_KIND_POISSON, T>(C, nullptr, nullptr); break;
-    case GR_KIND_HAMILTONIAN: b = coarse_lds_layout<GR_KIND_HAMILTONIAN, T>(C, nullptr, nullptr); break;
-    case GR_KIND_CMC: b = coarse_lds_layout<GR_KIND_CMC, T>(C, nullptr, nullptr); break;
-    case K_LIN_POISSON: b = coarse_lds_layout<K_LIN_POISSON, T>(C, nullptr, nullptr); break;
-    case K_LIN_HAM: b = coarse_lds_layout<K_LIN_HAM, T>(C, nullptr, nullptr); break;
-    default: b = coarse_lds_layout<K_LIN_CMC, T>(C, nullptr, nullptr); break;
+    case GR_KIND_POISSON: b = coarse_lds_layout<GR_KIND_POISSON, TG, T>(C, nullptr, (T *)nullptr); break;
+    case GR_KIND_HAMILTONIAN: b = coarse_lds_layout<GR_KIND_HAMILTONIAN, TG, T>(C, nullptr, (T *)nullptr); break;
+    case GR_KIND_CMC: b = coarse_lds_layout<GR_KIND_CMC, TG, T>(C, nullptr, (T *)nullptr); break;
+    case K_LIN_POISSON: b = coarse_lds_layout<K_LIN_POISSON, TG, T>(C, nullptr, (T *)nullptr); break;
+    case K_LIN_HAM: b = coarse_lds_layout<K_LIN_HAM, TG, T>(C, nullptr, (T *)nullptr); break;
+    default: b = coarse_lds_layout<K_LIN_CMC, TG, T>(C, nullptr, (T *)nullptr); break;
     }
     return b <= kCoarseLdsBytes;
 }
@@ -1045,8 +1059,8 @@ static bool coarse_lds_fits(int kind, const CoarseLevelsT<T> &C)
 void launch_coarse_vcycle(int kind, hipStream_t s, const CoarseLevelsT<double> &C, int nu1, int nu2, OpConst oc,
                           const double *fbar0, const double *fshift0)
 {
-    if (coarse_lds_fits<double>(kind, C)) {
-        GR_DISPATCH_KT(kind, double, k_coarse_vcycle_lds, 1, CTPB, C, nu1, nu2, oc, fbar0, fshift0);
+    if (coarse_lds_fits<double, double>(kind, C)) {
+        GR_DISPATCH_K2T(kind, double, double, k_coarse_vcycle_lds, 1, CTPB, C, nu1, nu2, oc, fbar0, fshift0);
         return;
     }
     GR_DISPATCH_KT(kind, double, k_coarse_vcycle, 1, CTPB, C, nu1, nu2, oc, fbar0, fshift0);
@@ -1055,8 +1069,10 @@ void launch_coarse_vcycle(int kind, hipStream_t s, const CoarseLevelsT<double> &
 void launch_coarse_vcycle_f32(int kind, hipStream_t s, const CoarseLevelsT<float> &C, int nu1, int nu2, OpConst oc,
                               const double *zero)
 {
-    if (coarse_lds_fits<float>(kind, C)) {
-        GR_DISPATCH_KT(kind, float, k_coarse_vcycle_lds, 1, CTPB, C, nu1, nu2, oc, zero, zero);
+    // FP32 arrays, the cycle in FP64 in LDS (the global-memory fallback, for
+    // thresholds whose levels do not fit, computes in FP32)
+    if (coarse_lds_fits<float, double>(kind, C)) {
+        GR_DISPATCH_K2T(kind, float, double, k_coarse_vcycle_lds, 1, CTPB, C, nu1, nu2, oc, zero, zero);
         return;
     }
     GR_DISPATCH_KT(kind, float, k_coarse_vcycle, 1, CTPB, C, nu1, nu2, oc, zero, zero);
