@@ -334,9 +334,10 @@ void timed_sweep(gr_grid g, int l, int kind, F launch)
     g->sweep_ev.push_back({kind, a, b});
 }
 
-// nsweeps red-black sweeps of level l on L.phi.  The fused kernel works out
-// of place, alternating between L.phi and L.tmp; an odd count ends with a copy
-// back so that the iterate always ends in L.phi.
+// nsweeps red-black sweeps of level l on L.phi.  The fused kernels work out
+// of place, alternating between L.phi and L.tmp; after an odd number of
+// launches the two pointers are exchanged, so the iterate is L.phi again (the
+// V-cycle of the level puts them back, copying only if its launches were odd).
 int smooth(gr_grid g, const EqCtx &E, int l, int nsweeps)
 {
     Level &L = g->lev[l];
@@ -349,21 +350,38 @@ int smooth(gr_grid g, const EqCtx &E, int l, int nsweeps)
         return GR_OK;
     }
     double *a = L.phi, *b = L.tmp;
+    const FusedCfg &cfg = fused_cfg(g, l, E.kind);
     for (int it = 0; it < nsweeps; ++it) {
         timed_sweep(g, l, E.kind, [&] {
-            launch_rb_fused(E.kind, s, a, b, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l),
-                            fused_cfg(g, l, E.kind));
+            launch_rb_fused(E.kind, s, a, b, L.f, L.coef, L.n, L.h, E.oc, fbar_ptr(g, l), fshift_ptr(g, l), cfg);
         });
         double *t = a;
         a = b;
         b = t;
     }
-    if (a != L.phi) launch_copy(s, L.phi, a, L.N);
+    if (a != L.phi) std::swap(L.phi, L.tmp);
     LAUNCHCHK();
     return GR_OK;
 }
 
+int vcycle_body(gr_grid g, const EqCtx &E, int l);
+
+// Every V-cycle leaves the iterate of its level in the array it found it in.
 int vcycle(gr_grid g, const EqCtx &E, int l)
+{
+    Level &L = g->lev[l];
+    double *orig = L.phi;
+    const int st = vcycle_body(g, E, l);
+    if (L.phi != orig) {
+        launch_copy(g->stream, orig, L.phi, L.N);
+        L.tmp = L.phi;
+        L.phi = orig;
+        LAUNCHCHK();
+    }
+    return st;
+}
+
+int vcycle_body(gr_grid g, const EqCtx &E, int l)
 {
     Level &L = g->lev[l];
     hipStream_t s = g->stream;
@@ -504,16 +522,15 @@ int smooth32(gr_grid g, int lkind, int l, int nsweeps, OpConst oc, bool e_is_zer
     }
     if (e_is_zero && nsweeps == 0) launch_fill_f32(s, V.e, L.N);
     float *a = V.e, *b = V.tmp;
+    const FusedCfg &cfg = fused_cfg(g, l, lkind);
     for (int it = 0; it < nsweeps; ++it) {
-        timed_sweep(g, l, lkind, [&] {
-            launch_rb_fused_f32(lkind, s, (it == 0 && e_is_zero) ? nullptr : a, b, V.b, V.c, V.a, L.n, L.h, oc, zero,
-                                fused_cfg(g, l, lkind));
-        });
+        const float *in = (it == 0 && e_is_zero) ? nullptr : a;
+        timed_sweep(g, l, lkind, [&] { launch_rb_fused_f32(lkind, s, in, b, V.b, V.c, V.a, L.n, L.h, oc, zero, cfg); });
         float *t = a;
         a = b;
         b = t;
     }
-    if (a != V.e) launch_copy_f32(s, V.e, a, L.N);
+    if (a != V.e) std::swap(V.e, V.tmp); // put back by the level's V-cycle
     LAUNCHCHK();
     return GR_OK;
 }
@@ -522,7 +539,25 @@ int smooth32(gr_grid g, int lkind, int l, int nsweeps, OpConst oc, bool e_is_zer
 // level; on level l it may be unwritten when e_unset): sweeps, b^H = R(b - J e),
 // recursion, e += P e^H, sweeps; the coarsest level (always inside the
 // single-workgroup kernel) does 32 sweeps and removes the mean of its correction.
+int vcycle32_body(gr_grid g, int lkind, int l, int nu1, int nu2, OpConst oc, bool e_unset);
+
+// Every correction V-cycle leaves the correction of its level in the array it
+// found it in.
 int vcycle32(gr_grid g, int lkind, int l, int nu1, int nu2, OpConst oc, bool e_unset)
+{
+    Level32 &V = g->lev32[l];
+    float *orig = V.e;
+    const int st = vcycle32_body(g, lkind, l, nu1, nu2, oc, e_unset);
+    if (V.e != orig) {
+        launch_copy_f32(g->stream, orig, V.e, g->lev[l].N);
+        V.tmp = V.e;
+        V.e = orig;
+        LAUNCHCHK();
+    }
+    return st;
+}
+
+int vcycle32_body(gr_grid g, int lkind, int l, int nu1, int nu2, OpConst oc, bool e_unset)
 {
     Level &L = g->lev[l];
     Level32 &V = g->lev32[l];
@@ -1337,6 +1372,7 @@ int gr_autotune(gr_grid g, char *report, size_t report_bytes)
                         split = true;
                     }
                 }
+                if (st != GR_OK) break;
                 std::lock_guard<std::mutex> lk(g_tune_mu);
                 g_tune_cache.push_back({L.n, kind, best, best_us, split});
             }
@@ -1411,9 +1447,18 @@ int gr_debug_sweep(gr_grid g, int kind, int field, double Fbar, double fshift, i
     hipStream_t s = g->stream;
     launch_set_scalar(s, g->scal + S_FBAR, Fbar);
     launch_set_scalar(s, g->scal + S_FSHIFT, fshift);
-    g->lev[0].phi = g->field[field];
+    Level &L = g->lev[0];
+    L.phi = g->field[field];
+    double *tmp = L.tmp;
     EqCtx E{kind, g->oc(), 0, 0};
-    return smooth(g, E, 0, nsweeps);
+    const int st = smooth(g, E, 0, nsweeps);
+    if (L.phi != g->field[field]) { // odd number of launches: the result is in the scratch array
+        launch_copy(s, g->field[field], L.phi, L.N);
+        L.phi = g->field[field];
+    }
+    L.tmp = tmp;
+    LAUNCHCHK();
+    return st;
 }
 
 int gr_debug_residual(gr_grid g, int kind, int field, double Fbar, double fshift, double *d_out)
