@@ -248,7 +248,11 @@ int gr_debug_residual(gr_grid g, int kind, int field, double Fbar, double fshift
  * together: every phase of the cycle runs as one launch over all boxes, each
  * box stops on its own residual test (the single-grid criterion), and each
  * cycle's launch sequence is captured once per field in a hipGraph (only on a
- * non-null stream; GRMG_BATCH_GRAPH=0 disables it) and replayed.  FP64 only.
+ * non-null stream; GRMG_BATCH_GRAPH=0 disables it) and replayed.  Precision
+ * GR_FP64, or GR_MIXED: the periodic boxes then run the single grid's
+ * iterative refinement (FP64 residual and update, FP32 correction cycles whose
+ * levels from 8^3 down run in FP64) without its FP64 fallback; patches stay
+ * FP64.
  * Same memory rules as a single grid: the caller allocates
  * gr_batch_workspace_bytes() of device memory. */
 typedef struct gr_batch_s *gr_batch;

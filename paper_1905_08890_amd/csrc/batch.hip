@@ -29,6 +29,7 @@
 #include "sources_ops.h"
 #include "patch_ops.h"
 #include "fused_sweep.h"
+#include "coarse_cycle.h"
 #include "march.h"
 
 using namespace grmg;
@@ -45,10 +46,14 @@ struct BoxLev {
     int n;
     double h;
     double *phi, *phi0, *f, *coef, *tmp; // phi of level 0 is the current field array
+    // mixed precision (periodic boxes): FP32 correction e, its source b, the
+    // frozen linearisation a (chi) and c, scratch
+    float *e, *b32, *a32, *c32, *t32;
 };
 struct BoxDev {
     int nlev;
     int centry; // first level handled by the single-workgroup coarse cycle
+    int centry32; // first level of the FP32 correction cycle handled by the single-workgroup kernel
     int patch;  // 1: Dirichlet patch (padded iterate arrays), 0: periodic box
     int parent; // patch: index of the periodic box its boundary values come from
     double origin[3]; // patch: lower corner in the parent's frame (box units)
@@ -61,7 +66,7 @@ struct BoxDev {
 };
 
 // per-box scalars (device)
-enum BoxScal { B_FBAR, B_FSHIFT, B_FMEAN, B_MEAN, B_RN, B_FN, B_REL, B_TMP, B_NSCAL };
+enum BoxScal { B_FBAR, B_FSHIFT, B_FMEAN, B_MEAN, B_RN, B_FN, B_REL, B_TMP, B_ZERO, B_NSCAL }; // B_ZERO stays 0
 
 struct BatchDev {
     const BoxDev *box;
@@ -265,7 +270,7 @@ __device__ __forceinline__ void block_store(double (&v)[NC], double *__restrict_
     }
 }
 
-// what: 0 sum(phi), 1 sum F (Hamiltonian), 2 sum(m2 phi), 3 sum(f), 4..6 sum(s_x..s_z)
+// what: 0 sum(phi), 1 sum F (Hamiltonian), 2 sum(m2 phi), 3 sum(f), 4..6 sum(s_x..s_z), 7 sum(e) (FP32 correction)
 __global__ void __launch_bounds__(TPB) kb_sum(BatchDev D, const int *__restrict__ tab, int fid, int what, OpConst oc,
                                               int active_only)
 {
@@ -285,6 +290,7 @@ __global__ void __launch_bounds__(TPB) kb_sum(BatchDev D, const int *__restrict_
             v[0] = (L.f[t] - oc.A * (chi6 - 1.0)) / chi + 0.25 * L.coef[t] * chim7;
         } else if (what == 2) v[0] = L.coef[t] * ph;
         else if (what == 3) v[0] = L.f[t];
+        else if (what == 7) v[0] = (double)X.lev[0].e[t];
         else v[0] = X.src[what - 3][t];
     }
     block_store<1>(v, D.partials, total);
@@ -630,6 +636,203 @@ __global__ void __launch_bounds__(CTPB) kb_coarse_vcycle(BatchDev D, int fid, in
         __syncthreads();
         for (int it = 0; it < nu2; ++it) cvb_sweep<KIND>(phi, V.f, V.coef, n, inv_h2, oc, Fb, fs);
     }
+}
+
+// ------------------------------------------- mixed precision (periodic boxes)
+//
+// Iterative refinement as on a single grid: the FP64 residual of the
+// regularised fine equation (with the cycle's frozen means) becomes the FP32
+// source b = -r of the linearised correction equation J e = b, which one FP32
+// V-cycle solves approximately (coarse levels from 8^3 down in FP64, in LDS,
+// one workgroup per box); then phi += e - <e> in FP64.
+
+// FP64 residual -> b (FP32), the frozen Hamiltonian linearisation a = chi and
+// c = dL/dPsi + 6 chi/h^2, and block partials of r^2 and (f - fshift)^2
+template <int KIND>
+__global__ void __launch_bounds__(TPB) kb_ir_residual(BatchDev D, const int *__restrict__ tab, int fid, OpConst oc)
+{
+    BOX_PROLOGUE(tab)
+    const int total = tab[D.nbox];
+    const BoxLev &L = X.lev[0];
+    const int n = L.n;
+    double v[2] = {0.0, 0.0};
+    if (D.active[b] && t < n * n * n) {
+        int x, y, z;
+        decode3(t, n, n, x, y, z);
+        const double Fb = D.scal[b * B_NSCAL + B_FBAR], fs = D.scal[b * B_NSCAL + B_FSHIFT];
+        const double inv_h2 = 1.0 / (L.h * L.h);
+        const double *phi = X.field[fid];
+        const double ph = phi[t];
+        double J;
+        const double Lv = op_point<KIND, double>(ph, nb_sum(phi, x, y, z, n), inv_h2, load_c1<KIND>(L.coef, t), 0.0,
+                                                 oc, Fb, J);
+        const double fe = L.f[t] - fs;
+        const double e = Lv - fe;
+        v[0] = e * e;
+        v[1] = fe * fe;
+        L.b32[t] = (float)(-e);
+        if constexpr (KIND == GR_KIND_HAMILTONIAN) {
+            const double chi = 1.0 - oc.kappa * ph;
+            L.a32[t] = (float)chi;
+            L.c32[t] = (float)(J + 6.0 * chi * inv_h2);
+        }
+    }
+    block_store<2>(v, D.partials, total);
+}
+
+// c = -m2 in FP32 on the finest level (linearised CMC coefficient)
+__global__ void __launch_bounds__(TPB) kb_neg_coef32(BatchDev D, const int *__restrict__ tab)
+{
+    BOX_PROLOGUE(tab)
+    const BoxLev &L = X.lev[0];
+    if (t < L.n * L.n * L.n) L.c32[t] = (float)(-L.coef[t]);
+}
+
+// FP32 restriction of the linearisation, level d -> d+1 (which: 0 c, 1 a)
+__global__ void __launch_bounds__(TPB) kb_restrict32(BatchDev D, const int *__restrict__ tab, int d, int which)
+{
+    BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
+    const BoxLev &V = X.lev[d], &C = X.lev[d + 1];
+    const int m = C.n, n = V.n;
+    if (t >= m * m * m) return;
+    int I, J, K;
+    decode3(t, m, m, I, J, K);
+    const float *src = which ? V.a32 : V.c32;
+    float s = 0.f;
+    for (int c = 0; c < 8; ++c) s += src[lin(2 * I + (c & 1), 2 * J + ((c >> 1) & 1), 2 * K + (c >> 2), n)];
+    (which ? C.a32 : C.c32)[t] = s / 8.f;
+}
+
+__global__ void __launch_bounds__(TPB) kb32_fill(BatchDev D, const int *__restrict__ tab, int d)
+{
+    BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
+    const BoxLev &L = X.lev[d];
+    if (t < L.n * L.n * L.n) L.e[t] = 0.f;
+}
+
+// one colour of a red-black sweep of the correction equation on level d
+template <int LKIND>
+__global__ void __launch_bounds__(TPB) kb32_colour(BatchDev D, const int *__restrict__ tab, int d, int colour,
+                                                   OpConst oc)
+{
+    BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
+    const BoxLev &L = X.lev[d];
+    const int n = L.n, half = n >> 1;
+    if (t >= n * n * half) return;
+    int x2, y, z;
+    decode3(t, half, n, x2, y, z);
+    const int i = 2 * x2 + ((y + z + colour) & 1);
+    const long p = lin(i, y, z, n);
+    const float ph = L.e[p];
+    float J;
+    const float Lv = op_point<LKIND, float>(ph, nb_sum(L.e, i, y, z, n), (float)(1.0 / (L.h * L.h)),
+                                            load_c1<LKIND>(L.c32, p), load_c2<LKIND>(L.a32, p), oc, 0.f, J);
+    L.e[p] = ph - (Lv - L.b32[p]) / J;
+}
+
+// fused red-black sweeps of the correction equation (rb_fused_tile in FP32)
+// for the boxes whose level d takes fused tiles: even sweeps e -> t32, odd
+// t32 -> e
+template <int LKIND, int TX, int TY>
+__global__ void __launch_bounds__((TX / 2) * TY) kb32_fused(BatchDev D, const int *__restrict__ tab, int d, int sweep,
+                                                            OpConst oc)
+{
+    const int b = find_box(tab, D.nbox, blockIdx.x);
+    if (!D.active[b]) return;
+    const BoxDev &X = D.box[b];
+    const BoxLev &L = X.lev[d];
+    const int n = L.n, lb = blockIdx.x - tab[b];
+    const int nz = n / kFZ, tiles_y = n / TY;
+    const int zchunk = lb % nz, t2 = lb / nz;
+    const float *in = (sweep & 1) ? L.t32 : L.e;
+    float *out = (sweep & 1) ? L.e : L.t32;
+    rb_fused_tile<LKIND, float, TX, TY, 2>(in, out, L.b32, L.c32, L.a32, n, kFZ, (float)(1.0 / (L.h * L.h)), oc, 0.f,
+                                           0.f, (t2 / tiles_y) * TX, (t2 % tiles_y) * TY, zchunk * kFZ);
+}
+
+// coarse source b^H = R(b - J e) and e^H = 0: one thread per cell of level d+1
+template <int LKIND>
+__global__ void __launch_bounds__(TPB) kb32_lin_rr(BatchDev D, const int *__restrict__ tab, int d, OpConst oc)
+{
+    BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
+    const BoxLev &V = X.lev[d], &C = X.lev[d + 1];
+    const int n = V.n, m = C.n;
+    if (t >= m * m * m) return;
+    int I, J, K;
+    decode3(t, m, m, I, J, K);
+    const float inv_h2 = (float)(1.0 / (V.h * V.h));
+    float sr = 0.f;
+    for (int c = 0; c < 8; ++c) {
+        const int i = 2 * I + (c & 1), j = 2 * J + ((c >> 1) & 1), k = 2 * K + (c >> 2);
+        const long p = lin(i, j, k, n);
+        float Jd;
+        const float Lv = op_point<LKIND, float>(V.e[p], nb_sum(V.e, i, j, k, n), inv_h2, load_c1<LKIND>(V.c32, p),
+                                                load_c2<LKIND>(V.a32, p), oc, 0.f, Jd);
+        sr += V.b32[p] - Lv;
+    }
+    C.b32[t] = sr / 8.f;
+    C.e[t] = 0.f;
+}
+
+// e^h += P e^H (cell-centred trilinear, periodic): one thread per fine cell
+__global__ void __launch_bounds__(TPB) kb32_prolong(BatchDev D, const int *__restrict__ tab, int d)
+{
+    BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
+    const BoxLev &V = X.lev[d], &C = X.lev[d + 1];
+    const int n = V.n, m = C.n;
+    if (t >= n * n * n) return;
+    int i, j, k;
+    decode3(t, n, n, i, j, k);
+    const int I = i >> 1, J = j >> 1, K = k >> 1;
+    const int Is[2] = {I, wrapi(I + ((i & 1) ? 1 : -1), m)};
+    const int Js[2] = {J, wrapi(J + ((j & 1) ? 1 : -1), m)};
+    const int Ks[2] = {K, wrapi(K + ((k & 1) ? 1 : -1), m)};
+    float v = 0.f;
+    for (int c = 0; c < 8; ++c) {
+        const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+        const float w = (ox ? 0.25f : 0.75f) * (oy ? 0.25f : 0.75f) * (oz ? 0.25f : 0.75f);
+        v += w * C.e[lin(Is[ox], Js[oy], Ks[oz], m)];
+    }
+    V.e[t] += v;
+}
+
+// the correction cycle from the box's FP32 entry level down, one workgroup per
+// box, computed in FP64 in LDS
+template <int LKIND>
+__global__ void __launch_bounds__(kCoarseThreads) kb32_coarse(BatchDev D, int nu1, int nu2, OpConst oc)
+{
+    const int b = blockIdx.x;
+    if (!D.active[b]) return;
+    const BoxDev &X = D.box[b];
+    CoarseLevelsT<float> G;
+    G.nl = X.nlev - X.centry32;
+    for (int i = 0; i < G.nl; ++i) {
+        const BoxLev &V = X.lev[X.centry32 + i];
+        G.n[i] = V.n;
+        G.inv_h2[i] = 1.0 / (V.h * V.h);
+        G.phi[i] = V.e;
+        G.phi0[i] = nullptr;
+        G.f[i] = V.b32;
+        G.c1[i] = V.c32;
+        G.c2[i] = V.a32;
+        G.tmp[i] = V.t32;
+    }
+    const double *zero = D.scal + b * B_NSCAL + B_ZERO;
+    coarse_cycle_lds<LKIND, float, double>(G, nu1, nu2, oc, zero, zero);
+}
+
+// phi += e - <e> (mean in B_MEAN), FP64
+__global__ void __launch_bounds__(TPB) kb_ir_update(BatchDev D, const int *__restrict__ tab, int fid)
+{
+    BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
+    const BoxLev &L = X.lev[0];
+    if (t < L.n * L.n * L.n) X.field[fid][t] += (double)L.e[t] - D.scal[b * B_NSCAL + B_MEAN];
 }
 
 // ------------------------------------------------- Dirichlet patches
@@ -1035,11 +1238,15 @@ struct gr_batch_s {
     hipStream_t stream = nullptr;
     bool bound = false;
     bool use_graph = true;
-    hipGraphExec_t graph[20]{};     // per field: the captured cycle sequence (10 + field: patches)
-    gr_solve_opts graph_opts[20]{}; // options it was captured with
+    hipGraphExec_t graph[30]{};     // per field: the captured cycle (10 + field: patches, 20 + field: mixed)
+    gr_solve_opts graph_opts[30]{}; // options it was captured with
     // patches: levels handled by grouped launches (depth < pmaxdepth), all levels (< pmaxlev)
     int pmaxdepth = 0, pmaxlev = 0;
     Tab pfine;                                  // interior cells of level 0
+    // mixed precision (periodic boxes): grouped levels of the FP32 correction cycle
+    int maxdepth32 = 0;
+    std::vector<Tab> colour32, cells32, coarse32; // per depth: half cells, cells, cells of the next level
+    std::vector<Tab> colour32nf;                  // per depth: half cells of the boxes not swept fused
     std::vector<Tab> pcell;                     // per level above a patch's entry: half its cells (colour passes)
     std::vector<Tab> pcellf;                    // per level above a patch's entry: its cells (prolongation)
     std::vector<Tab> pcoarse;                   // per depth d: interior cells of level d + 1 (grouped levels)
@@ -1087,6 +1294,14 @@ size_t batch_layout(gr_batch B, char *base)
             BoxLev &L = X.lev[l];
             const long M = (long)L.n * L.n * L.n;
             L.phi = l == 0 ? nullptr : takeD(iter_len(L.n));
+            if (!X.patch) {
+                auto takeF = [&](long count) { return reinterpret_cast<float *>(take(sizeof(float) * count)); };
+                L.e = takeF(M);
+                L.b32 = takeF(M);
+                L.a32 = takeF(M);
+                L.c32 = takeF(M);
+                L.t32 = takeF(M);
+            }
             L.phi0 = takeD(M);
             L.f = takeD(M);
             L.coef = takeD(M);
@@ -1117,7 +1332,8 @@ size_t batch_layout(gr_batch B, char *base)
     }
     for (size_t d = 0; d < B->coefr.size(); ++d) B->coefr[d].dev = takeI(B->nbox + 1);
     B->pfine.dev = takeI(B->nbox + 1);
-    for (auto *v : {&B->pcell, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces})
+    for (auto *v : {&B->pcell, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces, &B->colour32, &B->cells32,
+                    &B->coarse32, &B->colour32nf})
         for (auto &T : *v) T.dev = takeI(B->nbox + 1);
     return off;
 }
@@ -1183,6 +1399,19 @@ void batch_smooth(gr_batch B, int kind, int d, int fid, int nu)
     }
 }
 
+// FP32 correction smoothing at depth d: boxes whose level d is swept fused
+// (forms 1, 2: the FP64 tables fz / fz64) and the rest one launch per colour
+void smooth32_tab(gr_batch B, int d)
+{
+    const auto &H = B->host;
+    make_tab(B->colour32nf[d], B->nbox, [&](int b) {
+        if (H[b].patch || d >= H[b].centry32) return 0L;
+        const bool fused = d < (int)B->form.size() && B->form[d][b] >= 1;
+        const long n = H[b].lev[d].n;
+        return fused ? 0L : n * n * n / 2;
+    });
+}
+
 // smoothing tables of depth d from the boxes' forms
 void smooth_tabs(gr_batch B, int d)
 {
@@ -1194,6 +1423,7 @@ void smooth_tabs(gr_batch B, int d)
     make_tab(B->fz[d], nb, [&](int b) { return F[b] == 1 ? blocks(b, 32, 16) * TPB : 0L; });
     make_tab(B->fz64[d], nb, [&](int b) { return F[b] == 2 ? blocks(b, 64, 16) * TPB : 0L; });
     make_tab(B->colour_nf[d], nb, [&](int b) { long n = H[b].lev[d].n; return F[b] == 0 ? n * n * n / 2 : 0L; });
+    if (d < (int)B->colour32nf.size()) smooth32_tab(B, d);
 }
 
 int batch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
@@ -1305,6 +1535,101 @@ int batch_field(gr_batch B, int kind, int fid, const gr_solve_opts &o)
     BCHK(batch_pin(B, fid, 0));
     BCHK(run_cycles(B, s, B->D.any_active, fid, o, [&] { return batch_cycle(B, kind, fid, o); }));
     if (kind == GR_KIND_POISSON) BCHK(batch_pin(B, fid, 0));
+    return read_rel(B, s, fid, 0, B->nper);
+}
+
+#define LDISPATCH(kind, KERNEL, GRID, BLOCK, ...)                                                      \
+    do {                                                                                              \
+        if ((kind) == GR_KIND_POISSON) KERNEL<K_LIN_POISSON><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__);    \
+        else if ((kind) == GR_KIND_HAMILTONIAN) KERNEL<K_LIN_HAM><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__); \
+        else KERNEL<K_LIN_CMC><<<GRID, BLOCK, 0, s>>>(__VA_ARGS__);                                  \
+    } while (0)
+
+template <int TX, int TY>
+void launch_kb32_fused(hipStream_t s, int kind, const Tab &T, BatchDev D, int d, int it, OpConst oc)
+{
+    constexpr int NT = (TX / 2) * TY;
+    if (kind == GR_KIND_POISSON) kb32_fused<K_LIN_POISSON, TX, TY><<<T.total(), NT, 0, s>>>(D, T.dev, d, it, oc);
+    else if (kind == GR_KIND_HAMILTONIAN) kb32_fused<K_LIN_HAM, TX, TY><<<T.total(), NT, 0, s>>>(D, T.dev, d, it, oc);
+    else kb32_fused<K_LIN_CMC, TX, TY><<<T.total(), NT, 0, s>>>(D, T.dev, d, it, oc);
+}
+
+// nu sweeps of the correction on level d of every box: fused where the box's
+// form says so (an even count ends in e), one launch per colour elsewhere
+void batch_smooth32(gr_batch B, int kind, int d, int nu)
+{
+    hipStream_t s = B->stream;
+    const OpConst oc = opc(B);
+    const bool formed = d < B->maxdepth;
+    const bool fused = formed && nu % 2 == 0 && (B->fz[d].total() > 0 || B->fz64[d].total() > 0);
+    const Tab &TC = fused ? B->colour32nf[d] : B->colour32[d];
+    for (int it = 0; it < nu; ++it) {
+        if (fused && B->fz[d].total()) launch_kb32_fused<32, 16>(s, kind, B->fz[d], B->D, d, it, oc);
+        if (fused && B->fz64[d].total()) launch_kb32_fused<64, 16>(s, kind, B->fz64[d], B->D, d, it, oc);
+        if (TC.total() > 0)
+            for (int colour = 0; colour < 2; ++colour)
+                LDISPATCH(kind, kb32_colour, TC.total(), TPB, B->D, TC.dev, d, colour, oc);
+    }
+}
+
+// one refinement step of every active box: frozen means, FP64 residual and
+// stopping test, FP32 correction V-cycle, FP64 update
+int batch_cycle_mixed(gr_batch B, int kind, int fid, const gr_solve_opts &o)
+{
+    hipStream_t s = B->stream;
+    const OpConst oc = opc(B);
+    const int FT = B->fine.total();
+    if (kind == GR_KIND_HAMILTONIAN) {
+        kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid, 1, oc, 1);
+        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FBAR, -1, 1, 0);
+    } else if (kind == GR_KIND_CMC) {
+        kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid, 2, oc, 1);
+        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FSHIFT, B_FMEAN, 1, 0);
+    }
+    KDISPATCH(kind, kb_ir_residual, FT, TPB, B->D, B->fine.dev, fid, oc);
+    kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 2, B_RN, -1, 1, 0);
+    kb_control<<<1, 1024, 0, s>>>(B->D, fid, o.rtol, o.max_cycles, 0, B->nper);
+    if (kind == GR_KIND_HAMILTONIAN) // the linearisation frozen at this iterate, on every level
+        for (size_t d = 0; d < B->coefr.size(); ++d)
+            if (B->coefr[d].total())
+                for (int which = 0; which < 2; ++which)
+                    kb_restrict32<<<B->coefr[d].total(), TPB, 0, s>>>(B->D, B->coefr[d].dev, (int)d, which);
+    kb32_fill<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, 0); // the correction starts from e = 0
+    for (int d = 0; d < B->maxdepth32; ++d) {
+        if (B->colour32[d].total() == 0) continue;
+        batch_smooth32(B, kind, d, o.nu1);
+        LDISPATCH(kind, kb32_lin_rr, B->coarse32[d].total(), TPB, B->D, B->coarse32[d].dev, d, oc);
+    }
+    LDISPATCH(kind, kb32_coarse, B->nper, kCoarseThreads, B->D, o.nu1, o.nu2, oc);
+    for (int d = B->maxdepth32 - 1; d >= 0; --d) {
+        const Tab &TC = B->colour32[d];
+        if (TC.total() == 0) continue;
+        kb32_prolong<<<B->cells32[d].total(), TPB, 0, s>>>(B->D, B->cells32[d].dev, d);
+        batch_smooth32(B, kind, d, o.nu2);
+    }
+    kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid, 7, oc, 1);
+    kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_MEAN, -1, 1, 0);
+    kb_ir_update<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid);
+    BLAUNCH();
+    return GR_OK;
+}
+
+int batch_field_mixed(gr_batch B, int kind, int fid, const gr_solve_opts &o)
+{
+    hipStream_t s = B->stream;
+    const OpConst oc = opc(B);
+    kb_begin_field<<<1, 1024, 0, s>>>(B->D, fid, 0, B->nper, fid);
+    if (kind == GR_KIND_CMC) { // <f>, and c = -m2 in FP32 on every level (fixed for the solve)
+        kb_sum<<<B->fine.total(), TPB, 0, s>>>(B->D, B->fine.dev, fid, 3, oc, 0);
+        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FMEAN, -1, 0, 0);
+        kb_neg_coef32<<<B->fine.total(), TPB, 0, s>>>(B->D, B->fine.dev);
+        for (size_t d = 0; d < B->coefr.size(); ++d)
+            if (B->coefr[d].total())
+                kb_restrict32<<<B->coefr[d].total(), TPB, 0, s>>>(B->D, B->coefr[d].dev, (int)d, 0);
+    }
+    BLAUNCH();
+    BCHK(batch_pin(B, fid, 0));
+    BCHK(run_cycles(B, s, B->D.any_active, 20 + fid, o, [&] { return batch_cycle_mixed(B, kind, fid, o); }));
     return read_rel(B, s, fid, 0, B->nper);
 }
 
@@ -1429,6 +1754,13 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
             X.lev[l].h = descs[b].h * (double)(1 << l);
             if ((n >> l) <= B->coarse_n && X.centry == X.nlev - 1 && l < X.centry) X.centry = l;
         }
+        X.centry32 = X.nlev - 1; // FP32 correction cycle: single workgroup from 8^3 down
+        for (int l = 0; l < X.nlev - 1; ++l)
+            if (X.lev[l].n <= 8) {
+                X.centry32 = l;
+                break;
+            }
+        B->maxdepth32 = std::max(B->maxdepth32, X.centry32);
         maxd = std::max(maxd, X.centry);
         maxc = std::max(maxc, X.nlev - 1);
         B->total_points += (long)n * n * n;
@@ -1501,6 +1833,18 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
             long m = !H[b].patch && d + 1 < H[b].nlev ? H[b].lev[d + 1].n : 0;
             return m * m * m;
         });
+    // FP32 correction cycle tables (periodic boxes, levels above their FP32 entry)
+    B->colour32.resize(B->maxdepth32);
+    B->cells32.resize(B->maxdepth32);
+    B->coarse32.resize(B->maxdepth32);
+    B->colour32nf.resize(B->maxdepth32);
+    for (int d = 0; d < B->maxdepth32; ++d) {
+        auto on = [&](int b) { return !H[b].patch && d < H[b].centry32; };
+        make_tab(B->colour32[d], nb, [&](int b) { long n = on(b) ? H[b].lev[d].n : 0; return n * n * n / 2; });
+        make_tab(B->cells32[d], nb, [&](int b) { long n = on(b) ? H[b].lev[d].n : 0; return n * n * n; });
+        make_tab(B->coarse32[d], nb, [&](int b) { long m = on(b) ? H[b].lev[d + 1].n : 0; return m * m * m; });
+        smooth32_tab(B, d); // after the forms (built above)
+    }
     // patch tables: no blocks for periodic boxes
     auto cells = [&](int b, int l) { long n = H[b].patch && l < H[b].nlev ? H[b].lev[l].n : 0; return n * n * n; };
     make_tab(B->pfine, nb, [&](int b) { return cells(b, 0); });
@@ -1587,7 +1931,8 @@ int gr_batch_bind(gr_batch B, void *d_ws, size_t bytes, void *stream)
     }
     for (auto &T : B->coefr) BHIP(up(T));
     BHIP(up(B->pfine));
-    for (auto *v : {&B->pcell, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces})
+    for (auto *v : {&B->pcell, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces, &B->colour32, &B->cells32,
+                    &B->coarse32, &B->colour32nf})
         for (auto &T : *v) BHIP(up(T));
     BHIP(hipStreamSynchronize(s)); // host tables must outlive the copies
     B->D.nbox = B->nbox;
@@ -1684,7 +2029,7 @@ int gr_batch_autotune(gr_batch B, char *report, size_t report_bytes)
     BHIP(hipEventCreate(&e1));
     auto upload = [&](int d) {
         hipError_t e = hipSuccess;
-        for (Tab *T : {&B->fz[d], &B->fz64[d], &B->colour_nf[d]})
+        for (Tab *T : {&B->fz[d], &B->fz64[d], &B->colour_nf[d], &B->colour32nf[d]})
             if (e == hipSuccess)
                 e = hipMemcpyAsync(T->dev, T->start.data(), sizeof(int) * T->start.size(), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s); // the host tables change next
@@ -1783,7 +2128,7 @@ int gr_batch_solve(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_
     if (!B->bound) return bfail(GR_ESTATE, "batch not bound");
     if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 64 || o->nu2 > 64 || o->max_cycles < 0 || o->max_cycles > 100000)
         return bfail(GR_EINVAL, "bad cycle options");
-    if (o->precision != GR_FP64) return bfail(GR_EINVAL, "the batched solve runs in FP64 only");
+    if (o->precision != GR_FP64 && o->precision != GR_MIXED) return bfail(GR_EINVAL, "bad precision");
     if (o->guess != GR_GUESS_ZERO && o->guess != GR_GUESS_CURRENT) return bfail(GR_EINVAL, "bad guess mode");
     hipStream_t s = B->stream;
     const gr_params &P = B->prm;
@@ -1900,7 +2245,8 @@ int gr_batch_solve(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_
         S.pre_box();
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) bstatus = bfail(GR_EDEVICE, "kernel launch: %s", hipGetErrorString(e));
-        if (bstatus == GR_OK && (mask & (1u << S.fid))) bstatus = batch_field(B, S.kind, S.fid, *o);
+        if (bstatus == GR_OK && (mask & (1u << S.fid)))
+            bstatus = o->precision == GR_MIXED ? batch_field_mixed(B, S.kind, S.fid, *o) : batch_field(B, S.kind, S.fid, *o);
         if (bstatus != GR_OK) break;
         if (conc) {
             if (!(mask & (1u << S.fid))) { // no solve synchronised the stream
