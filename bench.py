@@ -292,7 +292,7 @@ def main():
                     help="only the finest-level sweeps and a copy of known size (for hardware counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path (asked for {args.gpus})",
+        print(f"bench.py runs on exactly one GPU: the library has no multi-GPU path (asked for {args.gpus})",
               file=sys.stderr)
         sys.exit(2)
 
