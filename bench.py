@@ -23,6 +23,7 @@ HBM_PEAK_GBPS = 8000.0
 # algorithmic bytes per grid point of one red-black sweep (both colours):
 # phi read + write, source read, coefficient read (none for Poisson)
 SWEEP_BYTES = {"hamiltonian": 32.0, "poisson": 24.0}
+SWEEP_BYTES_KIND = {0: 24.0, 1: 32.0, 2: 32.0, 3: 12.0, 4: 20.0, 5: 16.0}
 KIND_NAMES = {0: "poisson_fp64", 1: "hamiltonian_fp64", 2: "cmc_fp64", 3: "poisson_fp32", 4: "hamiltonian_fp32",
               5: "cmc_fp32"}
 
@@ -178,6 +179,30 @@ def c1_workload(torch, grmg, synth):
     return {"workload": "32^3 Hamiltonian only, s0 = 1 + GRF(k^-2, sigma 0.1, seed 0), FP64, rtol 1e-10",
             "ms": round(sorted(times[1:])[len(times[1:]) // 2] * 1e3, 3), "cycles": cyc,
             "factor_per_cycle": round(rep["rel_res"][grmg.PSI] ** (1.0 / max(cyc, 1)), 4)}, src
+
+
+def c2_workload(torch, grmg, synth):
+    """The 128^3 all-field FP64 solve: 128^3 Zel'dovich particles (seed 1, rms
+    displacement 0.3 cells), CIC, the ten fields from zero guesses to 1e-10."""
+    n = 128
+    g = grmg.Grid(n, a=1.0, omega_m=synth.OMEGA_M, c_tilde=synth.C_TILDE, device="cuda:0")
+    pos, u, mass = synth.zeldovich(n, 1, 0.3)
+    pos_d = torch.as_tensor(pos, device="cuda:0")
+    u_d = torch.as_tensor(u, device="cuda:0")
+    grmg.autotune(g.handle)
+    times = []
+    for _ in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.deposit_sources(pos_d, u_d, mass)
+        rep = g.solve_constraints(rtol=1e-10)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    g.close()
+    dt = sorted(times[1:])[len(times[1:]) // 2]
+    return {"workload": "128^3 Zel'dovich particles seed 1 rms 0.3 cells, CIC + 10 fields FP64 from zero guess, "
+                        "rtol 1e-10", "ms": round(dt * 1e3, 3), "cycles": rep["cycles"],
+            "points_cycles_per_s": round(n ** 3 * sum(rep["cycles"]) / dt, 1)}
 
 
 def c1_oracle_seconds(src, cycles):
@@ -398,6 +423,9 @@ def main():
                                f"{n}^3 points per launch, mean of {in_solve[1][0]} launches in one FP64 solve step "
                                f"({in_solve[1][1] * 1e3:.2f} us)"},
         "in_solve_sweeps_us": {KIND_NAMES[k]: round(v[1] * 1e3, 2) for k, v in in_solve.items()},
+        # algorithmic GB/s of the in-solve sweeps: FP64 phi r+w, f, coefficient; FP32 e r+w, b, c (and a)
+        "in_solve_sweeps_GBps": {KIND_NAMES[k]: round(SWEEP_BYTES_KIND[k] * N / (v[1] * 1e-3) / 1e9, 1)
+                                 for k, v in in_solve.items() if v[1] > 0},
     }
     traffic = pmc_traffic(n)
     if traffic is not None:
@@ -406,6 +434,8 @@ def main():
     del d_pos, d_u
     c1, c1_src = c1_workload(torch, grmg, synth)
     out["c1"] = c1
+    log("c2: 128^3 all fields")
+    out["c2"] = c2_workload(torch, grmg, synth)
     if not args.no_learned and n == 256:
         log("learned guess: held-out trajectory")
         out["learned"] = bench_learned(torch, grmg, synth, n)
