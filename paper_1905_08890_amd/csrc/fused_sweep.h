@@ -82,15 +82,16 @@ __device__ __forceinline__ void rb_fused_tile(const T *__restrict__ in, T *__res
         return (long)wrapi(z, n) * plane + wrapi(y0 + hy - 2, n) * n + wrapi(x0 + hx - 2, n);
     };
 
-    // Operands travel PF (1 or 2) planes ahead, in PF alternating register
-    // sets: the iterate plane stored at iteration it was loaded at it - PF, and
-    // so were the pair and halo values used by the red pass at it.
+    // Operands travel PF (1 to 4) planes ahead, in PF rotating register sets:
+    // the iterate plane stored at iteration it was loaded at it - PF, and so
+    // were the pair and halo values used by the red pass at it.
     struct Set {
         T pre[NLOAD];
         T2 f, c, a;
         T hf, hc, ha;
     };
-    Set A, B;
+    static_assert(PF >= 1 && PF <= 4, "prefetch depth 1 to 4");
+    Set S[PF];
     // in == nullptr: the incoming iterate is identically zero (first sweep of a
     // correction cycle), so the plane loads are skipped
     const bool zero_in = in == nullptr;
@@ -118,25 +119,27 @@ __device__ __forceinline__ void rb_fused_tile(const T *__restrict__ in, T *__res
             if (NC >= 2) S.ha = c2[hg];
         }
     };
-    A.f.x = A.f.y = A.c.x = A.c.y = A.a.x = A.a.y = A.hf = A.hc = A.ha = T(0);
-    B.f = A.f;
-    B.c = A.c;
-    B.a = A.a;
-    B.hf = B.hc = B.ha = T(0);
-    load_plane(A, z0 - 2);
-    if (PF == 2) load_plane(B, z0 - 1);
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        S[q].f.x = S[q].f.y = S[q].c.x = S[q].c.y = S[q].a.x = S[q].a.y = S[q].hf = S[q].hc = S[q].ha = T(0);
+        load_plane(S[q], z0 - 2 + q);
+    }
+    // the red pass at it (>= 2) works on plane z0 - 3 + it; below it = PF its
+    // operands were not loaded inside the loop
+#pragma unroll
+    for (int q = 2; q < PF; ++q) load_operands(S[q], z0 - 3 + q);
     T fbk = 0, cbk = 0, abk = 0; // black half of the pair for the black pass of the next iteration
 
     int slot = 0; // slot of plane zz = z0 - 2 + it is it % 5
-    auto body = [&](const int it, Set &S) {
+    auto body = [&](const int it, Set &R) {
         const int zz = z0 - 2 + it;
         T *cur = ring[slot];
 #pragma unroll
         for (int q = 0; q < NLOAD; ++q)
-            if (lidx[q] >= 0) cur[lidx[q]] = S.pre[q];
+            if (lidx[q] >= 0) cur[lidx[q]] = R.pre[q];
         __syncthreads();
         const bool ahead = it + PF < zc + 4;
-        if (ahead) load_plane(S, zz + PF);
+        if (ahead) load_plane(R, zz + PF);
         const int s1 = slot == 0 ? 4 : slot - 1, s2 = s1 == 0 ? 4 : s1 - 1, s3 = s2 == 0 ? 4 : s2 - 1;
         if (it >= 2) { // red points of plane zr = zz - 1, tile + 1-cell halo
             const int zr = zz - 1;
@@ -149,8 +152,8 @@ __device__ __forceinline__ void rb_fused_tile(const T *__restrict__ in, T *__res
                 const T ph = mid[c];
                 const T nbs = mid[c - 1] + mid[c + 1] + mid[c - W] + mid[c + W] + lo[c] + hi[c];
                 T J;
-                const T L = op_point<KIND, T>(ph, nbs, inv_h2, o ? S.c.y : S.c.x, o ? S.a.y : S.a.x, oc, Fb, J);
-                mid[c] = ph - (L - ((o ? S.f.y : S.f.x) - fs)) / J;
+                const T L = op_point<KIND, T>(ph, nbs, inv_h2, o ? R.c.y : R.c.x, o ? R.a.y : R.a.x, oc, Fb, J);
+                mid[c] = ph - (L - ((o ? R.f.y : R.f.x) - fs)) / J;
             }
             if (tid < HALO) {
                 int hy, hx;
@@ -159,14 +162,14 @@ __device__ __forceinline__ void rb_fused_tile(const T *__restrict__ in, T *__res
                 const T ph = mid[c];
                 const T nbs = mid[c - 1] + mid[c + 1] + mid[c - W] + mid[c + W] + lo[c] + hi[c];
                 T J;
-                const T L = op_point<KIND, T>(ph, nbs, inv_h2, S.hc, S.ha, oc, Fb, J);
-                mid[c] = ph - (L - (S.hf - fs)) / J;
+                const T L = op_point<KIND, T>(ph, nbs, inv_h2, R.hc, R.ha, oc, Fb, J);
+                mid[c] = ph - (L - (R.hf - fs)) / J;
             }
         }
         // plane zz - 1 had its red pass now; its black half is used at it + 1
         const int ob = (ly + zz) & 1;
-        const T nfb = ob ? S.f.y : S.f.x, ncb = ob ? S.c.y : S.c.x, nab = ob ? S.a.y : S.a.x;
-        if (ahead) load_operands(S, zz + PF - 1); // red pass of plane zz + PF - 1 at it + PF
+        const T nfb = ob ? R.f.y : R.f.x, ncb = ob ? R.c.y : R.c.x, nab = ob ? R.a.y : R.a.x;
+        if (ahead) load_operands(R, zz + PF - 1); // red pass of plane zz + PF - 1 at it + PF
         __syncthreads();
         if (it >= 4) { // black points of plane zb = zz - 2, tile only; write both colours
             const int zb = zz - 2;
@@ -191,13 +194,10 @@ __device__ __forceinline__ void rb_fused_tile(const T *__restrict__ in, T *__res
         abk = nab;
         slot = slot == 4 ? 0 : slot + 1;
     };
-    if (PF == 2) {
-        for (int it = 0; it < zc + 4; it += 2) {
-            body(it, A);
-            if (it + 1 < zc + 4) body(it + 1, B);
-        }
-    } else {
-        for (int it = 0; it < zc + 4; ++it) body(it, A);
+    for (int it = 0; it < zc + 4; it += PF) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q)
+            if (it + q < zc + 4) body(it + q, S[q]);
     }
 }
 

@@ -81,12 +81,26 @@ __global__ void __launch_bounds__((TX / 2) * TY) k_rb_fused(
 {
     int b = blockIdx.x;
     const int G = gridDim.x;
-    if (xcd_remap && (G & 7) == 0) b = (b & 7) * (G >> 3) + (b >> 3); // one XCD gets a contiguous range
     const int nz = n / zc;
-    const int zchunk = b % nz;
-    const int t2 = b / nz;
-    rb_fused_tile<KIND, T, TX, TY, PF>(in, out, f, c1, c2, n, zc, inv_h2, oc, T(*fbar), T(*fshift),
-                                       (t2 / tiles_y) * TX, (t2 % tiles_y) * TY, zchunk * zc);
+    int zchunk, tx, ty;
+    if (xcd_remap == 2 && (G & 7) == 0) {
+        // Workgroups are dispatched to the 8 XCDs in turn: give XCD b % 8 a
+        // contiguous run of G / 8 tiles of one z-chunk, x fastest, so the
+        // halos the tiles exchange are fetched into that XCD's own L2 once.
+        const int w = (b & 7) * (G >> 3) + (b >> 3);
+        const int per_plane = G / nz, tiles_x = per_plane / tiles_y, t = w % per_plane;
+        zchunk = w / per_plane;
+        tx = t % tiles_x;
+        ty = t / tiles_x;
+    } else {
+        if (xcd_remap == 1 && (G & 7) == 0) b = (b & 7) * (G >> 3) + (b >> 3); // one XCD gets a contiguous range
+        zchunk = b % nz;
+        const int t2 = b / nz;
+        tx = t2 / tiles_y;
+        ty = t2 % tiles_y;
+    }
+    rb_fused_tile<KIND, T, TX, TY, PF>(in, out, f, c1, c2, n, zc, inv_h2, oc, T(*fbar), T(*fshift), tx * TX, ty * TY,
+                                       zchunk * zc);
 }
 
 // ------------------------------------------------- residual and restriction
@@ -623,7 +637,15 @@ static void launch_fused_k(int pf, unsigned grid, hipStream_t s, const T *in, T 
     // FP64 Hamiltonian and CMC sweeps in tiles under 64x16, whose extra
     // registers would cost a resident workgroup per CU
     if (pf <= 0) pf = (TX * TY >= 1024 || sizeof(T) == 4 || KIND == GR_KIND_POISSON) ? 2 : 1;
-    if (pf == 2)
+    // deeper prefetch (3 or 4 planes) is built for the 64 x 16 tile only
+    if (pf > 2 && TX * TY < 1024) pf = 2;
+    if (TX * TY >= 1024 && pf == 4)
+        k_rb_fused<KIND, T, TX, TY, (TX * TY >= 1024 ? 4 : 2)><<<grid, NT, 0, s>>>(
+            in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift, tiles_y, xcd_remap);
+    else if (TX * TY >= 1024 && pf == 3)
+        k_rb_fused<KIND, T, TX, TY, (TX * TY >= 1024 ? 3 : 2)><<<grid, NT, 0, s>>>(
+            in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift, tiles_y, xcd_remap);
+    else if (pf == 2)
         k_rb_fused<KIND, T, TX, TY, 2><<<grid, NT, 0, s>>>(in, out, f, c1, c2, n, zc, inv_h2, oc, fbar, fshift,
                                                              tiles_y, xcd_remap);
     else

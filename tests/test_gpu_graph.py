@@ -88,6 +88,30 @@ def test_autotuned_launch_shapes_give_the_same_solve(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("pf,remap", [("3", "0"), ("4", "2"), ("1", "1")])
+def test_forced_launch_shapes_give_the_same_solve(precision, pf, remap, monkeypatch):
+    """Every prefetch depth and workgroup order of the 64x16 fused sweep (FP64
+    and FP32 kinds, fused from 64^3 down) gives the default shapes' solve bit
+    for bit."""
+    n = 128
+    print(f"[gpu] forced shapes n={n} {precision} pf={pf} remap={remap}", flush=True)
+    a = grmg.Grid(n, **PRM)
+    monkeypatch.setenv("GRMG_FUSED_MIN", "64")
+    monkeypatch.setenv("GRMG_FUSED_TILE", "2")
+    monkeypatch.setenv("GRMG_FUSED_PF", pf)
+    monkeypatch.setenv("GRMG_XCD_REMAP", remap)
+    b = grmg.Grid(n, **PRM)
+    pos, u, mass = synth.zeldovich(n, 6, 0.5)
+    a.deposit_sources(pos, u, mass)
+    _same_sources(b, a)
+    ra = a.solve_constraints(rtol=1e-10, precision=precision)
+    rb = b.solve_constraints(rtol=1e-10, precision=precision)
+    assert ra["cycles"] == rb["cycles"]
+    for f in range(10):
+        assert torch.equal(a.get_field(f), b.get_field(f)), f
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_concurrent_vector_components_match_sequential(precision, monkeypatch):
     """The three components of the vector equations solved side by side, each on
     a helper hierarchy with its own stream, give the sequential solve bit for bit."""
