@@ -38,6 +38,7 @@ using namespace grmg::detail;
 namespace {
 
 constexpr int TPB = 256;
+constexpr int kSumPPT = 8; // points per thread of the batch sums and mean subtraction
 constexpr int CTPB = 1024;
 constexpr int kMaxBoxes = 4096;
 
@@ -271,27 +272,39 @@ __device__ __forceinline__ void block_store(double (&v)[NC], double *__restrict_
 }
 
 // what: 0 sum(phi), 1 sum F (Hamiltonian), 2 sum(m2 phi), 3 sum(f), 4..6 sum(s_x..s_z), 7 sum(e) (FP32 correction)
+// PPT points per thread (strided by the block size, so each pass is coalesced);
+// the table gives each box ceil(n^3 / (PPT TPB)) blocks
+template <int PPT>
 __global__ void __launch_bounds__(TPB) kb_sum(BatchDev D, const int *__restrict__ tab, int fid, int what, OpConst oc,
                                               int active_only)
 {
-    BOX_PROLOGUE(tab)
+    const int b = find_box(tab, D.nbox, blockIdx.x);
+    const BoxDev &X = D.box[b];
     const int total = tab[D.nbox];
     double v[1] = {0.0};
     const BoxLev &L = X.lev[0];
     const int N = L.n * L.n * L.n;
-    if (t < N && (!active_only || D.active[b])) {
-        const double ph = X.field[fid][t];
-        if (what == 0) v[0] = ph;
-        else if (what == 1) {
-            const double chi = 1.0 - oc.kappa * ph;
-            const double chi2 = chi * chi;
-            const double chi6 = chi2 * chi2 * chi2;
-            const double chim7 = 1.0 / (chi6 * chi);
-            v[0] = (L.f[t] - oc.A * (chi6 - 1.0)) / chi + 0.25 * L.coef[t] * chim7;
-        } else if (what == 2) v[0] = L.coef[t] * ph;
-        else if (what == 3) v[0] = L.f[t];
-        else if (what == 7) v[0] = (double)X.lev[0].e[t];
-        else v[0] = X.src[what - 3][t];
+    if (!active_only || D.active[b]) {
+        const int t0 = (blockIdx.x - tab[b]) * TPB * PPT + threadIdx.x;
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int t = t0 + q * TPB;
+            if (t >= N) break;
+            const double ph = X.field[fid][t];
+            double x;
+            if (what == 0) x = ph;
+            else if (what == 1) {
+                const double chi = 1.0 - oc.kappa * ph;
+                const double chi2 = chi * chi;
+                const double chi6 = chi2 * chi2 * chi2;
+                const double chim7 = 1.0 / (chi6 * chi);
+                x = (L.f[t] - oc.A * (chi6 - 1.0)) / chi + 0.25 * L.coef[t] * chim7;
+            } else if (what == 2) x = L.coef[t] * ph;
+            else if (what == 3) x = L.f[t];
+            else if (what == 7) x = (double)X.lev[0].e[t];
+            else x = X.src[what - 3][t];
+            v[0] += x;
+        }
     }
     block_store<1>(v, D.partials, total);
 }
@@ -408,13 +421,22 @@ __global__ void __launch_bounds__(TPB) kb_finalize(BatchDev D, const int *__rest
     }
 }
 
-// phi -= box mean (B_MEAN)
+// phi -= box mean (B_MEAN); PPT points per thread as in kb_sum
+template <int PPT>
 __global__ void __launch_bounds__(TPB) kb_sub_mean(BatchDev D, const int *__restrict__ tab, int fid, int active_only)
 {
-    BOX_PROLOGUE(tab)
+    const int b = find_box(tab, D.nbox, blockIdx.x);
+    const BoxDev &X = D.box[b];
     if (active_only && !D.active[b]) return;
-    const int n = X.lev[0].n;
-    if (t < n * n * n) X.field[fid][t] -= D.scal[b * B_NSCAL + B_MEAN];
+    const int n = X.lev[0].n, N = n * n * n;
+    const double mean = D.scal[b * B_NSCAL + B_MEAN];
+    double *phi = X.field[fid];
+    const int t0 = (blockIdx.x - tab[b]) * TPB * PPT + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+        const int t = t0 + q * TPB;
+        if (t < N) phi[t] -= mean;
+    }
 }
 
 // Stopping test per item of [b0, b1) (same criterion as the single-grid
@@ -1223,6 +1245,7 @@ struct gr_batch_s {
     std::vector<BoxDev> host;   // pointers into the workspace
     int maxdepth = 0;           // deepest multigrid level handled by grouped launches
     Tab fine;                   // fine level of every box
+    Tab fine8;                  // the same, kSumPPT points per thread (sums, mean subtraction)
     std::vector<Tab> colour, cdom, coefr; // per depth
     std::vector<Tab> fz, fz64, colour_nf;       // per depth: fused boxes (32x16, 64x16 tiles), the others' colour passes
     // per depth and box: how level d is smoothed: 0 one launch per colour,
@@ -1321,6 +1344,7 @@ size_t batch_layout(gr_batch B, char *base)
     B->p_partials = takeD((size_t)B->pfine.total() * 2 + 16);
     B->p_any = takeI(1);
     B->fine.dev = takeI(B->nbox + 1);
+    B->fine8.dev = takeI(B->nbox + 1);
     B->norms.dev = takeI(B->nbox + 1);
     for (int d = 0; d < B->maxdepth; ++d) {
         B->colour[d].dev = takeI(B->nbox + 1);
@@ -1363,9 +1387,9 @@ OpConst opc(gr_batch B)
 int batch_pin(gr_batch B, int fid, int active_only)
 {
     hipStream_t s = B->stream;
-    kb_sum<<<B->fine.total(), TPB, 0, s>>>(B->D, B->fine.dev, fid, 0, opc(B), active_only);
-    kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_MEAN, -1, active_only, 0);
-    kb_sub_mean<<<B->fine.total(), TPB, 0, s>>>(B->D, B->fine.dev, fid, active_only);
+    kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, fid, 0, opc(B), active_only);
+    kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_MEAN, -1, active_only, 0);
+    kb_sub_mean<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, fid, active_only);
     BLAUNCH();
     return GR_OK;
 }
@@ -1432,11 +1456,11 @@ int batch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
     const OpConst oc = opc(B);
     const int FT = B->fine.total();
     if (kind == GR_KIND_HAMILTONIAN) {
-        kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid, 1, oc, 1);
-        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FBAR, -1, 1, 0);
+        kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, fid, 1, oc, 1);
+        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_FBAR, -1, 1, 0);
     } else if (kind == GR_KIND_CMC) {
-        kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid, 2, oc, 1);
-        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FSHIFT, B_FMEAN, 1, 0);
+        kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, fid, 2, oc, 1);
+        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_FSHIFT, B_FMEAN, 1, 0);
     }
     KDISPATCH(kind, kb_norms_m, B->norms.total(), TPB, B->D, B->norms.dev, fid, oc);
     kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->norms.dev, 2, B_RN, -1, 1, 0);
@@ -1528,8 +1552,8 @@ int batch_field(gr_batch B, int kind, int fid, const gr_solve_opts &o)
             if (B->coefr[d].total())
                 kb_restrict_coef<<<B->coefr[d].total(), TPB, 0, s>>>(B->D, B->coefr[d].dev, (int)d);
     if (kind == GR_KIND_CMC) {
-        kb_sum<<<B->fine.total(), TPB, 0, s>>>(B->D, B->fine.dev, fid, 3, oc, 0);
-        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FMEAN, -1, 0, 0);
+        kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, fid, 3, oc, 0);
+        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_FMEAN, -1, 0, 0);
     }
     BLAUNCH();
     BCHK(batch_pin(B, fid, 0));
@@ -1580,11 +1604,11 @@ int batch_cycle_mixed(gr_batch B, int kind, int fid, const gr_solve_opts &o)
     const OpConst oc = opc(B);
     const int FT = B->fine.total();
     if (kind == GR_KIND_HAMILTONIAN) {
-        kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid, 1, oc, 1);
-        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FBAR, -1, 1, 0);
+        kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, fid, 1, oc, 1);
+        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_FBAR, -1, 1, 0);
     } else if (kind == GR_KIND_CMC) {
-        kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid, 2, oc, 1);
-        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FSHIFT, B_FMEAN, 1, 0);
+        kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, fid, 2, oc, 1);
+        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_FSHIFT, B_FMEAN, 1, 0);
     }
     KDISPATCH(kind, kb_ir_residual, FT, TPB, B->D, B->fine.dev, fid, oc);
     kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 2, B_RN, -1, 1, 0);
@@ -1607,8 +1631,8 @@ int batch_cycle_mixed(gr_batch B, int kind, int fid, const gr_solve_opts &o)
         kb32_prolong<<<B->cells32[d].total(), TPB, 0, s>>>(B->D, B->cells32[d].dev, d);
         batch_smooth32(B, kind, d, o.nu2);
     }
-    kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid, 7, oc, 1);
-    kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_MEAN, -1, 1, 0);
+    kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, fid, 7, oc, 1);
+    kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_MEAN, -1, 1, 0);
     kb_ir_update<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid);
     BLAUNCH();
     return GR_OK;
@@ -1620,8 +1644,8 @@ int batch_field_mixed(gr_batch B, int kind, int fid, const gr_solve_opts &o)
     const OpConst oc = opc(B);
     kb_begin_field<<<1, 1024, 0, s>>>(B->D, fid, 0, B->nper, fid);
     if (kind == GR_KIND_CMC) { // <f>, and c = -m2 in FP32 on every level (fixed for the solve)
-        kb_sum<<<B->fine.total(), TPB, 0, s>>>(B->D, B->fine.dev, fid, 3, oc, 0);
-        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_FMEAN, -1, 0, 0);
+        kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, fid, 3, oc, 0);
+        kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_FMEAN, -1, 0, 0);
         kb_neg_coef32<<<B->fine.total(), TPB, 0, s>>>(B->D, B->fine.dev);
         for (size_t d = 0; d < B->coefr.size(); ++d)
             if (B->coefr[d].total())
@@ -1791,6 +1815,10 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
     auto &H = B->host;
     // periodic tables: no blocks for patches
     make_tab(B->fine, nb, [&](int b) { long n = H[b].patch ? 0 : H[b].lev[0].n; return n * n * n; });
+    make_tab(B->fine8, nb, [&](int b) {
+        long n = H[b].patch ? 0 : H[b].lev[0].n;
+        return (n * n * n + kSumPPT - 1) / kSumPPT;
+    });
     B->colour.resize(maxd);
     B->cdom.resize(maxd);
     B->fz.resize(maxd);
@@ -1920,6 +1948,7 @@ int gr_batch_bind(gr_batch B, void *d_ws, size_t bytes, void *stream)
         return hipMemcpyAsync(T.dev, T.start.data(), sizeof(int) * T.start.size(), hipMemcpyHostToDevice, s);
     };
     BHIP(up(B->fine));
+    BHIP(up(B->fine8));
     BHIP(up(B->norms));
     for (int d = 0; d < B->maxdepth; ++d) {
         BHIP(up(B->colour[d]));
@@ -2165,18 +2194,18 @@ int gr_batch_solve(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_
     };
     const std::vector<Step> steps = {
         {GR_KIND_POISSON, GR_VX, [&] {
-             kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, 0, 4, oc, 0);
-             kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_TMP, -1, 0, 0);
+             kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, 0, 4, oc, 0);
+             kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_TMP, -1, 0, 0);
              build(0, 0);
          }, [&] { pbuild(0, 0); }},
         {GR_KIND_POISSON, GR_VY, [&] {
-             kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, 0, 5, oc, 0);
-             kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_TMP, -1, 0, 0);
+             kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, 0, 5, oc, 0);
+             kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_TMP, -1, 0, 0);
              build(0, 1);
          }, [&] { pbuild(0, 1); }},
         {GR_KIND_POISSON, GR_VZ, [&] {
-             kb_sum<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, 0, 6, oc, 0);
-             kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 1, B_TMP, -1, 0, 0);
+             kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, 0, 6, oc, 0);
+             kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_TMP, -1, 0, 0);
              build(0, 2);
          }, [&] { pbuild(0, 2); }},
         {GR_KIND_POISSON, GR_U, [&] { build(1, 0); }, [&] { pbuild(1, 0); }},
