@@ -90,6 +90,34 @@ def test_sweep_matches_oracle(kind, n, mode, monkeypatch):
 
 
 @pytest.mark.parametrize("kind", list(KINDS))
+def test_sweep_full_size_in_tuned_shapes(kind):
+    """256^3, after the autotuner has chosen the launch shapes the benchmark
+    times (tile, workgroups, prefetch depth, workgroup order): 2 and 3 sweeps
+    against the oracle, every element."""
+    k = KINDS[kind]
+    n = 256
+    print(f"[gpu] full-size tuned sweep kind={kind}", flush=True)
+    phi, f, coef, prm = random_problem(k, n, 900)
+    Fbar, fshift = (0.37, 0.0) if k == O.HAMILTONIAN else ((0.0, 0.21) if k == O.CMC else (0.0, 0.0))
+    g = grid(n, prm)
+    report = grmg.autotune(g.handle)
+    assert "n=256" in report
+    p = O.params(**prm)
+    ref = phi
+    done = 0
+    for nsweeps in (2, 3):
+        g.set_field("Psi", phi)
+        g.set_field("rhs", f)
+        g.set_field("coef", coef)
+        grmg.debug_sweep(g.handle, k, grmg.PSI, Fbar, fshift, nsweeps)
+        while done < nsweeps:
+            ref = O.rb_sweep(k, ref, f, coef, prm=p, Fbar=Fbar, fshift=fshift)
+            done += 1
+        assert maxrel(g.get_field("Psi"), ref) < 1e-13, nsweeps
+        ref, done = phi, 0
+
+
+@pytest.mark.parametrize("kind", list(KINDS))
 def test_residual_matches_oracle(kind):
     k = KINDS[kind]
     n = 24
@@ -331,6 +359,57 @@ def test_full_size_256_properties():
         rel = O.cycle_residual(kind, F[name], f, coef, prm=p)
         print(name, rep["cycles"][O.FIELDS.index(name)], rel, flush=True)
         assert rel <= 1.0001e-10, name
+
+
+@pytest.mark.timeout(400)
+def test_max_size_512():
+    """The largest grid this workload sizes for (512^3: a 68 GB workspace),
+    in autotuned launch shapes.  Poisson: a product of sines of wave numbers
+    (1, 2, 3) is an eigenfunction of the 7-point Laplacian, so the converged
+    solution is the source over the discrete eigenvalue (closed form).  All
+    ten fields from s0 = 1 + plane waves, s_m from plane waves, s_i = 0 (so
+    V, U, A_ij, B, b vanish): the Hamiltonian and CMC fields meet 1e-10 when
+    the oracle re-evaluates their stopping quantities."""
+    n = 512
+    h = 1.0 / n
+    x = (np.arange(n) + 0.5) * h
+    g = grid(n, DEFAULT)
+    report = grmg.autotune(g.handle)
+    assert "n=512" in report
+    wx, wy, wz = (np.sin(2 * np.pi * k * x) for k in (1, 2, 3))
+    mode = wz[:, None, None] * wy[None, :, None] * wx[None, None, :]
+    lam = -sum((2.0 - 2.0 * np.cos(2 * np.pi * k * h)) / h ** 2 for k in (1, 2, 3))
+    f = 50.0 * mode
+    g.set_field("rhs", f)
+    rep = g.solve_equation(O.POISSON, "Vx", rtol=1e-10)
+    assert rep["status"] == 0
+    print("[gpu] 512 Poisson cycles", rep["cycles"], flush=True)
+    assert maxrel(g.get_field("Vx"), f / lam) < 1e-8
+    del f
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+
+    cx, cy = np.cos(2 * np.pi * x), np.cos(4 * np.pi * x)
+    s0 = 1.0 + 0.3 * (cx[None, None, :] * cy[None, :, None] + 0.5 * wz[:, None, None])
+    sm = 1e-3 * cy[:, None, None] * wx[None, None, :] * np.ones((1, n, 1))
+    zero = np.zeros((n, n, n))
+    g2 = grid(n, DEFAULT)
+    grmg.autotune(g2.handle)  # the shapes chosen above, from the tuner's cache
+    for name, v in (("s0", s0), ("sx", zero), ("sy", zero), ("sz", zero), ("sm", sm)):
+        g2.set_field(name, v)
+    rep = g2.solve_constraints(rtol=1e-10)
+    print("[gpu] 512 all fields cycles", rep["cycles"], flush=True)
+    assert rep["status"] == 0
+    for name in ("Vx", "U", "Bx", "b"):
+        assert float(g2.get_field(name).abs().max()) == 0.0, name
+    p = O.params(**DEFAULT)
+    psi = g2.get_field("Psi").cpu().numpy()
+    rel = O.cycle_residual(O.HAMILTONIAN, psi, 1.5 * p.a * p.omega_m * (s0 - 1.0), zero, prm=p)
+    assert rel <= 1.0001e-10, rel
+    m2, fxi = O.build_cmc(psi, s0, sm, zero, prm=p)
+    rel = O.cycle_residual(O.CMC, g2.get_field("xi").cpu().numpy(), fxi, m2, prm=p)
+    assert rel <= 1.0001e-10, rel
 
 
 # ------------------------------------------------------------ error paths
