@@ -80,6 +80,7 @@ struct BatchDev {
     int *any_active;
     double *partials;
     int nbox;
+    int march; // the stopping norms and residual + restriction use the plane-marching form where it applies
 };
 
 __device__ __forceinline__ int find_box(const int *__restrict__ start, int nbox, int blk)
@@ -286,25 +287,29 @@ __global__ void __launch_bounds__(TPB) kb_sum(BatchDev D, const int *__restrict_
     const int N = L.n * L.n * L.n;
     if (!active_only || D.active[b]) {
         const int t0 = (blockIdx.x - tab[b]) * TPB * PPT + threadIdx.x;
+        // every load of the thread is issued before the first is used
+        double x[PPT];
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             const int t = t0 + q * TPB;
-            if (t >= N) break;
-            const double ph = X.field[fid][t];
-            double x;
-            if (what == 0) x = ph;
+            const bool in = t < N;
+            const int tc = in ? t : 0;
+            double val;
+            if (what == 0) val = X.field[fid][tc];
             else if (what == 1) {
-                const double chi = 1.0 - oc.kappa * ph;
+                const double chi = 1.0 - oc.kappa * X.field[fid][tc];
                 const double chi2 = chi * chi;
                 const double chi6 = chi2 * chi2 * chi2;
                 const double chim7 = 1.0 / (chi6 * chi);
-                x = (L.f[t] - oc.A * (chi6 - 1.0)) / chi + 0.25 * L.coef[t] * chim7;
-            } else if (what == 2) x = L.coef[t] * ph;
-            else if (what == 3) x = L.f[t];
-            else if (what == 7) x = (double)X.lev[0].e[t];
-            else x = X.src[what - 3][t];
-            v[0] += x;
+                val = (L.f[tc] - oc.A * (chi6 - 1.0)) / chi + 0.25 * L.coef[tc] * chim7;
+            } else if (what == 2) val = L.coef[tc] * X.field[fid][tc];
+            else if (what == 3) val = L.f[tc];
+            else if (what == 7) val = (double)X.lev[0].e[tc];
+            else val = X.src[what - 3][tc];
+            x[q] = in ? val : 0.0;
         }
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) v[0] += x[q];
     }
     block_store<1>(v, D.partials, total);
 }
@@ -331,7 +336,7 @@ __global__ void __launch_bounds__(TPB) kb_norms_m(BatchDev D, const int *__restr
     double v[2] = {0.0, 0.0};
     if (D.active[b]) {
         const double *phi = X.field[fid];
-        if (marchable(n)) {
+        if (D.march && marchable(n)) { // the block table gives march_blocks(n) blocks
             const int nzc = n / kMZ, tiles_y = n / MTY, tile = lb / nzc, zchunk = lb % nzc;
             march_tile<M_NORMS, KIND, double>(phi, L.f, L.coef, nullptr, n, kMZ, 1.0 / (L.h * L.h), oc, Fb, fs,
                                               (tile / tiles_y) * MTX, (tile % tiles_y) * MTY, zchunk * kMZ, nullptr,
@@ -366,7 +371,7 @@ __global__ void __launch_bounds__(TPB) kb_rr_m(BatchDev D, const int *__restrict
     const double *phi = d == 0 ? X.field[fid] : L.phi;
     const double Fb = d == 0 ? D.scal[b * B_NSCAL + B_FBAR] : 0.0;
     const double fs = d == 0 ? D.scal[b * B_NSCAL + B_FSHIFT] : 0.0;
-    if (marchable(n)) {
+    if (D.march && marchable(n)) { // the block table gives march_blocks(n) blocks
         const int nzc = n / kMZ, tiles_y = n / MTY, tile = lb / nzc, zchunk = lb % nzc;
         double v[2];
         march_tile<M_RESTRICT, KIND, double>(phi, L.f, L.coef, nullptr, n, kMZ, 1.0 / (L.h * L.h), oc, Fb, fs,
@@ -670,33 +675,47 @@ __global__ void __launch_bounds__(CTPB) kb_coarse_vcycle(BatchDev D, int fid, in
 
 // FP64 residual -> b (FP32), the frozen Hamiltonian linearisation a = chi and
 // c = dL/dPsi + 6 chi/h^2, and block partials of r^2 and (f - fshift)^2
+// (the norms table's block layout: the plane-marching form for the boxes it
+// marches, one thread per point for the others)
 template <int KIND>
-__global__ void __launch_bounds__(TPB) kb_ir_residual(BatchDev D, const int *__restrict__ tab, int fid, OpConst oc)
+__global__ void __launch_bounds__(TPB) kb_ir_m(BatchDev D, const int *__restrict__ tab, int fid, OpConst oc)
 {
-    BOX_PROLOGUE(tab)
+    const int b = find_box(tab, D.nbox, blockIdx.x);
+    const BoxDev &X = D.box[b];
     const int total = tab[D.nbox];
+    const int lb = blockIdx.x - tab[b];
     const BoxLev &L = X.lev[0];
     const int n = L.n;
     double v[2] = {0.0, 0.0};
-    if (D.active[b] && t < n * n * n) {
-        int x, y, z;
-        decode3(t, n, n, x, y, z);
+    if (D.active[b]) {
         const double Fb = D.scal[b * B_NSCAL + B_FBAR], fs = D.scal[b * B_NSCAL + B_FSHIFT];
         const double inv_h2 = 1.0 / (L.h * L.h);
         const double *phi = X.field[fid];
-        const double ph = phi[t];
-        double J;
-        const double Lv = op_point<KIND, double>(ph, nb_sum(phi, x, y, z, n), inv_h2, load_c1<KIND>(L.coef, t), 0.0,
-                                                 oc, Fb, J);
-        const double fe = L.f[t] - fs;
-        const double e = Lv - fe;
-        v[0] = e * e;
-        v[1] = fe * fe;
-        L.b32[t] = (float)(-e);
-        if constexpr (KIND == GR_KIND_HAMILTONIAN) {
-            const double chi = 1.0 - oc.kappa * ph;
-            L.a32[t] = (float)chi;
-            L.c32[t] = (float)(J + 6.0 * chi * inv_h2);
+        if (D.march && marchable(n)) { // the block table gives march_blocks(n) blocks
+            const int nzc = n / kMZ, tiles_y = n / MTY, tile = lb / nzc, zchunk = lb % nzc;
+            march_tile<M_IR, KIND, double>(phi, L.f, L.coef, nullptr, n, kMZ, inv_h2, oc, Fb, fs,
+                                           (tile / tiles_y) * MTX, (tile % tiles_y) * MTY, zchunk * kMZ, nullptr,
+                                           nullptr, nullptr, L.b32, L.a32, L.c32, v);
+        } else {
+            const int t = lb * TPB + threadIdx.x;
+            if (t < n * n * n) {
+                int x, y, z;
+                decode3(t, n, n, x, y, z);
+                const double ph = phi[t];
+                double J;
+                const double Lv = op_point<KIND, double>(ph, nb_sum(phi, x, y, z, n), inv_h2,
+                                                         load_c1<KIND>(L.coef, t), 0.0, oc, Fb, J);
+                const double fe = L.f[t] - fs;
+                const double e = Lv - fe;
+                v[0] = e * e;
+                v[1] = fe * fe;
+                L.b32[t] = (float)(-e);
+                if constexpr (KIND == GR_KIND_HAMILTONIAN) {
+                    const double chi = 1.0 - oc.kappa * ph;
+                    L.a32[t] = (float)chi;
+                    L.c32[t] = (float)(J + 6.0 * chi * inv_h2);
+                }
+            }
         }
     }
     block_store<2>(v, D.partials, total);
@@ -726,12 +745,16 @@ __global__ void __launch_bounds__(TPB) kb_restrict32(BatchDev D, const int *__re
     (which ? C.a32 : C.c32)[t] = s / 8.f;
 }
 
+// (fine8 table: kSumPPT points per thread)
 __global__ void __launch_bounds__(TPB) kb32_fill(BatchDev D, const int *__restrict__ tab, int d)
 {
-    BOX_PROLOGUE(tab)
+    const int b = find_box(tab, D.nbox, blockIdx.x);
     if (!D.active[b]) return;
-    const BoxLev &L = X.lev[d];
-    if (t < L.n * L.n * L.n) L.e[t] = 0.f;
+    const BoxLev &L = D.box[b].lev[d];
+    const int N = L.n * L.n * L.n, t0 = (blockIdx.x - tab[b]) * TPB * kSumPPT + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < kSumPPT; ++q)
+        if (t0 + q * TPB < N) L.e[t0 + q * TPB] = 0.f;
 }
 
 // one colour of a red-black sweep of the correction equation on level d
@@ -849,12 +872,21 @@ __global__ void __launch_bounds__(kCoarseThreads) kb32_coarse(BatchDev D, int nu
 }
 
 // phi += e - <e> (mean in B_MEAN), FP64
+// (fine8 table: kSumPPT points per thread)
 __global__ void __launch_bounds__(TPB) kb_ir_update(BatchDev D, const int *__restrict__ tab, int fid)
 {
-    BOX_PROLOGUE(tab)
+    const int b = find_box(tab, D.nbox, blockIdx.x);
     if (!D.active[b]) return;
+    const BoxDev &X = D.box[b];
     const BoxLev &L = X.lev[0];
-    if (t < L.n * L.n * L.n) X.field[fid][t] += (double)L.e[t] - D.scal[b * B_NSCAL + B_MEAN];
+    const double mean = D.scal[b * B_NSCAL + B_MEAN];
+    double *phi = X.field[fid];
+    const int N = L.n * L.n * L.n, t0 = (blockIdx.x - tab[b]) * TPB * kSumPPT + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < kSumPPT; ++q) {
+        const int t = t0 + q * TPB;
+        if (t < N) phi[t] += (double)L.e[t] - mean;
+    }
 }
 
 // ------------------------------------------------- Dirichlet patches
@@ -1454,7 +1486,6 @@ int batch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
 {
     hipStream_t s = B->stream;
     const OpConst oc = opc(B);
-    const int FT = B->fine.total();
     if (kind == GR_KIND_HAMILTONIAN) {
         kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, fid, 1, oc, 1);
         kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_FBAR, -1, 1, 0);
@@ -1602,7 +1633,6 @@ int batch_cycle_mixed(gr_batch B, int kind, int fid, const gr_solve_opts &o)
 {
     hipStream_t s = B->stream;
     const OpConst oc = opc(B);
-    const int FT = B->fine.total();
     if (kind == GR_KIND_HAMILTONIAN) {
         kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, fid, 1, oc, 1);
         kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_FBAR, -1, 1, 0);
@@ -1610,15 +1640,15 @@ int batch_cycle_mixed(gr_batch B, int kind, int fid, const gr_solve_opts &o)
         kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, fid, 2, oc, 1);
         kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_FSHIFT, B_FMEAN, 1, 0);
     }
-    KDISPATCH(kind, kb_ir_residual, FT, TPB, B->D, B->fine.dev, fid, oc);
-    kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine.dev, 2, B_RN, -1, 1, 0);
+    KDISPATCH(kind, kb_ir_m, B->norms.total(), TPB, B->D, B->norms.dev, fid, oc);
+    kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->norms.dev, 2, B_RN, -1, 1, 0);
     kb_control<<<1, 1024, 0, s>>>(B->D, fid, o.rtol, o.max_cycles, 0, B->nper);
     if (kind == GR_KIND_HAMILTONIAN) // the linearisation frozen at this iterate, on every level
         for (size_t d = 0; d < B->coefr.size(); ++d)
             if (B->coefr[d].total())
                 for (int which = 0; which < 2; ++which)
                     kb_restrict32<<<B->coefr[d].total(), TPB, 0, s>>>(B->D, B->coefr[d].dev, (int)d, which);
-    kb32_fill<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, 0); // the correction starts from e = 0
+    kb32_fill<<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, 0); // the correction starts from e = 0
     for (int d = 0; d < B->maxdepth32; ++d) {
         if (B->colour32[d].total() == 0) continue;
         batch_smooth32(B, kind, d, o.nu1);
@@ -1633,7 +1663,7 @@ int batch_cycle_mixed(gr_batch B, int kind, int fid, const gr_solve_opts &o)
     }
     kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, fid, 7, oc, 1);
     kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_MEAN, -1, 1, 0);
-    kb_ir_update<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, fid);
+    kb_ir_update<<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, fid);
     BLAUNCH();
     return GR_OK;
 }
@@ -1825,6 +1855,7 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
     B->fz64.resize(maxd);
     B->rr.resize(maxd);
     if (const char *e = std::getenv("GRMG_MARCH")) B->use_march = std::atoi(e) != 0;
+    B->D.march = B->use_march ? 1 : 0;
     make_tab(B->norms, nb, [&](int b) {
         if (H[b].patch) return 0L;
         const long n = H[b].lev[0].n;

@@ -165,3 +165,29 @@ def test_batch_mixed_precision_matches_fp64():
         assert all(x <= 1e-10 for x in r32["rel_res"][i])
         for f in range(10):
             assert abs(r32["cycles"][i][f] - r64["cycles"][i][f]) <= 2, (i, f, r32["cycles"][i], r64["cycles"][i])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_per_point_forms_match_marching(precision, monkeypatch):
+    """With the plane-marching stopping norms, residual + restriction and
+    refinement residual switched off (one thread per point everywhere), the
+    batch gives the same cycle counts and fields within 1e-12 of the default
+    forms (only the order of the norm sums differs)."""
+    sides = [64, 48, 96]
+    print(f"[gpu] batch per-point forms {sides} {precision}", flush=True)
+    srcs = [synth._matter_sources(n, 850 + i, 0.3) for i, n in enumerate(sides)]
+    monkeypatch.setenv("GRMG_MARCH", "0")
+    P = grmg.Batch(sides, **PRM)
+    monkeypatch.delenv("GRMG_MARCH")
+    Q = grmg.Batch(sides, **PRM)
+    for B in (P, Q):
+        for i, src in enumerate(srcs):
+            for name, v in zip(("s0", "sx", "sy", "sz", "sm"), src):
+                B.set_field(i, name, v)
+    rp = P.solve(rtol=1e-10, precision=precision)
+    rq = Q.solve(rtol=1e-10, precision=precision)
+    assert rp["status"] == rq["status"] == grmg.OK
+    assert rp["cycles"] == rq["cycles"]
+    for i in range(len(sides)):
+        for f in range(10):
+            assert maxrel(P.get_field(i, f), Q.get_field(i, f).cpu().numpy()) < 1e-12, (i, f)

@@ -117,6 +117,36 @@ def test_sweep_full_size_in_tuned_shapes(kind):
         ref, done = phi, 0
 
 
+def test_builders_match_oracle():
+    """The source and coefficient builders as one step each (1e-13): with no
+    field selected, a constraint solve still builds every source from the
+    current fields, which leaves A_ij A^ij, the CMC mass term and the last
+    source (-1/4 div B) in place; the derived outputs are read back too."""
+    n = 48
+    print(f"[gpu] builders n={n}", flush=True)
+    fields = {name: 0.01 * synth.grf(n, 600 + i, -3.0, 1.0) for i, name in enumerate(O.FIELDS)}
+    fields["Psi"] = 0.3 * synth.grf(n, 620, -4.0, 1.0)
+    s0 = 1.0 + synth.grf(n, 621, -2.0, 0.2)
+    sm = 1e-3 * synth.grf(n, 622, -2.0, 1.0)
+    g = grid(n, DEFAULT)
+    for name, v in fields.items():
+        g.set_field(name, v)
+    g.set_field("s0", s0)
+    g.set_field("sm", sm)
+    rep = g.solve_constraints(field_mask=0, guess="current")
+    assert rep["status"] == 0 and rep["cycles"] == [0] * 10
+    p = O.params(**DEFAULT)
+    F = fields
+    A6, AA = O.build_Aij(F["Vx"], F["Vy"], F["Vz"], F["U"])
+    assert maxrel(g.get_field("AA"), AA) < 1e-13
+    m2, _ = O.build_cmc(F["Psi"], s0, sm, AA, prm=p)
+    assert maxrel(g.get_field("coef"), m2) < 1e-13
+    assert maxrel(g.get_field("rhs"), O.build_div_quarter(F["Bx"], F["By"], F["Bz"])) < 1e-13
+    Phi, bx, by, bz = O.derived(F["Psi"], F["xi"], F["Bx"], F["By"], F["Bz"], F["b"], prm=p)
+    for name, ref in (("Phi", Phi), ("beta_x", bx), ("beta_y", by), ("beta_z", bz)):
+        assert maxrel(g.get_field(name), ref) < 1e-13, name
+
+
 @pytest.mark.parametrize("kind", list(KINDS))
 def test_residual_matches_oracle(kind):
     k = KINDS[kind]
