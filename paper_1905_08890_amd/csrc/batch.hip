@@ -823,27 +823,42 @@ __global__ void __launch_bounds__(TPB) kb32_lin_rr(BatchDev D, const int *__rest
     C.e[t] = 0.f;
 }
 
-// e^h += P e^H (cell-centred trilinear, periodic): one thread per fine cell
+// e^h += P e^H (cell-centred trilinear, periodic): one thread per coarse cell,
+// which reads its 3^3 coarse neighbourhood once and updates its 8 children
+// (each child sums its 8 coarse neighbours in the same order as the FP64 form)
 __global__ void __launch_bounds__(TPB) kb32_prolong(BatchDev D, const int *__restrict__ tab, int d)
 {
     BOX_PROLOGUE(tab)
     if (!D.active[b]) return;
     const BoxLev &V = X.lev[d], &C = X.lev[d + 1];
     const int n = V.n, m = C.n;
-    if (t >= n * n * n) return;
-    int i, j, k;
-    decode3(t, n, n, i, j, k);
-    const int I = i >> 1, J = j >> 1, K = k >> 1;
-    const int Is[2] = {I, wrapi(I + ((i & 1) ? 1 : -1), m)};
-    const int Js[2] = {J, wrapi(J + ((j & 1) ? 1 : -1), m)};
-    const int Ks[2] = {K, wrapi(K + ((k & 1) ? 1 : -1), m)};
-    float v = 0.f;
-    for (int c = 0; c < 8; ++c) {
-        const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
-        const float w = (ox ? 0.25f : 0.75f) * (oy ? 0.25f : 0.75f) * (oz ? 0.25f : 0.75f);
-        v += w * C.e[lin(Is[ox], Js[oy], Ks[oz], m)];
-    }
-    V.e[t] += v;
+    if (t >= m * m * m) return;
+    int x, y, z;
+    decode3(t, m, m, x, y, z);
+    float e[3][3][3];
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx)
+                e[dz + 1][dy + 1][dx + 1] = C.e[lin(wrapi(x + dx, m), wrapi(y + dy, m), wrapi(z + dz, m), m)];
+    for (int cz = 0; cz < 2; ++cz)
+        for (int cy = 0; cy < 2; ++cy) {
+            float v[2];
+            for (int cx = 0; cx < 2; ++cx) {
+                const int sx = cx ? 1 : -1, sy = cy ? 1 : -1, sz = cz ? 1 : -1;
+                float a = 0.f;
+                for (int c = 0; c < 8; ++c) {
+                    const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+                    const float w = (ox ? 0.25f : 0.75f) * (oy ? 0.25f : 0.75f) * (oz ? 0.25f : 0.75f);
+                    a += w * e[1 + oz * sz][1 + oy * sy][1 + ox * sx];
+                }
+                v[cx] = a;
+            }
+            float2 *dst = reinterpret_cast<float2 *>(V.e + lin(2 * x, 2 * y + cy, 2 * z + cz, n));
+            float2 old = *dst;
+            old.x += v[0];
+            old.y += v[1];
+            *dst = old;
+        }
 }
 
 // the correction cycle from the box's FP32 entry level down, one workgroup per
@@ -1300,7 +1315,7 @@ struct gr_batch_s {
     Tab pfine;                                  // interior cells of level 0
     // mixed precision (periodic boxes): grouped levels of the FP32 correction cycle
     int maxdepth32 = 0;
-    std::vector<Tab> colour32, cells32, coarse32; // per depth: half cells, cells, cells of the next level
+    std::vector<Tab> colour32, coarse32; // per depth: half cells, cells of the next level
     std::vector<Tab> colour32nf;                  // per depth: half cells of the boxes not swept fused
     std::vector<Tab> pcell;                     // per level above a patch's entry: half its cells (colour passes)
     std::vector<Tab> pcellf;                    // per level above a patch's entry: its cells (prolongation)
@@ -1388,7 +1403,7 @@ size_t batch_layout(gr_batch B, char *base)
     }
     for (size_t d = 0; d < B->coefr.size(); ++d) B->coefr[d].dev = takeI(B->nbox + 1);
     B->pfine.dev = takeI(B->nbox + 1);
-    for (auto *v : {&B->pcell, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces, &B->colour32, &B->cells32,
+    for (auto *v : {&B->pcell, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces, &B->colour32,
                     &B->coarse32, &B->colour32nf})
         for (auto &T : *v) T.dev = takeI(B->nbox + 1);
     return off;
@@ -1658,7 +1673,7 @@ int batch_cycle_mixed(gr_batch B, int kind, int fid, const gr_solve_opts &o)
     for (int d = B->maxdepth32 - 1; d >= 0; --d) {
         const Tab &TC = B->colour32[d];
         if (TC.total() == 0) continue;
-        kb32_prolong<<<B->cells32[d].total(), TPB, 0, s>>>(B->D, B->cells32[d].dev, d);
+        kb32_prolong<<<B->coarse32[d].total(), TPB, 0, s>>>(B->D, B->coarse32[d].dev, d);
         batch_smooth32(B, kind, d, o.nu2);
     }
     kb_sum<kSumPPT><<<B->fine8.total(), TPB, 0, s>>>(B->D, B->fine8.dev, fid, 7, oc, 1);
@@ -1894,13 +1909,11 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
         });
     // FP32 correction cycle tables (periodic boxes, levels above their FP32 entry)
     B->colour32.resize(B->maxdepth32);
-    B->cells32.resize(B->maxdepth32);
     B->coarse32.resize(B->maxdepth32);
     B->colour32nf.resize(B->maxdepth32);
     for (int d = 0; d < B->maxdepth32; ++d) {
         auto on = [&](int b) { return !H[b].patch && d < H[b].centry32; };
         make_tab(B->colour32[d], nb, [&](int b) { long n = on(b) ? H[b].lev[d].n : 0; return n * n * n / 2; });
-        make_tab(B->cells32[d], nb, [&](int b) { long n = on(b) ? H[b].lev[d].n : 0; return n * n * n; });
         make_tab(B->coarse32[d], nb, [&](int b) { long m = on(b) ? H[b].lev[d + 1].n : 0; return m * m * m; });
         smooth32_tab(B, d); // after the forms (built above)
     }
@@ -1991,7 +2004,7 @@ int gr_batch_bind(gr_batch B, void *d_ws, size_t bytes, void *stream)
     }
     for (auto &T : B->coefr) BHIP(up(T));
     BHIP(up(B->pfine));
-    for (auto *v : {&B->pcell, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces, &B->colour32, &B->cells32,
+    for (auto *v : {&B->pcell, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces, &B->colour32,
                     &B->coarse32, &B->colour32nf})
         for (auto &T : *v) BHIP(up(T));
     BHIP(hipStreamSynchronize(s)); // host tables must outlive the copies
