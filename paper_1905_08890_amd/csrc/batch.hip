@@ -806,10 +806,19 @@ __global__ void __launch_bounds__(TPB) kb32_lin_rr(BatchDev D, const int *__rest
     if (!D.active[b]) return;
     const BoxLev &V = X.lev[d], &C = X.lev[d + 1];
     const int n = V.n, m = C.n;
+    const float inv_h2 = (float)(1.0 / (V.h * V.h));
+    if (D.march && marchable(n)) { // the block table gives march_blocks(n) blocks
+        const int lb = blockIdx.x - tab[b];
+        const int nzc = n / kMZ, tiles_y = n / MTY, tile = lb / nzc, zchunk = lb % nzc;
+        double v[2];
+        march_tile<M_RESTRICT_LIN, LKIND, float>(V.e, V.b32, V.c32, V.a32, n, kMZ, inv_h2, oc, 0.f, 0.f,
+                                                 (tile / tiles_y) * MTX, (tile % tiles_y) * MTY, zchunk * kMZ, C.b32,
+                                                 C.e, nullptr, nullptr, nullptr, nullptr, v);
+        return;
+    }
     if (t >= m * m * m) return;
     int I, J, K;
     decode3(t, m, m, I, J, K);
-    const float inv_h2 = (float)(1.0 / (V.h * V.h));
     float sr = 0.f;
     for (int c = 0; c < 8; ++c) {
         const int i = 2 * I + (c & 1), j = 2 * J + ((c >> 1) & 1), k = 2 * K + (c >> 2);
@@ -1315,7 +1324,7 @@ struct gr_batch_s {
     Tab pfine;                                  // interior cells of level 0
     // mixed precision (periodic boxes): grouped levels of the FP32 correction cycle
     int maxdepth32 = 0;
-    std::vector<Tab> colour32, coarse32; // per depth: half cells, cells of the next level
+    std::vector<Tab> colour32, coarse32, rr32; // per depth: half cells, cells of the next level, residual + restriction
     std::vector<Tab> colour32nf;                  // per depth: half cells of the boxes not swept fused
     std::vector<Tab> pcell;                     // per level above a patch's entry: half its cells (colour passes)
     std::vector<Tab> pcellf;                    // per level above a patch's entry: its cells (prolongation)
@@ -1404,7 +1413,7 @@ size_t batch_layout(gr_batch B, char *base)
     for (size_t d = 0; d < B->coefr.size(); ++d) B->coefr[d].dev = takeI(B->nbox + 1);
     B->pfine.dev = takeI(B->nbox + 1);
     for (auto *v : {&B->pcell, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces, &B->colour32,
-                    &B->coarse32, &B->colour32nf})
+                    &B->coarse32, &B->rr32, &B->colour32nf})
         for (auto &T : *v) T.dev = takeI(B->nbox + 1);
     return off;
 }
@@ -1667,7 +1676,7 @@ int batch_cycle_mixed(gr_batch B, int kind, int fid, const gr_solve_opts &o)
     for (int d = 0; d < B->maxdepth32; ++d) {
         if (B->colour32[d].total() == 0) continue;
         batch_smooth32(B, kind, d, o.nu1);
-        LDISPATCH(kind, kb32_lin_rr, B->coarse32[d].total(), TPB, B->D, B->coarse32[d].dev, d, oc);
+        LDISPATCH(kind, kb32_lin_rr, B->rr32[d].total(), TPB, B->D, B->rr32[d].dev, d, oc);
     }
     LDISPATCH(kind, kb32_coarse, B->nper, kCoarseThreads, B->D, o.nu1, o.nu2, oc);
     for (int d = B->maxdepth32 - 1; d >= 0; --d) {
@@ -1910,11 +1919,17 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
     // FP32 correction cycle tables (periodic boxes, levels above their FP32 entry)
     B->colour32.resize(B->maxdepth32);
     B->coarse32.resize(B->maxdepth32);
+    B->rr32.resize(B->maxdepth32);
     B->colour32nf.resize(B->maxdepth32);
     for (int d = 0; d < B->maxdepth32; ++d) {
         auto on = [&](int b) { return !H[b].patch && d < H[b].centry32; };
         make_tab(B->colour32[d], nb, [&](int b) { long n = on(b) ? H[b].lev[d].n : 0; return n * n * n / 2; });
         make_tab(B->coarse32[d], nb, [&](int b) { long m = on(b) ? H[b].lev[d + 1].n : 0; return m * m * m; });
+        make_tab(B->rr32[d], nb, [&](int b) {
+            if (!on(b)) return 0L;
+            const long n = H[b].lev[d].n, m = H[b].lev[d + 1].n;
+            return B->use_march && marchable((int)n) ? march_blocks((int)n) * TPB : m * m * m;
+        });
         smooth32_tab(B, d); // after the forms (built above)
     }
     // patch tables: no blocks for periodic boxes
@@ -2005,7 +2020,7 @@ int gr_batch_bind(gr_batch B, void *d_ws, size_t bytes, void *stream)
     for (auto &T : B->coefr) BHIP(up(T));
     BHIP(up(B->pfine));
     for (auto *v : {&B->pcell, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces, &B->colour32,
-                    &B->coarse32, &B->colour32nf})
+                    &B->coarse32, &B->rr32, &B->colour32nf})
         for (auto &T : *v) BHIP(up(T));
     BHIP(hipStreamSynchronize(s)); // host tables must outlive the copies
     B->D.nbox = B->nbox;
