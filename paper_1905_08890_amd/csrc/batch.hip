@@ -1303,9 +1303,9 @@ struct gr_batch_s {
     Tab fine;                   // fine level of every box
     Tab fine8;                  // the same, kSumPPT points per thread (sums, mean subtraction)
     std::vector<Tab> colour, cdom, coefr; // per depth
-    std::vector<Tab> fz, fz64, colour_nf;       // per depth: fused boxes (32x16, 64x16 tiles), the others' colour passes
+    std::vector<Tab> fz, fz64, fz16, colour_nf; // per depth: fused boxes (32x16, 64x16, 16x16 tiles), the others' colour passes
     // per depth and box: how level d is smoothed: 0 one launch per colour,
-    // 1 fused 32x16, 2 fused 64x16, -1 not at all (only while tuning)
+    // 1 fused 32x16, 2 fused 64x16, 3 fused 16x16, -1 not at all (only while tuning)
     std::vector<std::vector<signed char>> form;
     std::string tune_report;
     std::vector<Tab> rr;                        // per depth: residual + restriction (marching or per cell)
@@ -1407,6 +1407,7 @@ size_t batch_layout(gr_batch B, char *base)
         B->cdom[d].dev = takeI(B->nbox + 1);
         B->fz[d].dev = takeI(B->nbox + 1);
         B->fz64[d].dev = takeI(B->nbox + 1);
+        B->fz16[d].dev = takeI(B->nbox + 1);
         B->rr[d].dev = takeI(B->nbox + 1);
         B->colour_nf[d].dev = takeI(B->nbox + 1);
     }
@@ -1468,11 +1469,12 @@ void batch_smooth(gr_batch B, int kind, int d, int fid, int nu)
     hipStream_t s = B->stream;
     const OpConst oc = opc(B);
     // the fused forms work out of place in pairs of sweeps
-    const bool fused = nu % 2 == 0 && (B->fz[d].total() > 0 || B->fz64[d].total() > 0);
+    const bool fused = nu % 2 == 0 && (B->fz[d].total() > 0 || B->fz64[d].total() > 0 || B->fz16[d].total() > 0);
     const Tab &TC = fused ? B->colour_nf[d] : B->colour[d];
     for (int it = 0; it < nu; ++it) {
         if (fused && B->fz[d].total()) launch_kb_fused<32, 16>(s, kind, B->fz[d], B->D, d, fid, it, oc);
         if (fused && B->fz64[d].total()) launch_kb_fused<64, 16>(s, kind, B->fz64[d], B->D, d, fid, it, oc);
+        if (fused && B->fz16[d].total()) launch_kb_fused<16, 16>(s, kind, B->fz16[d], B->D, d, fid, it, oc);
         if (TC.total() > 0)
             for (int colour = 0; colour < 2; ++colour)
                 KDISPATCH(kind, kb_colour, TC.total(), TPB, B->D, TC.dev, d, fid, colour, oc);
@@ -1502,6 +1504,7 @@ void smooth_tabs(gr_batch B, int d)
     // block counts for the 512-thread 64x16 launches, as items of TPB threads
     make_tab(B->fz[d], nb, [&](int b) { return F[b] == 1 ? blocks(b, 32, 16) * TPB : 0L; });
     make_tab(B->fz64[d], nb, [&](int b) { return F[b] == 2 ? blocks(b, 64, 16) * TPB : 0L; });
+    make_tab(B->fz16[d], nb, [&](int b) { return F[b] == 3 ? blocks(b, 16, 16) * TPB : 0L; });
     make_tab(B->colour_nf[d], nb, [&](int b) { long n = H[b].lev[d].n; return F[b] == 0 ? n * n * n / 2 : 0L; });
     if (d < (int)B->colour32nf.size()) smooth32_tab(B, d);
 }
@@ -1640,11 +1643,13 @@ void batch_smooth32(gr_batch B, int kind, int d, int nu)
     hipStream_t s = B->stream;
     const OpConst oc = opc(B);
     const bool formed = d < B->maxdepth;
-    const bool fused = formed && nu % 2 == 0 && (B->fz[d].total() > 0 || B->fz64[d].total() > 0);
+    const bool fused =
+        formed && nu % 2 == 0 && (B->fz[d].total() > 0 || B->fz64[d].total() > 0 || B->fz16[d].total() > 0);
     const Tab &TC = fused ? B->colour32nf[d] : B->colour32[d];
     for (int it = 0; it < nu; ++it) {
         if (fused && B->fz[d].total()) launch_kb32_fused<32, 16>(s, kind, B->fz[d], B->D, d, it, oc);
         if (fused && B->fz64[d].total()) launch_kb32_fused<64, 16>(s, kind, B->fz64[d], B->D, d, it, oc);
+        if (fused && B->fz16[d].total()) launch_kb32_fused<16, 16>(s, kind, B->fz16[d], B->D, d, it, oc);
         if (TC.total() > 0)
             for (int colour = 0; colour < 2; ++colour)
                 LDISPATCH(kind, kb32_colour, TC.total(), TPB, B->D, TC.dev, d, colour, oc);
@@ -1877,6 +1882,7 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
     B->cdom.resize(maxd);
     B->fz.resize(maxd);
     B->fz64.resize(maxd);
+    B->fz16.resize(maxd);
     B->rr.resize(maxd);
     if (const char *e = std::getenv("GRMG_MARCH")) B->use_march = std::atoi(e) != 0;
     B->D.march = B->use_march ? 1 : 0;
@@ -1904,10 +1910,19 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
         make_tab(B->cdom[d], nb, [&](int b) { long m = grouped(b, d) ? H[b].lev[d + 1].n : 0; return m * m * m; });
     }
     // untuned forms: 32x16 fused sweeps where they tile, else one launch per colour
+    // GRMG_BATCH_FORM = 3: the 16x16 fused form wherever the 32x16 one does not
+    // apply and the side allows it (a test knob; the autotuner chooses otherwise)
+    int extra16 = 0;
+    if (const char *e = std::getenv("GRMG_BATCH_FORM")) extra16 = std::atoi(e) == 3;
     B->form.assign(maxd, std::vector<signed char>(nb, 0));
     for (int d = 0; d < maxd; ++d) {
-        for (int b = 0; b < nb; ++b)
-            B->form[d][b] = !grouped(b, d) ? -1 : (B->use_fused && fusable(b, d) ? 1 : 0);
+        for (int b = 0; b < nb; ++b) {
+            const int n = H[b].lev[d].n;
+            B->form[d][b] = !grouped(b, d) ? -1
+                            : !B->use_fused ? 0
+                            : fusable(b, d) ? 1
+                            : (extra16 && n >= 32 && n % 16 == 0) ? 3 : 0;
+        }
         smooth_tabs(B, d);
     }
     B->coefr.resize(maxc);
@@ -2014,6 +2029,7 @@ int gr_batch_bind(gr_batch B, void *d_ws, size_t bytes, void *stream)
         BHIP(up(B->cdom[d]));
         BHIP(up(B->fz[d]));
         BHIP(up(B->fz64[d]));
+        BHIP(up(B->fz16[d]));
         BHIP(up(B->rr[d]));
         BHIP(up(B->colour_nf[d]));
     }
@@ -2117,7 +2133,7 @@ int gr_batch_autotune(gr_batch B, char *report, size_t report_bytes)
     BHIP(hipEventCreate(&e1));
     auto upload = [&](int d) {
         hipError_t e = hipSuccess;
-        for (Tab *T : {&B->fz[d], &B->fz64[d], &B->colour_nf[d], &B->colour32nf[d]})
+        for (Tab *T : {&B->fz[d], &B->fz64[d], &B->fz16[d], &B->colour_nf[d], &B->colour32nf[d]})
             if (e == hipSuccess)
                 e = hipMemcpyAsync(T->dev, T->start.data(), sizeof(int) * T->start.size(), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s); // the host tables change next
@@ -2131,15 +2147,15 @@ int gr_batch_autotune(gr_batch B, char *report, size_t report_bytes)
         for (int b = 0; b < B->nper; ++b)
             if (base[b] >= 0) {
                 const int n = H[b].lev[d].n;
-                if (n >= 64 && n % 32 == 0 && std::find(sides.begin(), sides.end(), n) == sides.end()) sides.push_back(n);
+                if (n >= 32 && n % 16 == 0 && std::find(sides.begin(), sides.end(), n) == sides.end()) sides.push_back(n);
             }
         std::sort(sides.begin(), sides.end());
         std::vector<signed char> best = base;
         for (int n : sides) {
             int best_form = -1;
             float best_us = 0.f;
-            for (int form = 0; form <= 2 && st == GR_OK; ++form) {
-                if (form == 2 && n % 64) continue;
+            for (int form = 0; form <= 3 && st == GR_OK; ++form) {
+                if ((form == 1 && (n < 64 || n % 32)) || (form == 2 && (n < 64 || n % 64))) continue;
                 auto &F = B->form[d];
                 for (int b = 0; b < B->nper; ++b) F[b] = (base[b] >= 0 && H[b].lev[d].n == n) ? form : -1;
                 for (int b = B->nper; b < B->nbox; ++b) F[b] = -1;
@@ -2169,7 +2185,7 @@ int gr_batch_autotune(gr_batch B, char *report, size_t report_bytes)
             if (st != GR_OK) break;
             for (int b = 0; b < B->nper; ++b)
                 if (base[b] >= 0 && H[b].lev[d].n == n) best[b] = (signed char)best_form;
-            static const char *const names[3] = {"colour", "fused32x16", "fused64x16"};
+            static const char *const names[4] = {"colour", "fused32x16", "fused64x16", "fused16x16"};
             char line[128];
             std::snprintf(line, sizeof line, "depth=%d n=%d form=%s us=%.2f\n", d, n, names[best_form], best_us);
             rep += line;

@@ -191,3 +191,29 @@ def test_batch_per_point_forms_match_marching(precision, monkeypatch):
     for i in range(len(sides)):
         for f in range(10):
             assert maxrel(P.get_field(i, f), Q.get_field(i, f).cpu().numpy()) < 1e-12, (i, f)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_fused16_form_is_bit_identical(precision, monkeypatch):
+    """The fused 16x16 form (forced where the 32x16 one does not apply: the
+    48^3 and 32^3 boxes and the 48^3 and 32^3 levels of the larger ones) gives
+    the per-colour launches' solve bit for bit, in FP64 and in the FP32
+    correction cycles."""
+    sides = [48, 96, 32, 64]
+    print(f"[gpu] batch fused16 {sides} {precision}", flush=True)
+    srcs = [synth._matter_sources(n, 900 + i, 0.3) for i, n in enumerate(sides)]
+    A = grmg.Batch(sides, **PRM)
+    monkeypatch.setenv("GRMG_BATCH_FORM", "3")
+    F = grmg.Batch(sides, **PRM)
+    monkeypatch.delenv("GRMG_BATCH_FORM")
+    for B in (A, F):
+        for i, src in enumerate(srcs):
+            for name, v in zip(("s0", "sx", "sy", "sz", "sm"), src):
+                B.set_field(i, name, v)
+    ra = A.solve(rtol=1e-10, precision=precision)
+    rf = F.solve(rtol=1e-10, precision=precision)
+    assert ra["status"] == rf["status"] == grmg.OK
+    assert ra["cycles"] == rf["cycles"]
+    for i in range(len(sides)):
+        for f in range(10):
+            assert torch.equal(A.get_field(i, f), F.get_field(i, f)), (i, f)
