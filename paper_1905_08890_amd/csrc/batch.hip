@@ -318,10 +318,11 @@ __global__ void __launch_bounds__(TPB) kb_sum(BatchDev D, const int *__restrict_
 // Plane-marching forms (march_tile, 16-plane chunks) for boxes whose level
 // takes 32 x 8 tiles, the one-thread-per-point forms for the others, in one
 // launch: the table gives each box its blocks for whichever form it takes.
-constexpr int kMZ = 16;
+// z-chunk of the plane-marching forms: 32 planes for the large boxes, 16 for the others
+__host__ __device__ inline int mz_chunk(int n) { return n >= 96 ? 32 : 16; }
 
 __host__ __device__ inline bool marchable(int n) { return n >= 64 && n % 32 == 0; }
-__host__ __device__ inline long march_blocks(int n) { return (long)(n / MTX) * (n / MTY) * (n / kMZ); }
+__host__ __device__ inline long march_blocks(int n) { return (long)(n / MTX) * (n / MTY) * (n / mz_chunk(n)); }
 
 template <int KIND>
 __global__ void __launch_bounds__(TPB) kb_norms_m(BatchDev D, const int *__restrict__ tab, int fid, OpConst oc)
@@ -337,9 +338,9 @@ __global__ void __launch_bounds__(TPB) kb_norms_m(BatchDev D, const int *__restr
     if (D.active[b]) {
         const double *phi = X.field[fid];
         if (D.march && marchable(n)) { // the block table gives march_blocks(n) blocks
-            const int nzc = n / kMZ, tiles_y = n / MTY, tile = lb / nzc, zchunk = lb % nzc;
-            march_tile<M_NORMS, KIND, double>(phi, L.f, L.coef, nullptr, n, kMZ, 1.0 / (L.h * L.h), oc, Fb, fs,
-                                              (tile / tiles_y) * MTX, (tile % tiles_y) * MTY, zchunk * kMZ, nullptr,
+            const int mz = mz_chunk(n), nzc = n / mz, tiles_y = n / MTY, tile = lb / nzc, zchunk = lb % nzc;
+            march_tile<M_NORMS, KIND, double>(phi, L.f, L.coef, nullptr, n, mz, 1.0 / (L.h * L.h), oc, Fb, fs,
+                                              (tile / tiles_y) * MTX, (tile % tiles_y) * MTY, zchunk * mz, nullptr,
                                               nullptr, nullptr, nullptr, nullptr, nullptr, v);
         } else {
             const int t = lb * TPB + threadIdx.x;
@@ -372,10 +373,10 @@ __global__ void __launch_bounds__(TPB) kb_rr_m(BatchDev D, const int *__restrict
     const double Fb = d == 0 ? D.scal[b * B_NSCAL + B_FBAR] : 0.0;
     const double fs = d == 0 ? D.scal[b * B_NSCAL + B_FSHIFT] : 0.0;
     if (D.march && marchable(n)) { // the block table gives march_blocks(n) blocks
-        const int nzc = n / kMZ, tiles_y = n / MTY, tile = lb / nzc, zchunk = lb % nzc;
+        const int mz = mz_chunk(n), nzc = n / mz, tiles_y = n / MTY, tile = lb / nzc, zchunk = lb % nzc;
         double v[2];
-        march_tile<M_RESTRICT, KIND, double>(phi, L.f, L.coef, nullptr, n, kMZ, 1.0 / (L.h * L.h), oc, Fb, fs,
-                                             (tile / tiles_y) * MTX, (tile % tiles_y) * MTY, zchunk * kMZ, C.phi,
+        march_tile<M_RESTRICT, KIND, double>(phi, L.f, L.coef, nullptr, n, mz, 1.0 / (L.h * L.h), oc, Fb, fs,
+                                             (tile / tiles_y) * MTX, (tile % tiles_y) * MTY, zchunk * mz, C.phi,
                                              C.phi0, C.tmp, nullptr, nullptr, nullptr, v);
         return;
     }
@@ -692,9 +693,9 @@ __global__ void __launch_bounds__(TPB) kb_ir_m(BatchDev D, const int *__restrict
         const double inv_h2 = 1.0 / (L.h * L.h);
         const double *phi = X.field[fid];
         if (D.march && marchable(n)) { // the block table gives march_blocks(n) blocks
-            const int nzc = n / kMZ, tiles_y = n / MTY, tile = lb / nzc, zchunk = lb % nzc;
-            march_tile<M_IR, KIND, double>(phi, L.f, L.coef, nullptr, n, kMZ, inv_h2, oc, Fb, fs,
-                                           (tile / tiles_y) * MTX, (tile % tiles_y) * MTY, zchunk * kMZ, nullptr,
+            const int mz = mz_chunk(n), nzc = n / mz, tiles_y = n / MTY, tile = lb / nzc, zchunk = lb % nzc;
+            march_tile<M_IR, KIND, double>(phi, L.f, L.coef, nullptr, n, mz, inv_h2, oc, Fb, fs,
+                                           (tile / tiles_y) * MTX, (tile % tiles_y) * MTY, zchunk * mz, nullptr,
                                            nullptr, nullptr, L.b32, L.a32, L.c32, v);
         } else {
             const int t = lb * TPB + threadIdx.x;
@@ -809,10 +810,10 @@ __global__ void __launch_bounds__(TPB) kb32_lin_rr(BatchDev D, const int *__rest
     const float inv_h2 = (float)(1.0 / (V.h * V.h));
     if (D.march && marchable(n)) { // the block table gives march_blocks(n) blocks
         const int lb = blockIdx.x - tab[b];
-        const int nzc = n / kMZ, tiles_y = n / MTY, tile = lb / nzc, zchunk = lb % nzc;
+        const int mz = mz_chunk(n), nzc = n / mz, tiles_y = n / MTY, tile = lb / nzc, zchunk = lb % nzc;
         double v[2];
-        march_tile<M_RESTRICT_LIN, LKIND, float>(V.e, V.b32, V.c32, V.a32, n, kMZ, inv_h2, oc, 0.f, 0.f,
-                                                 (tile / tiles_y) * MTX, (tile % tiles_y) * MTY, zchunk * kMZ, C.b32,
+        march_tile<M_RESTRICT_LIN, LKIND, float>(V.e, V.b32, V.c32, V.a32, n, mz, inv_h2, oc, 0.f, 0.f,
+                                                 (tile / tiles_y) * MTX, (tile % tiles_y) * MTY, zchunk * mz, C.b32,
                                                  C.e, nullptr, nullptr, nullptr, nullptr, v);
         return;
     }
