@@ -222,24 +222,30 @@ def bench_learned(torch, grmg, synth, n):
     """Held-out trajectory (seed 2000, amplitudes 1.0, 1.25, 1.5 cells): per
     step, time to 1e-10 from (i) zero guess FP64, (ii) previous step FP64,
     (iii) previous step mixed, (iv) previous step + network increment, mixed,
-    judged per field by the FP64 residual (network time included), and the
-    same with untrained weights (control)."""
+    judged per field by the FP64 residual (network time included), the same
+    with untrained weights (control), and (v) the true increment restricted to
+    the network's level in place of the network (the ceiling of any guess at
+    that level).  rel_ratio: per field, the held guess's stopping quantity over
+    the previous step's (below 1: the held guess is kept)."""
     from paper_1905_08890_amd import learned
 
     path = os.path.join(ROOT, "paper_1905_08890_amd", "weights", "unet_level1_zeldovich256.npz")
     gs = learned.LearnedGuess(path, n, torch)
     ctl = learned.LearnedGuess(path, n, torch)
     ctl.net.init(4242)
-    res = learned.evaluate(gs, n, [2000], 3, 1.0, torch, control=ctl, exact=False)
+    res = learned.evaluate(gs, n, [2000], 3, 1.0, torch, control=ctl, exact=True)
     summ = learned.summarise(res)
     out = {"workload": f"{n}^3 Zel'dovich trajectory, held-out seed 2000, 2 steps after the first; "
                        f"network on level 1 ({n // 2}^3), weights {os.path.basename(path)}"}
     for k, v in summ.items():
         out[k] = {"ms": round(v["ms"], 3), "cycles": v["cycles"], "fallback_fields": v["fallback"]}
+        if "rel_ratio" in v:
+            out[k]["rel_ratio"] = [float(f"{x:.3g}") for x in v["rel_ratio"]]
     z, l = summ["zero_fp64"]["ms"], summ["learned_mixed"]["ms"]
     out["speedup_learned_mixed_vs_zero_fp64"] = round(z / l, 3)
     out["speedup_learned_mixed_vs_prev_fp64"] = round(summ["prev_fp64"]["ms"] / l, 3)
     out["speedup_prev_mixed_vs_zero_fp64"] = round(z / summ["prev_mixed"]["ms"], 3)
+    out["speedup_exact_mixed_vs_zero_fp64"] = round(z / summ["exact_mixed"]["ms"], 3)
     return out
 
 
