@@ -61,7 +61,7 @@ void launch_rb_sweep(int kind, hipStream_t s, double *phi, const double *f, cons
 // fused out-of-place sweep (both colours, one pass); used where fused_sweep_ok
 struct FusedCfg {
     int min_n = 128;      // smallest level that uses it (smaller levels: one kernel per colour)
-    int tile = 2;         // 0: 64x8 tiles, 1: 32x16, 2: 64x16
+    int tile = 2;         // 0: 64x8 tiles, 1: 32x16, 2: 64x16, 3: 128x8 (n % 128 == 0)
     int xcd_remap = 2;    // 0: z-chunk fastest, 1: XCD-contiguous workgroup order, 2: XCD-contiguous tile regions
     int target_wgs = 256; // about one workgroup per CU (measured best for the FP64 kinds at 256^3)
     int pf = 0;           // operand prefetch depth in planes (1 or 2; 0: per-kind default)

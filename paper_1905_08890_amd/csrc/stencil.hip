@@ -690,7 +690,9 @@ static void launch_fused_any(int kind, hipStream_t s, const T *in, T *out, const
 {
     if (cfg.tile == 1)
         launch_fused_t<T, 32, 16>(kind, s, in, out, f, c1, c2, n, h, oc, fbar, fshift, cfg);
-    else if (cfg.tile == 2)
+    else if (cfg.tile == 3 && n % 128 == 0) // 1 KB contiguous rows; other sizes take 64x16
+        launch_fused_t<T, 128, 8>(kind, s, in, out, f, c1, c2, n, h, oc, fbar, fshift, cfg);
+    else if (cfg.tile >= 2)
         launch_fused_t<T, 64, 16>(kind, s, in, out, f, c1, c2, n, h, oc, fbar, fshift, cfg);
     else
         launch_fused_t<T, 64, 8>(kind, s, in, out, f, c1, c2, n, h, oc, fbar, fshift, cfg);

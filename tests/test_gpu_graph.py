@@ -88,16 +88,16 @@ def test_autotuned_launch_shapes_give_the_same_solve(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("pf,remap", [("3", "0"), ("4", "2"), ("1", "1")])
-def test_forced_launch_shapes_give_the_same_solve(precision, pf, remap, monkeypatch):
-    """Every prefetch depth and workgroup order of the 64x16 fused sweep (FP64
-    and FP32 kinds, fused from 64^3 down) gives the default shapes' solve bit
-    for bit."""
+@pytest.mark.parametrize("tile,pf,remap", [("2", "3", "0"), ("2", "4", "2"), ("2", "1", "1"), ("3", "2", "2")])
+def test_forced_launch_shapes_give_the_same_solve(precision, tile, pf, remap, monkeypatch):
+    """Every prefetch depth and workgroup order of the 64x16 fused sweep, and
+    the 128x8 tile (FP64 and FP32 kinds, fused from 64^3 down; 128x8 where the
+    side allows it), give the default shapes' solve bit for bit."""
     n = 128
-    print(f"[gpu] forced shapes n={n} {precision} pf={pf} remap={remap}", flush=True)
+    print(f"[gpu] forced shapes n={n} {precision} tile={tile} pf={pf} remap={remap}", flush=True)
     a = grmg.Grid(n, **PRM)
     monkeypatch.setenv("GRMG_FUSED_MIN", "64")
-    monkeypatch.setenv("GRMG_FUSED_TILE", "2")
+    monkeypatch.setenv("GRMG_FUSED_TILE", tile)
     monkeypatch.setenv("GRMG_FUSED_PF", pf)
     monkeypatch.setenv("GRMG_XCD_REMAP", remap)
     b = grmg.Grid(n, **PRM)

@@ -56,18 +56,20 @@ def random_problem(kind, n, seed):
 FUSED_MODES = {  # (tile: 0 64x8, 1 32x16, 2 64x16; prefetch depth; workgroup order)
     "fused": ("0", "0", "0"), "fused32x16": ("1", "0", "0"), "fused64x16": ("2", "0", "0"),
     "fused64x16pf3": ("2", "3", "0"), "fused64x16pf4": ("2", "4", "0"), "fused64x16xcd": ("2", "2", "2"),
+    "fused128x8": ("3", "0", "0"), "fused128x8xcd": ("3", "2", "2"),
 }
 
 
 @pytest.mark.parametrize("kind", list(KINDS))
 @pytest.mark.parametrize("n,mode", [(24, "split"), (40, "split"), (64, "split"), (64, "fused"),
                                     (128, "fused"), (128, "fused32x16"), (128, "fused64x16"),
-                                    (128, "fused64x16pf3"), (128, "fused64x16pf4"), (128, "fused64x16xcd")])
+                                    (128, "fused64x16pf3"), (128, "fused64x16pf4"), (128, "fused64x16xcd"),
+                                    (128, "fused128x8"), (128, "fused128x8xcd")])
 def test_sweep_matches_oracle(kind, n, mode, monkeypatch):
     """3 sweeps (odd: the out-of-place fused path ends with a copy back), with
-    the colour-split kernels and with the fused tile kernel (64x8, 32x16 and
-    64x16 tiles, several z-chunks, prefetch depths 1 to 4, both workgroup
-    orders)."""
+    the colour-split kernels and with the fused tile kernel (64x8, 32x16,
+    64x16 and 128x8 tiles, several z-chunks, prefetch depths 1 to 4, all
+    workgroup orders)."""
     monkeypatch.setenv("GRMG_SMOOTHER", "split" if mode == "split" else "fused")
     tile, pf, remap = FUSED_MODES.get(mode, ("0", "0", "0"))
     monkeypatch.setenv("GRMG_FUSED_TILE", tile)
