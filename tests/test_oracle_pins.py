@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle as O
-from closed_forms import (apply_symbol, centres, dcen_symbol, helmholtz_fft, lap_symbol, maxrel,
+from closed_forms import (apply_symbol, centres, dcen_symbol, helmholtz_fft, maxrel,
                           roll_lap)
 from paper_1905_08890_amd import synth
 
