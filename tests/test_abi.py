@@ -101,3 +101,16 @@ def test_batch_with_patches_host_side():
     extra = sizes[1] - sizes[0]
     assert extra >= 8 * (10 * 26 ** 3 + 19 * 24 ** 3)
     assert extra < 8 * (10 * 26 ** 3 + 19 * 24 ** 3 + 5 * 14 ** 3 + 5 * 8 ** 3 + 5 * 5 ** 3) + 64 * 1024
+
+
+def test_bench_runs_on_one_gpu_only():
+    """The benchmark refuses a multi-GPU run before touching a device."""
+    import subprocess
+    import sys
+    from pathlib import Path
+
+    root = Path(__file__).resolve().parents[1]
+    r = subprocess.run([sys.executable, str(root / "bench.py"), "--gpus", "2", "--steps", "1"], cwd=root,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "exactly one GPU" in (r.stdout + r.stderr)
