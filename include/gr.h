@@ -214,11 +214,14 @@ int gr_set_guess(gr_grid g, int level, int count, const int *fields, const doubl
                  int flags);
 
 /* Autotuner of the fused red-black sweep (sec. 4.3.1 smoother): for every
- * level that uses it and each of the six operator kinds (FP64 Poisson,
- * Hamiltonian, CMC; their FP32 linearised forms), times every candidate launch
- * configuration (tile 32x16 or 64x8, 512/1024/2048 workgroups, operand
- * prefetch 1 or 2 planes) on workspace scratch and keeps the fastest for this
- * grid; results are cached per process by (n, kind).  Results of the sweeps
+ * level the fused sweep can tile (n >= 64, n % 64 == 0) and each of the six
+ * operator kinds (FP64 Poisson, Hamiltonian, CMC; their FP32 linearised
+ * forms), times every candidate launch configuration on workspace scratch:
+ * tile 64x8, 32x16, 64x16 or (n % 128 == 0) 128x8; a target of 256, 512,
+ * 1024 or 2048 workgroups; operand prefetch 1 or 2 planes (1 to 4 for the
+ * 64x16 tile); and one launch per colour instead of the fused sweep.  It
+ * keeps the fastest for this grid; results are cached per process by
+ * (n, kind).  Results of the sweeps
  * do not depend on the configuration.  Writes one line per (level, kind) to
  * report (may be NULL).  Must not overlap a deposit on the same grid (it uses
  * the deposit's scratch).  Errors: GR_ESTATE if unbound, GR_EDEVICE. */
@@ -305,11 +308,13 @@ int gr_batch_get_field(gr_batch b, int item, int field, void *d_dst, int dtype);
  * summed over the fields).  Returns the first non-OK box status. */
 int gr_batch_solve(gr_batch b, const gr_solve_opts *opts, int *cycles, double *rel_res, double *item_seconds);
 /* Tunes how each level of the periodic boxes is smoothed: for every depth
- * handled by grouped launches and every box side there with n >= 64 and
- * n % 32 == 0 it times one launch per colour, fused 32x16 tiles and (n % 64
- * == 0) fused 64x16 tiles on that side's boxes, and keeps the fastest.  All
- * forms compute the same bits.  Uses field b of the boxes as scratch and
- * restores it; drops the captured cycle graphs.  Writes one line per (depth,
+ * handled by grouped launches and every box side there with n >= 32 and
+ * n % 16 == 0 it times one launch per colour, fused 16x16 tiles, and, where
+ * the side allows, fused 32x16 tiles (n >= 64, n % 32 == 0) and fused 64x16
+ * tiles (n >= 64, n % 64 == 0) on that side's boxes, and keeps the fastest.
+ * All forms compute the same bits.  Uses field b of the boxes as scratch and
+ * restores it; drops every captured cycle graph (FP64, mixed precision and
+ * patches).  Writes one line per (depth,
  * side) to `report` (may be NULL).  Errors: GR_ESTATE if unbound. */
 int gr_batch_autotune(gr_batch b, char *report, size_t report_bytes);
 /* Low level, for checks of the boundary values: writes the boundary values of

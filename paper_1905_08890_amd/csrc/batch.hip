@@ -2202,10 +2202,12 @@ int gr_batch_autotune(gr_batch B, char *report, size_t report_bytes)
     (void)hipEventDestroy(e1);
     for (int b = 0; b < B->nper; ++b) launch_copy(s, H[b].field[GR_BB], H[b].fB[0], (long)H[b].lev[0].n * H[b].lev[0].n * H[b].lev[0].n);
     BLAUNCH();
-    for (int f = 0; f < 10; ++f) // captured cycles hold the old launch shapes
-        if (B->graph[f]) {
-            (void)hipGraphExecDestroy(B->graph[f]);
-            B->graph[f] = nullptr;
+    // every captured cycle (boxes, patches, mixed-precision boxes) holds the old
+    // launch shapes and tables
+    for (auto &ge : B->graph)
+        if (ge) {
+            (void)hipGraphExecDestroy(ge);
+            ge = nullptr;
         }
     B->tune_report = rep;
     if (report && report_bytes) std::snprintf(report, report_bytes, "%s", rep.c_str());
@@ -2229,6 +2231,7 @@ int gr_batch_debug_boundary(gr_batch B, int item, int field, int level, double *
 
 int gr_batch_solve(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_res, double *item_seconds)
 {
+    b_err.clear(); // a message left by an earlier call must not be reported for this one
     if (!B || !o) return bfail(GR_EINVAL, "null argument");
     if (!B->bound) return bfail(GR_ESTATE, "batch not bound");
     if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 64 || o->nu2 > 64 || o->max_cycles < 0 || o->max_cycles > 100000)

@@ -1028,6 +1028,7 @@ int gr_get_field(gr_grid g, int field, void *d_dst, int dtype)
 
 int gr_solve_equation(gr_grid g, int kind, int field, const gr_solve_opts *opts, gr_solve_report *rep)
 {
+    g_err.clear();
     CHK(check_bound(g));
     CHK(check_opts(opts));
     if (kind < 0 || kind > 2) return fail(GR_EINVAL, "bad kind %d", kind);
@@ -1057,6 +1058,7 @@ int gr_solve_equation(gr_grid g, int kind, int field, const gr_solve_opts *opts,
 
 int gr_solve_constraints(gr_grid g, const gr_solve_opts *opts, gr_solve_report *rep)
 {
+    g_err.clear(); // a message left by an earlier call must not be reported for this one
     CHK(check_bound(g));
     CHK(check_opts(opts));
     WorkScope ws(g);

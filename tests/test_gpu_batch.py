@@ -121,6 +121,10 @@ def test_batch_autotune_keeps_the_solve_bit_identical():
         for i, src in enumerate(srcs):
             for name, v in zip(("s0", "sx", "sy", "sz", "sm"), src):
                 B.set_field(i, name, v)
+    # a mixed-precision solve before tuning captures the mixed cycle graphs,
+    # which the tuner must drop together with the FP64 ones
+    rm0 = T.solve(rtol=1e-10, precision=grmg.MIXED)
+    assert rm0["status"] == grmg.OK
     b_before = [T.get_field(i, "b").clone() for i in range(len(sides))]
     rep = T.autotune()
     lines = [ln for ln in rep.splitlines() if ln.startswith("depth=")]
@@ -134,6 +138,13 @@ def test_batch_autotune_keeps_the_solve_bit_identical():
     for i in range(len(sides)):
         for f in range(10):
             assert torch.equal(A.get_field(i, f), T.get_field(i, f)), (i, f)
+    ma = A.solve(rtol=1e-10, precision=grmg.MIXED)
+    mt = T.solve(rtol=1e-10, precision=grmg.MIXED)
+    assert ma["status"] == mt["status"] == grmg.OK
+    assert ma["cycles"] == mt["cycles"]
+    for i in range(len(sides)):
+        for f in range(10):
+            assert torch.equal(A.get_field(i, f), T.get_field(i, f)), ("mixed", i, f)
 
 
 def test_batch_mixed_precision_matches_fp64():
