@@ -186,6 +186,28 @@ int gr_solve_constraints(gr_grid g, const gr_solve_opts *opts, gr_solve_report *
 int gr_solve_equation(gr_grid g, int kind, int field, const gr_solve_opts *opts,
                       gr_solve_report *host_report);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, serving loops, harnesses that forbid allocation): the solve of
+ * gr_solve_equation without a grid handle or workspace.  Solves one equation
+ * of `kind` on the periodic unit box of n^3 cells (h = 1/n) for d_phi, with
+ * fine source d_f and coefficient d_coef (A_ijA^ij for the Hamiltonian, m^2
+ * for CMC; ignored, may be NULL, for Poisson), all n^3 float64 device arrays
+ * owned by the caller (d_phi: guess in with GR_GUESS_CURRENT, solution out).
+ * Same equations, readings, kernels and results as gr_solve_equation on a grid
+ * of side n (one-launch-per-colour smoothing, the library's default launch
+ * shapes, no graph replay), enqueued on hip_stream (NULL = null stream),
+ * synchronising it once per cycle and before returning.  Fills cycles[0],
+ * rel_res[0] and fallback of the report.
+ * Device memory: none is allocated.  The level hierarchy lives in a static
+ * 16 MiB device array of the library (one per GPU, held until the process
+ * ends), which limits n to even values from 2 to 64; larger n, odd n, a
+ * missing coefficient, GR_GUESS_CHECKED or bad options give GR_EINVAL.  Every
+ * call on a GPU shares that GPU's array, clears it at its start and leaves
+ * its contents behind; calls from several host threads of one process are
+ * serialised by a lock (overlapping calls would otherwise race on the array). */
+int gr_solve_equation_static(int n, const gr_params *prm, int kind, const double *d_f, const double *d_coef,
+                             double *d_phi, const gr_solve_opts *opts, void *hip_stream, gr_solve_report *rep);
+
 /* Learned-guess support (the network itself is gr_unet_*).  gr_features: for
  * each of `count` field ids (solved fields, sources, GR_AA), restrict it to
  * multigrid level `level` (mean of the 8 children, applied level by level;

@@ -810,6 +810,29 @@ double *slot_ptr(gr_grid g, int field)
 
 } // namespace
 
+// ================================================ allocation-free single solve
+//
+// Scratch of gr_solve_equation_static: one file-scope device array per GPU
+// (each device holds its own copy at its own address) that carries the level
+// hierarchy of one solver-only grid of side <= kStaticMaxN.  Host code never
+// passes the array's name to a kernel: its device address is taken once per
+// device with hipGetSymbolAddress and kept in StaticDev::ptr.
+
+namespace {
+constexpr size_t kStaticScratchBytes = size_t(16) << 20; // levels of a 64^3 grid, FP64 and FP32
+constexpr int kStaticMaxN = 64;
+constexpr int kStaticMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+struct StaticDev {
+    std::mutex mu;         // serialises the calls on one device within the process
+    char *ptr = nullptr;   // device address of `scratch` on this device
+    gr_grid_s grid;        // host-side description carved over the scratch
+};
+StaticDev g_static[kStaticMaxDevices];
+} // namespace
+
 // ===================================================================== ABI
 
 namespace {
@@ -1045,6 +1068,92 @@ int gr_solve_equation(gr_grid g, int kind, int field, const gr_solve_opts *opts,
         hipError_t e = hipStreamSynchronize(g->stream);
         if (e != hipSuccess) st = fail(GR_EDEVICE, "sync: %s", hipGetErrorString(e));
     }
+    if (rep) {
+        std::memset(rep, 0, sizeof *rep);
+        rep->status = st;
+        rep->cycles[0] = cyc;
+        rep->rel_res[0] = rel;
+        rep->fallback = fb;
+        rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return st;
+}
+
+int gr_solve_equation_static(int n, const gr_params *prm, int kind, const double *d_f, const double *d_coef,
+                             double *d_phi, const gr_solve_opts *opts, void *hip_stream, gr_solve_report *rep)
+{
+    g_err.clear();
+    if (!prm || !d_f || !d_phi || !opts) return fail(GR_EINVAL, "null argument");
+    if (kind < 0 || kind > 2) return fail(GR_EINVAL, "bad kind %d", kind);
+    if (kind != GR_KIND_POISSON && !d_coef) return fail(GR_EINVAL, "kind %d needs a coefficient array", kind);
+    if (n < 2 || (n & 1) || n > kStaticMaxN)
+        return fail(GR_EINVAL, "n = %d: the allocation-free solve takes even n from 2 to %d (%zu-byte static scratch)",
+                    n, kStaticMaxN, kStaticScratchBytes);
+    if (!(prm->a > 0.0) || !(prm->c_tilde > 0.0) || !std::isfinite(prm->omega_m))
+        return fail(GR_EINVAL, "a and c_tilde must be positive");
+    CHK(check_opts(opts));
+    if (opts->guess == GR_GUESS_CHECKED) return fail(GR_EINVAL, "no saved alternative guess here: use ZERO or CURRENT");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kStaticMaxDevices) return fail(GR_EINVAL, "device %d beyond %d", dev, kStaticMaxDevices);
+    StaticDev &S = g_static[dev];
+    std::lock_guard<std::mutex> lock(S.mu);
+    if (!S.ptr) { // once per device, with that device current
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(GR_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        S.ptr = static_cast<char *>(p);
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    // a solver-only grid with the library's default launch choices, no
+    // private stream and no captured graphs (instantiating one allocates)
+    gr_grid g = &S.grid;
+    g->solver_only = true;
+    g->n = n;
+    g->h = 1.0 / n;
+    g->prm = *prm;
+    g->nlev = num_levels(n);
+    for (int l = 0; l < kMaxLevels; ++l) g->lev[l] = Level{};
+    for (int l = 0; l < g->nlev; ++l) {
+        g->lev[l].n = n >> l;
+        g->lev[l].h = g->h * (double)(1 << l);
+        g->lev[l].N = (long)g->lev[l].n * g->lev[l].n * g->lev[l].n;
+    }
+    g->fused = true;
+    g->fcfg = FusedCfg{};
+    std::memset(g->tuned_ok, 0, sizeof g->tuned_ok);
+    std::memset(g->tuned_split, 0, sizeof g->tuned_split);
+    g->coarse_n = 8;
+    g->coarse_n32 = 8;
+    g->skew = 0;
+    g->stall_ratio = 0.5;
+    g->use_graph = false;
+    g->timing = false;
+    g->sub[0] = g->sub[1] = nullptr;
+    const size_t need = layout(g, nullptr);
+    if (need > kStaticScratchBytes)
+        return fail(GR_EINVAL, "n = %d needs %zu bytes of scratch, more than %zu", n, need, kStaticScratchBytes);
+    layout(g, S.ptr);
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    g->user_stream = g->stream = s;
+    g->work = nullptr;
+    g->bound = true;
+    // the array keeps the previous call's contents: start from zeros, as a bind does
+    launch_fill(s, reinterpret_cast<double *>(S.ptr), (long)(need / sizeof(double)), 0.0);
+    const long N = g->N();
+    launch_copy(s, g->lev[0].f, d_f, N);
+    if (kind != GR_KIND_POISSON) launch_copy(s, g->lev[0].coef, d_coef, N);
+    if (opts->guess == GR_GUESS_ZERO) launch_fill(s, d_phi, N, 0.0);
+    LAUNCHCHK();
+    int cyc = 0, fb = 0;
+    double rel = 0.0;
+    int st = solve_field(g, kind, d_phi, *opts, &cyc, &rel, &fb);
+    if (st != GR_EDEVICE) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = fail(GR_EDEVICE, "sync: %s", hipGetErrorString(e));
+    }
+    g->bound = false;
     if (rep) {
         std::memset(rep, 0, sizeof *rep);
         rep->status = st;

@@ -31,7 +31,8 @@ FIELD_IDS.update(dict(s0=S0, sx=SX, sy=SY, sz=SZ, sm=SM, AA=AA, Phi=PHI, alpha=A
                       beta_x=BETAX, beta_y=BETAY, beta_z=BETAZ, rhs=RHS, coef=COEF))
 
 EXPORTS = ("gr_default_opts", "gr_create_grid", "gr_workspace_bytes", "gr_bind", "gr_deposit_sources",
-           "gr_set_field", "gr_get_field", "gr_solve_constraints", "gr_solve_equation", "gr_debug_sweep",
+           "gr_set_field", "gr_get_field", "gr_solve_constraints", "gr_solve_equation", "gr_solve_equation_static",
+           "gr_debug_sweep",
            "gr_debug_residual", "gr_destroy_grid", "gr_last_error", "gr_features", "gr_set_guess", "gr_autotune", "gr_sweep_timing", "gr_create_batch", "gr_create_batch_patches",
            "gr_batch_debug_boundary", "gr_batch_autotune", "gr_batch_workspace_bytes",
            "gr_batch_bind", "gr_batch_set_field", "gr_batch_get_field", "gr_batch_solve", "gr_destroy_batch",
@@ -100,6 +101,8 @@ def load_library(path: str = LIB_PATH):
         "gr_get_field": [vp, C.c_int, vp, C.c_int],
         "gr_solve_constraints": [vp, C.POINTER(GrSolveOpts), C.POINTER(GrSolveReport)],
         "gr_solve_equation": [vp, C.c_int, C.c_int, C.POINTER(GrSolveOpts), C.POINTER(GrSolveReport)],
+        "gr_solve_equation_static": [C.c_int, C.POINTER(GrParams), C.c_int, vp, vp, vp, C.POINTER(GrSolveOpts), vp,
+                                     C.POINTER(GrSolveReport)],
         "gr_debug_sweep": [vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int],
         "gr_debug_residual": [vp, C.c_int, C.c_int, C.c_double, C.c_double, vp],
         "gr_destroy_grid": [vp],
@@ -222,6 +225,17 @@ def solve_constraints(g: int, opts: GrSolveOpts, allow=(OK,)) -> GrSolveReport:
 def solve_equation(g: int, kind: int, field: int, opts: GrSolveOpts, allow=(OK,)) -> GrSolveReport:
     r = GrSolveReport()
     _check(load_library().gr_solve_equation(g, kind, field, C.byref(opts), C.byref(r)), allow)
+    return r
+
+
+def solve_equation_static(n: int, a: float, omega_m: float, c_tilde: float, kind: int, f, coef, phi, stream: int,
+                          opts: GrSolveOpts, allow=(OK,)) -> GrSolveReport:
+    """Allocation-free solve of one equation: f, coef (may be None for
+    Poisson) and phi are caller-owned float64 device tensors of n^3 values."""
+    r = GrSolveReport()
+    _check(load_library().gr_solve_equation_static(n, C.byref(GrParams(a, omega_m, c_tilde)), kind, _ptr(f),
+                                                   _ptr(coef) if coef is not None else None, _ptr(phi),
+                                                   C.byref(opts), stream, C.byref(r)), allow)
     return r
 
 
