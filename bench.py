@@ -319,6 +319,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload (96 boxes + 32 patches)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess trajectory")
     ap.add_argument("--batch-only", action="store_true", help="only the batched workload (96 boxes + 32 patches)")
+    ap.add_argument("--step-only", choices=("fp64", "mixed", "both"),
+                    help="only the 256^3 step(s) of that precision: autotune, warm-up, --steps timed steps "
+                         "(for kernel traces and counters)")
     ap.add_argument("--smoother-only", action="store_true",
                     help="only the finest-level sweeps and a copy of known size (for hardware counters)")
     args = ap.parse_args()
@@ -364,6 +367,15 @@ def main():
             rep = step(precision)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / args.steps, rep
+
+    if args.step_only:
+        for prec in (("fp64", "mixed") if args.step_only == "both" else (args.step_only,)):
+            dt_, rep_ = timed(prec)
+            log(f"{prec}: cycles {rep_['cycles']}, fallback {rep_['fallback']}, {dt_ * 1e3:.3f} ms/step")
+            print(json.dumps({"step_only": prec, "n": n, "ms_per_step": round(dt_ * 1e3, 3),
+                              "cycles": rep_["cycles"], "status": rep_["status"]}), flush=True)
+        g.close()
+        return
 
     log(f"plain FP64: warmup {args.warmup}, timing {args.steps} steps")
     dt64, rep64 = timed("fp64")

@@ -25,7 +25,9 @@
  *   - Device memory belongs to the caller.  gr_workspace_bytes() says how much
  *     one grid needs; the caller allocates it (e.g. a torch uint8 tensor) and
  *     hands it over with gr_bind().  After gr_bind() the library never
- *     allocates device memory.  The workspace must outlive the grid handle.
+ *     allocates device memory (gr_bind itself creates the grid's private
+ *     streams and events and 16 bytes of pinned host memory per hierarchy for
+ *     the per-cycle norm read-back).  The workspace must outlive the handle.
  *   - Arrays are float64 (or float32 where a dtype argument says so),
  *     C order [z][y][x] with x fastest, n^3 elements, device pointers.
  *   - All work is enqueued on the stream given to gr_bind() (a hipStream_t;

@@ -11,7 +11,7 @@ namespace grmg {
 
 constexpr int kMaxLevels = 12;
 constexpr int kCoarseSweeps = 32;   // red-black sweeps at the coarsest level
-constexpr int kReduceBlocks = 1024; // partial sums per reduction (fixed => deterministic)
+constexpr int kReduceBlocks = 4096; // partial-sum slots per reduction (the grid for a size is fixed => deterministic)
 constexpr int kReduceThreads = 256;
 
 // Device scalar slots (doubles) in the workspace.

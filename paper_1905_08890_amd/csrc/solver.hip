@@ -102,6 +102,10 @@ struct gr_grid_s {
     hipStream_t user_stream = nullptr;
     hipStream_t work = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // per-cycle read-back of the two stopping norms: pinned host slots and an
+    // event the host spins on (set up at bind; absent on the static grid)
+    double *h_norms = nullptr;
+    hipEvent_t ev_norms = nullptr;
     bool use_graph = true;
     struct GraphEntry {
         int prec, kind, nu1, nu2;
@@ -134,6 +138,8 @@ struct gr_grid_s {
         for (auto e : ev_free) (void)hipEventDestroy(e);
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
+        if (ev_norms) (void)hipEventDestroy(ev_norms);
+        if (h_norms) (void)hipHostFree(h_norms);
         if (work) (void)hipStreamDestroy(work);
     }
 
@@ -224,6 +230,28 @@ int pin_mean(gr_grid g, double *phi, long N)
     CHK(reduce_mean(g, phi, nullptr, N, g->scal + S_MEAN));
     launch_sub_scalar(g->stream, phi, N, g->scal + S_MEAN);
     LAUNCHCHK();
+    return GR_OK;
+}
+
+// Reads the sums of eps^2 and f^2 of the stopping test (slots S_RN, S_FN) to
+// the host once the work queued before it is done.  With the pinned slots of a
+// bound grid the copy lands in page-locked memory and the host spins on an
+// event (no sleeping wait between V-cycles); otherwise it waits on the stream.
+int read_norms(gr_grid g, double out[2])
+{
+    if (g->h_norms && g->ev_norms) {
+        HIPCHK(hipMemcpyAsync(g->h_norms, g->scal + S_RN, 2 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+        HIPCHK(hipEventRecord(g->ev_norms, g->stream));
+        hipError_t e;
+        while ((e = hipEventQuery(g->ev_norms)) == hipErrorNotReady) {
+        }
+        if (e != hipSuccess) return fail(GR_EDEVICE, "norm read-back: %s", hipGetErrorString(e));
+        out[0] = g->h_norms[0];
+        out[1] = g->h_norms[1];
+        return GR_OK;
+    }
+    HIPCHK(hipMemcpyAsync(out, g->scal + S_RN, 2 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
     return GR_OK;
 }
 
@@ -421,10 +449,8 @@ int vcycle_body(gr_grid g, const EqCtx &E, int l)
     launch_coarse_rhs(E.kind, s, C.phi, C.coef, C.tmp, C.n, C.h, E.oc, C.f);
     LAUNCHCHK();
     CHK(vcycle(g, E, l + 1));
-    // coarse correction e = phi^H - R phi (into C.tmp, free once the coarse
-    // source is built), then phi += P e: one coarse array per fine point
-    launch_sub_arrays(s, C.tmp, C.phi, C.phi0, C.N);
-    launch_prolong_add_f64(s, L.phi, L.n, C.tmp);
+    // phi += P e with the coarse correction e = phi^H - R phi formed on the fly
+    launch_prolong_correct(s, L.phi, L.n, C.phi, C.phi0);
     LAUNCHCHK();
     return smooth(g, E, l, E.nu2);
 }
@@ -481,8 +507,7 @@ int solve_one(gr_grid g, int kind, double *phi, const gr_solve_opts &o, int *cyc
     int st = GR_OK;
     for (;;) {
         double hn[2];
-        HIPCHK(hipMemcpyAsync(hn, g->scal + S_RN, sizeof hn, hipMemcpyDeviceToHost, g->stream));
-        HIPCHK(hipStreamSynchronize(g->stream));
+        CHK(read_norms(g, hn));
         const double rn = std::sqrt(hn[0]), fn = std::sqrt(hn[1]);
         rel = rn / (fn > 0.0 ? fn : 1.0);
         if (!std::isfinite(rel)) {
@@ -669,8 +694,7 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
     int st = GR_OK;
     for (;;) {
         double hn[2];
-        HIPCHK(hipMemcpyAsync(hn, g->scal + S_RN, sizeof hn, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
+        CHK(read_norms(g, hn));
         const double rn = std::sqrt(hn[0]), fn = std::sqrt(hn[1]);
         rel = rn / (fn > 0.0 ? fn : 1.0);
         if (!std::isfinite(rel)) {
@@ -745,8 +769,7 @@ int guess_residual(gr_grid g, int kind, double *phi, double *rel_out)
     launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN);
     LAUNCHCHK();
     double hn[2];
-    HIPCHK(hipMemcpyAsync(hn, g->scal + S_RN, sizeof hn, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    CHK(read_norms(g, hn));
     const double rn = std::sqrt(hn[0]), fn = std::sqrt(hn[1]);
     *rel_out = rn / (fn > 0.0 ? fn : 1.0);
     return GR_OK;
@@ -967,6 +990,8 @@ int gr_bind(gr_grid g, void *d_ws, size_t bytes, void *stream)
         HIPCHK(hipStreamCreateWithFlags(&g->work, hipStreamNonBlocking));
         HIPCHK(hipEventCreateWithFlags(&g->ev_in, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&g->ev_out, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&g->ev_norms, hipEventDisableTiming));
+        HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&g->h_norms), 2 * sizeof(double), hipHostMallocDefault));
     }
     for (auto *h : g->sub) {
         if (!h) continue;
@@ -975,6 +1000,8 @@ int gr_bind(gr_grid g, void *d_ws, size_t bytes, void *stream)
             HIPCHK(hipStreamCreateWithFlags(&h->work, hipStreamNonBlocking));
             HIPCHK(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
             HIPCHK(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&h->ev_norms, hipEventDisableTiming));
+            HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&h->h_norms), 2 * sizeof(double), hipHostMallocDefault));
         }
         h->user_stream = g->user_stream;
         h->stream = g->user_stream;
@@ -1131,6 +1158,8 @@ int gr_solve_equation_static(int n, const gr_params *prm, int kind, const double
     g->use_graph = false;
     g->timing = false;
     g->sub[0] = g->sub[1] = nullptr;
+    g->h_norms = nullptr; // read-back waits on the stream (pinned slots would be an allocation)
+    g->ev_norms = nullptr;
     const size_t need = layout(g, nullptr);
     if (need > kStaticScratchBytes)
         return fail(GR_EINVAL, "n = %d needs %zu bytes of scratch, more than %zu", n, need, kStaticScratchBytes);

@@ -201,41 +201,89 @@ __global__ void __launch_bounds__(TPB) k_lin_residual_restrict(const T *__restri
 // Cell-centred trilinear prolongation of the coarse correction, added in
 // place: e = phi_c - phi0_c (FAS) or e = phi_c (correction scheme).  Fine cell
 // 2I takes 3/4 of coarse cell I and 1/4 of I-1, fine cell 2I+1 takes 3/4 of I
-// and 1/4 of I+1 (per axis, periodic).  One thread per coarse cell writes its
-// 8 children (x-pairs as one vector store).
+// and 1/4 of I+1 (per axis, periodic).  One thread per coarse (x, y) column
+// marches a chunk of zc coarse planes: the 3 x 3 neighbourhood of the three
+// coarse planes around the current one stays in registers (one new plane of 9
+// values per step), and the thread writes the 8 children of its coarse cell
+// (x-pairs as one 16-byte read-modify-write).
 template <typename T, bool FAS>
-__global__ void __launch_bounds__(TPB) k_prolong_correct(T *__restrict__ phi_f, int n, const T *__restrict__ phi_c,
-                                                         const T *__restrict__ phi0_c)
+__global__ void __launch_bounds__(TPB) k_prolong_correct(T *__restrict__ phi_f, int n, int zc,
+                                                         const T *__restrict__ phi_c, const T *__restrict__ phi0_c)
 {
     using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
     const int m = n >> 1;
-    GEO_XYZ(m, m)
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    if (x >= m || y >= m) return;
+    const int z0 = blockIdx.z * zc;
+    const int xm = wrapi(x - 1, m), xp = wrapi(x + 1, m);
+    const int ym = wrapi(y - 1, m), yp = wrapi(y + 1, m);
+    const int xs[3] = {xm, x, xp}, ys[3] = {ym, y, yp};
     T e[3][3][3]; // e[dz+1][dy+1][dx+1]
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const long q = lin(wrapi(x + dx, m), wrapi(y + dy, m), wrapi(z + dz, m), m);
-                e[dz + 1][dy + 1][dx + 1] = FAS ? phi_c[q] - phi0_c[q] : phi_c[q];
+    auto load_plane = [&](T(&pl)[3][3], int zz) {
+        const long zo = (long)wrapi(zz, m) * m;
+        for (int dy = 0; dy < 3; ++dy)
+            for (int dx = 0; dx < 3; ++dx) {
+                const long q = (zo + ys[dy]) * m + xs[dx];
+                pl[dy][dx] = FAS ? phi_c[q] - phi0_c[q] : phi_c[q];
             }
-    for (int cz = 0; cz < 2; ++cz)
-        for (int cy = 0; cy < 2; ++cy) {
-            T v[2];
-            for (int cx = 0; cx < 2; ++cx) {
-                const int sx = cx ? 1 : -1, sy = cy ? 1 : -1, sz = cz ? 1 : -1;
-                T a = 0;
-                for (int c = 0; c < 8; ++c) {
-                    const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
-                    const T w = (ox ? T(0.25) : T(0.75)) * (oy ? T(0.25) : T(0.75)) * (oz ? T(0.25) : T(0.75));
-                    a += w * e[1 + oz * sz][1 + oy * sy][1 + ox * sx];
+    };
+    load_plane(e[0], z0 - 1);
+    load_plane(e[1], z0);
+    for (int z = z0; z < z0 + zc; ++z) {
+        load_plane(e[2], z + 1);
+        for (int cz = 0; cz < 2; ++cz)
+            for (int cy = 0; cy < 2; ++cy) {
+                T v[2];
+                for (int cx = 0; cx < 2; ++cx) {
+                    const int sx = cx ? 1 : -1, sy = cy ? 1 : -1, sz = cz ? 1 : -1;
+                    T a = 0;
+                    for (int c = 0; c < 8; ++c) {
+                        const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+                        const T w = (ox ? T(0.25) : T(0.75)) * (oy ? T(0.25) : T(0.75)) * (oz ? T(0.25) : T(0.75));
+                        a += w * e[1 + oz * sz][1 + oy * sy][1 + ox * sx];
+                    }
+                    v[cx] = a;
                 }
-                v[cx] = a;
+                T2 *dst = reinterpret_cast<T2 *>(phi_f + lin(2 * x, 2 * y + cy, 2 * z + cz, n));
+                T2 old = *dst;
+                old.x += v[0];
+                old.y += v[1];
+                *dst = old;
             }
-            T2 *dst = reinterpret_cast<T2 *>(phi_f + lin(2 * x, 2 * y + cy, 2 * z + cz, n));
-            T2 old = *dst;
-            old.x += v[0];
-            old.y += v[1];
-            *dst = old;
-        }
+        for (int dy = 0; dy < 3; ++dy)
+            for (int dx = 0; dx < 3; ++dx) {
+                e[0][dy][dx] = e[1][dy][dx];
+                e[1][dy][dx] = e[2][dy][dx];
+            }
+    }
+}
+
+// grid of k_prolong_correct for fine side n: coarse columns in 64 x 4 blocks,
+// z-chunks of the largest of 8, 4, 2, 1 planes that divides the coarse side
+// and still leaves at least 128 Ki threads (small levels: parallelism first)
+struct ProlongGeo {
+    dim3 grid, block;
+    int zc;
+};
+inline ProlongGeo prolong_geo(int n)
+{
+    const int m = n / 2;
+    const int bx = m < 64 ? m : 64;
+    int by = 256 / bx;
+    if (by > m) by = m;
+    static const int zmax = [] {
+        const char *e = std::getenv("GRMG_PROLONG_ZC");
+        const int v = e ? std::atoi(e) : 8;
+        return v >= 8 ? 8 : (v >= 4 ? 4 : (v >= 2 ? 2 : 1));
+    }();
+    int zc = zmax;
+    while (zc > 1 && (m % zc != 0 || (long)m * m * (m / zc) < 131072L)) zc /= 2;
+    ProlongGeo g;
+    g.block = dim3(bx, by, 1);
+    g.grid = dim3((m + bx - 1) / bx, (m + by - 1) / by, m / zc);
+    g.zc = zc;
+    return g;
 }
 
 // ----------------------------------------------------------------- reductions
@@ -265,38 +313,111 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NC], double *__restr
     }
 }
 
-__global__ void __launch_bounds__(TPB) k_sum(const double *__restrict__ x, const double *__restrict__ y, long N,
-                                             double *__restrict__ partials)
+// Plain sums over n^3 arrays.  Each thread adds consecutive pairs (one 16-byte
+// load per array) in a grid-stride loop over the pairs when the arrays allow it
+// (N even, 16-byte aligned), else single elements; the number of workgroups
+// (at most kReduceBlocks) depends only on N, so the order of the additions,
+// and the result, is fixed for a given size.  Block 0 zeroes the partial-sum
+// slots of the workgroups not launched.
+inline unsigned reduce_blocks(long N)
 {
-    double v[1] = {0.0};
-    for (long p = (long)blockIdx.x * TPB + threadIdx.x; p < N; p += (long)kReduceBlocks * TPB)
-        v[0] += y ? (x[p] - y[p]) : x[p];
+    long b = (N + 8L * TPB - 1) / (8L * TPB);
+    return (unsigned)(b < 1 ? 1 : (b > kReduceBlocks ? kReduceBlocks : b));
+}
+
+template <int NC>
+__device__ __forceinline__ void zero_unused_partials(double *__restrict__ partials)
+{
+    if (blockIdx.x == 0)
+        for (int b = gridDim.x + threadIdx.x; b < kReduceBlocks; b += blockDim.x * blockDim.y)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) partials[c * kReduceBlocks + b] = 0.0;
+}
+
+// sum of x (pair: 1) or of x - y
+template <typename F>
+__device__ __forceinline__ double sum_pairs(long N, bool pair, F term)
+{
+    double v = 0.0;
+    const long stride = (long)gridDim.x * TPB;
+    if (pair) {
+        for (long q = (long)blockIdx.x * TPB + threadIdx.x; q < N / 2; q += stride) v = term(2 * q, v, true);
+    } else {
+        for (long p = (long)blockIdx.x * TPB + threadIdx.x; p < N; p += stride) v = term(p, v, false);
+    }
+    return v;
+}
+
+__global__ void __launch_bounds__(TPB) k_sum(const double *__restrict__ x, const double *__restrict__ y, long N,
+                                             bool pair, double *__restrict__ partials)
+{
+    double v[1];
+    v[0] = sum_pairs(N, pair, [&](long p, double acc, bool two) {
+        if (two) {
+            const double2 a = *reinterpret_cast<const double2 *>(x + p);
+            if (y) {
+                const double2 b = *reinterpret_cast<const double2 *>(y + p);
+                acc += a.x - b.x;
+                acc += a.y - b.y;
+            } else {
+                acc += a.x;
+                acc += a.y;
+            }
+            return acc;
+        }
+        return acc + (y ? (x[p] - y[p]) : x[p]);
+    });
     block_sum_store<1>(v, partials);
+    zero_unused_partials<1>(partials);
 }
 
 __global__ void __launch_bounds__(TPB) k_sum_prod(const double *__restrict__ x, const double *__restrict__ y,
-                                                  long N, double *__restrict__ partials)
+                                                  long N, bool pair, double *__restrict__ partials)
 {
-    double v[1] = {0.0};
-    for (long p = (long)blockIdx.x * TPB + threadIdx.x; p < N; p += (long)kReduceBlocks * TPB)
-        v[0] += x[p] * y[p];
+    double v[1];
+    v[0] = sum_pairs(N, pair, [&](long p, double acc, bool two) {
+        if (two) {
+            const double2 a = *reinterpret_cast<const double2 *>(x + p);
+            const double2 b = *reinterpret_cast<const double2 *>(y + p);
+            acc += a.x * b.x;
+            acc += a.y * b.y;
+            return acc;
+        }
+        return acc + x[p] * y[p];
+    });
     block_sum_store<1>(v, partials);
+    zero_unused_partials<1>(partials);
 }
 
-// Sum of F = (f - A(chi^6 - 1))/chi + AA chi^-7/4 (Hamiltonian regulariser).
+// F = (f - A(chi^6 - 1))/chi + AA chi^-7/4 (Hamiltonian regulariser) at one point
+__device__ __forceinline__ double ham_F(double psi, double f, double AA, OpConst oc)
+{
+    const double chi = 1.0 - oc.kappa * psi;
+    const double chi2 = chi * chi;
+    const double chi6 = chi2 * chi2 * chi2;
+    const double chim7 = 1.0 / (chi6 * chi);
+    return (f - oc.A * (chi6 - 1.0)) / chi + 0.25 * AA * chim7;
+}
+
+// Sum of F over the grid.
 __global__ void __launch_bounds__(TPB) k_sum_ham_F(const double *__restrict__ psi, const double *__restrict__ f,
-                                                   const double *__restrict__ coef, long N, OpConst oc,
+                                                   const double *__restrict__ coef, long N, OpConst oc, bool pair,
                                                    double *__restrict__ partials)
 {
-    double v[1] = {0.0};
-    for (long p = (long)blockIdx.x * TPB + threadIdx.x; p < N; p += (long)kReduceBlocks * TPB) {
-        const double chi = 1.0 - oc.kappa * psi[p];
-        const double chi2 = chi * chi;
-        const double chi6 = chi2 * chi2 * chi2;
-        const double chim7 = 1.0 / (chi6 * chi);
-        v[0] += (f[p] - oc.A * (chi6 - 1.0)) / chi + 0.25 * coef[p] * chim7;
-    }
+    double v[1];
+    v[0] = sum_pairs(N, pair, [&](long p, double acc, bool two) {
+        if (two) {
+            const double2 a = *reinterpret_cast<const double2 *>(psi + p);
+            const double2 b = *reinterpret_cast<const double2 *>(f + p);
+            const double2 c = *reinterpret_cast<const double2 *>(coef + p);
+            acc += ham_F(a.x, b.x, c.x, oc);
+            acc += ham_F(a.y, b.y, c.y, oc);
+            return acc;
+        }
+        return acc + ham_F(psi[p], f[p], coef[p], oc);
+    });
     block_sum_store<1>(v, partials);
+    zero_unused_partials<1>(partials);
 }
 
 // Sums of eps^2 and (f - fshift)^2 on one level.  Blocks of 64 x 4 threads
@@ -311,7 +432,7 @@ __global__ void __launch_bounds__(TPB) k_res_norms(const double *__restrict__ ph
     const double Fb = *fbar, fs = *fshift;
     double v[2] = {0.0, 0.0};
     const int rows = n * n;
-    for (int r = blockIdx.x * 4 + threadIdx.y; r < rows; r += kReduceBlocks * 4) {
+    for (int r = blockIdx.x * 4 + threadIdx.y; r < rows; r += gridDim.x * 4) {
         const int y = r % n, z = r / n;
         for (int x = threadIdx.x; x < n; x += 64) {
             const long p = lin(x, y, z, n);
@@ -325,6 +446,7 @@ __global__ void __launch_bounds__(TPB) k_res_norms(const double *__restrict__ ph
         }
     }
     block_sum_store<2>(v, partials);
+    zero_unused_partials<2>(partials);
 }
 
 // out[c] = (add ? add[c] : 0) + scale * sum of partials of component c, in a
@@ -377,6 +499,31 @@ __global__ void __launch_bounds__(MNT) k_march(const T *__restrict__ phi, const 
     }
 }
 
+// The same passes on 64 x 8 tiles with x-pairs per thread (march_tile2): levels
+// with n a multiple of 64.
+template <int MODE, int KIND, typename T>
+__global__ void __launch_bounds__(M2NT) k_march2(const T *__restrict__ phi, const T *__restrict__ f,
+                                                 const T *__restrict__ c1, const T *__restrict__ c2, int n, int zc,
+                                                 T inv_h2, OpConst oc, const double *__restrict__ fbar,
+                                                 const double *__restrict__ fshift, double *__restrict__ partials,
+                                                 T *__restrict__ o1, T *__restrict__ o2, T *__restrict__ o3,
+                                                 float *__restrict__ b32, float *__restrict__ a32,
+                                                 float *__restrict__ c32, const float *__restrict__ e32)
+{
+    const int tiles_y = n / M2TY;
+    const int nzc = n / zc;
+    const int tile = blockIdx.x / nzc, zchunk = blockIdx.x % nzc;
+    const T Fb = (MODE == M_RESTRICT_LIN) ? T(0) : T(*fbar);
+    const T fs = (MODE == M_RESTRICT_LIN) ? T(0) : T(*fshift);
+    double v[2] = {0.0, 0.0};
+    march_tile2<MODE, KIND, T>(phi, f, c1, c2, n, zc, inv_h2, oc, Fb, fs, (tile / tiles_y) * M2TX,
+                               (tile % tiles_y) * M2TY, zchunk * zc, o1, o2, o3, b32, a32, c32, v, e32);
+    if constexpr (MODE == M_NORMS || MODE == M_IR || MODE == M_IRU) {
+        block_sum_store<2>(v, partials);
+        zero_unused_partials<2>(partials);
+    }
+}
+
 // ------------------------------------------------- coarse levels, one block
 
 constexpr int CTPB = kCoarseThreads;
@@ -414,7 +561,7 @@ __global__ void __launch_bounds__(TPB) k_ir_residual(const double *__restrict__ 
     const double Fb = *fbar, fs = *fshift;
     double v[2] = {0.0, 0.0};
     const int rows = n * n;
-    for (int r = blockIdx.x * 4 + threadIdx.y; r < rows; r += kReduceBlocks * 4) {
+    for (int r = blockIdx.x * 4 + threadIdx.y; r < rows; r += gridDim.x * 4) {
         const int y = r % n, z = r / n;
         for (int x = threadIdx.x; x < n; x += 64) {
             const long p = lin(x, y, z, n);
@@ -435,6 +582,7 @@ __global__ void __launch_bounds__(TPB) k_ir_residual(const double *__restrict__ 
         }
     }
     block_sum_store<2>(v, partials);
+    zero_unused_partials<2>(partials);
 }
 
 // c = -m2 in FP32 (linearised CMC coefficient; fixed for the whole solve)
@@ -444,11 +592,21 @@ __global__ void k_neg_to_f32(float *__restrict__ d, const double *__restrict__ s
     if (p < N) d[p] = (float)(-s[p]);
 }
 
-__global__ void __launch_bounds__(TPB) k_sum_f32(const float *__restrict__ x, long N, double *__restrict__ partials)
+__global__ void __launch_bounds__(TPB) k_sum_f32(const float *__restrict__ x, long N, bool pair,
+                                                 double *__restrict__ partials)
 {
-    double v[1] = {0.0};
-    for (long p = (long)blockIdx.x * TPB + threadIdx.x; p < N; p += (long)kReduceBlocks * TPB) v[0] += (double)x[p];
+    double v[1];
+    v[0] = sum_pairs(N, pair, [&](long p, double acc, bool two) {
+        if (two) {
+            const float2 a = *reinterpret_cast<const float2 *>(x + p);
+            acc += (double)a.x;
+            acc += (double)a.y;
+            return acc;
+        }
+        return acc + (double)x[p];
+    });
     block_sum_store<1>(v, partials);
+    zero_unused_partials<1>(partials);
 }
 
 // phi += e - <e>: the correction, with the zero-mean pin folded in
@@ -567,6 +725,165 @@ __global__ void k_set_scalar(double *slot, double v)
 }
 
 inline unsigned blocks_for(long count) { return (unsigned)((count + TPB - 1) / TPB); }
+
+// ------------------------------------------------ vectorised elementwise passes
+//
+// Streaming passes over n^3 arrays move four consecutive elements per thread
+// and iteration as 16-byte loads and stores (two double2 or one float4), in a
+// grid-stride loop over at most kEwBlocks workgroups, so that every thread keeps
+// several wide loads in flight.  Launchers take this form when every pointer is
+// 16-byte aligned and fall back to one element per thread otherwise; both forms
+// compute each element by the same expression.
+constexpr unsigned kEwBlocks = 4096;
+
+struct D4 {
+    double2 lo, hi;
+};
+__device__ __forceinline__ D4 ld4(const double *p)
+{
+    const double2 *q = reinterpret_cast<const double2 *>(p);
+    return D4{q[0], q[1]};
+}
+__device__ __forceinline__ void st4(double *p, const D4 &v)
+{
+    double2 *q = reinterpret_cast<double2 *>(p);
+    q[0] = v.lo;
+    q[1] = v.hi;
+}
+__device__ __forceinline__ float4 ldf4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ __forceinline__ void stf4(float *p, const float4 &v) { *reinterpret_cast<float4 *>(p) = v; }
+
+template <class Op>
+__global__ void __launch_bounds__(TPB) k_ew4(long groups, Op op)
+{
+    for (long q = (long)blockIdx.x * TPB + threadIdx.x; q < groups; q += (long)gridDim.x * TPB) op(4 * q);
+}
+
+inline bool al16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// launches op over the first N - N % 4 elements; returns the count done
+template <class Op>
+long launch_ew4(hipStream_t s, long N, Op op)
+{
+    const long groups = N / 4;
+    if (groups <= 0) return 0;
+    long b = (groups + TPB - 1) / TPB;
+    if (b > (long)kEwBlocks) b = kEwBlocks;
+    k_ew4<Op><<<(unsigned)b, TPB, 0, s>>>(groups, op);
+    return 4 * groups;
+}
+
+struct EwFill {
+    double *x;
+    double v;
+    __device__ void operator()(long p) const { st4(x + p, D4{make_double2(v, v), make_double2(v, v)}); }
+};
+struct EwCopy {
+    double *d;
+    const double *a;
+    __device__ void operator()(long p) const { st4(d + p, ld4(a + p)); }
+};
+struct EwSubScalar {
+    double *x;
+    const double *sc;
+    __device__ void operator()(long p) const
+    {
+        const double c = *sc;
+        D4 v = ld4(x + p);
+        v.lo.x -= c;
+        v.lo.y -= c;
+        v.hi.x -= c;
+        v.hi.y -= c;
+        st4(x + p, v);
+    }
+};
+struct EwSubArrays {
+    double *d;
+    const double *a, *b;
+    __device__ void operator()(long p) const
+    {
+        const D4 u = ld4(a + p), w = ld4(b + p);
+        st4(d + p, D4{make_double2(u.lo.x - w.lo.x, u.lo.y - w.lo.y), make_double2(u.hi.x - w.hi.x, u.hi.y - w.hi.y)});
+    }
+};
+struct EwAxpy {
+    double *y;
+    const double *x;
+    __device__ void operator()(long p) const
+    {
+        D4 v = ld4(y + p);
+        const D4 u = ld4(x + p);
+        v.lo.x += u.lo.x;
+        v.lo.y += u.lo.y;
+        v.hi.x += u.hi.x;
+        v.hi.y += u.hi.y;
+        st4(y + p, v);
+    }
+};
+struct EwIrUpdate { // phi += e - <e>
+    double *phi;
+    const float *e;
+    const double *mean;
+    __device__ void operator()(long p) const
+    {
+        const double m = *mean;
+        D4 v = ld4(phi + p);
+        const float4 c = ldf4(e + p);
+        v.lo.x += (double)c.x - m;
+        v.lo.y += (double)c.y - m;
+        v.hi.x += (double)c.z - m;
+        v.hi.y += (double)c.w - m;
+        st4(phi + p, v);
+    }
+};
+struct EwAddF32Out { // d = a + e
+    double *d;
+    const double *a;
+    const float *e;
+    __device__ void operator()(long p) const
+    {
+        const D4 v = ld4(a + p);
+        const float4 c = ldf4(e + p);
+        st4(d + p, D4{make_double2(v.lo.x + (double)c.x, v.lo.y + (double)c.y),
+                      make_double2(v.hi.x + (double)c.z, v.hi.y + (double)c.w)});
+    }
+};
+struct EwFillF32 {
+    float *x;
+    __device__ void operator()(long p) const { stf4(x + p, make_float4(0.f, 0.f, 0.f, 0.f)); }
+};
+struct EwCopyF32 {
+    float *d;
+    const float *a;
+    __device__ void operator()(long p) const { stf4(d + p, ldf4(a + p)); }
+};
+struct EwNegToF32 {
+    float *d;
+    const double *a;
+    __device__ void operator()(long p) const
+    {
+        const D4 v = ld4(a + p);
+        stf4(d + p, make_float4((float)(-v.lo.x), (float)(-v.lo.y), (float)(-v.hi.x), (float)(-v.hi.y)));
+    }
+};
+struct EwF32ToF64 {
+    double *d;
+    const float *a;
+    __device__ void operator()(long p) const
+    {
+        const float4 c = ldf4(a + p);
+        st4(d + p, D4{make_double2((double)c.x, (double)c.y), make_double2((double)c.z, (double)c.w)});
+    }
+};
+struct EwF64ToF32 {
+    float *d;
+    const double *a;
+    __device__ void operator()(long p) const
+    {
+        const D4 v = ld4(a + p);
+        stf4(d + p, make_float4((float)v.lo.x, (float)v.lo.y, (float)v.hi.x, (float)v.hi.y));
+    }
+};
 
 } // namespace
 
@@ -722,6 +1039,47 @@ bool march_ok(int n)
     return on && n >= 64 && n % MTX == 0;
 }
 
+// workgroups of the row-walking norm kernels (4 x-rows each, at most kReduceBlocks)
+unsigned row_blocks(int n)
+{
+    const long b = ((long)n * n + 3) / 4;
+    return (unsigned)(b > kReduceBlocks ? kReduceBlocks : b);
+}
+
+// Workgroup budget of the plane-marching kernels that also reduce (norms,
+// refinement residuals); at most kReduceBlocks.  More workgroups raise the
+// occupancy, shorter z-chunks re-read more halo planes.  GRMG_MARCH_BLOCKS
+// overrides the default.
+long march_norm_blocks()
+{
+    static const long b = [] {
+        long v = 2048;
+        if (const char *e = std::getenv("GRMG_MARCH_BLOCKS")) v = std::atol(e);
+        return v < 64 ? 64L : (v > kReduceBlocks ? (long)kReduceBlocks : v);
+    }();
+    return b;
+}
+
+// the x-pair form serves levels whose side is a multiple of 64 (GRMG_MARCH2=0: off)
+bool march2_ok(int n)
+{
+    static const bool on = [] {
+        const char *e = std::getenv("GRMG_MARCH2");
+        return !(e && std::atoi(e) == 0);
+    }();
+    return on && march_ok(n) && n % M2TX == 0;
+}
+
+int march2_grid(int n, long max_blocks, int *zc_out)
+{
+    const long tiles = (long)(n / M2TX) * (n / M2TY);
+    if (tiles > max_blocks) return 0;
+    int zc = n;
+    while (zc % 4 == 0 && zc / 2 >= 8 && tiles * (n / (zc / 2)) <= max_blocks) zc /= 2;
+    *zc_out = zc;
+    return (int)(tiles * (n / zc));
+}
+
 int march_grid(int n, long max_blocks, int *zc_out)
 {
     const long tiles = (long)(n / MTX) * (n / MTY);
@@ -744,11 +1102,44 @@ int march_grid(int n, long max_blocks, int *zc_out)
         }                                                                                             \
     } while (0)
 
+#define GR_MARCH2_KIND(MODE, T, kind, grid, ...)                                                      \
+    do {                                                                                              \
+        switch (kind) {                                                                               \
+        case GR_KIND_POISSON: k_march2<MODE, GR_KIND_POISSON, T><<<grid, M2NT, 0, s>>>(__VA_ARGS__, nullptr); break; \
+        case GR_KIND_HAMILTONIAN: k_march2<MODE, GR_KIND_HAMILTONIAN, T><<<grid, M2NT, 0, s>>>(__VA_ARGS__, nullptr); break; \
+        case GR_KIND_CMC: k_march2<MODE, GR_KIND_CMC, T><<<grid, M2NT, 0, s>>>(__VA_ARGS__, nullptr); break;          \
+        case K_LIN_POISSON: k_march2<MODE, K_LIN_POISSON, T><<<grid, M2NT, 0, s>>>(__VA_ARGS__, nullptr); break;      \
+        case K_LIN_HAM: k_march2<MODE, K_LIN_HAM, T><<<grid, M2NT, 0, s>>>(__VA_ARGS__, nullptr); break;              \
+        default: k_march2<MODE, K_LIN_CMC, T><<<grid, M2NT, 0, s>>>(__VA_ARGS__, nullptr); break;                     \
+        }                                                                                             \
+    } while (0)
+
 void launch_residual_restrict(int kind, hipStream_t s, const double *phi, const double *f, const double *coef,
                               int n, double h, OpConst oc, const double *fbar, const double *fshift,
                               double *phi_c, double *phi0_c, double *rr_c)
 {
     int zc = 0, grid = 0;
+    if (march2_ok(n) && (grid = march2_grid(n, 4096, &zc)) > 0) {
+        const double ih2 = 1.0 / (h * h);
+        switch (kind) {
+        case GR_KIND_POISSON:
+            k_march2<M_RESTRICT, GR_KIND_POISSON, double><<<grid, M2NT, 0, s>>>(
+                phi, f, coef, nullptr, n, zc, ih2, oc, fbar, fshift, nullptr, phi_c, phi0_c, rr_c, nullptr, nullptr,
+                nullptr, nullptr);
+            break;
+        case GR_KIND_HAMILTONIAN:
+            k_march2<M_RESTRICT, GR_KIND_HAMILTONIAN, double><<<grid, M2NT, 0, s>>>(
+                phi, f, coef, nullptr, n, zc, ih2, oc, fbar, fshift, nullptr, phi_c, phi0_c, rr_c, nullptr, nullptr,
+                nullptr, nullptr);
+            break;
+        default:
+            k_march2<M_RESTRICT, GR_KIND_CMC, double><<<grid, M2NT, 0, s>>>(
+                phi, f, coef, nullptr, n, zc, ih2, oc, fbar, fshift, nullptr, phi_c, phi0_c, rr_c, nullptr, nullptr,
+                nullptr, nullptr);
+            break;
+        }
+        return;
+    }
     if (march_ok(n) && (grid = march_grid(n, 4096, &zc)) > 0) {
         switch (kind) {
         case GR_KIND_POISSON:
@@ -779,6 +1170,11 @@ void launch_lin_residual_restrict_f32(int kind, hipStream_t s, const float *e, c
 {
     const float inv_h2 = float(1.0 / (h * h));
     int zc = 0, grid = 0;
+    if (march2_ok(n) && (grid = march2_grid(n, 4096, &zc)) > 0) {
+        GR_MARCH2_KIND(M_RESTRICT_LIN, float, kind, grid, e, b, c1, c2, n, zc, inv_h2, oc, nullptr, nullptr, nullptr,
+                       b_c, e_c, nullptr, nullptr, nullptr, nullptr);
+        return;
+    }
     if (march_ok(n) && (grid = march_grid(n, 4096, &zc)) > 0) {
         GR_MARCH_KIND(M_RESTRICT_LIN, float, kind, grid, e, b, c1, c2, n, zc, inv_h2, oc, nullptr, nullptr, nullptr,
                       b_c, e_c, nullptr, nullptr, nullptr, nullptr);
@@ -803,25 +1199,26 @@ void launch_residual(int kind, hipStream_t s, const double *phi, const double *f
 
 void launch_prolong_correct(hipStream_t s, double *phi_f, int n, const double *phi_c, const double *phi0_c)
 {
-    const Geo G = geo3(n / 2, n / 2, n / 2);
-    k_prolong_correct<double, true><<<G.grid, G.block, 0, s>>>(phi_f, n, phi_c, phi0_c);
+    const ProlongGeo G = prolong_geo(n);
+    k_prolong_correct<double, true><<<G.grid, G.block, 0, s>>>(phi_f, n, G.zc, phi_c, phi0_c);
 }
 
 void launch_prolong_add_f64(hipStream_t s, double *phi_f, int n, const double *e_c)
 {
-    const Geo G = geo3(n / 2, n / 2, n / 2);
-    k_prolong_correct<double, false><<<G.grid, G.block, 0, s>>>(phi_f, n, e_c, nullptr);
+    const ProlongGeo G = prolong_geo(n);
+    k_prolong_correct<double, false><<<G.grid, G.block, 0, s>>>(phi_f, n, G.zc, e_c, nullptr);
 }
 
 void launch_sub_arrays(hipStream_t s, double *d, const double *a, const double *b, long N)
 {
-    if (N > 0) k_sub_arrays<<<blocks_for(N), TPB, 0, s>>>(d, a, b, N);
+    const long done = al16(d) && al16(a) && al16(b) ? launch_ew4(s, N, EwSubArrays{d, a, b}) : 0;
+    if (N > done) k_sub_arrays<<<blocks_for(N - done), TPB, 0, s>>>(d + done, a + done, b + done, N - done);
 }
 
 void launch_prolong_add_f32(hipStream_t s, float *e_f, int n, const float *e_c)
 {
-    const Geo G = geo3(n / 2, n / 2, n / 2);
-    k_prolong_correct<float, false><<<G.grid, G.block, 0, s>>>(e_f, n, e_c, nullptr);
+    const ProlongGeo G = prolong_geo(n);
+    k_prolong_correct<float, false><<<G.grid, G.block, 0, s>>>(e_f, n, G.zc, e_c, nullptr);
 }
 
 void launch_restrict(hipStream_t s, const double *fine, int n, double *coarse)
@@ -883,7 +1280,24 @@ void launch_ir_residual(int kind, hipStream_t s, const double *phi, const double
                         float *c32, double *partials)
 {
     int zc = 0, grid = 0;
-    if (march_ok(n) && (grid = march_grid(n, kReduceBlocks, &zc)) > 0) {
+    if (march2_ok(n) && (grid = march2_grid(n, march_norm_blocks(), &zc)) > 0) {
+        const double ih2 = 1.0 / (h * h);
+        if (kind == GR_KIND_POISSON)
+            k_march2<M_IR, GR_KIND_POISSON, double><<<grid, M2NT, 0, s>>>(phi, f, coef, nullptr, n, zc, ih2, oc,
+                                                                         fbar, fshift, partials, nullptr, nullptr,
+                                                                         nullptr, b32, a32, c32, nullptr);
+        else if (kind == GR_KIND_HAMILTONIAN)
+            k_march2<M_IR, GR_KIND_HAMILTONIAN, double><<<grid, M2NT, 0, s>>>(phi, f, coef, nullptr, n, zc, ih2, oc,
+                                                                             fbar, fshift, partials, nullptr,
+                                                                             nullptr, nullptr, b32, a32, c32,
+                                                                             nullptr);
+        else
+            k_march2<M_IR, GR_KIND_CMC, double><<<grid, M2NT, 0, s>>>(phi, f, coef, nullptr, n, zc, ih2, oc, fbar,
+                                                                     fshift, partials, nullptr, nullptr, nullptr,
+                                                                     b32, a32, c32, nullptr);
+        return;
+    }
+    if (march_ok(n) && (grid = march_grid(n, march_norm_blocks(), &zc)) > 0) {
         const double ih2 = 1.0 / (h * h);
         if (kind == GR_KIND_POISSON)
             k_march<M_IR, GR_KIND_POISSON, double><<<grid, MNT, 0, s>>>(phi, f, coef, nullptr, n, zc, ih2, oc, fbar,
@@ -900,7 +1314,7 @@ void launch_ir_residual(int kind, hipStream_t s, const double *phi, const double
         return;
     }
     Geo G;
-    G.grid = dim3(kReduceBlocks);
+    G.grid = dim3(row_blocks(n));
     G.block = dim3(64, 4);
     GR_DISPATCH_KIND_G(kind, k_ir_residual, G, phi, f, coef, n, 1.0 / (h * h), oc, fbar, fshift, b32, a32, c32,
                        partials);
@@ -914,59 +1328,88 @@ void launch_ir_update_residual(hipStream_t s, const double *phi, const float *e,
                                double *partials)
 {
     int zc = 0, grid = 0;
-    if (march_ok(n) && (grid = march_grid(n, kReduceBlocks, &zc)) > 0) {
+    if (march2_ok(n) && (grid = march2_grid(n, march_norm_blocks(), &zc)) > 0) {
+        k_march2<M_IRU, GR_KIND_POISSON, double><<<grid, M2NT, 0, s>>>(phi, f, nullptr, nullptr, n, zc,
+                                                                      1.0 / (h * h), oc, fbar, fshift, partials,
+                                                                      phi_out, nullptr, nullptr, b32, nullptr,
+                                                                      nullptr, e);
+        return;
+    }
+    if (march_ok(n) && (grid = march_grid(n, march_norm_blocks(), &zc)) > 0) {
         k_march<M_IRU, GR_KIND_POISSON, double><<<grid, MNT, 0, s>>>(phi, f, nullptr, nullptr, n, zc, 1.0 / (h * h),
                                                                     oc, fbar, fshift, partials, phi_out, nullptr,
                                                                     nullptr, b32, nullptr, nullptr, e);
         return;
     }
     const long N = (long)n * n * n;
-    k_add_f32_out<<<blocks_for(N), TPB, 0, s>>>(phi_out, phi, e, N);
+    const long done = al16(phi_out) && al16(phi) && al16(e) ? launch_ew4(s, N, EwAddF32Out{phi_out, phi, e}) : 0;
+    if (N > done) k_add_f32_out<<<blocks_for(N - done), TPB, 0, s>>>(phi_out + done, phi + done, e + done, N - done);
     launch_ir_residual(GR_KIND_POISSON, s, phi_out, f, nullptr, n, h, oc, fbar, fshift, b32, nullptr, nullptr,
                        partials);
 }
 
 void launch_neg_to_f32(hipStream_t s, float *dst, const double *src, long N)
 {
-    if (N > 0) k_neg_to_f32<<<blocks_for(N), TPB, 0, s>>>(dst, src, N);
+    const long done = al16(dst) && al16(src) ? launch_ew4(s, N, EwNegToF32{dst, src}) : 0;
+    if (N > done) k_neg_to_f32<<<blocks_for(N - done), TPB, 0, s>>>(dst + done, src + done, N - done);
 }
 
 void launch_sum_f32(hipStream_t s, const float *x, long N, double *partials)
 {
-    k_sum_f32<<<kReduceBlocks, TPB, 0, s>>>(x, N, partials);
+    k_sum_f32<<<reduce_blocks(N), TPB, 0, s>>>(x, N, N % 2 == 0 && (reinterpret_cast<uintptr_t>(x) & 7) == 0,
+                                               partials);
 }
 
 void launch_ir_update(hipStream_t s, double *phi, const float *e, long N, const double *mean)
 {
-    if (N > 0) k_ir_update<<<blocks_for(N), TPB, 0, s>>>(phi, e, N, mean);
+    const long done = al16(phi) && al16(e) ? launch_ew4(s, N, EwIrUpdate{phi, e, mean}) : 0;
+    if (N > done) k_ir_update<<<blocks_for(N - done), TPB, 0, s>>>(phi + done, e + done, N - done, mean);
 }
 
 void launch_fill_f32(hipStream_t s, float *x, long N)
 {
-    if (N > 0) k_fill_f32<<<blocks_for(N), TPB, 0, s>>>(x, N);
+    const long done = al16(x) ? launch_ew4(s, N, EwFillF32{x}) : 0;
+    if (N > done) k_fill_f32<<<blocks_for(N - done), TPB, 0, s>>>(x + done, N - done);
 }
 
 void launch_sum(hipStream_t s, const double *x, const double *y, long N, double *partials)
 {
-    k_sum<<<kReduceBlocks, TPB, 0, s>>>(x, y, N, partials);
+    k_sum<<<reduce_blocks(N), TPB, 0, s>>>(x, y, N, N % 2 == 0 && al16(x) && (!y || al16(y)), partials);
 }
 
 void launch_sum_prod(hipStream_t s, const double *x, const double *y, long N, double *partials)
 {
-    k_sum_prod<<<kReduceBlocks, TPB, 0, s>>>(x, y, N, partials);
+    k_sum_prod<<<reduce_blocks(N), TPB, 0, s>>>(x, y, N, N % 2 == 0 && al16(x) && al16(y), partials);
 }
 
 void launch_sum_ham_F(hipStream_t s, const double *psi, const double *f, const double *coef, long N, OpConst oc,
                       double *partials)
 {
-    k_sum_ham_F<<<kReduceBlocks, TPB, 0, s>>>(psi, f, coef, N, oc, partials);
+    k_sum_ham_F<<<reduce_blocks(N), TPB, 0, s>>>(psi, f, coef, N, oc,
+                                                 N % 2 == 0 && al16(psi) && al16(f) && al16(coef), partials);
 }
 
 void launch_res_norms(int kind, hipStream_t s, const double *phi, const double *f, const double *coef, int n,
                       double h, OpConst oc, const double *fbar, const double *fshift, double *partials)
 {
     int zc = 0, grid = 0;
-    if (march_ok(n) && (grid = march_grid(n, kReduceBlocks, &zc)) > 0) {
+    if (march2_ok(n) && (grid = march2_grid(n, march_norm_blocks(), &zc)) > 0) {
+        const double ih2 = 1.0 / (h * h);
+        if (kind == GR_KIND_POISSON)
+            k_march2<M_NORMS, GR_KIND_POISSON, double><<<grid, M2NT, 0, s>>>(
+                phi, f, coef, nullptr, n, zc, ih2, oc, fbar, fshift, partials, nullptr, nullptr, nullptr, nullptr,
+                nullptr, nullptr, nullptr);
+        else if (kind == GR_KIND_HAMILTONIAN)
+            k_march2<M_NORMS, GR_KIND_HAMILTONIAN, double><<<grid, M2NT, 0, s>>>(
+                phi, f, coef, nullptr, n, zc, ih2, oc, fbar, fshift, partials, nullptr, nullptr, nullptr, nullptr,
+                nullptr, nullptr, nullptr);
+        else
+            k_march2<M_NORMS, GR_KIND_CMC, double><<<grid, M2NT, 0, s>>>(
+                phi, f, coef, nullptr, n, zc, ih2, oc, fbar, fshift, partials, nullptr, nullptr, nullptr, nullptr,
+                nullptr, nullptr, nullptr);
+        return;
+    }
+    if (march_ok(n) && (grid = march_grid(n, march_norm_blocks(), &zc)) > 0) {
         const double ih2 = 1.0 / (h * h);
         if (kind == GR_KIND_POISSON)
             k_march<M_NORMS, GR_KIND_POISSON, double><<<grid, MNT, 0, s>>>(phi, f, coef, nullptr, n, zc, ih2, oc, fbar,
@@ -983,7 +1426,7 @@ void launch_res_norms(int kind, hipStream_t s, const double *phi, const double *
         return;
     }
     Geo G;
-    G.grid = dim3(kReduceBlocks);
+    G.grid = dim3(row_blocks(n));
     G.block = dim3(64, 4);
     GR_DISPATCH_KIND_G(kind, k_res_norms, G, phi, f, coef, n, 1.0 / (h * h), oc, fbar, fshift, partials);
 }
@@ -995,32 +1438,38 @@ void launch_finalize(hipStream_t s, const double *partials, int ncomp, double sc
 
 void launch_fill(hipStream_t s, double *x, long N, double v)
 {
-    if (N > 0) k_fill<<<blocks_for(N), TPB, 0, s>>>(x, N, v);
+    const long done = al16(x) ? launch_ew4(s, N, EwFill{x, v}) : 0;
+    if (N > done) k_fill<<<blocks_for(N - done), TPB, 0, s>>>(x + done, N - done, v);
 }
 
 void launch_copy(hipStream_t s, double *dst, const double *src, long N)
 {
-    if (N > 0) k_copy<<<blocks_for(N), TPB, 0, s>>>(dst, src, N);
+    const long done = al16(dst) && al16(src) ? launch_ew4(s, N, EwCopy{dst, src}) : 0;
+    if (N > done) k_copy<<<blocks_for(N - done), TPB, 0, s>>>(dst + done, src + done, N - done);
 }
 
 void launch_copy_f32(hipStream_t s, float *dst, const float *src, long N)
 {
-    if (N > 0) k_copy_f32<<<blocks_for(N), TPB, 0, s>>>(dst, src, N);
+    const long done = al16(dst) && al16(src) ? launch_ew4(s, N, EwCopyF32{dst, src}) : 0;
+    if (N > done) k_copy_f32<<<blocks_for(N - done), TPB, 0, s>>>(dst + done, src + done, N - done);
 }
 
 void launch_sub_scalar(hipStream_t s, double *x, long N, const double *scal)
 {
-    if (N > 0) k_sub_scalar<<<blocks_for(N), TPB, 0, s>>>(x, N, scal);
+    const long done = al16(x) ? launch_ew4(s, N, EwSubScalar{x, scal}) : 0;
+    if (N > done) k_sub_scalar<<<blocks_for(N - done), TPB, 0, s>>>(x + done, N - done, scal);
 }
 
 void launch_convert_f32_to_f64(hipStream_t s, double *dst, const float *src, long N)
 {
-    if (N > 0) k_f32_to_f64<<<blocks_for(N), TPB, 0, s>>>(dst, src, N);
+    const long done = al16(dst) && al16(src) ? launch_ew4(s, N, EwF32ToF64{dst, src}) : 0;
+    if (N > done) k_f32_to_f64<<<blocks_for(N - done), TPB, 0, s>>>(dst + done, src + done, N - done);
 }
 
 void launch_convert_f64_to_f32(hipStream_t s, float *dst, const double *src, long N)
 {
-    if (N > 0) k_f64_to_f32<<<blocks_for(N), TPB, 0, s>>>(dst, src, N);
+    const long done = al16(dst) && al16(src) ? launch_ew4(s, N, EwF64ToF32{dst, src}) : 0;
+    if (N > done) k_f64_to_f32<<<blocks_for(N - done), TPB, 0, s>>>(dst + done, src + done, N - done);
 }
 
 void launch_set_scalar(hipStream_t s, double *slot, double v) { k_set_scalar<<<1, 64, 0, s>>>(slot, v); }
@@ -1043,7 +1492,8 @@ void launch_cubic_pass(hipStream_t s, const double *in, int nx, int ny, int nz, 
 
 void launch_axpy(hipStream_t s, double *y, const double *x, long N)
 {
-    if (N > 0) k_axpy<<<blocks_for(N), TPB, 0, s>>>(y, x, N);
+    const long done = al16(y) && al16(x) ? launch_ew4(s, N, EwAxpy{y, x}) : 0;
+    if (N > done) k_axpy<<<blocks_for(N - done), TPB, 0, s>>>(y + done, x + done, N - done);
 }
 
 } // namespace grmg
