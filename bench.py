@@ -159,6 +159,67 @@ def smoother_only(torch, grmg, n):
                       "poisson_GBps": round(SWEEP_BYTES["poisson"] * N / t_poi / 1e9, 1)}), flush=True)
 
 
+C12_FIELDS = ("Vx", "Vy", "Vz", "U", "Psi", "xi", "Phi", "Bx", "By", "Bz", "b", "beta_x", "beta_y", "beta_z")
+
+
+def c3_errors(torch, grmg, g, d_pos, d_u, mass):
+    """Per-field error of the mixed-precision solve refined to rms(eps)/rms(f)
+    <= 1e-12 against the FP64 path run to its floor (rtol 1e-14, at most 30
+    cycles per field): max|x - x_ref| / max|x_ref| per deviation field."""
+    g.deposit_sources(d_pos, d_u, mass)
+    r64 = g.solve_constraints(allow=(grmg.OK, grmg.ENOTCONV), rtol=1e-14, max_cycles=30)
+    ref = {name: g.get_field(name) for name in C12_FIELDS}
+    g.deposit_sources(d_pos, d_u, mass)
+    rm = g.solve_constraints(rtol=1e-12, precision="mixed")
+    errs = {}
+    for name in C12_FIELDS:
+        x = g.get_field(name)
+        errs[name] = float(((x - ref[name]).abs().max() / ref[name].abs().max()).item())
+    del ref
+    return {"workload": "same particles; mixed refined to 1e-12 vs FP64 at its floor (rtol 1e-14, <= 30 cycles)",
+            "max_rel_err": {k: float(f"{v:.3e}") for k, v in errs.items()},
+            "worst": float(f"{max(errs.values()):.3e}"), "bar": 1e-9,
+            "fp64_floor_rel_res_max": float(f"{max(r64['rel_res']):.3e}"), "mixed_status": rm["status"],
+            "mixed_fallback_fields": rm["fallback"]}
+
+
+def unet_only(torch, grmg, m, reps):
+    """The shipped network (15 -> 10 channels, 16/32/64/64) on an m^3 grid:
+    `reps` forward passes and `reps` loss-gradient passes on seeded inputs, each
+    kind timed with HIP events; FLOP counts of the 3^3 convolutions (2 x 27 x
+    cin x cout per voxel, backward 2x forward) give the MFMA rate."""
+    net = grmg.UNet(15, 10, (16, 32, 64, 64), max_n=m, device="cuda:0")
+    net.init(7)
+    gen = torch.Generator(device="cuda:0").manual_seed(3)
+    x = torch.randn((15, m, m, m), device="cuda:0", dtype=torch.float32, generator=gen)
+    t = torch.randn((10, m, m, m), device="cuda:0", dtype=torch.float32, generator=gen)
+    c = (16, 32, 64, 64)
+    convs = [(15, c[0]), (c[0], c[0])]
+    for l in range(1, 4):
+        convs += [(c[l - 1], c[l]), (c[l], c[l])]
+    for l in (2, 1, 0):
+        convs += [(c[l + 1] + c[l], c[l]), (c[l], c[l])]
+    levels = [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0]
+    fwd_flop = sum(2.0 * 27 * ci * co * (m >> lv) ** 3 for (ci, co), lv in zip(convs, levels))
+    net.forward(x)
+    net.loss_grad(x, t)
+    torch.cuda.synchronize()
+    out = {}
+    for name, fn, flop in (("forward", lambda: net.forward(x), fwd_flop),
+                           ("loss_grad", lambda: net.loss_grad(x, t), 3.0 * fwd_flop)):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(net.stream)
+        for _ in range(reps):
+            fn()
+        e1.record(net.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": round(ms, 3), "conv_TFLOPs": round(flop / (ms * 1e-3) / 1e12, 1)}
+    print(json.dumps({"unet_only": m, "in_ch": 15, "out_ch": 10, "channels": c, "conv_GFLOP_forward": round(fwd_flop / 1e9, 1),
+                      **out}), flush=True)
+
+
 def c1_workload(torch, grmg, synth):
     """The 32^3 Hamiltonian-only solve (s0 = 1 + k^-2 GRF, sigma 0.1, seed 0;
     V(2,2) from Psi = 0 to 1e-10): launch-latency bound on the GPU."""
@@ -322,6 +383,9 @@ def main():
     ap.add_argument("--step-only", choices=("fp64", "mixed", "both"),
                     help="only the 256^3 step(s) of that precision: autotune, warm-up, --steps timed steps "
                          "(for kernel traces and counters)")
+    ap.add_argument("--unet-only", action="store_true",
+                    help="only the learned-guess network at its shipped shape (level 1 of 256^3: 128^3, 15 -> 10 "
+                         "channels): --steps forward passes and loss-gradient passes (for MFMA counters)")
     ap.add_argument("--smoother-only", action="store_true",
                     help="only the finest-level sweeps and a copy of known size (for hardware counters)")
     args = ap.parse_args()
@@ -335,6 +399,9 @@ def main():
     from paper_1905_08890_amd import grmg, synth
 
     n = args.n
+    if args.unet_only:
+        unet_only(torch, grmg, n // 2, max(1, args.steps))
+        return
     if args.smoother_only:
         smoother_only(torch, grmg, n)
         return
@@ -374,6 +441,12 @@ def main():
             log(f"{prec}: cycles {rep_['cycles']}, fallback {rep_['fallback']}, {dt_ * 1e3:.3f} ms/step")
             print(json.dumps({"step_only": prec, "n": n, "ms_per_step": round(dt_ * 1e3, 3),
                               "cycles": rep_["cycles"], "status": rep_["status"]}), flush=True)
+        # one plain copy of n^3 doubles (reads and writes 8 n^3 bytes): the
+        # calibration of the hardware byte counters in the same run
+        src = torch.zeros((n,) * 3, device=dev, dtype=torch.float64)
+        torch.cuda.synchronize()
+        g.set_field("rhs", src)
+        torch.cuda.synchronize()
         g.close()
         return
 
@@ -384,6 +457,9 @@ def main():
     dt, rep = timed("mixed")
     log(f"  refinement steps per field {rep['cycles']}, fallback {rep['fallback']}, {dt * 1e3:.2f} ms/step")
     cycles = rep64["cycles"]
+    log("c3: per-field error of mixed (1e-12) against FP64 at its floor")
+    c3 = c3_errors(torch, grmg, g, d_pos, d_u, mass)
+    log(f"  {c3['max_rel_err']}")
 
     # the dominant kernel inside the solves: every finest-level fused sweep of one
     # FP64 and one mixed step, bracketed by HIP events on the solve's stream
@@ -430,6 +506,7 @@ def main():
         "cycles_fp64": rep64["cycles"],
         "refinement_steps_mixed": rep["cycles"],
         "mixed_fallback_fields": rep["fallback"],
+        "c3_mixed_vs_fp64_floor": c3,
         "points_cycles_per_s_fp64": round(N * sum(rep64["cycles"]) / dt64, 1),
         "autotune": {"seconds": round(tune_s, 3), "choices": tune_report.strip().splitlines()},
         "smoother_back_to_back": {"hamiltonian_us_per_sweep": round(t_ham * 1e6, 2), "hamiltonian_GBps": round(gbps_ham, 1),

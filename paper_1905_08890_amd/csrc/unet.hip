@@ -86,63 +86,111 @@ __global__ void __launch_bounds__(256) k_conv3(const bf16 *__restrict__ in, int 
     }
 }
 
-// dW[co][tap*cin + ci] += sum_v g[v][gcoff + co] in[v + off(tap)][icoff + ci]; db[co] += sum_v g[v][co].
-// Block: one tap, a chunk of voxels; 256 threads each own up to 32 (co, ci)
-// accumulators (co = tid % cout, ci = tid / cout + 8-stride loop).
-constexpr int WG_VOX = 32;
+// Weight gradient of a 3^3 convolution on the BF16 matrix cores:
+//   dW[co][tap*cin + ci] = sum_v g[v][gcoff + co] in[v + off(tap)][icoff + ci],
+//   db[co] = sum_v g[v][gcoff + co].
+// Per tap this is a GEMM with M = cout, N = cin and K = the voxels.  A block
+// owns one tap and every WB-th chunk of 64 consecutive voxels; each chunk's
+// output gradient and shifted input are staged in LDS transposed (channel
+// rows of 64 voxels), so an MFMA operand (8 consecutive voxels of one channel)
+// is one 16-byte LDS read.  Each wave accumulates its 16 x 16 (co, ci) tiles
+// over the block's chunks in FP32; the block writes its partial sums, and
+// k_wgrad_reduce adds the WB partials in a fixed order (deterministic).
+constexpr int WG_CHUNK = 64;              // voxels per staged chunk (two K steps)
+constexpr int WG_ROW = WG_CHUNK + 8;      // LDS row pitch in bf16 (144 bytes)
+constexpr int WG_MAXC = 128;              // largest channel count of either side
+constexpr int WG_MAXT = 8;                // 16 x 16 tiles per wave (cout/16 * cin/16 <= 32)
 __global__ void __launch_bounds__(TPB) k_conv3_wgrad(const bf16 *__restrict__ g, int cout, int gcstride, int gcoff,
                                                      const bf16 *__restrict__ in, int cin, int icstride, int icoff,
-                                                     float *__restrict__ dw, int kpad, float *__restrict__ db, int n,
-                                                     int vox_per_block)
+                                                     float *__restrict__ part, float *__restrict__ bpart, int n)
 {
-    __shared__ float sg[WG_VOX][128];
-    __shared__ float si[WG_VOX][128];
+    __shared__ __attribute__((aligned(16))) bf16 sg[64 * WG_ROW];
+    __shared__ __attribute__((aligned(16))) bf16 si[WG_MAXC * WG_ROW];
     const int tap = blockIdx.y;
     const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
-    const int N = n * n * n;
-    const int vbeg = blockIdx.x * vox_per_block, vend = min(N, vbeg + vox_per_block);
-    const int npair = cout * cin;
-    float acc[32];
+    const long N = (long)n * n * n;
+    const long nchunk = N / WG_CHUNK;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, gq = lane >> 4;
+    const int tco = cout / 16, tci = cin / 16, ntile = tco * tci;
+    floatx4 acc[WG_MAXT];
 #pragma unroll
-    for (int q = 0; q < 32; ++q) acc[q] = 0.0f;
+    for (int t = 0; t < WG_MAXT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
     float bacc = 0.0f;
-    for (int vb = vbeg; vb < vend; vb += WG_VOX) {
-        const int nv = min(WG_VOX, vend - vb);
-        for (int e = threadIdx.x; e < WG_VOX * 128; e += TPB) {
-            const int r = e / 128, c = e % 128;
-            float gv = 0.0f, iv = 0.0f;
-            if (r < nv) {
-                const int v = vb + r;
-                if (c < cout) gv = (float)g[(long)v * gcstride + gcoff + c];
-                if (c < cin) {
-                    const int x = v % n, y = (v / n) % n, z = v / (n * n);
-                    const long q = ((long)wrapn(z + dz, n) * n + wrapn(y + dy, n)) * n + wrapn(x + dx, n);
-                    iv = (float)in[q * icstride + icoff + c];
+    const int gvec = cout / 8, ivec = cin / 8;
+    for (long ch = blockIdx.x; ch < nchunk; ch += gridDim.x) {
+        const long v0 = ch * WG_CHUNK;
+        // stage: g rows [co][voxel], input rows [ci][voxel] at the tap's shifted voxels
+        for (int e = threadIdx.x; e < WG_CHUNK * gvec; e += TPB) {
+            const int r = e / gvec, q = e % gvec;
+            const bf16x8 val = *reinterpret_cast<const bf16x8 *>(g + (v0 + r) * gcstride + gcoff + 8 * q);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sg[(8 * q + j) * WG_ROW + r] = val[j];
+        }
+        for (int e = threadIdx.x; e < WG_CHUNK * ivec; e += TPB) {
+            const int r = e / ivec, q = e % ivec;
+            const long v = v0 + r;
+            const int x = (int)(v % n), y = (int)((v / n) % n), z = (int)(v / ((long)n * n));
+            const long src = ((long)wrapn(z + dz, n) * n + wrapn(y + dy, n)) * n + wrapn(x + dx, n);
+            const bf16x8 val = *reinterpret_cast<const bf16x8 *>(in + src * icstride + icoff + 8 * q);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) si[(8 * q + j) * WG_ROW + r] = val[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < WG_MAXT; ++t) {
+            const int tile = wave + 4 * t;
+            if (tile < ntile) {
+                const int cot = tile / tci, cit = tile % tci;
+#pragma unroll
+                for (int ks = 0; ks < WG_CHUNK / 32; ++ks) {
+                    const int k = 32 * ks + 8 * gq;
+                    const bf16x8 a = *reinterpret_cast<const bf16x8 *>(sg + (16 * cot + i) * WG_ROW + k);
+                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(si + (16 * cit + i) * WG_ROW + k);
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
                 }
             }
-            sg[r][c] = gv;
-            si[r][c] = iv;
         }
-        __syncthreads();
-        for (int r = 0; r < nv; ++r) {
-#pragma unroll
-            for (int q = 0; q < 32; ++q) {
-                const int pidx = threadIdx.x + q * TPB;
-                if (pidx < npair) acc[q] += sg[r][pidx % cout] * si[r][pidx / cout];
-            }
-            if (tap == 13 && threadIdx.x < cout) bacc += sg[r][threadIdx.x];
+        if (tap == 13 && (int)threadIdx.x < cout) {
+            float s = 0.0f;
+            for (int r = 0; r < WG_CHUNK; ++r) s += (float)sg[threadIdx.x * WG_ROW + r];
+            bacc += s;
         }
         __syncthreads();
     }
+    // partial of this block: part[blockIdx.x][tap][co][ci]; lane holds D[4gq + j][i]
+    float *dst = part + ((long)blockIdx.x * 27 + tap) * cout * cin;
 #pragma unroll
-    for (int q = 0; q < 32; ++q) {
-        const int pidx = threadIdx.x + q * TPB;
-        if (pidx < npair) {
-            const int co = pidx % cout, ci = pidx / cout;
-            atomicAdd(dw + (long)co * kpad + tap * cin + ci, acc[q]);
+    for (int t = 0; t < WG_MAXT; ++t) {
+        const int tile = wave + 4 * t;
+        if (tile < ntile) {
+            const int cot = tile / tci, cit = tile % tci;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) dst[(long)(16 * cot + 4 * gq + j) * cin + 16 * cit + i] = acc[t][j];
         }
     }
-    if (tap == 13 && threadIdx.x < cout && db) atomicAdd(db + threadIdx.x, bacc);
+    if (tap == 13 && (int)threadIdx.x < cout) bpart[(long)blockIdx.x * cout + threadIdx.x] = bacc;
+}
+
+// dw[co][tap*cin + ci] += sum over the nb block partials (in order); db likewise
+__global__ void k_wgrad_reduce(const float *__restrict__ part, const float *__restrict__ bpart, int nbk, int cout,
+                               int cin, float *__restrict__ dw, float *__restrict__ db)
+{
+    const long per = 27L * cout * cin;
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < per) {
+        const int tap = (int)(q / ((long)cout * cin));
+        const int rem = (int)(q % ((long)cout * cin));
+        const int co = rem / cin, ci = rem % cin;
+        float s = 0.0f;
+        for (int b = 0; b < nbk; ++b) s += part[(long)b * per + q];
+        dw[(long)co * 27 * cin + tap * cin + ci] += s;
+    }
+    if (db && q < cout) {
+        float s = 0.0f;
+        for (int b = 0; b < nbk; ++b) s += bpart[(long)b * cout + q];
+        db[q] += s;
+    }
 }
 
 // ------------------------------------------------------------ elementwise
@@ -321,31 +369,58 @@ __global__ void k_lap_loss2(const float *__restrict__ q, float *__restrict__ gy,
     }
 }
 
-// head backward: gh[v][c] = sum_o w[o][c] gy[o][v]; dW, db accumulated per block then atomically
-__global__ void k_head_bwd(const float *__restrict__ gy, const bf16 *__restrict__ h, int c, const float *__restrict__ w,
-                           int cout, bf16 *__restrict__ gh, float *__restrict__ dw, float *__restrict__ db, long N)
+// head backward: gh[v][c] = sum_o w[o][c] gy[o][v]; the block's partial sums of
+// dW[o][c] = sum_v gy[o][v] h[v][c] and db[o] = sum_v gy[o][v] over its 256
+// voxels, one parameter per thread in voxel order, to part[block][cout*c + cout]
+// (k_head_reduce adds the blocks in order: deterministic).
+__global__ void __launch_bounds__(TPB) k_head_bwd(const float *__restrict__ gy, const bf16 *__restrict__ h, int c,
+                                                  const float *__restrict__ w, int cout, bf16 *__restrict__ gh,
+                                                  float *__restrict__ part, long N)
 {
-    __shared__ float sdw[16 * 16 + 16];
-    for (int e = threadIdx.x; e < cout * c + cout; e += TPB) sdw[e] = 0.0f;
-    __syncthreads();
-    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float sgy[16][TPB];
+    __shared__ float sh[TPB][17];
+    const long v0 = (long)blockIdx.x * TPB;
+    const long v = v0 + threadIdx.x;
     if (v < N) {
         float hv[16];
-        for (int k = 0; k < c; ++k) hv[k] = (float)h[v * c + k];
+        for (int k = 0; k < c; ++k) {
+            hv[k] = (float)h[v * c + k];
+            sh[threadIdx.x][k] = hv[k];
+        }
+        for (int o = 0; o < cout; ++o) sgy[o][threadIdx.x] = gy[o * N + v];
         for (int k = 0; k < c; ++k) {
             float s = 0.0f;
             for (int o = 0; o < cout; ++o) s += w[o * c + k] * gy[o * N + v];
             gh[v * c + k] = (bf16)s;
         }
-        for (int o = 0; o < cout; ++o) {
-            const float go = gy[o * N + v];
-            for (int k = 0; k < c; ++k) atomicAdd(&sdw[o * c + k], go * hv[k]);
-            atomicAdd(&sdw[cout * c + o], go);
-        }
+    } else {
+        for (int k = 0; k < c; ++k) sh[threadIdx.x][k] = 0.0f;
+        for (int o = 0; o < cout; ++o) sgy[o][threadIdx.x] = 0.0f;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < cout * c; e += TPB) atomicAdd(dw + e, sdw[e]);
-    for (int e = threadIdx.x; e < cout; e += TPB) atomicAdd(db + e, sdw[cout * c + e]);
+    const int npar = cout * c + cout;
+    for (int q = threadIdx.x; q < npar; q += TPB) {
+        float s = 0.0f;
+        if (q < cout * c) {
+            const int o = q / c, k = q % c;
+            for (int r = 0; r < TPB; ++r) s += sgy[o][r] * sh[r][k];
+        } else {
+            const int o = q - cout * c;
+            for (int r = 0; r < TPB; ++r) s += sgy[o][r];
+        }
+        part[(long)blockIdx.x * npar + q] = s;
+    }
+}
+
+__global__ void k_head_reduce(const float *__restrict__ part, int nblk, int npar, int nw, float *__restrict__ dw,
+                              float *__restrict__ db)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= npar) return;
+    float s = 0.0f;
+    for (int b = 0; b < nblk; ++b) s += part[(long)b * npar + q];
+    if (q < nw) dw[q] += s;
+    else db[q - nw] += s;
 }
 
 // FP32 master weights -> BF16 forward layout [co][kpad] and the flipped /
@@ -443,6 +518,8 @@ int ufail(int code, const char *fmt, ...)
 
 int pad32(int k) { return (k + 31) / 32 * 32; }
 
+constexpr int kWgradBlocks = 64; // voxel-chunk blocks per tap of the weight gradient
+
 template <bool RELU, bool BIAS>
 bool launch_conv_t(hipStream_t s, int cout, const bf16 *in, int cin, int ics, int icoff, const bf16 *w, int kpad,
                    const float *bias, bf16 *out, int ocs, int ocoff, int n)
@@ -489,6 +566,7 @@ struct gr_unet_s {
     // device
     float *param = nullptr, *grad = nullptr, *adam_m = nullptr, *adam_v = nullptr;
     float *loss_partial = nullptr, *y = nullptr, *gy = nullptr, *lq = nullptr;
+    float *wg_part = nullptr, *wg_bpart = nullptr; // weight-gradient block partials
     bf16 *x0 = nullptr;
     Act ea[4], eb3, cat[3], p[3], da[3], db[3];       // forward
     Act g_ea[4], g_eb3, g_cat[3], g_p[3], g_da[3], g_db[3], g_x; // backward
@@ -523,6 +601,11 @@ size_t unet_layout(gr_unet U, char *base)
     const int n = U->max_n;
     const long N = (long)n * n * n;
     U->loss_partial = takeF(2048);
+    // block partials of the weight gradients: the 3^3 convolutions' (64 blocks x 27
+    // taps x cout x cin) or the head's (one block per 256 voxels x its parameters)
+    const size_t head_part = (size_t)((N + TPB - 1) / TPB) * (size_t)(U->d.out_ch * U->c[0] + U->d.out_ch);
+    U->wg_part = takeF(std::max((size_t)kWgradBlocks * 27 * WG_MAXC * 64, head_part));
+    U->wg_bpart = takeF((size_t)kWgradBlocks * 64);
     U->y = takeF((size_t)U->d.out_ch * N);
     U->gy = takeF((size_t)U->d.out_ch * N);
     U->lq = takeF((size_t)U->d.out_ch * N);
@@ -576,10 +659,15 @@ int conv_wgrad(gr_unet U, int li, const bf16 *gout, int gcs, int gcoff, const bf
 {
     const ConvLayer &L = U->conv[li];
     const long N = (long)n * n * n;
-    const int vpb = (int)std::max<long>(WG_VOX, std::min<long>(2048, N / 16));
-    dim3 grid((unsigned)((N + vpb - 1) / vpb), 27);
-    k_conv3_wgrad<<<grid, TPB, 0, U->stream>>>(gout, L.cout, gcs, gcoff, in, L.cin, ics, icoff, U->grad + L.w_off, 27 * L.cin,
-                                              U->grad + L.b_off, n, vpb);
+    if (N % WG_CHUNK || L.cout % 16 || L.cin % 16 || L.cout > 64 || L.cin > WG_MAXC ||
+        (L.cout / 16) * (L.cin / 16) > 4 * WG_MAXT)
+        return ufail(GR_EINVAL, "weight gradient: unsupported shape (n %d, cin %d, cout %d)", n, L.cin, L.cout);
+    const int nbk = (int)std::min<long>(kWgradBlocks, N / WG_CHUNK);
+    k_conv3_wgrad<<<dim3((unsigned)nbk, 27), TPB, 0, U->stream>>>(gout, L.cout, gcs, gcoff, in, L.cin, ics, icoff,
+                                                                 U->wg_part, U->wg_bpart, n);
+    const long per = 27L * L.cout * L.cin;
+    k_wgrad_reduce<<<nb(per), TPB, 0, U->stream>>>(U->wg_part, U->wg_bpart, nbk, L.cout, L.cin, U->grad + L.w_off,
+                                                   U->grad + L.b_off);
     ULAUNCH();
     return GR_OK;
 }
@@ -652,9 +740,15 @@ int backward(gr_unet U, int n)
     hipStream_t s = U->stream;
     const long N = (long)n * n * n;
     const int *c = U->c;
-    k_head_bwd<<<nb(N), TPB, 0, s>>>(U->gy, U->db[0].p, c[0], U->param + U->head_w, U->d.out_ch, U->g_db[0].p,
-                                     U->grad + U->head_w, U->grad + U->head_b, N);
-    ULAUNCH();
+    {
+        const int nw = U->d.out_ch * c[0], npar = nw + U->d.out_ch;
+        const unsigned nblk = nb(N);
+        k_head_bwd<<<nblk, TPB, 0, s>>>(U->gy, U->db[0].p, c[0], U->param + U->head_w, U->d.out_ch, U->g_db[0].p,
+                                        U->wg_part, N);
+        k_head_reduce<<<nb(npar), TPB, 0, s>>>(U->wg_part, (int)nblk, npar, nw, U->grad + U->head_w,
+                                               U->grad + U->head_b);
+        ULAUNCH();
+    }
     // decoder, fine to coarse: each level's concat gradient feeds the next coarser output
     for (int k = 0; k <= 2; ++k) {
         const int nk = n >> k;

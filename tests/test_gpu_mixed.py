@@ -99,3 +99,38 @@ def test_mixed_stagnation_falls_back_to_fp64(monkeypatch):
     ref, *_ = O.solve_equation(O.HAMILTONIAN, np.zeros_like(f), f, coef, prm=O.params(**DEFAULT), rtol=1e-14,
                                max_cycles=40)
     assert maxrel(g.get_field("Psi"), ref) < MIXED_TOL
+
+
+C12_FIELDS = ("Vx", "Vy", "Vz", "U", "Psi", "xi", "Phi", "Bx", "By", "Bz", "b", "beta_x", "beta_y", "beta_z")
+
+
+def test_c3_all_fields_256_mixed_vs_fp64_floor():
+    """The 256^3 workload (256^3 Zel'dovich particles, seed 2, rms 1 cell):
+    all ten fields in mixed precision refined to 1e-12 against the FP64 path
+    run to its floor (rtol 1e-14, at most 30 cycles per field; itself within
+    1e-12 of the oracle at equal cycle counts), per deviation field (the ten
+    solved fields, Phi and beta^i), bar 1e-9; the oracle re-evaluates each
+    mixed field's stopping quantity from the GPU fields."""
+    n = 256
+    print("[gpu] c3 all fields 256^3 mixed vs fp64 floor", flush=True)
+    pos, u, mass = synth.zeldovich(n, 2, 1.0)
+    ref = grmg.Grid(n, **DEFAULT)
+    ref.deposit_sources(pos, u, mass)
+    r64 = ref.solve_constraints(rtol=1e-14, max_cycles=30, allow=(0, grmg.ENOTCONV))
+    assert max(r64["rel_res"]) < 1e-12
+    gm = grmg.Grid(n, **DEFAULT)
+    gm.deposit_sources(pos, u, mass)
+    rm = gm.solve_constraints(precision="mixed", rtol=1e-12)
+    assert rm["status"] == 0 and rm["fallback"] == 0
+    errs = {name: maxrel(gm.get_field(name), ref.get_field(name).cpu().numpy()) for name in C12_FIELDS}
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for name, err in errs.items():
+        assert err < MIXED_TOL, (name, err)
+    # the oracle's stopping quantity of the Hamiltonian and CMC fields from the GPU data
+    p = O.params(**DEFAULT)
+    s0 = gm.get_field("s0").cpu().numpy()
+    AA = gm.get_field("AA").cpu().numpy()
+    psi = gm.get_field("Psi").cpu().numpy()
+    assert O.cycle_residual(O.HAMILTONIAN, psi, 1.5 * p.a * p.omega_m * (s0 - 1.0), AA, prm=p) <= 1.0001e-12
+    m2, fxi = O.build_cmc(psi, s0, gm.get_field("sm").cpu().numpy(), AA, prm=p)
+    assert O.cycle_residual(O.CMC, gm.get_field("xi").cpu().numpy(), fxi, m2, prm=p) <= 1.0001e-12

@@ -86,3 +86,47 @@ def test_training_reduces_loss():
     last = np.mean(losses[-10:])
     print("loss", first, last, flush=True)
     assert last < first / 5
+
+
+def test_shipped_shape_forward_elementwise():
+    """The shipped network's shape (15 -> 10 channels, 16/32/64/64) on 64^3:
+    every output element within 6e-2 of the largest reference output (14
+    layers of BF16 rounding, relative 2^-9 each, with FP32 sums: the
+    accumulated error is a few 1e-2 of the output scale at most)."""
+    rng = np.random.default_rng(5)
+    net = grmg.UNet(15, 10, CH, max_n=64)
+    net.init(21)
+    p = net.get_params().cpu().numpy().astype(np.float64)
+    x = smooth_field(rng, (15, 64, 64, 64))
+    y = net.forward(x).cpu().numpy()
+    ref = R.predict(p, x, CH, 10)
+    err = float(np.abs(y - ref).max() / np.abs(ref).max())
+    print("shipped-shape forward max|dy|/max|y|", err, flush=True)
+    assert err < 6e-2
+
+
+def test_shipped_shape_gradient_and_determinism():
+    """Weight gradients of the shipped shape at 32^3 against the FP64
+    reference (per layer relative 6e-2, cosine 0.998), and two evaluations
+    give identical bits (the weight gradient sums its block partials in a
+    fixed order)."""
+    rng = np.random.default_rng(6)
+    net = grmg.UNet(15, 10, CH, max_n=32)
+    net.init(23)
+    p = net.get_params().cpu().numpy().astype(np.float64)
+    x = smooth_field(rng, (15, 32, 32, 32))
+    t = smooth_field(rng, (10, 32, 32, 32))
+    loss, g = net.loss_grad(x, t)
+    loss2, g2 = net.loss_grad(x, t)
+    assert loss == loss2 and torch.equal(g, g2)
+    g = g.cpu().numpy().astype(np.float64)
+    rloss, rg = R.loss_and_grad(p, x, t, CH, 10, 0.0)
+    assert abs(loss - rloss) < 3e-2 * rloss
+    cos = float(g @ rg / (np.linalg.norm(g) * np.linalg.norm(rg)))
+    assert cos > 0.998, cos
+    off = 0
+    for name, ci, co in R.layer_shapes(CH, 10):
+        nw = co * 27 * ci
+        assert rel(g[off:off + nw], rg[off:off + nw]) < 6e-2, name
+        assert rel(g[off + nw:off + nw + co], rg[off + nw:off + nw + co]) < 6e-2, name + " bias"
+        off += nw + co
