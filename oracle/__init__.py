@@ -72,6 +72,8 @@ def lib():
         _lib.orc_derived.argtypes = [C.c_int, C.POINTER(_Params), P, P, P, P, P, P, P, P, P, P]
         _lib.orc_cycle_residual.argtypes = [C.c_int, C.c_double, C.POINTER(_Params), C.c_int, P, P, P]
         _lib.orc_cycle_residual.restype = C.c_double
+        _lib.orc_kick.argtypes = [C.c_int, C.POINTER(_Params), P, P, P, P, P, C.c_long, P, P, C.c_double, C.c_int]
+        _lib.orc_drift.argtypes = [C.c_int, C.POINTER(_Params), P, P, P, P, P, C.c_long, P, P, C.c_double]
     return _lib
 
 
@@ -236,3 +238,30 @@ def derived(psi, xi, Bx, By, Bz, b, prm=None):
     lib().orc_derived(n, C.byref(prm), *[_p(_f64(x)) for x in (psi, xi, Bx, By, Bz, b)],
                       *[_p(o) for o in outs])
     return tuple(outs)
+
+
+KICK_FORWARD, KICK_REVERSE = 0, 1
+
+
+def kick(Phi, Psi, beta, pos, u, dt, order=KICK_FORWARD, prm=None):
+    """One kick of length dt (five substeps, sec. 4.4); returns the new u [np][3]."""
+    prm = prm or params()
+    n = Psi.shape[0]
+    pos = _f64(pos).reshape(-1, 3)
+    out = _f64(u).reshape(-1, 3).copy()
+    bx, by, bz = (_f64(b) for b in beta)
+    lib().orc_kick(n, C.byref(prm), _p(_f64(Phi)), _p(_f64(Psi)), _p(bx), _p(by), _p(bz), pos.shape[0], _p(pos),
+                   _p(out), dt, order)
+    return out
+
+
+def drift(Phi, Psi, beta, pos, u, dt, prm=None):
+    """Drift of length dt (sec. 4.4); returns the new positions [np][3] in [0, 1)."""
+    prm = prm or params()
+    n = Psi.shape[0]
+    out = _f64(pos).reshape(-1, 3).copy()
+    u = _f64(u).reshape(-1, 3)
+    bx, by, bz = (_f64(b) for b in beta)
+    lib().orc_drift(n, C.byref(prm), _p(_f64(Phi)), _p(_f64(Psi)), _p(bx), _p(by), _p(bz), out.shape[0], _p(out),
+                    _p(u), dt)
+    return out

@@ -724,3 +724,133 @@ double orc_cycle_residual(int n, double h, const orc_params *prm, int kind, cons
     free(fe);
     return rn / (fn > 0.0 ? fn : 1.0);
 }
+
+/* ------------------------------------------------ particle evolution (N-body) */
+
+/* Readings of sec. 4.4 (particles evolution) and of the leapfrog of the
+ * appendix on time evolution:
+ *   - the metric quantities at a particle are the cloud-in-cell interpolation
+ *     (the deposit's cell-centred weights and periodic wrap) of the grid
+ *     values: Phi, Psi, beta^i and their 3-point central-difference gradients
+ *     d_i Phi, d_i Psi, d_i beta^j (sec. 4.3.1 difference stencil);
+ *   - W^2 = c^2 + a^-2 chi^-4 u.u with chi = 1 - Psi/(2 a^2 c^2) from the
+ *     interpolated Psi and the particle's current u;
+ *   - the kick splits F_i = sum_j c_j (f_j)_i into five substeps, each taking
+ *     c_j from the velocity as updated by the substeps before it, the f_j
+ *     (gradients at the particle) fixed during the kick;
+ *   - the drift uses the fields at the old position and the given u. */
+enum { ORC_KICK_FORWARD = 0, ORC_KICK_REVERSE = 1 };
+
+typedef struct {
+    double Phi, Psi, beta[3];
+    double dPhi[3], dPsi[3];
+    double dbeta[3][3]; /* dbeta[i][j] = d_i beta^j */
+} pfield_t;
+
+static void particle_fields(int n, const double *Phi, const double *Psi, const double *const beta[3],
+                            const double *x, pfield_t *F)
+{
+    double h = 1.0 / n;
+    int i0[3];
+    double t[3];
+    for (int d = 0; d < 3; ++d) {
+        double g = x[d] / h - 0.5;
+        double fl = floor(g);
+        i0[d] = (int)fl;
+        t[d] = g - fl;
+    }
+    memset(F, 0, sizeof *F);
+    for (int cc = 0; cc < 8; ++cc) {
+        int ox = cc & 1, oy = (cc >> 1) & 1, oz = cc >> 2;
+        double w = (ox ? t[0] : 1.0 - t[0]) * (oy ? t[1] : 1.0 - t[1]) * (oz ? t[2] : 1.0 - t[2]);
+        /* corner indices, wrapped once so that the stencil offsets stay within one box length */
+        int ci = i0[0] + ox, cj = i0[1] + oy, ck = i0[2] + oz;
+        ci = (ci % n + n) % n;
+        cj = (cj % n + n) % n;
+        ck = (ck % n + n) % n;
+        long p = at(n, ci, cj, ck);
+        F->Phi += w * Phi[p];
+        F->Psi += w * Psi[p];
+        for (int d = 0; d < 3; ++d) {
+            F->beta[d] += w * beta[d][p];
+            F->dPhi[d] += w * dcen(Phi, n, h, d, ci, cj, ck);
+            F->dPsi[d] += w * dcen(Psi, n, h, d, ci, cj, ck);
+            for (int j = 0; j < 3; ++j) F->dbeta[d][j] += w * dcen(beta[j], n, h, d, ci, cj, ck);
+        }
+    }
+}
+
+static double lorentz_W(const orc_params *prm, double Psi, const double u[3])
+{
+    double a = prm->a, c = prm->c_tilde;
+    double chi = 1.0 - Psi / (2.0 * a * a * c * c);
+    double chi2 = chi * chi;
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    return sqrt(c * c + uu / (a * a * chi2 * chi2));
+}
+
+/* One kick of length dt for np particles (sec. 4.4): u_i += dt c_j (f_j)_i for
+ * the five force contributions
+ *   j = 1, 2, 3: c_j = -u_j,  (f_j)_i = -d_i beta^j
+ *   j = 4:       c_4 = (W^2 - c^2)/(W c) (1 + Phi/(a^2c^2))/(1 - Psi/(2a^2c^2)),  (f_4)_i = -d_i Psi
+ *   j = 5:       c_5 = W/c,  (f_5)_i = -d_i Phi
+ * in the order 1..5 (ORC_KICK_FORWARD: the synchronising second kick, the
+ * dominant term last) or 5..1 (ORC_KICK_REVERSE: the first kick).
+ * Phi, Psi, beta: grid fields (n^3); pos, u: [np][3]. */
+void orc_kick(int n, const orc_params *prm, const double *Phi, const double *Psi, const double *bx,
+              const double *by, const double *bz, long np, const double *pos, double *u, double dt, int order)
+{
+    const double *beta[3] = {bx, by, bz};
+    double a = prm->a, c = prm->c_tilde;
+    for (long q = 0; q < np; ++q) {
+        pfield_t F;
+        particle_fields(n, Phi, Psi, beta, pos + 3 * q, &F);
+        double *uq = u + 3 * q;
+        for (int s = 0; s < 5; ++s) {
+            int j = order == ORC_KICK_FORWARD ? s + 1 : 5 - s;
+            double cj, f[3];
+            if (j <= 3) {
+                cj = -uq[j - 1];
+                for (int i = 0; i < 3; ++i) f[i] = -F.dbeta[i][j - 1];
+            } else {
+                double W = lorentz_W(prm, F.Psi, uq);
+                if (j == 4) {
+                    cj = (W * W - c * c) / (W * c) * (1.0 + F.Phi / (a * a * c * c))
+                         / (1.0 - F.Psi / (2.0 * a * a * c * c));
+                    for (int i = 0; i < 3; ++i) f[i] = -F.dPsi[i];
+                } else {
+                    cj = W / c;
+                    for (int i = 0; i < 3; ++i) f[i] = -F.dPhi[i];
+                }
+            }
+            for (int i = 0; i < 3; ++i) uq[i] += dt * cj * f[i];
+        }
+    }
+}
+
+/* Drift (sec. 4.4): x^i += dt V^i,
+ * V^i = (1 + Phi/(a^2c^2)) (1 - Psi/(2a^2c^2))^-4 (c/W) u_i - beta^i,
+ * with the fields at the old position; positions wrapped into [0, 1). */
+void orc_drift(int n, const orc_params *prm, const double *Phi, const double *Psi, const double *bx,
+               const double *by, const double *bz, long np, double *pos, const double *u, double dt)
+{
+    const double *beta[3] = {bx, by, bz};
+    double a = prm->a, c = prm->c_tilde;
+    for (long q = 0; q < np; ++q) {
+        pfield_t F;
+        double *x = pos + 3 * q;
+        const double *uq = u + 3 * q;
+        particle_fields(n, Phi, Psi, beta, x, &F);
+        double W = lorentz_W(prm, F.Psi, uq);
+        double chi = 1.0 - F.Psi / (2.0 * a * a * c * c);
+        double chi2 = chi * chi;
+        double fac = (1.0 + F.Phi / (a * a * c * c)) / (chi2 * chi2) * (c / W);
+        for (int d = 0; d < 3; ++d) {
+            double v = fac * uq[d] - F.beta[d];
+            double y = x[d] + dt * v;
+            y -= floor(y);
+            if (y >= 1.0) y = 0.0;
+            x[d] = y;
+        }
+    }
+}
