@@ -134,6 +134,53 @@ def cpu_baseline(n, pos, u, mass, cycles):
     return est, sample_s
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sample_worker(args):
+    """One process: the bounded oracle sample (as cpu_baseline) on its own
+    copy of the inputs; returns its wall time."""
+    n, pos, u, mass = args
+    import oracle as O
+    from paper_1905_08890_amd import synth
+    import numpy as np
+
+    prm = O.params(1.0, synth.OMEGA_M, synth.C_TILDE)
+    t0 = time.perf_counter()
+    s0, sx, sy, sz, sm = O.cic_deposit(n, pos, u, mass, prm=prm)
+    z = np.zeros_like(s0)
+    m2, f_c = O.build_cmc(z, s0, sm, z, prm=prm)
+    for kind, f, coef in ((O.POISSON, 3 * prm.omega_m * (sx - sx.mean()), None),
+                          (O.HAMILTONIAN, 1.5 * prm.omega_m * (s0 - 1.0), z), (O.CMC, f_c, m2)):
+        O.solve_equation(kind, z, f, coef, prm=prm, rtol=0, max_cycles=2)
+    return time.perf_counter() - t0
+
+
+def cpu_all_cores(n, pos, u, mass, sample_1core):
+    """The same bounded sample run as independent copies in P processes at
+    once (P = the host threads available to this process, at most 16): the
+    oracle is serial, so all cores serve independent work; the ratio of P
+    samples to the wall time is the throughput gain over one core."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    P = max(1, min(16, len(os.sched_getaffinity(0))))
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(P) as pool:
+        per = pool.map(_oracle_sample_worker, [(n, pos, u, mass)] * P)
+    wall = time.perf_counter() - t0
+    return P, wall, P * sample_1core / wall, float(np.median(per))
+
+
 def smoother_only(torch, grmg, n):
     """Finest-level sweeps on seeded smooth data plus one plain copy of n^3
     doubles (gr_set_field: reads 8 n^3 and writes 8 n^3 bytes), whose counter
@@ -280,33 +327,41 @@ def c1_oracle_seconds(src, cycles):
 
 
 def bench_learned(torch, grmg, synth, n):
-    """Held-out trajectory (seed 2000, amplitudes 1.0, 1.25, 1.5 cells): per
-    step, time to 1e-10 from (i) zero guess FP64, (ii) previous step FP64,
-    (iii) previous step mixed, (iv) previous step + network increment, mixed,
-    judged per field by the FP64 residual (network time included), the same
-    with untrained weights (control), and (v) the true increment restricted to
-    the network's level in place of the network (the ceiling of any guess at
-    that level).  rel_ratio: per field, the held guess's stopping quantity over
-    the previous step's (below 1: the held guess is kept)."""
+    """Held-out trajectory (seed 2000, amplitudes 1.0, 1.25, 1.5, 1.75 cells):
+    the first two steps build the history; for the next two, time to 1e-10
+    from (i) zero guess FP64, (ii) previous step FP64, (iii) previous step
+    mixed, (iv) linear extrapolation of the two previous steps, mixed (no
+    network), (v) extrapolation + network correction, mixed (network time
+    included), each guess judged per field against the previous step by the
+    FP64 stopping quantity; the same with untrained weights (control); and
+    (vi) extrapolation + the true correction restricted to the network's level
+    (the ceiling of any prediction there).  rel_ratio: per field, the held
+    guess's stopping quantity over the previous step's (below 1: kept)."""
     from paper_1905_08890_amd import learned
 
-    path = os.path.join(ROOT, "paper_1905_08890_amd", "weights", "unet_level1_zeldovich256.npz")
+    path = learned.WEIGHTS
     gs = learned.LearnedGuess(path, n, torch)
     ctl = learned.LearnedGuess(path, n, torch)
     ctl.net.init(4242)
-    res = learned.evaluate(gs, n, [2000], 3, 1.0, torch, control=ctl, exact=True)
+    res = learned.evaluate(gs, n, [2000], 4, 1.0, torch, control=ctl, exact=True)
     summ = learned.summarise(res)
-    out = {"workload": f"{n}^3 Zel'dovich trajectory, held-out seed 2000, 2 steps after the first; "
-                       f"network on level 1 ({n // 2}^3), weights {os.path.basename(path)}"}
+    out = {"workload": f"{n}^3 Zel'dovich trajectory, held-out seed 2000, steps 3 and 4 (after two steps of "
+                       f"history); network on level 1 ({n // 2}^3), weights {os.path.basename(path)} "
+                       f"({gs.meta.get('samples')} training pairs from seeds {gs.meta.get('seeds')})"}
     for k, v in summ.items():
         out[k] = {"ms": round(v["ms"], 3), "cycles": v["cycles"], "fallback_fields": v["fallback"]}
         if "rel_ratio" in v:
             out[k]["rel_ratio"] = [float(f"{x:.3g}") for x in v["rel_ratio"]]
+            out[k]["field_cycles"] = v["field_cycles"]
     z, l = summ["zero_fp64"]["ms"], summ["learned_mixed"]["ms"]
     out["speedup_learned_mixed_vs_zero_fp64"] = round(z / l, 3)
     out["speedup_learned_mixed_vs_prev_fp64"] = round(summ["prev_fp64"]["ms"] / l, 3)
+    out["speedup_learned_mixed_vs_prev_mixed"] = round(summ["prev_mixed"]["ms"] / l, 3)
+    out["speedup_learned_mixed_vs_extrap_mixed"] = round(summ["extrap_mixed"]["ms"] / l, 3)
     out["speedup_prev_mixed_vs_zero_fp64"] = round(z / summ["prev_mixed"]["ms"], 3)
     out["speedup_exact_mixed_vs_zero_fp64"] = round(z / summ["exact_mixed"]["ms"], 3)
+    out["cycles_saved_by_network_vs_extrapolation"] = round(summ["extrap_mixed"]["cycles"] - summ["learned_mixed"]["cycles"], 2)
+    out["cycles_saved_vs_previous_step"] = round(summ["prev_mixed"]["cycles"] - summ["learned_mixed"]["cycles"], 2)
     return out
 
 
@@ -377,6 +432,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-all-cores", action="store_true", help="skip the all-cores oracle timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload (96 boxes + 32 patches)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess trajectory")
     ap.add_argument("--batch-only", action="store_true", help="only the batched workload (96 boxes + 32 patches)")
@@ -542,7 +598,16 @@ def main():
         out["cpu_baseline"] = {"value": round(est * 1e3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
                                "sample": f"CIC + two V(2,2) cycles of each equation kind at {n}^3 "
                                          f"({sample_s:.1f} s measured), scaled by the GPU per-field cycle counts",
+                               "cpu_model": cpu_model(),
                                "c1_oracle_ms": round(c1_oracle_seconds(c1_src, c1["cycles"]) * 1e3, 1)}
+        if not args.no_cpu_all_cores:
+            log("cpu baseline, all cores (independent copies of the sample)")
+            P, wall, gain, per = cpu_all_cores(n, pos, u, mass, sample_s)
+            out["cpu_baseline"]["all_cores"] = {
+                "cores": P, "wall_s": round(wall, 2), "median_sample_s": round(per, 2),
+                "throughput_gain": round(gain, 2), "value": round(est * 1e3 / gain, 1), "unit": "ms",
+                "note": f"{P} copies of the bounded sample in {P} processes at once; value = the one-core step "
+                        f"estimate divided by the measured throughput gain (the oracle is serial)"}
     print(json.dumps(out), flush=True)
 
 

@@ -75,7 +75,12 @@ enum {
     /* low-level slots read by gr_solve_equation / gr_debug_*: fine source f
        and operator coefficient (AA for the Hamiltonian, m2 for CMC) */
     GR_RHS = 22, GR_COEF = 23,
-    GR_NUM_FIELD_IDS = 24
+    /* solved field f's history (GR_HIST + f): its value before the last
+       gr_set_guess with GR_SET_EXTRAP; gr_set_field on it sets the history
+       and marks it recorded, a gr_solve_constraints from GR_GUESS_ZERO
+       discards it (a new trajectory) */
+    GR_HIST = 24,
+    GR_NUM_FIELD_IDS = 34
 };
 
 #define GR_F64 0
@@ -167,6 +172,32 @@ int gr_bind(gr_grid g, void *d_workspace, size_t bytes, void *hip_stream);
 int gr_deposit_sources(gr_grid g, const double *d_pos, const double *d_u, double mass,
                        int64_t n_particles);
 
+/* Particle evolution with the metric the grid holds (its last solve), sec. 4.4
+ * and the leapfrog of the appendix on time evolution.  The metric at a
+ * particle is the cloud-in-cell interpolation (the deposit's cell-centred
+ * weights, periodic) of Phi = xi/chi, Psi, beta^i = B^i + d_i b and of their
+ * 3-point central-difference gradients; W^2 = c^2 + a^-2 chi^-4 u.u from the
+ * interpolated Psi and the particle's current u (lower-index, code units).
+ * gr_kick: u_i += dt sum_j c_j (f_j)_i in five substeps, each taking c_j from
+ * the velocity as updated by the substeps before it:
+ *   j = 1, 2, 3: c_j = -u_j, (f_j)_i = -d_i beta^j;
+ *   j = 4: c_4 = (W^2 - c^2)/(W c) (1 + Phi/(a^2c^2))/(1 - Psi/(2a^2c^2)), (f_4)_i = -d_i Psi;
+ *   j = 5: c_5 = W/c, (f_5)_i = -d_i Phi;
+ * order GR_KICK_FORWARD runs j = 1..5 (the synchronising kick, dominant term
+ * last), GR_KICK_REVERSE j = 5..1 (the first kick); dt is the kick's length
+ * (dt/2 of a time step for a half kick).
+ * gr_drift: x^i += dt [(1 + Phi/(a^2c^2)) chi^-4 (c/W) u_i - beta^i] with the
+ * metric at the old position, positions wrapped into [0, 1).
+ * d_pos, d_u: [np][3] float64 device arrays (the caller's).  Both run on the
+ * grid's stream without synchronising and use the grid's A_ij scratch for Phi
+ * and beta (rebuilt by the next solve).  Errors: GR_ESTATE if unbound,
+ * GR_EINVAL for null arrays with np > 0, np < 0, non-finite dt, a bad order,
+ * or a grid that is not the unit box (h != 1/n). */
+#define GR_KICK_FORWARD 0
+#define GR_KICK_REVERSE 1
+int gr_kick(gr_grid g, const double *d_pos, double *d_u, int64_t n_particles, double dt, int order);
+int gr_drift(gr_grid g, double *d_pos, const double *d_u, int64_t n_particles, double dt);
+
 /* Copy n^3 values of dtype GR_F64/GR_F32 from d_src into a field slot
  * (solved fields as guesses, sources, GR_RHS, GR_COEF).  Derived ids are
  * rejected with GR_EINVAL. */
@@ -224,13 +255,19 @@ int gr_solve_equation_static(int n, const gr_params *prm, int kind, const double
  * discrete Laplacian shows far smaller interpolation kinks).  With GR_SET_ADD it
  * is added to the held field after the held values are saved as that field's
  * alternative guess (see GR_GUESS_CHECKED); without, it replaces the field
- * (and clears the alternative).
+ * (and clears the alternative).  With GR_SET_EXTRAP (for trajectories of time
+ * steps) the held field f (the previous step) is first extrapolated linearly
+ * from its history h (the step before, see GR_HIST): the field becomes
+ * (2 f - h) + prediction, or f + prediction when no history has been recorded
+ * yet; f is then saved both as the alternative and as the new history.  A
+ * zero scale gives the plain linear extrapolation.
  * Both run on the grid's stream, read and write device memory only, and
  * return GR_EINVAL for a bad level, count, field id, flag or null pointer
  * (nothing is launched then).  d_dst / d_src hold count * n_level^3 floats,
  * owned by the caller. */
 #define GR_SET_ADD 1
 #define GR_SET_CUBIC 2
+#define GR_SET_EXTRAP 4
 #define GR_FEAT_ACCUMULATE 1
 int gr_features(gr_grid g, int level, int count, const int *fields, const double *offset, const double *scale,
                 float *d_dst, int flags);
@@ -366,6 +403,8 @@ typedef struct {
     int c[4];
     float lap_weight; /* loss = mean (y-t)^2 + lap_weight * mean (Lap(y-t))^2 (7-point,
                          periodic, unit spacing, per channel); 0: plain MSE */
+    float clip_norm;  /* training: the gradient is scaled to at most this L2 norm before
+                         each Adam step (a non-finite norm skips the step); 0: no clipping */
 } gr_unet_desc;
 
 int gr_unet_create(const gr_unet_desc *desc, int max_n, gr_unet *out);
@@ -381,7 +420,8 @@ int gr_unet_forward(gr_unet u, int n, const float *d_in, float *d_out);
 /* Mean-square loss against d_target and its parameter gradient (copied to
  * d_grad[param_count] when not NULL); *h_loss (host) receives the loss. */
 int gr_unet_loss_grad(gr_unet u, int n, const float *d_in, const float *d_target, float *d_grad, double *h_loss);
-/* One Adam step (beta 0.9/0.999, eps 1e-8) with learning rate lr. */
+/* One Adam step (beta 0.9/0.999, eps 1e-8) with learning rate lr, on the
+ * gradient clipped to the descriptor's clip_norm. */
 int gr_unet_train_step(gr_unet u, int n, const float *d_in, const float *d_target, float lr, double *h_loss);
 int gr_destroy_unet(gr_unet u);
 const char *gr_unet_last_error(void);

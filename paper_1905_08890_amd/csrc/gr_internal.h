@@ -137,6 +137,8 @@ void launch_set_scalar(hipStream_t s, double *slot, double v);
 void launch_affine_to_f32(hipStream_t s, float *dst, const double *src, long N, double off, double scale, bool acc);
 void launch_f32_scaled_to_f64(hipStream_t s, double *dst, const float *src, long N, double scale);
 void launch_axpy(hipStream_t s, double *y, const double *x, long N);
+// field, history, alternative: old = field; alt = old; field = (hv ? 2 old - hist : old) + add; hist = old
+void launch_extrapolate(hipStream_t s, double *field, double *hist, double *alt, const double *add, bool hv, long N);
 void launch_cubic_pass(hipStream_t s, const double *in, int nx, int ny, int nz, int dim, double *out);
 
 // ---- sources.hip launchers ----
@@ -159,6 +161,11 @@ void launch_build_cmc(hipStream_t s, double *m2, double *f, const double *psi, c
                       const double *sm, const double *AA, long N, double a, double om, double c_tilde);
 void launch_shift_source(hipStream_t s, double *fB[3], const double *psi, const double *xi,
                          double *const A6[6], int n, double h, double a, double c_tilde);
+// ---- particles.hip launchers (fields: Phi, Psi and beta^i grids of side n) ----
+void launch_kick(hipStream_t s, int n, double a, double c, const double *Phi, const double *Psi,
+                 const double *const beta[3], const double *pos, double *u, long np, double dt, int order);
+void launch_drift(hipStream_t s, int n, double a, double c, const double *Phi, const double *Psi,
+                  const double *const beta[3], double *pos, const double *u, long np, double dt);
 void launch_derived(hipStream_t s, int which, double *out, const double *psi, const double *xi,
                     const double *Bcomp, const double *b, int n, double h, double a, double c_tilde);
 

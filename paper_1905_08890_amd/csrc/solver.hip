@@ -76,6 +76,8 @@ struct gr_grid_s {
     double *fB[3]{}; // sources of B^i (kept for the three solves)
     double *alt[10]{}; // alternative (previous-step) guesses, saved by gr_set_guess
     bool alt_valid[10]{};
+    double *hist[10]{}; // history: each field as it was before the last GR_SET_EXTRAP guess
+    bool hist_valid[10]{};
     double *gtmp = nullptr; // 3/4 of a fine array: cubic guess interpolation passes
     // Helper hierarchies (levels, FP32 levels, reductions, stream) that solve
     // components 1 and 2 of a vector equation concurrently with component 0.
@@ -186,6 +188,7 @@ size_t layout(gr_grid g, char *base)
         g->AA = take(fb);
         for (int c = 0; c < 3; ++c) g->fB[c] = take(fb);
         for (int f = 0; f < 10; ++f) g->alt[f] = take(fb);
+        for (int f = 0; f < 10; ++f) g->hist[f] = take(fb);
         g->gtmp = take(3 * fb / 4);
         g->cic = take(cic_sorted_bytes(g->N(), g->N()));
     }
@@ -828,6 +831,7 @@ double *slot_ptr(gr_grid g, int field)
     if (field == GR_AA) return g->AA;
     if (field == GR_RHS) return g->lev[0].f;
     if (field == GR_COEF) return g->lev[0].coef;
+    if (field >= GR_HIST && field < GR_HIST + 10 && !g->solver_only) return g->hist[field - GR_HIST];
     return nullptr;
 }
 
@@ -1008,6 +1012,7 @@ int gr_bind(gr_grid g, void *d_ws, size_t bytes, void *stream)
         h->bound = true;
     }
     layout(g, reinterpret_cast<char *>(d_ws));
+    for (int f = 0; f < 10; ++f) g->alt_valid[f] = g->hist_valid[f] = false;
     launch_fill(g->stream, reinterpret_cast<double *>(d_ws), (long)(g->ws_bytes / sizeof(double)), 0.0);
     LAUNCHCHK();
     g->bound = true;
@@ -1038,11 +1043,60 @@ int gr_deposit_sources(gr_grid g, const double *d_pos, const double *d_u, double
     return GR_OK;
 }
 
+// Phi (into the scratch A6[0]) and beta^i (A6[1..3]) from the held fields, for
+// the particle calls; A_ij is rebuilt by the next solve.
+namespace {
+int particle_metric(gr_grid g, const double **Phi, const double *beta[3])
+{
+    const double a = g->prm.a, c = g->prm.c_tilde;
+    launch_derived(g->stream, 0, g->A6[0], g->field[GR_PSI], g->field[GR_XI], nullptr, nullptr, g->n, g->h, a, c);
+    for (int d = 0; d < 3; ++d)
+        launch_derived(g->stream, 3 + d, g->A6[1 + d], g->field[GR_PSI], g->field[GR_XI], g->field[GR_BX + d],
+                       g->field[GR_BB], g->n, g->h, a, c);
+    LAUNCHCHK();
+    *Phi = g->A6[0];
+    for (int d = 0; d < 3; ++d) beta[d] = g->A6[1 + d];
+    return GR_OK;
+}
+
+int check_particles(gr_grid g, const void *pos, const void *u, int64_t np, double dt)
+{
+    CHK(check_bound(g));
+    if (np < 0 || (np > 0 && (!pos || !u))) return fail(GR_EINVAL, "bad particle arrays");
+    if (!std::isfinite(dt)) return fail(GR_EINVAL, "dt not finite");
+    if (std::fabs(g->h * g->n - 1.0) > 1e-12) return fail(GR_EINVAL, "particles need the unit box (h = 1/n)");
+    return GR_OK;
+}
+} // namespace
+
+int gr_kick(gr_grid g, const double *d_pos, double *d_u, int64_t np, double dt, int order)
+{
+    CHK(check_particles(g, d_pos, d_u, np, dt));
+    if (order != GR_KICK_FORWARD && order != GR_KICK_REVERSE) return fail(GR_EINVAL, "bad kick order %d", order);
+    const double *Phi = nullptr, *beta[3];
+    CHK(particle_metric(g, &Phi, beta));
+    launch_kick(g->stream, g->n, g->prm.a, g->prm.c_tilde, Phi, g->field[GR_PSI], beta, d_pos, d_u, (long)np, dt,
+                order);
+    LAUNCHCHK();
+    return GR_OK;
+}
+
+int gr_drift(gr_grid g, double *d_pos, const double *d_u, int64_t np, double dt)
+{
+    CHK(check_particles(g, d_pos, d_u, np, dt));
+    const double *Phi = nullptr, *beta[3];
+    CHK(particle_metric(g, &Phi, beta));
+    launch_drift(g->stream, g->n, g->prm.a, g->prm.c_tilde, Phi, g->field[GR_PSI], beta, d_pos, d_u, (long)np, dt);
+    LAUNCHCHK();
+    return GR_OK;
+}
+
 int gr_set_field(gr_grid g, int field, const void *d_src, int dtype)
 {
     CHK(check_bound(g));
     double *dst = slot_ptr(g, field);
     if (!dst) return fail(GR_EINVAL, "field %d cannot be set", field);
+    if (field >= GR_HIST && field < GR_HIST + 10) g->hist_valid[field - GR_HIST] = true;
     if (!d_src) return fail(GR_EINVAL, "null source");
     if (dtype == GR_F64) launch_copy(g->stream, dst, static_cast<const double *>(d_src), g->N());
     else if (dtype == GR_F32) launch_convert_f32_to_f64(g->stream, dst, static_cast<const float *>(d_src), g->N());
@@ -1211,7 +1265,10 @@ int gr_solve_constraints(gr_grid g, const gr_solve_opts *opts, gr_solve_report *
     int first_bad = GR_OK;
     if (opts->guess == GR_GUESS_ZERO)
         for (int f = 0; f < 10; ++f)
-            if (mask & (1u << f)) launch_fill(s, g->field[f], N, 0.0);
+            if (mask & (1u << f)) {
+                launch_fill(s, g->field[f], N, 0.0);
+                g->hist_valid[f] = false; // a solve from zero starts a new trajectory
+            }
     LAUNCHCHK();
     double *fine_f = g->lev[0].f;
     double *fine_c = g->lev[0].coef;
@@ -1372,7 +1429,7 @@ int gr_set_guess(gr_grid g, int level, int count, const int *fields, const doubl
 {
     CHK(check_bound(g));
     if (level < 0 || level >= g->nlev || count < 1 || count > 10 || !fields || !scale || !d_src ||
-        (flags & ~(GR_SET_ADD | GR_SET_CUBIC)))
+        (flags & ~(GR_SET_ADD | GR_SET_CUBIC | GR_SET_EXTRAP)))
         return fail(GR_EINVAL, "bad argument");
     for (int c = 0; c < count; ++c)
         if (fields[c] < 0 || fields[c] > 9) return fail(GR_EINVAL, "field %d is not a solved field", fields[c]);
@@ -1399,7 +1456,13 @@ int gr_set_guess(gr_grid g, int level, int count, const int *fields, const doubl
             }
             cur = F.tmp;
         }
-        if (flags & GR_SET_ADD) {
+        if (flags & GR_SET_EXTRAP) {
+            // held f (previous step), history h (the step before): field = (2f - h) + P pred,
+            // or f + P pred without a history; then history and alternative = f
+            launch_extrapolate(s, g->field[f], g->hist[f], g->alt[f], cur, g->hist_valid[f], N);
+            g->hist_valid[f] = true;
+            g->alt_valid[f] = true;
+        } else if (flags & GR_SET_ADD) {
             launch_copy(s, g->alt[f], g->field[f], N);
             g->alt_valid[f] = true;
             launch_axpy(s, g->field[f], cur, N);

@@ -848,6 +848,26 @@ struct EwAddF32Out { // d = a + e
                       make_double2(v.hi.x + (double)c.z, v.hi.y + (double)c.w)});
     }
 };
+struct EwExtrapolate { // history-based guess: see launch_extrapolate
+    double *field, *hist, *alt;
+    const double *add;
+    bool hv;
+    __device__ void operator()(long p) const
+    {
+        const D4 o = ld4(field + p), a = ld4(add + p);
+        D4 r;
+        if (hv) {
+            const D4 h = ld4(hist + p);
+            r = D4{make_double2((2.0 * o.lo.x - h.lo.x) + a.lo.x, (2.0 * o.lo.y - h.lo.y) + a.lo.y),
+                   make_double2((2.0 * o.hi.x - h.hi.x) + a.hi.x, (2.0 * o.hi.y - h.hi.y) + a.hi.y)};
+        } else {
+            r = D4{make_double2(o.lo.x + a.lo.x, o.lo.y + a.lo.y), make_double2(o.hi.x + a.hi.x, o.hi.y + a.hi.y)};
+        }
+        st4(field + p, r);
+        st4(hist + p, o);
+        st4(alt + p, o);
+    }
+};
 struct EwFillF32 {
     float *x;
     __device__ void operator()(long p) const { stf4(x + p, make_float4(0.f, 0.f, 0.f, 0.f)); }
@@ -1488,6 +1508,27 @@ void launch_cubic_pass(hipStream_t s, const double *in, int nx, int ny, int nz, 
 {
     const long M = 2L * nx * ny * nz;
     if (M > 0) k_cubic_pass<<<blocks_for(M), TPB, 0, s>>>(in, nx, ny, nz, dim, out);
+}
+
+__global__ void k_extrapolate(double *__restrict__ field, double *__restrict__ hist, double *__restrict__ alt,
+                              const double *__restrict__ add, bool hv, long N)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const double o = field[p];
+    field[p] = (hv ? 2.0 * o - hist[p] : o) + add[p];
+    hist[p] = o;
+    alt[p] = o;
+}
+
+void launch_extrapolate(hipStream_t s, double *field, double *hist, double *alt, const double *add, bool hv, long N)
+{
+    const long done = al16(field) && al16(hist) && al16(alt) && al16(add)
+                          ? launch_ew4(s, N, EwExtrapolate{field, hist, alt, add, hv})
+                          : 0;
+    if (N > done)
+        k_extrapolate<<<blocks_for(N - done), TPB, 0, s>>>(field + done, hist + done, alt + done, add + done, hv,
+                                                           N - done);
 }
 
 void launch_axpy(hipStream_t s, double *y, const double *x, long N)

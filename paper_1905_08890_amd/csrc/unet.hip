@@ -447,13 +447,45 @@ __global__ void k_prep_weights(const float *__restrict__ w, int cout, int cin, i
     }
 }
 
-// Adam (FP32): p -= lr * mhat / (sqrt(vhat) + eps)
+// Gradient-norm clipping: per-block sums of g^2 (FP64, fixed grid), then one
+// block adds them in order and writes scale = min(1, clip / |g|) (1 for a zero
+// or non-finite norm is not used: a non-finite norm gives scale 0, so the step
+// leaves the weights unchanged).
+constexpr int kClipBlocks = 256;
+__global__ void __launch_bounds__(TPB) k_sumsq(const float *__restrict__ g, long N, double *__restrict__ part)
+{
+    __shared__ double sh[TPB];
+    double s = 0.0;
+    for (long q = (long)blockIdx.x * TPB + threadIdx.x; q < N; q += (long)gridDim.x * TPB) s += (double)g[q] * g[q];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = TPB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void k_clip_scale(const double *__restrict__ part, int nbk, float clip, float *__restrict__ scale,
+                             float *__restrict__ norm_out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < nbk; ++b) s += part[b];
+    const double nrm = sqrt(s);
+    norm_out[0] = (float)nrm;
+    scale[0] = !isfinite(nrm) ? 0.0f : (nrm > (double)clip ? (float)((double)clip / nrm) : 1.0f);
+}
+
+// Adam (FP32) on the gradient times *gscale (1 without clipping):
+// p -= lr * mhat / (sqrt(vhat) + eps)
 __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
-                       long N, float lr, float b1, float b2, float eps, float c1, float c2)
+                       long N, float lr, float b1, float b2, float eps, float c1, float c2,
+                       const float *__restrict__ gscale)
 {
     const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= N) return;
-    const float gq = g[q];
+    const float gq = g[q] * gscale[0];
     const float mq = b1 * m[q] + (1.0f - b1) * gq;
     const float vq = b2 * v[q] + (1.0f - b2) * gq * gq;
     m[q] = mq;
@@ -567,6 +599,8 @@ struct gr_unet_s {
     float *param = nullptr, *grad = nullptr, *adam_m = nullptr, *adam_v = nullptr;
     float *loss_partial = nullptr, *y = nullptr, *gy = nullptr, *lq = nullptr;
     float *wg_part = nullptr, *wg_bpart = nullptr; // weight-gradient block partials
+    double *gn_part = nullptr;                       // gradient-norm block partials
+    float *gscale = nullptr;
     bf16 *x0 = nullptr;
     Act ea[4], eb3, cat[3], p[3], da[3], db[3];       // forward
     Act g_ea[4], g_eb3, g_cat[3], g_p[3], g_da[3], g_db[3], g_x; // backward
@@ -601,6 +635,8 @@ size_t unet_layout(gr_unet U, char *base)
     const int n = U->max_n;
     const long N = (long)n * n * n;
     U->loss_partial = takeF(2048);
+    U->gn_part = reinterpret_cast<double *>(take(sizeof(double) * kClipBlocks));
+    U->gscale = takeF(2); // [0] clip scale of the gradient, [1] its norm
     // block partials of the weight gradients: the 3^3 convolutions' (64 blocks x 27
     // taps x cout x cin) or the head's (one block per 256 voxels x its parameters)
     const size_t head_part = (size_t)((N + TPB - 1) / TPB) * (size_t)(U->d.out_ch * U->c[0] + U->d.out_ch);
@@ -852,6 +888,8 @@ int gr_unet_create(const gr_unet_desc *d, int max_n, gr_unet *out)
         return ufail(GR_EINVAL, "in_ch and out_ch must be 1..16");
     if (!(d->lap_weight >= 0.0f) || !std::isfinite(d->lap_weight))
         return ufail(GR_EINVAL, "lap_weight must be finite and >= 0");
+    if (!(d->clip_norm >= 0.0f) || !std::isfinite(d->clip_norm))
+        return ufail(GR_EINVAL, "clip_norm must be finite and >= 0");
     if (d->c[0] != 16) return ufail(GR_EINVAL, "c[0] must be 16");
     for (int k = 1; k < 4; ++k)
         if (d->c[k] < 16 || d->c[k] > 64 || d->c[k] % 16) return ufail(GR_EINVAL, "c[%d] must be 16, 32, 48 or 64", k);
@@ -981,8 +1019,12 @@ int gr_unet_train_step(gr_unet U, int n, const float *d_in, const float *d_targe
     UCHK(loss_and_grad(U, n, d_in, d_target, h_loss));
     ++U->step;
     const float b1 = 0.9f, b2 = 0.999f;
+    const float clip = U->d.clip_norm > 0.0f ? U->d.clip_norm : 3.4e38f;
+    k_sumsq<<<kClipBlocks, TPB, 0, U->stream>>>(U->grad, U->nparam, U->gn_part);
+    k_clip_scale<<<1, 64, 0, U->stream>>>(U->gn_part, kClipBlocks, clip, U->gscale, U->gscale + 1);
     k_adam<<<nb(U->nparam), TPB, 0, U->stream>>>(U->param, U->grad, U->adam_m, U->adam_v, U->nparam, lr, b1, b2, 1e-8f,
-                                                1.0f - std::pow(b1, (float)U->step), 1.0f - std::pow(b2, (float)U->step));
+                                                1.0f - std::pow(b1, (float)U->step), 1.0f - std::pow(b2, (float)U->step),
+                                                U->gscale);
     ULAUNCH();
     return refresh_weights(U);
 }

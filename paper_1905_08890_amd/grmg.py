@@ -22,17 +22,19 @@ POISSON, HAMILTONIAN, CMC = 0, 1, 2
 F64, F32 = 0, 1
 FP64, MIXED = 0, 1
 GUESS_ZERO, GUESS_CURRENT, GUESS_CHECKED = 0, 1, 2
-SET_ADD, SET_CUBIC = 1, 2
+SET_ADD, SET_CUBIC, SET_EXTRAP = 1, 2, 4
+HIST = 24   # GR_HIST + f: history of solved field f (read only)
 FEAT_ACCUMULATE = 1
 ALL_FIELDS = 0x3FF
 SOLVED = ("Vx", "Vy", "Vz", "U", "Psi", "xi", "Bx", "By", "Bz", "b")
 FIELD_IDS = {name: i for i, name in enumerate(SOLVED)}
 FIELD_IDS.update(dict(s0=S0, sx=SX, sy=SY, sz=SZ, sm=SM, AA=AA, Phi=PHI, alpha=ALPHA, psi_conf=CONF,
                       beta_x=BETAX, beta_y=BETAY, beta_z=BETAZ, rhs=RHS, coef=COEF))
+FIELD_IDS.update({f"hist_{name}": HIST + i for i, name in enumerate(SOLVED)})
 
 EXPORTS = ("gr_default_opts", "gr_create_grid", "gr_workspace_bytes", "gr_bind", "gr_deposit_sources",
            "gr_set_field", "gr_get_field", "gr_solve_constraints", "gr_solve_equation", "gr_solve_equation_static",
-           "gr_debug_sweep",
+           "gr_debug_sweep", "gr_kick", "gr_drift",
            "gr_debug_residual", "gr_destroy_grid", "gr_last_error", "gr_features", "gr_set_guess", "gr_autotune", "gr_sweep_timing", "gr_create_batch", "gr_create_batch_patches",
            "gr_batch_debug_boundary", "gr_batch_autotune", "gr_batch_workspace_bytes",
            "gr_batch_bind", "gr_batch_set_field", "gr_batch_get_field", "gr_batch_solve", "gr_destroy_batch",
@@ -59,7 +61,8 @@ class GrSolveOpts(C.Structure):
 
 
 class GrUnetDesc(C.Structure):
-    _fields_ = [("in_ch", C.c_int), ("out_ch", C.c_int), ("c", C.c_int * 4), ("lap_weight", C.c_float)]
+    _fields_ = [("in_ch", C.c_int), ("out_ch", C.c_int), ("c", C.c_int * 4), ("lap_weight", C.c_float),
+                ("clip_norm", C.c_float)]
 
 
 class GrSolveReport(C.Structure):
@@ -104,6 +107,8 @@ def load_library(path: str = LIB_PATH):
         "gr_solve_equation_static": [C.c_int, C.POINTER(GrParams), C.c_int, vp, vp, vp, C.POINTER(GrSolveOpts), vp,
                                      C.POINTER(GrSolveReport)],
         "gr_debug_sweep": [vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int],
+        "gr_kick": [vp, vp, vp, i64, C.c_double, C.c_int],
+        "gr_drift": [vp, vp, vp, i64, C.c_double],
         "gr_debug_residual": [vp, C.c_int, C.c_int, C.c_double, C.c_double, vp],
         "gr_destroy_grid": [vp],
         "gr_features": [vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double), vp,
@@ -237,6 +242,17 @@ def solve_equation_static(n: int, a: float, omega_m: float, c_tilde: float, kind
                                                    _ptr(coef) if coef is not None else None, _ptr(phi),
                                                    C.byref(opts), stream, C.byref(r)), allow)
     return r
+
+
+KICK_FORWARD, KICK_REVERSE = 0, 1
+
+
+def kick(g: int, pos, u, dt: float, order: int) -> None:
+    _check(load_library().gr_kick(g, _ptr(pos), _ptr(u), int(pos.shape[0]), float(dt), int(order)))
+
+
+def drift(g: int, pos, u, dt: float) -> None:
+    _check(load_library().gr_drift(g, _ptr(pos), _ptr(u), int(pos.shape[0]), float(dt)))
 
 
 def debug_sweep(g: int, kind: int, field: int, Fbar: float, fshift: float, nsweeps: int) -> None:
@@ -498,7 +514,7 @@ class UNet:
     """The U-Net of the learned guess (see gr.h); device memory from torch."""
 
     def __init__(self, in_ch: int, out_ch: int, channels=(16, 32, 64, 64), max_n: int = 64, device="cuda",
-                 stream=None, lap_weight: float = 0.0):
+                 stream=None, lap_weight: float = 0.0, clip_norm: float = 0.0):
         import torch
 
         self.torch = torch
@@ -506,8 +522,8 @@ class UNet:
         self.device = torch.device(device)
         lib = load_library()
         h = C.c_void_p()
-        _ucheck(lib.gr_unet_create(C.byref(GrUnetDesc(in_ch, out_ch, (C.c_int * 4)(*channels), lap_weight)), max_n,
-                                   C.byref(h)))
+        _ucheck(lib.gr_unet_create(C.byref(GrUnetDesc(in_ch, out_ch, (C.c_int * 4)(*channels), lap_weight,
+                                                      clip_norm)), max_n, C.byref(h)))
         self.lap_weight = lap_weight
         self.handle = h.value
         nbytes, cnt = C.c_size_t(), C.c_int64()

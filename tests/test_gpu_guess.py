@@ -97,7 +97,7 @@ def test_features_and_set_guess_reject_bad_arguments():
     with pytest.raises(grmg.GrError):
         grmg.set_guess(g.handle, 0, [grmg.S0], [1.0], out, 1)
     with pytest.raises(grmg.GrError):
-        grmg.set_guess(g.handle, 0, [0], [1.0], out, 4)
+        grmg.set_guess(g.handle, 0, [0], [1.0], out, 8)   # no such flag
     assert lib.gr_features(g.handle, 0, 1, None, None, None, None, 0) == grmg.EINVAL
 
 
@@ -175,3 +175,77 @@ def test_checked_guess_keeps_a_better_prediction(trajectory):
     # a second solve without a new prediction has no alternative left: plain CURRENT
     rep2 = g.solve_constraints(rtol=1e-10, guess="checked")
     assert rep2["guess_fallback"] == 0
+
+
+@pytest.mark.parametrize("n,level", [(32, 1), (64, 1), (48, 2)])
+def test_extrapolated_guess_and_history(n, level):
+    """GR_SET_EXTRAP: without a history the field becomes f + P pred (the
+    previous step); the history then holds f; the next call gives
+    (2 f' - f) + P pred'.  P = the oracle's cubic interpolation (1e-13); the
+    history is readable (GR_HIST), settable, and a zero-guess solve discards
+    it (the next extrapolation is again f + P pred)."""
+    print(f"[gpu] extrapolated guess n={n} level={level}", flush=True)
+    g = grmg.Grid(n, **PRM)
+    rng = np.random.default_rng(11 * n + level)
+    m = n >> level
+    fields = [grmg.VX, grmg.PSI, grmg.BB]
+    f0 = [rng.standard_normal((n, n, n)) for _ in fields]
+    f1 = [rng.standard_normal((n, n, n)) for _ in fields]
+    p0 = rng.standard_normal((len(fields), m, m, m)).astype(np.float32)
+    p1 = rng.standard_normal((len(fields), m, m, m)).astype(np.float32)
+    sc = [0.5, -2.0, 3.0]
+    flags = grmg.SET_EXTRAP | grmg.SET_CUBIC
+
+    def prolonged(p, c):
+        e = p[c].astype(np.float64) * sc[c]
+        for _ in range(level):
+            e = O.interp_cubic(e)
+        return e
+
+    for f, v in zip(fields, f0):
+        g.set_field(f, v)
+    grmg.set_guess(g.handle, level, fields, sc, torch.tensor(p0, device="cuda"), flags)
+    for c, f in enumerate(fields):
+        assert maxrel(g.get_field(f).cpu().numpy(), f0[c] + prolonged(p0, c)) < 1e-13
+        assert np.array_equal(g.get_field(grmg.HIST + f).cpu().numpy(), f0[c])
+    for f, v in zip(fields, f1):
+        g.set_field(f, v)
+    grmg.set_guess(g.handle, level, fields, sc, torch.tensor(p1, device="cuda"), flags)
+    for c, f in enumerate(fields):
+        ref = (2.0 * f1[c] - f0[c]) + prolonged(p1, c)
+        assert maxrel(g.get_field(f).cpu().numpy(), ref) < 1e-13
+        assert np.array_equal(g.get_field(grmg.HIST + f).cpu().numpy(), f1[c])
+    # a history set from outside is used; a zero-guess solve discards it
+    for c, f in enumerate(fields):
+        g.set_field(grmg.HIST + f, f0[c])
+        g.set_field(f, f1[c])
+    grmg.set_guess(g.handle, level, fields, [0.0] * 3, torch.tensor(p1, device="cuda"), flags)
+    for c, f in enumerate(fields):
+        assert maxrel(g.get_field(f).cpu().numpy(), 2.0 * f1[c] - f0[c]) < 1e-13
+    g.set_field("s0", np.ones((n, n, n)))
+    g.solve_constraints(rtol=1e-10)          # zero guess: a new trajectory
+    for c, f in enumerate(fields):
+        g.set_field(f, f1[c])
+    grmg.set_guess(g.handle, level, fields, sc, torch.tensor(p0, device="cuda"), flags)
+    for c, f in enumerate(fields):
+        assert maxrel(g.get_field(f).cpu().numpy(), f1[c] + prolonged(p0, c)) < 1e-13
+
+
+def test_shipped_learned_guess_saves_cycles():
+    """The shipped network on the 256^3 workload's held-out trajectory (seed
+    2000, steps 3 and 4 after two steps of history): extrapolation + network
+    needs fewer V-cycles than the previous-step guess, keeps its guess on
+    every field (no fallback), and does not need more cycles than the plain
+    extrapolation (what the network adds)."""
+    from paper_1905_08890_amd import learned
+
+    print("[gpu] shipped learned guess 256^3", flush=True)
+    n = 256
+    g = learned.LearnedGuess(learned.WEIGHTS, n, torch)
+    res = learned.evaluate(g, n, [2000], 4, 1.0, torch, exact=False)
+    summ = learned.summarise(res)
+    print({k: (v["cycles"], v["fallback"], round(v["ms"], 1)) for k, v in summ.items()}, flush=True)
+    assert all(v["all_ok"] for v in summ.values())
+    assert summ["learned_mixed"]["cycles"] < summ["prev_mixed"]["cycles"]
+    assert summ["learned_mixed"]["fallback"] < 10
+    assert summ["learned_mixed"]["cycles"] <= summ["extrap_mixed"]["cycles"]
