@@ -74,6 +74,8 @@ def lib():
         _lib.orc_cycle_residual.restype = C.c_double
         _lib.orc_kick.argtypes = [C.c_int, C.POINTER(_Params), P, P, P, P, P, C.c_long, P, P, C.c_double, C.c_int]
         _lib.orc_drift.argtypes = [C.c_int, C.POINTER(_Params), P, P, P, P, P, C.c_long, P, P, C.c_double]
+        _lib.orc_newtonian_kick.argtypes = [C.c_int, C.POINTER(_Params), P, P, C.c_long, P, P, C.c_double,
+                                            C.c_double, C.c_int, C.POINTER(C.c_int)]
     return _lib
 
 
@@ -265,3 +267,17 @@ def drift(Phi, Psi, beta, pos, u, dt, prm=None):
     lib().orc_drift(n, C.byref(prm), _p(_f64(Phi)), _p(_f64(Psi)), _p(bx), _p(by), _p(bz), out.shape[0], _p(out),
                     _p(u), dt)
     return out
+
+
+def newtonian_kick(s0, pos, u, dt, prm=None, rtol=1e-10, max_cycles=100):
+    """Newtonian potential Lap Phi_N = 3/2 a Om (s0 - 1) and the kick
+    u -= dt grad Phi_N at the particles.  Returns (u_new, Phi_N, status, cycles)."""
+    prm = prm or params()
+    n = s0.shape[0]
+    pos = _f64(pos).reshape(-1, 3)
+    out = _f64(u).reshape(-1, 3).copy()
+    phiN = np.empty((n, n, n))
+    cyc = C.c_int()
+    st = lib().orc_newtonian_kick(n, C.byref(prm), _p(_f64(s0)), _p(phiN), pos.shape[0], _p(pos), _p(out), dt,
+                                  rtol, max_cycles, C.byref(cyc))
+    return out, phiN, st, cyc.value

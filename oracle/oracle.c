@@ -854,3 +854,35 @@ void orc_drift(int n, const orc_params *prm, const double *Phi, const double *Ps
         }
     }
 }
+
+/* Newtonian potential and kick (the temporary synchronisation option of
+ * sec. 4.5 and of the appendix on time evolution): Phi_N solves the code-unit
+ * Newtonian Poisson equation Lap Phi_N = 3/2 a Om (s0 - 1) (the weak-field,
+ * chi -> 1 limit of the Hamiltonian constraint's source) by the Poisson
+ * V-cycles to rtol, pinned to zero mean; then u_i -= dt d_i Phi_N at every
+ * particle (the CIC interpolation of the central difference).  phiN (n^3)
+ * receives the potential.  Returns the solve's status. */
+int orc_newtonian_kick(int n, const orc_params *prm, const double *s0, double *phiN, long np, const double *pos,
+                       double *u, double dt, double rtol, int max_cycles, int *cycles)
+{
+    long N = (long)n * n * n;
+    double A = 1.5 * prm->a * prm->omega_m;
+    double *f = malloc(N * sizeof(double));
+    if (!f) return ORC_ENOMEM;
+    for (long p = 0; p < N; ++p) f[p] = A * (s0[p] - 1.0);
+    double rel = 0.0;
+    memset(phiN, 0, N * sizeof(double));
+    orc_opts o = {2, 2, max_cycles, rtol};
+    int st = orc_solve_equation(n, 1.0 / n, prm, ORC_POISSON, phiN, f, NULL, &o, cycles, &rel);
+    free(f);
+    double *zero = calloc((size_t)N, sizeof(double));
+    if (!zero) return ORC_ENOMEM;
+    const double *beta[3] = {zero, zero, zero};
+    for (long q = 0; q < np; ++q) {
+        pfield_t F;
+        particle_fields(n, phiN, zero, beta, pos + 3 * q, &F);
+        for (int d = 0; d < 3; ++d) u[3 * q + d] -= dt * F.dPhi[d];
+    }
+    free(zero);
+    return st;
+}

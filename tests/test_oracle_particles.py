@@ -130,3 +130,25 @@ def test_flrw_fields_leave_particles_on_straight_lines():
     W = np.sqrt(CT ** 2 + (u ** 2).sum(1) / A ** 2)
     ref = (pos + dt * CT * u / W[:, None]) % 1.0
     assert np.abs(O.drift(z, z, [z, z, z], pos, u, dt, prm=PRM) - ref).max() < 1e-15
+
+
+def test_newtonian_potential_is_weak_field_psi():
+    """The Newtonian potential of the temporary synchronisation solves the
+    chi -> 1 limit of the Hamiltonian constraint, so for weak sources it
+    equals the solved Psi up to the screening term mu^2 = 9 a Om kappa
+    (relative 1e-3 at the default c~), and its kick on particles at rest is
+    the GR kick's Newtonian term: u = -dt grad Psi there (rtol 1e-3)."""
+    n = 32
+    prm = O.params()
+    s0 = 1.0 + 1e-3 * __import__("paper_1905_08890_amd.synth", fromlist=["grf"]).grf(n, 44, -2.0, 1.0)
+    z = np.zeros((n, n, n))
+    A_ = 1.5 * prm.a * prm.omega_m
+    psi, st, _, _ = O.solve_equation(O.HAMILTONIAN, z, A_ * (s0 - 1.0), z, prm=prm, rtol=1e-13)
+    pos, _ = _particles(300, 8)
+    u0 = np.zeros_like(pos)
+    uN, phiN, st2, cyc = O.newtonian_kick(s0, pos, u0, 0.1, prm=prm, rtol=1e-13)
+    assert st == st2 == O.OK and cyc > 0
+    assert np.abs(phiN - psi).max() < 1e-3 * np.abs(psi).max()
+    assert abs(phiN.mean()) < 1e-14 * np.abs(phiN).max()
+    uGR = O.kick(psi, z, [z, z, z], pos, u0, 0.1, O.KICK_FORWARD, prm=prm)   # Phi := Psi, no Psi, beta terms
+    assert np.abs(uN - uGR).max() < 1e-3 * np.abs(uGR).max()
