@@ -198,6 +198,19 @@ int gr_deposit_sources(gr_grid g, const double *d_pos, const double *d_u, double
 int gr_kick(gr_grid g, const double *d_pos, double *d_u, int64_t n_particles, double dt, int order);
 int gr_drift(gr_grid g, double *d_pos, const double *d_u, int64_t n_particles, double dt);
 
+/* The Newtonian half of the temporary synchronisation option (sec. 4.5, last
+ * paragraph; appendix on time evolution): solves the code-unit Newtonian
+ * Poisson equation Lap Phi_N = 3/2 a Om (s0 - <s0>) from the held s0 (Poisson
+ * V-cycles from zero with opts' rtol, max_cycles and precision; zero mean),
+ * then u_i -= dt d_i Phi_N at every particle (the same interpolation as
+ * gr_kick).  With dt = half a time step this gives u_N^{n+1} from u^{n+1/2};
+ * the caller keeps a copy of u to revert to exactly after depositing with u_N
+ * and solving.  Fills cycles[0] / rel_res[0] of the report; synchronises the
+ * stream before returning.  Uses the grid's A_ij scratch for Phi_N.  Errors as
+ * gr_kick, plus bad options (GR_GUESS_CHECKED is rejected). */
+int gr_newtonian_kick(gr_grid g, const double *d_pos, double *d_u, int64_t n_particles, double dt,
+                      const gr_solve_opts *opts, gr_solve_report *host_report);
+
 /* Copy n^3 values of dtype GR_F64/GR_F32 from d_src into a field slot
  * (solved fields as guesses, sources, GR_RHS, GR_COEF).  Derived ids are
  * rejected with GR_EINVAL. */

@@ -857,11 +857,12 @@ void orc_drift(int n, const orc_params *prm, const double *Phi, const double *Ps
 
 /* Newtonian potential and kick (the temporary synchronisation option of
  * sec. 4.5 and of the appendix on time evolution): Phi_N solves the code-unit
- * Newtonian Poisson equation Lap Phi_N = 3/2 a Om (s0 - 1) (the weak-field,
- * chi -> 1 limit of the Hamiltonian constraint's source) by the Poisson
- * V-cycles to rtol, pinned to zero mean; then u_i -= dt d_i Phi_N at every
- * particle (the CIC interpolation of the central difference).  phiN (n^3)
- * receives the potential.  Returns the solve's status. */
+ * Newtonian Poisson equation Lap Phi_N = 3/2 a Om (s0 - <s0>) (the weak-field,
+ * chi -> 1 limit of the Hamiltonian constraint's source; the mean is removed
+ * for periodic solvability, as sec. 4.3.1 does for the momentum source) by the
+ * Poisson V-cycles to rtol, pinned to zero mean; then u_i -= dt d_i Phi_N at
+ * every particle (the CIC interpolation of the central difference).  phiN
+ * (n^3) receives the potential.  Returns the solve's status. */
 int orc_newtonian_kick(int n, const orc_params *prm, const double *s0, double *phiN, long np, const double *pos,
                        double *u, double dt, double rtol, int max_cycles, int *cycles)
 {
@@ -869,7 +870,11 @@ int orc_newtonian_kick(int n, const orc_params *prm, const double *s0, double *p
     double A = 1.5 * prm->a * prm->omega_m;
     double *f = malloc(N * sizeof(double));
     if (!f) return ORC_ENOMEM;
+    /* A (s0 - 1), then minus its own mean: the same source as A (s0 - <s0>),
+     * with the mean taken of the small deviations (no cancellation against 1) */
     for (long p = 0; p < N; ++p) f[p] = A * (s0[p] - 1.0);
+    double fm = mean_of(f, N);
+    for (long p = 0; p < N; ++p) f[p] -= fm;
     double rel = 0.0;
     memset(phiN, 0, N * sizeof(double));
     orc_opts o = {2, 2, max_cycles, rtol};

@@ -164,6 +164,7 @@ void launch_shift_source(hipStream_t s, double *fB[3], const double *psi, const 
 // ---- particles.hip launchers (fields: Phi, Psi and beta^i grids of side n) ----
 void launch_kick(hipStream_t s, int n, double a, double c, const double *Phi, const double *Psi,
                  const double *const beta[3], const double *pos, double *u, long np, double dt, int order);
+void launch_newton_kick(hipStream_t s, int n, const double *phiN, const double *pos, double *u, long np, double dt);
 void launch_drift(hipStream_t s, int n, double a, double c, const double *Phi, const double *Psi,
                   const double *const beta[3], double *pos, const double *u, long np, double dt);
 void launch_derived(hipStream_t s, int which, double *out, const double *psi, const double *xi,

@@ -140,7 +140,39 @@ __global__ void __launch_bounds__(TPB) k_drift(Metric M, double a, double c, dou
     }
 }
 
+// Newtonian kick of the temporary synchronisation: u_i -= dt d_i Phi_N (CIC
+// interpolation of the central difference at the eight cloud corners)
+__global__ void __launch_bounds__(TPB) k_newton_kick(const double *__restrict__ phiN, int n, double inv2h,
+                                                     const double *__restrict__ pos, double *__restrict__ u, long np,
+                                                     double dt)
+{
+    const long q = (long)blockIdx.x * TPB + threadIdx.x;
+    if (q >= np) return;
+    int i0[3];
+    double t[3];
+    for (int d = 0; d < 3; ++d) {
+        const double g = pos[3 * q + d] * (double)n - 0.5;
+        const double fl = floor(g);
+        i0[d] = (int)fl;
+        t[d] = g - fl;
+    }
+    double grad[3] = {0.0, 0.0, 0.0};
+    for (int cc = 0; cc < 8; ++cc) {
+        const int ox = cc & 1, oy = (cc >> 1) & 1, oz = cc >> 2;
+        const double w = (ox ? t[0] : 1.0 - t[0]) * (oy ? t[1] : 1.0 - t[1]) * (oz ? t[2] : 1.0 - t[2]);
+        const int ci = wrapc(i0[0] + ox, n), cj = wrapc(i0[1] + oy, n), ck = wrapc(i0[2] + oz, n);
+        for (int d = 0; d < 3; ++d) grad[d] += w * dc(phiN, d, ci, cj, ck, n, inv2h);
+    }
+    for (int d = 0; d < 3; ++d) u[3 * q + d] -= dt * grad[d];
+}
+
 } // namespace
+
+void launch_newton_kick(hipStream_t s, int n, const double *phiN, const double *pos, double *u, long np, double dt)
+{
+    if (np <= 0) return;
+    k_newton_kick<<<(unsigned)((np + TPB - 1) / TPB), TPB, 0, s>>>(phiN, n, 0.5 * n, pos, u, np, dt);
+}
 
 void launch_kick(hipStream_t s, int n, double a, double c, const double *Phi, const double *Psi,
                  const double *const beta[3], const double *pos, double *u, long np, double dt, int order)

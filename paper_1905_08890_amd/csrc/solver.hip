@@ -1091,6 +1091,45 @@ int gr_drift(gr_grid g, double *d_pos, const double *d_u, int64_t np, double dt)
     return GR_OK;
 }
 
+int gr_newtonian_kick(gr_grid g, const double *d_pos, double *d_u, int64_t np, double dt, const gr_solve_opts *opts,
+                      gr_solve_report *rep)
+{
+    g_err.clear();
+    CHK(check_particles(g, d_pos, d_u, np, dt));
+    CHK(check_opts(opts));
+    if (opts->guess == GR_GUESS_CHECKED) return fail(GR_EINVAL, "the Newtonian potential starts from zero");
+    WorkScope ws(g);
+    if (!ws.ok) return fail(GR_EDEVICE, "cannot join the work stream");
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = g->stream;
+    const long N = g->N();
+    double *phiN = g->A6[5]; // scratch until the next solve rebuilds A_ij
+    // Lap Phi_N = 3/2 a Om (s0 - <s0>) for periodic solvability, formed as
+    // 3/2 a Om (s0 - 1) minus its own mean (no cancellation of the mean against 1)
+    launch_ham_rhs(s, g->lev[0].f, g->src[0], N, 1.5 * g->prm.a * g->prm.omega_m);
+    CHK(reduce_mean(g, g->lev[0].f, nullptr, N, g->scal + S_SCRATCH));
+    launch_sub_scalar(s, g->lev[0].f, N, g->scal + S_SCRATCH);
+    launch_fill(s, phiN, N, 0.0);
+    LAUNCHCHK();
+    int cyc = 0, fb = 0;
+    double rel = 0.0;
+    int st = solve_field(g, GR_KIND_POISSON, phiN, *opts, &cyc, &rel, &fb);
+    if (st == GR_EDEVICE) return st;
+    launch_newton_kick(s, g->n, phiN, d_pos, d_u, (long)np, dt);
+    LAUNCHCHK();
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = fail(GR_EDEVICE, "sync: %s", hipGetErrorString(e));
+    if (rep) {
+        std::memset(rep, 0, sizeof *rep);
+        rep->status = st;
+        rep->cycles[0] = cyc;
+        rep->rel_res[0] = rel;
+        rep->fallback = fb;
+        rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return st;
+}
+
 int gr_set_field(gr_grid g, int field, const void *d_src, int dtype)
 {
     CHK(check_bound(g));

@@ -34,7 +34,7 @@ FIELD_IDS.update({f"hist_{name}": HIST + i for i, name in enumerate(SOLVED)})
 
 EXPORTS = ("gr_default_opts", "gr_create_grid", "gr_workspace_bytes", "gr_bind", "gr_deposit_sources",
            "gr_set_field", "gr_get_field", "gr_solve_constraints", "gr_solve_equation", "gr_solve_equation_static",
-           "gr_debug_sweep", "gr_kick", "gr_drift",
+           "gr_debug_sweep", "gr_kick", "gr_drift", "gr_newtonian_kick",
            "gr_debug_residual", "gr_destroy_grid", "gr_last_error", "gr_features", "gr_set_guess", "gr_autotune", "gr_sweep_timing", "gr_create_batch", "gr_create_batch_patches",
            "gr_batch_debug_boundary", "gr_batch_autotune", "gr_batch_workspace_bytes",
            "gr_batch_bind", "gr_batch_set_field", "gr_batch_get_field", "gr_batch_solve", "gr_destroy_batch",
@@ -109,6 +109,7 @@ def load_library(path: str = LIB_PATH):
         "gr_debug_sweep": [vp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int],
         "gr_kick": [vp, vp, vp, i64, C.c_double, C.c_int],
         "gr_drift": [vp, vp, vp, i64, C.c_double],
+        "gr_newtonian_kick": [vp, vp, vp, i64, C.c_double, C.POINTER(GrSolveOpts), C.POINTER(GrSolveReport)],
         "gr_debug_residual": [vp, C.c_int, C.c_int, C.c_double, C.c_double, vp],
         "gr_destroy_grid": [vp],
         "gr_features": [vp, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double), C.POINTER(C.c_double), vp,
@@ -253,6 +254,13 @@ def kick(g: int, pos, u, dt: float, order: int) -> None:
 
 def drift(g: int, pos, u, dt: float) -> None:
     _check(load_library().gr_drift(g, _ptr(pos), _ptr(u), int(pos.shape[0]), float(dt)))
+
+
+def newtonian_kick(g: int, pos, u, dt: float, opts: GrSolveOpts, allow=(OK,)) -> GrSolveReport:
+    r = GrSolveReport()
+    _check(load_library().gr_newtonian_kick(g, _ptr(pos), _ptr(u), int(pos.shape[0]), float(dt), C.byref(opts),
+                                            C.byref(r)), allow)
+    return r
 
 
 def debug_sweep(g: int, kind: int, field: int, Fbar: float, fshift: float, nsweeps: int) -> None:

@@ -191,3 +191,35 @@ def test_flrw_lattice_stays_at_rest():
     assert float(ud.abs().max()) < 1e-10
     d = (pd.cpu().numpy() - pos0 + 0.5) % 1.0 - 0.5
     assert np.abs(d).max() < 1e-12
+
+
+def test_newtonian_synchronisation_matches_oracle():
+    """The temporary synchronisation of sec. 4.5: from the deposited s0, the
+    Newtonian potential (equal cycle counts) and the half kick u_N = u -
+    dt/2 grad Phi_N against the oracle; the sources deposited with u_N against
+    the oracle's; the velocities restored from the caller's copy are the
+    originals bit for bit (the exact revert)."""
+    n = 32
+    dt = 0.02
+    prm = dict(a=1.0, omega_m=synth.OMEGA_M, c_tilde=synth.C_TILDE)
+    p = O.params(**prm)
+    pos, u, mass = synth.zeldovich(n, 3, 0.5)
+    u = 50.0 * u
+    g = grmg.Grid(n, **prm)
+    pd, ud = _dev(pos), _dev(u)
+    g.deposit_sources(pd, ud, mass)
+    u_save = ud.clone()
+    rep = grmg.newtonian_kick(g.handle, pd, ud, dt / 2, grmg.default_opts(rtol=1e-10))
+    assert rep.status == grmg.OK and rep.cycles[0] > 0
+    src = O.cic_deposit(n, pos, u, mass, prm=p)
+    uN, phiN, st, cyc = O.newtonian_kick(src[0], pos, u, dt / 2, prm=p, rtol=0.0, max_cycles=rep.cycles[0])
+    assert st == O.OK and cyc == rep.cycles[0]
+    ulp4 = 4.0 * np.finfo(np.float64).eps * np.abs(uN).max()
+    assert np.abs((ud.cpu().numpy() - u) - (uN - u)).max() <= 1e-12 * np.abs(uN - u).max() + ulp4
+    g.deposit_sources(pd, ud, mass)
+    src_N = O.cic_deposit(n, pos, uN, mass, prm=p)
+    for k, name in enumerate(("s0", "sx", "sy", "sz", "sm")):
+        got = g.get_field(name).cpu().numpy()
+        assert np.abs(got - src_N[k]).max() <= 1e-12 * np.abs(src_N[k]).max(), name
+    ud.copy_(u_save)
+    assert torch.equal(ud, _dev(u))
