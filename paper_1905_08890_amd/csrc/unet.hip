@@ -37,53 +37,86 @@ __device__ __forceinline__ int wrapn(int i, int n) { return i < 0 ? i + n : (i >
 
 // out[v][ocoff + co] = act(bias[co] + sum_k in[v + off(tap)][icoff + ci] w[co][k]),
 // k = tap * cin + ci, taps ordered (dz, dy, dx) in {-1,0,1}^3 with dx fastest.
-// One wave: 16 consecutive voxels x all COUT channels.  n^3 must be a multiple
-// of 64 (4 waves per block).
-template <int COUT, bool RELU, bool BIAS>
+// One wave: VG groups of 16 consecutive voxels x all COUT channels, so each
+// weight operand (B) feeds VG matrix-core products.  Each lane's 8 K entries
+// lie in one tap (cin % 8 == 0); the lane's (tap, channel) and tap offsets are
+// advanced incrementally along K (no integer division in the loop).  n^3 must
+// be a multiple of 64 VG (4 waves per block).
+template <int COUT, int VG, bool RELU, bool BIAS>
 __global__ void __launch_bounds__(256) k_conv3(const bf16 *__restrict__ in, int cin, int icstride, int icoff,
                                                const bf16 *__restrict__ w, int kpad, const float *__restrict__ bias,
                                                bf16 *__restrict__ out, int ocstride, int ocoff, int n)
 {
     constexpr int NT = COUT / 16;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int v0 = (blockIdx.x * 4 + wave) * 16;
+    const int v0 = (blockIdx.x * 4 + wave) * 16 * VG;
     const int i = lane & 15, g = lane >> 4;
-    const int v = v0 + i;
-    const int x = v % n, y = (v / n) % n, z = v / (n * n);
-    floatx4 acc[NT];
+    int xs[VG], ys[VG], zs[VG];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < VG; ++q) {
+        const int v = v0 + 16 * q + i;
+        xs[q] = v % n;
+        ys[q] = (v / n) % n;
+        zs[q] = v / (n * n);
+    }
+    floatx4 acc[VG][NT];
+#pragma unroll
+    for (int q = 0; q < VG; ++q)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[q][t] = floatx4{0.f, 0.f, 0.f, 0.f};
     const int ktot = 27 * cin;
+    // this lane's first K entry 8 g: tap and channel, and the tap's offsets
+    int ci = 8 * g, tap = 0;
+    while (ci >= cin) {
+        ci -= cin;
+        ++tap;
+    }
+    int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
     for (int k0c = 0; k0c < kpad; k0c += 32) {
         const int k0 = k0c + 8 * g;
-        bf16x8 a;
-        if (k0 < ktot) {
-            const int tap = k0 / cin, ci = k0 - tap * cin;
-            const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
-            const long nv = ((long)wrapn(z + dz, n) * n + wrapn(y + dy, n)) * n + wrapn(x + dx, n);
-            a = *reinterpret_cast<const bf16x8 *>(in + nv * icstride + icoff + ci);
-        } else {
+        bf16x8 bw[NT];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) a[j] = (bf16)0.0f;
+        for (int t = 0; t < NT; ++t) bw[t] = *reinterpret_cast<const bf16x8 *>(w + (long)(16 * t + i) * kpad + k0);
+#pragma unroll
+        for (int q = 0; q < VG; ++q) {
+            bf16x8 a;
+            if (k0 < ktot) {
+                const long nv = ((long)wrapn(zs[q] + dz, n) * n + wrapn(ys[q] + dy, n)) * n + wrapn(xs[q] + dx, n);
+                a = *reinterpret_cast<const bf16x8 *>(in + nv * icstride + icoff + ci);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) a[j] = (bf16)0.0f;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[t], acc[q][t], 0, 0, 0);
         }
+        // advance this lane's K entry by 32
+        ci += 32;
+        while (ci >= cin) {
+            ci -= cin;
+            if (++dx > 1) {
+                dx = -1;
+                if (++dy > 1) {
+                    dy = -1;
+                    ++dz;
+                }
+            }
+        }
+    }
+    // lane holds D[4g + j][i]: voxel v0 + 16 q + 4g + j, channel 16t + i
+#pragma unroll
+    for (int q = 0; q < VG; ++q)
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(w + (long)(16 * t + i) * kpad + k0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, acc[t], 0, 0, 0);
-        }
-    }
-    // lane holds D[4g + j][i]: voxel v0 + 4g + j, channel 16t + i
+            const int co = 16 * t + i;
+            const float b = BIAS ? bias[co] : 0.0f;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int co = 16 * t + i;
-        const float b = BIAS ? bias[co] : 0.0f;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            float r = acc[t][j] + b;
-            if (RELU) r = r > 0.0f ? r : 0.0f;
-            out[(long)(v0 + 4 * g + j) * ocstride + ocoff + co] = (bf16)r;
+            for (int j = 0; j < 4; ++j) {
+                float r = acc[q][t][j] + b;
+                if (RELU) r = r > 0.0f ? r : 0.0f;
+                out[(long)(v0 + 16 * q + 4 * g + j) * ocstride + ocoff + co] = (bf16)r;
+            }
         }
-    }
 }
 
 // Weight gradient of a 3^3 convolution on the BF16 matrix cores:
@@ -412,15 +445,25 @@ __global__ void __launch_bounds__(TPB) k_head_bwd(const float *__restrict__ gy, 
     }
 }
 
-__global__ void k_head_reduce(const float *__restrict__ part, int nblk, int npar, int nw, float *__restrict__ dw,
-                              float *__restrict__ db)
+// one block per parameter: thread t adds partials t, t + 256, ... in order,
+// then a fixed tree over the threads (deterministic)
+__global__ void __launch_bounds__(TPB) k_head_reduce(const float *__restrict__ part, int nblk, int npar, int nw,
+                                                     float *__restrict__ dw, float *__restrict__ db)
 {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= npar) return;
+    __shared__ float sh[TPB];
+    const int q = blockIdx.x;
     float s = 0.0f;
-    for (int b = 0; b < nblk; ++b) s += part[(long)b * npar + q];
-    if (q < nw) dw[q] += s;
-    else db[q - nw] += s;
+    for (int b = threadIdx.x; b < nblk; b += TPB) s += part[(long)b * npar + q];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = TPB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (q < nw) dw[q] += sh[0];
+        else db[q - nw] += sh[0];
+    }
 }
 
 // FP32 master weights -> BF16 forward layout [co][kpad] and the flipped /
@@ -557,9 +600,15 @@ bool launch_conv_t(hipStream_t s, int cout, const bf16 *in, int cin, int ics, in
                    const float *bias, bf16 *out, int ocs, int ocoff, int n)
 {
     const long N = (long)n * n * n;
-    const unsigned grid = (unsigned)(N / 64);
+    // four voxel groups per wave where the grid allows it (two for the widest outputs), else one
+    const int vg = (N % 256 == 0) ? (cout >= 96 ? 2 : 4) : 1;
+    const unsigned grid = (unsigned)(N / (64 * vg));
 #define CONV_CASE(C)                                                                                  \
-    case C: k_conv3<C, RELU, BIAS><<<grid, 256, 0, s>>>(in, cin, ics, icoff, w, kpad, bias, out, ocs, ocoff, n); break;
+    case C:                                                                                           \
+        if (vg == 4) k_conv3<C, 4, RELU, BIAS><<<grid, 256, 0, s>>>(in, cin, ics, icoff, w, kpad, bias, out, ocs, ocoff, n); \
+        else if (vg == 2) k_conv3<C, 2, RELU, BIAS><<<grid, 256, 0, s>>>(in, cin, ics, icoff, w, kpad, bias, out, ocs, ocoff, n); \
+        else k_conv3<C, 1, RELU, BIAS><<<grid, 256, 0, s>>>(in, cin, ics, icoff, w, kpad, bias, out, ocs, ocoff, n); \
+        break;
     switch (cout) {
         CONV_CASE(16)
         CONV_CASE(32)
@@ -781,8 +830,8 @@ int backward(gr_unet U, int n)
         const unsigned nblk = nb(N);
         k_head_bwd<<<nblk, TPB, 0, s>>>(U->gy, U->db[0].p, c[0], U->param + U->head_w, U->d.out_ch, U->g_db[0].p,
                                         U->wg_part, N);
-        k_head_reduce<<<nb(npar), TPB, 0, s>>>(U->wg_part, (int)nblk, npar, nw, U->grad + U->head_w,
-                                               U->grad + U->head_b);
+        k_head_reduce<<<(unsigned)npar, TPB, 0, s>>>(U->wg_part, (int)nblk, npar, nw, U->grad + U->head_w,
+                                                     U->grad + U->head_b);
         ULAUNCH();
     }
     // decoder, fine to coarse: each level's concat gradient feeds the next coarser output
