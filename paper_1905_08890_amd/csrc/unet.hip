@@ -5,10 +5,9 @@
 //
 // Layout: activations channels-last [z][y][x][C] in BF16, periodic boundaries
 // (the fields live on a periodic box).  Convolutions are implicit GEMMs on the
-// BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation):
-// M = 16 voxels per wave, N = output channels (16 per tile), K = 27 taps x
-// input channels, padded to a multiple of 32; each lane feeds 8 consecutive
-// input channels of one tap (a 16-byte load).  The input-gradient of a
+// BF16 matrix cores (FP32 accumulation): M = 16 voxels per product, N =
+// output channels (16 per tile), K = 27 taps x input channels (weight rows
+// padded to a multiple of 32).  The input-gradient of a
 // convolution is the same kernel applied to the output-gradient with the
 // weights flipped in space and transposed in channels.  Weight gradients
 // accumulate in FP32; Adam keeps FP32 master weights.
@@ -26,6 +25,7 @@
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -38,71 +38,84 @@ __device__ __forceinline__ int wrapn(int i, int n) { return i < 0 ? i + n : (i >
 // out[v][ocoff + co] = act(bias[co] + sum_k in[v + off(tap)][icoff + ci] w[co][k]),
 // k = tap * cin + ci, taps ordered (dz, dy, dx) in {-1,0,1}^3 with dx fastest.
 // One wave: VG groups of 16 consecutive voxels x all COUT channels, so each
-// weight operand (B) feeds VG matrix-core products.  Each lane's 8 K entries
-// lie in one tap (cin % 8 == 0); the lane's (tap, channel) and tap offsets are
-// advanced incrementally along K (no integer division in the loop).  n^3 must
-// be a multiple of 64 VG (4 waves per block).
-template <int COUT, int VG, bool RELU, bool BIAS>
+// weight operand (B) feeds VG matrix-core products.  The 27 taps are unrolled
+// (every lane of a product works on the same tap) and each tap runs over the
+// input channels in steps of KS = 32 (v_mfma_f32_16x16x32_bf16, 8 channels per
+// lane) when cin % 32 == 0, else KS = 16 (v_mfma_f32_16x16x16_bf16, 4 channels
+// per lane); a lane's neighbour rows are formed once, so the inner loop is
+// loads and matrix products.  n^3 must be a multiple of 64 VG (4 waves per
+// block) and cin a multiple of KS.
+template <int KS> struct ConvOperand;
+template <> struct ConvOperand<32> {
+    typedef bf16x8 type;
+    static __device__ __forceinline__ floatx4 mfma(type a, type b, floatx4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct ConvOperand<16> {
+    typedef shortx4 type;
+    static __device__ __forceinline__ floatx4 mfma(type a, type b, floatx4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    }
+};
+
+template <int COUT, int VG, int KS, bool RELU, bool BIAS>
 __global__ void __launch_bounds__(256) k_conv3(const bf16 *__restrict__ in, int cin, int icstride, int icoff,
                                                const bf16 *__restrict__ w, int kpad, const float *__restrict__ bias,
                                                bf16 *__restrict__ out, int ocstride, int ocoff, int n)
 {
-    constexpr int NT = COUT / 16;
+    typedef ConvOperand<KS> Op;
+    typedef typename Op::type opT;
+    constexpr int NT = COUT / 16, PER = KS / 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int v0 = (blockIdx.x * 4 + wave) * 16 * VG;
     const int i = lane & 15, g = lane >> 4;
-    int xs[VG], ys[VG], zs[VG];
+    // neighbour coordinates of this lane's voxel in each group: x, y * n, z * n^2
+    int xo[VG][3], yo[VG][3], zo[VG][3];
 #pragma unroll
     for (int q = 0; q < VG; ++q) {
         const int v = v0 + 16 * q + i;
-        xs[q] = v % n;
-        ys[q] = (v / n) % n;
-        zs[q] = v / (n * n);
+        const int x = v % n, y = (v / n) % n, z = v / (n * n);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            xo[q][d] = wrapn(x + d - 1, n);
+            yo[q][d] = wrapn(y + d - 1, n) * n;
+            zo[q][d] = wrapn(z + d - 1, n) * n * n;
+        }
     }
     floatx4 acc[VG][NT];
 #pragma unroll
     for (int q = 0; q < VG; ++q)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[q][t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int ktot = 27 * cin;
-    // this lane's first K entry 8 g: tap and channel, and the tap's offsets
-    int ci = 8 * g, tap = 0;
-    while (ci >= cin) {
-        ci -= cin;
-        ++tap;
-    }
-    int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
-    for (int k0c = 0; k0c < kpad; k0c += 32) {
-        const int k0 = k0c + 8 * g;
-        bf16x8 bw[NT];
+    const bf16 *wl = w + (long)i * kpad + PER * g;
+    const long wstep = (long)16 * kpad;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) bw[t] = *reinterpret_cast<const bf16x8 *>(w + (long)(16 * t + i) * kpad + k0);
+    for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
-        for (int q = 0; q < VG; ++q) {
-            bf16x8 a;
-            if (k0 < ktot) {
-                const long nv = ((long)wrapn(zs[q] + dz, n) * n + wrapn(ys[q] + dy, n)) * n + wrapn(xs[q] + dx, n);
-                a = *reinterpret_cast<const bf16x8 *>(in + nv * icstride + icoff + ci);
-            } else {
+        for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-                for (int j = 0; j < 8; ++j) a[j] = (bf16)0.0f;
-            }
+            for (int dx = 0; dx < 3; ++dx) {
+                const int tap = (dz * 3 + dy) * 3 + dx;
+                const bf16 *src[VG];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[t], acc[q][t], 0, 0, 0);
-        }
-        // advance this lane's K entry by 32
-        ci += 32;
-        while (ci >= cin) {
-            ci -= cin;
-            if (++dx > 1) {
-                dx = -1;
-                if (++dy > 1) {
-                    dy = -1;
-                    ++dz;
+                for (int q = 0; q < VG; ++q)
+                    src[q] = in + (long)(zo[q][dz] + yo[q][dy] + xo[q][dx]) * icstride + icoff + PER * g;
+                const bf16 *wt = wl + tap * cin;
+                for (int c0 = 0; c0 < cin; c0 += KS) {
+                    opT bw[NT];
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) bw[t] = *reinterpret_cast<const opT *>(wt + t * wstep + c0);
+#pragma unroll
+                    for (int q = 0; q < VG; ++q) {
+                        const opT a = *reinterpret_cast<const opT *>(src[q] + c0);
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) acc[q][t] = Op::mfma(a, bw[t], acc[q][t]);
+                    }
                 }
             }
-        }
-    }
     // lane holds D[4g + j][i]: voxel v0 + 16 q + 4g + j, channel 16t + i
 #pragma unroll
     for (int q = 0; q < VG; ++q)
@@ -117,6 +130,131 @@ __global__ void __launch_bounds__(256) k_conv3(const bf16 *__restrict__ in, int 
                 out[(long)(v0 + 16 * q + 4 * g + j) * ocstride + ocoff + co] = (bf16)r;
             }
         }
+}
+
+// The same convolution with the input staged in LDS: one block computes a
+// 16 (x) x 4 (y) x 4 (z) tile of output voxels; wave w takes the plane z0 + w
+// and its product group q the row y0 + q.  For each chunk of CW input
+// channels the block copies the tile's 18 x 6 x 6 input halo into LDS (voxel
+// stride CW + 8 elements, so the 16-byte reads of 8 consecutive lanes fall in
+// distinct banks), then every tap reads its operand at a constant offset from
+// the lane's base.  CW = 32: one v_mfma_f32_16x16x32_bf16 per tap, all lanes
+// on the same tap.  CW = 16: taps go in pairs, lanes g < 2 on the first and
+// g >= 2 on the second (8 channels each), the unpaired 27th tap padded with
+// zeros.  n must be a multiple of 16 and cin of CW.
+constexpr int CT_HX = 18, CT_HY = 6, CT_HZ = 6, CT_HV = CT_HX * CT_HY * CT_HZ;
+
+template <int COUT, int CW, bool RELU, bool BIAS>
+__global__ void __launch_bounds__(256) k_conv3_lds(const bf16 *__restrict__ in, int cin, int icstride, int icoff,
+                                                   const bf16 *__restrict__ w, int kpad,
+                                                   const float *__restrict__ bias, bf16 *__restrict__ out,
+                                                   int ocstride, int ocoff, int n)
+{
+    constexpr int NT = COUT / 16, STR = CW + 8, UPV = CW / 8, NU = CT_HV * UPV, PERT = (NU + 255) / 256;
+    __shared__ __align__(16) bf16 tile[CT_HV * STR];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, g = lane >> 4;
+    // blocks in contiguous runs per XCD (dispatch is round-robin over the 8 XCDs)
+    const int nblk = gridDim.x;
+    int b = blockIdx.x;
+    if (nblk % 8 == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+    const int tx = n >> 4, ty = n >> 2;
+    const int X0 = (b % tx) * 16, Y0 = ((b / tx) % ty) * 4, Z0 = (b / tx / ty) * 4;
+    floatx4 acc[4][NT];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[q][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const bool hi = g >= 2;
+    const int lbase = (wave * CT_HY * CT_HX + i) * STR + (CW == 32 ? 8 * g : 8 * (g & 1));
+    const bf16 *wl = w + (long)i * kpad + (CW == 32 ? 8 * g : 8 * (g & 1));
+    const long wstep = (long)16 * kpad;
+    for (int c0 = 0; c0 < cin; c0 += CW) {
+        bf16x8 stage[PERT];
+#pragma unroll
+        for (int r = 0; r < PERT; ++r) {
+            const int u = threadIdx.x + 256 * r;
+            if (u < NU) {
+                const int h = u / UPV, cu = u % UPV;
+                const int hx = h % CT_HX, hy = (h / CT_HX) % CT_HY, hz = h / (CT_HX * CT_HY);
+                const long src = ((long)wrapn(Z0 - 1 + hz, n) * n + wrapn(Y0 - 1 + hy, n)) * n + wrapn(X0 - 1 + hx, n);
+                stage[r] = *reinterpret_cast<const bf16x8 *>(in + src * icstride + icoff + c0 + 8 * cu);
+            }
+        }
+        __syncthreads(); // the previous chunk's reads are done
+#pragma unroll
+        for (int r = 0; r < PERT; ++r) {
+            const int u = threadIdx.x + 256 * r;
+            if (u < NU) *reinterpret_cast<bf16x8 *>(tile + (u / UPV) * STR + 8 * (u % UPV)) = stage[r];
+        }
+        __syncthreads();
+        if (CW == 32) {
+            // rows (dz, dy) in a loop, the three dx of a row unrolled
+#pragma unroll 1
+            for (int r = 0; r < 9; ++r) {
+                const int roff = ((r / 3) * CT_HY + r % 3) * CT_HX * STR;
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) {
+                    const int tap = 3 * r + dx;
+                    bf16x8 bw[NT];
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        bw[t] = *reinterpret_cast<const bf16x8 *>(wl + t * wstep + tap * cin + c0);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const bf16x8 a =
+                            *reinterpret_cast<const bf16x8 *>(tile + lbase + q * CT_HX * STR + roff + dx * STR);
+#pragma unroll
+                        for (int t = 0; t < NT; ++t)
+                            acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[t], acc[q][t], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+#pragma unroll 1
+            for (int m = 0; m < 14; ++m) {
+                const int tap = 2 * m + (hi ? 1 : 0);
+                const bool valid = tap < 27;
+                const int toff = (((tap / 9) * CT_HY + (tap / 3) % 3) * CT_HX + tap % 3) * STR;
+                const int wk = tap * cin + c0;
+                bf16x8 bw[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    if (valid) bw[t] = *reinterpret_cast<const bf16x8 *>(wl + t * wstep + wk);
+                    else
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) bw[t][j] = (bf16)0.0f;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    bf16x8 a;
+                    if (valid) a = *reinterpret_cast<const bf16x8 *>(tile + lbase + q * CT_HX * STR + toff);
+                    else
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) a[j] = (bf16)0.0f;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[t], acc[q][t], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // lane holds D[4g + j][i]: voxel (X0 + 4g + j, Y0 + q, Z0 + wave), channel 16t + i
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const long vrow = ((long)(Z0 + wave) * n + (Y0 + q)) * n + X0 + 4 * g;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int co = 16 * t + i;
+            const float bb = BIAS ? bias[co] : 0.0f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float r = acc[q][t][j] + bb;
+                if (RELU) r = r > 0.0f ? r : 0.0f;
+                out[(vrow + j) * ocstride + ocoff + co] = (bf16)r;
+            }
+        }
+    }
 }
 
 // Weight gradient of a 3^3 convolution on the BF16 matrix cores:
@@ -595,19 +733,50 @@ int pad32(int k) { return (k + 31) / 32 * 32; }
 
 constexpr int kWgradBlocks = 64; // voxel-chunk blocks per tap of the weight gradient
 
+template <int COUT, int VG, bool RELU, bool BIAS>
+void launch_conv_ks(hipStream_t s, unsigned grid, const bf16 *in, int cin, int ics, int icoff, const bf16 *w, int kpad,
+                    const float *bias, bf16 *out, int ocs, int ocoff, int n)
+{
+    if (cin % 32 == 0)
+        k_conv3<COUT, VG, 32, RELU, BIAS><<<grid, 256, 0, s>>>(in, cin, ics, icoff, w, kpad, bias, out, ocs, ocoff, n);
+    else
+        k_conv3<COUT, VG, 16, RELU, BIAS><<<grid, 256, 0, s>>>(in, cin, ics, icoff, w, kpad, bias, out, ocs, ocoff, n);
+}
+
 template <bool RELU, bool BIAS>
 bool launch_conv_t(hipStream_t s, int cout, const bf16 *in, int cin, int ics, int icoff, const bf16 *w, int kpad,
                    const float *bias, bf16 *out, int ocs, int ocoff, int n)
 {
     const long N = (long)n * n * n;
+    if (cin % 16 || N % 64 || N >= (1L << 31)) return false;
+    if (n % 16 == 0) {
+        const unsigned gl = (unsigned)((n / 16) * (n / 4) * (n / 4));
+#define CONV_LDS(C)                                                                                           \
+    case C:                                                                                                   \
+        if (cin % 32 == 0)                                                                                    \
+            k_conv3_lds<C, 32, RELU, BIAS><<<gl, 256, 0, s>>>(in, cin, ics, icoff, w, kpad, bias, out, ocs, ocoff, n); \
+        else                                                                                                  \
+            k_conv3_lds<C, 16, RELU, BIAS><<<gl, 256, 0, s>>>(in, cin, ics, icoff, w, kpad, bias, out, ocs, ocoff, n); \
+        return true;
+        switch (cout) {
+            CONV_LDS(16)
+            CONV_LDS(32)
+            CONV_LDS(48)
+            CONV_LDS(64)
+            CONV_LDS(96)
+            CONV_LDS(128)
+        default: return false;
+        }
+#undef CONV_LDS
+    }
     // four voxel groups per wave where the grid allows it (two for the widest outputs), else one
     const int vg = (N % 256 == 0) ? (cout >= 96 ? 2 : 4) : 1;
     const unsigned grid = (unsigned)(N / (64 * vg));
-#define CONV_CASE(C)                                                                                  \
-    case C:                                                                                           \
-        if (vg == 4) k_conv3<C, 4, RELU, BIAS><<<grid, 256, 0, s>>>(in, cin, ics, icoff, w, kpad, bias, out, ocs, ocoff, n); \
-        else if (vg == 2) k_conv3<C, 2, RELU, BIAS><<<grid, 256, 0, s>>>(in, cin, ics, icoff, w, kpad, bias, out, ocs, ocoff, n); \
-        else k_conv3<C, 1, RELU, BIAS><<<grid, 256, 0, s>>>(in, cin, ics, icoff, w, kpad, bias, out, ocs, ocoff, n); \
+#define CONV_CASE(C)                                                                                          \
+    case C:                                                                                                   \
+        if (vg == 4) launch_conv_ks<C, 4, RELU, BIAS>(s, grid, in, cin, ics, icoff, w, kpad, bias, out, ocs, ocoff, n); \
+        else if (vg == 2) launch_conv_ks<C, 2, RELU, BIAS>(s, grid, in, cin, ics, icoff, w, kpad, bias, out, ocs, ocoff, n); \
+        else launch_conv_ks<C, 1, RELU, BIAS>(s, grid, in, cin, ics, icoff, w, kpad, bias, out, ocs, ocoff, n); \
         break;
     switch (cout) {
         CONV_CASE(16)

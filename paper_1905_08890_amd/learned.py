@@ -377,7 +377,11 @@ def main(argv=None):
     ap.add_argument("--eval-seed0", type=int, default=2000)
     ap.add_argument("--eval-steps", type=int, default=4)
     ap.add_argument("--eval-json", default="")
+    ap.add_argument("--eval-only", action="store_true", help="evaluate the weights at --out without training")
     a = ap.parse_args(argv)
+    if a.eval_only:
+        evaluate_saved(a, torch)
+        return
     t0 = time.time()
     xs, ys = generate(a.n, range(a.seed0, a.seed0 + a.seeds), a.steps, a.r0, a.level, torch)
     norm = fit_normaliser(xs, ys)
@@ -393,15 +397,22 @@ def main(argv=None):
     save(a.out, net, norm, a.level, meta)
     log(f"saved {a.out} after {time.time() - t0:.0f} s")
     if a.eval_seeds > 0:
-        g = LearnedGuess(a.out, a.n, torch)
-        ctl = LearnedGuess(a.out, a.n, torch)
-        ctl.net.init(a.seed0 + 777)  # same normaliser, untrained weights
-        res = evaluate(g, a.n, range(a.eval_seed0, a.eval_seed0 + a.eval_seeds), a.eval_steps, a.r0, torch,
-                       control=ctl)
-        print(json.dumps(summarise(res)), flush=True)
-        if a.eval_json:
-            with open(a.eval_json, "w") as fh:
-                json.dump(dict(summary=summarise(res), rows=res), fh, indent=1)
+        evaluate_saved(a, torch)
+
+
+def evaluate_saved(a, torch):
+    """Held-out evaluation of the weights at `a.out` (see `evaluate`)."""
+    g = LearnedGuess(a.out, a.n, torch)
+    ctl = LearnedGuess(a.out, a.n, torch)
+    ctl.net.init(a.seed0 + 777)  # same normaliser, untrained weights
+    seeds = range(a.eval_seed0, a.eval_seed0 + a.eval_seeds)
+    res = evaluate(g, a.n, seeds, a.eval_steps, a.r0, torch, control=ctl)
+    summary = summarise(res)
+    summary["eval"] = dict(seeds=[seeds[0], seeds[-1]], steps=a.eval_steps, weights=os.path.basename(a.out))
+    print(json.dumps(summary), flush=True)
+    if a.eval_json:
+        with open(a.eval_json, "w") as fh:
+            json.dump(dict(summary=summary, rows=res), fh, indent=1)
 
 
 if __name__ == "__main__":
