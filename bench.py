@@ -267,6 +267,43 @@ def unet_only(torch, grmg, m, reps):
                       **out}), flush=True)
 
 
+def vector_modes(torch, grmg, g, n, reps=5):
+    """Vector-mode extraction (curl, divergence, FFTs, shell spectra up to a
+    quarter of Nyquist) of the solved shift beta^i and of the momentum density
+    s_i on the bench grid; the FFT's per-pass rate from one 3-D transform of a
+    complex n^3 array (each pass reads and writes 16 B per point)."""
+    S = grmg.Spectra(n, n // 8, stream=g.stream)
+    res = {"workload": f"beta^i and s_i of the {n}^3 step, {n // 8} shells (a quarter of Nyquist), FP64"}
+    for name, ids in (("beta", (grmg.BETAX, grmg.BETAY, grmg.BETAZ)), ("s", (grmg.SX, grmg.SY, grmg.SZ))):
+        f = [g.get_field(i) for i in ids]
+        spec = S.vector(*f)
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            spec = S.vector(*f)
+            ts.append(time.perf_counter() - t0)
+        res[f"{name}_ms"] = round(sorted(ts)[len(ts) // 2] * 1e3, 3)
+        res[f"{name}_shell0"] = {"k": round(float(spec[0, 0]), 4), "modes": int(spec[1, 0]),
+                                 "p_vector": float(f"{spec[4, 0]:.4e}"), "p_scalar": float(f"{spec[5, 0]:.4e}")}
+        del f
+    buf = torch.zeros((n, n, n), dtype=torch.complex128, device=g.device)
+    S.fft(buf)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lib = grmg.load_library()
+    e0.record(g.stream)
+    for _ in range(reps):
+        assert lib.gr_spectra_fft(S.handle, buf.data_ptr()) == grmg.OK
+    e1.record(g.stream)
+    e1.synchronize()
+    t_pass = e0.elapsed_time(e1) * 1e-3 / (3 * reps)
+    res["fft_pass_us"] = round(t_pass * 1e6, 1)
+    res["fft_pass_GBps"] = round(32.0 * n ** 3 / t_pass / 1e9, 1)
+    del buf
+    S.close()
+    return res
+
+
 def c1_workload(torch, grmg, synth):
     """The 32^3 Hamiltonian-only solve (s0 = 1 + k^-2 GRF, sigma 0.1, seed 0;
     V(2,2) from Psi = 0 to 1e-10): launch-latency bound on the GPU."""
@@ -581,6 +618,8 @@ def main():
     traffic = pmc_traffic(n)
     if traffic is not None:
         out["roofline"]["traffic"] = traffic
+    log("vector modes of the solved shift and momentum density")
+    out["vector_modes"] = vector_modes(torch, grmg, g, n)
     g.close()
     del d_pos, d_u
     c1, c1_src = c1_workload(torch, grmg, synth)

@@ -439,6 +439,40 @@ int gr_unet_train_step(gr_unet u, int n, const float *d_in, const float *d_targe
 int gr_destroy_unet(gr_unet u);
 const char *gr_unet_last_error(void);
 
+/* ---- vector-mode extraction (sec. 6.2, the shift-vector power spectrum) ----
+ * The shift beta^i (also B^i, and the momentum density s_i that sources it)
+ * carries a scalar and a vector mode; a discrete curl removes the scalar
+ * mode and k^2 P_V(k) = P_curl(k) gives the vector mode's power.
+ * gr_vector_spectra takes three real FP64 fields v_x, v_y, v_z on the
+ * periodic unit box (device arrays [z][y][x], x fastest, n^3 each, e.g. from
+ * gr_get_field of GR_BETAX.., GR_BX.. or GR_SX..), forms the curl and the
+ * divergence by 3-point central differences, transforms them with a 3-D FFT
+ * on the device (F[g](m) = sum_x g(x) exp(-2 pi i m.x), integer m, k = 2 pi m)
+ * and bins the modes in shells: shell j (0 <= j < nbins) holds the modes with
+ * j + 1/2 <= |m| < j + 3/2.  Per mode P_curl = sum_i |F[(curl v)_i]|^2 / N^2,
+ * P_div = |F[div v]|^2 / N^2 (N = n^3, box volume 1), and the vector- and
+ * scalar-mode power of v itself P_vector = P_curl / |k_eff|^2, P_scalar =
+ * P_div / |k_eff|^2 with k_eff,i = n sin(2 pi m_i / n), the central
+ * difference's symbol (so P_vector + P_scalar is v's own power per mode).
+ * h_out (host, [6][nbins]) receives per shell the mean |k|, the mode count,
+ * and the means of P_curl, P_div, P_vector, P_scalar over its modes.  nbins =
+ * n / 8 reaches a quarter of the Nyquist wave number pi n.
+ * Handle: n a power of two in [8, 1024], 1 <= nbins <= n / 4; the workspace
+ * (two complex n^3 arrays plus small tables, gr_spectra_workspace_bytes,
+ * 256-byte aligned) is the caller's.  gr_vector_spectra runs on the bound
+ * stream and synchronises it before returning; the results are deterministic
+ * (fixed summation order).  gr_spectra_fft: in-place forward 3-D FFT of an
+ * n^3 complex array (interleaved re, im doubles) with the same kernels.
+ * Errors: GR_EINVAL (null, sizes, alignment), GR_ESTATE (unbound), GR_EDEVICE. */
+typedef struct gr_spectra_s *gr_spectra;
+int gr_create_spectra(int n, int nbins, gr_spectra *out);
+int gr_spectra_workspace_bytes(gr_spectra s, size_t *bytes);
+int gr_spectra_bind(gr_spectra s, void *d_workspace, size_t bytes, void *hip_stream);
+int gr_vector_spectra(gr_spectra s, const double *d_vx, const double *d_vy, const double *d_vz, double *h_out);
+int gr_spectra_fft(gr_spectra s, double *d_data);
+int gr_destroy_spectra(gr_spectra s);
+const char *gr_spectra_last_error(void);
+
 /* Destroy a handle (the workspace stays the caller's). NULL is accepted. */
 int gr_destroy_grid(gr_grid g);
 

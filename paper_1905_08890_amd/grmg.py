@@ -40,7 +40,9 @@ EXPORTS = ("gr_default_opts", "gr_create_grid", "gr_workspace_bytes", "gr_bind",
            "gr_batch_bind", "gr_batch_set_field", "gr_batch_get_field", "gr_batch_solve", "gr_destroy_batch",
            "gr_batch_last_error", "gr_unet_create", "gr_unet_workspace_bytes", "gr_unet_param_count", "gr_unet_bind",
            "gr_unet_init", "gr_unet_set_params", "gr_unet_get_params", "gr_unet_forward", "gr_unet_loss_grad",
-           "gr_unet_train_step", "gr_destroy_unet", "gr_unet_last_error")
+           "gr_unet_train_step", "gr_destroy_unet", "gr_unet_last_error", "gr_create_spectra",
+           "gr_spectra_workspace_bytes", "gr_spectra_bind", "gr_vector_spectra", "gr_spectra_fft", "gr_destroy_spectra",
+           "gr_spectra_last_error")
 
 
 class GrParams(C.Structure):
@@ -140,6 +142,12 @@ def load_library(path: str = LIB_PATH):
         "gr_unet_loss_grad": [vp, C.c_int, vp, vp, vp, C.POINTER(C.c_double)],
         "gr_unet_train_step": [vp, C.c_int, vp, vp, C.c_float, C.POINTER(C.c_double)],
         "gr_destroy_unet": [vp],
+        "gr_create_spectra": [C.c_int, C.c_int, C.POINTER(vp)],
+        "gr_spectra_workspace_bytes": [vp, C.POINTER(C.c_size_t)],
+        "gr_spectra_bind": [vp, vp, C.c_size_t, vp],
+        "gr_vector_spectra": [vp, vp, vp, vp, C.POINTER(C.c_double)],
+        "gr_spectra_fft": [vp, vp],
+        "gr_destroy_spectra": [vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -151,6 +159,8 @@ def load_library(path: str = LIB_PATH):
     lib.gr_batch_last_error.restype = C.c_char_p
     lib.gr_unet_last_error.argtypes = []
     lib.gr_unet_last_error.restype = C.c_char_p
+    lib.gr_spectra_last_error.argtypes = []
+    lib.gr_spectra_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -596,3 +606,75 @@ class UNet:
         _ucheck(load_library().gr_unet_train_step(self.handle, x.shape[-1], x.data_ptr(), t.data_ptr(), lr,
                                                   C.byref(loss)))
         return loss.value
+
+
+# ---- vector-mode extraction ----
+
+SPECTRA_ROWS = ("k", "count", "p_curl", "p_div", "p_vector", "p_scalar")
+
+
+def spectra_last_error() -> str:
+    return load_library().gr_spectra_last_error().decode()
+
+
+def _scheck(code: int):
+    if code != OK:
+        raise GrError(code, spectra_last_error())
+    return code
+
+
+class Spectra:
+    """Shell-binned curl / divergence power spectra of a 3-component field
+    (see gr.h, gr_vector_spectra); workspace from torch."""
+
+    def __init__(self, n: int, nbins: int | None = None, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.n = n
+        self.nbins = n // 8 if nbins is None else nbins
+        self.device = torch.device(device)
+        lib = load_library()
+        h = C.c_void_p()
+        _scheck(lib.gr_create_spectra(n, self.nbins, C.byref(h)))
+        self.handle = h.value
+        nbytes = C.c_size_t()
+        _scheck(lib.gr_spectra_workspace_bytes(self.handle, C.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _scheck(lib.gr_spectra_bind(self.handle, self.workspace.data_ptr(), nbytes.value, self.stream.cuda_stream))
+
+    def _f64(self, x):
+        t = self.torch
+        x = x if isinstance(x, t.Tensor) else t.as_tensor(x)
+        x = x.to(device=self.device, dtype=t.float64).contiguous()
+        assert tuple(x.shape) == (self.n,) * 3
+        return x
+
+    def vector(self, vx, vy, vz):
+        """[6][nbins] numpy array, rows SPECTRA_ROWS."""
+        import numpy as np
+
+        v = [self._f64(a) for a in (vx, vy, vz)]
+        out = np.zeros(6 * self.nbins)
+        _scheck(load_library().gr_vector_spectra(self.handle, v[0].data_ptr(), v[1].data_ptr(), v[2].data_ptr(),
+                                                 out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out.reshape(6, self.nbins)
+
+    def fft(self, data):
+        """In-place forward 3-D FFT of a complex128 (n, n, n) device tensor."""
+        assert data.dtype == self.torch.complex128 and data.is_contiguous() and tuple(data.shape) == (self.n,) * 3
+        _scheck(load_library().gr_spectra_fft(self.handle, data.data_ptr()))
+        self.stream.synchronize()
+        return data
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().gr_destroy_spectra(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -114,3 +114,27 @@ def test_bench_runs_on_one_gpu_only():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "exactly one GPU" in (r.stdout + r.stderr)
+
+
+def test_spectra_handle_validation():
+    lib = grmg.load_library()
+    h = C.c_void_p()
+    for n, nb in [(12, 1), (4, 1), (2048, 4), (32, 0), (32, 9), (64, -1)]:
+        assert lib.gr_create_spectra(n, nb, C.byref(h)) == grmg.EINVAL, (n, nb)
+    assert lib.gr_create_spectra(32, 4, None) == grmg.EINVAL
+    assert lib.gr_create_spectra(32, 8, C.byref(h)) == grmg.OK
+    try:
+        nbytes = C.c_size_t()
+        assert lib.gr_spectra_workspace_bytes(h, C.byref(nbytes)) == grmg.OK
+        # two complex n^3 arrays plus the twiddles and the shell partials
+        assert 2 * 16 * 32 ** 3 <= nbytes.value < 2 * 16 * 32 ** 3 + (1 << 20)
+        out = (C.c_double * 48)()
+        x = C.c_void_p(256)
+        # not bound: rejected before any device work
+        assert lib.gr_vector_spectra(h, x, x, x, out) == grmg.ESTATE
+        assert lib.gr_spectra_fft(h, x) == grmg.ESTATE
+        assert lib.gr_vector_spectra(h, None, x, x, out) == grmg.EINVAL
+        assert lib.gr_spectra_bind(h, x, nbytes.value - 1, None) == grmg.EINVAL
+        assert lib.gr_spectra_bind(h, C.c_void_p(257), nbytes.value, None) == grmg.EINVAL
+    finally:
+        assert lib.gr_destroy_spectra(h) == grmg.OK
