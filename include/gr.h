@@ -391,6 +391,13 @@ int gr_batch_solve(gr_batch b, const gr_solve_opts *opts, int *cycles, double *r
  * patches).  Writes one line per (depth,
  * side) to `report` (may be NULL).  Errors: GR_ESTATE if unbound. */
 int gr_batch_autotune(gr_batch b, char *report, size_t report_bytes);
+/* Per item and field of the last gr_batch_solve (h_flags, host, [items][10]):
+ * 1 where mixed precision's refinement stalled (two steps in a row keeping
+ * more than half of the FP64 residual, the single grid's rule; ratio from
+ * GRMG_MIXED_STALL at creation) and the item finished that field with FP64
+ * FAS cycles from its current iterate, 0 elsewhere (always 0 for FP64 solves
+ * and for patches). */
+int gr_batch_mixed_fallbacks(gr_batch b, int *h_flags);
 /* Low level, for checks of the boundary values: writes the boundary values of
  * every level of every patch from their parents' current `field`, then copies
  * level `level` of patch `item`'s iterate, padded ((n_l+2)^3, x fastest; the

@@ -67,7 +67,9 @@ struct BoxDev {
 };
 
 // per-box scalars (device)
-enum BoxScal { B_FBAR, B_FSHIFT, B_FMEAN, B_MEAN, B_RN, B_FN, B_REL, B_TMP, B_ZERO, B_NSCAL }; // B_ZERO stays 0
+// B_ZERO stays 0; B_PREV, B_STALL, B_FB: mixed precision's previous relative
+// residual, count of stalled refinement steps in a row, and fallback flag
+enum BoxScal { B_FBAR, B_FSHIFT, B_FMEAN, B_MEAN, B_RN, B_FN, B_REL, B_TMP, B_ZERO, B_PREV, B_STALL, B_FB, B_NSCAL };
 
 struct BatchDev {
     const BoxDev *box;
@@ -447,8 +449,11 @@ __global__ void __launch_bounds__(TPB) kb_sub_mean(BatchDev D, const int *__rest
 
 // Stopping test per item of [b0, b1) (same criterion as the single-grid
 // solver) and the cycle count; marks converged items inactive with the device
-// clock time.
-__global__ void kb_control(BatchDev D, int fid, double rtol, int max_cycles, int b0, int b1)
+// clock time.  stall_ratio >= 0 (mixed precision): a refinement step that keeps
+// more than that fraction of the previous relative residual counts as
+// stalled, and two in a row stop the item's refinement with its fallback flag
+// set (the host then finishes it with FP64 cycles, as the single grid does).
+__global__ void kb_control(BatchDev D, int fid, double rtol, int max_cycles, int b0, int b1, double stall_ratio)
 {
     __shared__ int any;
     if (threadIdx.x == 0) any = 0;
@@ -468,6 +473,15 @@ __global__ void kb_control(BatchDev D, int fid, double rtol, int max_cycles, int
         } else if (D.cycles[b * 10 + fid] >= max_cycles) {
             if (rtol > 0.0) D.status[b] = GR_ENOTCONV;
             stop = 1;
+        }
+        if (!stop && stall_ratio >= 0.0) {
+            s[B_STALL] = rel > stall_ratio * s[B_PREV] ? s[B_STALL] + 1.0 : 0.0;
+            s[B_PREV] = rel;
+            if (s[B_STALL] >= 2.0) {
+                s[B_FB] = 1.0;
+                D.active[b] = 0;
+                continue;
+            }
         }
         if (stop) {
             D.active[b] = 0;
@@ -490,8 +504,27 @@ __global__ void kb_begin_field(BatchDev D, int fid, int b0, int b1, int ts)
         double *s = D.scal + b * B_NSCAL;
         s[B_FBAR] = 0.0;
         s[B_FSHIFT] = 0.0;
+        s[B_PREV] = HUGE_VAL;
+        s[B_STALL] = 0.0;
+        s[B_FB] = 0.0;
     }
     if (threadIdx.x == 0) D.t_start[ts] = wall_clock64();
+}
+
+// items of [b0, b1) whose mixed refinement stalled become the active set
+// (set = 1), or every item inactive (set = 0); any_active reports the set
+__global__ void kb_activate_fallback(BatchDev D, int b0, int b1, int set)
+{
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    for (int b = b0 + threadIdx.x; b < b1; b += blockDim.x) {
+        const int on = set && D.scal[b * B_NSCAL + B_FB] != 0.0;
+        D.active[b] = on;
+        if (on) atomicOr(&any, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *D.any_active = any;
 }
 
 // ------------------------------------------------------------- builders
@@ -1342,6 +1375,8 @@ struct gr_batch_s {
     hipEvent_t pdone = nullptr;
     bool conc = true;
     std::vector<double> rel_hist;   // [nbox][10] final relative residual per field
+    std::vector<int> fb_hist;       // [nbox][10] mixed precision fell back to FP64 cycles
+    double stall_ratio = 0.5;       // mixed precision: stalled refinement step ratio (GRMG_MIXED_STALL)
     double clock_khz = 0.0;
     long total_points = 0;
 };
@@ -1523,7 +1558,7 @@ int batch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
     }
     KDISPATCH(kind, kb_norms_m, B->norms.total(), TPB, B->D, B->norms.dev, fid, oc);
     kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->norms.dev, 2, B_RN, -1, 1, 0);
-    kb_control<<<1, 1024, 0, s>>>(B->D, fid, o.rtol, o.max_cycles, 0, B->nper);
+    kb_control<<<1, 1024, 0, s>>>(B->D, fid, o.rtol, o.max_cycles, 0, B->nper, -1.0);
     // descent through the levels handled by grouped launches
     for (int d = 0; d < B->maxdepth; ++d) {
         const Tab &TC = B->colour[d], &TD = B->cdom[d];
@@ -1597,7 +1632,10 @@ int read_rel(gr_batch B, hipStream_t s, int fid, int b0, int b1)
     std::vector<double> sc((size_t)B->nbox * B_NSCAL);
     BHIP(hipMemcpyAsync(sc.data(), B->D.scal, sizeof(double) * sc.size(), hipMemcpyDeviceToHost, s));
     BHIP(hipStreamSynchronize(s));
-    for (int b = b0; b < b1; ++b) B->rel_hist[(size_t)b * 10 + fid] = sc[(size_t)b * B_NSCAL + B_REL];
+    for (int b = b0; b < b1; ++b) {
+        B->rel_hist[(size_t)b * 10 + fid] = sc[(size_t)b * B_NSCAL + B_REL];
+        B->fb_hist[(size_t)b * 10 + fid] = sc[(size_t)b * B_NSCAL + B_FB] != 0.0;
+    }
     return GR_OK;
 }
 
@@ -1672,7 +1710,7 @@ int batch_cycle_mixed(gr_batch B, int kind, int fid, const gr_solve_opts &o)
     }
     KDISPATCH(kind, kb_ir_m, B->norms.total(), TPB, B->D, B->norms.dev, fid, oc);
     kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->norms.dev, 2, B_RN, -1, 1, 0);
-    kb_control<<<1, 1024, 0, s>>>(B->D, fid, o.rtol, o.max_cycles, 0, B->nper);
+    kb_control<<<1, 1024, 0, s>>>(B->D, fid, o.rtol, o.max_cycles, 0, B->nper, B->stall_ratio);
     if (kind == GR_KIND_HAMILTONIAN) // the linearisation frozen at this iterate, on every level
         for (size_t d = 0; d < B->coefr.size(); ++d)
             if (B->coefr[d].total())
@@ -1714,6 +1752,27 @@ int batch_field_mixed(gr_batch B, int kind, int fid, const gr_solve_opts &o)
     BLAUNCH();
     BCHK(batch_pin(B, fid, 0));
     BCHK(run_cycles(B, s, B->D.any_active, 20 + fid, o, [&] { return batch_cycle_mixed(B, kind, fid, o); }));
+    // items whose refinement stalled finish with FP64 FAS cycles from their
+    // current iterate, the cycle count continuing
+    kb_activate_fallback<<<1, 1024, 0, s>>>(B->D, 0, B->nper, 1);
+    BLAUNCH();
+    int any = 0;
+    BHIP(hipMemcpyAsync(&any, B->D.any_active, sizeof any, hipMemcpyDeviceToHost, s));
+    BHIP(hipStreamSynchronize(s));
+    if (any) {
+        if (kind != GR_KIND_POISSON)
+            for (size_t d = 0; d < B->coefr.size(); ++d)
+                if (B->coefr[d].total())
+                    kb_restrict_coef<<<B->coefr[d].total(), TPB, 0, s>>>(B->D, B->coefr[d].dev, (int)d);
+        BLAUNCH();
+        BCHK(run_cycles(B, s, B->D.any_active, fid, o, [&] { return batch_cycle(B, kind, fid, o); }));
+        if (kind == GR_KIND_POISSON) { // the FP64 cycles pin once at the end
+            kb_activate_fallback<<<1, 1024, 0, s>>>(B->D, 0, B->nper, 1);
+            BCHK(batch_pin(B, fid, 1));
+            kb_activate_fallback<<<1, 1024, 0, s>>>(B->D, 0, B->nper, 0);
+            BLAUNCH();
+        }
+    }
     return read_rel(B, s, fid, 0, B->nper);
 }
 
@@ -1734,7 +1793,7 @@ int patch_cycle(gr_batch B, hipStream_t s, int kind, int fid, const gr_solve_opt
     const OpConst oc = opc(B);
     KDISPATCH(kind, kp_norms, B->pfine.total(), TPB, B->Dp, B->pfine.dev, fid, oc);
     kb_finalize<<<B->npatch, TPB, 0, s>>>(B->Dp, B->pfine.dev, 2, B_RN, -1, 1, B->nper);
-    kb_control<<<1, 1024, 0, s>>>(B->Dp, fid, o.rtol, o.max_cycles, B->nper, B->nbox);
+    kb_control<<<1, 1024, 0, s>>>(B->Dp, fid, o.rtol, o.max_cycles, B->nper, B->nbox, -1.0);
     for (int d = 0; d < B->pmaxdepth; ++d) {
         if (B->pcell[d].total() == 0) continue;
         patch_smooth(B, s, kind, d, fid, o.nu1);
@@ -1819,6 +1878,7 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
     B->npatch = npatch;
     B->prm = *prm;
     if (const char *e = std::getenv("GRMG_COARSE_N")) B->coarse_n = std::max(2, std::atoi(e));
+    if (const char *e = std::getenv("GRMG_MIXED_STALL")) B->stall_ratio = std::atof(e);
     if (const char *e = std::getenv("GRMG_BATCH_GRAPH")) B->use_graph = std::atoi(e) != 0;
     if (const char *e = std::getenv("GRMG_BATCH_CONCURRENT")) B->conc = std::atoi(e) != 0;
     B->host.resize(count + npatch);
@@ -2214,6 +2274,15 @@ int gr_batch_autotune(gr_batch B, char *report, size_t report_bytes)
     return st;
 }
 
+int gr_batch_mixed_fallbacks(gr_batch B, int *h_flags)
+{
+    if (!B || !h_flags) return bfail(GR_EINVAL, "null argument");
+    for (int b = 0; b < B->nbox; ++b)
+        for (int f = 0; f < 10; ++f)
+            h_flags[b * 10 + f] = B->fb_hist.empty() ? 0 : B->fb_hist[(size_t)b * 10 + f];
+    return GR_OK;
+}
+
 int gr_batch_debug_boundary(gr_batch B, int item, int field, int level, double *d_dst)
 {
     if (!B || !B->bound) return bfail(B ? GR_ESTATE : GR_EINVAL, "batch not bound");
@@ -2244,6 +2313,7 @@ int gr_batch_solve(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_
     const OpConst oc = opc(B);
     const int FT = B->fine.total();
     B->rel_hist.assign((size_t)B->nbox * 10, 0.0);
+    B->fb_hist.assign((size_t)B->nbox * 10, 0);
     std::vector<int> zero(B->nbox, 0);
     BHIP(hipMemcpyAsync(B->D.status, zero.data(), sizeof(int) * B->nbox, hipMemcpyHostToDevice, s));
     std::vector<unsigned long long> tz((size_t)B->nbox * 10, 0ull);

@@ -36,7 +36,7 @@ EXPORTS = ("gr_default_opts", "gr_create_grid", "gr_workspace_bytes", "gr_bind",
            "gr_set_field", "gr_get_field", "gr_solve_constraints", "gr_solve_equation", "gr_solve_equation_static",
            "gr_debug_sweep", "gr_kick", "gr_drift", "gr_newtonian_kick",
            "gr_debug_residual", "gr_destroy_grid", "gr_last_error", "gr_features", "gr_set_guess", "gr_autotune", "gr_sweep_timing", "gr_create_batch", "gr_create_batch_patches",
-           "gr_batch_debug_boundary", "gr_batch_autotune", "gr_batch_workspace_bytes",
+           "gr_batch_debug_boundary", "gr_batch_autotune", "gr_batch_mixed_fallbacks", "gr_batch_workspace_bytes",
            "gr_batch_bind", "gr_batch_set_field", "gr_batch_get_field", "gr_batch_solve", "gr_destroy_batch",
            "gr_batch_last_error", "gr_unet_create", "gr_unet_workspace_bytes", "gr_unet_param_count", "gr_unet_bind",
            "gr_unet_init", "gr_unet_set_params", "gr_unet_get_params", "gr_unet_forward", "gr_unet_loss_grad",
@@ -124,6 +124,7 @@ def load_library(path: str = LIB_PATH):
                                     C.POINTER(GrParams), C.POINTER(vp)],
         "gr_batch_debug_boundary": [vp, C.c_int, C.c_int, C.c_int, vp],
         "gr_batch_autotune": [vp, C.c_char_p, C.c_size_t],
+        "gr_batch_mixed_fallbacks": [vp, C.POINTER(C.c_int)],
         "gr_batch_workspace_bytes": [vp, C.POINTER(C.c_size_t)],
         "gr_batch_bind": [vp, vp, C.c_size_t, vp],
         "gr_batch_set_field": [vp, C.c_int, C.c_int, vp, C.c_int],
@@ -513,7 +514,11 @@ class Batch:
     def solve(self, allow=(OK,), **kw):
         st, cyc, rel, sec = batch_solve(self.handle, len(self.ns), default_opts(**kw), allow)
         self._keep.clear()
-        return dict(status=st, cycles=cyc, rel_res=rel, item_seconds=sec)
+        count = len(self.ns)
+        fb = (C.c_int * (10 * count))()
+        _bcheck(load_library().gr_batch_mixed_fallbacks(self.handle, fb))
+        return dict(status=st, cycles=cyc, rel_res=rel, item_seconds=sec,
+                    fallback=[list(fb[10 * i:10 * i + 10]) for i in range(count)])
 
 
 # ---- learned initial guess network ----

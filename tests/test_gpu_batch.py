@@ -228,3 +228,61 @@ def test_batch_fused16_form_is_bit_identical(precision, monkeypatch):
     for i in range(len(sides)):
         for f in range(10):
             assert torch.equal(A.get_field(i, f), F.get_field(i, f)), (i, f)
+
+
+@pytest.mark.parametrize("tuned", [False, True])
+def test_batch_fused_boxes_match_oracle(tuned):
+    """A 64^3 and a 96^3 box, which take the batched fused sweeps (the default
+    32x16 form, or the forms the batch autotuner picks), beside a 32^3 box:
+    every field equals the oracle's at the batch's own per-field cycle counts
+    (1e-12)."""
+    items = [synth.batch_item(700 + i, sides=(side,), sigma_range=(0.05, 0.5)) for i, side in
+             enumerate((64, 96, 32))]
+    print(f"[gpu] batch fused boxes vs oracle, tuned={tuned}", flush=True)
+    B = grmg.Batch([n for n, _ in items], **PRM)
+    load(B, items)
+    if tuned:
+        print(B.autotune(), flush=True)
+    rep = B.solve(rtol=1e-10)
+    assert rep["status"] == 0
+    p = O.params(**PRM)
+    for i, (n, src) in enumerate(items[:2]):
+        fields, st, cyc, rel, AA = O.solve_all(*src, prm=p, rtol=0, max_cycles=rep["cycles"][i])
+        assert list(cyc) == list(rep["cycles"][i])
+        for name in O.FIELDS:
+            assert maxrel(B.get_field(i, name), fields[name]) < 1e-12, (n, name)
+
+
+def test_batch_mixed_stagnation_falls_back_to_fp64(monkeypatch):
+    """Forced from the host: with a stagnation ratio of 0 every refinement step
+    after the first counts as stalled, so each box's field finishes with FP64
+    FAS cycles after its third measurement (the single grid's rule); the
+    result meets the tolerance, equals the FP64 solution within 1e-9, and the
+    fallback flags say so.  With the default ratio nothing falls back."""
+    sides = [32, 48, 64]
+    srcs = [synth._matter_sources(n, 820 + i, 0.4) for i, n in enumerate(sides)]
+
+    def make():
+        B = grmg.Batch(sides, **PRM)
+        for i, src in enumerate(srcs):
+            for name, v in zip(("s0", "sx", "sy", "sz", "sm"), src):
+                B.set_field(i, name, v)
+        return B
+
+    A = make()
+    ra = A.solve(rtol=1e-13, max_cycles=60)
+    N = make()
+    rn = N.solve(rtol=1e-12, max_cycles=60, precision="mixed")
+    assert rn["status"] == grmg.OK and all(f == 0 for row in rn["fallback"] for f in row)
+    monkeypatch.setenv("GRMG_MIXED_STALL", "0")
+    print("[gpu] batch mixed forced stagnation", flush=True)
+    M = make()
+    rm = M.solve(rtol=1e-12, max_cycles=60, precision="mixed")
+    assert ra["status"] == rm["status"] == grmg.OK
+    for i in range(len(sides)):
+        assert all(x <= 1e-12 for x in rm["rel_res"][i])
+        for f in range(10):
+            assert rm["fallback"][i][f] == 1, (i, f, rm["cycles"][i])
+            ref = A.get_field(i, f).cpu().numpy()
+            got = M.get_field(i, f).cpu().numpy()
+            assert np.max(np.abs(got - ref)) <= 1e-9 * np.max(np.abs(ref)), (i, f)
