@@ -54,6 +54,7 @@ struct BoxLev {
 struct BoxDev {
     int nlev;
     int centry; // first level handled by the single-workgroup coarse cycle
+    int qentry; // first level run by the device task queue (== centry: only the coarse cycle)
     int centry32; // first level of the FP32 correction cycle handled by the single-workgroup kernel
     int patch;  // 1: Dirichlet patch (padded iterate arrays), 0: periodic box
     int parent; // patch: index of the periodic box its boundary values come from
@@ -611,10 +612,8 @@ __device__ double cvb_block_sum(double v)
 }
 
 template <int KIND>
-__global__ void __launch_bounds__(CTPB) kb_coarse_vcycle(BatchDev D, int fid, int nu1, int nu2, OpConst oc)
+__device__ void coarse_vcycle_box(const BatchDev &D, int b, int fid, int nu1, int nu2, OpConst oc)
 {
-    const int b = blockIdx.x;
-    if (!D.active[b]) return;
     const BoxDev &X = D.box[b];
     const int l0 = X.centry, L = X.nlev;
     auto PHI = [&](int i) { return i == 0 ? X.field[fid] : X.lev[i].phi; };
@@ -696,6 +695,176 @@ __global__ void __launch_bounds__(CTPB) kb_coarse_vcycle(BatchDev D, int fid, in
         }
         __syncthreads();
         for (int it = 0; it < nu2; ++it) cvb_sweep<KIND>(phi, V.f, V.coef, n, inv_h2, oc, Fb, fs);
+    }
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(CTPB) kb_coarse_vcycle(BatchDev D, int fid, int nu1, int nu2, OpConst oc)
+{
+    if (!D.active[blockIdx.x]) return;
+    coarse_vcycle_box<KIND>(D, blockIdx.x, fid, nu1, nu2, oc);
+}
+
+// ------------------------------------------------ persistent task queue
+//
+// One launch per V-cycle runs, for every active box, its levels from the
+// queue entry (the first level of at most queue_n^3 points) down to the
+// single-workgroup coarse cycle and back up.  Tasks (item, level, phase,
+// z-range) are taken in table order from a device-wide ticket; the table lists
+// the phases of all items phase-major, each phase split into z-ranges of
+// about kQTarget points.  A task first waits until its item's counter of
+// completed tasks reaches the number of the item's tasks in earlier phases,
+// so one item's phases run in order while items and z-ranges run in parallel.
+// A worker only ever waits on tasks with smaller tickets, which running
+// workers already hold, so the queue drains whatever the residency.  Every
+// wait is bounded: on a timeout the item's status becomes GR_EDEVICE and the
+// queue's abort flag makes all later tasks skip.  Data written by one task
+// and read by a later one (possibly on another XCD) is published with an
+// agent-scope release before the counter increment and acquired after the
+// wait.
+enum QPhase { Q_RED = 0, Q_BLACK = 1, Q_RR = 2, Q_CRHS = 3, Q_PROLONG = 4, Q_COARSE = 5 };
+struct QTask {
+    int item, phase, level, z0, z1, prefix;
+};
+constexpr int kQTarget = 8192;  // points per task
+constexpr int kQueueMaxNu = 8;  // task table capacity: nu1, nu2 <= 8
+constexpr long kQSpin = 1L << 22; // bounded wait (iterations of a short sleep)
+
+// ctl[0]: ticket, ctl[1]: abort (full = 1 also clears it); done[item] = 0
+__global__ void kb_queue_reset(int *__restrict__ ctl, int *__restrict__ done, int nbox, int full)
+{
+    for (int b = threadIdx.x; b < nbox; b += blockDim.x) done[b] = 0;
+    if (threadIdx.x == 0) {
+        ctl[0] = 0;
+        if (full) ctl[1] = 0;
+    }
+}
+
+template <int KIND>
+__device__ void q_run(const BatchDev &D, const QTask &q, int fid, int nu1, int nu2, OpConst oc)
+{
+    const int b = q.item, i = q.level;
+    if (q.phase == Q_COARSE) {
+        coarse_vcycle_box<KIND>(D, b, fid, nu1, nu2, oc);
+        return;
+    }
+    const BoxDev &X = D.box[b];
+    const BoxLev &V = X.lev[i];
+    const int n = V.n;
+    double *phi = i == 0 ? X.field[fid] : V.phi;
+    const double Fb = i == 0 ? D.scal[b * B_NSCAL + B_FBAR] : 0.0;
+    const double fs = i == 0 ? D.scal[b * B_NSCAL + B_FSHIFT] : 0.0;
+    if (q.phase == Q_RED || q.phase == Q_BLACK) { // one colour of planes z0..z1 (as kb_colour)
+        const int colour = q.phase, half = n >> 1, tot = (q.z1 - q.z0) * n * half;
+        const double inv_h2 = 1.0 / (V.h * V.h);
+        for (int t = threadIdx.x; t < tot; t += CTPB) {
+            const int x2 = t % half, r = t / half, y = r % n, z = q.z0 + r / n;
+            const int ii = 2 * x2 + ((y + z + colour) & 1);
+            const long p = lin(ii, y, z, n);
+            const double ph = phi[p];
+            double J;
+            const double Lv = op_point<KIND, double>(ph, nb_sum(phi, ii, y, z, n), inv_h2, load_c1<KIND>(V.coef, p),
+                                                     0.0, oc, Fb, J);
+            phi[p] = ph - (Lv - (V.f[p] - fs)) / J;
+        }
+        return;
+    }
+    const BoxLev &C = X.lev[i + 1];
+    const int m = C.n;
+    if (q.phase == Q_RR) { // residual + restriction into coarse planes z0..z1 (as kb_rr_m per cell)
+        const int tot = (q.z1 - q.z0) * m * m;
+        const double inv_h2 = 1.0 / (V.h * V.h);
+        for (int t = threadIdx.x; t < tot; t += CTPB) {
+            const int I = t % m, J = (t / m) % m, K = q.z0 + t / (m * m);
+            double sr = 0.0, sp = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                const int a = 2 * I + (c & 1), bb = 2 * J + ((c >> 1) & 1), k = 2 * K + (c >> 2);
+                const long p = lin(a, bb, k, n);
+                const double ph = phi[p];
+                double Jd;
+                const double Lv = op_point<KIND, double>(ph, nb_sum(phi, a, bb, k, n), inv_h2,
+                                                         load_c1<KIND>(V.coef, p), 0.0, oc, Fb, Jd);
+                sr += Lv - (V.f[p] - fs);
+                sp += ph;
+            }
+            const long c0 = lin(I, J, K, m);
+            const double rp = sp / 8.0;
+            C.phi[c0] = rp;
+            C.phi0[c0] = rp;
+            C.tmp[c0] = sr / 8.0;
+        }
+    } else if (q.phase == Q_CRHS) { // FAS source of coarse planes z0..z1 (as kb_coarse_rhs)
+        const int tot = (q.z1 - q.z0) * m * m;
+        const double inv_H2 = 1.0 / (C.h * C.h);
+        for (int t = threadIdx.x; t < tot; t += CTPB) {
+            const int I = t % m, J = (t / m) % m, K = q.z0 + t / (m * m);
+            const long c0 = lin(I, J, K, m);
+            double Jd;
+            const double Lv = op_point<KIND, double>(C.phi[c0], nb_sum(C.phi, I, J, K, m), inv_H2,
+                                                     load_c1<KIND>(C.coef, c0), 0.0, oc, 0.0, Jd);
+            C.f[c0] = Lv - C.tmp[c0];
+        }
+    } else { // Q_PROLONG: fine planes z0..z1 += P (phi^H - phi0^H), the coarse cycle's per-point form
+        const int tot = (q.z1 - q.z0) * n * n;
+        for (int t = threadIdx.x; t < tot; t += CTPB) {
+            const int a = t % n, bb = (t / n) % n, dd = q.z0 + t / (n * n);
+            const int I = a >> 1, J = bb >> 1, K = dd >> 1;
+            const int Is[2] = {I, wrapi(I + ((a & 1) ? 1 : -1), m)};
+            const int Js[2] = {J, wrapi(J + ((bb & 1) ? 1 : -1), m)};
+            const int Ks[2] = {K, wrapi(K + ((dd & 1) ? 1 : -1), m)};
+            double v = 0.0;
+            for (int c = 0; c < 8; ++c) {
+                const int ox = c & 1, oy = (c >> 1) & 1, oz = c >> 2;
+                const double w = (ox ? 0.25 : 0.75) * (oy ? 0.25 : 0.75) * (oz ? 0.25 : 0.75);
+                const long qq = lin(Is[ox], Js[oy], Ks[oz], m);
+                v += w * (C.phi[qq] - C.phi0[qq]);
+            }
+            phi[lin(a, bb, dd, n)] += v;
+        }
+    }
+}
+
+template <int KIND>
+__global__ void __launch_bounds__(CTPB) kb_queue(BatchDev D, const QTask *__restrict__ tasks, int ntasks,
+                                                 int *__restrict__ ctl, int *__restrict__ done, int fid, int nu1,
+                                                 int nu2, OpConst oc, long spin_limit)
+{
+    __shared__ int s_t, s_go;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int t = atomicAdd(&ctl[0], 1);
+            int go = 0;
+            if (t < ntasks) {
+                const QTask q = tasks[t];
+                if (D.active[q.item] && !__hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    go = 1;
+                    long it = 0;
+                    while (__hip_atomic_load(&done[q.item], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < q.prefix) {
+                        if (++it > spin_limit || __hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                            if (it > spin_limit) D.status[q.item] = GR_EDEVICE;
+                            __hip_atomic_store(&ctl[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            go = 0;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+            }
+            s_t = t;
+            s_go = go;
+        }
+        __syncthreads();
+        const int t = s_t, go = s_go;
+        if (t >= ntasks) return;
+        if (go) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const QTask q = tasks[t];
+            q_run<KIND>(D, q, fid, nu1, nu2, oc);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (threadIdx.x == 0) __hip_atomic_fetch_add(&done[q.item], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads(); // s_t, s_go are rewritten next
     }
 }
 
@@ -1379,6 +1548,15 @@ struct gr_batch_s {
     double stall_ratio = 0.5;       // mixed precision: stalled refinement step ratio (GRMG_MIXED_STALL)
     double clock_khz = 0.0;
     long total_points = 0;
+    // device task queue (GRMG_BATCH_QUEUE=1): levels of at most queue_n^3
+    // points and the coarse cycle of every box in one persistent launch
+    bool use_queue = false;
+    int queue_n = 32;
+    int qcap = 0;                   // task table capacity (nu1, nu2 <= kQueueMaxNu)
+    QTask *qtasks = nullptr;        // device task table
+    int *qctl = nullptr, *qdone = nullptr;
+    int qcount = 0, qnu1 = -1, qnu2 = -1, qworkers = 0, cus = 0;
+    std::vector<QTask> qhost;
 };
 
 namespace {
@@ -1435,6 +1613,9 @@ size_t batch_layout(gr_batch B, char *base)
     B->D.partials = takeD((size_t)B->fine.total() * 2 + 16);
     B->p_partials = takeD((size_t)B->pfine.total() * 2 + 16);
     B->p_any = takeI(1);
+    B->qtasks = reinterpret_cast<QTask *>(take(sizeof(QTask) * (size_t)std::max(B->qcap, 1)));
+    B->qctl = takeI(4);
+    B->qdone = takeI(B->nbox);
     B->fine.dev = takeI(B->nbox + 1);
     B->fine8.dev = takeI(B->nbox + 1);
     B->norms.dev = takeI(B->nbox + 1);
@@ -1474,6 +1655,74 @@ OpConst opc(gr_batch B)
     o.kappa = 1.0 / (2.0 * B->prm.a * B->prm.a * B->prm.c_tilde * B->prm.c_tilde);
     o.A = 1.5 * B->prm.a * B->prm.omega_m;
     return o;
+}
+
+// The task table of the queue for V(nu1, nu2) cycles: per box, the phases of
+// its levels from qentry down to the coarse cycle and back up, each split
+// into z-ranges of about kQTarget points; emitted phase-major over the boxes,
+// each task with the count of its box's tasks in earlier phases.
+void q_build(const gr_batch B, int nu1, int nu2, std::vector<QTask> &out)
+{
+    out.clear();
+    const auto &H = B->host;
+    std::vector<std::vector<std::vector<QTask>>> ph(B->nper);
+    for (int b = 0; b < B->nper; ++b) {
+        const BoxDev &X = H[b];
+        auto add = [&](int phase, int level, int planes, long plane_pts) {
+            std::vector<QTask> v;
+            const int pz = (int)std::max(1L, std::min((long)planes, (kQTarget + plane_pts - 1) / plane_pts));
+            for (int z0 = 0; z0 < planes; z0 += pz) v.push_back(QTask{b, phase, level, z0, std::min(planes, z0 + pz), 0});
+            ph[b].push_back(v);
+        };
+        for (int i = X.qentry; i < X.centry; ++i) {
+            const int n = X.lev[i].n, m = X.lev[i + 1].n;
+            for (int it = 0; it < nu1; ++it) {
+                add(Q_RED, i, n, (long)n * n / 2);
+                add(Q_BLACK, i, n, (long)n * n / 2);
+            }
+            add(Q_RR, i, m, (long)m * m);
+            add(Q_CRHS, i, m, (long)m * m);
+        }
+        add(Q_COARSE, X.centry, 1, kQTarget);
+        for (int i = X.centry - 1; i >= X.qentry; --i) {
+            const int n = X.lev[i].n;
+            add(Q_PROLONG, i, n, (long)n * n);
+            for (int it = 0; it < nu2; ++it) {
+                add(Q_RED, i, n, (long)n * n / 2);
+                add(Q_BLACK, i, n, (long)n * n / 2);
+            }
+        }
+    }
+    size_t maxp = 0;
+    for (const auto &v : ph) maxp = std::max(maxp, v.size());
+    std::vector<int> prefix(B->nper, 0);
+    for (size_t p = 0; p < maxp; ++p)
+        for (int b = 0; b < B->nper; ++b) {
+            if (p >= ph[b].size()) continue;
+            for (QTask q : ph[b][p]) {
+                q.prefix = prefix[b];
+                out.push_back(q);
+            }
+            prefix[b] += (int)ph[b][p].size();
+        }
+}
+
+// the task table for V(nu1, nu2) on the device (before any capture of a cycle)
+int q_prepare(gr_batch B, int nu1, int nu2)
+{
+    if (!B->use_queue) return GR_OK;
+    if (nu1 > kQueueMaxNu || nu2 > kQueueMaxNu)
+        return bfail(GR_EINVAL, "the batch task queue takes nu1, nu2 <= %d", kQueueMaxNu);
+    if (nu1 == B->qnu1 && nu2 == B->qnu2) return GR_OK;
+    q_build(B, nu1, nu2, B->qhost);
+    if ((int)B->qhost.size() > B->qcap) return bfail(GR_EDEVICE, "task table exceeds its capacity");
+    BHIP(hipMemcpyAsync(B->qtasks, B->qhost.data(), sizeof(QTask) * B->qhost.size(), hipMemcpyHostToDevice, B->stream));
+    BHIP(hipStreamSynchronize(B->stream));
+    B->qcount = (int)B->qhost.size();
+    B->qworkers = std::max(1, std::min(B->qcount, 2 * std::max(B->cus, 1)));
+    B->qnu1 = nu1;
+    B->qnu2 = nu2;
+    return GR_OK;
 }
 
 // pin (all boxes or active ones): mean then subtract
@@ -1567,7 +1816,13 @@ int batch_cycle(gr_batch B, int kind, int fid, const gr_solve_opts &o)
         KDISPATCH(kind, kb_rr_m, B->rr[d].total(), TPB, B->D, B->rr[d].dev, d, fid, oc);
         KDISPATCH(kind, kb_coarse_rhs, TD.total(), TPB, B->D, TD.dev, d, oc);
     }
-    KDISPATCH(kind, kb_coarse_vcycle, B->nper, CTPB, B->D, fid, o.nu1, o.nu2, oc);
+    if (B->use_queue) { // the levels from each box's queue entry and its coarse cycle: one persistent launch
+        kb_queue_reset<<<1, 1024, 0, s>>>(B->qctl, B->qdone, B->nbox, 0);
+        KDISPATCH(kind, kb_queue, B->qworkers, CTPB, B->D, B->qtasks, B->qcount, B->qctl, B->qdone, fid, o.nu1, o.nu2,
+                  oc, kQSpin);
+    } else {
+        KDISPATCH(kind, kb_coarse_vcycle, B->nper, CTPB, B->D, fid, o.nu1, o.nu2, oc);
+    }
     for (int d = B->maxdepth - 1; d >= 0; --d) {
         const Tab &TC = B->colour[d], &TD = B->cdom[d];
         if (TC.total() == 0) continue;
@@ -1653,6 +1908,7 @@ int batch_field(gr_batch B, int kind, int fid, const gr_solve_opts &o)
         kb_finalize<<<B->nper, TPB, 0, s>>>(B->D, B->fine8.dev, 1, B_FMEAN, -1, 0, 0);
     }
     BLAUNCH();
+    BCHK(q_prepare(B, o.nu1, o.nu2));
     BCHK(batch_pin(B, fid, 0));
     BCHK(run_cycles(B, s, B->D.any_active, fid, o, [&] { return batch_cycle(B, kind, fid, o); }));
     if (kind == GR_KIND_POISSON) BCHK(batch_pin(B, fid, 0));
@@ -1765,6 +2021,7 @@ int batch_field_mixed(gr_batch B, int kind, int fid, const gr_solve_opts &o)
                 if (B->coefr[d].total())
                     kb_restrict_coef<<<B->coefr[d].total(), TPB, 0, s>>>(B->D, B->coefr[d].dev, (int)d);
         BLAUNCH();
+        BCHK(q_prepare(B, o.nu1, o.nu2));
         BCHK(run_cycles(B, s, B->D.any_active, fid, o, [&] { return batch_cycle(B, kind, fid, o); }));
         if (kind == GR_KIND_POISSON) { // the FP64 cycles pin once at the end
             kb_activate_fallback<<<1, 1024, 0, s>>>(B->D, 0, B->nper, 1);
@@ -1879,6 +2136,8 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
     B->prm = *prm;
     if (const char *e = std::getenv("GRMG_COARSE_N")) B->coarse_n = std::max(2, std::atoi(e));
     if (const char *e = std::getenv("GRMG_MIXED_STALL")) B->stall_ratio = std::atof(e);
+    if (const char *e = std::getenv("GRMG_BATCH_QUEUE")) B->use_queue = std::atoi(e) != 0;
+    if (const char *e = std::getenv("GRMG_QUEUE_N")) B->queue_n = std::max(2, std::atoi(e));
     if (const char *e = std::getenv("GRMG_BATCH_GRAPH")) B->use_graph = std::atoi(e) != 0;
     if (const char *e = std::getenv("GRMG_BATCH_CONCURRENT")) B->conc = std::atoi(e) != 0;
     B->host.resize(count + npatch);
@@ -1898,6 +2157,13 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
             X.lev[l].h = descs[b].h * (double)(1 << l);
             if ((n >> l) <= B->coarse_n && X.centry == X.nlev - 1 && l < X.centry) X.centry = l;
         }
+        X.qentry = X.centry;
+        if (B->use_queue)
+            for (int l = 0; l < X.centry; ++l)
+                if (X.lev[l].n <= B->queue_n) {
+                    X.qentry = l;
+                    break;
+                }
         X.centry32 = X.nlev - 1; // FP32 correction cycle: single workgroup from 8^3 down
         for (int l = 0; l < X.nlev - 1; ++l)
             if (X.lev[l].n <= 8) {
@@ -1925,6 +2191,7 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
             X.lev[l].h = q.h * (double)(1 << l);
             if ((q.n >> l) <= kPatchCoarseN && X.centry == X.nlev - 1 && l < X.centry) X.centry = l;
         }
+        X.qentry = X.centry;
         pmaxd = std::max(pmaxd, X.centry);
         pmaxl = std::max(pmaxl, X.nlev);
         B->total_points += (long)q.n * q.n * q.n;
@@ -1956,9 +2223,11 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
     if (const char *e = std::getenv("GRMG_BATCH_FUSED")) B->use_fused = std::atoi(e) != 0;
     auto fusable = [&](int b, int d) {
         const int n = H[b].lev[d].n;
-        return !H[b].patch && d < H[b].centry && n >= 64 && n % 32 == 0;
+        return !H[b].patch && d < H[b].qentry && n >= 64 && n % 32 == 0;
     };
-    auto grouped = [&](int b, int d) { return !H[b].patch && d < H[b].centry; };
+    // levels of periodic boxes run by grouped launches: above the queue entry
+    // (the coarse cycle's entry when the queue is off)
+    auto grouped = [&](int b, int d) { return !H[b].patch && d < H[b].qentry; };
     for (int d = 0; d < maxd; ++d) {
         make_tab(B->colour[d], nb, [&](int b) { long n = H[b].lev[d].n; return grouped(b, d) ? n * n * n / 2 : 0L; });
 
@@ -2028,6 +2297,11 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
             long w = H[b].patch && l < H[b].nlev ? H[b].lev[l].n + 2 : 0;
             return w * w * w;
         });
+    if (B->use_queue) {
+        std::vector<QTask> t;
+        q_build(B, kQueueMaxNu, kQueueMaxNu, t);
+        B->qcap = (int)t.size();
+    }
     B->ws_bytes = batch_layout(B, nullptr);
     *out = B;
     return GR_OK;
@@ -2112,6 +2386,10 @@ int gr_batch_bind(gr_batch B, void *d_ws, size_t bytes, void *stream)
     BHIP(hipGetDevice(&dev));
     BHIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     B->clock_khz = khz > 0 ? khz : 100000.0;
+    BHIP(hipDeviceGetAttribute(&B->cus, hipDeviceAttributeMultiprocessorCount, dev));
+    B->qnu1 = B->qnu2 = -1; // the task table lives in the (new) workspace
+    kb_queue_reset<<<1, 1024, 0, s>>>(B->qctl, B->qdone, B->nbox, 1);
+    BLAUNCH();
     B->bound = true;
     return GR_OK;
 }

@@ -286,3 +286,65 @@ def test_batch_mixed_stagnation_falls_back_to_fp64(monkeypatch):
             ref = A.get_field(i, f).cpu().numpy()
             got = M.get_field(i, f).cpu().numpy()
             assert np.max(np.abs(got - ref)) <= 1e-9 * np.max(np.abs(ref)), (i, f)
+
+
+QUEUE_SIDES = (8, 12, 16, 24, 32, 48, 64, 96, 128)
+
+
+def _solve_sides(items, monkeypatch, queue, graph="1", tune=False, **kw):
+    monkeypatch.setenv("GRMG_BATCH_QUEUE", "1" if queue else "0")
+    monkeypatch.setenv("GRMG_BATCH_GRAPH", graph)
+    B = grmg.Batch([n for n, _ in items], **PRM)
+    load(B, items)
+    if tune:
+        B.autotune()
+    rep = B.solve(**kw)
+    return B, rep
+
+
+def test_batch_queue_is_bit_identical_to_grouped_launches(monkeypatch):
+    """The device task queue (levels of at most 32^3 points and the coarse
+    cycle of every box in one persistent launch per cycle) runs each phase with
+    the per-cell arithmetic of the grouped per-colour and per-cell launches, so
+    with those forms (GRMG_MARCH=0) every field of every box is bit-identical
+    and the cycle counts equal; the same with eager launches instead of the
+    captured cycle."""
+    monkeypatch.setenv("GRMG_MARCH", "0")
+    items = [synth.batch_item(900 + i, sides=(side,), sigma_range=(0.05, 0.5)) for i, side in enumerate(QUEUE_SIDES)]
+    print("[gpu] batch queue vs grouped, sides", QUEUE_SIDES, flush=True)
+    A, ra = _solve_sides(items, monkeypatch, queue=False, rtol=1e-10)
+    Q, rq = _solve_sides(items, monkeypatch, queue=True, rtol=1e-10)
+    E, re_ = _solve_sides(items, monkeypatch, queue=True, graph="0", rtol=1e-10)
+    assert ra["status"] == rq["status"] == re_["status"] == grmg.OK
+    assert ra["cycles"] == rq["cycles"] == re_["cycles"]
+    for i in range(len(items)):
+        for f in range(10):
+            a = A.get_field(i, f)
+            assert torch.equal(a, Q.get_field(i, f)), (QUEUE_SIDES[i], f)
+            assert torch.equal(a, E.get_field(i, f)), (QUEUE_SIDES[i], f)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_queue_with_tuned_forms(precision, monkeypatch):
+    """Default (plane-marching) forms and autotuned sweeps: the queue gives the
+    grouped launches' cycle counts and fields within 1e-12 (the marching
+    restriction adds in another order than the queue's per-cell form), and a
+    32^3 box equals the oracle at those cycle counts; V-cycles beyond the
+    queue's task table (nu > 8) are rejected."""
+    items = [synth.batch_item(950 + i, sides=(side,), sigma_range=(0.05, 0.5)) for i, side in
+             enumerate((32, 64, 96, 48))]
+    print(f"[gpu] batch queue tuned, {precision}", flush=True)
+    A, ra = _solve_sides(items, monkeypatch, queue=False, tune=True, rtol=1e-10, precision=precision)
+    Q, rq = _solve_sides(items, monkeypatch, queue=True, tune=True, rtol=1e-10, precision=precision)
+    assert ra["status"] == rq["status"] == grmg.OK
+    assert ra["cycles"] == rq["cycles"]
+    for i in range(len(items)):
+        for f in range(10):
+            assert maxrel(Q.get_field(i, f), A.get_field(i, f).cpu().numpy()) < 1e-12, (i, f)
+    if precision == "fp64":
+        n, src = items[0]
+        fields, *_ = O.solve_all(*src, prm=O.params(**PRM), rtol=0, max_cycles=rq["cycles"][0])
+        for name in O.FIELDS:
+            assert maxrel(Q.get_field(0, name), fields[name]) < 1e-12, name
+        st = Q.solve(allow=(grmg.OK, grmg.EINVAL), rtol=1e-10, nu1=9, nu2=2)
+        assert st["status"] == grmg.EINVAL
