@@ -439,6 +439,26 @@ def bench_batch(torch, grmg, synth, steps):
         rep_m = B.solve(rtol=1e-10, precision="mixed")
         mtimes.append(time.perf_counter() - t0)
     dtm = min(mtimes)
+    B.close()
+    # the same solve with the device task queue (levels of at most 32^3 points and
+    # each box's coarse cycle in one persistent launch per cycle)
+    os.environ["GRMG_BATCH_QUEUE"] = "1"
+    try:
+        Q = grmg.Batch(sides, a=1.0, omega_m=synth.OMEGA_M, c_tilde=synth.C_TILDE, device="cuda:0",
+                       patches=[d for d, _ in pitems])
+    finally:
+        del os.environ["GRMG_BATCH_QUEUE"]
+    for i, src in enumerate([src for _, src in items] + [src for _, src in pitems]):
+        for name, x in zip(("s0", "sx", "sy", "sz", "sm"), src):
+            Q.set_field(i, name, x)
+    Q.autotune()
+    rep_q = Q.solve(rtol=1e-10)
+    qtimes = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        rep_q = Q.solve(rtol=1e-10)
+        qtimes.append(time.perf_counter() - t0)
+    Q.close()
     pts = np.array([n ** 3 for n in sides] + [d[0] ** 3 for d, _ in pitems], dtype=np.float64)
     cyc = np.array(rep["cycles"], dtype=np.float64)
     secs = np.array(rep["item_seconds"]) * 1e3
@@ -456,9 +476,12 @@ def bench_batch(torch, grmg, synth, steps):
            "patch_cycles_min_max": [int(cyc[npb:].sum(1).min()), int(cyc[npb:].sum(1).max())],
            "autotune": {"seconds": round(tune_s, 3), "choices": tune.strip().splitlines()},
            "mixed": {"status": rep_m["status"], "seconds": round(dtm, 4),
-                     "note": "boxes by FP64/FP32 iterative refinement, patches in FP64"}}
+                     "note": "boxes by FP64/FP32 iterative refinement, patches in FP64"},
+           "queue": {"status": rep_q["status"], "seconds": round(min(qtimes), 4),
+                     "same_cycles": rep_q["cycles"] == rep["cycles"],
+                     "note": "FP64 with the device task queue for every box's levels of at most 32^3 points and "
+                             "its coarse cycle (one persistent launch per cycle), grouped launches above"}}
     log(f"batch: {out}")
-    B.close()
     return out
 
 

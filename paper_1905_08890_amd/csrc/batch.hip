@@ -719,14 +719,15 @@ __global__ void __launch_bounds__(CTPB) kb_coarse_vcycle(BatchDev D, int fid, in
 // workers already hold, so the queue drains whatever the residency.  Every
 // wait is bounded: on a timeout the item's status becomes GR_EDEVICE and the
 // queue's abort flag makes all later tasks skip.  Data written by one task
-// and read by a later one (possibly on another XCD) is published with an
-// agent-scope release before the counter increment and acquired after the
-// wait.
+// and read by a later one (possibly on another XCD) is published by thread 0's
+// agent-scope release increment after a workgroup barrier, and acquired by the
+// waiting thread 0's agent-scope acquire load before a barrier (the pattern of
+// a grid-wide barrier).
 enum QPhase { Q_RED = 0, Q_BLACK = 1, Q_RR = 2, Q_CRHS = 3, Q_PROLONG = 4, Q_COARSE = 5 };
 struct QTask {
     int item, phase, level, z0, z1, prefix;
 };
-constexpr int kQTarget = 8192;  // points per task
+constexpr int kQTarget = 4096;  // points per task (default; GRMG_QUEUE_TARGET)
 constexpr int kQueueMaxNu = 8;  // task table capacity: nu1, nu2 <= 8
 constexpr long kQSpin = 1L << 22; // bounded wait (iterations of a short sleep)
 
@@ -856,12 +857,10 @@ __global__ void __launch_bounds__(CTPB) kb_queue(BatchDev D, const QTask *__rest
         __syncthreads();
         const int t = s_t, go = s_go;
         if (t >= ntasks) return;
-        if (go) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (go) { // thread 0's acquire, then the barrier, orders every thread's reads after the wait
             const QTask q = tasks[t];
             q_run<KIND>(D, q, fid, nu1, nu2, oc);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __syncthreads();
+            __syncthreads(); // every thread's writes before thread 0's release
             if (threadIdx.x == 0) __hip_atomic_fetch_add(&done[q.item], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads(); // s_t, s_go are rewritten next
@@ -1552,6 +1551,7 @@ struct gr_batch_s {
     // points and the coarse cycle of every box in one persistent launch
     bool use_queue = false;
     int queue_n = 32;
+    long queue_target = kQTarget;
     int qcap = 0;                   // task table capacity (nu1, nu2 <= kQueueMaxNu)
     QTask *qtasks = nullptr;        // device task table
     int *qctl = nullptr, *qdone = nullptr;
@@ -1670,7 +1670,7 @@ void q_build(const gr_batch B, int nu1, int nu2, std::vector<QTask> &out)
         const BoxDev &X = H[b];
         auto add = [&](int phase, int level, int planes, long plane_pts) {
             std::vector<QTask> v;
-            const int pz = (int)std::max(1L, std::min((long)planes, (kQTarget + plane_pts - 1) / plane_pts));
+            const int pz = (int)std::max(1L, std::min((long)planes, (B->queue_target + plane_pts - 1) / plane_pts));
             for (int z0 = 0; z0 < planes; z0 += pz) v.push_back(QTask{b, phase, level, z0, std::min(planes, z0 + pz), 0});
             ph[b].push_back(v);
         };
@@ -1683,7 +1683,7 @@ void q_build(const gr_batch B, int nu1, int nu2, std::vector<QTask> &out)
             add(Q_RR, i, m, (long)m * m);
             add(Q_CRHS, i, m, (long)m * m);
         }
-        add(Q_COARSE, X.centry, 1, kQTarget);
+        add(Q_COARSE, X.centry, 1, 1);
         for (int i = X.centry - 1; i >= X.qentry; --i) {
             const int n = X.lev[i].n;
             add(Q_PROLONG, i, n, (long)n * n);
@@ -2138,6 +2138,7 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
     if (const char *e = std::getenv("GRMG_MIXED_STALL")) B->stall_ratio = std::atof(e);
     if (const char *e = std::getenv("GRMG_BATCH_QUEUE")) B->use_queue = std::atoi(e) != 0;
     if (const char *e = std::getenv("GRMG_QUEUE_N")) B->queue_n = std::max(2, std::atoi(e));
+    if (const char *e = std::getenv("GRMG_QUEUE_TARGET")) B->queue_target = std::max(64L, std::atol(e));
     if (const char *e = std::getenv("GRMG_BATCH_GRAPH")) B->use_graph = std::atoi(e) != 0;
     if (const char *e = std::getenv("GRMG_BATCH_CONCURRENT")) B->conc = std::atoi(e) != 0;
     B->host.resize(count + npatch);
