@@ -5,8 +5,9 @@ the CPU-baseline leg of the benchmark, never by the product path.  It shares
 no code with the GPU library.
 
 A patch is a cube of n^3 cells of spacing h whose lower corner sits at
-`origin` (box units) in the frame of a periodic parent box of N^3 cells of
-spacing H.  The iterate of every patch level is padded by one cell on each
+`origin` (box units) in the frame of its parent: a periodic box of N^3 cells
+of spacing H, or (nested refinement) another patch of N^3 interior cells of
+spacing H, whose frame starts at that patch's lower corner.  The iterate of every patch level is padded by one cell on each
 side: shape (n+2, n+2, n+2), [z][y][x] with x fastest, interior [1:n+1]^3;
 the cell across a face holds that face's boundary value (edge and corner
 cells are zero and unused).  Sources, coefficients and right-hand sides are
@@ -41,6 +42,14 @@ readings are taken:
      difference stencil reaches outside the patch it reads the parent's field
      (V_i, U, Psi, xi, B^i, b, and A_ij for d_j of the shift source) at that
      outside cell's centre, by the same interpolation.
+  D6 nested refinement (the parent code's AMR hierarchy): a patch whose
+     parent is a patch takes its boundary values and outside stencil values
+     from that patch's solved interior by the same interpolation, without
+     wrap; every sample must then fall strictly between the parent's cell
+     centres (a child at least (H + h)/2 inside each face of its parent).
+     Levels are solved coarse to fine, each with the finished field of the
+     level above; the coarser levels' potentials are kept, so a refined level
+     can be solved again (a sub-step) from them.
 Red-black order, restriction (mean of 8 children), cell-centred trilinear
 prolongation, Newton point update and the stopping test rms(eps)/rms(f) are
 those of the periodic solver.
@@ -73,21 +82,32 @@ def _kappa(prm) -> float:
 
 # ----------------------------------------------------------------- ghosts
 
-def sample_parent(parent: np.ndarray, H: float, n: int, h: float, origin) -> np.ndarray:
-    """Trilinear interpolation of a periodic parent field (cell-centred, spacing
-    H) at the (n+2)^3 cell centres origin + (i + 1/2) h, i = -1..n, of a padded
+def _cells(g, N, periodic):
+    """Per-axis cells and weight of the cell-centred linear interpolation at
+    parent coordinates g (cell units, centres at integers): cells i0, i0 + 1
+    with weights (1 - t, t).  Periodic: wrapped.  Non-periodic (a parent
+    patch): every g must lie strictly inside (0, N - 1)."""
+    i0 = np.floor(g)
+    t = g - i0
+    i0 = i0.astype(np.int64)
+    if periodic:
+        return np.mod(i0, N), np.mod(i0 + 1, N), t
+    if np.any(g <= 0.0) or np.any(g >= N - 1):
+        raise ValueError("nested patch too close to its parent's faces (reading D6)")
+    return i0, i0 + 1, t
+
+
+def sample_parent(parent: np.ndarray, H: float, n: int, h: float, origin, periodic: bool = True) -> np.ndarray:
+    """Trilinear interpolation of a parent field (cell-centred, spacing H) at
+    the (n+2)^3 cell centres origin + (i + 1/2) h, i = -1..n, of a padded
     patch level (reading D2).  Per axis: g = x/H - 1/2, i0 = floor(g),
-    t = g - i0, weights (1 - t, t) on parent cells i0, i0 + 1 (wrapped)."""
+    t = g - i0, weights (1 - t, t) on parent cells i0, i0 + 1 (wrapped for a
+    periodic box; inside only for a parent patch, reading D6)."""
     N = parent.shape[0]
     idx = np.arange(-1, n + 1, dtype=np.float64)
 
     def axis(o):
-        x = o + (idx + 0.5) * h
-        g = x / H - 0.5
-        i0 = np.floor(g)
-        t = g - i0
-        i0 = i0.astype(np.int64)
-        return np.mod(i0, N), np.mod(i0 + 1, N), t
+        return _cells((o + (idx + 0.5) * h) / H - 0.5, N, periodic)
 
     x0, x1, tx = axis(origin[0])
     y0, y1, ty = axis(origin[1])
@@ -105,18 +125,14 @@ def sample_parent(parent: np.ndarray, H: float, n: int, h: float, origin) -> np.
     return out
 
 
-def face_values(parent: np.ndarray, H: float, n: int, h: float, origin) -> np.ndarray:
+def face_values(parent: np.ndarray, H: float, n: int, h: float, origin, periodic: bool = True) -> np.ndarray:
     """Padded (n+2)^3 array whose cells across the six faces hold the parent
     sampled at the face centres (reading D2); everything else is zero."""
     N = parent.shape[0]
     u = np.concatenate(([0.0], np.arange(n) + 0.5, [float(n)]))    # face-clamped cell coordinates
 
     def axis(o):
-        g = (o + u * h) / H - 0.5
-        i0 = np.floor(g)
-        t = g - i0
-        i0 = i0.astype(np.int64)
-        return np.mod(i0, N), np.mod(i0 + 1, N), t
+        return _cells((o + u * h) / H - 0.5, N, periodic)
 
     x0, x1, tx = axis(origin[0])
     y0, y1, ty = axis(origin[1])
@@ -142,9 +158,9 @@ def _faces(n):
     return [(0, I, I), (n + 1, I, I), (I, 0, I), (I, n + 1, I), (I, I, 0), (I, I, n + 1)]
 
 
-def boundary_of(parent: np.ndarray, H: float, n: int, h: float, origin) -> list[np.ndarray]:
+def boundary_of(parent: np.ndarray, H: float, n: int, h: float, origin, periodic: bool = True) -> list[np.ndarray]:
     """Face values of every level of the patch (reading D2)."""
-    return [face_values(parent, H, m, h * (n // m), origin) for m in levels(n)]
+    return [face_values(parent, H, m, h * (n // m), origin, periodic) for m in levels(n)]
 
 
 # -------------------------------------------------------------- operators
@@ -407,30 +423,34 @@ def build_shift_source(psi, xi, A6p, h, prm):
 # ------------------------------------------------------------ whole patch
 
 def solve_patch(parent: dict, parent_A6: np.ndarray, H: float, src: dict, n: int, h: float, origin,
-                prm, nu1=2, nu2=2, max_cycles=100, rtol=1e-10):
+                prm, nu1=2, nu2=2, max_cycles=100, rtol=1e-10, periodic: bool = True, return_A6: bool = False):
     """The ten equations on one patch in the order of the solution scheme
     (sec. 2.4), zero interior guesses, boundary values from the solved parent.
-      parent    : the parent's ten solved fields by name (N^3, periodic)
+      parent    : the parent's ten solved fields by name (N^3: a periodic box,
+                  or with periodic=False the interior of a parent patch, D6)
       parent_A6 : the parent's A_ij (6, N, N, N)
       src       : the patch's s0, sx, sy, sz, sm (interior, n^3)
+      max_cycles: an int, or one count per field (exactly that many cycles
+                  with rtol = 0)
     Returns (fields: name -> padded array with the face values, status,
-    cycles[10], rel[10], AA)."""
+    cycles[10], rel[10], AA) and, with return_A6, the patch's A_ij."""
     a, om = prm.a, prm.omega_m
     out, cycles, rels, status = {}, [0] * 10, [0.0] * 10, OK
 
     def run(name, kind, f, coef=None):
         nonlocal status
-        g = boundary_of(parent[name], H, n, h, origin)
+        g = boundary_of(parent[name], H, n, h, origin, periodic)
         phi = g[0].copy()
-        phi, st, cyc, rel = solve(kind, phi, f, coef, g[1:], h, prm, nu1, nu2, max_cycles, rtol)
         k = FIELDS.index(name)
+        mc = max_cycles[k] if hasattr(max_cycles, "__len__") else max_cycles
+        phi, st, cyc, rel = solve(kind, phi, f, coef, g[1:], h, prm, nu1, nu2, mc, rtol)
         out[name], cycles[k], rels[k] = phi, cyc, rel
         if st != OK and status == OK:
             status = st
 
     def stencil_view(name):
         """The solved field with the parent at the outside cell centres (D5)."""
-        v = sample_parent(parent[name], H, n, h, origin)
+        v = sample_parent(parent[name], H, n, h, origin, periodic)
         interior(v)[...] = interior(out[name])
         return v
 
@@ -442,11 +462,13 @@ def solve_patch(parent: dict, parent_A6: np.ndarray, H: float, src: dict, n: int
     run("Psi", HAMILTONIAN, 1.5 * a * om * (np.asarray(src["s0"], dtype=np.float64) - 1.0), AA)
     m2, fxi = build_cmc(interior(out["Psi"]), src["s0"], src["sm"], AA, prm)
     run("xi", CMC, fxi, m2)
-    A6p = np.stack([sample_parent(parent_A6[c], H, n, h, origin) for c in range(6)])
+    A6p = np.stack([sample_parent(parent_A6[c], H, n, h, origin, periodic) for c in range(6)])
     A6p[:, 1:-1, 1:-1, 1:-1] = A6
     fB = build_shift_source(stencil_view("Psi"), stencil_view("xi"), A6p, h, prm)
     for d, name in enumerate(("Bx", "By", "Bz")):
         run(name, POISSON, fB[d])
     Bv = [stencil_view(k) for k in ("Bx", "By", "Bz")]
     run("b", POISSON, div_quarter(Bv[0], Bv[1], Bv[2], h))
+    if return_A6:
+        return out, status, cycles, rels, AA, A6
     return out, status, cycles, rels, AA

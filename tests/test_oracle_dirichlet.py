@@ -302,3 +302,72 @@ def test_patch_of_a_solved_parent_at_same_spacing_reproduces_it():
         assert maxrel(D.interior(out[k]), F[k][sl]) < 1e-9, k
     for k in ("Psi", "xi"):
         assert maxrel(D.interior(out[k]), F[k][sl]) < 5e-2, k
+
+
+def test_nested_sampling_matches_scipy_inside_and_refuses_outside():
+    """A parent patch is sampled without wrap (reading D6): scipy's linear
+    interpolation (order 1) at interior points, exact on linear fields, and a
+    child too close to the parent's faces is refused."""
+    rng = np.random.default_rng(7)
+    N, H = 12, 1.0 / 24
+    parent = rng.standard_normal((N, N, N))
+    n, h = 8, H / 2
+    origin = (1.5 * H, 2.0 * H, 3.0 * H)          # >= (H + h)/2 inside every face
+    out = D.sample_parent(parent, H, n, h, origin, periodic=False)
+    c = [(o + (np.arange(-1, n + 1) + 0.5) * h) / H - 0.5 for o in origin]
+    Z, Y, X = np.meshgrid(c[2], c[1], c[0], indexing="ij")
+    ref = ndimage.map_coordinates(parent, [Z.ravel(), Y.ravel(), X.ravel()], order=1).reshape(out.shape)
+    assert np.max(np.abs(out - ref)) < 1e-13
+    fv = D.face_values(parent, H, n, h, origin, periodic=False)
+    u = np.concatenate(([0.0], np.arange(n) + 0.5, [float(n)]))
+    c = [(o + u * h) / H - 0.5 for o in origin]
+    Z, Y, X = np.meshgrid(c[2], c[1], c[0], indexing="ij")
+    ref = ndimage.map_coordinates(parent, [Z.ravel(), Y.ravel(), X.ravel()], order=1).reshape(fv.shape)
+    I = slice(1, n + 1)
+    for sl in ((0, I, I), (n + 1, I, I), (I, 0, I), (I, n + 1, I), (I, I, 0), (I, I, n + 1)):
+        assert np.max(np.abs(fv[sl] - ref[sl])) < 1e-13
+    x = (np.arange(N) + 0.5) * H
+    Zp, Yp, Xp = np.meshgrid(x, x, x, indexing="ij")
+    lin_f = 0.2 - 0.9 * Xp + 1.3 * Yp + 0.4 * Zp
+    got = D.sample_parent(lin_f, H, n, h, origin, periodic=False)
+    cc = [o + (np.arange(-1, n + 1) + 0.5) * h for o in origin]
+    z, y, xx = np.meshgrid(cc[2], cc[1], cc[0], indexing="ij")
+    assert np.max(np.abs(got - (0.2 - 0.9 * xx + 1.3 * y + 0.4 * z))) < 1e-13
+    for bad in ((0.5 * H, 2.0 * H, 3.0 * H), (1.5 * H, 2.0 * H, (N - 4.5) * H)):
+        with pytest.raises(ValueError):
+            D.sample_parent(parent, H, n, h, bad, periodic=False)
+
+
+def test_nested_patch_at_same_spacing_reproduces_its_parent_patch():
+    """Nested pin: a patch (the first refinement of a solved periodic box)
+    and, inside it, a child patch at the same spacing aligned with its cells
+    and fed the same sources.  Both solve the plain discrete equations (no
+    regularisation on patches), and the child's face values and outside
+    stencil values are the parent patch's own cells, so all ten fields of the
+    child equal the parent patch's on that block to the solve tolerance."""
+    N = 16
+    H = 1.0 / N
+    prm = O.params()
+    s0 = 1.0 + synth.grf(N, 41, -2.0, 0.1)
+    sx, sy, sz = (synth.grf(N, 42 + d, -3.0, 1e-3) for d in range(3))
+    sm = np.zeros((N, N, N))
+    F, st, *_ = O.solve_all(s0, sx, sy, sz, sm, rtol=1e-13)
+    assert st == O.OK
+    A6, _ = O.build_Aij(F["Vx"], F["Vy"], F["Vz"], F["U"])
+    # level 1: 12^3 at H/2, lower corner at parent cell (3, 5, 2)
+    n1, h1, o1 = 12, H / 2, (3 * H, 5 * H, 2 * H)
+    rng = np.random.default_rng(9)
+    src1 = dict(s0=1.0 + 0.1 * rng.standard_normal((n1,) * 3), sm=np.zeros((n1,) * 3),
+                **{k: 1e-3 * rng.standard_normal((n1,) * 3) for k in ("sx", "sy", "sz")})
+    P1, st1, c1, r1, AA1, A61 = D.solve_patch(F, A6, H, src1, n1, h1, o1, prm, rtol=1e-13, return_A6=True)
+    assert st1 == D.OK
+    # level 2: 6^3 at the same spacing, 3 cells inside the parent patch
+    n2, off = 6, (3, 2, 4)
+    o2 = tuple(k * h1 for k in off)
+    sl = np.ix_(*[np.arange(off[a], off[a] + n2) for a in (2, 1, 0)])
+    src2 = {k: v[sl] for k, v in src1.items()}
+    parent = {k: D.interior(P1[k]) for k in D.FIELDS}
+    P2, st2, *_ = D.solve_patch(parent, A61, h1, src2, n2, h1, o2, prm, rtol=1e-13, periodic=False)
+    assert st2 == D.OK
+    for k in D.FIELDS:
+        assert maxrel(D.interior(P2[k]), parent[k][sl]) < 1e-9, k
