@@ -341,8 +341,13 @@ int gr_create_batch(const gr_grid_desc *descs, int count, const gr_params *prm, 
 /* A Dirichlet refinement patch (the refined levels of sec. 3, whose boundary
  * values come from the coarser level): n^3 cells (3 <= n <= 512) of spacing
  * h (0 < h <= 1e3) whose lower corner sits at origin[x,y,z] (box units,
- * |origin| <= 1e6) in the frame of the periodic box `parent` of the same
- * batch.  Anything else: GR_EINVAL.
+ * |origin| <= 1e6) in the frame of its parent: the periodic box `parent`
+ * (0 <= parent < nbox), or for nested refinement an earlier patch (parent =
+ * nbox + j', j' below this patch's index), whose frame starts at that patch's
+ * lower corner.  A nested patch must keep every interpolation sample strictly
+ * between its parent's cell centres: per axis origin > (H + h)/2 and
+ * origin + (n + 1/2) h < (N - 1/2) H for a parent of N cells of spacing H.
+ * Anything else: GR_EINVAL.
  * Readings: levels halve while n is even and n/2 >= 3 (24..80 in steps of 8
  * end at 3, 4, 5, 3, 7, 4, 9, 5 cells); on every level the boundary value of
  * each boundary face is the parent's solved field at the face centre by
@@ -364,9 +369,11 @@ typedef struct {
 
 /* A batch of nbox periodic boxes (items 0..nbox-1) and npatch patches (items
  * nbox..nbox+npatch-1), nbox + npatch <= 4096.  gr_batch_solve solves each
- * field of the patches right after that field of the boxes.  set/get_field
- * on a patch item move dense n^3 arrays (solved fields are stored padded
- * internally). */
+ * field of the patches right after that field of the boxes, nested patches
+ * depth by depth (each depth from the finished field of the one above).
+ * Every potential keeps its own array per item, so the coarser levels' fields
+ * stay available after a solve.  set/get_field on a patch item move dense n^3
+ * arrays (solved fields are stored padded internally). */
 int gr_create_batch_patches(const gr_grid_desc *boxes, int nbox, const gr_patch_desc *patches, int npatch,
                             const gr_params *prm, gr_batch *out);
 int gr_batch_workspace_bytes(gr_batch b, size_t *bytes);
@@ -381,6 +388,14 @@ int gr_batch_get_field(gr_batch b, int item, int field, void *d_dst, int dtype);
  * time from the start of each field's solve until the box met its tolerance,
  * summed over the fields).  Returns the first non-OK box status. */
 int gr_batch_solve(gr_batch b, const gr_solve_opts *opts, int *cycles, double *rel_res, double *item_seconds);
+/* A sub-step of the refined levels (the parent code's adaptive time steps,
+ * sec. 7): the ten equations of the patches only, from their current sources
+ * (gr_batch_set_field on the patch items), with boundary and outside-stencil
+ * values from the kept fields of the boxes and of the patches above them; the
+ * boxes are neither read for their sources nor changed.  Outputs as
+ * gr_batch_solve (a box's entries stay those of the last solve that ran it).
+ * GR_EINVAL if the batch has no patches. */
+int gr_batch_solve_patches(gr_batch b, const gr_solve_opts *opts, int *cycles, double *rel_res, double *item_seconds);
 /* Tunes how each level of the periodic boxes is smoothed: for every depth
  * handled by grouped launches and every box side there with n >= 32 and
  * n % 16 == 0 it times one launch per colour, fused 16x16 tiles, and, where

@@ -57,7 +57,8 @@ struct BoxDev {
     int qentry; // first level run by the device task queue (== centry: only the coarse cycle)
     int centry32; // first level of the FP32 correction cycle handled by the single-workgroup kernel
     int patch;  // 1: Dirichlet patch (padded iterate arrays), 0: periodic box
-    int parent; // patch: index of the periodic box its boundary values come from
+    int parent; // patch: index of the item (periodic box or earlier patch) its boundary values come from
+    int depth;  // 0: periodic box; patch: its parent's depth + 1
     double origin[3]; // patch: lower corner in the parent's frame (box units)
     double *field[10];
     double *src[5];
@@ -526,6 +527,13 @@ __global__ void kb_activate_fallback(BatchDev D, int b0, int b1, int set)
     }
     __syncthreads();
     if (threadIdx.x == 0) *D.any_active = any;
+}
+
+// patches of [b0, b1) at nesting depth `depth` (all of them: depth < 0)
+// become the active set
+__global__ void kb_activate_depth(BatchDev D, int b0, int b1, int depth)
+{
+    for (int b = b0 + threadIdx.x; b < b1; b += blockDim.x) D.active[b] = depth < 0 || D.box[b].depth == depth;
 }
 
 // ------------------------------------------------------------- builders
@@ -1256,6 +1264,7 @@ __global__ void __launch_bounds__(TPB) kp_norms(BatchDev D, const int *__restric
 __global__ void __launch_bounds__(TPB) kp_faces(BatchDev D, const int *__restrict__ tab, int d, int fid)
 {
     BOX_PROLOGUE(tab)
+    if (!D.active[b]) return;
     const BoxLev &L = X.lev[d];
     const int n = L.n, W = n + 2;
     if (t >= W * W * W) return;
@@ -1266,8 +1275,8 @@ __global__ void __launch_bounds__(TPB) kp_faces(BatchDev D, const int *__restric
     if (out != 1) return;
     auto u = [n](int q) { return q < 0 ? 0.0 : (q >= n ? (double)n : q + 0.5); }; // face-clamped coordinate
     const BoxDev &P = D.box[X.parent];
-    const double val = sample_periodic(P.field[fid], P.lev[0].n, P.lev[0].h, X.origin[0] + u(i) * L.h,
-                                       X.origin[1] + u(j) * L.h, X.origin[2] + u(k) * L.h);
+    const double val = sample_parent_at(P.field[fid], P.patch, 1, P.lev[0].n, P.lev[0].h, X.origin[0] + u(i) * L.h,
+                                        X.origin[1] + u(j) * L.h, X.origin[2] + u(k) * L.h);
     patch_phi(X, d, fid)[t] = val;
 }
 
@@ -1297,10 +1306,12 @@ __global__ void __launch_bounds__(TPB) kp_build(BatchDev D, const int *__restric
     int x, y, z;
     decode3(t, n, n, x, y, z);
     const BoxDev &P = D.box[X.parent];
-    auto F = [&](const double *mine, int padded, const double *theirs) {
-        return PatchField{mine, padded, n, L.h, X.origin[0], X.origin[1], X.origin[2], theirs, P.lev[0].n, P.lev[0].h};
+    // the parent's fields are padded when it is a patch; its A_ij is dense
+    auto F = [&](const double *mine, int padded, const double *theirs, int ppadded) {
+        return PatchField{mine, padded, n, L.h, X.origin[0], X.origin[1], X.origin[2], theirs, P.lev[0].n, P.lev[0].h,
+                          P.patch, ppadded};
     };
-    auto FF = [&](int f) { return F(X.field[f], 1, P.field[f]); };
+    auto FF = [&](int f) { return F(X.field[f], 1, P.field[f], 1); };
     const double inv2h = 1.0 / (2.0 * L.h);
     switch (what) {
     case 0: L.f[t] = (3.0 * om * a) * X.src[1 + comp][t]; break;
@@ -1318,8 +1329,8 @@ __global__ void __launch_bounds__(TPB) kp_build(BatchDev D, const int *__restric
         cmc_point(X.field[GR_PSI][pidx(x, y, z, n)], X.src[0][t], X.src[4][t], X.AA[t], a, om, c, L.coef[t], L.f[t]);
         break;
     case 4: {
-        const PatchField A[6] = {F(X.A6[0], 0, P.A6[0]), F(X.A6[1], 0, P.A6[1]), F(X.A6[2], 0, P.A6[2]),
-                                 F(X.A6[3], 0, P.A6[3]), F(X.A6[4], 0, P.A6[4]), F(X.A6[5], 0, P.A6[5])};
+        const PatchField A[6] = {F(X.A6[0], 0, P.A6[0], 0), F(X.A6[1], 0, P.A6[1], 0), F(X.A6[2], 0, P.A6[2], 0),
+                                 F(X.A6[3], 0, P.A6[3], 0), F(X.A6[4], 0, P.A6[4], 0), F(X.A6[5], 0, P.A6[5], 0)};
         double out[3];
         shift_source_f(FF(GR_PSI), FF(GR_XI), A, x, y, z, L.h, a, c, out);
         X.fB[0][t] = out[0];
@@ -1523,6 +1534,7 @@ struct gr_batch_s {
     gr_solve_opts graph_opts[30]{}; // options it was captured with
     // patches: levels handled by grouped launches (depth < pmaxdepth), all levels (< pmaxlev)
     int pmaxdepth = 0, pmaxlev = 0;
+    int pnest = 0; // deepest patch nesting (1: every patch's parent is a box)
     Tab pfine;                                  // interior cells of level 0
     // mixed precision (periodic boxes): grouped levels of the FP32 correction cycle
     int maxdepth32 = 0;
@@ -2075,6 +2087,8 @@ void patch_faces(gr_batch B, hipStream_t s, int fid)
         if (B->pfaces[l].total()) kp_faces<<<B->pfaces[l].total(), TPB, 0, s>>>(B->Dp, B->pfaces[l].dev, l, fid);
 }
 
+// field fid of every patch, nesting depth by depth: each depth's boundary
+// values come from the finished field of the depth above (reading D6)
 int patch_field(gr_batch B, hipStream_t s, int kind, int fid, const gr_solve_opts &o)
 {
     kb_begin_field<<<1, 1024, 0, s>>>(B->Dp, fid, B->nper, B->nbox, 10 + fid);
@@ -2082,9 +2096,12 @@ int patch_field(gr_batch B, hipStream_t s, int kind, int fid, const gr_solve_opt
         for (size_t d = 0; d < B->pcoefr.size(); ++d)
             if (B->pcoefr[d].total())
                 kp_restrict_coef<<<B->pcoefr[d].total(), TPB, 0, s>>>(B->Dp, B->pcoefr[d].dev, (int)d);
-    patch_faces(B, s, fid);
-    BLAUNCH();
-    BCHK(run_cycles(B, s, B->Dp.any_active, 10 + fid, o, [&] { return patch_cycle(B, s, kind, fid, o); }));
+    for (int depth = 1; depth <= B->pnest; ++depth) {
+        if (B->pnest > 1) kb_activate_depth<<<1, 1024, 0, s>>>(B->Dp, B->nper, B->nbox, depth);
+        patch_faces(B, s, fid);
+        BLAUNCH();
+        BCHK(run_cycles(B, s, B->Dp.any_active, 10 + fid, o, [&] { return patch_cycle(B, s, kind, fid, o); }));
+    }
     return read_rel(B, s, fid, B->nper, B->nbox);
 }
 
@@ -2124,9 +2141,22 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
         const gr_patch_desc &q = patches[j];
         const bool origin_ok = std::fabs(q.origin[0]) <= 1e6 && std::fabs(q.origin[1]) <= 1e6 &&
                                std::fabs(q.origin[2]) <= 1e6; // false for NaN
-        if (q.n < 3 || q.n > 512 || !(q.h > 0.0) || !(q.h <= 1e3) || q.parent < 0 || q.parent >= count || !origin_ok)
-            return bfail(GR_EINVAL, "patch %d: n = %d must be 3..512, 0 < h <= 1e3, parent a box index, |origin| <= 1e6",
+        if (q.n < 3 || q.n > 512 || !(q.h > 0.0) || !(q.h <= 1e3) || q.parent < 0 || q.parent >= count + j ||
+            !origin_ok)
+            return bfail(GR_EINVAL,
+                         "patch %d: n = %d must be 3..512, 0 < h <= 1e3, parent a box or an earlier patch, "
+                         "|origin| <= 1e6",
                          j, q.n);
+        if (q.parent >= count) { // nested: every sample strictly between the parent patch's cell centres
+            const gr_patch_desc &P = patches[q.parent - count];
+            for (int a = 0; a < 3; ++a) {
+                const double glo = (q.origin[a] - 0.5 * q.h) / P.h - 0.5;
+                const double ghi = (q.origin[a] + (q.n + 0.5) * q.h) / P.h - 0.5;
+                if (!(glo > 0.0) || !(ghi < P.n - 1.0))
+                    return bfail(GR_EINVAL, "patch %d: must lie at least (H + h)/2 inside its parent patch %d",
+                                 j, q.parent - count);
+            }
+        }
     }
     gr_batch B = new (std::nothrow) gr_batch_s();
     if (!B) return bfail(GR_EINVAL, "out of host memory");
@@ -2184,6 +2214,8 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
         std::memset(&X, 0, sizeof X);
         X.patch = 1;
         X.parent = q.parent;
+        X.depth = q.parent < count ? 1 : B->host[q.parent].depth + 1;
+        B->pnest = std::max(B->pnest, X.depth);
         for (int a = 0; a < 3; ++a) X.origin[a] = q.origin[a];
         X.nlev = patch_levels(q.n);
         X.centry = X.nlev - 1;
@@ -2570,6 +2602,7 @@ int gr_batch_debug_boundary(gr_batch B, int item, int field, int level, double *
     const BoxDev &X = B->host[item];
     if (level < 0 || level >= X.nlev) return bfail(GR_EINVAL, "level %d outside 0..%d", level, X.nlev - 1);
     hipStream_t s = B->stream;
+    kb_activate_depth<<<1, 1024, 0, s>>>(B->Dp, B->nper, B->nbox, -1); // the face kernel serves active patches
     patch_faces(B, s, field);
     const long w = X.lev[level].n + 2;
     launch_copy(s, d_dst, level == 0 ? X.field[field] : X.lev[level].phi, w * w * w);
@@ -2577,11 +2610,14 @@ int gr_batch_debug_boundary(gr_batch B, int item, int field, int level, double *
     return GR_OK;
 }
 
-int gr_batch_solve(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_res, double *item_seconds)
+// the whole batch, or (patches_only) the patches alone from the boxes' kept fields
+static int batch_solve_impl(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_res, double *item_seconds,
+                            bool patches_only)
 {
     b_err.clear(); // a message left by an earlier call must not be reported for this one
     if (!B || !o) return bfail(GR_EINVAL, "null argument");
     if (!B->bound) return bfail(GR_ESTATE, "batch not bound");
+    if (patches_only && B->npatch == 0) return bfail(GR_EINVAL, "the batch has no patches");
     if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 64 || o->nu2 > 64 || o->max_cycles < 0 || o->max_cycles > 100000)
         return bfail(GR_EINVAL, "bad cycle options");
     if (o->precision != GR_FP64 && o->precision != GR_MIXED) return bfail(GR_EINVAL, "bad precision");
@@ -2591,8 +2627,10 @@ int gr_batch_solve(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_
     const unsigned mask = o->field_mask;
     const OpConst oc = opc(B);
     const int FT = B->fine.total();
-    B->rel_hist.assign((size_t)B->nbox * 10, 0.0);
-    B->fb_hist.assign((size_t)B->nbox * 10, 0);
+    if (!patches_only || B->rel_hist.size() != (size_t)B->nbox * 10) {
+        B->rel_hist.assign((size_t)B->nbox * 10, 0.0);
+        B->fb_hist.assign((size_t)B->nbox * 10, 0);
+    }
     std::vector<int> zero(B->nbox, 0);
     BHIP(hipMemcpyAsync(B->D.status, zero.data(), sizeof(int) * B->nbox, hipMemcpyHostToDevice, s));
     std::vector<unsigned long long> tz((size_t)B->nbox * 10, 0ull);
@@ -2601,12 +2639,12 @@ int gr_batch_solve(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_
     if (o->guess == GR_GUESS_ZERO)
         for (int f = 0; f < 10; ++f)
             if (mask & (1u << f)) {
-                kb_fill_field<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, f);
+                if (!patches_only) kb_fill_field<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, f);
                 if (PT) kp_fill_field<<<PT, TPB, 0, s>>>(B->Dp, B->pfine.dev, f);
             }
     BLAUNCH();
     // the patches' stream: their own, joined to the batch's by events, or the batch's
-    const bool conc = B->npatch && B->conc && B->pstream && s != nullptr;
+    const bool conc = !patches_only && B->npatch && B->conc && B->pstream && s != nullptr;
     hipStream_t ps = conc ? B->pstream : s;
     auto build = [&](int what, int comp) {
         kb_build<<<FT, TPB, 0, s>>>(B->D, B->fine.dev, what, comp, P.a, P.omega_m, P.c_tilde);
@@ -2697,7 +2735,9 @@ int gr_batch_solve(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_
         });
     }
     int bstatus = GR_OK;
-    for (size_t k = 0; k < steps.size() && bstatus == GR_OK; ++k) {
+    for (size_t k = 0; k < steps.size() && bstatus == GR_OK && patches_only; ++k)
+        bstatus = patch_step(steps[k]); // a sub-step of the refined levels: the boxes' fields are kept
+    for (size_t k = 0; k < steps.size() && bstatus == GR_OK && !patches_only; ++k) {
         const Step &S = steps[k];
         S.pre_box();
         hipError_t e = hipGetLastError();
@@ -2768,6 +2808,16 @@ int gr_batch_solve(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_
             break;
         }
     return first_bad;
+}
+
+int gr_batch_solve(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_res, double *item_seconds)
+{
+    return batch_solve_impl(B, o, cycles, rel_res, item_seconds, false);
+}
+
+int gr_batch_solve_patches(gr_batch B, const gr_solve_opts *o, int *cycles, double *rel_res, double *item_seconds)
+{
+    return batch_solve_impl(B, o, cycles, rel_res, item_seconds, true);
 }
 
 } // extern "C"

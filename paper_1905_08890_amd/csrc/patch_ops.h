@@ -5,7 +5,8 @@
 // cell across each boundary face holds that face's boundary value b, taken
 // from the parent box at the face centre.  The 7-point stencil of a boundary
 // cell uses 2b - phi_cell across the face (the linear extrapolation whose face
-// average is b), so the boundary sits on the same faces on every level and is
+// average is b), the parent being a periodic box or (nested refinement) a
+// patch, so the boundary sits on the same faces on every level and is
 // second order.  Sources, coefficients and the restricted quantities stay
 // dense n^3.  The paper takes the boundary values of refined levels from the
 // coarser level (sec. 3) and regularises only the periodic equations
@@ -57,6 +58,41 @@ __device__ __forceinline__ double sample_periodic(const double *__restrict__ P, 
     return s;
 }
 
+// The same interpolation inside a parent patch (nested refinement): no wrap;
+// the patch's placement was checked so that floor(g) and floor(g) + 1 are
+// interior cells of the parent for every sample.  P is the parent's array,
+// padded (n+2)^3 or dense n^3.
+__device__ __forceinline__ double sample_inside(const double *__restrict__ P, int padded, int N, double H, double x,
+                                                double y, double z)
+{
+    const double gx = x / H - 0.5, gy = y / H - 0.5, gz = z / H - 0.5;
+    const double fx = floor(gx), fy = floor(gy), fz = floor(gz);
+    const double t[3] = {gx - fx, gy - fy, gz - fz};
+    const int i0[3] = {(int)fx, (int)fy, (int)fz};
+    double s = 0.0;
+    for (int cz = 0; cz < 2; ++cz) {
+        const double wz = cz ? t[2] : 1.0 - t[2];
+        const int zz = i0[2] + cz;
+        for (int cy = 0; cy < 2; ++cy) {
+            const double wy = cy ? t[1] : 1.0 - t[1];
+            const int yy = i0[1] + cy;
+            for (int cx = 0; cx < 2; ++cx) {
+                const double wx = cx ? t[0] : 1.0 - t[0];
+                const int xx = i0[0] + cx;
+                s += (wz * wy) * wx * P[padded ? pidx(xx, yy, zz, N) : lin(xx, yy, zz, N)];
+            }
+        }
+    }
+    return s;
+}
+
+// A parent's field at a point of its frame: periodic box or patch
+__device__ __forceinline__ double sample_parent_at(const double *__restrict__ P, int parent_is_patch, int padded,
+                                                   int N, double H, double x, double y, double z)
+{
+    return parent_is_patch ? sample_inside(P, padded, N, H, x, y, z) : sample_periodic(P, N, H, x, y, z);
+}
+
 // A patch field for the source builders: the patch's own value inside, the
 // parent's field at the cell centre outside (one cell beyond the faces, edges
 // and corners included).
@@ -68,11 +104,13 @@ struct PatchField {
     const double *parent;
     int N;
     double H;
+    int ppatch, ppadded; // parent is a patch; its array is padded
     __device__ __forceinline__ double operator()(int i, int j, int k) const
     {
         if ((unsigned)i < (unsigned)n && (unsigned)j < (unsigned)n && (unsigned)k < (unsigned)n)
             return p[padded ? pidx(i, j, k, n) : lin(i, j, k, n)];
-        return sample_periodic(parent, N, H, ox + (i + 0.5) * h, oy + (j + 0.5) * h, oz + (k + 0.5) * h);
+        return sample_parent_at(parent, ppatch, ppadded, N, H, ox + (i + 0.5) * h, oy + (j + 0.5) * h,
+                                oz + (k + 0.5) * h);
     }
 };
 

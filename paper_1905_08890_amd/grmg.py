@@ -37,7 +37,8 @@ EXPORTS = ("gr_default_opts", "gr_create_grid", "gr_workspace_bytes", "gr_bind",
            "gr_debug_sweep", "gr_kick", "gr_drift", "gr_newtonian_kick",
            "gr_debug_residual", "gr_destroy_grid", "gr_last_error", "gr_features", "gr_set_guess", "gr_autotune", "gr_sweep_timing", "gr_create_batch", "gr_create_batch_patches",
            "gr_batch_debug_boundary", "gr_batch_autotune", "gr_batch_mixed_fallbacks", "gr_batch_workspace_bytes",
-           "gr_batch_bind", "gr_batch_set_field", "gr_batch_get_field", "gr_batch_solve", "gr_destroy_batch",
+           "gr_batch_bind", "gr_batch_set_field", "gr_batch_get_field", "gr_batch_solve", "gr_batch_solve_patches",
+           "gr_destroy_batch",
            "gr_batch_last_error", "gr_unet_create", "gr_unet_workspace_bytes", "gr_unet_param_count", "gr_unet_bind",
            "gr_unet_init", "gr_unet_set_params", "gr_unet_get_params", "gr_unet_forward", "gr_unet_loss_grad",
            "gr_unet_train_step", "gr_destroy_unet", "gr_unet_last_error", "gr_create_spectra",
@@ -131,6 +132,8 @@ def load_library(path: str = LIB_PATH):
         "gr_batch_get_field": [vp, C.c_int, C.c_int, vp, C.c_int],
         "gr_batch_solve": [vp, C.POINTER(GrSolveOpts), C.POINTER(C.c_int), C.POINTER(C.c_double),
                            C.POINTER(C.c_double)],
+        "gr_batch_solve_patches": [vp, C.POINTER(GrSolveOpts), C.POINTER(C.c_int), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double)],
         "gr_destroy_batch": [vp],
         "gr_unet_create": [C.POINTER(GrUnetDesc), C.c_int, C.POINTER(vp)],
         "gr_unet_workspace_bytes": [vp, C.POINTER(C.c_size_t)],
@@ -427,11 +430,13 @@ def batch_debug_boundary(b: int, item: int, field: int, level: int, dst) -> None
     _bcheck(load_library().gr_batch_debug_boundary(b, item, field, level, _ptr(dst)))
 
 
-def batch_solve(b: int, count: int, opts: GrSolveOpts, allow=(OK,)):
+def batch_solve(b: int, count: int, opts: GrSolveOpts, allow=(OK,), patches_only: bool = False):
     cyc = (C.c_int * (10 * count))()
     rel = (C.c_double * (10 * count))()
     sec = (C.c_double * count)()
-    st = _bcheck(load_library().gr_batch_solve(b, C.byref(opts), cyc, rel, sec), allow)
+    lib = load_library()
+    fn = lib.gr_batch_solve_patches if patches_only else lib.gr_batch_solve
+    st = _bcheck(fn(b, C.byref(opts), cyc, rel, sec), allow)
     return st, [list(cyc[10 * i:10 * i + 10]) for i in range(count)], \
         [list(rel[10 * i:10 * i + 10]) for i in range(count)], list(sec)
 
@@ -511,8 +516,10 @@ class Batch:
         self.stream.synchronize()
         return out
 
-    def solve(self, allow=(OK,), **kw):
-        st, cyc, rel, sec = batch_solve(self.handle, len(self.ns), default_opts(**kw), allow)
+    def solve(self, allow=(OK,), patches_only=False, **kw):
+        """All items, or (patches_only) a sub-step of the patches from the kept
+        fields of the boxes and of the patches above them."""
+        st, cyc, rel, sec = batch_solve(self.handle, len(self.ns), default_opts(**kw), allow, patches_only)
         self._keep.clear()
         count = len(self.ns)
         fb = (C.c_int * (10 * count))()

@@ -138,3 +138,16 @@ def test_spectra_handle_validation():
         assert lib.gr_spectra_bind(h, C.c_void_p(257), nbytes.value, None) == grmg.EINVAL
     finally:
         assert lib.gr_destroy_spectra(h) == grmg.OK
+
+
+def test_nested_patch_descriptors_rejected():
+    """A nested patch needs an earlier parent and every interpolation sample
+    strictly between its parent patch's cell centres (host-side checks)."""
+    nb = 1
+    good = (24, 1 / 64, 0, (5 / 32, 6 / 32, 8 / 32))
+    for bad in [(8, 1 / 128, nb + 1, (0.05, 0.05, 0.05)),       # parent not earlier
+                (8, 1 / 128, nb + 0, (0.005, 0.05, 0.05)),      # closer than (H + h)/2 to the low face
+                (16, 1 / 128, nb + 0, (0.05, 0.3, 0.05))]:      # beyond the high face
+        with pytest.raises(grmg.GrError):
+            grmg.create_batch([32], 1.0, 0.3, 1.0, patches=[good, bad])
+    grmg.destroy_batch(grmg.create_batch([32], 1.0, 0.3, 1.0, patches=[good, (8, 1 / 128, nb + 0, (0.05, 0.05, 0.05))]))

@@ -176,3 +176,91 @@ def test_patch_descriptors_rejected():
         B.debug_boundary(0, "U", 0)                                        # not a patch
     with pytest.raises(grmg.GrError):
         B.debug_boundary(1, "U", 3)                                        # 8 -> 4: two levels
+
+
+def _nested_case():
+    boxes = [32]
+    nb = len(boxes)
+    patches = [(24, 1 / 64, 0, (5 / 32, 6 / 32, 8 / 32)),              # depth 1
+               (16, 1 / 128, nb + 0, (3 / 64, 5 / 64, 2 / 64)),       # depth 2, inside patch 0
+               (8, 1 / 256, nb + 1, (2 / 128, 4 / 128, 3 / 128)),     # depth 3, inside patch 1
+               (8, 1 / 128, nb + 0, (10 / 64, 12 / 64, 9 / 64))]      # depth 2, inside patch 0
+    box_src = [synth._matter_sources(n, 600 + b, 0.2) for b, n in enumerate(boxes)]
+    patch_src = [synth._matter_sources(n, 700 + j, 0.1) for j, (n, _, _, _) in enumerate(patches)]
+    return boxes, patches, box_src, patch_src
+
+
+def _oracle_patches(boxes, patches, parents_box, patch_src, prm, K):
+    """Oracle solves of the patches in item order (parents first), each from
+    its parent's oracle fields: (fields by name as interior arrays, A_ij)."""
+    nb = len(boxes)
+    res = []
+    for j, (n, h, par, o) in enumerate(patches):
+        src = dict(zip(SRC, patch_src[j]))
+        if par < nb:
+            F, A6 = parents_box[par]
+            H, periodic = 1.0 / boxes[par], True
+        else:
+            F, A6 = res[par - nb]
+            H, periodic = patches[par - nb][1], False
+        out, st, cyc, rel, AA, pA6 = OD.solve_patch(F, A6, H, src, n, h, o, prm, max_cycles=K, rtol=0.0,
+                                                   periodic=periodic, return_A6=True)
+        assert st == OD.OK
+        res.append(({k: OD.interior(out[k]) for k in OD.FIELDS}, pA6))
+    return res
+
+
+def test_nested_patches_match_oracle_at_equal_cycles():
+    """Nested refinement (reading D6): patches inside patches, three deep,
+    each depth solved from the finished field of the depth above; after
+    exactly 12 cycles per field every patch equals the patch oracle fed with
+    the oracle's own parents (1e-12)."""
+    K = 12
+    boxes, patches, box_src, patch_src = _nested_case()
+    print("[gpu] nested patches vs oracle", flush=True)
+    B = grmg.Batch(boxes, **PRM, patches=patches)
+    _load(B, boxes, box_src, patch_src)
+    r = B.solve(rtol=0.0, max_cycles=K)
+    assert r["status"] == grmg.OK and all(c == [K] * 10 for c in r["cycles"])
+    prm = O.params(a=PRM["a"], omega_m=PRM["omega_m"], c_tilde=PRM["c_tilde"])
+    F, st, *_ = O.solve_all(*box_src[0], prm=prm, max_cycles=K, rtol=0.0)
+    for k in O.FIELDS:
+        assert maxrel(B.get_field(0, k).cpu().numpy(), F[k]) < 1e-12, k
+    ref = _oracle_patches(boxes, patches, [(F, O.build_Aij(F["Vx"], F["Vy"], F["Vz"], F["U"])[0])], patch_src,
+                          prm, K)
+    for j in range(len(patches)):
+        for k in OD.FIELDS:
+            got = B.get_field(len(boxes) + j, k).cpu().numpy()
+            assert maxrel(got, ref[j][0][k]) < 1e-12, (j, k)
+
+
+def test_patch_substep_keeps_the_coarse_fields():
+    """A sub-step of the refined levels: after a full solve, new sources on
+    the patches and gr_batch_solve_patches leave the box's fields bit for bit
+    and give the patches the oracle's solution from those kept fields (12
+    cycles per field, 1e-12)."""
+    K = 12
+    boxes, patches, box_src, patch_src = _nested_case()
+    print("[gpu] patch sub-step", flush=True)
+    B = grmg.Batch(boxes, **PRM, patches=patches)
+    _load(B, boxes, box_src, patch_src)
+    assert B.solve(rtol=1e-10)["status"] == grmg.OK
+    kept = [B.get_field(0, f).clone() for f in range(10)]
+    new_src = [synth._matter_sources(n, 800 + j, 0.1) for j, (n, _, _, _) in enumerate(patches)]
+    for j, src in enumerate(new_src):
+        for name, v in zip(SRC, src):
+            B.set_field(len(boxes) + j, name, v)
+    r = B.solve(patches_only=True, rtol=0.0, max_cycles=K)
+    assert r["status"] == grmg.OK
+    for j in range(len(patches)):
+        assert r["cycles"][len(boxes) + j] == [K] * 10
+    for f in range(10):
+        assert torch.equal(B.get_field(0, f), kept[f]), f
+    prm = O.params(a=PRM["a"], omega_m=PRM["omega_m"], c_tilde=PRM["c_tilde"])
+    F = {k: kept[i].cpu().numpy() for i, k in enumerate(O.FIELDS)}
+    ref = _oracle_patches(boxes, patches, [(F, O.build_Aij(F["Vx"], F["Vy"], F["Vz"], F["U"])[0])], new_src, prm, K)
+    for j in range(len(patches)):
+        for k in OD.FIELDS:
+            got = B.get_field(len(boxes) + j, k).cpu().numpy()
+            assert maxrel(got, ref[j][0][k]) < 1e-12, (j, k)
+
