@@ -439,6 +439,14 @@ def bench_batch(torch, grmg, synth, steps):
         rep_m = B.solve(rtol=1e-10, precision="mixed")
         mtimes.append(time.perf_counter() - t0)
     dtm = min(mtimes)
+    # a sub-step of the refined levels: the 32 patches alone, from the boxes'
+    # kept fields (as between two coarse time steps)
+    rep_p = B.solve(rtol=1e-10, patches_only=True)
+    ptimes = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        rep_p = B.solve(rtol=1e-10, patches_only=True)
+        ptimes.append(time.perf_counter() - t0)
     B.close()
     # the same solve with the device task queue (levels of at most 32^3 points and
     # each box's coarse cycle in one persistent launch per cycle)
@@ -477,6 +485,8 @@ def bench_batch(torch, grmg, synth, steps):
            "autotune": {"seconds": round(tune_s, 3), "choices": tune.strip().splitlines()},
            "mixed": {"status": rep_m["status"], "seconds": round(dtm, 4),
                      "note": "boxes by FP64/FP32 iterative refinement, patches in FP64"},
+           "patch_substep": {"status": rep_p["status"], "seconds": round(min(ptimes), 4),
+                             "note": "the 32 patches solved again from the boxes' kept fields (gr_batch_solve_patches)"},
            "queue": {"status": rep_q["status"], "seconds": round(min(qtimes), 4),
                      "same_cycles": rep_q["cycles"] == rep["cycles"],
                      "note": "FP64 with the device task queue for every box's levels of at most 32^3 points and "
