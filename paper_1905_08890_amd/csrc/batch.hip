@@ -47,6 +47,7 @@ struct BoxLev {
     int n;
     double h;
     double *phi, *phi0, *f, *coef, *tmp; // phi of level 0 is the current field array
+    double *ptmp; // patch levels swept fused: padded scratch iterate (its faces hold the boundary values too)
     // mixed precision (periodic boxes): FP32 correction e, its source b, the
     // frozen linearisation a (chi) and c, scratch
     float *e, *b32, *a32, *c32, *t32;
@@ -1154,6 +1155,101 @@ __global__ void __launch_bounds__(TPB) kp_colour(BatchDev D, const int *__restri
     phi[p] = phi[p] - (Lv - L.f[q]) / J;
 }
 
+// Fused red-black sweep of patch levels: one workgroup per TX x TY x TZ tile
+// of a level.  The tile's neighbourhood with a 2-cell halo (the face values b
+// in the padded layer included) is read into LDS; red points of the tile and of
+// its 1-cell ring are updated from old values, then the tile's black points
+// from those, and the tile is written out of place (even sweeps phi -> ptmp,
+// odd ptmp -> phi), so tiles never read each other's output and the result is
+// the red-then-black sweep of kp_colour.  Boundary cells use 2b - phi_cell
+// across their faces with the matching Newton derivative; the Poisson kinds
+// multiply by the constant -1/J = h^2/(6 + faces) instead of dividing.
+__constant__ const double kInvDiag[4] = {1.0 / 6.0, 1.0 / 7.0, 1.0 / 8.0, 1.0 / 9.0}; // 1/(6 + boundary faces)
+
+template <int KIND>
+__device__ __forceinline__ double patch_op_lds(const double *__restrict__ s, int q, int W, int W2, int i, int j, int k,
+                                               int n, double inv_h2, double c1, OpConst oc, double &J, int &nf)
+{
+    const double ph = s[q];
+    double nbs = s[q - 1] + s[q + 1] + s[q - W] + s[q + W] + s[q - W2] + s[q + W2];
+    nf = 0;
+    if (i == 0) { nbs += s[q - 1] - ph; ++nf; }
+    if (i == n - 1) { nbs += s[q + 1] - ph; ++nf; }
+    if (j == 0) { nbs += s[q - W] - ph; ++nf; }
+    if (j == n - 1) { nbs += s[q + W] - ph; ++nf; }
+    if (k == 0) { nbs += s[q - W2] - ph; ++nf; }
+    if (k == n - 1) { nbs += s[q + W2] - ph; ++nf; }
+    const double L = op_point<KIND, double>(ph, nbs, inv_h2, c1, 0.0, oc, 0.0, J);
+    if (nf) J -= (double)nf * inv_h2 * (KIND == GR_KIND_HAMILTONIAN ? 1.0 - oc.kappa * ph : 1.0);
+    return L;
+}
+
+template <int KIND, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(TPB) kp_fused(BatchDev D, const int *__restrict__ tab, int d, int fid, int sweep,
+                                                OpConst oc)
+{
+    constexpr int HX = TX + 4, HY = TY + 4, HZ = TZ + 4, RX = TX + 2, RY = TY + 2, RZ = TZ + 2;
+    __shared__ double s_old[HX * HY * HZ];
+    __shared__ double s_red[RX * RY * RZ];
+    // XCD-contiguous order: the grid is a multiple of 8 and block g (on XCD
+    // g mod 8) takes tile v, so every XCD sweeps one contiguous run of tiles
+    // and neighbouring tiles share their halos in that XCD's L2
+    const int per = gridDim.x >> 3, v = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (v >= tab[D.nbox]) return;
+    const int b = find_box(tab, D.nbox, v);
+    if (!D.active[b]) return;
+    const BoxDev &X = D.box[b];
+    const BoxLev &L = X.lev[d];
+    const int n = L.n, ntx = (n + TX - 1) / TX, nty = (n + TY - 1) / TY, lb = v - tab[b];
+    const int ox = (lb % ntx) * TX, oy = ((lb / ntx) % nty) * TY, oz = (lb / (ntx * nty)) * TZ;
+    double *phi = patch_phi(X, d, fid);
+    const double *in = (sweep & 1) ? L.ptmp : phi;
+    double *out = (sweep & 1) ? phi : L.ptmp;
+    const double inv_h2 = 1.0 / (L.h * L.h), h2 = L.h * L.h;
+    // old values of the 12^3 neighbourhood (cells beyond the padded layer are never used)
+    for (int t = threadIdx.x; t < HX * HY * HZ; t += TPB) {
+        const int a = t % HX, c = (t / HX) % HY, e = t / (HX * HY);
+        const int i = ox - 2 + a, j = oy - 2 + c, k = oz - 2 + e;
+        const bool in_pad = i >= -1 && i <= n && j >= -1 && j <= n && k >= -1 && k <= n;
+        s_old[t] = in_pad ? in[pidx(i, j, k, n)] : 0.0;
+    }
+    __syncthreads();
+    // red points of the tile and its ring from old values; every other cell keeps its old value
+    for (int t = threadIdx.x; t < RX * RY * RZ; t += TPB) {
+        const int a = t % RX, c = (t / RX) % RY, e = t / (RX * RY);
+        const int i = ox - 1 + a, j = oy - 1 + c, k = oz - 1 + e;
+        const int q = ((e + 1) * HY + (c + 1)) * HX + (a + 1);
+        double v = s_old[q];
+        if (i >= 0 && i < n && j >= 0 && j < n && k >= 0 && k < n && ((i + j + k) & 1) == 0) {
+            double J;
+            int nf;
+            const long g = lin(i, j, k, n);
+            const double Lv = patch_op_lds<KIND>(s_old, q, HX, HX * HY, i, j, k, n, inv_h2, load_c1<KIND>(L.coef, g),
+                                                 oc, J, nf);
+            v = KIND == GR_KIND_POISSON ? v + (Lv - L.f[g]) * (h2 * kInvDiag[nf]) : v - (Lv - L.f[g]) / J;
+        }
+        s_red[t] = v;
+    }
+    __syncthreads();
+    // black points of the tile from the updated red values; the tile written out
+    for (int t = threadIdx.x; t < TX * TY * TZ; t += TPB) {
+        const int a = t % TX, c = (t / TX) % TY, e = t / (TX * TY);
+        const int i = ox + a, j = oy + c, k = oz + e;
+        if (i >= n || j >= n || k >= n) continue;
+        const int q = ((e + 1) * RY + (c + 1)) * RX + (a + 1);
+        double v = s_red[q];
+        if (((i + j + k) & 1) == 1) {
+            double J;
+            int nf;
+            const long g = lin(i, j, k, n);
+            const double Lv = patch_op_lds<KIND>(s_red, q, RX, RX * RY, i, j, k, n, inv_h2, load_c1<KIND>(L.coef, g),
+                                                 oc, J, nf);
+            v = KIND == GR_KIND_POISSON ? v + (Lv - L.f[g]) * (h2 * kInvDiag[nf]) : v - (Lv - L.f[g]) / J;
+        }
+        out[pidx(i, j, k, n)] = v;
+    }
+}
+
 // residual at the 8 children, its mean, and the children's mean of phi (R phi,
 // also kept as phi0): one thread per interior cell of level d+1
 template <int KIND>
@@ -1278,6 +1374,7 @@ __global__ void __launch_bounds__(TPB) kp_faces(BatchDev D, const int *__restric
     const double val = sample_parent_at(P.field[fid], P.patch, 1, P.lev[0].n, P.lev[0].h, X.origin[0] + u(i) * L.h,
                                         X.origin[1] + u(j) * L.h, X.origin[2] + u(k) * L.h);
     patch_phi(X, d, fid)[t] = val;
+    if (L.ptmp) L.ptmp[t] = val;
 }
 
 // interior := 0 (zero guess)
@@ -1541,6 +1638,9 @@ struct gr_batch_s {
     std::vector<Tab> colour32, coarse32, rr32; // per depth: half cells, cells of the next level, residual + restriction
     std::vector<Tab> colour32nf;                  // per depth: half cells of the boxes not swept fused
     std::vector<Tab> pcell;                     // per level above a patch's entry: half its cells (colour passes)
+    std::vector<Tab> pfz;                       // per level above a patch's entry: its 8^3 tiles (fused sweeps)
+    bool pfused = true;                         // fused patch sweeps for even sweep counts (GRMG_PATCH_FUSED)
+    int ptile = 0;                              // their tile: 0 = 8x8x8, 1 = 16x8x8, 2 = 16x16x8 (GRMG_PATCH_TILE)
     std::vector<Tab> pcellf;                    // per level above a patch's entry: its cells (prolongation)
     std::vector<Tab> pcoarse;                   // per depth d: interior cells of level d + 1 (grouped levels)
     std::vector<Tab> pcoefr;                    // per depth d: interior cells of level d + 1 (all levels)
@@ -1611,6 +1711,7 @@ size_t batch_layout(gr_batch B, char *base)
             L.f = takeD(M);
             L.coef = takeD(M);
             L.tmp = takeD(M);
+            L.ptmp = X.patch && l < X.centry ? takeD(iter_len(L.n)) : nullptr;
         }
     }
     auto takeI = [&](size_t count) { return reinterpret_cast<int *>(take(sizeof(int) * count)); };
@@ -1642,7 +1743,7 @@ size_t batch_layout(gr_batch B, char *base)
     }
     for (size_t d = 0; d < B->coefr.size(); ++d) B->coefr[d].dev = takeI(B->nbox + 1);
     B->pfine.dev = takeI(B->nbox + 1);
-    for (auto *v : {&B->pcell, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces, &B->colour32,
+    for (auto *v : {&B->pcell, &B->pfz, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces, &B->colour32,
                     &B->coarse32, &B->rr32, &B->colour32nf})
         for (auto &T : *v) T.dev = takeI(B->nbox + 1);
     return off;
@@ -2047,9 +2148,29 @@ int batch_field_mixed(gr_batch B, int kind, int fid, const gr_solve_opts &o)
 
 // ------------------------------------------------------------ patch cycle
 
+#define PFUSED(kind, TX, TY, TZ)                                                                      \
+    do {                                                                                              \
+        if ((kind) == GR_KIND_POISSON)                                                                \
+            kp_fused<GR_KIND_POISSON, TX, TY, TZ><<<grid8, TPB, 0, s>>>(B->Dp, T.dev, d, fid, it, oc);  \
+        else if ((kind) == GR_KIND_HAMILTONIAN)                                                       \
+            kp_fused<GR_KIND_HAMILTONIAN, TX, TY, TZ><<<grid8, TPB, 0, s>>>(B->Dp, T.dev, d, fid, it, oc); \
+        else                                                                                          \
+            kp_fused<GR_KIND_CMC, TX, TY, TZ><<<grid8, TPB, 0, s>>>(B->Dp, T.dev, d, fid, it, oc); \
+    } while (0)
+
 void patch_smooth(gr_batch B, hipStream_t s, int kind, int d, int fid, int nu)
 {
     const OpConst oc = opc(B);
+    if (B->pfused && nu % 2 == 0) { // an even count of out-of-place sweeps ends in the iterate
+        const Tab &T = B->pfz[d];
+        const unsigned grid8 = (unsigned)((T.total() + 7) / 8 * 8);
+        for (int it = 0; it < nu; ++it) {
+            if (B->ptile == 2) PFUSED(kind, 16, 16, 8);
+            else if (B->ptile == 1) PFUSED(kind, 16, 8, 8);
+            else PFUSED(kind, 8, 8, 8);
+        }
+        return;
+    }
     const Tab &T = B->pcell[d];
     for (int it = 0; it < nu; ++it)
         for (int colour = 0; colour < 2; ++colour)
@@ -2167,6 +2288,8 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
     if (const char *e = std::getenv("GRMG_COARSE_N")) B->coarse_n = std::max(2, std::atoi(e));
     if (const char *e = std::getenv("GRMG_MIXED_STALL")) B->stall_ratio = std::atof(e);
     if (const char *e = std::getenv("GRMG_BATCH_QUEUE")) B->use_queue = std::atoi(e) != 0;
+    if (const char *e = std::getenv("GRMG_PATCH_FUSED")) B->pfused = std::atoi(e) != 0;
+    if (const char *e = std::getenv("GRMG_PATCH_TILE")) B->ptile = std::min(2, std::max(0, std::atoi(e)));
     if (const char *e = std::getenv("GRMG_QUEUE_N")) B->queue_n = std::max(2, std::atoi(e));
     if (const char *e = std::getenv("GRMG_QUEUE_TARGET")) B->queue_target = std::max(64L, std::atol(e));
     if (const char *e = std::getenv("GRMG_BATCH_GRAPH")) B->use_graph = std::atoi(e) != 0;
@@ -2314,11 +2437,17 @@ int create_batch(const gr_grid_desc *descs, int count, const gr_patch_desc *patc
     auto cells = [&](int b, int l) { long n = H[b].patch && l < H[b].nlev ? H[b].lev[l].n : 0; return n * n * n; };
     make_tab(B->pfine, nb, [&](int b) { return cells(b, 0); });
     B->pcell.resize(pmaxd);
+    B->pfz.resize(pmaxd);
     B->pcellf.resize(pmaxd);
     B->pcoarse.resize(pmaxd);
     for (int d = 0; d < pmaxd; ++d) {
         // levels above the entry have n > 16 and even n (they were halved)
         make_tab(B->pcell[d], nb, [&](int b) { return d < H[b].centry ? cells(b, d) / 2 : 0L; });
+        make_tab(B->pfz[d], nb, [&](int b) {
+            if (!(H[b].patch && d < H[b].centry)) return 0L;
+            const long n = H[b].lev[d].n, tx = B->ptile >= 1 ? 16 : 8, ty = B->ptile >= 2 ? 16 : 8;
+            return ((n + tx - 1) / tx) * ((n + ty - 1) / ty) * ((n + 7) / 8) * TPB;
+        });
         make_tab(B->pcellf[d], nb, [&](int b) { return d < H[b].centry ? cells(b, d) : 0L; });
         make_tab(B->pcoarse[d], nb, [&](int b) { return d < H[b].centry ? cells(b, d + 1) : 0L; });
     }
@@ -2403,7 +2532,7 @@ int gr_batch_bind(gr_batch B, void *d_ws, size_t bytes, void *stream)
     }
     for (auto &T : B->coefr) BHIP(up(T));
     BHIP(up(B->pfine));
-    for (auto *v : {&B->pcell, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces, &B->colour32,
+    for (auto *v : {&B->pcell, &B->pfz, &B->pcellf, &B->pcoarse, &B->pcoefr, &B->pfaces, &B->colour32,
                     &B->coarse32, &B->rr32, &B->colour32nf})
         for (auto &T : *v) BHIP(up(T));
     BHIP(hipStreamSynchronize(s)); // host tables must outlive the copies
