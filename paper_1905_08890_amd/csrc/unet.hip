@@ -371,7 +371,15 @@ __global__ void k_pack_input(const float *__restrict__ src, int cin, bf16 *__res
 {
     const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= N) return;
-    for (int c = 0; c < 16; ++c) dst[v * 16 + c] = (bf16)(c < cin ? src[c * N + v] : 0.0f);
+    bf16x8 lo, hi; // the voxel's 16 channels as two 16-byte stores
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        lo[c] = (bf16)(c < cin ? src[c * N + v] : 0.0f);
+        hi[c] = (bf16)(c + 8 < cin ? src[(c + 8) * N + v] : 0.0f);
+    }
+    bf16x8 *d = reinterpret_cast<bf16x8 *>(dst + v * 16);
+    d[0] = lo;
+    d[1] = hi;
 }
 
 // 2x2x2 average of channels [coff, coff + c) -> [m^3][c]
@@ -407,15 +415,19 @@ __global__ void k_pool_bwd_add(const bf16 *__restrict__ gout, int c, bf16 *__res
 }
 
 // nearest upsampling of [m^3][c] into channels [0, c) of out [n^3][cstride]
+// one thread per voxel and group of 8 channels (16-byte loads and stores;
+// c and cstride are multiples of 8)
 __global__ void k_upsample(const bf16 *__restrict__ in, int c, bf16 *__restrict__ out, int cstride, int n)
 {
     const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= (long)n * n * n * c) return;
-    const int ch = (int)(q % c);
-    const long v = q / c;
+    const int cg = c >> 3;
+    if (q >= (long)n * n * n * cg) return;
+    const int ch = (int)(q % cg) * 8;
+    const long v = q / cg;
     const int x = (int)(v % n), y = (int)((v / n) % n), z = (int)(v / ((long)n * n));
     const int m = n / 2;
-    out[v * cstride + ch] = in[(((long)(z / 2) * m + y / 2) * m + x / 2) * c + ch];
+    *reinterpret_cast<bf16x8 *>(out + v * cstride + ch) =
+        *reinterpret_cast<const bf16x8 *>(in + (((long)(z / 2) * m + y / 2) * m + x / 2) * c + ch);
 }
 
 // gradient of the upsampling: sum of the 8 children's channels [0, c)
@@ -453,7 +465,17 @@ __global__ void k_head(const bf16 *__restrict__ h, int c, const float *__restric
     const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= N) return;
     float hv[16];
-    for (int k = 0; k < c; ++k) hv[k] = (float)h[v * c + k];
+    if (c == 16) { // two 16-byte loads
+        const bf16x8 *hp = reinterpret_cast<const bf16x8 *>(h + v * 16);
+        const bf16x8 lo = hp[0], hi = hp[1];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            hv[k] = (float)lo[k];
+            hv[k + 8] = (float)hi[k];
+        }
+    } else {
+        for (int k = 0; k < c; ++k) hv[k] = (float)h[v * c + k];
+    }
     for (int o = 0; o < cout; ++o) {
         float s = b[o];
         for (int k = 0; k < c; ++k) s += w[o * c + k] * hv[k];
@@ -977,7 +999,7 @@ int forward(gr_unet U, int n, const float *d_in)
     for (int k = 2; k >= 0; --k) {
         const int nk = n >> k;
         const Act &src = (k == 2) ? U->eb3 : U->db[k + 1];
-        k_upsample<<<nb((long)nk * nk * nk * src.c), TPB, 0, s>>>(src.p, src.c, U->cat[k].p, c[k + 1] + c[k], nk);
+        k_upsample<<<nb((long)nk * nk * nk * (src.c / 8)), TPB, 0, s>>>(src.p, src.c, U->cat[k].p, c[k + 1] + c[k], nk);
         ULAUNCH();
         const int la = D2A + 2 * (2 - k), lb = D2B + 2 * (2 - k);
         UCHK(conv_fwd(U, la, U->cat[k].p, c[k + 1] + c[k], 0, U->da[k].p, c[k], 0, nk));
