@@ -9,8 +9,9 @@
 //      complex fields z1 = curl_x + i curl_y, z2 = curl_z + i div (two real
 //      transforms for the price of one complex transform each);
 //   2. 3-D FFT of z1 and z2: one pass per axis, each workgroup transforming a
-//      bundle of lines in LDS (radix-2, decimation in time from bit-reversed
-//      loads; y and z bundles take consecutive x so every load is a row);
+//      bundle of lines in LDS (radix-2 butterflies taken two stages at a time,
+//      decimation in time from bit-reversed loads; y and z bundles take
+//      consecutive x so every load is a row);
 //   3. per mode of the cube |m_i| <= nbins: separate the four transforms with
 //      F[a](m) = (Z(m) + conj Z(-m)) / 2, F[b](m) = (Z(m) - conj Z(-m)) / (2i),
 //      form the curl and divergence power and their ratio to |k_eff|^2, and
@@ -100,17 +101,39 @@ __global__ void __launch_bounds__(TPB) k_fft_lines(double2 *__restrict__ data, i
         s[(l << logn) + (int)(__brev((unsigned)j) >> shift)] = data[base + l * lstride + j * jstride];
     }
     __syncthreads();
-    for (int ls = 0; ls < logn; ++ls) {
-        const int hs = 1 << ls, tsh = logn - 1 - ls;
+    // radix-2 stages in pairs (one LDS round trip and barrier per pair): the
+    // same butterflies and twiddles as stage after stage; an odd first stage alone
+    int ls = 0;
+    if (logn & 1) {
         for (int bi = tid; bi < (tot >> 1); bi += TPB) {
             const int l = bi >> (logn - 1), t = bi & (half - 1);
+            const int i0 = (l << logn) + (t << 1), i1 = i0 + 1;
+            const double2 a = s[i0], c = s[i1]; // twiddle 1
+            s[i0] = double2{a.x + c.x, a.y + c.y};
+            s[i1] = double2{a.x - c.x, a.y - c.y};
+        }
+        __syncthreads();
+        ls = 1;
+    }
+    for (; ls < logn; ls += 2) {
+        const int hs = 1 << ls, t1 = logn - 1 - ls, t2 = logn - 2 - ls;
+        for (int gi = tid; gi < (tot >> 2); gi += TPB) {
+            const int l = gi >> (logn - 2), t = gi & ((n >> 2) - 1);
             const int k = t & (hs - 1), grp = t >> ls;
-            const int i0 = (l << logn) + (grp << (ls + 1)) + k, i1 = i0 + hs;
-            const double2 w = stw[k << tsh];
-            const double2 a = s[i0], c = s[i1];
-            const double bx = c.x * w.x - c.y * w.y, by = c.x * w.y + c.y * w.x;
-            s[i0] = double2{a.x + bx, a.y + by};
-            s[i1] = double2{a.x - bx, a.y - by};
+            const int i0 = (l << logn) + (grp << (ls + 2)) + k;
+            const double2 a0 = s[i0], a1 = s[i0 + hs], a2 = s[i0 + 2 * hs], a3 = s[i0 + 3 * hs];
+            const double2 w1 = stw[k << t1];
+            const double b1x = a1.x * w1.x - a1.y * w1.y, b1y = a1.x * w1.y + a1.y * w1.x;
+            const double b3x = a3.x * w1.x - a3.y * w1.y, b3y = a3.x * w1.y + a3.y * w1.x;
+            const double2 c0{a0.x + b1x, a0.y + b1y}, c1{a0.x - b1x, a0.y - b1y};
+            const double2 c2{a2.x + b3x, a2.y + b3y}, c3{a2.x - b3x, a2.y - b3y};
+            const double2 w2 = stw[k << t2], w3 = stw[(k + hs) << t2];
+            const double d2x = c2.x * w2.x - c2.y * w2.y, d2y = c2.x * w2.y + c2.y * w2.x;
+            const double d3x = c3.x * w3.x - c3.y * w3.y, d3y = c3.x * w3.y + c3.y * w3.x;
+            s[i0] = double2{c0.x + d2x, c0.y + d2y};
+            s[i0 + 2 * hs] = double2{c0.x - d2x, c0.y - d2y};
+            s[i0 + hs] = double2{c1.x + d3x, c1.y + d3y};
+            s[i0 + 3 * hs] = double2{c1.x - d3x, c1.y - d3y};
         }
         __syncthreads();
     }

@@ -75,7 +75,9 @@ def test_plane_wave_and_pure_modes():
     keff = n * np.sin(2 * np.pi * m0 / n)
     assert np.isclose(got[2, 2] * got[1, 2], A * A * keff * keff / 2, rtol=1e-12)
     assert np.isclose(got[4, 2] * got[1, 2], A * A / 2, rtol=1e-12)
-    assert np.all(got[3] == 0.0)
+    # the divergence is zero in every cell, but it shares a complex transform with
+    # curl_z, so its separated transform carries that transform's rounding (~eps)
+    assert np.all(got[3] <= 1e-28 * got[2].max())
     # a gradient has no vector mode, a curl no scalar mode (to rounding)
     phi = _fields(n, 7)[0]
     g = [OS._d(phi, ax) for ax in (2, 1, 0)]
