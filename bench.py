@@ -495,6 +495,47 @@ def bench_batch(torch, grmg, synth, steps):
     return out
 
 
+def substep_only(torch, grmg, synth, steps):
+    """The batched workload's 32 patches solved again from the kept fields of
+    their boxes (gr_batch_solve_patches), after one full solve; ends with a
+    plain copy of 256^3 doubles (the counters' calibration)."""
+    items = [synth.batch_item(100 + b) for b in range(96)]
+    sides = [n for n, _ in items]
+    pitems = [synth.patch_item(j, sides) for j in range(32)]
+    B = grmg.Batch(sides, a=1.0, omega_m=synth.OMEGA_M, c_tilde=synth.C_TILDE, device="cuda:0",
+                   patches=[d for d, _ in pitems])
+    for i, src in enumerate([src for _, src in items] + [src for _, src in pitems]):
+        for name, x in zip(("s0", "sx", "sy", "sz", "sm"), src):
+            B.set_field(i, name, x)
+    B.autotune()
+    B.solve(rtol=1e-10)
+    times = []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = B.solve(rtol=1e-10, patches_only=True)
+        times.append(time.perf_counter() - t0)
+    B.close()
+    g = grmg.Grid(256, a=1.0, omega_m=synth.OMEGA_M, c_tilde=synth.C_TILDE, device="cuda:0")
+    copy_probe(torch, grmg, g, 256, reps=1)
+    g.close()
+    print(json.dumps({"substep_s": round(min(times), 4), "status": rep["status"]}), flush=True)
+
+
+def spectra_only(torch, grmg, synth, n):
+    """The vector-mode extraction of the bench workload's solved shift and
+    momentum density (one mixed solve first), then a plain copy of n^3
+    doubles (the counters' calibration)."""
+    pos, u, mass = synth.zeldovich(n, 2, 1.0)
+    g = grmg.Grid(n, a=1.0, omega_m=synth.OMEGA_M, c_tilde=synth.C_TILDE, device="cuda:0")
+    g.deposit_sources(pos, u, mass)
+    g.solve_constraints(rtol=1e-10, precision="mixed")
+    res = vector_modes(torch, grmg, g, n, reps=2)
+    copy_probe(torch, grmg, g, n, reps=1)
+    g.close()
+    print(json.dumps({"vector_modes": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -514,6 +555,12 @@ def main():
                          "channels): --steps forward passes and loss-gradient passes (for MFMA counters)")
     ap.add_argument("--smoother-only", action="store_true",
                     help="only the finest-level sweeps and a copy of known size (for hardware counters)")
+    ap.add_argument("--substep-only", action="store_true",
+                    help="only the refined levels: the 32 patches of the batched workload solved again from their "
+                         "boxes' kept fields, --steps times, then a copy of known size (for traces and counters)")
+    ap.add_argument("--spectra-only", action="store_true",
+                    help="only the vector-mode extraction of the solved 256^3 step's shift and momentum density, "
+                         "then a copy of known size (for traces and counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU: the library has no multi-GPU path (asked for {args.gpus})",
@@ -533,6 +580,12 @@ def main():
         return
     if args.batch_only:
         print(json.dumps(bench_batch(torch, grmg, synth, max(1, args.steps))), flush=True)
+        return
+    if args.substep_only:
+        substep_only(torch, grmg, synth, max(1, args.steps))
+        return
+    if args.spectra_only:
+        spectra_only(torch, grmg, synth, n)
         return
     seed, rms = (2, 1.0) if n == 256 else (1, 0.3)
     log(f"generating Zel'dovich particles n={n} seed={seed} rms={rms}")
