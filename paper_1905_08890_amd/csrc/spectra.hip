@@ -70,6 +70,47 @@ __global__ void __launch_bounds__(TPB) k_curl_div(const double *__restrict__ vx,
     z2[p] = double2{dxvy - dyvx, dxvx + dyvy + dzvz};
 }
 
+// The same for n >= 64 by z-marching columns: a workgroup takes a 64 x 4
+// tile of (x, y) columns over kCdz planes, each thread keeping its column's
+// values at z - 1, z and z + 1 in registers (x and y neighbours are the
+// adjacent columns' loads, cache hits when the neighbouring tile ran on the
+// same XCD); identical arithmetic per cell.
+constexpr int kCdx = 64, kCdy = 4, kCdz = 16;
+__global__ void __launch_bounds__(TPB) k_curl_div_march(const double *__restrict__ vx, const double *__restrict__ vy,
+                                                        const double *__restrict__ vz, int n,
+                                                        double2 *__restrict__ z1, double2 *__restrict__ z2)
+{
+    const int ntx = n / kCdx, nty = n / kCdy;
+    // XCD-contiguous order (the grid is a multiple of 8): each XCD takes one run
+    // of consecutive tiles, so the y-neighbour rows of a tile sit in its L2
+    const int G = gridDim.x, v = (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
+    const int bx = v % ntx, by = (v / ntx) % nty, bz = v / (ntx * nty);
+    const int x = bx * kCdx + (threadIdx.x & (kCdx - 1)), y = by * kCdy + (threadIdx.x >> 6), z0 = bz * kCdz;
+    const int xp = wrapi(x + 1, n), xm = wrapi(x - 1, n), yp = wrapi(y + 1, n), ym = wrapi(y - 1, n);
+    const double f = 0.5 * n;
+    auto at = [&](int xx, int yy, int zz) { return ((long)zz * n + yy) * n + xx; };
+    const long pm = at(x, y, wrapi(z0 - 1, n)), pc = at(x, y, z0);
+    double px = vx[pm], py = vy[pm], pz = vz[pm];
+    double cx = vx[pc], cy = vy[pc], cz = vz[pc];
+    for (int z = z0; z < z0 + kCdz; ++z) {
+        const long p = at(x, y, z), pn = at(x, y, wrapi(z + 1, n));
+        const double nx = vx[pn], ny = vy[pn], nz = vz[pn];
+        const long xP = p - x + xp, xM = p - x + xm, yP = p + (long)(yp - y) * n, yM = p + (long)(ym - y) * n;
+        const double dyvz = (vz[yP] - vz[yM]) * f, dzvy = (ny - py) * f;
+        const double dzvx = (nx - px) * f, dxvz = (vz[xP] - vz[xM]) * f;
+        const double dxvy = (vy[xP] - vy[xM]) * f, dyvx = (vx[yP] - vx[yM]) * f;
+        const double dxvx = (vx[xP] - vx[xM]) * f, dyvy = (vy[yP] - vy[yM]) * f, dzvz = (nz - pz) * f;
+        z1[p] = double2{dyvz - dzvy, dzvx - dxvz};
+        z2[p] = double2{dxvy - dyvx, dxvx + dyvy + dzvz};
+        px = cx;
+        py = cy;
+        pz = cz;
+        cx = nx;
+        cy = ny;
+        cz = nz;
+    }
+}
+
 // In-place forward transform of every line along AXIS (0 = x, 1 = y, 2 = z)
 // of an n^3 complex array; a workgroup takes lb lines (lb * n <= kFftLds).
 template <int AXIS>
@@ -350,7 +391,11 @@ int gr_vector_spectra(gr_spectra S, const double *d_vx, const double *d_vy, cons
     double2 *z2 = reinterpret_cast<double2 *>(S->ws + S->off_z2);
     double *part = reinterpret_cast<double *>(S->ws + S->off_part);
     double *out = reinterpret_cast<double *>(S->ws + S->off_out);
-    k_curl_div<<<(unsigned)((N + TPB - 1) / TPB), TPB, 0, S->stream>>>(d_vx, d_vy, d_vz, n, z1, z2);
+    if (n >= kCdx)
+        k_curl_div_march<<<(unsigned)((n / kCdx) * (n / kCdy) * (n / kCdz)), TPB, 0, S->stream>>>(d_vx, d_vy, d_vz, n,
+                                                                                                 z1, z2);
+    else
+        k_curl_div<<<(unsigned)((N + TPB - 1) / TPB), TPB, 0, S->stream>>>(d_vx, d_vy, d_vz, n, z1, z2);
     SLAUNCH();
     int rc = fft3(S, z1);
     if (rc != GR_OK) return rc;
