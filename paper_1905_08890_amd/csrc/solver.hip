@@ -95,6 +95,8 @@ struct gr_grid_s {
     bool tuned_split[kMaxLevels][6]{}; // the tuner found one launch per colour faster
     int coarse_n = 8;      // levels with n <= coarse_n run in one single-workgroup launch
     int coarse_n32 = 8;    // the same for the FP32 correction cycles
+    int coarse_np = 16;    // the same threshold for the Poisson kind (FP64 and correction cycles): its point
+                           // update is cheap enough for one CU to take a 16^3 level faster than ~11 launches
     int skew = 0;          // workspace array skew in bytes (see layout)
     double stall_ratio = 0.5; // mixed precision: a refinement step that keeps more than this
                               // fraction of the residual counts as stalled (two in a row: FP64)
@@ -416,7 +418,7 @@ int vcycle_body(gr_grid g, const EqCtx &E, int l)
 {
     Level &L = g->lev[l];
     hipStream_t s = g->stream;
-    if (L.n <= g->coarse_n) {
+    if (L.n <= (E.kind == GR_KIND_POISSON ? g->coarse_np : g->coarse_n)) {
         CoarseLevelsT<double> C;
         C.nl = g->nlev - l;
         for (int i = 0; i < C.nl; ++i) {
@@ -590,7 +592,7 @@ int vcycle32_body(gr_grid g, int lkind, int l, int nu1, int nu2, OpConst oc, boo
     Level &L = g->lev[l];
     Level32 &V = g->lev32[l];
     hipStream_t s = g->stream;
-    if (L.n <= g->coarse_n32 || l == g->nlev - 1) {
+    if (L.n <= (lkind == K_LIN_POISSON ? g->coarse_np : g->coarse_n32) || l == g->nlev - 1) {
         if (e_unset) launch_fill_f32(s, V.e, L.N);
         CoarseLevelsT<float> C;
         C.nl = g->nlev - l;
@@ -911,7 +913,8 @@ int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out)
     // GRMG_FUSED_WGS (target workgroups per fused launch), GRMG_FUSED_PF (prefetch
     // depth 1 to 4 planes), GRMG_COARSE_N (levels
     // at or below this size run the rest of the V-cycle in one workgroup; 0: never;
-    // GRMG_COARSE_N32 likewise for the FP32 correction cycles),
+    // GRMG_COARSE_N32 likewise for the FP32 correction cycles; GRMG_COARSE_NP the
+    // same for the Poisson kind in both, 16 by default),
     // GRMG_MIXED_STALL (mixed-precision stagnation ratio), GRMG_GRAPH (0: launch
     // every cycle's kernels one by one instead of replaying a captured graph)
     if (const char *e = std::getenv("GRMG_SMOOTHER")) {
@@ -925,6 +928,7 @@ int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out)
     if (const char *e = std::getenv("GRMG_FUSED_PF")) g->fcfg.pf = std::min(4, std::max(0, std::atoi(e)));
     if (const char *e = std::getenv("GRMG_COARSE_N")) g->coarse_n = std::atoi(e);
     if (const char *e = std::getenv("GRMG_COARSE_N32")) g->coarse_n32 = std::atoi(e);
+    if (const char *e = std::getenv("GRMG_COARSE_NP")) g->coarse_np = std::atoi(e);
     if (const char *e = std::getenv("GRMG_MIXED_STALL")) g->stall_ratio = std::atof(e);
     if (const char *e = std::getenv("GRMG_GRAPH")) g->use_graph = std::atoi(e) != 0;
     if (const char *e = std::getenv("GRMG_SKEW")) g->skew = std::max(0, std::atoi(e));
@@ -961,6 +965,7 @@ int gr_create_grid(const gr_grid_desc *desc, const gr_params *prm, gr_grid *out)
             h->fcfg = g->fcfg;
             h->coarse_n = g->coarse_n;
             h->coarse_n32 = g->coarse_n32;
+            h->coarse_np = g->coarse_np;
             h->stall_ratio = g->stall_ratio;
             h->use_graph = g->use_graph;
             h->skew = g->skew;
@@ -1246,6 +1251,7 @@ int gr_solve_equation_static(int n, const gr_params *prm, int kind, const double
     std::memset(g->tuned_split, 0, sizeof g->tuned_split);
     g->coarse_n = 8;
     g->coarse_n32 = 8;
+    g->coarse_np = 16;
     g->skew = 0;
     g->stall_ratio = 0.5;
     g->use_graph = false;

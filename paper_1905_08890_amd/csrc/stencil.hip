@@ -451,21 +451,50 @@ __global__ void __launch_bounds__(TPB) k_res_norms(const double *__restrict__ ph
 
 // out[c] = (add ? add[c] : 0) + scale * sum of partials of component c, in a
 // fixed order (one block; thread t sums blocks t, t+256, ... then a tree).
+// Fixed-order sum of the block partials of up to two quantities: every thread
+// adds its 16 strided slots in slot order, then a tree over the threads (pairs
+// t, t + w for w = 128, 64, ..., 1).  All loads are issued before the first
+// add (the partials were just written by other XCDs and come from memory, so a
+// load-add chain would pay that latency 16 times); the last six tree levels run
+// in the first wavefront by lane shuffles, which pair the same values.
+constexpr int kFinalizeSlots = kReduceBlocks / TPB;
+
 __global__ void __launch_bounds__(TPB) k_finalize(const double *__restrict__ partials, int ncomp, double scale,
                                                   const double *__restrict__ add, double *__restrict__ out)
 {
-    __shared__ double sh[TPB];
-    for (int c = 0; c < ncomp; ++c) {
+    __shared__ double sh[2][TPB];
+    double v[2][kFinalizeSlots];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int j = 0; j < kFinalizeSlots; ++j)
+            v[c][j] = c < ncomp ? partials[c * kReduceBlocks + j * TPB + threadIdx.x] : 0.0;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < kReduceBlocks; b += TPB) s += partials[c * kReduceBlocks + b];
-        sh[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = TPB / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-            __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kFinalizeSlots; ++j) s += v[c][j];
+        sh[c][t] = s;
+    }
+    __syncthreads();
+    for (int w = TPB / 2; w >= 64; w >>= 1) {
+        if (t < w) {
+            sh[0][t] += sh[0][t + w];
+            sh[1][t] += sh[1][t + w];
         }
-        if (threadIdx.x == 0) out[c] = (add ? add[c] : 0.0) + scale * sh[0];
         __syncthreads();
+    }
+    if (t < 64) {
+        double s0 = sh[0][t], s1 = sh[1][t];
+        for (int w = 32; w > 0; w >>= 1) {
+            s0 += __shfl_down(s0, w, 64);
+            s1 += __shfl_down(s1, w, 64);
+        }
+        if (t == 0) {
+            out[0] = (add ? add[0] : 0.0) + scale * s0;
+            if (ncomp > 1) out[1] = (add ? add[1] : 0.0) + scale * s1;
+        }
     }
 }
 
@@ -1453,6 +1482,7 @@ void launch_res_norms(int kind, hipStream_t s, const double *phi, const double *
 
 void launch_finalize(hipStream_t s, const double *partials, int ncomp, double scale, const double *add, double *out)
 {
+    static_assert(kReduceBlocks % TPB == 0, "partial slots per thread");
     k_finalize<<<1, TPB, 0, s>>>(partials, ncomp, scale, add, out);
 }
 
