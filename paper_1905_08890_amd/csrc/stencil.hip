@@ -231,6 +231,12 @@ __global__ void __launch_bounds__(TPB) k_prolong_correct(T *__restrict__ phi_f, 
     load_plane(e[0], z0 - 1);
     load_plane(e[1], z0);
     for (int z = z0; z < z0 + zc; ++z) {
+        // the four fine x-pairs of this coarse cell are read before the next
+        // coarse plane, so all thirteen (FAS: twenty-two) loads are in flight at once
+        T2 old[2][2];
+        for (int cz = 0; cz < 2; ++cz)
+            for (int cy = 0; cy < 2; ++cy)
+                old[cz][cy] = *reinterpret_cast<const T2 *>(phi_f + lin(2 * x, 2 * y + cy, 2 * z + cz, n));
         load_plane(e[2], z + 1);
         for (int cz = 0; cz < 2; ++cz)
             for (int cy = 0; cy < 2; ++cy) {
@@ -245,11 +251,10 @@ __global__ void __launch_bounds__(TPB) k_prolong_correct(T *__restrict__ phi_f, 
                     }
                     v[cx] = a;
                 }
-                T2 *dst = reinterpret_cast<T2 *>(phi_f + lin(2 * x, 2 * y + cy, 2 * z + cz, n));
-                T2 old = *dst;
-                old.x += v[0];
-                old.y += v[1];
-                *dst = old;
+                T2 r = old[cz][cy];
+                r.x += v[0];
+                r.y += v[1];
+                *reinterpret_cast<T2 *>(phi_f + lin(2 * x, 2 * y + cy, 2 * z + cz, n)) = r;
             }
         for (int dy = 0; dy < 3; ++dy)
             for (int dx = 0; dx < 3; ++dx) {
@@ -532,7 +537,7 @@ __global__ void __launch_bounds__(MNT) k_march(const T *__restrict__ phi, const 
 // with n a multiple of 64.
 template <int MODE, int KIND, typename T>
 __global__ void __launch_bounds__(M2NT) k_march2(const T *__restrict__ phi, const T *__restrict__ f,
-                                                 const T *__restrict__ c1, const T *__restrict__ c2, int n, int zc,
+                                                 const T *__restrict__ c1, const T *__restrict__ c2, int n, int zc_arg,
                                                  T inv_h2, OpConst oc, const double *__restrict__ fbar,
                                                  const double *__restrict__ fshift, double *__restrict__ partials,
                                                  T *__restrict__ o1, T *__restrict__ o2, T *__restrict__ o3,
@@ -540,8 +545,18 @@ __global__ void __launch_bounds__(M2NT) k_march2(const T *__restrict__ phi, cons
                                                  float *__restrict__ c32, const float *__restrict__ e32)
 {
     const int tiles_y = n / M2TY;
+    const int zc = zc_arg & 0xffff;
     const int nzc = n / zc;
-    const int tile = blockIdx.x / nzc, zchunk = blockIdx.x % nzc;
+    int tile, zchunk;
+    if (zc_arg >> 16) { // z-chunk major in contiguous runs per XCD: tile neighbours in x, y and z share an L2
+        const int G = gridDim.x, ntiles = G / nzc;
+        const int v = (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
+        zchunk = v / ntiles;
+        tile = v - zchunk * ntiles;
+    } else {
+        tile = blockIdx.x / nzc;
+        zchunk = blockIdx.x % nzc;
+    }
     const T Fb = (MODE == M_RESTRICT_LIN) ? T(0) : T(*fbar);
     const T fs = (MODE == M_RESTRICT_LIN) ? T(0) : T(*fshift);
     double v[2] = {0.0, 0.0};
@@ -1119,14 +1134,22 @@ bool march2_ok(int n)
     return on && march_ok(n) && n % M2TX == 0;
 }
 
+// Grid of the x-pair passes; *zc_out carries the z-chunk length in its low 16
+// bits and the block order in bit 16 (z-chunk major in contiguous runs per XCD,
+// taken when the grid is a multiple of 8; GRMG_MARCH2_ORDER=0: tile major).
 int march2_grid(int n, long max_blocks, int *zc_out)
 {
+    static const int order = [] {
+        const char *e = std::getenv("GRMG_MARCH2_ORDER");
+        return e ? std::atoi(e) : 1;
+    }();
     const long tiles = (long)(n / M2TX) * (n / M2TY);
     if (tiles > max_blocks) return 0;
     int zc = n;
     while (zc % 4 == 0 && zc / 2 >= 8 && tiles * (n / (zc / 2)) <= max_blocks) zc /= 2;
-    *zc_out = zc;
-    return (int)(tiles * (n / zc));
+    const long grid = tiles * (n / zc);
+    *zc_out = zc | ((order == 1 && grid % 8 == 0) ? (1 << 16) : 0);
+    return (int)grid;
 }
 
 int march_grid(int n, long max_blocks, int *zc_out)
