@@ -1545,7 +1545,7 @@ int gr_autotune(gr_grid g, char *report, size_t report_bytes)
     for (int l = 0; l < g->nlev && st == GR_OK; ++l) {
         const Level &L = g->lev[l];
         // every level the fused sweep can tile (the size threshold is for untuned grids)
-        if (!g->fused || !fused_sweep_ok(L.n, 64)) continue;
+        if (!g->fused || !fused_sweep_ok(L.n, 32)) continue;
         const long M = L.N;
         double *d = static_cast<double *>(g->cic); // scratch: 8 n^3 doubles
         float *fl = static_cast<float *>(g->cic);
@@ -1565,6 +1565,7 @@ int gr_autotune(gr_grid g, char *report, size_t report_bytes)
             if (best_us < 0.f) {
                 for (int tile = 0; tile < (L.n % 128 == 0 ? 4 : 3); ++tile)
                     for (int wgs : {256, 512, 1024, 2048})
+                        if (L.n % 64 == 0 || tile == 1) // 32 x 16 only where 64-wide tiles do not fit
                         for (int pf = 1; pf <= (tile == 2 ? 4 : 2); ++pf) {
                             FusedCfg c = g->fcfg;
                             c.tile = tile;

@@ -1006,7 +1006,8 @@ void launch_rb_sweep_f32(int kind, hipStream_t s, float *e, const float *b, cons
     launch_rb_sweep_t<float>(kind, s, e, b, c1, c2, n, h, oc, zero, zero);
 }
 
-bool fused_sweep_ok(int n, int min_n) { return n >= min_n && n >= 64 && n % 64 == 0; }
+// 64-wide tiles need n % 64 == 0; levels of n % 64 == 32 (e.g. 32^3) take the 32 x 16 tile
+bool fused_sweep_ok(int n, int min_n) { return n >= min_n && n >= 32 && n % 32 == 0; }
 
 template <int KIND, typename T, int TX, int TY>
 static void launch_fused_k(int pf, unsigned grid, hipStream_t s, const T *in, T *out, const T *f, const T *c1,
@@ -1040,10 +1041,15 @@ static void launch_fused_t(int kind, hipStream_t s, const T *in, T *out, const T
 {
     const int tiles_x = n / TX, tiles_y = n / TY;
     const int tiles = tiles_x * tiles_y;
-    // z chunk: halve (keeping >= 8 planes and a divisor of n) until the grid
-    // reaches the target number of workgroups (one resident wave)
+    // z chunk: halve (keeping >= 8 planes, GRMG_FUSED_ZMIN, and a divisor of n)
+    // until the grid reaches the target number of workgroups (one resident wave);
+    // shorter chunks on the small levels (2 planes) measured no faster in the solve
+    static const int zmin = [] {
+        const char *e = std::getenv("GRMG_FUSED_ZMIN");
+        return e ? std::max(1, std::atoi(e)) : 8;
+    }();
     int zc = n;
-    while (zc % 2 == 0 && zc / 2 >= 8 && (long)tiles * (n / zc) < cfg.target_wgs) zc /= 2;
+    while (zc % 2 == 0 && zc / 2 >= zmin && (long)tiles * (n / zc) < cfg.target_wgs) zc /= 2;
     const unsigned grid = (unsigned)(tiles * (n / zc));
     const T inv_h2 = T(1.0 / (h * h));
 #define GR_FUSED_CASE(K)                                                                                      \
@@ -1069,7 +1075,7 @@ template <typename T>
 static void launch_fused_any(int kind, hipStream_t s, const T *in, T *out, const T *f, const T *c1, const T *c2,
                              int n, double h, OpConst oc, const double *fbar, const double *fshift, const FusedCfg &cfg)
 {
-    if (cfg.tile == 1)
+    if (cfg.tile == 1 || n % 64 != 0)
         launch_fused_t<T, 32, 16>(kind, s, in, out, f, c1, c2, n, h, oc, fbar, fshift, cfg);
     else if (cfg.tile == 3 && n % 128 == 0) // 1 KB contiguous rows; other sizes take 64x16
         launch_fused_t<T, 128, 8>(kind, s, in, out, f, c1, c2, n, h, oc, fbar, fshift, cfg);

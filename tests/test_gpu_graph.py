@@ -78,7 +78,7 @@ def test_autotuned_launch_shapes_give_the_same_solve(precision):
     _same_sources(b, a)
     report = grmg.autotune(b.handle)
     lines = [ln for ln in report.splitlines() if ln.startswith("n=")]
-    assert len(lines) == 12 and all("us=" in ln for ln in lines)   # levels 128^3 and 64^3, six kinds each
+    assert len(lines) == 18 and all("us=" in ln for ln in lines)   # levels 128^3, 64^3 and 32^3, six kinds each
     _same_sources(b, a)   # the tuner may use the deposit scratch, never the sources
     ra = a.solve_constraints(rtol=1e-10, precision=precision)
     rb = b.solve_constraints(rtol=1e-10, precision=precision)
