@@ -3,7 +3,12 @@
 Compiles every ``csrc/*.hip`` translation unit with hipcc for gfx950 and
 links them into ``paper_1905_08890_amd/libgrmg.so``.  Packed FP32 ALU
 operations are disabled (``-packed-fp32-ops``); FP64 atomics in the CIC
-deposit use the hardware instructions (``-munsafe-fp-atomics``).
+deposit use the hardware instructions (``-munsafe-fp-atomics``).  A multiply
+and an add are contracted into an FMA only within one source expression
+(``-ffp-contract=on``, not the default ``fast``, which also contracts across
+statements after inlining and so decides differently in different kernels):
+the launch forms of a smoother (fused tile, one launch per colour, batched)
+then round the same operations and give the same bits.
 """
 from __future__ import annotations
 
@@ -19,7 +24,7 @@ LIB = os.path.join(PKG, "libgrmg.so")
 INCLUDE = os.path.join(ROOT, "include")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
+FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-munsafe-fp-atomics", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
 

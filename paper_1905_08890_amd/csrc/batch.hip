@@ -983,10 +983,11 @@ __global__ void __launch_bounds__(TPB) kb32_colour(BatchDev D, const int *__rest
     const int i = 2 * x2 + ((y + z + colour) & 1);
     const long p = lin(i, y, z, n);
     const float ph = L.e[p];
+    const float ih2 = (float)(1.0 / (L.h * L.h));
     float J;
-    const float Lv = op_point<LKIND, float>(ph, nb_sum(L.e, i, y, z, n), (float)(1.0 / (L.h * L.h)),
-                                            load_c1<LKIND>(L.c32, p), load_c2<LKIND>(L.a32, p), oc, 0.f, J);
-    L.e[p] = ph - (Lv - L.b32[p]) / J;
+    const float Lv = op_point<LKIND, float>(ph, nb_sum(L.e, i, y, z, n), ih2, load_c1<LKIND>(L.c32, p),
+                                            load_c2<LKIND>(L.a32, p), oc, 0.f, J);
+    L.e[p] = newton_update<LKIND, float>(ph, Lv, L.b32[p], J, poisson_inv_diag(ih2));
 }
 
 // fused red-black sweeps of the correction equation (rb_fused_tile in FP32)

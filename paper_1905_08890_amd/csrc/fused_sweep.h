@@ -51,6 +51,7 @@ __device__ __forceinline__ void rb_fused_tile(const T *__restrict__ in, T *__res
 
     const int tid = threadIdx.x;
     const int plane = n * n;
+    const T rJ = poisson_inv_diag(inv_h2);
 
     // this thread's phi loads of a plane (tile + 2-halo)
     int goff[NLOAD];
@@ -153,7 +154,7 @@ __device__ __forceinline__ void rb_fused_tile(const T *__restrict__ in, T *__res
                 const T nbs = mid[c - 1] + mid[c + 1] + mid[c - W] + mid[c + W] + lo[c] + hi[c];
                 T J;
                 const T L = op_point<KIND, T>(ph, nbs, inv_h2, o ? R.c.y : R.c.x, o ? R.a.y : R.a.x, oc, Fb, J);
-                mid[c] = ph - (L - ((o ? R.f.y : R.f.x) - fs)) / J;
+                mid[c] = newton_update<KIND, T>(ph, L, (o ? R.f.y : R.f.x) - fs, J, rJ);
             }
             if (tid < HALO) {
                 int hy, hx;
@@ -163,7 +164,7 @@ __device__ __forceinline__ void rb_fused_tile(const T *__restrict__ in, T *__res
                 const T nbs = mid[c - 1] + mid[c + 1] + mid[c - W] + mid[c + W] + lo[c] + hi[c];
                 T J;
                 const T L = op_point<KIND, T>(ph, nbs, inv_h2, R.hc, R.ha, oc, Fb, J);
-                mid[c] = ph - (L - (R.hf - fs)) / J;
+                mid[c] = newton_update<KIND, T>(ph, L, R.hf - fs, J, rJ);
             }
         }
         // plane zz - 1 had its red pass now; its black half is used at it + 1
@@ -182,7 +183,7 @@ __device__ __forceinline__ void rb_fused_tile(const T *__restrict__ in, T *__res
             const T nbs = mid[c - 1] + mid[c + 1] + mid[c - W] + mid[c + W] + lo[c] + hi[c];
             T J;
             const T L = op_point<KIND, T>(ph, nbs, inv_h2, cbk, abk, oc, Fb, J);
-            const T nb = ph - (L - (fbk - fs)) / J;
+            const T nb = newton_update<KIND, T>(ph, L, fbk - fs, J, rJ);
             const T red = mid[ly * W + lxe + (1 - o)];
             T2 v;
             v.x = o ? red : nb;

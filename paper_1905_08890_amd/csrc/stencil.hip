@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(TPB) k_rb_colour(T *__restrict__ phi, const T 
     T J;
     const T L = op_point<KIND, T>(ph, nb_sum(phi, i, y, z, n), inv_h2, load_c1<KIND>(c1, p), load_c2<KIND>(c2, p),
                                   oc, T(*fbar), J);
-    phi[p] = ph - (L - (f[p] - T(*fshift))) / J;
+    phi[p] = newton_update<KIND, T>(ph, L, f[p] - T(*fshift), J, poisson_inv_diag(inv_h2));
 }
 
 // One workgroup per tile x z-chunk of the single grid (see rb_fused_tile).

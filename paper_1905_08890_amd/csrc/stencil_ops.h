@@ -64,6 +64,21 @@ __device__ __forceinline__ T op_point(T ph, T nbs, T inv_h2, T c1, T c2, OpConst
     }
 }
 
+// The point update ph - (L - fe) / J of every smoother.  The FP32 correction
+// equation of the Poisson kind has the constant diagonal J = -6/h^2: there the
+// update multiplies by its reciprocal rJ (formed once per kernel from inv_h2),
+// within an ulp of the division, which the FP32 correction does not need.
+template <typename T> __device__ __forceinline__ T poisson_inv_diag(T inv_h2) { return T(1) / (T(-6) * inv_h2); }
+
+template <int KIND, typename T>
+__device__ __forceinline__ T newton_update(T ph, T L, T fe, T J, T rJ)
+{
+    if constexpr (KIND == K_LIN_POISSON && sizeof(T) == 4)
+        return ph - (L - fe) * rJ;
+    else
+        return ph - (L - fe) / J;
+}
+
 template <int KIND, typename T>
 __device__ __forceinline__ T load_c1(const T *__restrict__ c1, long p)
 {
