@@ -103,6 +103,20 @@ void launch_ir_residual(int kind, hipStream_t s, const double *phi, const double
 void launch_neg_to_f32(hipStream_t s, float *dst, const double *src, long N);
 void launch_sum_f32(hipStream_t s, const float *x, long N, double *partials);
 void launch_ir_update(hipStream_t s, double *phi, const float *e, long N, const double *mean);
+// phi += e - <e>, fused with the next pass's sum over phi: of F (Hamiltonian;
+// coef = AA) or of coef * phi (CMC; coef = m2), partial sums as launch_sum_ham_F /
+// launch_sum_prod
+void launch_ir_update_sum(int kind, hipStream_t s, double *phi, const float *e, const double *mean, const double *f,
+                          const double *coef, long N, OpConst oc, double *partials);
+// the FP32 linearisation arrays a and c restricted one level (n: fine side)
+void launch_restrict2_f32(hipStream_t s, const float *fa, const float *fc, int n, float *ca, float *cc);
+// the same through levels 0..nl (sides n[0], n[0]/2, ...) in one workgroup
+struct RestrictChain {
+    int nl; // restrictions done: level l -> l + 1 for l < nl
+    int n[kMaxLevels];
+    float *a[kMaxLevels], *c[kMaxLevels];
+};
+void launch_restrict2_chain(hipStream_t s, const RestrictChain &R);
 void launch_fill_f32(hipStream_t s, float *x, long N);
 void launch_copy_f32(hipStream_t s, float *dst, const float *src, long N);
 

@@ -655,13 +655,14 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
     // array (the iterate is copied back to the field at the end)
     const bool fuse_update = kind == GR_KIND_POISSON;
     double *cur = phi, *other = F.tmp;
-    // frozen means, FP64 residual (as FP32 right-hand side) and the stopping norms
-    auto measure = [&]() -> int {
+    // frozen means (their sums already in the partials when `summed`), FP64
+    // residual (as FP32 right-hand side) and the stopping norms
+    auto measure = [&](bool summed = false) -> int {
         if (kind == GR_KIND_HAMILTONIAN) {
-            launch_sum_ham_F(s, phi, F.f, F.coef, N, oc, g->partials);
+            if (!summed) launch_sum_ham_F(s, phi, F.f, F.coef, N, oc, g->partials);
             launch_finalize(s, g->partials, 1, 1.0 / (double)N, nullptr, g->scal + S_FBAR);
         } else if (kind == GR_KIND_CMC) {
-            launch_sum_prod(s, F.coef, phi, N, g->partials);
+            if (!summed) launch_sum_prod(s, F.coef, phi, N, g->partials);
             launch_finalize(s, g->partials, 1, 1.0 / (double)N, g->scal + S_FMEAN, g->scal + S_FSHIFT);
         }
         launch_ir_residual(kind, s, cur, F.f, F.coef, F.n, F.h, oc, g->scal + S_FBAR, g->scal + S_FSHIFT, F32.b, F32.a,
@@ -672,11 +673,22 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
     };
     // one FP32 correction cycle and the FP64 update, then the next measurement
     auto step = [&]() -> int {
-        if (kind == GR_KIND_HAMILTONIAN)
-            for (int l = 1; l < g->nlev; ++l) {
-                launch_restrict_f32(s, g->lev32[l - 1].a, g->lev[l - 1].n, g->lev32[l].a);
-                launch_restrict_f32(s, g->lev32[l - 1].c, g->lev[l - 1].n, g->lev32[l].c);
+        if (kind == GR_KIND_HAMILTONIAN) { // a and c on every level: one launch per level above 32^3, then one
+            int l = 1;
+            for (; l < g->nlev && g->lev[l - 1].n > 32; ++l)
+                launch_restrict2_f32(s, g->lev32[l - 1].a, g->lev32[l - 1].c, g->lev[l - 1].n, g->lev32[l].a,
+                                     g->lev32[l].c);
+            if (l < g->nlev) {
+                RestrictChain R{};
+                R.nl = g->nlev - l;
+                for (int i = 0; i <= R.nl; ++i) {
+                    R.n[i] = g->lev[l - 1 + i].n;
+                    R.a[i] = g->lev32[l - 1 + i].a;
+                    R.c[i] = g->lev32[l - 1 + i].c;
+                }
+                launch_restrict2_chain(s, R);
             }
+        }
         CHK(vcycle32(g, lkind, 0, o.nu1, o.nu2, oc, true));
         if (fuse_update) { // shift-invariant: one pin at the end (as in the FP64 cycle)
             launch_ir_update_residual(s, cur, F32.e, other, F.f, F.n, F.h, oc, g->scal + S_FBAR, g->scal + S_FSHIFT,
@@ -684,13 +696,13 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
             launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN);
             LAUNCHCHK();
             return GR_OK;
-        } else {
+        } else { // the update fused with the next frozen-mean sum
             launch_sum_f32(s, F32.e, N, g->partials);
             launch_finalize(s, g->partials, 1, 1.0 / (double)N, nullptr, g->scal + S_MEAN);
-            launch_ir_update(s, phi, F32.e, N, g->scal + S_MEAN);
+            launch_ir_update_sum(kind, s, phi, F32.e, g->scal + S_MEAN, F.f, F.coef, N, oc, g->partials);
         }
         LAUNCHCHK();
-        return measure();
+        return measure(true);
     };
 
     CHK(measure());

@@ -425,6 +425,84 @@ __global__ void __launch_bounds__(TPB) k_sum_ham_F(const double *__restrict__ ps
     zero_unused_partials<1>(partials);
 }
 
+// The FP64 update of a refinement step, phi <- phi + e - <e>, fused with the
+// pass that follows it: the sum of F (Hamiltonian, coef = AA) or of coef * phi
+// (CMC, coef = m2) over the updated field.  Same thread mapping and order of
+// additions as k_sum_ham_F / k_sum_prod, and the update of EwIrUpdate, so the
+// fused pass gives the two separate passes' field and partial sums bit for bit.
+template <bool HAM>
+__global__ void __launch_bounds__(TPB) k_ir_update_sum(double *__restrict__ phi, const float *__restrict__ e,
+                                                       const double *__restrict__ mean, const double *__restrict__ f,
+                                                       const double *__restrict__ coef, long N, OpConst oc, bool pair,
+                                                       double *__restrict__ partials)
+{
+    const double m = *mean;
+    double v[1];
+    v[0] = sum_pairs(N, pair, [&](long p, double acc, bool two) {
+        if (two) {
+            double2 a = *reinterpret_cast<const double2 *>(phi + p);
+            const float2 u = *reinterpret_cast<const float2 *>(e + p);
+            a.x += (double)u.x - m;
+            a.y += (double)u.y - m;
+            *reinterpret_cast<double2 *>(phi + p) = a;
+            const double2 c = *reinterpret_cast<const double2 *>(coef + p);
+            if constexpr (HAM) {
+                const double2 b = *reinterpret_cast<const double2 *>(f + p);
+                acc += ham_F(a.x, b.x, c.x, oc);
+                acc += ham_F(a.y, b.y, c.y, oc);
+            } else {
+                acc += c.x * a.x;
+                acc += c.y * a.y;
+            }
+            return acc;
+        }
+        double a = phi[p];
+        a += (double)e[p] - m;
+        phi[p] = a;
+        return HAM ? acc + ham_F(a, f[p], coef[p], oc) : acc + coef[p] * a;
+    });
+    block_sum_store<1>(v, partials);
+    zero_unused_partials<1>(partials);
+}
+
+// Both linearisation arrays (a and c of the FP32 Hamiltonian correction)
+// restricted one level in one launch (the per-element arithmetic of k_restrict).
+__global__ void __launch_bounds__(TPB) k_restrict2(const float *__restrict__ fa, const float *__restrict__ fc, int n,
+                                                   float *__restrict__ ca, float *__restrict__ cc)
+{
+    const int m = n >> 1;
+    GEO_XYZ(m, m)
+    float sa = 0, sc = 0;
+    for (int c = 0; c < 8; ++c) {
+        const long q = lin(2 * x + (c & 1), 2 * y + ((c >> 1) & 1), 2 * z + (c >> 2), n);
+        sa += fa[q];
+        sc += fc[q];
+    }
+    ca[lin(x, y, z, m)] = sa / 8.f;
+    cc[lin(x, y, z, m)] = sc / 8.f;
+}
+
+// The same for the levels from side n down to side 2, in one workgroup (levels
+// of at most 32^3: one launch instead of one per level and array).
+__global__ void __launch_bounds__(kCoarseThreads) k_restrict2_chain(RestrictChain R)
+{
+    for (int l = 0; l < R.nl; ++l) {
+        const int n = R.n[l], m = n >> 1, M = m * m * m;
+        for (int q = threadIdx.x; q < M; q += kCoarseThreads) {
+            const int x = q % m, y = (q / m) % m, z = q / (m * m);
+            float sa = 0, sc = 0;
+            for (int c = 0; c < 8; ++c) {
+                const long p = lin(2 * x + (c & 1), 2 * y + ((c >> 1) & 1), 2 * z + (c >> 2), n);
+                sa += R.a[l][p];
+                sc += R.c[l][p];
+            }
+            R.a[l + 1][q] = sa / 8.f;
+            R.c[l + 1][q] = sc / 8.f;
+        }
+        __syncthreads();
+    }
+}
+
 // Sums of eps^2 and (f - fshift)^2 on one level.  Blocks of 64 x 4 threads
 // walk x-rows (row r = (y, z)) in a grid-stride loop over the n^2 rows.
 template <int KIND>
@@ -1465,6 +1543,27 @@ void launch_sum_ham_F(hipStream_t s, const double *psi, const double *f, const d
 {
     k_sum_ham_F<<<reduce_blocks(N), TPB, 0, s>>>(psi, f, coef, N, oc,
                                                  N % 2 == 0 && al16(psi) && al16(f) && al16(coef), partials);
+}
+
+void launch_ir_update_sum(int kind, hipStream_t s, double *phi, const float *e, const double *mean, const double *f,
+                          const double *coef, long N, OpConst oc, double *partials)
+{
+    const bool pair = N % 2 == 0 && al16(phi) && al16(f) && al16(coef) && (reinterpret_cast<uintptr_t>(e) & 7) == 0;
+    if (kind == GR_KIND_HAMILTONIAN)
+        k_ir_update_sum<true><<<reduce_blocks(N), TPB, 0, s>>>(phi, e, mean, f, coef, N, oc, pair, partials);
+    else
+        k_ir_update_sum<false><<<reduce_blocks(N), TPB, 0, s>>>(phi, e, mean, f, coef, N, oc, pair, partials);
+}
+
+void launch_restrict2_f32(hipStream_t s, const float *fa, const float *fc, int n, float *ca, float *cc)
+{
+    const Geo G = geo3(n / 2, n / 2, n / 2);
+    k_restrict2<<<G.grid, G.block, 0, s>>>(fa, fc, n, ca, cc);
+}
+
+void launch_restrict2_chain(hipStream_t s, const RestrictChain &R)
+{
+    k_restrict2_chain<<<1, kCoarseThreads, 0, s>>>(R);
 }
 
 void launch_res_norms(int kind, hipStream_t s, const double *phi, const double *f, const double *coef, int n,
