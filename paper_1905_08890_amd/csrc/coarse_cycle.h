@@ -22,16 +22,19 @@ __device__ void cv_sweep(T *__restrict__ phi, const T *__restrict__ f, const T *
                          const T *__restrict__ c2, int n, T inv_h2, OpConst oc, T Fb, T fs)
 {
     const int half = n >> 1, tot = n * n * half;
+    const SmallDiv dh(half), dn(n);
+    const T rJ = poisson_inv_diag(inv_h2);
     for (int colour = 0; colour < 2; ++colour) {
         for (int t = threadIdx.x; t < tot; t += kCoarseThreads) {
-            const int x2 = t % half, r = t / half, y = r % n, z = r / n;
+            const int r = dh.div(t), z = dn.div(r);
+            const int x2 = t - r * half, y = r - z * n;
             const int i = 2 * x2 + ((y + z + colour) & 1);
             const long p = lin(i, y, z, n);
             const T ph = phi[p];
             T J;
             const T L = op_point<KIND, T>(ph, nb_sum(phi, i, y, z, n), inv_h2, load_c1<KIND>(c1, p),
                                           load_c2<KIND>(c2, p), oc, Fb, J);
-            phi[p] = ph - (L - (f[p] - fs)) / J;
+            phi[p] = newton_update<KIND, T>(ph, L, f[p] - fs, J, rJ);
         }
         __syncthreads();
     }
@@ -62,8 +65,10 @@ __device__ void coarse_vcycle_body(const CoarseLevelsT<T> &C, int nu1, int nu2, 
         const T Fb = i == 0 ? Fb0 : T(0), fs = i == 0 ? fs0 : T(0);
         for (int it = 0; it < nu1; ++it) cv_sweep<KIND, T>(C.phi[i], C.f[i], C.c1[i], C.c2[i], n, inv_h2, oc, Fb, fs);
         const int M = m * m * m;
+        const SmallDiv dm(m);
         for (int q = threadIdx.x; q < M; q += kCoarseThreads) {
-            const int X = q % m, Y = (q / m) % m, Z = q / (m * m);
+            const int r = dm.div(q), Z = dm.div(r);
+            const int X = q - r * m, Y = r - Z * m;
             T sr = 0, sp = 0;
             for (int c = 0; c < 8; ++c) {
                 const int a = 2 * X + (c & 1), b = 2 * Y + ((c >> 1) & 1), d = 2 * Z + (c >> 2);
@@ -89,7 +94,8 @@ __device__ void coarse_vcycle_body(const CoarseLevelsT<T> &C, int nu1, int nu2, 
         if constexpr (!LIN) {
             const T inv_H2 = T(C.inv_h2[i + 1]);
             for (int q = threadIdx.x; q < M; q += kCoarseThreads) {
-                const int X = q % m, Y = (q / m) % m, Z = q / (m * m);
+                const int r = dm.div(q), Z = dm.div(r);
+                const int X = q - r * m, Y = r - Z * m;
                 T Jd;
                 const T Lv = op_point<KIND, T>(C.phi[i + 1][q], nb_sum(C.phi[i + 1], X, Y, Z, m), inv_H2,
                                                load_c1<KIND>(C.c1[i + 1], q), load_c2<KIND>(C.c2[i + 1], q), oc, T(0),
@@ -126,7 +132,7 @@ __device__ void coarse_vcycle_body(const CoarseLevelsT<T> &C, int nu1, int nu2, 
                     if (on && par == colour) {
                         T J;
                         const T Lv = op_point<KIND, T>(ph, nbs, inv_h2, cv1, cv2, oc, Fb, J);
-                        ph = ph - (Lv - (fv - fs)) / J;
+                        ph = newton_update<KIND, T>(ph, Lv, fv - fs, J, poisson_inv_diag(inv_h2));
                     }
                 }
             double dsum = on ? (double)(ph - old) : 0.0;
@@ -153,8 +159,10 @@ __device__ void coarse_vcycle_body(const CoarseLevelsT<T> &C, int nu1, int nu2, 
         const int n = C.n[i], m = n >> 1, N = n * n * n;
         const T inv_h2 = T(C.inv_h2[i]);
         const T Fb = i == 0 ? Fb0 : T(0), fs = i == 0 ? fs0 : T(0);
+        const SmallDiv dn(n);
         for (int p = threadIdx.x; p < N; p += kCoarseThreads) {
-            const int a = p % n, b = (p / n) % n, d = p / (n * n);
+            const int r = dn.div(p), d = dn.div(r);
+            const int a = p - r * n, b = r - d * n;
             const int I = a >> 1, J = b >> 1, K = d >> 1;
             const int Is[2] = {I, wrapi(I + ((a & 1) ? 1 : -1), m)};
             const int Js[2] = {J, wrapi(J + ((b & 1) ? 1 : -1), m)};

@@ -64,20 +64,33 @@ __device__ __forceinline__ T op_point(T ph, T nbs, T inv_h2, T c1, T c2, OpConst
     }
 }
 
-// The point update ph - (L - fe) / J of every smoother.  The FP32 correction
-// equation of the Poisson kind has the constant diagonal J = -6/h^2: there the
-// update multiplies by its reciprocal rJ (formed once per kernel from inv_h2),
-// within an ulp of the division, which the FP32 correction does not need.
+// The point update ph - (L - fe) / J of every smoother.  The correction
+// equation of the Poisson kind (FP32 sweeps, FP64 coarse levels) has the constant
+// diagonal J = -6/h^2: there the update multiplies by its reciprocal rJ (formed
+// once per kernel from inv_h2), within an ulp of the division, which the
+// correction does not need.
 template <typename T> __device__ __forceinline__ T poisson_inv_diag(T inv_h2) { return T(1) / (T(-6) * inv_h2); }
 
 template <int KIND, typename T>
 __device__ __forceinline__ T newton_update(T ph, T L, T fe, T J, T rJ)
 {
-    if constexpr (KIND == K_LIN_POISSON && sizeof(T) == 4)
+    if constexpr (KIND == K_LIN_POISSON)
         return ph - (L - fe) * rJ;
     else
         return ph - (L - fe) / J;
 }
+
+// t / d for 0 <= t < 2^24: for 1 < d < 2^8 a multiply-high with m = ceil(2^32 / d)
+// (the error term t (m d - 2^32) < 2^24 2^8 keeps the quotient exact), else a division.
+struct SmallDiv {
+    unsigned m;
+    int d;
+    __device__ __forceinline__ explicit SmallDiv(int d_)
+        : m(d_ > 1 && d_ < 256 ? 0xffffffffu / (unsigned)d_ + 1u : 0u), d(d_)
+    {
+    }
+    __device__ __forceinline__ int div(int t) const { return m ? (int)__umulhi((unsigned)t, m) : t / d; }
+};
 
 template <int KIND, typename T>
 __device__ __forceinline__ T load_c1(const T *__restrict__ c1, long p)
