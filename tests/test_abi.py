@@ -151,3 +151,23 @@ def test_nested_patch_descriptors_rejected():
         with pytest.raises(grmg.GrError):
             grmg.create_batch([32], 1.0, 0.3, 1.0, patches=[good, bad])
     grmg.destroy_batch(grmg.create_batch([32], 1.0, 0.3, 1.0, patches=[good, (8, 1 / 128, nb + 0, (0.05, 0.05, 0.05))]))
+
+
+def test_multiply_high_division_is_exact_where_the_coarse_cycle_uses_it():
+    """The single-workgroup coarse cycle divides cell indices t < 2^24 by level
+    sides 1 < d < 256 as the high 32 bits of t * ceil(2^32 / d): checked here
+    against integer division for every such d, on every t below 2^16, a stride
+    through the rest of the range, and the values just below and at the largest
+    multiples of d (where the rounding error of m is largest)."""
+    import numpy as np
+
+    small = np.arange(1 << 16, dtype=np.uint64)
+    stride = np.arange(1 << 16, 1 << 24, 997, dtype=np.uint64)
+    for d in range(2, 256):
+        m = np.uint64(0xFFFFFFFF // d + 1)
+        k = np.arange((1 << 24) // d - 64, (1 << 24) // d + 1, dtype=np.uint64)
+        edges = np.concatenate([k * np.uint64(d) - np.uint64(1), k * np.uint64(d)])
+        edges = edges[edges < (1 << 24)]
+        t = np.concatenate([small, stride, edges])
+        q = (t * m) >> np.uint64(32)
+        assert np.array_equal(q, t // np.uint64(d)), d
