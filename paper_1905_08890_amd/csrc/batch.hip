@@ -1468,9 +1468,11 @@ __device__ void cvp_sweep(double *__restrict__ phi, const double *__restrict__ f
                           int n, double inv_h2, OpConst oc)
 {
     const int N = n * n * n;
+    const SmallDiv dn(n);
     for (int colour = 0; colour < 2; ++colour) {
         for (int t = threadIdx.x; t < N; t += CTPB) {
-            const int i = t % n, j = (t / n) % n, k = t / (n * n);
+            const int r = dn.div(t), k = dn.div(r);
+            const int i = t - r * n, j = r - k * n;
             if (((i + j + k) & 1) != colour) continue;
             double J;
             const double Lv = patch_op<KIND>(phi, i, j, k, n, inv_h2, load_c1<KIND>(coef, t), oc, J);
@@ -1480,6 +1482,8 @@ __device__ void cvp_sweep(double *__restrict__ phi, const double *__restrict__ f
         __syncthreads();
     }
 }
+
+constexpr int kPatchCoarseLds = 4096; // doubles of LDS for the coarsest patch level (32 KB)
 
 template <int KIND>
 __global__ void __launch_bounds__(CTPB) kp_coarse_vcycle(BatchDev D, int fid, int nu1, int nu2, OpConst oc, int b0)
@@ -1519,10 +1523,29 @@ __global__ void __launch_bounds__(CTPB) kp_coarse_vcycle(BatchDev D, int fid, in
         __syncthreads();
     }
     {
+        // coarsest level: its 32 sweeps from LDS when the padded iterate, the
+        // source and the coefficient fit (every patch side of the usual
+        // hierarchies ends at 3^3 to 10^3), else from global memory
         const BoxLev &V = X.lev[L - 1];
         double *phi = patch_phi(X, L - 1, fid);
         const double inv_h2 = 1.0 / (V.h * V.h);
-        for (int it = 0; it < kCoarseSweeps; ++it) cvp_sweep<KIND>(phi, V.f, V.coef, V.n, inv_h2, oc);
+        const int n = V.n, P = (n + 2) * (n + 2) * (n + 2), N = n * n * n;
+        constexpr int NC = kNumCoef<KIND>();
+        __shared__ double lds[kPatchCoarseLds];
+        if (P + (1 + NC) * N <= kPatchCoarseLds) {
+            double *sphi = lds, *sf = lds + P, *sc = lds + P + N;
+            for (int q = threadIdx.x; q < P; q += CTPB) sphi[q] = phi[q];
+            for (int q = threadIdx.x; q < N; q += CTPB) {
+                sf[q] = V.f[q];
+                if (NC >= 1) sc[q] = V.coef[q];
+            }
+            __syncthreads();
+            for (int it = 0; it < kCoarseSweeps; ++it) cvp_sweep<KIND>(sphi, sf, sc, n, inv_h2, oc);
+            for (int q = threadIdx.x; q < P; q += CTPB) phi[q] = sphi[q];
+            __syncthreads();
+        } else {
+            for (int it = 0; it < kCoarseSweeps; ++it) cvp_sweep<KIND>(phi, V.f, V.coef, n, inv_h2, oc);
+        }
     }
     for (int i = L - 2; i >= l0; --i) {
         const BoxLev &V = X.lev[i], &C = X.lev[i + 1];
