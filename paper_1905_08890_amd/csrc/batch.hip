@@ -592,9 +592,11 @@ __device__ void cvb_sweep(double *__restrict__ phi, const double *__restrict__ f
                           double inv_h2, OpConst oc, double Fb, double fs)
 {
     const int half = n >> 1, tot = n * n * half;
+    const SmallDiv dh(half), dn(n);
     for (int colour = 0; colour < 2; ++colour) {
         for (int t = threadIdx.x; t < tot; t += CTPB) {
-            const int x2 = t % half, r = t / half, y = r % n, z = r / n;
+            const int r = dh.div(t), z = dn.div(r);
+            const int x2 = t - r * half, y = r - z * n;
             const int i = 2 * x2 + ((y + z + colour) & 1);
             const long p = lin(i, y, z, n);
             const double ph = phi[p];
@@ -619,6 +621,8 @@ __device__ double cvb_block_sum(double v)
     __syncthreads();
     return s;
 }
+
+constexpr int kBoxCoarseLds = 1024; // doubles of LDS for the coarsest box level (8 KB)
 
 template <int KIND>
 __device__ void coarse_vcycle_box(const BatchDev &D, int b, int fid, int nu1, int nu2, OpConst oc)
@@ -674,7 +678,24 @@ __device__ void coarse_vcycle_box(const BatchDev &D, int b, int fid, int nu1, in
         const double Fb = i == 0 ? Fb0 : 0.0, fs = i == 0 ? fs0 : 0.0;
         for (int q = threadIdx.x; q < N; q += CTPB) V.tmp[q] = phi[q];
         __syncthreads();
-        for (int it = 0; it < kCoarseSweeps; ++it) cvb_sweep<KIND>(phi, V.f, V.coef, n, inv_h2, oc, Fb, fs);
+        // the 32 sweeps from LDS when the level, its source and coefficient fit
+        // (the coarsest box levels are 2^3 to 6^3), else from global memory
+        constexpr int NC = kNumCoef<KIND>();
+        __shared__ double lds[kBoxCoarseLds];
+        if ((2 + NC) * N <= kBoxCoarseLds) {
+            double *sphi = lds, *sf = lds + N, *sc = lds + 2 * N;
+            for (int q = threadIdx.x; q < N; q += CTPB) {
+                sphi[q] = phi[q];
+                sf[q] = V.f[q];
+                if (NC >= 1) sc[q] = V.coef[q];
+            }
+            __syncthreads();
+            for (int it = 0; it < kCoarseSweeps; ++it) cvb_sweep<KIND>(sphi, sf, sc, n, inv_h2, oc, Fb, fs);
+            for (int q = threadIdx.x; q < N; q += CTPB) phi[q] = sphi[q];
+            __syncthreads();
+        } else {
+            for (int it = 0; it < kCoarseSweeps; ++it) cvb_sweep<KIND>(phi, V.f, V.coef, n, inv_h2, oc, Fb, fs);
+        }
         double dsum = 0.0;
         for (int q = threadIdx.x; q < N; q += CTPB) dsum += phi[q] - V.tmp[q];
         const double mean = cvb_block_sum(dsum) / (double)N;
