@@ -139,8 +139,11 @@ void launch_sum_prod(hipStream_t s, const double *x, const double *y, long N, do
 void launch_res_norms(int kind, hipStream_t s, const double *phi, const double *f, const double *coef,
                       int n, double h, OpConst oc, const double *fbar, const double *fshift,
                       double *partials);
+// out[c] = add[c] + scale * (fixed-order sum of the partials of quantity c);
+// host_out (optional): page-locked, coherent host memory that receives the same
+// values, written before the kernel ends (the per-cycle stopping norms)
 void launch_finalize(hipStream_t s, const double *partials, int ncomp, double scale, const double *add,
-                     double *out);
+                     double *out, double *host_out = nullptr);
 
 void launch_fill(hipStream_t s, double *x, long N, double v);
 void launch_copy(hipStream_t s, double *dst, const double *src, long N);

@@ -106,9 +106,11 @@ struct gr_grid_s {
     hipStream_t user_stream = nullptr;
     hipStream_t work = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    // per-cycle read-back of the two stopping norms: pinned host slots and an
-    // event the host spins on (set up at bind; absent on the static grid)
-    double *h_norms = nullptr;
+    // per-cycle read-back of the two stopping norms: page-locked coherent host
+    // slots that the norm finalize writes directly (d_norms: their device
+    // address), and an event the host spins on (set up at bind; absent on the
+    // static grid)
+    double *h_norms = nullptr, *d_norms = nullptr;
     hipEvent_t ev_norms = nullptr;
     bool use_graph = true;
     struct GraphEntry {
@@ -239,20 +241,22 @@ int pin_mean(gr_grid g, double *phi, long N)
 }
 
 // Reads the sums of eps^2 and f^2 of the stopping test (slots S_RN, S_FN) to
-// the host once the work queued before it is done.  With the pinned slots of a
-// bound grid the copy lands in page-locked memory and the host spins on an
-// event (no sleeping wait between V-cycles); otherwise it waits on the stream.
+// the host once the work queued before it is done.  On a bound grid the
+// finalize that produced them (always the last kernel before this call) also
+// wrote them to the page-locked coherent slots h_norms, and the host spins on an
+// event (no copy, no sleeping wait between V-cycles); otherwise it copies and
+// waits on the stream.
 int read_norms(gr_grid g, double out[2])
 {
-    if (g->h_norms && g->ev_norms) {
-        HIPCHK(hipMemcpyAsync(g->h_norms, g->scal + S_RN, 2 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
+    if (g->d_norms && g->ev_norms) { // the norm finalize wrote them to h_norms
         HIPCHK(hipEventRecord(g->ev_norms, g->stream));
         hipError_t e;
         while ((e = hipEventQuery(g->ev_norms)) == hipErrorNotReady) {
         }
         if (e != hipSuccess) return fail(GR_EDEVICE, "norm read-back: %s", hipGetErrorString(e));
-        out[0] = g->h_norms[0];
-        out[1] = g->h_norms[1];
+        const volatile double *h = g->h_norms;
+        out[0] = h[0];
+        out[1] = h[1];
         return GR_OK;
     }
     HIPCHK(hipMemcpyAsync(out, g->scal + S_RN, 2 * sizeof(double), hipMemcpyDeviceToHost, g->stream));
@@ -491,7 +495,7 @@ int solve_one(gr_grid g, int kind, double *phi, const gr_solve_opts &o, int *cyc
         }
         launch_res_norms(kind, s, phi, F.f, F.coef, F.n, F.h, E.oc, g->scal + S_FBAR, g->scal + S_FSHIFT,
                          g->partials);
-        launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN);
+        launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN, g->d_norms);
         LAUNCHCHK();
         return GR_OK;
     };
@@ -667,7 +671,7 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
         }
         launch_ir_residual(kind, s, cur, F.f, F.coef, F.n, F.h, oc, g->scal + S_FBAR, g->scal + S_FSHIFT, F32.b, F32.a,
                            F32.c, g->partials);
-        launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN);
+        launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN, g->d_norms);
         LAUNCHCHK();
         return GR_OK;
     };
@@ -693,7 +697,7 @@ int solve_one_mixed(gr_grid g, int kind, double *phi, const gr_solve_opts &o, in
         if (fuse_update) { // shift-invariant: one pin at the end (as in the FP64 cycle)
             launch_ir_update_residual(s, cur, F32.e, other, F.f, F.n, F.h, oc, g->scal + S_FBAR, g->scal + S_FSHIFT,
                                       F32.b, g->partials);
-            launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN);
+            launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN, g->d_norms);
             LAUNCHCHK();
             return GR_OK;
         } else { // the update fused with the next frozen-mean sum
@@ -783,7 +787,7 @@ int guess_residual(gr_grid g, int kind, double *phi, double *rel_out)
         launch_finalize(s, g->partials, 1, 1.0 / (double)N, g->scal + S_FMEAN, g->scal + S_FSHIFT);
     }
     launch_res_norms(kind, s, phi, F.f, F.coef, F.n, F.h, oc, g->scal + S_FBAR, g->scal + S_FSHIFT, g->partials);
-    launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN);
+    launch_finalize(s, g->partials, 2, 1.0 / (double)N, nullptr, g->scal + S_RN, g->d_norms);
     LAUNCHCHK();
     double hn[2];
     CHK(read_norms(g, hn));
@@ -1012,7 +1016,9 @@ int gr_bind(gr_grid g, void *d_ws, size_t bytes, void *stream)
         HIPCHK(hipEventCreateWithFlags(&g->ev_in, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&g->ev_out, hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&g->ev_norms, hipEventDisableTiming));
-        HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&g->h_norms), 2 * sizeof(double), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&g->h_norms), 2 * sizeof(double),
+                             hipHostMallocMapped | hipHostMallocCoherent));
+        HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void **>(&g->d_norms), g->h_norms, 0));
     }
     for (auto *h : g->sub) {
         if (!h) continue;
@@ -1022,7 +1028,9 @@ int gr_bind(gr_grid g, void *d_ws, size_t bytes, void *stream)
             HIPCHK(hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
             HIPCHK(hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
             HIPCHK(hipEventCreateWithFlags(&h->ev_norms, hipEventDisableTiming));
-            HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&h->h_norms), 2 * sizeof(double), hipHostMallocDefault));
+            HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&h->h_norms), 2 * sizeof(double),
+                                 hipHostMallocMapped | hipHostMallocCoherent));
+            HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void **>(&h->d_norms), h->h_norms, 0));
         }
         h->user_stream = g->user_stream;
         h->stream = g->user_stream;

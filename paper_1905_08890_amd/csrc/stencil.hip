@@ -543,7 +543,8 @@ __global__ void __launch_bounds__(TPB) k_res_norms(const double *__restrict__ ph
 constexpr int kFinalizeSlots = kReduceBlocks / TPB;
 
 __global__ void __launch_bounds__(TPB) k_finalize(const double *__restrict__ partials, int ncomp, double scale,
-                                                  const double *__restrict__ add, double *__restrict__ out)
+                                                  const double *__restrict__ add, double *__restrict__ out,
+                                                  double *__restrict__ host_out)
 {
     __shared__ double sh[2][TPB];
     double v[2][kFinalizeSlots];
@@ -575,8 +576,14 @@ __global__ void __launch_bounds__(TPB) k_finalize(const double *__restrict__ par
             s1 += __shfl_down(s1, w, 64);
         }
         if (t == 0) {
-            out[0] = (add ? add[0] : 0.0) + scale * s0;
-            if (ncomp > 1) out[1] = (add ? add[1] : 0.0) + scale * s1;
+            const double r0 = (add ? add[0] : 0.0) + scale * s0, r1 = (add ? add[1] : 0.0) + scale * s1;
+            out[0] = r0;
+            if (ncomp > 1) out[1] = r1;
+            if (host_out) { // straight to the host's page-locked slots (no read-back copy)
+                host_out[0] = r0;
+                if (ncomp > 1) host_out[1] = r1;
+                __threadfence_system();
+            }
         }
     }
 }
@@ -1608,10 +1615,11 @@ void launch_res_norms(int kind, hipStream_t s, const double *phi, const double *
     GR_DISPATCH_KIND_G(kind, k_res_norms, G, phi, f, coef, n, 1.0 / (h * h), oc, fbar, fshift, partials);
 }
 
-void launch_finalize(hipStream_t s, const double *partials, int ncomp, double scale, const double *add, double *out)
+void launch_finalize(hipStream_t s, const double *partials, int ncomp, double scale, const double *add, double *out,
+                     double *host_out)
 {
     static_assert(kReduceBlocks % TPB == 0, "partial slots per thread");
-    k_finalize<<<1, TPB, 0, s>>>(partials, ncomp, scale, add, out);
+    k_finalize<<<1, TPB, 0, s>>>(partials, ncomp, scale, add, out, host_out);
 }
 
 void launch_fill(hipStream_t s, double *x, long N, double v)
