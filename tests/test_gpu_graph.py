@@ -112,6 +112,27 @@ def test_forced_launch_shapes_give_the_same_solve(precision, tile, pf, remap, mo
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_sweep_on_sides_of_32_mod_64_matches_per_colour(precision, monkeypatch):
+    """A level whose side is an odd multiple of 32 (96^3 here) takes the fused
+    sweep in 32x16 tiles; its solve equals one launch per colour bit for bit."""
+    n = 96
+    print(f"[gpu] fused 32x16 on n={n} {precision}", flush=True)
+    monkeypatch.setenv("GRMG_SMOOTHER", "split")
+    a = grmg.Grid(n, **PRM)
+    monkeypatch.setenv("GRMG_SMOOTHER", "fused")
+    monkeypatch.setenv("GRMG_FUSED_MIN", "96")
+    b = grmg.Grid(n, **PRM)
+    pos, u, mass = synth.zeldovich(n, 7, 0.5)
+    a.deposit_sources(pos, u, mass)
+    _same_sources(b, a)
+    ra = a.solve_constraints(rtol=1e-10, precision=precision)
+    rb = b.solve_constraints(rtol=1e-10, precision=precision)
+    assert ra["cycles"] == rb["cycles"]
+    for f in range(10):
+        assert torch.equal(a.get_field(f), b.get_field(f)), f
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_concurrent_vector_components_match_sequential(precision, monkeypatch):
     """The three components of the vector equations solved side by side, each on
     a helper hierarchy with its own stream, give the sequential solve bit for bit."""
