@@ -288,10 +288,11 @@ int gr_set_guess(gr_grid g, int level, int count, const int *fields, const doubl
                  int flags);
 
 /* Autotuner of the fused red-black sweep (sec. 4.3.1 smoother): for every
- * level the fused sweep can tile (n >= 64, n % 64 == 0) and each of the six
+ * level the fused sweep can tile (n >= 32, n % 32 == 0) and each of the six
  * operator kinds (FP64 Poisson, Hamiltonian, CMC; their FP32 linearised
  * forms), times every candidate launch configuration on workspace scratch:
- * tile 64x8, 32x16, 64x16 or (n % 128 == 0) 128x8; a target of 256, 512,
+ * tile 64x8, 32x16, 64x16 or (n % 128 == 0) 128x8 (only 32x16 where n % 64 ==
+ * 32); a target of 256, 512,
  * 1024 or 2048 workgroups; operand prefetch 1 or 2 planes (1 to 4 for the
  * 64x16 tile); and one launch per colour instead of the fused sweep.  It
  * keeps the fastest for this grid; results are cached per process by
