@@ -290,6 +290,7 @@ def evaluate(guess, n, seeds, steps, r0, torch, device="cuda", rtol=1e-10, contr
                 grid.set_field(grmg.HIST + f, v)
 
     for seed in seeds:
+        log(f"evaluating held-out seed {seed}")
         prev2 = prev = None
         for s, (pos, u, mass) in enumerate(synth.zeldovich_trajectory(n, seed, trajectory_amplitudes(r0, steps))):
             if prev2 is not None:
