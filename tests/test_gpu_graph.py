@@ -112,6 +112,30 @@ def test_forced_launch_shapes_give_the_same_solve(precision, tile, pf, remap, mo
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_poisson_single_workgroup_threshold_16_matches_8(precision, monkeypatch):
+    """The Poisson V-cycles take the 16^3 level into the single-workgroup cycle
+    by default; with that level on the multi-launch path instead the solve
+    agrees to rounding (the two forms add the restriction's children in other
+    orders): the same cycle counts, fields within 1e-12 (FP64) / 1e-10 (mixed)."""
+    n = 64
+    print(f"[gpu] single-workgroup threshold n={n} {precision}", flush=True)
+    a = grmg.Grid(n, **PRM)
+    monkeypatch.setenv("GRMG_COARSE_NP", "8")
+    b = grmg.Grid(n, **PRM)
+    pos, u, mass = synth.zeldovich(n, 8, 0.5)
+    a.deposit_sources(pos, u, mass)
+    _same_sources(b, a)
+    ra = a.solve_constraints(rtol=1e-10, precision=precision)
+    rb = b.solve_constraints(rtol=1e-10, precision=precision)
+    assert ra["status"] == rb["status"] == grmg.OK
+    assert ra["cycles"] == rb["cycles"]
+    tol = 1e-12 if precision == "fp64" else 1e-10
+    for f in range(10):
+        x, y = a.get_field(f), b.get_field(f)
+        assert float((x - y).abs().max()) <= tol * float(y.abs().max()), f
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_fused_sweep_on_sides_of_32_mod_64_matches_per_colour(precision, monkeypatch):
     """A level whose side is an odd multiple of 32 (96^3 here) takes the fused
     sweep in 32x16 tiles; its solve equals one launch per colour bit for bit."""
